@@ -1,0 +1,143 @@
+"""Seeded synthetic inputs shared by the tests, the benchmark and the oracle
+checks: graded tetrahedral meshes and blast initial states.
+
+This module holds no arithmetic of the method itself (no fluxes, gradients,
+levels or schedules); it only produces node coordinates, tetrahedra and
+primitive initial states, as plain NumPy arrays.
+
+Meshes: an nx*ny*nz hex grid whose coordinates are graded geometrically,
+x_k = (r^k - 1)/(r^n - 1) with r = G^(1/(n-1)) so that the last cell edge is
+G times the first ("grading ratio G end to end"), each hex split into the 6
+Kuhn tetrahedra along its (0,0,0)-(1,1,1) diagonal (a conforming split).
+Cell order is structured: tet t of hex (i, j, k) has id ((k*ny + j)*nx + i)*6 + t.
+"""
+import itertools
+
+import numpy as np
+
+GAMMA = 1.4
+
+
+def graded_coords(n, grading=1.0, length=1.0):
+    """n+1 node coordinates on [0, length], edge ratio last/first = grading."""
+    k = np.arange(n + 1, dtype=np.float64)
+    if n < 2 or grading == 1.0:
+        return length * k / n
+    r = grading ** (1.0 / (n - 1))
+    return length * (r ** k - 1.0) / (r ** n - 1.0)
+
+
+# the 6 Kuhn tets: for each permutation s of the axes, the path
+# (0,0,0) -> e_s0 -> e_s0 + e_s1 -> (1,1,1)
+_KUHN = []
+for perm in itertools.permutations(range(3)):
+    v = [0, 0, 0]
+    path = [tuple(v)]
+    for ax in perm:
+        v[ax] = 1
+        path.append(tuple(v))
+    _KUHN.append(path)
+
+
+def kuhn_tet_mesh(xs, ys, zs):
+    """Tetrahedral mesh of the tensor grid xs x ys x zs; returns
+    (nodes[n_nodes][3] float64, tets[n_tets][4] int64), positively oriented."""
+    xs, ys, zs = (np.asarray(a, dtype=np.float64) for a in (xs, ys, zs))
+    nx, ny, nz = len(xs) - 1, len(ys) - 1, len(zs) - 1
+    X, Y, Z = np.meshgrid(xs, ys, zs, indexing="ij")
+    # node id = (k*(ny+1) + j)*(nx+1) + i
+    nodes = np.stack([X.transpose(2, 1, 0).ravel(), Y.transpose(2, 1, 0).ravel(),
+                      Z.transpose(2, 1, 0).ravel()], axis=1)
+    i, j, k = np.meshgrid(np.arange(nx), np.arange(ny), np.arange(nz), indexing="ij")
+    i, j, k = (a.transpose(2, 1, 0).ravel() for a in (i, j, k))  # hex order k, j, i
+
+    def nid(di, dj, dk):
+        return ((k + dk) * (ny + 1) + (j + dj)) * (nx + 1) + (i + di)
+
+    tets = np.empty((nx * ny * nz, 6, 4), dtype=np.int64)
+    for t, path in enumerate(_KUHN):
+        for m, (di, dj, dk) in enumerate(path):
+            tets[:, t, m] = nid(di, dj, dk)
+    tets = tets.reshape(-1, 4)
+    # orient: swap the last two vertices where the signed volume is negative
+    p = nodes[tets]
+    det = np.einsum("ij,ij->i", p[:, 1] - p[:, 0], np.cross(p[:, 2] - p[:, 0], p[:, 3] - p[:, 0]))
+    neg = det < 0
+    tets[neg, 2], tets[neg, 3] = tets[neg, 3].copy(), tets[neg, 2].copy()
+    return nodes, tets
+
+
+def graded_cube_mesh(n, grading):
+    """n^3 hexes on the unit cube, graded toward the origin in x, y and z."""
+    x = graded_coords(n, grading)
+    return kuhn_tet_mesh(x, x, x)
+
+
+def column_mesh(n, grading=1.0, length=1.0, width=None):
+    """A column of n x 1 x 1 hexes along x (shock-tube tests); the square
+    cross section has edge `width` (default length/n)."""
+    x = graded_coords(n, grading, length)
+    h = length / n if width is None else width
+    return kuhn_tet_mesh(x, np.array([0.0, h]), np.array([0.0, h]))
+
+
+def tet_centroids(nodes, tets):
+    return nodes[tets].mean(axis=1)
+
+
+def blast_centre(seed):
+    """Blast centre jittered uniformly in [0.3, 0.7]^3 from a seeded generator."""
+    return np.random.default_rng(seed).uniform(0.3, 0.7, 3)
+
+
+def blast_state(nodes, tets, centre=(0.5, 0.5, 0.5), radius=0.2, p_in=10.0, p_out=1.0,
+                rho=1.0):
+    """Primitive state [n_tets][5] = (rho, u, v, w, p): rho everywhere, at rest,
+    p_in where the tet centroid lies strictly within `radius` of `centre`."""
+    c = tet_centroids(nodes, tets)
+    r = np.linalg.norm(c - np.asarray(centre, dtype=np.float64), axis=1)
+    prim = np.zeros((len(tets), 5))
+    prim[:, 0] = rho
+    prim[:, 4] = np.where(r < radius, p_in, p_out)
+    return prim
+
+
+def random_state(n, seed, rho=(0.5, 2.0), vel=0.5, p=(0.5, 2.0)):
+    """Smooth-free random primitive state (tests): uniform draws per cell."""
+    g = np.random.default_rng(seed)
+    prim = np.empty((n, 5))
+    prim[:, 0] = g.uniform(*rho, n)
+    prim[:, 1:4] = g.uniform(-vel, vel, (n, 3))
+    prim[:, 4] = g.uniform(*p, n)
+    return prim
+
+
+def sod_state(nodes, tets, x0=0.5, left=(1.0, 0.0, 1.0), right=(0.125, 0.0, 0.1)):
+    """Shock-tube state along x: (rho, u, p) left of x0, right of it
+    (Sod's 1978 data by default), zero transverse velocity."""
+    c = tet_centroids(nodes, tets)
+    prim = np.zeros((len(tets), 5))
+    lft = c[:, 0] < x0
+    prim[:, 0] = np.where(lft, left[0], right[0])
+    prim[:, 1] = np.where(lft, left[1], right[1])
+    prim[:, 4] = np.where(lft, left[2], right[2])
+    return prim
+
+
+# --- the configurations of the benchmark and the parity tests ------------
+
+def config_small():
+    """12^3 hexes, grading 4, 6 tets each (10,368 cells): first order, 3
+    levels, 8 dt_min units, blast centred at (0.5, 0.5, 0.5)."""
+    nodes, tets = graded_cube_mesh(12, 4.0)
+    return dict(nodes=nodes, tets=tets, prim=blast_state(nodes, tets),
+                order=1, max_levels=3, units=8)
+
+
+def config_scale(n=64, seed=0):
+    """n^3 hexes, grading 16, 6 tets each (n = 64: 1,572,864 cells): second
+    order, 5 levels, 32 dt_min units, blast centre drawn from `seed`."""
+    nodes, tets = graded_cube_mesh(n, 16.0)
+    return dict(nodes=nodes, tets=tets,
+                prim=blast_state(nodes, tets, centre=blast_centre(seed)),
+                order=2, max_levels=5, units=32)
