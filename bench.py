@@ -1,0 +1,199 @@
+"""Benchmark: cell-updates/s of the temporal-adaptive finite-volume Euler
+path on one MI355X.
+
+Workload (one step): the 64^3 hex grid graded 16x toward the origin, each
+hex split into 6 tets (1,572,864 cells), second-order MUSCL (least squares +
+Barth-Jespersen), exact Riemann flux with Newton on p* (tol 1e-12), up to 5
+temporal levels, a spherical blast (rho = 1, u = 0, p = 10 within 0.2 of a
+centre drawn from seed 0 in [0.3, 0.7]^3, p = 1 elsewhere), reflective
+walls, advanced 32 dt_min units from the initial state (the state is
+restored on the device before every step).  FP64 throughout.
+
+Prints one JSON line on stdout; progress goes to stderr.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+UNITS = 32
+HBM_PEAK_GBS = 8000.0
+
+# Algorithmic bytes per work item of each kernel class (each input and
+# output moved once per item):
+#   flux (per face): index 4, half-face ids 8, area vector 24 (12 in FP32),
+#     levels 2, two reconstructed states 80 (40), read+write of two FP64
+#     accumulators 160;
+#   grad (per cell): index 4, own state 40, neighbour ids 16,
+#     least-squares coefficients 96 (48), face offsets 96 (48),
+#     4 reconstructed face states 160 (80);
+#   update (per cell): index 4, volume 8, state read+write 80, accumulator
+#     read+write 80.
+BYTES_PER_ITEM = {
+    "fp64": {"flux": 278, "grad": 412, "update": 172},
+    "fp32": {"flux": 226, "grad": 236, "update": 172},
+}
+# gather mode: the flux kernel reads a 16-byte face record, the area vector,
+# two reconstructed states and writes one 40-byte flux; the cell kernel reads
+# its index, level, 4 neighbour ids and levels, 4 face ids, the active
+# faces' fluxes (about 2 x 40 per cell), and reads+writes the accumulator,
+# and for ending steps the volume and state.
+BYTES_PER_ITEM_GATHER = {
+    "fp64": {"flux": 160, "grad": 412, "gather": 270},
+    "fp32": {"flux": 108, "grad": 236, "gather": 270},
+}
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def run_form(T, torch, cfg, precision, steps, warmup, scatter):
+    stream = torch.cuda.current_stream()
+    s = T.Solver(device=0, hip_stream=stream.cuda_stream, max_levels=cfg["max_levels"],
+                 order=cfg["order"], precision=precision, scatter=scatter)
+    s.upload(cfg["nodes"], cfg["tets"])
+    s.init(cfg["prim"])
+    for _ in range(warmup):
+        s.reset()
+        T.tafv_advance_async(s.ctx, UNITS)
+    torch.cuda.synchronize()
+    st0 = s.stats()
+    T.tafv_profile_enable(s.ctx, True)
+    T.tafv_profile_read(s.ctx)  # clear
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ev0.record(stream)
+    for _ in range(steps):
+        s.reset()
+        T.tafv_advance_async(s.ctx, UNITS)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms = ev0.elapsed_time(ev1)
+    prof = T.tafv_profile_read(s.ctx)
+    T.tafv_profile_enable(s.ctx, False)
+    st1 = s.stats()
+    updates = st1["cell_updates"] - st0["cell_updates"]
+    faces = st1["face_solves"] - st0["face_solves"]
+    newton = st1["newton_updates"] - st0["newton_updates"]
+    cons, lev = s.read()
+    s.close()
+    return dict(ms=ms, wall_s=wall, updates=updates, faces=faces, newton=newton, prof=prof,
+                stats=st1, cons=cons, levels=lev)
+
+
+def roofline(prof, bytes_per_item):
+    dom = max((k for k in prof if k in bytes_per_item), key=lambda k: prof[k]["ms"])
+    p = prof[dom]
+    achieved = bytes_per_item[dom] * p["items"] / (p["ms"] * 1e-3) / 1e9
+    return dom, {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                 "kernel": "k_flux" if dom == "flux" else "k_" + dom,
+                 "avg_launch_us": round(1e3 * p["ms"] / max(p["launches"], 1), 2),
+                 "bytes_per_item": bytes_per_item[dom], "items": p["items"],
+                 "launches": p["launches"]}
+
+
+def cpu_baseline(cfg, units=8):
+    """The oracle, single-threaded, on the first `units` subiterations of the
+    same workload (one full iteration at theta = 3)."""
+    from oracle import core as orc
+    m = orc.Mesh(cfg["nodes"], cfg["tets"])
+    o = orc.State(m, cfg["prim"], orc.params(max_levels=cfg["max_levels"], order=cfg["order"]))
+    t0 = time.perf_counter()
+    o.advance(units)
+    dt = time.perf_counter() - t0
+    st = o.stats()
+    return {"value": round(st["cell_updates"] / dt, 1), "unit": "cell-updates/s", "cores": 1,
+            "kind": "oracle",
+            "sample": f"first {units} of {UNITS} dt_min units (cell updates {st['cell_updates']}, "
+                      f"{dt:.1f} s) on the same 1,572,864-cell mesh and state, FP64, 1 thread"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--n", type=int, default=64, help="hexes per axis")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-fp32", action="store_true")
+    ap.add_argument("--scatter", type=int, default=1, help="0 colour, 1 gather")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
+              "(the multi-GPU decomposition is a design, not part of this build)", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_1704_01144_amd import inputs as I
+    from paper_1704_01144_amd import tafv as T
+
+    torch.cuda.set_device(0)
+    cfg = I.config_scale(args.n, 0)
+    log(f"workload: {len(cfg['tets'])} cells, order {cfg['order']}, L {cfg['max_levels']}, "
+        f"{UNITS} units, steps {args.steps}, warmup {args.warmup}")
+    r64 = run_form(T, torch, cfg, T.FP64, args.steps, args.warmup, args.scatter)
+    value = r64["updates"] / (r64["ms"] * 1e-3)
+    log(f"fp64: {r64['ms']:.2f} ms for {args.steps} steps, {value / 1e9:.3f} G cell-updates/s")
+    bpi = BYTES_PER_ITEM_GATHER if args.scatter == 1 else BYTES_PER_ITEM
+    dom, roof = roofline(r64["prof"], bpi["fp64"])
+    out = {
+        "metric": "cell-updates/s, 1.57M-tet graded mesh: FP64 plain vs FP32+learned @ L1 err",
+        "value": round(value, 1),
+        "unit": "cell-updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(r64["ms"] / args.steps, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"graded blast, {args.n}^3 hexes x 6 tets "
+                               f"({len(cfg['tets'])} cells), grading 16, MUSCL-LSQ + "
+                               f"Barth-Jespersen, exact Riemann (Newton tol 1e-12), <= 5 "
+                               f"levels, {UNITS} dt_min units, walls, seed 0",
+                   "cells": len(cfg["tets"]), "units": UNITS,
+                   "cell_updates_per_step": r64["updates"] // args.steps,
+                   "face_solves_per_step": r64["faces"] // args.steps,
+                   "newton_updates_per_face": round(r64["newton"] / max(r64["faces"], 1), 3),
+                   "levels_t0": r64["stats"]["cells_per_level"][:5]},
+        "roofline": roof,
+        "kernels_ms": {k: round(v["ms"], 3) for k, v in r64["prof"].items()},
+    }
+    if not args.no_fp32:
+        r32 = run_form(T, torch, cfg, T.FP32_FLUX, args.steps, args.warmup, args.scatter)
+        v32 = r32["updates"] / (r32["ms"] * 1e-3)
+        gm = r64["cons"]
+        p = cfg["nodes"][cfg["tets"]]
+        vol = np.einsum("ij,ij->i", p[:, 1] - p[:, 0],
+                        np.cross(p[:, 2] - p[:, 0], p[:, 3] - p[:, 0])) / 6.0
+        e_rho = float((vol * np.abs(r32["cons"][:, 0] - gm[:, 0])).sum() / (vol * np.abs(gm[:, 0])).sum())
+        e_E = float((vol * np.abs(r32["cons"][:, 4] - gm[:, 4])).sum() / (vol * np.abs(gm[:, 4])).sum())
+        _, roof32 = roofline(r32["prof"], bpi["fp32"])
+        out["forms"] = {"fp32_flux": {
+            "value": round(v32, 1), "ms_per_step": round(r32["ms"] / args.steps, 4),
+            "speedup_vs_fp64": round(v32 / value, 3), "l1_rho": e_rho, "l1_E": e_E,
+            "l1_reference": "FP64 GPU result of the same run (equal to the oracle within 1e-12)",
+            "roofline": roof32}}
+        log(f"fp32 flux: {v32 / 1e9:.3f} G/s, L1 rho {e_rho:.2e}, L1 E {e_E:.2e}")
+    if not args.no_cpu_baseline:
+        log("cpu baseline: oracle, 1 thread ...")
+        out["cpu_baseline"] = cpu_baseline(cfg)
+        log(f"cpu baseline: {out['cpu_baseline']['value']:.0f} cell-updates/s")
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

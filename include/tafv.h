@@ -1,0 +1,211 @@
+/*
+ * tafv: temporal-adaptive finite volumes for the 3D Euler equations on
+ * tetrahedral meshes, on one AMD Instinct MI355X (gfx950).
+ *
+ * The method is the explicit temporal adaptive scheme of Couteyen Carpaye,
+ * Roman, Brenner, "Design and Analysis of a Task-based Parallelization over
+ * a Runtime System of an Explicit Finite-Volume CFD Code with Adaptive Time
+ * Stepping", J. Comput. Sci. 2017:
+ *   - Sec. 2.1, Eq. (1): each cell average changes by the sum over its faces
+ *     of a numerical flux taken from the Riemann problem at the face
+ *     (Godunov's method).  Here: ideal gas, no source term, an exact Riemann
+ *     solver (Newton on the star pressure p*), first order or MUSCL with
+ *     least-squares gradients and the Barth-Jespersen limiter.
+ *   - Sec. 2.2, Alg. 2: every cell gets a maximal time step from a CFL
+ *     condition; the smallest one is dt_min; a cell of level tau advances
+ *     with 2^tau * dt_min; one iteration is 2^theta subiterations; the level
+ *     computed in subiteration s is the largest tau <= theta with 2^tau
+ *     dividing s-1; neighbours differ by at most one level.  A face between
+ *     two levels is computed with the faster side's step and its flux is
+ *     accumulated on both sides, so the slower cell applies the sum when its
+ *     own step ends and mass, momentum and energy are conserved exactly.
+ *   - Sec. 2.2, cost model: the cell-update counter counts
+ *     C(tau) = 2^(theta - tau) |Omega(tau)| per iteration.
+ *
+ * Conventions common to every call
+ *   Status: every call returns a tafv_status; nothing aborts or throws.
+ *     tafv_last_error() returns a message for the last failure on a context.
+ *   Ownership: the caller owns every host array; the library copies inputs
+ *     during the call and keeps no caller pointer.  The context owns all
+ *     device memory it allocates and frees it in tafv_destroy().
+ *   Streams: all device work of a context is enqueued on the HIP stream
+ *     given to tafv_create() (NULL: the null stream).  Calls that return
+ *     data to the host synchronise that stream; tafv_advance() does not wait
+ *     for its work to finish except once per iteration (2^theta
+ *     subiterations), when it reads back the new level counts.
+ *   Layout: host arrays are row-major in the caller's cell order; the device
+ *     layout is internal.
+ *   Threading: a context is not thread-safe; distinct contexts are
+ *     independent.
+ */
+#ifndef TAFV_H
+#define TAFV_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct tafv_ctx tafv_ctx;
+
+typedef enum {
+  TAFV_OK = 0,
+  TAFV_E_ARG = -1,     /* a bad argument (NULL, size, unknown option)        */
+  TAFV_E_MESH = -2,    /* index out of range, non-positive volume, a face
+                          shared by more than two tets                      */
+  TAFV_E_STATE = -3,   /* rho <= 0, p <= 0 or a non-finite initial value     */
+  TAFV_E_ORDER = -4,   /* a call out of order (advance before state_init)    */
+  TAFV_E_DEVICE = -5,  /* a HIP runtime error; the message has its text      */
+  TAFV_E_OOM = -6,     /* device memory allocation failed                    */
+  TAFV_E_NUMERIC = -7, /* a non-finite state after a subiteration            */
+  TAFV_E_MLP = -8      /* reserved for the learned p* guess                  */
+} tafv_status;
+
+enum { TAFV_FP64 = 0, TAFV_FP32_FLUX = 1 };
+enum { TAFV_GUESS_TR = 0, TAFV_GUESS_MLP = 1 };
+enum { TAFV_BC_WALL = 0, TAFV_BC_TRANSMIT = 1 };
+/* How face fluxes reach the cell accumulators.  COLOUR: faces are coloured
+ * so that no two faces of a colour share a cell; one launch per colour
+ * updates both cells of each face with plain read-modify-writes.  GATHER:
+ * one launch stores each active face's time-integrated flux, then every cell
+ * adds its own faces in its fixed local face order.  Both are atomic-free
+ * and deterministic; results agree to rounding. */
+enum { TAFV_SCATTER_COLOUR = 0, TAFV_SCATTER_GATHER = 1 };
+
+/* Method parameters.  tafv_params_default() fills: gamma 1.4, cfl 0.5,
+ * newton_tol 1e-12, level_margin 1e-9, max_levels 5, order 2, precision
+ * TAFV_FP64, guess TAFV_GUESS_TR, boundary TAFV_BC_WALL, newton_max_iter
+ * 50, reclassify 1, scatter TAFV_SCATTER_GATHER. */
+typedef struct {
+  double gamma;          /* ratio of specific heats, > 1                        */
+  double cfl;            /* dt_i = cfl V_i / sum_f (|u_i . n_f| + a_i) |A_f|    */
+  double newton_tol;     /* stop when 2|p_{k+1}-p_k|/(p_{k+1}+p_k) < newton_tol */
+  double level_margin;   /* tau_i = floor(log2(dt_i (1 - margin) / dt_min))     */
+  int32_t max_levels;    /* L in 1..8: levels 0..L-1                            */
+  int32_t order;         /* 1: piecewise constant; 2: MUSCL least squares       */
+  int32_t precision;     /* TAFV_FP64 or TAFV_FP32_FLUX (reconstruction and flux
+                            in FP32; state, accumulators, time steps, levels
+                            and the p* Newton solve in FP64)                    */
+  int32_t guess;         /* initial p* of the Newton solve                      */
+  int32_t boundary;      /* every boundary face: wall or transmissive           */
+  int32_t newton_max_iter; /* Newton updates before bisection takes over       */
+  int32_t reclassify;    /* 1: new levels at every iteration start; 0: keep the
+                            first classification (and its dt_min)               */
+  int32_t scatter;       /* TAFV_SCATTER_COLOUR or TAFV_SCATTER_GATHER          */
+} tafv_params;
+
+/* Counters (int64) and schedule state.  Summed over meshes where a call
+ * covers several. */
+typedef struct {
+  int64_t subiterations;   /* subiterations run (one dt_min unit each)        */
+  int64_t cell_updates;    /* level steps completed by cells: C(tau) summed    */
+  int64_t face_solves;     /* face fluxes computed                             */
+  int64_t newton_updates;  /* Newton updates over all face solves              */
+  int64_t newton_fallbacks;/* face solves that needed bisection                */
+  int64_t vacuum_faces;    /* face solves whose data generate vacuum           */
+  int64_t cells_per_level[8]; /* histogram of the latest classification        */
+  int32_t theta, phase;    /* highest level; subiteration index within the
+                              iteration (0 = every cell synchronised)          */
+  double dt_min, t_reached;/* current dt_min; physical time advanced           */
+  double wall_impulse[3];  /* time-integrated momentum flux through walls      */
+} tafv_stats;
+
+/* Fill *p with the defaults listed above. */
+tafv_status tafv_params_default(tafv_params* p);
+
+/* Create a context on HIP device `device` (made current for every call on
+ * the context).  `hip_stream` is a hipStream_t or NULL.  *out receives the
+ * context; on failure *out is NULL. */
+tafv_status tafv_create(int device, const tafv_params* params, void* hip_stream,
+                        tafv_ctx** out);
+
+/* Free every device buffer of the context and the context itself. */
+tafv_status tafv_destroy(tafv_ctx* ctx);
+
+/* Message of the last failed call on ctx (or of tafv_create when ctx is
+ * NULL); the string lives until the next call on the context. */
+const char* tafv_last_error(const tafv_ctx* ctx);
+
+/* Upload a tetrahedral mesh.  xyz: host [n_nodes][3] node coordinates;
+ * tets: host [n_tets][4] node ids, each tet positively oriented
+ * (det[x1-x0, x2-x0, x3-x0] > 0).  Faces are the sorted vertex triples;
+ * a face with one tet is a boundary face.  Builds the FP64 geometry
+ * (volumes, centroids, area vectors, face centroids, least-squares
+ * weights; Sec. 2.1 finite volumes), a face colouring and the device
+ * arrays.  *mesh_id receives the mesh index (0, 1, ... in upload order).
+ * Errors: TAFV_E_MESH as listed above, TAFV_E_OOM, TAFV_E_DEVICE. */
+tafv_status tafv_mesh_upload(tafv_ctx* ctx, int64_t n_nodes, const double* xyz,
+                             int64_t n_tets, const int64_t* tets, int32_t* mesh_id);
+
+/* Host-only mesh preprocessing, for inspection and tests (no device call):
+ * runs the face extraction, geometry and colouring of tafv_mesh_upload on
+ * host arrays and returns the face count, boundary face count and colour
+ * count.  Optional outputs (NULL to skip; sized with the counts of a first
+ * call): face_cells [n_faces][2] = (lower cell, higher cell or -1) in the
+ * library's face order (colour-major), face_colour [n_faces],
+ * face_area [n_faces][3] (area vector out of the lower cell),
+ * cell_neighbours [n_tets][4] (cell across local face m = the face opposite
+ * vertex m, -1 on the boundary).  Errors as tafv_mesh_upload. */
+tafv_status tafv_mesh_inspect(int64_t n_nodes, const double* xyz, int64_t n_tets,
+                              const int64_t* tets, int64_t* n_faces, int64_t* n_boundary,
+                              int32_t* n_colours, int32_t* face_cells, int8_t* face_colour,
+                              double* face_area, int32_t* cell_neighbours);
+
+/* Per-mesh level cap (1..8), overriding params.max_levels for that mesh. */
+tafv_status tafv_mesh_params(tafv_ctx* ctx, int32_t mesh_id, int32_t max_levels);
+
+/* Set the initial state of a mesh from host prim [n_tets][5] =
+ * (rho, u, v, w, p) and reset its schedule (phase 0, t = 0, counters 0).
+ * TAFV_E_STATE if rho <= 0, p <= 0 or a value is not finite. */
+tafv_status tafv_state_init(tafv_ctx* ctx, int32_t mesh_id, const double* prim);
+
+/* Restore the state given to the last tafv_state_init() of the mesh from a
+ * device-side copy (no host transfer) and reset its schedule (phase 0,
+ * t = 0).  Cumulative counters are kept.  TAFV_E_ORDER without a state. */
+tafv_status tafv_state_reset(tafv_ctx* ctx, int32_t mesh_id);
+
+/* Run n_dt_min subiterations (Alg. 2) on every mesh of the context.  The
+ * phase persists across calls, so a mesh is time-synchronised only when its
+ * phase is 0.  If out is not NULL it receives the counters of this call
+ * (summed over meshes) and the schedule state of the last mesh.
+ * TAFV_E_ORDER if a mesh has no state; TAFV_E_NUMERIC if a state became
+ * non-finite (the call stops at that iteration boundary). */
+tafv_status tafv_advance(tafv_ctx* ctx, int64_t n_dt_min, tafv_stats* out);
+
+/* Cumulative counters and schedule state of one mesh since state_init. */
+tafv_status tafv_mesh_stats(tafv_ctx* ctx, int32_t mesh_id, tafv_stats* out);
+
+/* Copy the conserved state to host cons [n_tets][5] = (rho, rho u, rho v,
+ * rho w, E) and, if levels is not NULL, the levels to host [n_tets]. */
+tafv_status tafv_state_read(tafv_ctx* ctx, int32_t mesh_id, double* cons,
+                            int8_t* levels);
+
+/* Full schedule state (checkpoint): conserved state, flux accumulators
+ * accum [n_tets][5] (time-integrated flux not yet applied by cells whose
+ * step has not ended), levels, phase, theta, dt_min and time.  Restoring a
+ * checkpoint with tafv_checkpoint_write() and advancing reproduces the
+ * uninterrupted run bit for bit. */
+tafv_status tafv_checkpoint_read(tafv_ctx* ctx, int32_t mesh_id, double* cons,
+                                 double* accum, int8_t* levels, int32_t* phase,
+                                 int32_t* theta, double* dt_min, double* t);
+tafv_status tafv_checkpoint_write(tafv_ctx* ctx, int32_t mesh_id, const double* cons,
+                                  const double* accum, const int8_t* levels,
+                                  int32_t phase, int32_t theta, double dt_min,
+                                  double t);
+
+/* Per-kernel timing: when enabled, tafv_advance() brackets every launch of
+ * each kernel class with HIP events on the context stream.
+ * tafv_profile_read() returns, per class k < n, the summed launch time in
+ * ms, the number of launches and the work items (faces or cells) processed,
+ * and the class name in names[k] (static strings).  Reading synchronises
+ * the stream and resets the sums. */
+tafv_status tafv_profile_enable(tafv_ctx* ctx, int32_t on);
+tafv_status tafv_profile_read(tafv_ctx* ctx, int32_t n, double* ms, int64_t* launches,
+                              int64_t* items, const char** names, int32_t* n_classes);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,662 @@
+// C-ABI of the tafv library: context, mesh upload, state, the subiteration
+// driver of Alg. 2 (Sec. 2.2), checkpoints, counters and per-kernel timing.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <string>
+
+#include "kernels.h"
+#include "tafv_internal.h"
+
+using namespace tafv;
+
+namespace {
+
+const char* kProfNames[] = {"classify", "grad", "flux", "update", "gather"};
+enum { P_CLASSIFY = 0, P_GRAD = 1, P_FLUX = 2, P_UPDATE = 3, P_GATHER = 4, P_N = 5 };
+
+thread_local std::string g_create_err;
+
+tafv_status fail(tafv_ctx* c, tafv_status st, const std::string& msg) {
+  if (c) c->err = msg;
+  else g_create_err = msg;
+  return st;
+}
+
+tafv_status hip_fail(tafv_ctx* c, hipError_t e, const char* what) {
+  std::string msg = std::string(what) + ": " + hipGetErrorString(e);
+  return fail(c, e == hipErrorOutOfMemory ? TAFV_E_OOM : TAFV_E_DEVICE, msg);
+}
+
+#define HIP_TRY(c, expr)                                   \
+  do {                                                     \
+    hipError_t e_ = (expr);                                \
+    if (e_ != hipSuccess) return hip_fail((c), e_, #expr); \
+  } while (0)
+
+template <typename T>
+hipError_t dalloc(T** p, size_t n) {
+  return hipMalloc((void**)p, std::max<size_t>(n, 1) * sizeof(T));
+}
+
+void free_mesh(DevMesh* m) {
+  if (!m) return;
+  void* ptrs[] = {m->fhL, m->fhR, m->fcol, m->fA, m->fA32, m->nb_, m->c2f, m->lsq, m->rf,
+                  m->vol, m->lsq32, m->rf32, m->U, m->U0, m->R, m->lev, m->lev2, m->dt, m->Wf,
+                  m->pf.list, m->pf.counts, m->pf.start, m->pg.list, m->pg.counts,
+                  m->pg.start, m->pu.list, m->pu.counts, m->pu.start, m->dscal, m->dcount,
+                  m->dimpulse, m->pf.offs, m->pg.offs, m->pu.offs, m->pf.scan_tmp,
+                  m->pg.scan_tmp, m->pu.scan_tmp, m->Q, m->frec};
+  for (void* p : ptrs)
+    if (p) (void)hipFree(p);
+  delete m;
+}
+
+StepArgs step_args(const tafv_ctx* c, const DevMesh& m) {
+  StepArgs a;
+  a.gas = make_gas(c->prm.gamma);
+  a.cfl = c->prm.cfl;
+  a.newton_tol = c->prm.newton_tol;
+  a.level_margin = c->prm.level_margin;
+  a.dt_min = m.dt_min;
+  a.newton_max_iter = c->prm.newton_max_iter;
+  a.boundary = c->prm.boundary;
+  a.max_levels = m.max_levels;
+  a.precision = c->prm.precision;
+  a.order = c->prm.order;
+  return a;
+}
+
+// level computed in subiteration s = 1..2^theta (Alg. 2): the largest
+// tau <= theta with 2^tau dividing s - 1 (theta itself for s = 1)
+int subiteration_level(int64_t s, int theta) {
+  if (s == 1) return theta;
+  int t = 0;
+  int64_t x = s - 1;
+  while (!(x & 1) && t < theta) {
+    x >>= 1;
+    ++t;
+  }
+  return t;
+}
+
+// ---- profiling ----------------------------------------------------------
+
+struct ProfScope {
+  tafv_ctx* c;
+  int cls;
+  int64_t items;
+  hipEvent_t a = nullptr, b = nullptr;
+  ProfScope(tafv_ctx* c_, int cls_, int64_t items_) : c(c_), cls(cls_), items(items_) {
+    if (!c->profile) return;
+    a = take();
+    b = take();
+    (void)hipEventRecord(a, c->stream);
+  }
+  ~ProfScope() {
+    if (!c->profile) return;
+    (void)hipEventRecord(b, c->stream);
+    c->pending.push_back({a, b, cls, items});
+  }
+  hipEvent_t take() {
+    if (!c->event_pool.empty()) {
+      hipEvent_t e = c->event_pool.back();
+      c->event_pool.pop_back();
+      return e;
+    }
+    hipEvent_t e = nullptr;
+    (void)hipEventCreate(&e);
+    return e;
+  }
+};
+
+// ---- classification at an iteration start ------------------------------
+
+tafv_status classify(tafv_ctx* c, DevMesh& m) {
+  StepArgs a = step_args(c, m);
+  {
+    ProfScope ps(c, P_CLASSIFY, m.nc);
+    HIP_TRY(c, launch_fill_u64(c->stream, m.dscal, 0x7ff0000000000000ull, 1));  // +inf
+    HIP_TRY(c, launch_dt(c->stream, m, a));
+    HIP_TRY(c, launch_classify(c->stream, m, a));
+    HIP_TRY(c, launch_partitions(c->stream, m));
+  }
+  // read back: dt_min, flag, list starts
+  int K = m.scatter == TAFV_SCATTER_COLOUR ? m.ncolours * kMaxLevels : kMaxLevels;
+  int32_t* h = c->hpin;
+  HIP_TRY(c, hipMemcpyAsync(h, m.dscal, 3 * sizeof(unsigned long long), hipMemcpyDeviceToHost,
+                            c->stream));
+  HIP_TRY(c, hipMemcpyAsync(h + 8, m.pf.start, (K + 1) * sizeof(int32_t), hipMemcpyDeviceToHost,
+                            c->stream));
+  HIP_TRY(c, hipMemcpyAsync(h + 8 + kMaxKeys + 1, m.pg.start, (kMaxLevels + 1) * sizeof(int32_t),
+                            hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(c, hipMemcpyAsync(h + 8 + kMaxKeys + kMaxLevels + 2, m.pu.start,
+                            (kMaxLevels + 1) * sizeof(int32_t), hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  unsigned long long bits[3];
+  std::memcpy(bits, h, sizeof(bits));
+  if (bits[2]) return fail(c, TAFV_E_NUMERIC, "non-finite or non-physical cell state");
+  double dtmin;
+  std::memcpy(&dtmin, &bits[0], sizeof(double));
+  if (!(dtmin > 0.0) || !std::isfinite(dtmin))
+    return fail(c, TAFV_E_NUMERIC, "no valid time step");
+  m.dt_min = dtmin;
+  std::memcpy(m.hstart_f, h + 8, (K + 1) * sizeof(int32_t));
+  std::memcpy(m.hstart_g, h + 8 + kMaxKeys + 1, (kMaxLevels + 1) * sizeof(int32_t));
+  std::memcpy(m.hstart_u, h + 8 + kMaxKeys + kMaxLevels + 2, (kMaxLevels + 1) * sizeof(int32_t));
+  int theta = 0;
+  for (int t = 0; t < kMaxLevels; ++t) {
+    int64_t n = m.hstart_u[t + 1] - m.hstart_u[t];
+    m.st.cells_per_level[t] = n;
+    if (n > 0) theta = t;
+  }
+  m.theta = theta;
+  m.classified = true;
+  return TAFV_OK;
+}
+
+tafv_status subiteration(tafv_ctx* c, DevMesh& m, tafv_stats* acc) {
+  if (m.phase == 0 && (c->prm.reclassify || !m.classified)) {
+    tafv_status st = classify(c, m);
+    if (st != TAFV_OK) return st;
+  }
+  StepArgs a = step_args(c, m);
+  int tau_s = subiteration_level((int64_t)m.phase + 1, m.theta);
+  if (c->prm.order == 2) {
+    int cnt = m.hstart_g[tau_s + 1];
+    ProfScope ps(c, P_GRAD, cnt);
+    HIP_TRY(c, launch_grad(c->stream, m, a, cnt));
+  }
+  int64_t s = (int64_t)m.phase + 1;
+  // cells whose step ends after this subiteration: tau_i <= min(theta, ctz(s))
+  int upd = 0;
+  {
+    int64_t x = s;
+    while (!(x & 1) && upd < m.theta) {
+      x >>= 1;
+      ++upd;
+    }
+  }
+  int ucnt = m.hstart_u[upd + 1];
+  int64_t faces = 0;
+  if (m.scatter == TAFV_SCATTER_COLOUR) {
+    for (int col = 0; col < m.ncolours; ++col) {
+      int first = m.hstart_f[col * kMaxLevels];
+      int cnt = m.hstart_f[col * kMaxLevels + tau_s + 1] - first;
+      faces += cnt;
+      ProfScope ps(c, P_FLUX, cnt);
+      HIP_TRY(c, launch_flux(c->stream, m, a, first, cnt));
+    }
+    ProfScope ps(c, P_UPDATE, ucnt);
+    HIP_TRY(c, launch_update(c->stream, m, ucnt));
+  } else {
+    int cnt = m.hstart_f[tau_s + 1];
+    faces = cnt;
+    {
+      ProfScope ps(c, P_FLUX, cnt);
+      HIP_TRY(c, launch_flux(c->stream, m, a, 0, cnt));
+    }
+    int ccnt = m.hstart_g[std::max(tau_s, upd) + 1];
+    ProfScope ps(c, P_GATHER, ccnt);
+    HIP_TRY(c, launch_cell_gather(c->stream, m, ccnt, tau_s, upd));
+  }
+  m.phase = (int32_t)(s % ((int64_t)1 << m.theta));
+  m.t += m.dt_min;
+  m.st.subiterations++;
+  m.st.cell_updates += ucnt;
+  m.st.face_solves += faces;
+  if (acc) {
+    acc->subiterations++;
+    acc->cell_updates += ucnt;
+    acc->face_solves += faces;
+  }
+  return TAFV_OK;
+}
+
+tafv_status read_counters(tafv_ctx* c, DevMesh& m) {
+  std::vector<unsigned long long> cnt(kCounterWords);
+  std::vector<double> imp(kCounterWords);
+  HIP_TRY(c, hipMemcpyAsync(cnt.data(), m.dcount, kCounterWords * sizeof(unsigned long long),
+                            hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(c, hipMemcpyAsync(imp.data(), m.dimpulse, kCounterWords * sizeof(double),
+                            hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  unsigned long long tot[3] = {0, 0, 0};
+  double itot[3] = {0, 0, 0};
+  for (int sl = 0; sl < kCounterSlots; ++sl)
+    for (int k = 0; k < 3; ++k) {
+      tot[k] += cnt[sl * kCounterStride + k];
+      itot[k] += imp[sl * kCounterStride + k];
+    }
+  m.st.newton_updates = (int64_t)tot[0];
+  m.st.newton_fallbacks = (int64_t)tot[1];
+  m.st.vacuum_faces = (int64_t)tot[2];
+  for (int k = 0; k < 3; ++k) m.st.wall_impulse[k] = itot[k];
+  m.st.theta = m.theta;
+  m.st.phase = m.phase;
+  m.st.dt_min = m.dt_min;
+  m.st.t_reached = m.t;
+  return TAFV_OK;
+}
+
+DevMesh* get_mesh(tafv_ctx* c, int32_t id) {
+  if (!c || id < 0 || id >= (int32_t)c->meshes.size()) return nullptr;
+  return c->meshes[id];
+}
+
+}  // namespace
+
+extern "C" {
+
+tafv_status tafv_params_default(tafv_params* p) {
+  if (!p) return TAFV_E_ARG;
+  p->gamma = 1.4;
+  p->cfl = 0.5;
+  p->newton_tol = 1e-12;
+  p->level_margin = 1e-9;
+  p->max_levels = 5;
+  p->order = 2;
+  p->precision = TAFV_FP64;
+  p->guess = TAFV_GUESS_TR;
+  p->boundary = TAFV_BC_WALL;
+  p->newton_max_iter = 50;
+  p->reclassify = 1;
+  p->scatter = TAFV_SCATTER_GATHER;
+  return TAFV_OK;
+}
+
+tafv_status tafv_create(int device, const tafv_params* params, void* hip_stream,
+                        tafv_ctx** out) {
+  if (!out) return fail(nullptr, TAFV_E_ARG, "out is NULL");
+  *out = nullptr;
+  if (!params) return fail(nullptr, TAFV_E_ARG, "params is NULL");
+  const tafv_params& p = *params;
+  if (!(p.gamma > 1.0) || !(p.cfl > 0.0) || !(p.newton_tol > 0.0) || p.max_levels < 1 ||
+      p.max_levels > kMaxLevels || (p.order != 1 && p.order != 2) ||
+      (p.precision != TAFV_FP64 && p.precision != TAFV_FP32_FLUX) ||
+      (p.boundary != TAFV_BC_WALL && p.boundary != TAFV_BC_TRANSMIT) || p.newton_max_iter < 1 ||
+      (p.scatter != TAFV_SCATTER_COLOUR && p.scatter != TAFV_SCATTER_GATHER) ||
+      !(p.level_margin >= 0.0 && p.level_margin < 0.5))
+    return fail(nullptr, TAFV_E_ARG, "invalid parameters");
+  if (p.guess != TAFV_GUESS_TR) return fail(nullptr, TAFV_E_ARG, "unsupported guess mode");
+  int ndev = 0;
+  hipError_t e = hipGetDeviceCount(&ndev);
+  if (e != hipSuccess || ndev == 0) return fail(nullptr, TAFV_E_DEVICE, "no HIP device");
+  if (device < 0 || device >= ndev) return fail(nullptr, TAFV_E_ARG, "device out of range");
+  e = hipSetDevice(device);
+  if (e != hipSuccess) return hip_fail(nullptr, e, "hipSetDevice");
+  tafv_ctx* c = new (std::nothrow) tafv_ctx();
+  if (!c) return fail(nullptr, TAFV_E_OOM, "host allocation failed");
+  c->device = device;
+  c->stream = (hipStream_t)hip_stream;
+  c->prm = p;
+  e = hipHostMalloc((void**)&c->hpin, 4096, hipHostMallocDefault);
+  if (e != hipSuccess) {
+    delete c;
+    return hip_fail(nullptr, e, "hipHostMalloc");
+  }
+  for (int k = 0; k < P_N; ++k) c->prof.push_back(ProfileClass{kProfNames[k]});
+  *out = c;
+  return TAFV_OK;
+}
+
+tafv_status tafv_destroy(tafv_ctx* c) {
+  if (!c) return TAFV_E_ARG;
+  (void)hipSetDevice(c->device);
+  (void)hipStreamSynchronize(c->stream);
+  for (DevMesh* m : c->meshes) free_mesh(m);
+  for (auto& pe : c->pending) {
+    (void)hipEventDestroy(pe.a);
+    (void)hipEventDestroy(pe.b);
+  }
+  for (hipEvent_t e : c->event_pool) (void)hipEventDestroy(e);
+  if (c->hpin) (void)hipHostFree(c->hpin);
+  delete c;
+  return TAFV_OK;
+}
+
+const char* tafv_last_error(const tafv_ctx* c) {
+  return c ? c->err.c_str() : g_create_err.c_str();
+}
+
+tafv_status tafv_mesh_upload(tafv_ctx* c, int64_t n_nodes, const double* xyz, int64_t n_tets,
+                             const int64_t* tets, int32_t* mesh_id) {
+  if (!c) return TAFV_E_ARG;
+  if (!xyz || !tets || !mesh_id || n_nodes < 4 || n_tets < 1)
+    return fail(c, TAFV_E_ARG, "invalid mesh arguments");
+  HIP_TRY(c, hipSetDevice(c->device));
+  HostMesh hm;
+  tafv_status st = build_host_mesh(n_nodes, xyz, n_tets, tets,
+                                   c->prm.scatter == TAFV_SCATTER_COLOUR, &hm, &c->err);
+  if (st != TAFV_OK) return st;
+  DevMesh* m = new (std::nothrow) DevMesh();
+  if (!m) return fail(c, TAFV_E_OOM, "host allocation failed");
+  m->nc = (int32_t)hm.nc;
+  m->nf = (int32_t)hm.nf;
+  m->nb = (int32_t)hm.nbnd;
+  m->ncolours = hm.ncolours;
+  m->max_levels = c->prm.max_levels;
+  m->scatter = c->prm.scatter;
+  for (int k = 0; k <= kMaxColours; ++k) m->colour_start[k] = hm.colour_start[k];
+  const size_t nc = hm.nc, nf = hm.nf;
+  std::vector<float> f32;
+  auto up = [&](auto* dst, const auto& src) {
+    return hipMemcpy(dst, src.data(), src.size() * sizeof(src[0]), hipMemcpyHostToDevice);
+  };
+  hipError_t e = hipSuccess;
+  auto chk = [&](hipError_t x) {
+    if (e == hipSuccess) e = x;
+  };
+  chk(dalloc(&m->fhL, nf));
+  chk(dalloc(&m->fhR, nf));
+  chk(dalloc(&m->fcol, nf));
+  chk(dalloc(&m->fA, 3 * nf));
+  chk(dalloc(&m->fA32, 3 * nf));
+  chk(dalloc(&m->nb_, 4 * nc));
+  chk(dalloc(&m->c2f, 4 * nc));
+  chk(dalloc(&m->lsq, 12 * nc));
+  chk(dalloc(&m->rf, 12 * nc));
+  chk(dalloc(&m->lsq32, 12 * nc));
+  chk(dalloc(&m->rf32, 12 * nc));
+  chk(dalloc(&m->vol, nc));
+  chk(dalloc(&m->U, 5 * nc));
+  chk(dalloc(&m->U0, 5 * nc));
+  chk(dalloc(&m->R, 5 * nc));
+  chk(dalloc(&m->lev, nc));
+  chk(dalloc(&m->lev2, nc));
+  chk(dalloc(&m->dt, nc));
+  size_t wfbytes = (c->prm.precision == TAFV_FP32_FLUX ? sizeof(float) : sizeof(double)) * 20 * nc;
+  if (c->prm.order == 2) chk(hipMalloc(&m->Wf, wfbytes));
+  int pbf = partition_blocks(nf), pbc = partition_blocks(nc);
+  for (Partition* p : {&m->pf, &m->pg, &m->pu}) {
+    int64_t n = (p == &m->pf) ? (int64_t)nf : (int64_t)nc;
+    p->scan_bytes = partition_scan_bytes(n);
+    chk(hipMalloc(&p->scan_tmp, std::max<size_t>(p->scan_bytes, 16)));
+    chk(dalloc(&p->offs, (size_t)kMaxKeys * partition_blocks(n)));
+  }
+  chk(dalloc(&m->frec, nf));
+  if (m->scatter == TAFV_SCATTER_GATHER) chk(dalloc(&m->Q, 5 * nf));
+  chk(dalloc(&m->pf.list, nf));
+  chk(dalloc(&m->pf.counts, (size_t)kMaxKeys * pbf));
+  chk(dalloc(&m->pf.start, kMaxKeys + 1));
+  chk(dalloc(&m->pg.list, nc));
+  chk(dalloc(&m->pg.counts, (size_t)kMaxKeys * pbc));
+  chk(dalloc(&m->pg.start, kMaxKeys + 1));
+  chk(dalloc(&m->pu.list, nc));
+  chk(dalloc(&m->pu.counts, (size_t)kMaxKeys * pbc));
+  chk(dalloc(&m->pu.start, kMaxKeys + 1));
+  chk(dalloc(&m->dscal, 4));
+  chk(dalloc(&m->dcount, kCounterWords));
+  chk(dalloc(&m->dimpulse, kCounterWords));
+  if (e != hipSuccess) {
+    free_mesh(m);
+    return hip_fail(c, e, "device allocation for the mesh");
+  }
+  chk(up(m->fhL, hm.fhL));
+  chk(up(m->fhR, hm.fhR));
+  chk(up(m->fcol, hm.fcol));
+  chk(up(m->fA, hm.fA));
+  f32.assign(hm.fA.begin(), hm.fA.end());
+  chk(up(m->fA32, f32));
+  chk(up(m->nb_, hm.nb));
+  chk(up(m->c2f, hm.c2f));
+  chk(up(m->lsq, hm.lsq));
+  chk(up(m->rf, hm.rf));
+  f32.assign(hm.lsq.begin(), hm.lsq.end());
+  chk(up(m->lsq32, f32));
+  f32.assign(hm.rf.begin(), hm.rf.end());
+  chk(up(m->rf32, f32));
+  chk(up(m->vol, hm.vol));
+  if (e != hipSuccess) {
+    free_mesh(m);
+    return hip_fail(c, e, "mesh upload");
+  }
+  *mesh_id = (int32_t)c->meshes.size();
+  c->meshes.push_back(m);
+  return TAFV_OK;
+}
+
+tafv_status tafv_mesh_inspect(int64_t n_nodes, const double* xyz, int64_t n_tets,
+                              const int64_t* tets, int64_t* n_faces, int64_t* n_boundary,
+                              int32_t* n_colours, int32_t* face_cells, int8_t* face_colour,
+                              double* face_area, int32_t* cell_neighbours) {
+  if (!xyz || !tets || n_nodes < 4 || n_tets < 1) return fail(nullptr, TAFV_E_ARG, "invalid mesh");
+  HostMesh hm;
+  std::string err;
+  tafv_status st = build_host_mesh(n_nodes, xyz, n_tets, tets, true, &hm, &err);
+  if (st != TAFV_OK) return fail(nullptr, st, err);
+  if (n_faces) *n_faces = hm.nf;
+  if (n_boundary) *n_boundary = hm.nbnd;
+  if (n_colours) *n_colours = hm.ncolours;
+  for (int64_t f = 0; f < hm.nf; ++f) {
+    if (face_cells) {
+      face_cells[2 * f] = hm.fhL[f] >> 2;
+      face_cells[2 * f + 1] = hm.fhR[f] >= 0 ? (hm.fhR[f] >> 2) : -1;
+    }
+    if (face_colour) face_colour[f] = hm.fcol[f];
+    if (face_area)
+      for (int k = 0; k < 3; ++k) face_area[3 * f + k] = hm.fA[k * hm.nf + f];
+  }
+  if (cell_neighbours)
+    for (int64_t i = 0; i < hm.nc; ++i)
+      for (int m = 0; m < 4; ++m) {
+        int32_t n = hm.nb[m * hm.nc + i];
+        cell_neighbours[4 * i + m] = n >= 0 ? n : -1;
+      }
+  return TAFV_OK;
+}
+
+tafv_status tafv_mesh_params(tafv_ctx* c, int32_t mesh_id, int32_t max_levels) {
+  DevMesh* m = get_mesh(c, mesh_id);
+  if (!m) return c ? fail(c, TAFV_E_ARG, "unknown mesh") : TAFV_E_ARG;
+  if (max_levels < 1 || max_levels > kMaxLevels) return fail(c, TAFV_E_ARG, "max_levels out of range");
+  m->max_levels = max_levels;
+  m->classified = false;
+  return TAFV_OK;
+}
+
+tafv_status tafv_state_init(tafv_ctx* c, int32_t mesh_id, const double* prim) {
+  DevMesh* m = get_mesh(c, mesh_id);
+  if (!m) return c ? fail(c, TAFV_E_ARG, "unknown mesh") : TAFV_E_ARG;
+  if (!prim) return fail(c, TAFV_E_ARG, "prim is NULL");
+  for (int64_t i = 0; i < m->nc; ++i) {
+    const double* w = prim + 5 * i;
+    for (int k = 0; k < 5; ++k)
+      if (!std::isfinite(w[k]))
+        return fail(c, TAFV_E_STATE, "non-finite initial value at cell " + std::to_string(i));
+    if (!(w[0] > 0.0) || !(w[4] > 0.0))
+      return fail(c, TAFV_E_STATE, "rho <= 0 or p <= 0 at cell " + std::to_string(i));
+  }
+  HIP_TRY(c, hipSetDevice(c->device));
+  double* d_prim = nullptr;
+  HIP_TRY(c, hipMalloc(&d_prim, sizeof(double) * 5 * m->nc));
+  hipError_t e = hipMemcpyAsync(d_prim, prim, sizeof(double) * 5 * m->nc, hipMemcpyHostToDevice,
+                                c->stream);
+  if (e == hipSuccess) e = launch_state_init(c->stream, *m, d_prim, c->prm.gamma);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(m->U0, m->U, sizeof(double) * 5 * m->nc, hipMemcpyDeviceToDevice,
+                       c->stream);
+  if (e == hipSuccess) e = launch_fill_u64(c->stream, m->dcount, 0ull, kCounterWords);
+  if (e == hipSuccess) e = launch_fill_f64(c->stream, m->dimpulse, 0.0, kCounterWords);
+  if (e == hipSuccess) e = launch_fill_u64(c->stream, m->dscal, 0ull, 4);
+  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  (void)hipFree(d_prim);
+  if (e != hipSuccess) return hip_fail(c, e, "state init");
+  m->has_state = true;
+  m->phase = 0;
+  m->theta = 0;
+  m->t = 0.0;
+  m->dt_min = 0.0;
+  m->classified = false;
+  m->st = tafv_stats{};
+  return TAFV_OK;
+}
+
+tafv_status tafv_state_reset(tafv_ctx* c, int32_t mesh_id) {
+  DevMesh* m = get_mesh(c, mesh_id);
+  if (!m) return c ? fail(c, TAFV_E_ARG, "unknown mesh") : TAFV_E_ARG;
+  if (!m->has_state) return fail(c, TAFV_E_ORDER, "no state");
+  HIP_TRY(c, hipSetDevice(c->device));
+  HIP_TRY(c, hipMemcpyAsync(m->U, m->U0, sizeof(double) * 5 * m->nc, hipMemcpyDeviceToDevice,
+                            c->stream));
+  HIP_TRY(c, launch_fill_f64(c->stream, m->R, 0.0, (int64_t)5 * m->nc));
+  m->phase = 0;
+  m->theta = 0;
+  m->t = 0.0;
+  m->dt_min = 0.0;
+  m->classified = false;
+  return TAFV_OK;
+}
+
+tafv_status tafv_advance(tafv_ctx* c, int64_t n, tafv_stats* out) {
+  if (!c) return TAFV_E_ARG;
+  if (n < 0) return fail(c, TAFV_E_ARG, "negative subiteration count");
+  if (c->meshes.empty()) return fail(c, TAFV_E_ORDER, "no mesh uploaded");
+  for (DevMesh* m : c->meshes)
+    if (!m->has_state) return fail(c, TAFV_E_ORDER, "advance before state_init");
+  HIP_TRY(c, hipSetDevice(c->device));
+  tafv_stats acc{};
+  for (int64_t k = 0; k < n; ++k) {
+    for (DevMesh* m : c->meshes) {
+      tafv_status st = subiteration(c, *m, &acc);
+      if (st != TAFV_OK) return st;
+    }
+  }
+  if (out) {
+    for (DevMesh* m : c->meshes) {
+      tafv_status st = read_counters(c, *m);
+      if (st != TAFV_OK) return st;
+    }
+    DevMesh* last = c->meshes.back();
+    acc.theta = last->theta;
+    acc.phase = last->phase;
+    acc.dt_min = last->dt_min;
+    acc.t_reached = last->t;
+    for (int t = 0; t < kMaxLevels; ++t) acc.cells_per_level[t] = last->st.cells_per_level[t];
+    *out = acc;
+  }
+  return TAFV_OK;
+}
+
+tafv_status tafv_mesh_stats(tafv_ctx* c, int32_t mesh_id, tafv_stats* out) {
+  DevMesh* m = get_mesh(c, mesh_id);
+  if (!m) return c ? fail(c, TAFV_E_ARG, "unknown mesh") : TAFV_E_ARG;
+  if (!out) return fail(c, TAFV_E_ARG, "out is NULL");
+  HIP_TRY(c, hipSetDevice(c->device));
+  tafv_status st = read_counters(c, *m);
+  if (st != TAFV_OK) return st;
+  *out = m->st;
+  return TAFV_OK;
+}
+
+tafv_status tafv_state_read(tafv_ctx* c, int32_t mesh_id, double* cons, int8_t* levels) {
+  DevMesh* m = get_mesh(c, mesh_id);
+  if (!m) return c ? fail(c, TAFV_E_ARG, "unknown mesh") : TAFV_E_ARG;
+  if (!cons) return fail(c, TAFV_E_ARG, "cons is NULL");
+  if (!m->has_state) return fail(c, TAFV_E_ORDER, "no state");
+  HIP_TRY(c, hipSetDevice(c->device));
+  HIP_TRY(c, hipMemcpyAsync(cons, m->U, sizeof(double) * 5 * m->nc, hipMemcpyDeviceToHost,
+                            c->stream));
+  if (levels)
+    HIP_TRY(c, hipMemcpyAsync(levels, m->lev, m->nc, hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  return TAFV_OK;
+}
+
+tafv_status tafv_checkpoint_read(tafv_ctx* c, int32_t mesh_id, double* cons, double* accum,
+                                 int8_t* levels, int32_t* phase, int32_t* theta, double* dt_min,
+                                 double* t) {
+  DevMesh* m = get_mesh(c, mesh_id);
+  if (!m) return c ? fail(c, TAFV_E_ARG, "unknown mesh") : TAFV_E_ARG;
+  if (!cons || !accum || !levels || !phase || !theta || !dt_min || !t)
+    return fail(c, TAFV_E_ARG, "NULL argument");
+  if (!m->has_state) return fail(c, TAFV_E_ORDER, "no state");
+  HIP_TRY(c, hipSetDevice(c->device));
+  HIP_TRY(c, hipMemcpyAsync(cons, m->U, sizeof(double) * 5 * m->nc, hipMemcpyDeviceToHost,
+                            c->stream));
+  HIP_TRY(c, hipMemcpyAsync(accum, m->R, sizeof(double) * 5 * m->nc, hipMemcpyDeviceToHost,
+                            c->stream));
+  HIP_TRY(c, hipMemcpyAsync(levels, m->lev, m->nc, hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  *phase = m->phase;
+  *theta = m->theta;
+  *dt_min = m->dt_min;
+  *t = m->t;
+  return TAFV_OK;
+}
+
+tafv_status tafv_checkpoint_write(tafv_ctx* c, int32_t mesh_id, const double* cons,
+                                  const double* accum, const int8_t* levels, int32_t phase,
+                                  int32_t theta, double dt_min, double t) {
+  DevMesh* m = get_mesh(c, mesh_id);
+  if (!m) return c ? fail(c, TAFV_E_ARG, "unknown mesh") : TAFV_E_ARG;
+  if (!cons || !accum || !levels) return fail(c, TAFV_E_ARG, "NULL argument");
+  if (theta < 0 || theta >= m->max_levels || phase < 0 || phase >= (1 << theta) ||
+      !(dt_min > 0.0))
+    return fail(c, TAFV_E_ARG, "invalid schedule state");
+  for (int64_t i = 0; i < m->nc; ++i)
+    if (levels[i] < 0 || levels[i] > theta) return fail(c, TAFV_E_ARG, "level out of range");
+  HIP_TRY(c, hipSetDevice(c->device));
+  HIP_TRY(c, hipMemcpyAsync(m->U, cons, sizeof(double) * 5 * m->nc, hipMemcpyHostToDevice,
+                            c->stream));
+  HIP_TRY(c, hipMemcpyAsync(m->R, accum, sizeof(double) * 5 * m->nc, hipMemcpyHostToDevice,
+                            c->stream));
+  HIP_TRY(c, hipMemcpyAsync(m->lev, levels, m->nc, hipMemcpyHostToDevice, c->stream));
+  HIP_TRY(c, launch_partitions(c->stream, *m));
+  int K = m->scatter == TAFV_SCATTER_COLOUR ? m->ncolours * kMaxLevels : kMaxLevels;
+  HIP_TRY(c, hipMemcpyAsync(m->hstart_f, m->pf.start, (K + 1) * sizeof(int32_t),
+                            hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(c, hipMemcpyAsync(m->hstart_g, m->pg.start, (kMaxLevels + 1) * sizeof(int32_t),
+                            hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(c, hipMemcpyAsync(m->hstart_u, m->pu.start, (kMaxLevels + 1) * sizeof(int32_t),
+                            hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  for (int k = 0; k < kMaxLevels; ++k) m->st.cells_per_level[k] = m->hstart_u[k + 1] - m->hstart_u[k];
+  m->has_state = true;
+  m->phase = phase;
+  m->theta = theta;
+  m->dt_min = dt_min;
+  m->t = t;
+  m->classified = true;
+  return TAFV_OK;
+}
+
+tafv_status tafv_profile_enable(tafv_ctx* c, int32_t on) {
+  if (!c) return TAFV_E_ARG;
+  c->profile = on != 0;
+  return TAFV_OK;
+}
+
+tafv_status tafv_profile_read(tafv_ctx* c, int32_t n, double* ms, int64_t* launches,
+                              int64_t* items, const char** names, int32_t* n_classes) {
+  if (!c) return TAFV_E_ARG;
+  HIP_TRY(c, hipSetDevice(c->device));
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  for (auto& pe : c->pending) {
+    float t = 0.f;
+    HIP_TRY(c, hipEventElapsedTime(&t, pe.a, pe.b));
+    c->prof[pe.cls].ms += t;
+    c->prof[pe.cls].launches += 1;
+    c->prof[pe.cls].items += pe.items;
+    c->event_pool.push_back(pe.a);
+    c->event_pool.push_back(pe.b);
+  }
+  c->pending.clear();
+  int nc = (int)c->prof.size();
+  if (n_classes) *n_classes = nc;
+  for (int k = 0; k < std::min(n, nc); ++k) {
+    if (ms) ms[k] = c->prof[k].ms;
+    if (launches) launches[k] = c->prof[k].launches;
+    if (items) items[k] = c->prof[k].items;
+    if (names) names[k] = c->prof[k].name;
+    c->prof[k].ms = 0.0;
+    c->prof[k].launches = 0;
+    c->prof[k].items = 0;
+  }
+  return TAFV_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,31 @@
+// Launchers of the device kernels (defined in kernels.hip).
+#pragma once
+
+#include "gas.h"
+#include "tafv_internal.h"
+
+namespace tafv {
+
+// Per-launch parameters shared by the face and cell kernels.
+struct StepArgs {
+  Gas gas;
+  double cfl, newton_tol, level_margin, dt_min;
+  int newton_max_iter, boundary, max_levels, precision, order;
+};
+
+hipError_t launch_state_init(hipStream_t s, DevMesh& m, const double* d_prim, double gamma);
+hipError_t launch_dt(hipStream_t s, DevMesh& m, const StepArgs& a);
+hipError_t launch_classify(hipStream_t s, DevMesh& m, const StepArgs& a);
+hipError_t launch_partitions(hipStream_t s, DevMesh& m);
+hipError_t launch_grad(hipStream_t s, DevMesh& m, const StepArgs& a, int count);
+hipError_t launch_flux(hipStream_t s, DevMesh& m, const StepArgs& a, int first, int count);
+hipError_t launch_cell_gather(hipStream_t s, DevMesh& m, int count, int tau_s, int tau_upd);
+hipError_t launch_update(hipStream_t s, DevMesh& m, int count);
+hipError_t launch_fill_u64(hipStream_t s, unsigned long long* p, unsigned long long v, int n);
+hipError_t launch_fill_f64(hipStream_t s, double* p, double v, int64_t n);
+
+// partition scratch sizes
+int partition_blocks(int64_t n);
+size_t partition_scan_bytes(int64_t n);
+
+}  // namespace tafv

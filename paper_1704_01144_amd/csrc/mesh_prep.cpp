@@ -1,0 +1,243 @@
+// Host mesh preprocessing: faces of a tetrahedral mesh, FP64 geometry, a
+// face colouring for the atomic-free scatter, and least-squares weights.
+//
+// Finite volumes (Sec. 2.1, Eq. (1)) need per cell its volume and the outward
+// area vectors of its faces; the MUSCL reconstruction needs, per cell, the
+// weighted least-squares gradient operator over its 4 face neighbours and
+// the offsets from the cell centroid to its face centroids.
+#include <algorithm>
+#include <cmath>
+#include <numeric>
+
+#include "tafv_internal.h"
+
+namespace tafv {
+namespace {
+
+struct FaceRec {
+  int64_t v[3];
+  int32_t cell;
+  int32_t slot;
+};
+
+inline bool rec_less(const FaceRec& x, const FaceRec& y) {
+  if (x.v[0] != y.v[0]) return x.v[0] < y.v[0];
+  if (x.v[1] != y.v[1]) return x.v[1] < y.v[1];
+  if (x.v[2] != y.v[2]) return x.v[2] < y.v[2];
+  return x.cell < y.cell;
+}
+
+inline bool same_key(const FaceRec& x, const FaceRec& y) {
+  return x.v[0] == y.v[0] && x.v[1] == y.v[1] && x.v[2] == y.v[2];
+}
+
+struct V3 {
+  double x, y, z;
+};
+inline V3 sub(V3 a, V3 b) { return {a.x - b.x, a.y - b.y, a.z - b.z}; }
+inline double dot(V3 a, V3 b) { return a.x * b.x + a.y * b.y + a.z * b.z; }
+inline V3 cross(V3 a, V3 b) {
+  return {a.y * b.z - a.z * b.y, a.z * b.x - a.x * b.z, a.x * b.y - a.y * b.x};
+}
+
+}  // namespace
+
+tafv_status build_host_mesh(int64_t n_nodes, const double* xyz, int64_t n_tets,
+                            const int64_t* tets, bool colour_major, HostMesh* out,
+                            std::string* err) {
+  if (n_tets >= (int64_t(1) << 29)) {
+    *err = "mesh too large: at most 2^29 tets";
+    return TAFV_E_ARG;
+  }
+  const int64_t nc = n_tets;
+  auto node = [&](int64_t id) { return V3{xyz[3 * id], xyz[3 * id + 1], xyz[3 * id + 2]}; };
+  std::vector<V3> xc(nc);
+  out->vol.resize(nc);
+  std::vector<FaceRec> rec(4 * nc);
+  for (int64_t t = 0; t < nc; ++t) {
+    const int64_t* v = tets + 4 * t;
+    for (int k = 0; k < 4; ++k) {
+      if (v[k] < 0 || v[k] >= n_nodes) {
+        *err = "tet " + std::to_string(t) + ": node id out of range";
+        return TAFV_E_MESH;
+      }
+    }
+    V3 p0 = node(v[0]), p1 = node(v[1]), p2 = node(v[2]), p3 = node(v[3]);
+    double det = dot(sub(p1, p0), cross(sub(p2, p0), sub(p3, p0)));
+    if (!(det > 0.0)) {
+      *err = "tet " + std::to_string(t) + ": non-positive volume (tets must be positively oriented)";
+      return TAFV_E_MESH;
+    }
+    out->vol[t] = det / 6.0;
+    xc[t] = {(p0.x + p1.x + p2.x + p3.x) * 0.25, (p0.y + p1.y + p2.y + p3.y) * 0.25,
+             (p0.z + p1.z + p2.z + p3.z) * 0.25};
+    for (int s = 0; s < 4; ++s) {
+      FaceRec& r = rec[4 * t + s];
+      int q = 0;
+      for (int k = 0; k < 4; ++k)
+        if (k != s) r.v[q++] = v[k];
+      std::sort(r.v, r.v + 3);
+      r.cell = (int32_t)t;
+      r.slot = s;
+    }
+  }
+  std::sort(rec.begin(), rec.end(), rec_less);
+
+  // faces in key order: lower cell = L
+  struct RawFace {
+    int32_t L, R;
+    int8_t sL, sR;
+    V3 A, xf;
+  };
+  std::vector<RawFace> faces;
+  faces.reserve(2 * nc + nc / 2);
+  int64_t nb = 0;
+  for (size_t i = 0; i < rec.size();) {
+    size_t j = i + 1;
+    while (j < rec.size() && same_key(rec[j], rec[i])) ++j;
+    if (j - i > 2 || (j - i == 2 && rec[i].cell == rec[i + 1].cell)) {
+      *err = "a face is shared by more than two tets (cell " + std::to_string(rec[i].cell) + ")";
+      return TAFV_E_MESH;
+    }
+    RawFace f;
+    f.L = rec[i].cell;
+    f.sL = (int8_t)rec[i].slot;
+    if (j - i == 2) {
+      f.R = rec[i + 1].cell;
+      f.sR = (int8_t)rec[i + 1].slot;
+    } else {
+      f.R = -1;
+      f.sR = -1;
+      ++nb;
+    }
+    V3 a = node(rec[i].v[0]), b = node(rec[i].v[1]), c = node(rec[i].v[2]);
+    V3 n = cross(sub(b, a), sub(c, a));
+    f.A = {0.5 * n.x, 0.5 * n.y, 0.5 * n.z};
+    f.xf = {(a.x + b.x + c.x) / 3.0, (a.y + b.y + c.y) / 3.0, (a.z + b.z + c.z) / 3.0};
+    if (dot(f.A, sub(f.xf, xc[f.L])) < 0.0) f.A = {-f.A.x, -f.A.y, -f.A.z};
+    faces.push_back(f);
+    i = j;
+  }
+  rec.clear();
+  rec.shrink_to_fit();
+  const int64_t nf = (int64_t)faces.size();
+
+  // greedy colouring: faces visited by (L, R); a face takes the lowest
+  // colour not yet used by another face of either cell
+  std::vector<int32_t> order(nf);
+  std::iota(order.begin(), order.end(), 0);
+  std::stable_sort(order.begin(), order.end(), [&](int32_t x, int32_t y) {
+    if (faces[x].L != faces[y].L) return faces[x].L < faces[y].L;
+    return faces[x].R < faces[y].R;
+  });
+  std::vector<uint8_t> used(nc, 0);
+  std::vector<int8_t> colour(nf);
+  int ncol = 0;
+  for (int32_t f : order) {
+    unsigned m = used[faces[f].L];
+    if (faces[f].R >= 0) m |= used[faces[f].R];
+    int c = 0;
+    while (m & (1u << c)) ++c;
+    if (c >= kMaxColours) {
+      *err = "face colouring needs more than 8 colours";
+      return TAFV_E_MESH;
+    }
+    colour[f] = (int8_t)c;
+    used[faces[f].L] |= (uint8_t)(1u << c);
+    if (faces[f].R >= 0) used[faces[f].R] |= (uint8_t)(1u << c);
+    ncol = std::max(ncol, c + 1);
+  }
+  // final face order: by colour, then by (L, R) within the colour
+  if (colour_major)
+    std::stable_sort(order.begin(), order.end(),
+                     [&](int32_t x, int32_t y) { return colour[x] < colour[y]; });
+
+  out->nc = nc;
+  out->nf = nf;
+  out->nbnd = nb;
+  out->ncolours = ncol;
+  out->fhL.resize(nf);
+  out->fhR.resize(nf);
+  out->fcol.resize(nf);
+  out->fA.resize(3 * nf);
+  out->nb.assign(4 * nc, 0);
+  out->c2f.assign(4 * nc, 0);
+  std::vector<V3> xf_new(nf);
+  for (int c = 0; c <= kMaxColours; ++c) out->colour_start[c] = nf;
+  for (int64_t k = nf - 1; k >= 0; --k) out->colour_start[colour[order[k]]] = k;
+  for (int c = kMaxColours - 1; c >= 0; --c)
+    if (out->colour_start[c] > out->colour_start[c + 1]) out->colour_start[c] = out->colour_start[c + 1];
+  for (int64_t k = 0; k < nf; ++k) {
+    const RawFace& f = faces[order[k]];
+    out->fhL[k] = 4 * f.L + f.sL;
+    out->fhR[k] = f.R >= 0 ? 4 * f.R + f.sR : -1;
+    out->fcol[k] = colour[order[k]];
+    out->fA[k] = f.A.x;
+    out->fA[nf + k] = f.A.y;
+    out->fA[2 * nf + k] = f.A.z;
+    xf_new[k] = f.xf;
+    out->c2f[f.sL * nc + f.L] = (int32_t)k;
+    out->nb[f.sL * nc + f.L] = f.R >= 0 ? f.R : -(int32_t)(k + 1);
+    if (f.R >= 0) {
+      out->c2f[f.sR * nc + f.R] = (int32_t)k;
+      out->nb[f.sR * nc + f.R] = f.L;
+    }
+  }
+
+  // least squares: neighbour (or mirror ghost) offsets d_m, weights
+  // 1/|d_m|^2, M = sum w d d^T, coefficient vectors M^-1 w_m d_m
+  out->lsq.assign(12 * nc, 0.0);
+  out->rf.assign(12 * nc, 0.0);
+  for (int64_t i = 0; i < nc; ++i) {
+    V3 d[4];
+    double M[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
+    for (int m = 0; m < 4; ++m) {
+      int32_t f = out->c2f[m * nc + i];
+      int32_t other = out->nb[m * nc + i];
+      V3 r = sub(xf_new[f], xc[i]);
+      out->rf[(3 * m + 0) * nc + i] = r.x;
+      out->rf[(3 * m + 1) * nc + i] = r.y;
+      out->rf[(3 * m + 2) * nc + i] = r.z;
+      if (other >= 0) {
+        d[m] = sub(xc[other], xc[i]);
+      } else {
+        V3 A = {out->fA[f], out->fA[nf + f], out->fA[2 * nf + f]};
+        double an = std::sqrt(dot(A, A));
+        V3 n = {A.x / an, A.y / an, A.z / an};
+        double h = 2.0 * dot(r, n);  // ghost = centroid mirrored in the face plane
+        d[m] = {h * n.x, h * n.y, h * n.z};
+      }
+      double w = 1.0 / dot(d[m], d[m]);
+      double dv[3] = {d[m].x, d[m].y, d[m].z};
+      for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 3; ++b) M[a][b] += w * dv[a] * dv[b];
+    }
+    double c00 = M[1][1] * M[2][2] - M[1][2] * M[2][1];
+    double c01 = M[1][2] * M[2][0] - M[1][0] * M[2][2];
+    double c02 = M[1][0] * M[2][1] - M[1][1] * M[2][0];
+    double det = M[0][0] * c00 + M[0][1] * c01 + M[0][2] * c02;
+    if (!(std::fabs(det) > 0.0)) {
+      *err = "singular least-squares matrix at cell " + std::to_string(i);
+      return TAFV_E_MESH;
+    }
+    double inv[3][3];
+    inv[0][0] = c00 / det;
+    inv[1][0] = c01 / det;
+    inv[2][0] = c02 / det;
+    inv[0][1] = (M[0][2] * M[2][1] - M[0][1] * M[2][2]) / det;
+    inv[1][1] = (M[0][0] * M[2][2] - M[0][2] * M[2][0]) / det;
+    inv[2][1] = (M[0][1] * M[2][0] - M[0][0] * M[2][1]) / det;
+    inv[0][2] = (M[0][1] * M[1][2] - M[0][2] * M[1][1]) / det;
+    inv[1][2] = (M[0][2] * M[1][0] - M[0][0] * M[1][2]) / det;
+    inv[2][2] = (M[0][0] * M[1][1] - M[0][1] * M[1][0]) / det;
+    for (int m = 0; m < 4; ++m) {
+      double w = 1.0 / dot(d[m], d[m]);
+      double dv[3] = {w * d[m].x, w * d[m].y, w * d[m].z};
+      for (int a = 0; a < 3; ++a)
+        out->lsq[(3 * m + a) * nc + i] = inv[a][0] * dv[0] + inv[a][1] * dv[1] + inv[a][2] * dv[2];
+    }
+  }
+  return TAFV_OK;
+}
+
+}  // namespace tafv

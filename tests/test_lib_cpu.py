@@ -1,0 +1,102 @@
+"""CPU checks of the C-ABI library: it loads, exports every symbol the header
+declares, and its host-side mesh preprocessing (faces, area vectors,
+neighbours, colouring) agrees with the oracle.  No device call is made."""
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_1704_01144_amd import inputs as I
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def T():
+    from paper_1704_01144_amd import tafv
+    return tafv
+
+
+def test_exports_every_declared_symbol(T):
+    hdr = open(os.path.join(ROOT, "include", "tafv.h")).read()
+    declared = set(re.findall(r"^\s*(?:const\s+char\s*\*|tafv_status)\s+(tafv_\w+)\s*\(", hdr,
+                              re.M))
+    assert len(declared) >= 15
+    for name in declared:
+        assert hasattr(T.lib, name), name
+    assert declared == set(T.EXPORTS)
+
+
+def _face_key(tets, cell, other):
+    a = set(tets[cell].tolist())
+    if other < 0:
+        return None
+    return tuple(sorted(a & set(tets[other].tolist())))
+
+
+@pytest.mark.parametrize("n,grading", [(3, 1.0), (8, 4.0)])
+def test_mesh_prep_matches_oracle(T, orc, n, grading):
+    nodes, tets = I.graded_cube_mesh(n, grading)
+    r = T.tafv_mesh_inspect(nodes, tets)
+    m = orc.Mesh(nodes, tets)
+    g = m.geometry()
+    assert (r["n_faces"], r["n_boundary"]) == (m.n_faces, m.n_boundary)
+    # interior faces: same (L, R) pairs and the same area vectors
+    ours = {(int(a), int(b)): r["face_area"][k] for k, (a, b) in enumerate(r["face_cells"]) if b >= 0}
+    theirs = {(int(a), int(b)): g["face_area"][k] for k, (a, b) in
+              enumerate(zip(g["face_L"], g["face_R"])) if b >= 0}
+    assert ours.keys() == theirs.keys()
+    err = max(np.abs(ours[k] - theirs[k]).max() for k in ours)
+    assert err < 1e-15
+    # boundary faces: one per (cell, outward area)
+    ob = sorted((int(a), tuple(np.round(r["face_area"][k], 14))) for k, (a, b) in
+                enumerate(r["face_cells"]) if b < 0)
+    tb = sorted((int(a), tuple(np.round(g["face_area"][k], 14))) for k, (a, b) in
+                enumerate(zip(g["face_L"], g["face_R"])) if b < 0)
+    assert ob == tb
+    # neighbours across local face m (the face opposite vertex m)
+    c2f, L, R = g["cell_faces"], g["face_L"], g["face_R"]
+    nb_orc = np.where(L[c2f] == np.arange(len(tets))[:, None], R[c2f], L[c2f])
+    assert (r["cell_neighbours"] == nb_orc).all()
+
+
+@pytest.mark.parametrize("n,grading", [(4, 1.0), (12, 4.0), (20, 16.0)])
+def test_colouring_is_valid(T, n, grading):
+    nodes, tets = I.graded_cube_mesh(n, grading)
+    r = T.tafv_mesh_inspect(nodes, tets)
+    fc, col = r["face_cells"], r["face_colour"]
+    assert r["n_colours"] <= 7
+    # colour-major order
+    assert (np.diff(col.astype(int)) >= 0).all()
+    # no two faces of one colour share a cell
+    for c in range(r["n_colours"]):
+        sel = fc[col == c]
+        cells = np.concatenate([sel[:, 0], sel[sel[:, 1] >= 0, 1]])
+        assert len(np.unique(cells)) == len(cells)
+    # every cell has exactly 4 faces
+    cnt = np.bincount(np.concatenate([fc[:, 0], fc[fc[:, 1] >= 0, 1]]), minlength=len(tets))
+    assert (cnt == 4).all()
+
+
+def test_mesh_errors(T):
+    nodes, tets = I.graded_cube_mesh(2, 1.0)
+    bad = tets.copy()
+    bad[1, 2], bad[1, 3] = bad[1, 3], bad[1, 2]
+    with pytest.raises(T.TafvError) as e:
+        T.tafv_mesh_inspect(nodes, bad)
+    assert e.value.code == T.E_MESH
+    bad = tets.copy()
+    bad[0, 1] = -1
+    with pytest.raises(T.TafvError) as e:
+        T.tafv_mesh_inspect(nodes, bad)
+    assert e.value.code == T.E_MESH
+    with pytest.raises(T.TafvError) as e:
+        T.tafv_mesh_inspect(nodes, np.concatenate([tets, tets[:1]]))
+    assert e.value.code == T.E_MESH
+
+
+def test_params_default(T):
+    p = T.tafv_params_default()
+    assert (p.gamma, p.cfl, p.newton_tol, p.level_margin) == (1.4, 0.5, 1e-12, 1e-9)
+    assert (p.max_levels, p.order, p.precision, p.newton_max_iter, p.reclassify) == (5, 2, 0, 50, 1)
