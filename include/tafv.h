@@ -73,11 +73,15 @@ enum { TAFV_BC_WALL = 0, TAFV_BC_TRANSMIT = 1 };
  * adds its own faces in its fixed local face order.  Both are atomic-free
  * and deterministic; results agree to rounding. */
 enum { TAFV_SCATTER_COLOUR = 0, TAFV_SCATTER_GATHER = 1 };
+/* Internal cell order: the caller's order, or a Morton (Z-order) sort of
+ * the cell centroids for meshes given in an order without locality.  Host
+ * arrays always use the caller's order. */
+enum { TAFV_ORDER_CALLER = 0, TAFV_ORDER_MORTON = 1 };
 
 /* Method parameters.  tafv_params_default() fills: gamma 1.4, cfl 0.5,
  * newton_tol 1e-12, level_margin 1e-9, max_levels 5, order 2, precision
  * TAFV_FP64, guess TAFV_GUESS_TR, boundary TAFV_BC_WALL, newton_max_iter
- * 50, reclassify 1, scatter TAFV_SCATTER_GATHER. */
+ * 50, reclassify 1, scatter TAFV_SCATTER_GATHER, cell_order TAFV_ORDER_CALLER. */
 typedef struct {
   double gamma;          /* ratio of specific heats, > 1                        */
   double cfl;            /* dt_i = cfl V_i / sum_f (|u_i . n_f| + a_i) |A_f|    */
@@ -94,6 +98,7 @@ typedef struct {
   int32_t reclassify;    /* 1: new levels at every iteration start; 0: keep the
                             first classification (and its dt_min)               */
   int32_t scatter;       /* TAFV_SCATTER_COLOUR or TAFV_SCATTER_GATHER          */
+  int32_t cell_order;    /* TAFV_ORDER_CALLER or TAFV_ORDER_MORTON              */
 } tafv_params;
 
 /* Counters (int64) and schedule state.  Summed over meshes where a call

@@ -46,10 +46,10 @@ void free_mesh(DevMesh* m) {
   if (!m) return;
   void* ptrs[] = {m->fhL, m->fhR, m->fcol, m->fA, m->fA32, m->nb_, m->c2f, m->lsq, m->rf,
                   m->vol, m->lsq32, m->rf32, m->U, m->U0, m->R, m->lev, m->lev2, m->dt, m->Wf,
-                  m->pf.list, m->pf.counts, m->pf.start, m->pg.list, m->pg.counts,
-                  m->pg.start, m->pu.list, m->pu.counts, m->pu.start, m->dscal, m->dcount,
-                  m->dimpulse, m->pf.offs, m->pg.offs, m->pu.offs, m->pf.scan_tmp,
-                  m->pg.scan_tmp, m->pu.scan_tmp, m->Q, m->frec};
+                  m->pf.list, m->pf.counts, m->pf.start, m->pc.list, m->pc.counts,
+                  m->pc.start, m->dscal, m->dcount, m->dimpulse, m->pf.offs, m->pc.offs,
+                  m->pf.scan_tmp, m->pc.scan_tmp, m->Q, m->frec, m->fkey, m->ckey, m->fpack,
+                  m->perm, m->xfer, m->chist, m->rb};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   delete m;
@@ -115,6 +115,18 @@ struct ProfScope {
 
 // ---- classification at an iteration start ------------------------------
 
+// per-level cell counts of the latest classification; returns theta
+int level_histogram(DevMesh& m) {
+  int theta = 0;
+  for (int t = 0; t < kMaxLevels; ++t) {
+    int64_t n = 0;
+    for (int g = 0; g < kMaxLevels; ++g) n += m.hhist[g * kMaxLevels + t];
+    m.st.cells_per_level[t] = n;
+    if (n > 0) theta = t;
+  }
+  return theta;
+}
+
 tafv_status classify(tafv_ctx* c, DevMesh& m) {
   StepArgs a = step_args(c, m);
   {
@@ -127,14 +139,9 @@ tafv_status classify(tafv_ctx* c, DevMesh& m) {
   // read back: dt_min, flag, list starts
   int K = m.scatter == TAFV_SCATTER_COLOUR ? m.ncolours * kMaxLevels : kMaxLevels;
   int32_t* h = c->hpin;
-  HIP_TRY(c, hipMemcpyAsync(h, m.dscal, 3 * sizeof(unsigned long long), hipMemcpyDeviceToHost,
+  HIP_TRY(c, launch_pack_readback(c->stream, m, K));
+  HIP_TRY(c, hipMemcpyAsync(h, m.rb, kReadbackInts * sizeof(int32_t), hipMemcpyDeviceToHost,
                             c->stream));
-  HIP_TRY(c, hipMemcpyAsync(h + 8, m.pf.start, (K + 1) * sizeof(int32_t), hipMemcpyDeviceToHost,
-                            c->stream));
-  HIP_TRY(c, hipMemcpyAsync(h + 8 + kMaxKeys + 1, m.pg.start, (kMaxLevels + 1) * sizeof(int32_t),
-                            hipMemcpyDeviceToHost, c->stream));
-  HIP_TRY(c, hipMemcpyAsync(h + 8 + kMaxKeys + kMaxLevels + 2, m.pu.start,
-                            (kMaxLevels + 1) * sizeof(int32_t), hipMemcpyDeviceToHost, c->stream));
   HIP_TRY(c, hipStreamSynchronize(c->stream));
   unsigned long long bits[3];
   std::memcpy(bits, h, sizeof(bits));
@@ -145,17 +152,23 @@ tafv_status classify(tafv_ctx* c, DevMesh& m) {
     return fail(c, TAFV_E_NUMERIC, "no valid time step");
   m.dt_min = dtmin;
   std::memcpy(m.hstart_f, h + 8, (K + 1) * sizeof(int32_t));
-  std::memcpy(m.hstart_g, h + 8 + kMaxKeys + 1, (kMaxLevels + 1) * sizeof(int32_t));
-  std::memcpy(m.hstart_u, h + 8 + kMaxKeys + kMaxLevels + 2, (kMaxLevels + 1) * sizeof(int32_t));
-  int theta = 0;
-  for (int t = 0; t < kMaxLevels; ++t) {
-    int64_t n = m.hstart_u[t + 1] - m.hstart_u[t];
-    m.st.cells_per_level[t] = n;
-    if (n > 0) theta = t;
-  }
+  std::memcpy(m.hstart_c, h + 8 + kMaxKeys + 1, (kMaxLevels + 1) * sizeof(int32_t));
+  std::memcpy(m.hhist, h + 8 + kMaxKeys + kMaxLevels + 2, kMaxKeys * sizeof(int32_t));
+  int theta = level_histogram(m);
   m.theta = theta;
   m.classified = true;
   return TAFV_OK;
+}
+
+// cells listed by tau_g: count of cells with tau_g <= g
+int cells_upto_g(const DevMesh& m, int g) { return m.hstart_c[g + 1]; }
+
+// cells with tau <= t
+int64_t cells_upto_tau(const DevMesh& m, int t) {
+  int64_t n = 0;
+  for (int g = 0; g < kMaxLevels; ++g)
+    for (int u = 0; u <= t; ++u) n += m.hhist[g * kMaxLevels + u];
+  return n;
 }
 
 tafv_status subiteration(tafv_ctx* c, DevMesh& m, tafv_stats* acc) {
@@ -166,7 +179,7 @@ tafv_status subiteration(tafv_ctx* c, DevMesh& m, tafv_stats* acc) {
   StepArgs a = step_args(c, m);
   int tau_s = subiteration_level((int64_t)m.phase + 1, m.theta);
   if (c->prm.order == 2) {
-    int cnt = m.hstart_g[tau_s + 1];
+    int cnt = cells_upto_g(m, tau_s);
     ProfScope ps(c, P_GRAD, cnt);
     HIP_TRY(c, launch_grad(c->stream, m, a, cnt));
   }
@@ -180,7 +193,7 @@ tafv_status subiteration(tafv_ctx* c, DevMesh& m, tafv_stats* acc) {
       ++upd;
     }
   }
-  int ucnt = m.hstart_u[upd + 1];
+  int64_t ucnt = cells_upto_tau(m, upd);
   int64_t faces = 0;
   if (m.scatter == TAFV_SCATTER_COLOUR) {
     for (int col = 0; col < m.ncolours; ++col) {
@@ -190,8 +203,9 @@ tafv_status subiteration(tafv_ctx* c, DevMesh& m, tafv_stats* acc) {
       ProfScope ps(c, P_FLUX, cnt);
       HIP_TRY(c, launch_flux(c->stream, m, a, first, cnt));
     }
-    ProfScope ps(c, P_UPDATE, ucnt);
-    HIP_TRY(c, launch_update(c->stream, m, ucnt));
+    int ulist = cells_upto_g(m, upd);
+    ProfScope ps(c, P_UPDATE, ulist);
+    HIP_TRY(c, launch_update(c->stream, m, ulist, upd));
   } else {
     int cnt = m.hstart_f[tau_s + 1];
     faces = cnt;
@@ -199,7 +213,7 @@ tafv_status subiteration(tafv_ctx* c, DevMesh& m, tafv_stats* acc) {
       ProfScope ps(c, P_FLUX, cnt);
       HIP_TRY(c, launch_flux(c->stream, m, a, 0, cnt));
     }
-    int ccnt = m.hstart_g[std::max(tau_s, upd) + 1];
+    int ccnt = cells_upto_g(m, std::max(tau_s, upd));
     ProfScope ps(c, P_GATHER, ccnt);
     HIP_TRY(c, launch_cell_gather(c->stream, m, ccnt, tau_s, upd));
   }
@@ -265,6 +279,7 @@ tafv_status tafv_params_default(tafv_params* p) {
   p->newton_max_iter = 50;
   p->reclassify = 1;
   p->scatter = TAFV_SCATTER_GATHER;
+  p->cell_order = TAFV_ORDER_CALLER;
   return TAFV_OK;
 }
 
@@ -279,6 +294,7 @@ tafv_status tafv_create(int device, const tafv_params* params, void* hip_stream,
       (p.precision != TAFV_FP64 && p.precision != TAFV_FP32_FLUX) ||
       (p.boundary != TAFV_BC_WALL && p.boundary != TAFV_BC_TRANSMIT) || p.newton_max_iter < 1 ||
       (p.scatter != TAFV_SCATTER_COLOUR && p.scatter != TAFV_SCATTER_GATHER) ||
+      (p.cell_order != TAFV_ORDER_CALLER && p.cell_order != TAFV_ORDER_MORTON) ||
       !(p.level_margin >= 0.0 && p.level_margin < 0.5))
     return fail(nullptr, TAFV_E_ARG, "invalid parameters");
   if (p.guess != TAFV_GUESS_TR) return fail(nullptr, TAFV_E_ARG, "unsupported guess mode");
@@ -330,7 +346,8 @@ tafv_status tafv_mesh_upload(tafv_ctx* c, int64_t n_nodes, const double* xyz, in
   HIP_TRY(c, hipSetDevice(c->device));
   HostMesh hm;
   tafv_status st = build_host_mesh(n_nodes, xyz, n_tets, tets,
-                                   c->prm.scatter == TAFV_SCATTER_COLOUR, &hm, &c->err);
+                                   c->prm.scatter == TAFV_SCATTER_COLOUR,
+                                   c->prm.cell_order == TAFV_ORDER_MORTON, &hm, &c->err);
   if (st != TAFV_OK) return st;
   DevMesh* m = new (std::nothrow) DevMesh();
   if (!m) return fail(c, TAFV_E_OOM, "host allocation failed");
@@ -370,24 +387,24 @@ tafv_status tafv_mesh_upload(tafv_ctx* c, int64_t n_nodes, const double* xyz, in
   chk(dalloc(&m->dt, nc));
   size_t wfbytes = (c->prm.precision == TAFV_FP32_FLUX ? sizeof(float) : sizeof(double)) * 20 * nc;
   if (c->prm.order == 2) chk(hipMalloc(&m->Wf, wfbytes));
-  int pbf = partition_blocks(nf), pbc = partition_blocks(nc);
-  for (Partition* p : {&m->pf, &m->pg, &m->pu}) {
+  for (Partition* p : {&m->pf, &m->pc}) {
     int64_t n = (p == &m->pf) ? (int64_t)nf : (int64_t)nc;
     p->scan_bytes = partition_scan_bytes(n);
     chk(hipMalloc(&p->scan_tmp, std::max<size_t>(p->scan_bytes, 16)));
     chk(dalloc(&p->offs, (size_t)kMaxKeys * partition_blocks(n)));
+    chk(dalloc(&p->list, n));
+    chk(dalloc(&p->counts, (size_t)kMaxKeys * partition_blocks(n)));
+    chk(dalloc(&p->start, kMaxKeys + 1));
   }
   chk(dalloc(&m->frec, nf));
   if (m->scatter == TAFV_SCATTER_GATHER) chk(dalloc(&m->Q, 5 * nf));
-  chk(dalloc(&m->pf.list, nf));
-  chk(dalloc(&m->pf.counts, (size_t)kMaxKeys * pbf));
-  chk(dalloc(&m->pf.start, kMaxKeys + 1));
-  chk(dalloc(&m->pg.list, nc));
-  chk(dalloc(&m->pg.counts, (size_t)kMaxKeys * pbc));
-  chk(dalloc(&m->pg.start, kMaxKeys + 1));
-  chk(dalloc(&m->pu.list, nc));
-  chk(dalloc(&m->pu.counts, (size_t)kMaxKeys * pbc));
-  chk(dalloc(&m->pu.start, kMaxKeys + 1));
+  chk(dalloc(&m->fkey, nf));
+  chk(dalloc(&m->ckey, nc));
+  chk(dalloc(&m->fpack, nc));
+  chk(dalloc(&m->perm, nc));
+  chk(dalloc(&m->chist, kMaxKeys));
+  chk(dalloc(&m->rb, kReadbackInts));
+  chk(dalloc(&m->xfer, 5 * nc));
   chk(dalloc(&m->dscal, 4));
   chk(dalloc(&m->dcount, kCounterWords));
   chk(dalloc(&m->dimpulse, kCounterWords));
@@ -410,6 +427,7 @@ tafv_status tafv_mesh_upload(tafv_ctx* c, int64_t n_nodes, const double* xyz, in
   f32.assign(hm.rf.begin(), hm.rf.end());
   chk(up(m->rf32, f32));
   chk(up(m->vol, hm.vol));
+  chk(up(m->perm, hm.perm));
   if (e != hipSuccess) {
     free_mesh(m);
     return hip_fail(c, e, "mesh upload");
@@ -426,15 +444,16 @@ tafv_status tafv_mesh_inspect(int64_t n_nodes, const double* xyz, int64_t n_tets
   if (!xyz || !tets || n_nodes < 4 || n_tets < 1) return fail(nullptr, TAFV_E_ARG, "invalid mesh");
   HostMesh hm;
   std::string err;
-  tafv_status st = build_host_mesh(n_nodes, xyz, n_tets, tets, true, &hm, &err);
+  tafv_status st = build_host_mesh(n_nodes, xyz, n_tets, tets, true, false, &hm, &err);
   if (st != TAFV_OK) return fail(nullptr, st, err);
   if (n_faces) *n_faces = hm.nf;
   if (n_boundary) *n_boundary = hm.nbnd;
   if (n_colours) *n_colours = hm.ncolours;
+  const std::vector<int32_t>& perm = hm.perm;  // internal -> caller
   for (int64_t f = 0; f < hm.nf; ++f) {
     if (face_cells) {
-      face_cells[2 * f] = hm.fhL[f] >> 2;
-      face_cells[2 * f + 1] = hm.fhR[f] >= 0 ? (hm.fhR[f] >> 2) : -1;
+      face_cells[2 * f] = perm[hm.fhL[f] >> 2];
+      face_cells[2 * f + 1] = hm.fhR[f] >= 0 ? perm[hm.fhR[f] >> 2] : -1;
     }
     if (face_colour) face_colour[f] = hm.fcol[f];
     if (face_area)
@@ -444,7 +463,7 @@ tafv_status tafv_mesh_inspect(int64_t n_nodes, const double* xyz, int64_t n_tets
     for (int64_t i = 0; i < hm.nc; ++i)
       for (int m = 0; m < 4; ++m) {
         int32_t n = hm.nb[m * hm.nc + i];
-        cell_neighbours[4 * i + m] = n >= 0 ? n : -1;
+        cell_neighbours[4 * (int64_t)perm[i] + m] = n >= 0 ? perm[n] : -1;
       }
   return TAFV_OK;
 }
@@ -471,11 +490,9 @@ tafv_status tafv_state_init(tafv_ctx* c, int32_t mesh_id, const double* prim) {
       return fail(c, TAFV_E_STATE, "rho <= 0 or p <= 0 at cell " + std::to_string(i));
   }
   HIP_TRY(c, hipSetDevice(c->device));
-  double* d_prim = nullptr;
-  HIP_TRY(c, hipMalloc(&d_prim, sizeof(double) * 5 * m->nc));
-  hipError_t e = hipMemcpyAsync(d_prim, prim, sizeof(double) * 5 * m->nc, hipMemcpyHostToDevice,
+  hipError_t e = hipMemcpyAsync(m->xfer, prim, sizeof(double) * 5 * m->nc, hipMemcpyHostToDevice,
                                 c->stream);
-  if (e == hipSuccess) e = launch_state_init(c->stream, *m, d_prim, c->prm.gamma);
+  if (e == hipSuccess) e = launch_state_init(c->stream, *m, m->xfer, c->prm.gamma);
   if (e == hipSuccess)
     e = hipMemcpyAsync(m->U0, m->U, sizeof(double) * 5 * m->nc, hipMemcpyDeviceToDevice,
                        c->stream);
@@ -483,7 +500,6 @@ tafv_status tafv_state_init(tafv_ctx* c, int32_t mesh_id, const double* prim) {
   if (e == hipSuccess) e = launch_fill_f64(c->stream, m->dimpulse, 0.0, kCounterWords);
   if (e == hipSuccess) e = launch_fill_u64(c->stream, m->dscal, 0ull, 4);
   if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
-  (void)hipFree(d_prim);
   if (e != hipSuccess) return hip_fail(c, e, "state init");
   m->has_state = true;
   m->phase = 0;
@@ -558,10 +574,14 @@ tafv_status tafv_state_read(tafv_ctx* c, int32_t mesh_id, double* cons, int8_t* 
   if (!cons) return fail(c, TAFV_E_ARG, "cons is NULL");
   if (!m->has_state) return fail(c, TAFV_E_ORDER, "no state");
   HIP_TRY(c, hipSetDevice(c->device));
-  HIP_TRY(c, hipMemcpyAsync(cons, m->U, sizeof(double) * 5 * m->nc, hipMemcpyDeviceToHost,
+  HIP_TRY(c, launch_to_caller_f64(c->stream, *m, m->U, m->xfer));
+  HIP_TRY(c, hipMemcpyAsync(cons, m->xfer, sizeof(double) * 5 * m->nc, hipMemcpyDeviceToHost,
                             c->stream));
-  if (levels)
-    HIP_TRY(c, hipMemcpyAsync(levels, m->lev, m->nc, hipMemcpyDeviceToHost, c->stream));
+  if (levels) {
+    int8_t* stage = (int8_t*)m->xfer;
+    HIP_TRY(c, launch_to_caller_i8(c->stream, *m, m->lev, stage));
+    HIP_TRY(c, hipMemcpyAsync(levels, stage, m->nc, hipMemcpyDeviceToHost, c->stream));
+  }
   HIP_TRY(c, hipStreamSynchronize(c->stream));
   return TAFV_OK;
 }
@@ -575,11 +595,16 @@ tafv_status tafv_checkpoint_read(tafv_ctx* c, int32_t mesh_id, double* cons, dou
     return fail(c, TAFV_E_ARG, "NULL argument");
   if (!m->has_state) return fail(c, TAFV_E_ORDER, "no state");
   HIP_TRY(c, hipSetDevice(c->device));
-  HIP_TRY(c, hipMemcpyAsync(cons, m->U, sizeof(double) * 5 * m->nc, hipMemcpyDeviceToHost,
+  HIP_TRY(c, launch_to_caller_f64(c->stream, *m, m->U, m->xfer));
+  HIP_TRY(c, hipMemcpyAsync(cons, m->xfer, sizeof(double) * 5 * m->nc, hipMemcpyDeviceToHost,
                             c->stream));
-  HIP_TRY(c, hipMemcpyAsync(accum, m->R, sizeof(double) * 5 * m->nc, hipMemcpyDeviceToHost,
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  HIP_TRY(c, launch_to_caller_f64(c->stream, *m, m->R, m->xfer));
+  HIP_TRY(c, hipMemcpyAsync(accum, m->xfer, sizeof(double) * 5 * m->nc, hipMemcpyDeviceToHost,
                             c->stream));
-  HIP_TRY(c, hipMemcpyAsync(levels, m->lev, m->nc, hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  HIP_TRY(c, launch_to_caller_i8(c->stream, *m, m->lev, (int8_t*)m->xfer));
+  HIP_TRY(c, hipMemcpyAsync(levels, m->xfer, m->nc, hipMemcpyDeviceToHost, c->stream));
   HIP_TRY(c, hipStreamSynchronize(c->stream));
   *phase = m->phase;
   *theta = m->theta;
@@ -600,21 +625,26 @@ tafv_status tafv_checkpoint_write(tafv_ctx* c, int32_t mesh_id, const double* co
   for (int64_t i = 0; i < m->nc; ++i)
     if (levels[i] < 0 || levels[i] > theta) return fail(c, TAFV_E_ARG, "level out of range");
   HIP_TRY(c, hipSetDevice(c->device));
-  HIP_TRY(c, hipMemcpyAsync(m->U, cons, sizeof(double) * 5 * m->nc, hipMemcpyHostToDevice,
+  HIP_TRY(c, hipMemcpyAsync(m->xfer, cons, sizeof(double) * 5 * m->nc, hipMemcpyHostToDevice,
                             c->stream));
-  HIP_TRY(c, hipMemcpyAsync(m->R, accum, sizeof(double) * 5 * m->nc, hipMemcpyHostToDevice,
+  HIP_TRY(c, launch_from_caller_f64(c->stream, *m, m->xfer, m->U));
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  HIP_TRY(c, hipMemcpyAsync(m->xfer, accum, sizeof(double) * 5 * m->nc, hipMemcpyHostToDevice,
                             c->stream));
-  HIP_TRY(c, hipMemcpyAsync(m->lev, levels, m->nc, hipMemcpyHostToDevice, c->stream));
+  HIP_TRY(c, launch_from_caller_f64(c->stream, *m, m->xfer, m->R));
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  HIP_TRY(c, hipMemcpyAsync(m->xfer, levels, m->nc, hipMemcpyHostToDevice, c->stream));
+  HIP_TRY(c, launch_from_caller_i8(c->stream, *m, (const int8_t*)m->xfer, m->lev));
   HIP_TRY(c, launch_partitions(c->stream, *m));
   int K = m->scatter == TAFV_SCATTER_COLOUR ? m->ncolours * kMaxLevels : kMaxLevels;
   HIP_TRY(c, hipMemcpyAsync(m->hstart_f, m->pf.start, (K + 1) * sizeof(int32_t),
                             hipMemcpyDeviceToHost, c->stream));
-  HIP_TRY(c, hipMemcpyAsync(m->hstart_g, m->pg.start, (kMaxLevels + 1) * sizeof(int32_t),
+  HIP_TRY(c, hipMemcpyAsync(m->hstart_c, m->pc.start, (kMaxLevels + 1) * sizeof(int32_t),
                             hipMemcpyDeviceToHost, c->stream));
-  HIP_TRY(c, hipMemcpyAsync(m->hstart_u, m->pu.start, (kMaxLevels + 1) * sizeof(int32_t),
-                            hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(c, hipMemcpyAsync(m->hhist, m->chist, kMaxKeys * sizeof(int32_t), hipMemcpyDeviceToHost,
+                            c->stream));
   HIP_TRY(c, hipStreamSynchronize(c->stream));
-  for (int k = 0; k < kMaxLevels; ++k) m->st.cells_per_level[k] = m->hstart_u[k + 1] - m->hstart_u[k];
+  level_histogram(*m);
   m->has_state = true;
   m->phase = phase;
   m->theta = theta;

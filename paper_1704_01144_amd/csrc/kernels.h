@@ -20,7 +20,14 @@ hipError_t launch_partitions(hipStream_t s, DevMesh& m);
 hipError_t launch_grad(hipStream_t s, DevMesh& m, const StepArgs& a, int count);
 hipError_t launch_flux(hipStream_t s, DevMesh& m, const StepArgs& a, int first, int count);
 hipError_t launch_cell_gather(hipStream_t s, DevMesh& m, int count, int tau_s, int tau_upd);
-hipError_t launch_update(hipStream_t s, DevMesh& m, int count);
+hipError_t launch_update(hipStream_t s, DevMesh& m, int count, int tau_upd);
+hipError_t launch_pack_readback(hipStream_t s, DevMesh& m, int Kf);
+constexpr int kReadbackInts = 8 + kMaxKeys + 1 + kMaxLevels + 1 + kMaxKeys;
+// host-transfer staging: rows of 5 doubles or 1 byte, caller <-> internal order
+hipError_t launch_to_caller_f64(hipStream_t s, DevMesh& m, const double* src, double* dst);
+hipError_t launch_from_caller_f64(hipStream_t s, DevMesh& m, const double* src, double* dst);
+hipError_t launch_to_caller_i8(hipStream_t s, DevMesh& m, const int8_t* src, int8_t* dst);
+hipError_t launch_from_caller_i8(hipStream_t s, DevMesh& m, const int8_t* src, int8_t* dst);
 hipError_t launch_fill_u64(hipStream_t s, unsigned long long* p, unsigned long long v, int n);
 hipError_t launch_fill_f64(hipStream_t s, double* p, double v, int64_t n);
 

@@ -66,11 +66,12 @@ __device__ inline void cons2prim(const double* U, double gm1, double* w) {
 // ---------------------------------------------------------------------------
 // state init and small fills
 
-__global__ void k_state_init(int nc, const double* __restrict__ prim, double gm1,
-                             double* __restrict__ U, double* __restrict__ R) {
+// prim in the caller's cell order; U, R in the internal order
+__global__ void k_state_init(int nc, const int* __restrict__ perm, const double* __restrict__ prim,
+                             double gm1, double* __restrict__ U, double* __restrict__ R) {
   int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= nc) return;
-  const double* w = prim + 5 * (size_t)i;
+  const double* w = prim + 5 * (size_t)perm[i];
   double r = w[0];
   U[5 * (size_t)i + 0] = r;
   U[5 * (size_t)i + 1] = r * w[1];
@@ -163,38 +164,79 @@ __global__ void k_sweep(int nc, const int* __restrict__ nb, const int8_t* __rest
 // ---------------------------------------------------------------------------
 // stable partition of indices by a small key, with wavefront ballots
 
-struct FaceKey {  // (colour, tau_f) with the colour left out in gather mode
-  const int* fhL;
-  const int* fhR;
-  const int8_t* fcol;
-  const int8_t* lev;
-  int use_colour;
-  __device__ int operator()(int f) const {
-    int t = lev[fhL[f] >> 2];
-    int h = fhR[f];
-    if (h >= 0) t = min(t, (int)lev[h >> 2]);
-    return use_colour ? fcol[f] * kMaxLevels + t : t;
-  }
+struct ByteKey {
+  const int8_t* key;
+  __device__ int operator()(int i) const { return key[i]; }
 };
 
-struct GradKey {  // lowest level among the cell and its neighbours
-  const int* nb;
-  const int8_t* lev;
-  int nc;
-  __device__ int operator()(int i) const {
-    int t = lev[i];
+// per face: tau_f = level of the faster side; key (colour, tau_f) or tau_f
+__global__ void k_face_keys(int nf, const int* __restrict__ fhL, const int* __restrict__ fhR,
+                            const int8_t* __restrict__ fcol, const int8_t* __restrict__ lev,
+                            int use_colour, int8_t* __restrict__ fkey) {
+  int f = blockIdx.x * blockDim.x + threadIdx.x;
+  if (f >= nf) return;
+  int t = lev[fhL[f] >> 2];
+  int h = fhR[f];
+  if (h >= 0) t = min(t, (int)lev[h >> 2]);
+  fkey[f] = (int8_t)(use_colour ? fcol[f] * kMaxLevels + t : t);
+}
+
+// per cell: tau_g = lowest level of its faces (the partition key), the
+// packed face word (tau_f per local face, higher-id side bits, tau), and
+// the histogram hist[tau_g * 8 + tau] (block-local in LDS, then one atomic
+// per bin and block)
+__global__ __launch_bounds__(kBlock) void k_cell_keys(int nc, const int* __restrict__ nb,
+                                                      const int8_t* __restrict__ lev,
+                                                      int8_t* __restrict__ ckey,
+                                                      uint32_t* __restrict__ fpack,
+                                                      int* __restrict__ hist) {
+  __shared__ int h[kMaxKeys];
+  for (int k = threadIdx.x; k < kMaxKeys; k += blockDim.x) h[k] = 0;
+  __syncthreads();
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < nc) {
+    int ti = lev[i], tg = ti;
+    uint32_t pk = (uint32_t)ti << 20;
     for (int m = 0; m < 4; ++m) {
       int n = nb[m * nc + i];
-      if (n >= 0) t = min(t, (int)lev[n]);
+      int tf = n >= 0 ? min(ti, (int)lev[n]) : ti;
+      tg = min(tg, tf);
+      pk |= (uint32_t)tf << (4 * m);
+      if (n >= 0 && n < i) pk |= 1u << (16 + m);
     }
-    return t;
+    ckey[i] = (int8_t)tg;
+    fpack[i] = pk;
+    atomicAdd(&h[tg * kMaxLevels + ti], 1);
   }
-};
+  __syncthreads();
+  for (int k = threadIdx.x; k < kMaxKeys; k += blockDim.x)
+    if (h[k]) atomicAdd(&hist[k], h[k]);
+}
 
-struct CellKey {
-  const int8_t* lev;
-  __device__ int operator()(int i) const { return lev[i]; }
-};
+// one buffer for the host readback at an iteration start: [0..5] the
+// scalars (dt_min bits, theta slot, non-finite flag), [8..8+Kf] face list
+// starts, [8+65..] cell list starts, [8+65+9..] the (tau_g, tau) histogram
+__global__ void k_pack_readback(const unsigned long long* __restrict__ dscal,
+                                const int* __restrict__ fstart, int Kf,
+                                const int* __restrict__ cstart, const int* __restrict__ hist,
+                                int* __restrict__ out) {
+  int t = threadIdx.x;
+  if (t < 6) out[t] = ((const int*)dscal)[t];
+  if (t <= Kf) out[8 + t] = fstart[t];
+  if (t <= kMaxLevels) out[8 + kMaxKeys + 1 + t] = cstart[t];
+  if (t < kMaxKeys) out[8 + kMaxKeys + kMaxLevels + 2 + t] = hist[t];
+}
+
+hipError_t launch_pack_readback(hipStream_t s, DevMesh& m, int Kf) {
+  hipLaunchKernelGGL(k_pack_readback, dim3(1), dim3(128), 0, s, m.dscal, m.pf.start, Kf,
+                     m.pc.start, m.chist, m.rb);
+  return hipGetLastError();
+}
+
+__global__ void k_fill_i32(int* p, int v, int n) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
 
 template <typename Key>
 __global__ __launch_bounds__(64) void k_part_count(int n, Key key, int K, int nblocks,
@@ -604,9 +646,8 @@ __global__ __launch_bounds__(kBlock) void k_flux_store(FluxArgs<T> a) {
 // active faces' fluxes in local face order (-q where the cell is the lower
 // id of the face, +q otherwise), then U += R / V, R = 0 for ending steps.
 __global__ __launch_bounds__(kBlock) void k_cell_gather(int count, const int* __restrict__ list,
-                                                        int nc, const int* __restrict__ nb,
+                                                        int nc, const uint32_t* __restrict__ fpack,
                                                         const int* __restrict__ c2f,
-                                                        const int8_t* __restrict__ lev,
                                                         const double* __restrict__ Q,
                                                         const double* __restrict__ vol,
                                                         double* __restrict__ U,
@@ -615,24 +656,28 @@ __global__ __launch_bounds__(kBlock) void k_cell_gather(int count, const int* __
   int idx = xcd_block() * kBlock + threadIdx.x;
   if (idx >= count) return;
   int i = list[idx];
-  int ti = lev[i];
-  double* Ri = R + 5 * (size_t)i;
-  double acc[5];
-  for (int k = 0; k < 5; ++k) acc[k] = Ri[k];
+  uint32_t pk = fpack[i];
+  int ti = (pk >> 20) & 15;
+  bool ends = ti <= tau_upd;
   bool touched = false;
+  double acc[5] = {0, 0, 0, 0, 0};
+  double* Ri = R + 5 * (size_t)i;
   for (int m = 0; m < 4; ++m) {
-    int n = nb[m * nc + i];
-    int tf = n >= 0 ? min(ti, (int)lev[n]) : ti;
-    if (tf > tau_s) continue;
+    if ((int)((pk >> (4 * m)) & 15) > tau_s) continue;
+    if (!touched) {
+      for (int k = 0; k < 5; ++k) acc[k] = Ri[k];
+      touched = true;
+    }
     const double* q = Q + 5 * (size_t)c2f[m * nc + i];
-    if (n >= 0 && n < i) {
+    if (pk & (1u << (16 + m))) {
       for (int k = 0; k < 5; ++k) acc[k] += q[k];
     } else {
       for (int k = 0; k < 5; ++k) acc[k] -= q[k];
     }
-    touched = true;
   }
-  if (ti <= tau_upd) {
+  if (ends) {
+    if (!touched)
+      for (int k = 0; k < 5; ++k) acc[k] = Ri[k];
     double v = vol[i];
     bool bad = false;
     for (int k = 0; k < 5; ++k) {
@@ -651,12 +696,14 @@ __global__ __launch_bounds__(kBlock) void k_cell_gather(int count, const int* __
 // cells whose level step ends: U += R / V, R = 0
 
 __global__ __launch_bounds__(kBlock) void k_update(int count, const int* __restrict__ list,
+                                                   const int8_t* __restrict__ lev, int tau_upd,
                                                    const double* __restrict__ vol,
                                                    double* __restrict__ U, double* __restrict__ R,
                                                    unsigned long long* dscal) {
   int idx = xcd_block() * kBlock + threadIdx.x;
   if (idx >= count) return;
   int i = list[idx];
+  if (lev[i] > tau_upd) return;
   double v = vol[i];
   bool bad = false;
   for (int k = 0; k < 5; ++k) {
@@ -668,6 +715,23 @@ __global__ __launch_bounds__(kBlock) void k_update(int count, const int* __restr
   if (bad) atomicOr(&dscal[2], 1ull);
 }
 
+// caller-order staging: rows of `width` elements
+template <typename T>
+__global__ void k_rows_to_caller(int n, int width, const int* __restrict__ perm,
+                                 const T* __restrict__ src, T* __restrict__ dst) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  for (int k = 0; k < width; ++k) dst[(size_t)perm[i] * width + k] = src[(size_t)i * width + k];
+}
+
+template <typename T>
+__global__ void k_rows_from_caller(int n, int width, const int* __restrict__ perm,
+                                   const T* __restrict__ src, T* __restrict__ dst) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  for (int k = 0; k < width; ++k) dst[(size_t)i * width + k] = src[(size_t)perm[i] * width + k];
+}
+
 // ---------------------------------------------------------------------------
 // launchers
 
@@ -676,8 +740,8 @@ static inline int blocks_for(int64_t n, int bs = kBlock) { return (int)((n + bs 
 int partition_blocks(int64_t n) { return (int)((n + kPartChunk - 1) / kPartChunk); }
 
 hipError_t launch_state_init(hipStream_t s, DevMesh& m, const double* d_prim, double gamma) {
-  hipLaunchKernelGGL(k_state_init, dim3(blocks_for(m.nc)), dim3(kBlock), 0, s, m.nc, d_prim,
-                     gamma - 1.0, m.U, m.R);
+  hipLaunchKernelGGL(k_state_init, dim3(blocks_for(m.nc)), dim3(kBlock), 0, s, m.nc, m.perm,
+                     d_prim, gamma - 1.0, m.U, m.R);
   return hipGetLastError();
 }
 
@@ -709,25 +773,51 @@ hipError_t launch_classify(hipStream_t s, DevMesh& m, const StepArgs& a) {
 }
 
 hipError_t launch_partitions(hipStream_t s, DevMesh& m) {
-  hipError_t e;
   int use_colour = m.scatter == TAFV_SCATTER_COLOUR;
   int Kf = use_colour ? m.ncolours * kMaxLevels : kMaxLevels;
-  e = run_partition(s, m.nf, FaceKey{m.fhL, m.fhR, m.fcol, m.lev, use_colour}, Kf, m.pf,
-                    FaceWriter{m.frec, m.fhL, m.fhR});
+  hipLaunchKernelGGL(k_face_keys, dim3(blocks_for(m.nf)), dim3(kBlock), 0, s, m.nf, m.fhL, m.fhR,
+                     m.fcol, m.lev, use_colour, m.fkey);
+  hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(kMaxKeys), 0, s, m.chist, 0, kMaxKeys);
+  hipLaunchKernelGGL(k_cell_keys, dim3(blocks_for(m.nc)), dim3(kBlock), 0, s, m.nc, m.nb_, m.lev,
+                     m.ckey, m.fpack, m.chist);
+  hipError_t e = run_partition(s, m.nf, ByteKey{m.fkey}, Kf, m.pf, FaceWriter{m.frec, m.fhL, m.fhR});
   if (e != hipSuccess) return e;
-  e = run_partition(s, m.nc, GradKey{m.nb_, m.lev, m.nc}, kMaxLevels, m.pg, IndexWriter{m.pg.list});
-  if (e != hipSuccess) return e;
-  return run_partition(s, m.nc, CellKey{m.lev}, kMaxLevels, m.pu, IndexWriter{m.pu.list});
+  return run_partition(s, m.nc, ByteKey{m.ckey}, kMaxLevels, m.pc, IndexWriter{m.pc.list});
+}
+
+template <typename T>
+static hipError_t rows_to_caller(hipStream_t s, DevMesh& m, int width, const T* src, T* dst) {
+  hipLaunchKernelGGL((k_rows_to_caller<T>), dim3(blocks_for(m.nc)), dim3(kBlock), 0, s, m.nc,
+                     width, m.perm, src, dst);
+  return hipGetLastError();
+}
+template <typename T>
+static hipError_t rows_from_caller(hipStream_t s, DevMesh& m, int width, const T* src, T* dst) {
+  hipLaunchKernelGGL((k_rows_from_caller<T>), dim3(blocks_for(m.nc)), dim3(kBlock), 0, s, m.nc,
+                     width, m.perm, src, dst);
+  return hipGetLastError();
+}
+hipError_t launch_to_caller_f64(hipStream_t s, DevMesh& m, const double* src, double* dst) {
+  return rows_to_caller<double>(s, m, 5, src, dst);
+}
+hipError_t launch_from_caller_f64(hipStream_t s, DevMesh& m, const double* src, double* dst) {
+  return rows_from_caller<double>(s, m, 5, src, dst);
+}
+hipError_t launch_to_caller_i8(hipStream_t s, DevMesh& m, const int8_t* src, int8_t* dst) {
+  return rows_to_caller<int8_t>(s, m, 1, src, dst);
+}
+hipError_t launch_from_caller_i8(hipStream_t s, DevMesh& m, const int8_t* src, int8_t* dst) {
+  return rows_from_caller<int8_t>(s, m, 1, src, dst);
 }
 
 hipError_t launch_grad(hipStream_t s, DevMesh& m, const StepArgs& a, int count) {
   if (count <= 0) return hipSuccess;
   if (a.precision == TAFV_FP32_FLUX) {
-    GradArgs<float> g{m.pg.list, count, m.nc, m.nf, m.U, m.nb_, m.lsq32, m.rf32, m.fA,
+    GradArgs<float> g{m.pc.list, count, m.nc, m.nf, m.U, m.nb_, m.lsq32, m.rf32, m.fA,
                       (float*)m.Wf, a.gas.gm1, a.boundary};
     hipLaunchKernelGGL(k_grad<float>, dim3(blocks_for(count)), dim3(kBlock), 0, s, g);
   } else {
-    GradArgs<double> g{m.pg.list, count, m.nc, m.nf, m.U, m.nb_, m.lsq, m.rf, m.fA,
+    GradArgs<double> g{m.pc.list, count, m.nc, m.nf, m.U, m.nb_, m.lsq, m.rf, m.fA,
                        (double*)m.Wf, a.gas.gm1, a.boundary};
     hipLaunchKernelGGL(k_grad<double>, dim3(blocks_for(count)), dim3(kBlock), 0, s, g);
   }
@@ -766,15 +856,15 @@ hipError_t launch_flux(hipStream_t s, DevMesh& m, const StepArgs& a, int first, 
 hipError_t launch_cell_gather(hipStream_t s, DevMesh& m, int count, int tau_s, int tau_upd) {
   if (count <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_cell_gather, dim3(blocks_for(count)), dim3(kBlock), 0, s, count,
-                     m.pg.list, m.nc, m.nb_, m.c2f, m.lev, m.Q, m.vol, m.U, m.R, tau_s, tau_upd,
+                     m.pc.list, m.nc, m.fpack, m.c2f, m.Q, m.vol, m.U, m.R, tau_s, tau_upd,
                      m.dscal);
   return hipGetLastError();
 }
 
-hipError_t launch_update(hipStream_t s, DevMesh& m, int count) {
+hipError_t launch_update(hipStream_t s, DevMesh& m, int count, int tau_upd) {
   if (count <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_update, dim3(blocks_for(count)), dim3(kBlock), 0, s, count, m.pu.list,
-                     m.vol, m.U, m.R, m.dscal);
+  hipLaunchKernelGGL(k_update, dim3(blocks_for(count)), dim3(kBlock), 0, s, count, m.pc.list,
+                     m.lev, tau_upd, m.vol, m.U, m.R, m.dscal);
   return hipGetLastError();
 }
 

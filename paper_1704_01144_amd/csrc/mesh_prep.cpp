@@ -43,17 +43,17 @@ inline V3 cross(V3 a, V3 b) {
 }  // namespace
 
 tafv_status build_host_mesh(int64_t n_nodes, const double* xyz, int64_t n_tets,
-                            const int64_t* tets, bool colour_major, HostMesh* out,
-                            std::string* err) {
+                            const int64_t* tets, bool colour_major, bool morton,
+                            HostMesh* out, std::string* err) {
   if (n_tets >= (int64_t(1) << 29)) {
     *err = "mesh too large: at most 2^29 tets";
     return TAFV_E_ARG;
   }
   const int64_t nc = n_tets;
   auto node = [&](int64_t id) { return V3{xyz[3 * id], xyz[3 * id + 1], xyz[3 * id + 2]}; };
-  std::vector<V3> xc(nc);
-  out->vol.resize(nc);
-  std::vector<FaceRec> rec(4 * nc);
+  // validate and measure in the caller's order
+  std::vector<V3> xcc(nc);
+  std::vector<double> volc(nc);
   for (int64_t t = 0; t < nc; ++t) {
     const int64_t* v = tets + 4 * t;
     for (int k = 0; k < 4; ++k) {
@@ -68,16 +68,58 @@ tafv_status build_host_mesh(int64_t n_nodes, const double* xyz, int64_t n_tets,
       *err = "tet " + std::to_string(t) + ": non-positive volume (tets must be positively oriented)";
       return TAFV_E_MESH;
     }
-    out->vol[t] = det / 6.0;
-    xc[t] = {(p0.x + p1.x + p2.x + p3.x) * 0.25, (p0.y + p1.y + p2.y + p3.y) * 0.25,
-             (p0.z + p1.z + p2.z + p3.z) * 0.25};
+    volc[t] = det / 6.0;
+    xcc[t] = {(p0.x + p1.x + p2.x + p3.x) * 0.25, (p0.y + p1.y + p2.y + p3.y) * 0.25,
+              (p0.z + p1.z + p2.z + p3.z) * 0.25};
+  }
+  // internal cell order: the caller's, or the Morton (Z-order) code of the
+  // centroid in the bounding box, 21 bits per axis, ties by caller id
+  out->perm.resize(nc);
+  std::iota(out->perm.begin(), out->perm.end(), 0);
+  if (morton) {
+    V3 lo = xcc[0], hi = xcc[0];
+    for (const V3& c : xcc) {
+      lo = {std::min(lo.x, c.x), std::min(lo.y, c.y), std::min(lo.z, c.z)};
+      hi = {std::max(hi.x, c.x), std::max(hi.y, c.y), std::max(hi.z, c.z)};
+    }
+    auto spread = [](uint64_t v) {  // bits 0..20 -> every third bit
+      v &= 0x1fffff;
+      v = (v | v << 32) & 0x1f00000000ffffull;
+      v = (v | v << 16) & 0x1f0000ff0000ffull;
+      v = (v | v << 8) & 0x100f00f00f00f00full;
+      v = (v | v << 4) & 0x10c30c30c30c30c3ull;
+      v = (v | v << 2) & 0x1249249249249249ull;
+      return v;
+    };
+    auto q = [](double x, double a, double b) {
+      double s = b > a ? (x - a) / (b - a) : 0.0;
+      return (uint64_t)std::min(2097151.0, std::max(0.0, std::floor(s * 2097151.0)));
+    };
+    std::vector<uint64_t> key(nc);
+    for (int64_t t = 0; t < nc; ++t)
+      key[t] = spread(q(xcc[t].x, lo.x, hi.x)) | spread(q(xcc[t].y, lo.y, hi.y)) << 1 |
+               spread(q(xcc[t].z, lo.z, hi.z)) << 2;
+    std::stable_sort(out->perm.begin(), out->perm.end(),
+                     [&](int32_t a, int32_t b) { return key[a] < key[b]; });
+  }
+  std::vector<int32_t> inv(nc);
+  for (int64_t i = 0; i < nc; ++i) inv[out->perm[i]] = (int32_t)i;
+  std::vector<V3> xc(nc);
+  out->vol.resize(nc);
+  for (int64_t i = 0; i < nc; ++i) {
+    xc[i] = xcc[out->perm[i]];
+    out->vol[i] = volc[out->perm[i]];
+  }
+  std::vector<FaceRec> rec(4 * nc);
+  for (int64_t t = 0; t < nc; ++t) {
+    const int64_t* v = tets + 4 * t;
     for (int s = 0; s < 4; ++s) {
       FaceRec& r = rec[4 * t + s];
       int q = 0;
       for (int k = 0; k < 4; ++k)
         if (k != s) r.v[q++] = v[k];
       std::sort(r.v, r.v + 3);
-      r.cell = (int32_t)t;
+      r.cell = inv[t];
       r.slot = s;
     }
   }

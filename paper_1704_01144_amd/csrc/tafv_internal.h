@@ -34,15 +34,17 @@ struct HostMesh {
   std::vector<double> lsq;         // [12][nc] least-squares coefficient vectors
   std::vector<double> rf;          // [12][nc] face centroid minus cell centroid
   std::vector<double> vol;         // [nc]
+  std::vector<int32_t> perm;       // [nc] internal cell -> caller cell
 };
 
 // Builds faces, geometry, colouring and least-squares weights.  Returns
 // TAFV_OK or TAFV_E_MESH with a message.
 // colour_major: faces ordered by (colour, lower cell, higher cell), else by
-// (lower cell, higher cell).
+// (lower cell, higher cell).  morton: internal cells in Z-order of their
+// centroids, else in the caller's order.
 tafv_status build_host_mesh(int64_t n_nodes, const double* xyz, int64_t n_tets,
-                            const int64_t* tets, bool colour_major, HostMesh* out,
-                            std::string* err);
+                            const int64_t* tets, bool colour_major, bool morton,
+                            HostMesh* out, std::string* err);
 
 // Partition scratch for building level-ordered index lists.
 struct Partition {
@@ -80,7 +82,15 @@ struct DevMesh {
   double* Q = nullptr;     // [nf][5] gather mode: time-integrated face fluxes
   int4* frec = nullptr;    // [nf] face records {f, hL, hR, tau_f} in partition order
   // schedule lists
-  Partition pf, pg, pu;    // faces by (colour, tau_f); cells by tau_g; cells by tau
+  Partition pf, pc;        // faces by (colour, tau_f); cells by tau_g
+  int8_t* fkey = nullptr;  // [nf] partition key of each face
+  int8_t* ckey = nullptr;  // [nc] tau_g of each cell
+  int* chist = nullptr;    // [64] cell count per (tau_g, tau)
+  int* rb = nullptr;       // packed readback buffer
+  uint32_t* fpack = nullptr; // [nc] per local face m: tau_f in bits 4m..4m+3, the cell
+                           // is the higher-id side in bit 16+m; tau in bits 20..23
+  int32_t* perm = nullptr; // [nc] internal cell -> caller cell
+  double* xfer = nullptr;  // [nc][5] staging for host transfers in caller order
   // device scalars: [0] dt_min bits, [1] theta, [2] non-finite flag
   unsigned long long* dscal = nullptr;
   // device counters: newton updates, fallbacks, vacuum; wall impulse x3
@@ -91,8 +101,8 @@ struct DevMesh {
   int32_t phase = 0, theta = 0;
   double dt_min = 0.0, t = 0.0;
   int32_t hstart_f[kMaxKeys + 1] = {0};
-  int32_t hstart_g[kMaxLevels + 1] = {0};
-  int32_t hstart_u[kMaxLevels + 1] = {0};
+  int32_t hstart_c[kMaxLevels + 1] = {0};
+  int32_t hhist[kMaxKeys] = {0};
   bool classified = false;
   tafv_stats st{};
 };

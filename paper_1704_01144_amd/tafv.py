@@ -19,6 +19,7 @@ FP64, FP32_FLUX = 0, 1
 GUESS_TR, GUESS_MLP = 0, 1
 BC_WALL, BC_TRANSMIT = 0, 1
 SCATTER_COLOUR, SCATTER_GATHER = 0, 1
+ORDER_CALLER, ORDER_MORTON = 0, 1
 
 
 class TafvError(RuntimeError):
@@ -32,7 +33,7 @@ class tafv_params(C.Structure):
                 ("level_margin", C.c_double), ("max_levels", C.c_int32), ("order", C.c_int32),
                 ("precision", C.c_int32), ("guess", C.c_int32), ("boundary", C.c_int32),
                 ("newton_max_iter", C.c_int32), ("reclassify", C.c_int32),
-                ("scatter", C.c_int32)]
+                ("scatter", C.c_int32), ("cell_order", C.c_int32)]
 
 
 class tafv_stats(C.Structure):

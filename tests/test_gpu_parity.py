@@ -42,11 +42,11 @@ def l1_rel(a, b, vol):
 
 
 def run_pair(T, orc, nodes, tets, prim, order, L, units, chunks=None, precision=0, boundary=0,
-             check_levels=True, scatter=1):
+             check_levels=True, scatter=1, cell_order=0):
     say(f"case: cells={len(tets)} order={order} L={L} units={units} precision={precision} "
-        f"scatter={scatter}")
+        f"scatter={scatter} cell_order={cell_order}")
     s = T.Solver(max_levels=L, order=order, precision=precision, boundary=boundary,
-                 scatter=scatter)
+                 scatter=scatter, cell_order=cell_order)
     s.upload(nodes, tets)
     s.init(prim)
     m = orc.Mesh(nodes, tets)
@@ -95,6 +95,15 @@ def test_graded_24_second_order(T, orc, scatter):
     u_g, o, m, st = run_pair(T, orc, nodes, tets, prim, 2, 5, 32, chunks=[3, 5, 8, 16],
                              scatter=scatter)
     assert st["theta"] >= 2
+
+
+def test_morton_cell_order(T, orc):
+    # internal Z-order of the cells: results in caller order unchanged
+    nodes, tets = I.graded_cube_mesh(16, 16.0)
+    prim = I.blast_state(nodes, tets, centre=I.blast_centre(1))
+    for scatter in (0, 1):
+        run_pair(T, orc, nodes, tets, prim, 2, 5, 16, chunks=[7, 9], scatter=scatter,
+                 cell_order=1)
 
 
 @SCATTERS

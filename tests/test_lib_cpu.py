@@ -42,8 +42,13 @@ def test_mesh_prep_matches_oracle(T, orc, n, grading):
     m = orc.Mesh(nodes, tets)
     g = m.geometry()
     assert (r["n_faces"], r["n_boundary"]) == (m.n_faces, m.n_boundary)
-    # interior faces: same (L, R) pairs and the same area vectors
-    ours = {(int(a), int(b)): r["face_area"][k] for k, (a, b) in enumerate(r["face_cells"]) if b >= 0}
+    # interior faces: the same cell pairs and the same area vectors (the
+    # library orients a face out of its lower internal cell id, so a pair
+    # may come swapped with the area negated)
+    ours = {}
+    for k, (a, b) in enumerate(r["face_cells"]):
+        if b >= 0:
+            ours[(int(min(a, b)), int(max(a, b)))] = r["face_area"][k] * (1 if a < b else -1)
     theirs = {(int(a), int(b)): g["face_area"][k] for k, (a, b) in
               enumerate(zip(g["face_L"], g["face_R"])) if b >= 0}
     assert ours.keys() == theirs.keys()
