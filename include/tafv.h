@@ -60,7 +60,8 @@ typedef enum {
   TAFV_E_DEVICE = -5,  /* a HIP runtime error; the message has its text      */
   TAFV_E_OOM = -6,     /* device memory allocation failed                    */
   TAFV_E_NUMERIC = -7, /* a non-finite state after a subiteration            */
-  TAFV_E_MLP = -8      /* reserved for the learned p* guess                  */
+  TAFV_E_MLP = -8      /* learned guess: no network set, or a non-finite
+                          parameter                                         */
 } tafv_status;
 
 enum { TAFV_FP64 = 0, TAFV_FP32_FLUX = 1 };
@@ -81,7 +82,8 @@ enum { TAFV_ORDER_CALLER = 0, TAFV_ORDER_MORTON = 1 };
 /* Method parameters.  tafv_params_default() fills: gamma 1.4, cfl 0.5,
  * newton_tol 1e-12, level_margin 1e-9, max_levels 5, order 2, precision
  * TAFV_FP64, guess TAFV_GUESS_TR, boundary TAFV_BC_WALL, newton_max_iter
- * 50, reclassify 1, scatter TAFV_SCATTER_GATHER, cell_order TAFV_ORDER_CALLER. */
+ * 50, reclassify 1, scatter TAFV_SCATTER_GATHER, cell_order TAFV_ORDER_CALLER,
+ * guess_stats 0, guess_gate 0. */
 typedef struct {
   double gamma;          /* ratio of specific heats, > 1                        */
   double cfl;            /* dt_i = cfl V_i / sum_f (|u_i . n_f| + a_i) |A_f|    */
@@ -92,13 +94,22 @@ typedef struct {
   int32_t precision;     /* TAFV_FP64 or TAFV_FP32_FLUX (reconstruction and flux
                             in FP32; state, accumulators, time steps, levels
                             and the p* Newton solve in FP64)                    */
-  int32_t guess;         /* initial p* of the Newton solve                      */
+  int32_t guess;         /* initial p* of the Newton solve: TAFV_GUESS_TR (the
+                            two-rarefaction value p_TR), or TAFV_GUESS_MLP
+                            (gamma 1.4 and TAFV_SCATTER_GATHER only): where p_TR
+                            is inexact and the network's correction y exceeds
+                            guess_gate in size, p_TR exp(y); the Newton
+                            iteration and its stop test are unchanged          */
   int32_t boundary;      /* every boundary face: wall or transmissive           */
   int32_t newton_max_iter; /* Newton updates before bisection takes over       */
   int32_t reclassify;    /* 1: new levels at every iteration start; 0: keep the
                             first classification (and its dt_min)               */
   int32_t scatter;       /* TAFV_SCATTER_COLOUR or TAFV_SCATTER_GATHER          */
   int32_t cell_order;    /* TAFV_ORDER_CALLER or TAFV_ORDER_MORTON              */
+  int32_t guess_stats;   /* 1: count the faces where the two-rarefaction start
+                            is inexact (at least one shock) and their Newton
+                            updates, also with TAFV_GUESS_TR                    */
+  double guess_gate;     /* |y| threshold of the learned correction (>= 0)      */
 } tafv_params;
 
 /* Counters (int64) and schedule state.  Summed over meshes where a call
@@ -115,6 +126,11 @@ typedef struct {
                               iteration (0 = every cell synchronised)          */
   double dt_min, t_reached;/* current dt_min; physical time advanced           */
   double wall_impulse[3];  /* time-integrated momentum flux through walls      */
+  int64_t guess_faces;     /* face solves where two-rarefaction is inexact
+                              (counted with guess_stats or TAFV_GUESS_MLP)     */
+  int64_t guess_newton_updates; /* Newton updates on those faces               */
+  int64_t guess_rejected;  /* network guesses rejected (non-finite or <= 0)    */
+  int64_t guess_used;      /* face solves started from the network's guess     */
 } tafv_stats;
 
 /* Fill *p with the defaults listed above. */
@@ -199,6 +215,49 @@ tafv_status tafv_checkpoint_write(tafv_ctx* ctx, int32_t mesh_id, const double* 
                                   const double* accum, const int8_t* levels,
                                   int32_t phase, int32_t theta, double dt_min,
                                   double t);
+
+/* ---- learned initial guess of the star pressure ----------------------
+ * A 6-32-32-1 ReLU network maps the normalised face states
+ * x = (rho_L/rho_m, u_L/a_m, p_L/p_m, rho_R/rho_m, u_R/a_m, p_R/p_m)
+ * (normal velocities; rho_m, p_m side averages; a_m = sqrt(g p_m/rho_m)) to
+ * a correction y ~ ln(p_star / p_TR) of the two-rarefaction value p_TR,
+ * p_star the exact star pressure; the Newton solve starts from
+ * p_TR exp(y).  BF16 inputs, weights and activations, FP32 accumulation, on
+ * the matrix cores.  Parameter vector (TAFV_MLP_PARAMS floats): W1 [32][6]
+ * row-major, b1 [32], W2 [32][32] row-major, b2 [32], w3 [32], b3.  The
+ * context keeps FP32 master parameters and their BF16 device copy. */
+#define TAFV_MLP_PARAMS 1313
+
+/* Set / read the FP32 parameters (n must be TAFV_MLP_PARAMS).  Setting
+ * resets the optimiser state. */
+tafv_status tafv_mlp_set(tafv_ctx* ctx, const float* params, int64_t n);
+tafv_status tafv_mlp_get(tafv_ctx* ctx, float* params, int64_t n);
+
+/* Network outputs y[n] for host inputs x [n][6]. TAFV_E_MLP if unset. */
+tafv_status tafv_mlp_forward(tafv_ctx* ctx, const float* x, int64_t n, float* y);
+
+/* Gradient of the mean squared error mean((y - t)^2) over the n rows of x
+ * [n][6] with targets t[n], computed by the training kernels (BF16 forward,
+ * MFMA backward, FP32 sums); grad[TAFV_MLP_PARAMS], *loss the mean squared
+ * error (either may be NULL). */
+tafv_status tafv_mlp_grad(tafv_ctx* ctx, const float* x, const float* t, int64_t n,
+                          float* grad, float* loss);
+
+/* Train on the GPU with Adam (lr, beta1 0.9, beta2 0.999, eps 1e-8) for
+ * `epochs` passes over the n rows in minibatches of `batch` rows; each
+ * epoch visits the rows in the order i -> (a i + b) mod n with a, b drawn
+ * from `seed` and the epoch by the splitmix64 generator.  loss[epochs]
+ * (nullable) receives the mean squared error of each epoch. */
+tafv_status tafv_mlp_train(tafv_ctx* ctx, const float* x, const float* t, int64_t n,
+                           int32_t epochs, int32_t batch, float lr, uint64_t seed, float* loss);
+
+/* Face logging: during tafv_advance, a hashed sample (probability `rate`,
+ * hash of seed, face and subiteration) of the face solves where the
+ * two-rarefaction start is inexact writes a row of 7 floats (the 6 network
+ * inputs and the target ln(p_star / p_TR)) until `capacity` rows are held.
+ * capacity 0 turns logging off.  Reading returns min(rows logged, cap). */
+tafv_status tafv_facelog_config(tafv_ctx* ctx, int64_t capacity, double rate, uint64_t seed);
+tafv_status tafv_facelog_read(tafv_ctx* ctx, float* rows, int64_t cap, int64_t* n_rows);
 
 /* Per-kernel timing: when enabled, tafv_advance() brackets every launch of
  * each kernel class with HIP events on the context stream.

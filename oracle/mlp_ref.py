@@ -10,8 +10,9 @@ the design notes list):
           p -> s c^2 p, which leaves x and ln(p*/p_m) unchanged, so the
           target is a function of x alone;
   network h1 = relu(W1 x + b1) (32), h2 = relu(W2 h1 + b2) (32),
-          y = w3 . h2 + b3, the guess is p0 = p_m exp(y);
-  target  y* = ln(p*/p_m);
+          y = w3 . h2 + b3, a correction of the two-rarefaction value p_TR
+          (Toro, ch. 4): the guess is p0 = p_TR exp(y);
+  target  y* = ln(p*/p_TR), also invariant under the scaling above;
   loss    mean squared error of y over a batch.
 Parameter vector (1313 values): W1 [32][6] row-major, b1 [32], W2 [32][32]
 row-major, b2 [32], w3 [32], b3.
@@ -63,8 +64,22 @@ def features(wl, wr, gamma=1.4):
     return x, rm, pm, am
 
 
-def target(p_star, pm):
-    return np.log(np.asarray(p_star, dtype=np.float64) / pm)
+def two_rarefaction(wl, wr, gamma=1.4):
+    """p_TR = [(a_L + a_R - (g-1)/2 (u_R - u_L)) / (a_L p_L^-z + a_R p_R^-z)]^(1/z),
+    z = (g-1)/(2g): the star pressure if both waves are rarefactions."""
+    wl = np.atleast_2d(np.asarray(wl, dtype=np.float64))
+    wr = np.atleast_2d(np.asarray(wr, dtype=np.float64))
+    z = (gamma - 1.0) / (2.0 * gamma)
+    al = np.sqrt(gamma * wl[:, 2] / wl[:, 0])
+    ar = np.sqrt(gamma * wr[:, 2] / wr[:, 0])
+    num = al + ar - 0.5 * (gamma - 1.0) * (wr[:, 1] - wl[:, 1])
+    den = al * wl[:, 2] ** (-z) + ar * wr[:, 2] ** (-z)
+    return (num / den) ** (1.0 / z)
+
+
+def target(p_star, p_tr):
+    """ln(p*/p_TR)."""
+    return np.log(np.asarray(p_star, dtype=np.float64) / p_tr)
 
 
 def forward(theta, x, emulate_bf16=False):

@@ -9,6 +9,7 @@
 #include <string>
 
 #include "kernels.h"
+#include "mlp_kernels.h"
 #include "tafv_internal.h"
 
 using namespace tafv;
@@ -171,6 +172,22 @@ int64_t cells_upto_tau(const DevMesh& m, int t) {
   return n;
 }
 
+FluxFeatures flux_features(tafv_ctx* c, DevMesh& m) {
+  FluxFeatures ft;
+  bool mlp = c->prm.guess == TAFV_GUESS_MLP;
+  bool stats = c->prm.guess_stats || c->log_cap > 0;
+  ft.feat = (stats ? 1 : 0) | (mlp ? 2 : 0);
+  ft.mlp = (const MlpDev*)c->mlp_w;
+  ft.log_rows = c->log_rows;
+  ft.log_count = c->log_count;
+  ft.log_cap = c->log_cap;
+  ft.log_rate = c->log_rate;
+  ft.log_seed = c->log_seed;
+  ft.subit = (unsigned long long)m.st.subiterations;
+  ft.guess_gate = (float)c->prm.guess_gate;
+  return ft;
+}
+
 tafv_status subiteration(tafv_ctx* c, DevMesh& m, tafv_stats* acc) {
   if (m.phase == 0 && (c->prm.reclassify || !m.classified)) {
     tafv_status st = classify(c, m);
@@ -201,7 +218,7 @@ tafv_status subiteration(tafv_ctx* c, DevMesh& m, tafv_stats* acc) {
       int cnt = m.hstart_f[col * kMaxLevels + tau_s + 1] - first;
       faces += cnt;
       ProfScope ps(c, P_FLUX, cnt);
-      HIP_TRY(c, launch_flux(c->stream, m, a, first, cnt));
+      HIP_TRY(c, launch_flux(c->stream, m, a, first, cnt, FluxFeatures{}));
     }
     int ulist = cells_upto_g(m, upd);
     ProfScope ps(c, P_UPDATE, ulist);
@@ -211,7 +228,7 @@ tafv_status subiteration(tafv_ctx* c, DevMesh& m, tafv_stats* acc) {
     faces = cnt;
     {
       ProfScope ps(c, P_FLUX, cnt);
-      HIP_TRY(c, launch_flux(c->stream, m, a, 0, cnt));
+      HIP_TRY(c, launch_flux(c->stream, m, a, 0, cnt, flux_features(c, m)));
     }
     int ccnt = cells_upto_g(m, std::max(tau_s, upd));
     ProfScope ps(c, P_GATHER, ccnt);
@@ -238,16 +255,19 @@ tafv_status read_counters(tafv_ctx* c, DevMesh& m) {
   HIP_TRY(c, hipMemcpyAsync(imp.data(), m.dimpulse, kCounterWords * sizeof(double),
                             hipMemcpyDeviceToHost, c->stream));
   HIP_TRY(c, hipStreamSynchronize(c->stream));
-  unsigned long long tot[3] = {0, 0, 0};
+  unsigned long long tot[7] = {0, 0, 0, 0, 0, 0, 0};
   double itot[3] = {0, 0, 0};
-  for (int sl = 0; sl < kCounterSlots; ++sl)
-    for (int k = 0; k < 3; ++k) {
-      tot[k] += cnt[sl * kCounterStride + k];
-      itot[k] += imp[sl * kCounterStride + k];
-    }
+  for (int sl = 0; sl < kCounterSlots; ++sl) {
+    for (int k = 0; k < 7; ++k) tot[k] += cnt[sl * kCounterStride + k];
+    for (int k = 0; k < 3; ++k) itot[k] += imp[sl * kCounterStride + k];
+  }
   m.st.newton_updates = (int64_t)tot[0];
   m.st.newton_fallbacks = (int64_t)tot[1];
   m.st.vacuum_faces = (int64_t)tot[2];
+  m.st.guess_faces = (int64_t)tot[3];
+  m.st.guess_newton_updates = (int64_t)tot[4];
+  m.st.guess_rejected = (int64_t)tot[5];
+  m.st.guess_used = (int64_t)tot[6];
   for (int k = 0; k < 3; ++k) m.st.wall_impulse[k] = itot[k];
   m.st.theta = m.theta;
   m.st.phase = m.phase;
@@ -280,6 +300,8 @@ tafv_status tafv_params_default(tafv_params* p) {
   p->reclassify = 1;
   p->scatter = TAFV_SCATTER_GATHER;
   p->cell_order = TAFV_ORDER_CALLER;
+  p->guess_stats = 0;
+  p->guess_gate = 0.0;
   return TAFV_OK;
 }
 
@@ -297,7 +319,11 @@ tafv_status tafv_create(int device, const tafv_params* params, void* hip_stream,
       (p.cell_order != TAFV_ORDER_CALLER && p.cell_order != TAFV_ORDER_MORTON) ||
       !(p.level_margin >= 0.0 && p.level_margin < 0.5))
     return fail(nullptr, TAFV_E_ARG, "invalid parameters");
-  if (p.guess != TAFV_GUESS_TR) return fail(nullptr, TAFV_E_ARG, "unsupported guess mode");
+  if (p.guess != TAFV_GUESS_TR && p.guess != TAFV_GUESS_MLP)
+    return fail(nullptr, TAFV_E_ARG, "unknown guess mode");
+  if (!(p.guess_gate >= 0.0)) return fail(nullptr, TAFV_E_ARG, "negative guess gate");
+  if (p.guess == TAFV_GUESS_MLP && (p.gamma != 1.4 || p.scatter != TAFV_SCATTER_GATHER))
+    return fail(nullptr, TAFV_E_ARG, "the learned guess needs gamma 1.4 and gather scatter");
   int ndev = 0;
   hipError_t e = hipGetDeviceCount(&ndev);
   if (e != hipSuccess || ndev == 0) return fail(nullptr, TAFV_E_DEVICE, "no HIP device");
@@ -329,6 +355,10 @@ tafv_status tafv_destroy(tafv_ctx* c) {
     (void)hipEventDestroy(pe.b);
   }
   for (hipEvent_t e : c->event_pool) (void)hipEventDestroy(e);
+  void* bufs[] = {c->mlp_th, c->mlp_m, c->mlp_v, c->mlp_grad, c->mlp_gpart, c->mlp_lpart,
+                  c->mlp_loss, c->mlp_w, c->log_rows, c->log_count};
+  for (void* b : bufs)
+    if (b) (void)hipFree(b);
   if (c->hpin) (void)hipHostFree(c->hpin);
   delete c;
   return TAFV_OK;
@@ -533,6 +563,8 @@ tafv_status tafv_advance(tafv_ctx* c, int64_t n, tafv_stats* out) {
   if (c->meshes.empty()) return fail(c, TAFV_E_ORDER, "no mesh uploaded");
   for (DevMesh* m : c->meshes)
     if (!m->has_state) return fail(c, TAFV_E_ORDER, "advance before state_init");
+  if (c->prm.guess == TAFV_GUESS_MLP && !c->mlp_ready)
+    return fail(c, TAFV_E_MLP, "learned guess selected but no network set");
   HIP_TRY(c, hipSetDevice(c->device));
   tafv_stats acc{};
   for (int64_t k = 0; k < n; ++k) {
@@ -552,6 +584,16 @@ tafv_status tafv_advance(tafv_ctx* c, int64_t n, tafv_stats* out) {
     acc.dt_min = last->dt_min;
     acc.t_reached = last->t;
     for (int t = 0; t < kMaxLevels; ++t) acc.cells_per_level[t] = last->st.cells_per_level[t];
+    for (DevMesh* m : c->meshes) {
+      acc.newton_updates += m->st.newton_updates;
+      acc.newton_fallbacks += m->st.newton_fallbacks;
+      acc.vacuum_faces += m->st.vacuum_faces;
+      acc.guess_faces += m->st.guess_faces;
+      acc.guess_newton_updates += m->st.guess_newton_updates;
+      acc.guess_rejected += m->st.guess_rejected;
+      acc.guess_used += m->st.guess_used;
+      for (int k = 0; k < 3; ++k) acc.wall_impulse[k] += m->st.wall_impulse[k];
+    }
     *out = acc;
   }
   return TAFV_OK;
@@ -651,6 +693,210 @@ tafv_status tafv_checkpoint_write(tafv_ctx* c, int32_t mesh_id, const double* co
   m->dt_min = dt_min;
   m->t = t;
   m->classified = true;
+  return TAFV_OK;
+}
+
+static tafv_status ensure_mlp(tafv_ctx* c) {
+  if (c->mlp_th) return TAFV_OK;
+  hipError_t e = hipSuccess;
+  auto chk = [&](hipError_t x) {
+    if (e == hipSuccess) e = x;
+  };
+  chk(hipMalloc(&c->mlp_th, kMlpParams * sizeof(float)));
+  chk(hipMalloc(&c->mlp_m, kMlpParams * sizeof(float)));
+  chk(hipMalloc(&c->mlp_v, kMlpParams * sizeof(float)));
+  chk(hipMalloc(&c->mlp_grad, kMlpParams * sizeof(float)));
+  chk(hipMalloc(&c->mlp_loss, 4096 * sizeof(float)));
+  chk(hipMalloc(&c->mlp_w, sizeof(MlpDev)));
+  if (e != hipSuccess) return hip_fail(c, e, "network allocation");
+  return TAFV_OK;
+}
+
+static tafv_status ensure_gpart(tafv_ctx* c, int64_t rows) {
+  int64_t nb = (rows + 63) / 64;
+  if (nb <= c->mlp_gpart_blocks) return TAFV_OK;
+  if (c->mlp_gpart) (void)hipFree(c->mlp_gpart);
+  if (c->mlp_lpart) (void)hipFree(c->mlp_lpart);
+  c->mlp_gpart = nullptr;
+  c->mlp_lpart = nullptr;
+  c->mlp_gpart_blocks = 0;
+  HIP_TRY(c, hipMalloc(&c->mlp_gpart, (size_t)nb * kMlpParams * sizeof(float)));
+  HIP_TRY(c, hipMalloc(&c->mlp_lpart, (size_t)nb * sizeof(float)));
+  c->mlp_gpart_blocks = nb;
+  return TAFV_OK;
+}
+
+// device copies of host rows for the network calls, freed on scope exit
+struct DevBuf {
+  void* p = nullptr;
+  ~DevBuf() {
+    if (p) (void)hipFree(p);
+  }
+};
+
+tafv_status tafv_mlp_set(tafv_ctx* c, const float* params, int64_t n) {
+  if (!c) return TAFV_E_ARG;
+  if (!params || n != kMlpParams) return fail(c, TAFV_E_ARG, "expected 1313 parameters");
+  for (int64_t k = 0; k < n; ++k)
+    if (!std::isfinite(params[k])) return fail(c, TAFV_E_MLP, "non-finite network parameter");
+  HIP_TRY(c, hipSetDevice(c->device));
+  tafv_status st = ensure_mlp(c);
+  if (st != TAFV_OK) return st;
+  HIP_TRY(c, hipMemcpyAsync(c->mlp_th, params, kMlpParams * sizeof(float), hipMemcpyHostToDevice,
+                            c->stream));
+  HIP_TRY(c, mlp_fill(c->stream, c->mlp_m, 0.f, kMlpParams));
+  HIP_TRY(c, mlp_fill(c->stream, c->mlp_v, 0.f, kMlpParams));
+  HIP_TRY(c, mlp_pack(c->stream, c->mlp_th, (MlpDev*)c->mlp_w));
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  c->mlp_step = 0;
+  c->mlp_ready = true;
+  return TAFV_OK;
+}
+
+tafv_status tafv_mlp_get(tafv_ctx* c, float* params, int64_t n) {
+  if (!c) return TAFV_E_ARG;
+  if (!params || n != kMlpParams) return fail(c, TAFV_E_ARG, "expected 1313 parameters");
+  if (!c->mlp_ready) return fail(c, TAFV_E_MLP, "no network set");
+  HIP_TRY(c, hipSetDevice(c->device));
+  HIP_TRY(c, hipMemcpyAsync(params, c->mlp_th, kMlpParams * sizeof(float), hipMemcpyDeviceToHost,
+                            c->stream));
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  return TAFV_OK;
+}
+
+tafv_status tafv_mlp_forward(tafv_ctx* c, const float* x, int64_t n, float* y) {
+  if (!c) return TAFV_E_ARG;
+  if (!x || !y || n < 0 || n > INT32_MAX / 8) return fail(c, TAFV_E_ARG, "invalid arguments");
+  if (!c->mlp_ready) return fail(c, TAFV_E_MLP, "no network set");
+  if (n == 0) return TAFV_OK;
+  HIP_TRY(c, hipSetDevice(c->device));
+  DevBuf dx, dy;
+  HIP_TRY(c, hipMalloc(&dx.p, n * kMlpIn * sizeof(float)));
+  HIP_TRY(c, hipMalloc(&dy.p, n * sizeof(float)));
+  HIP_TRY(c, hipMemcpyAsync(dx.p, x, n * kMlpIn * sizeof(float), hipMemcpyHostToDevice, c->stream));
+  HIP_TRY(c, mlp_forward(c->stream, (int)n, (const float*)dx.p, (const MlpDev*)c->mlp_w,
+                         (float*)dy.p));
+  HIP_TRY(c, hipMemcpyAsync(y, dy.p, n * sizeof(float), hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  return TAFV_OK;
+}
+
+tafv_status tafv_mlp_grad(tafv_ctx* c, const float* x, const float* t, int64_t n, float* grad,
+                          float* loss) {
+  if (!c) return TAFV_E_ARG;
+  if (!x || !t || n < 1 || n > INT32_MAX / 8) return fail(c, TAFV_E_ARG, "invalid arguments");
+  if (!c->mlp_ready) return fail(c, TAFV_E_MLP, "no network set");
+  HIP_TRY(c, hipSetDevice(c->device));
+  tafv_status st = ensure_gpart(c, n);
+  if (st != TAFV_OK) return st;
+  DevBuf dx, dt;
+  HIP_TRY(c, hipMalloc(&dx.p, n * kMlpIn * sizeof(float)));
+  HIP_TRY(c, hipMalloc(&dt.p, n * sizeof(float)));
+  HIP_TRY(c, hipMemcpyAsync(dx.p, x, n * kMlpIn * sizeof(float), hipMemcpyHostToDevice, c->stream));
+  HIP_TRY(c, hipMemcpyAsync(dt.p, t, n * sizeof(float), hipMemcpyHostToDevice, c->stream));
+  HIP_TRY(c, mlp_fill(c->stream, c->mlp_loss, 0.f, 1));
+  HIP_TRY(c, mlp_gradient(c->stream, 1ull, 0ull, (unsigned long long)n, 0, n, (const float*)dx.p,
+                          (const float*)dt.p, (const MlpDev*)c->mlp_w, c->mlp_gpart,
+                          c->mlp_lpart, c->mlp_grad, c->mlp_loss, 1.0f / (float)n));
+  if (grad)
+    HIP_TRY(c, hipMemcpyAsync(grad, c->mlp_grad, kMlpParams * sizeof(float),
+                              hipMemcpyDeviceToHost, c->stream));
+  float l = 0.f;
+  HIP_TRY(c, hipMemcpyAsync(&l, c->mlp_loss, sizeof(float), hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  if (loss) *loss = l;
+  return TAFV_OK;
+}
+
+static uint64_t splitmix64(uint64_t& s) {
+  uint64_t z = (s += 0x9E3779B97F4A7C15ull);
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+
+static uint64_t gcd_u64(uint64_t a, uint64_t b) {
+  while (b) {
+    uint64_t t = a % b;
+    a = b;
+    b = t;
+  }
+  return a;
+}
+
+tafv_status tafv_mlp_train(tafv_ctx* c, const float* x, const float* t, int64_t n,
+                           int32_t epochs, int32_t batch, float lr, uint64_t seed, float* loss) {
+  if (!c) return TAFV_E_ARG;
+  if (!x || !t || n < 1 || n > INT32_MAX / 8 || epochs < 0 || epochs > 4096 || batch < 1 ||
+      !(lr > 0.f))
+    return fail(c, TAFV_E_ARG, "invalid arguments");
+  if (!c->mlp_ready) return fail(c, TAFV_E_MLP, "no network set (initial parameters)");
+  HIP_TRY(c, hipSetDevice(c->device));
+  tafv_status st = ensure_gpart(c, std::min<int64_t>(batch, n));
+  if (st != TAFV_OK) return st;
+  DevBuf dx, dt;
+  HIP_TRY(c, hipMalloc(&dx.p, n * kMlpIn * sizeof(float)));
+  HIP_TRY(c, hipMalloc(&dt.p, n * sizeof(float)));
+  HIP_TRY(c, hipMemcpyAsync(dx.p, x, n * kMlpIn * sizeof(float), hipMemcpyHostToDevice, c->stream));
+  HIP_TRY(c, hipMemcpyAsync(dt.p, t, n * sizeof(float), hipMemcpyHostToDevice, c->stream));
+  HIP_TRY(c, mlp_fill(c->stream, c->mlp_loss, 0.f, std::max(epochs, 1)));
+  uint64_t state = seed;
+  for (int e = 0; e < epochs; ++e) {
+    uint64_t un = (uint64_t)n;
+    uint64_t a = un > 2 ? 1 + 2 * (splitmix64(state) % (un / 2)) : 1;
+    while (gcd_u64(a, un) != 1) a += 2;
+    uint64_t b = splitmix64(state) % un;
+    for (int64_t first = 0; first < n; first += batch) {
+      int64_t cnt = std::min<int64_t>(batch, n - first);
+      HIP_TRY(c, mlp_gradient(c->stream, a, b, un, first, cnt, (const float*)dx.p,
+                              (const float*)dt.p, (const MlpDev*)c->mlp_w, c->mlp_gpart,
+                              c->mlp_lpart, c->mlp_grad, c->mlp_loss + e, 1.0f / (float)n));
+      HIP_TRY(c, mlp_adam(c->stream, c->mlp_th, c->mlp_m, c->mlp_v, c->mlp_grad, lr,
+                          ++c->mlp_step));
+      HIP_TRY(c, mlp_pack(c->stream, c->mlp_th, (MlpDev*)c->mlp_w));
+    }
+  }
+  if (loss && epochs > 0)
+    HIP_TRY(c, hipMemcpyAsync(loss, c->mlp_loss, epochs * sizeof(float), hipMemcpyDeviceToHost,
+                              c->stream));
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  return TAFV_OK;
+}
+
+tafv_status tafv_facelog_config(tafv_ctx* c, int64_t capacity, double rate, uint64_t seed) {
+  if (!c) return TAFV_E_ARG;
+  if (capacity < 0 || !(rate >= 0.0 && rate <= 1.0)) return fail(c, TAFV_E_ARG, "invalid log");
+  HIP_TRY(c, hipSetDevice(c->device));
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  if (c->log_rows) (void)hipFree(c->log_rows);
+  c->log_rows = nullptr;
+  c->log_cap = 0;
+  if (!c->log_count) HIP_TRY(c, hipMalloc(&c->log_count, sizeof(unsigned long long)));
+  HIP_TRY(c, launch_fill_u64(c->stream, c->log_count, 0ull, 1));
+  if (capacity > 0) HIP_TRY(c, hipMalloc(&c->log_rows, (size_t)capacity * 7 * sizeof(float)));
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  c->log_cap = capacity;
+  c->log_rate = rate;
+  c->log_seed = seed;
+  return TAFV_OK;
+}
+
+tafv_status tafv_facelog_read(tafv_ctx* c, float* rows, int64_t cap, int64_t* n_rows) {
+  if (!c) return TAFV_E_ARG;
+  if (!n_rows || cap < 0 || (cap > 0 && !rows)) return fail(c, TAFV_E_ARG, "invalid arguments");
+  *n_rows = 0;
+  if (!c->log_count) return TAFV_OK;
+  HIP_TRY(c, hipSetDevice(c->device));
+  unsigned long long cnt = 0;
+  HIP_TRY(c, hipMemcpyAsync(&cnt, c->log_count, sizeof(cnt), hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  int64_t k = std::min<int64_t>((int64_t)std::min<unsigned long long>(cnt, (unsigned long long)c->log_cap), cap);
+  if (k > 0) {
+    HIP_TRY(c, hipMemcpyAsync(rows, c->log_rows, (size_t)k * 7 * sizeof(float),
+                              hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+  }
+  *n_rows = k;
   return TAFV_OK;
 }
 

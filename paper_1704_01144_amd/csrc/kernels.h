@@ -2,6 +2,7 @@
 #pragma once
 
 #include "gas.h"
+#include "mlp.h"
 #include "tafv_internal.h"
 
 namespace tafv {
@@ -18,7 +19,20 @@ hipError_t launch_dt(hipStream_t s, DevMesh& m, const StepArgs& a);
 hipError_t launch_classify(hipStream_t s, DevMesh& m, const StepArgs& a);
 hipError_t launch_partitions(hipStream_t s, DevMesh& m);
 hipError_t launch_grad(hipStream_t s, DevMesh& m, const StepArgs& a, int count);
-hipError_t launch_flux(hipStream_t s, DevMesh& m, const StepArgs& a, int first, int count);
+// optional flux features: feat bit 0 = gate statistics and face logging,
+// bit 1 = learned guess (gamma = 1.4, gather mode)
+struct FluxFeatures {
+  int feat = 0;
+  const MlpDev* mlp = nullptr;
+  float* log_rows = nullptr;
+  unsigned long long* log_count = nullptr;
+  long long log_cap = 0;
+  double log_rate = 0.0;
+  unsigned long long log_seed = 0, subit = 0;
+  float guess_gate = 0.f;
+};
+hipError_t launch_flux(hipStream_t s, DevMesh& m, const StepArgs& a, int first, int count,
+                       const FluxFeatures& ft);
 hipError_t launch_cell_gather(hipStream_t s, DevMesh& m, int count, int tau_s, int tau_upd);
 hipError_t launch_update(hipStream_t s, DevMesh& m, int count, int tau_upd);
 hipError_t launch_pack_readback(hipStream_t s, DevMesh& m, int Kf);

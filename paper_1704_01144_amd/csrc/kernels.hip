@@ -23,6 +23,7 @@
 #include <hipcub/hipcub.hpp>
 
 #include "kernels.h"
+#include "mlp.h"
 
 namespace tafv {
 
@@ -434,6 +435,14 @@ struct FluxArgs {
   unsigned long long* dcount;
   double* dimpulse;
   StepArgs s;
+  // learned guess and face logging (kernels with features only)
+  const MlpDev* mlp;
+  float* log_rows;  // [log_cap][7]: 6 inputs, ln(p*/p_m)
+  unsigned long long* log_count;
+  long long log_cap;
+  double log_rate;
+  unsigned long long log_seed, subit;
+  float guess_gate;
 };
 
 template <int ORDER, typename T>
@@ -450,6 +459,7 @@ __device__ inline void load_side(const FluxArgs<T>& a, int h, T* w) {
 
 struct SolveInfo {
   int iters, fallback, vacuum;
+  int gated, gated_iters, rejected, used;  // faces where two-rarefaction is inexact
 };
 
 // |A| F(W(0)) . n for one face: reconstructed states, rotation to the face
@@ -467,7 +477,6 @@ __device__ inline void face_flux(const FluxArgs<T>& a, int4 r, T* phi, SolveInfo
   T am = a2 * ia;
   T nx = ax * ia, ny = ay * ia, nz = az * ia;
   T unl = wl[1] * nx + wl[2] * ny + wl[3] * nz;
-  info.iters = info.fallback = info.vacuum = 0;
   if (hR < 0 && a.s.boundary != TAFV_BC_WALL) {  // transmissive: F(W_L)
     T E = wl[4] * (T)(1.0 / G.gm1) + (T)0.5 * wl[0] * (wl[1] * wl[1] + wl[2] * wl[2] + wl[3] * wl[3]);
     phi[0] = am * wl[0] * unl;
@@ -545,21 +554,20 @@ __device__ inline void face_flux(const FluxArgs<T>& a, int4 r, T* phi, SolveInfo
 // serialise on one address; the host sums the slots.
 __device__ inline void flush_counters(const SolveInfo& info, double i0, double i1, double i2,
                                       unsigned long long* dcount, double* dimpulse) {
-  __shared__ int s_cnt[3];
+  __shared__ int s_cnt[7];
   __shared__ double s_imp[3];
-  if (threadIdx.x < 3) {
-    s_cnt[threadIdx.x] = 0;
-    s_imp[threadIdx.x] = 0.0;
-  }
+  if (threadIdx.x < 7) s_cnt[threadIdx.x] = 0;
+  if (threadIdx.x < 3) s_imp[threadIdx.x] = 0.0;
   __syncthreads();
-  int it = wave_sum(info.iters), fb = wave_sum(info.fallback), vc = wave_sum(info.vacuum);
+  int c[7] = {wave_sum(info.iters), wave_sum(info.fallback), wave_sum(info.vacuum),
+              wave_sum(info.gated), wave_sum(info.gated_iters), wave_sum(info.rejected),
+              wave_sum(info.used)};
   i0 = wave_sum(i0);
   i1 = wave_sum(i1);
   i2 = wave_sum(i2);
   if ((threadIdx.x & 63) == 0) {
-    atomicAdd(&s_cnt[0], it);
-    if (fb) atomicAdd(&s_cnt[1], fb);
-    if (vc) atomicAdd(&s_cnt[2], vc);
+    for (int k = 0; k < 7; ++k)
+      if (c[k]) atomicAdd(&s_cnt[k], c[k]);
     if (i0 != 0.0 || i1 != 0.0 || i2 != 0.0) {
       atomicAdd(&s_imp[0], i0);
       atomicAdd(&s_imp[1], i1);
@@ -568,10 +576,9 @@ __device__ inline void flush_counters(const SolveInfo& info, double i0, double i
   }
   __syncthreads();
   if (threadIdx.x == 0) {
-    unsigned long long* c = dcount + (blockIdx.x % kCountSlots) * kSlotStride;
-    if (s_cnt[0]) atomicAdd(&c[0], (unsigned long long)s_cnt[0]);
-    if (s_cnt[1]) atomicAdd(&c[1], (unsigned long long)s_cnt[1]);
-    if (s_cnt[2]) atomicAdd(&c[2], (unsigned long long)s_cnt[2]);
+    unsigned long long* cs = dcount + (blockIdx.x % kCountSlots) * kSlotStride;
+    for (int k = 0; k < 7; ++k)
+      if (s_cnt[k]) atomicAdd(&cs[k], (unsigned long long)s_cnt[k]);
     if (s_imp[0] != 0.0 || s_imp[1] != 0.0 || s_imp[2] != 0.0) {
       double* d = dimpulse + (blockIdx.x % kCountSlots) * kSlotStride;
       atomicAdd(&d[0], s_imp[0]);
@@ -588,7 +595,7 @@ __device__ inline void flush_counters(const SolveInfo& info, double i0, double i
 template <int ORDER, typename T, bool G14>
 __global__ __launch_bounds__(kBlock) void k_flux_colour(FluxArgs<T> a) {
   int idx = xcd_block() * kBlock + threadIdx.x;
-  SolveInfo info{0, 0, 0};
+  SolveInfo info{0, 0, 0, 0, 0, 0, 0};
   double i0 = 0, i1 = 0, i2 = 0;
   if (idx < a.count) {
     int4 r = a.rec[idx];
@@ -624,7 +631,7 @@ __global__ __launch_bounds__(kBlock) void k_flux_colour(FluxArgs<T> a) {
 template <int ORDER, typename T, bool G14>
 __global__ __launch_bounds__(kBlock) void k_flux_store(FluxArgs<T> a) {
   int idx = xcd_block() * kBlock + threadIdx.x;
-  SolveInfo info{0, 0, 0};
+  SolveInfo info{0, 0, 0, 0, 0, 0, 0};
   double i0 = 0, i1 = 0, i2 = 0;
   if (idx < a.count) {
     int4 r = a.rec[idx];
@@ -634,6 +641,180 @@ __global__ __launch_bounds__(kBlock) void k_flux_store(FluxArgs<T> a) {
     double* q = a.Q + 5 * (size_t)r.x;
     for (int k = 0; k < 5; ++k) q[k] = dtf * (double)phi[k];
     if (r.z < 0 && a.s.boundary == TAFV_BC_WALL) {
+      i0 = q[1];
+      i1 = q[2];
+      i2 = q[3];
+    }
+  }
+  flush_counters(info, i0, i1, i2, a.dcount, a.dimpulse);
+}
+
+// splitmix64 output function (Steele, Lea, Flood 2014): a counter-based
+// hash for sampling the logged faces
+__device__ inline unsigned long long mix64(unsigned long long z) {
+  z += 0x9E3779B97F4A7C15ull;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+
+// Gather-mode flux for gamma = 1.4 with the optional features:
+//   FEAT & 1: statistics of the faces where the two-rarefaction start is
+//             inexact (p_TR > min(p_L, p_R), at least one shock) and face
+//             logging of a hashed sample of them (inputs and ln(p*/p_TR));
+//   FEAT & 2: on those faces the network predicts y ~ ln(p*/p_TR); where
+//             |y| exceeds the gate the Newton solve starts from p_TR exp(y)
+//             (a non-finite or non-positive guess falls back to p_TR).  The
+//             network runs once per wave, on the matrix cores, when any lane
+//             of the wave needs it.
+// The Newton iteration and its stop test are unchanged, so p* is the same
+// root whichever start is used.
+template <int ORDER, typename T, int FEAT>
+__global__ __launch_bounds__(kBlock) void k_flux_feat(FluxArgs<T> a) {
+  __shared__ __attribute__((aligned(16))) uint16_t lds[(FEAT & 2) ? (kBlock / 64) * kMlpFwdLds : 8];
+  const Gas& G = a.s.gas;
+  int idx = xcd_block() * kBlock + threadIdx.x;
+  const bool valid = idx < a.count;
+  SolveInfo info{0, 0, 0, 0, 0, 0, 0};
+  double i0 = 0, i1 = 0, i2 = 0;
+  int4 r = valid ? a.rec[idx] : make_int4(0, 0, -1, 0);
+  T wl[5] = {1, 0, 0, 0, 1}, wr[5] = {1, 0, 0, 0, 1};
+  T am = 1, nx = 1, ny = 0, nz = 0, unl = 0, unr = 0;
+  bool wall = false, transmit = false, vac = false, gate = false;
+  double al = 1, ar = 1, ral = 1, rar = 1, ptr = -1.0, pm = 1.0;
+  K14 KL{}, KR{};
+  float x[kMlpIn] = {0, 0, 0, 0, 0, 0};
+  if (valid) {
+    const int f = r.x;
+    T ax = a.fA[f], ay = a.fA[a.nf + f], az = a.fA[2 * (size_t)a.nf + f];
+    load_side<ORDER, T>(a, r.y, wl);
+    wall = r.z < 0 && a.s.boundary == TAFV_BC_WALL;
+    transmit = r.z < 0 && !wall;
+    if (r.z >= 0) load_side<ORDER, T>(a, r.z, wr);
+    T a2 = ax * ax + ay * ay + az * az;
+    T ia = frsq(a2);
+    am = a2 * ia;
+    nx = ax * ia;
+    ny = ay * ia;
+    nz = az * ia;
+    unl = wl[1] * nx + wl[2] * ny + wl[3] * nz;
+    if (!transmit) {
+      double rl = wl[0], pl = wl[4];
+      double irl = frcp(rl), a2l = G.g * pl * irl;
+      ral = frsq(a2l);
+      al = a2l * ral;
+      KL = make_k14(G, pl, al, irl, ral);
+      if (wall) {
+        unr = -unl;
+        ar = al;
+        rar = ral;
+        KR = KL;
+      } else {
+        unr = wr[1] * nx + wr[2] * ny + wr[3] * nz;
+        double rr = wr[0], pr = wr[4];
+        double irr = frcp(rr), a2r = G.g * pr * irr;
+        rar = frsq(a2r);
+        ar = a2r * rar;
+        KR = make_k14(G, pr, ar, irr, rar);
+      }
+      vac = G.two_gm1 * (al + ar) <= (double)unr - (double)unl;
+      if (!vac) {
+        double num = al + ar - 0.5 * G.gm1 * ((double)unr - (double)unl);
+        double den = al * irt7(KL.p) + ar * irt7(KR.p);
+        double q = num * frcp(den), q2 = q * q, q3 = q2 * q;
+        ptr = q3 * q3 * q;
+        gate = !wall && ptr > fmin(KL.p, KR.p);
+      }
+      if (gate) {
+        double rr = wr[0];
+        double rm = 0.5 * ((double)wl[0] + rr);
+        pm = 0.5 * (KL.p + KR.p);
+        double amean = sqrt(G.g * pm / rm);
+        x[0] = (float)((double)wl[0] / rm);
+        x[1] = (float)((double)unl / amean);
+        x[2] = (float)(KL.p / pm);
+        x[3] = (float)(rr / rm);
+        x[4] = (float)((double)unr / amean);
+        x[5] = (float)(KR.p / pm);
+      }
+    }
+  }
+  float ym = 0.f;
+  if ((FEAT & 2) && __ballot(gate) != 0ull)
+    ym = mlp_wave_forward(*a.mlp, x, lds + (threadIdx.x >> 6) * kMlpFwdLds);
+  if (valid) {
+    T phi[5];
+    if (transmit) {
+      T E = wl[4] * (T)(1.0 / G.gm1) + (T)0.5 * wl[0] * (wl[1] * wl[1] + wl[2] * wl[2] + wl[3] * wl[3]);
+      phi[0] = am * wl[0] * unl;
+      phi[1] = am * (wl[0] * unl * wl[1] + wl[4] * nx);
+      phi[2] = am * (wl[0] * unl * wl[2] + wl[4] * ny);
+      phi[3] = am * (wl[0] * unl * wl[3] + wl[4] * nz);
+      phi[4] = am * unl * (E + wl[4]);
+    } else {
+      double guess = ptr;
+      if ((FEAT & 2) && gate && fabsf(ym) > a.guess_gate) {
+        double gm = ptr * exp((double)ym);
+        if (gm > 0.0 && isfinite(gm)) {
+          guess = gm;
+          info.used = 1;
+        } else {
+          info.rejected = 1;
+        }
+      }
+      Star st = solve_star14(G, unl, unr, al, ar, KL, KR, a.s.newton_tol, a.s.newton_max_iter,
+                             guess);
+      info.iters = st.iters;
+      info.fallback = st.fallback;
+      info.vacuum = st.vacuum;
+      if (gate) {
+        info.gated = 1;
+        info.gated_iters = st.iters;
+        if ((FEAT & 1) && a.log_cap > 0) {
+          unsigned long long h = mix64(a.log_seed ^ mix64(((unsigned long long)r.x << 24) ^ a.subit));
+          if ((double)(h >> 11) * 0x1.0p-53 < a.log_rate) {
+            unsigned long long slot = atomicAdd(a.log_count, 1ull);
+            if (slot < (unsigned long long)a.log_cap) {
+              float* row = a.log_rows + 7 * slot;
+              for (int k = 0; k < kMlpIn; ++k) row[k] = x[k];
+              row[6] = (float)log(st.p / ptr);
+            }
+          }
+        }
+      }
+      if (wall) {
+        T ps = (T)st.p;
+        phi[0] = 0;
+        phi[1] = ps * am * nx;
+        phi[2] = ps * am * ny;
+        phi[3] = ps * am * nz;
+        phi[4] = 0;
+      } else {
+        T rs, us, ps;
+        int side;
+        if (!st.vacuum)
+          side = sample14<T>(G, wl[0], unl, wl[4], (T)al, (T)KL.ip, (T)ral, wr[0], unr, wr[4],
+                             (T)ar, (T)KR.ip, (T)rar, (T)st.p, (T)st.u, rs, us, ps);
+        else
+          side = sample0<true, T>(G, wl[0], unl, wl[4], (T)al, wr[0], unr, wr[4], (T)ar, (T)st.p,
+                                  (T)st.u, st.vacuum, rs, us, ps);
+        const T* ws = side ? wr : wl;
+        T uns = side ? unr : unl;
+        T vx = us * nx + (ws[1] - uns * nx);
+        T vy = us * ny + (ws[2] - uns * ny);
+        T vz = us * nz + (ws[3] - uns * nz);
+        T E = ps * (T)(1.0 / G.gm1) + (T)0.5 * rs * (vx * vx + vy * vy + vz * vz);
+        phi[0] = am * rs * us;
+        phi[1] = am * (rs * us * vx + ps * nx);
+        phi[2] = am * (rs * us * vy + ps * ny);
+        phi[3] = am * (rs * us * vz + ps * nz);
+        phi[4] = am * us * (E + ps);
+      }
+    }
+    double dtf = ldexp(a.s.dt_min, r.w);
+    double* q = a.Q + 5 * (size_t)r.x;
+    for (int k = 0; k < 5; ++k) q[k] = dtf * (double)phi[k];
+    if (wall) {
       i0 = q[1];
       i1 = q[2];
       i2 = q[3];
@@ -836,18 +1017,41 @@ static void flux_launch(hipStream_t s, int order, int scatter, int count, const 
   }
 }
 
-hipError_t launch_flux(hipStream_t s, DevMesh& m, const StepArgs& a, int first, int count) {
+template <typename T>
+static void flux_feat_launch(hipStream_t s, int order, int feat, int count, const FluxArgs<T>& f) {
+  dim3 g(blocks_for(count)), b(kBlock);
+#define TAFV_FEAT(O, F) hipLaunchKernelGGL((k_flux_feat<O, T, F>), g, b, 0, s, f)
+  if (order == 2) {
+    if (feat == 1) TAFV_FEAT(2, 1);
+    else if (feat == 2) TAFV_FEAT(2, 2);
+    else TAFV_FEAT(2, 3);
+  } else {
+    if (feat == 1) TAFV_FEAT(1, 1);
+    else if (feat == 2) TAFV_FEAT(1, 2);
+    else TAFV_FEAT(1, 3);
+  }
+#undef TAFV_FEAT
+}
+
+hipError_t launch_flux(hipStream_t s, DevMesh& m, const StepArgs& a, int first, int count,
+                       const FluxFeatures& ft) {
   if (count <= 0) return hipSuccess;
   const int4* rec = m.frec + first;
   if (a.precision == TAFV_FP32_FLUX) {
     FluxArgs<float> f{rec, count, m.nf, m.nc, m.fA32, m.U, (const float*)m.Wf, m.R, m.Q, m.dcount,
-                      m.dimpulse, a};
-    if (a.gas.is14) flux_launch<float, true>(s, a.order, m.scatter, count, f);
+                      m.dimpulse, a, ft.mlp, ft.log_rows, ft.log_count, ft.log_cap,
+                      ft.log_rate, ft.log_seed, ft.subit, ft.guess_gate};
+    if (ft.feat && a.gas.is14 && m.scatter == TAFV_SCATTER_GATHER)
+      flux_feat_launch<float>(s, a.order, ft.feat, count, f);
+    else if (a.gas.is14) flux_launch<float, true>(s, a.order, m.scatter, count, f);
     else flux_launch<float, false>(s, a.order, m.scatter, count, f);
   } else {
-    FluxArgs<double> f{rec, count, m.nf, m.nc, m.fA, m.U, (const double*)m.Wf, m.R, m.Q, m.dcount,
-                       m.dimpulse, a};
-    if (a.gas.is14) flux_launch<double, true>(s, a.order, m.scatter, count, f);
+    FluxArgs<double> f{rec, count, m.nf, m.nc, m.fA, m.U, (const double*)m.Wf, m.R, m.Q,
+                       m.dcount, m.dimpulse, a, ft.mlp, ft.log_rows, ft.log_count, ft.log_cap,
+                       ft.log_rate, ft.log_seed, ft.subit, ft.guess_gate};
+    if (ft.feat && a.gas.is14 && m.scatter == TAFV_SCATTER_GATHER)
+      flux_feat_launch<double>(s, a.order, ft.feat, count, f);
+    else if (a.gas.is14) flux_launch<double, true>(s, a.order, m.scatter, count, f);
     else flux_launch<double, false>(s, a.order, m.scatter, count, f);
   }
   return hipGetLastError();

@@ -129,4 +129,17 @@ struct tafv_ctx {
   struct PendingEvent { hipEvent_t a, b; int cls; int64_t items; };
   std::vector<PendingEvent> pending;
   std::vector<hipEvent_t> event_pool;
+  // learned guess: FP32 master parameters, Adam moments, device network
+  float *mlp_th = nullptr, *mlp_m = nullptr, *mlp_v = nullptr, *mlp_grad = nullptr;
+  float *mlp_gpart = nullptr, *mlp_lpart = nullptr, *mlp_loss = nullptr;
+  int64_t mlp_gpart_blocks = 0;
+  void* mlp_w = nullptr;  // tafv::MlpDev
+  bool mlp_ready = false;
+  int mlp_step = 0;
+  // face log
+  float* log_rows = nullptr;
+  unsigned long long* log_count = nullptr;
+  int64_t log_cap = 0;
+  double log_rate = 0.0;
+  uint64_t log_seed = 0;
 };

@@ -33,7 +33,8 @@ class tafv_params(C.Structure):
                 ("level_margin", C.c_double), ("max_levels", C.c_int32), ("order", C.c_int32),
                 ("precision", C.c_int32), ("guess", C.c_int32), ("boundary", C.c_int32),
                 ("newton_max_iter", C.c_int32), ("reclassify", C.c_int32),
-                ("scatter", C.c_int32), ("cell_order", C.c_int32)]
+                ("scatter", C.c_int32), ("cell_order", C.c_int32),
+                ("guess_stats", C.c_int32), ("guess_gate", C.c_double)]
 
 
 class tafv_stats(C.Structure):
@@ -42,7 +43,9 @@ class tafv_stats(C.Structure):
                 ("newton_fallbacks", C.c_int64), ("vacuum_faces", C.c_int64),
                 ("cells_per_level", C.c_int64 * 8), ("theta", C.c_int32), ("phase", C.c_int32),
                 ("dt_min", C.c_double), ("t_reached", C.c_double),
-                ("wall_impulse", C.c_double * 3)]
+                ("wall_impulse", C.c_double * 3), ("guess_faces", C.c_int64),
+                ("guess_newton_updates", C.c_int64), ("guess_rejected", C.c_int64),
+                ("guess_used", C.c_int64)]
 
     def as_dict(self):
         d = {k: getattr(self, k) for k, _ in self._fields_}
@@ -58,6 +61,7 @@ def _load():
     P = C.c_void_p
     dp, i64p, i8p, i32p = (C.POINTER(C.c_double), C.POINTER(C.c_int64), C.POINTER(C.c_int8),
                            C.POINTER(C.c_int32))
+    fp = C.POINTER(C.c_float)
     sig = {
         "tafv_params_default": [C.POINTER(tafv_params)],
         "tafv_create": [C.c_int, C.POINTER(tafv_params), P, C.POINTER(P)],
@@ -75,6 +79,13 @@ def _load():
         "tafv_checkpoint_write": [P, C.c_int32, dp, dp, i8p, C.c_int32, C.c_int32, C.c_double,
                                   C.c_double],
         "tafv_profile_enable": [P, C.c_int32],
+        "tafv_mlp_set": [P, fp, C.c_int64],
+        "tafv_mlp_get": [P, fp, C.c_int64],
+        "tafv_mlp_forward": [P, fp, C.c_int64, fp],
+        "tafv_mlp_grad": [P, fp, fp, C.c_int64, fp, fp],
+        "tafv_mlp_train": [P, fp, fp, C.c_int64, C.c_int32, C.c_int32, C.c_float, C.c_uint64, fp],
+        "tafv_facelog_config": [P, C.c_int64, C.c_double, C.c_uint64],
+        "tafv_facelog_read": [P, fp, C.c_int64, i64p],
         "tafv_profile_read": [P, C.c_int32, dp, i64p, i64p, C.POINTER(C.c_char_p), i32p],
     }
     for name, args in sig.items():
@@ -92,7 +103,10 @@ lib = _load()
 EXPORTS = ["tafv_params_default", "tafv_create", "tafv_destroy", "tafv_last_error",
            "tafv_mesh_upload", "tafv_mesh_inspect", "tafv_mesh_params", "tafv_state_init", "tafv_state_reset", "tafv_advance",
            "tafv_mesh_stats", "tafv_state_read", "tafv_checkpoint_read", "tafv_checkpoint_write",
-           "tafv_profile_enable", "tafv_profile_read"]
+           "tafv_profile_enable", "tafv_profile_read", "tafv_mlp_set", "tafv_mlp_get",
+           "tafv_mlp_forward", "tafv_mlp_grad", "tafv_mlp_train", "tafv_facelog_config",
+           "tafv_facelog_read"]
+MLP_PARAMS = 1313
 
 
 def _d(a):
@@ -212,6 +226,57 @@ def tafv_checkpoint_write(ctx, mesh_id, cons, accum, levels, phase, theta, dt_mi
     _check(lib.tafv_checkpoint_write(ctx, mesh_id, _d(cons), _d(accum),
                                      levels.ctypes.data_as(C.POINTER(C.c_int8)), phase, theta,
                                      dt_min, t), ctx)
+
+
+def _f(a):
+    return a.ctypes.data_as(C.POINTER(C.c_float))
+
+
+def tafv_mlp_set(ctx, params):
+    params = np.ascontiguousarray(params, dtype=np.float32)
+    _check(lib.tafv_mlp_set(ctx, _f(params), params.size), ctx)
+
+
+def tafv_mlp_get(ctx):
+    out = np.empty(MLP_PARAMS, np.float32)
+    _check(lib.tafv_mlp_get(ctx, _f(out), out.size), ctx)
+    return out
+
+
+def tafv_mlp_forward(ctx, x):
+    x = np.ascontiguousarray(x, dtype=np.float32)
+    y = np.empty(x.shape[0], np.float32)
+    _check(lib.tafv_mlp_forward(ctx, _f(x), x.shape[0], _f(y)), ctx)
+    return y
+
+
+def tafv_mlp_grad(ctx, x, t):
+    x = np.ascontiguousarray(x, dtype=np.float32)
+    t = np.ascontiguousarray(t, dtype=np.float32)
+    g = np.empty(MLP_PARAMS, np.float32)
+    loss = np.zeros(1, np.float32)
+    _check(lib.tafv_mlp_grad(ctx, _f(x), _f(t), x.shape[0], _f(g), _f(loss)), ctx)
+    return g, float(loss[0])
+
+
+def tafv_mlp_train(ctx, x, t, epochs=20, batch=4096, lr=1e-3, seed=0):
+    x = np.ascontiguousarray(x, dtype=np.float32)
+    t = np.ascontiguousarray(t, dtype=np.float32)
+    loss = np.zeros(max(epochs, 1), np.float32)
+    _check(lib.tafv_mlp_train(ctx, _f(x), _f(t), x.shape[0], epochs, batch, lr, seed, _f(loss)),
+           ctx)
+    return loss[:epochs]
+
+
+def tafv_facelog_config(ctx, capacity, rate, seed=0):
+    _check(lib.tafv_facelog_config(ctx, int(capacity), float(rate), int(seed)), ctx)
+
+
+def tafv_facelog_read(ctx, cap):
+    rows = np.empty((max(cap, 1), 7), np.float32)
+    n = C.c_int64()
+    _check(lib.tafv_facelog_read(ctx, _f(rows), int(cap), C.byref(n)), ctx)
+    return rows[:n.value]
 
 
 def tafv_profile_enable(ctx, on=True):

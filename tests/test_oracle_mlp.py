@@ -57,7 +57,33 @@ def test_features_follow_scaling_symmetry(orc):
         r2 = orc.riemann_solve(sl, sr)
         if r1.vacuum:
             continue
-        assert abs(M.target(r1.p_star, pm1) - M.target(r2.p_star, pm2)) < 1e-11
+        t1 = M.target(r1.p_star, M.two_rarefaction(wl, wr)[0])
+        t2 = M.target(r2.p_star, M.two_rarefaction(sl, sr)[0])
+        assert abs(t1 - t2) < 1e-11
+
+
+def test_two_rarefaction_value(orc):
+    """Exact when both waves are rarefactions (target 0); with a shock it is a
+    positive estimate whose error grows with the shock strength."""
+    rng = np.random.default_rng(9)
+    n_rare = 0
+    for _ in range(2000):
+        wl = np.array([rng.uniform(0.2, 5), rng.uniform(-1, 1), rng.uniform(0.1, 10)])
+        wr = np.array([rng.uniform(0.2, 5), rng.uniform(-1, 1), rng.uniform(0.1, 10)])
+        rs = orc.riemann_solve(wl, wr)
+        if rs.vacuum:
+            continue
+        ptr = M.two_rarefaction(wl, wr)[0]
+        if rs.p_star <= min(wl[2], wr[2]):
+            assert abs(ptr - rs.p_star) < 1e-13 * rs.p_star
+            n_rare += 1
+        else:
+            assert np.isfinite(ptr) and ptr > 0
+    assert n_rare > 100
+    # a strong shock (100:1 at rest) is far from the two-rarefaction value
+    rs = orc.riemann_solve([1.0, 0.0, 100.0], [1.0, 0.0, 1.0])
+    ptr = M.two_rarefaction([1.0, 0.0, 100.0], [1.0, 0.0, 1.0])[0]
+    assert abs(np.log(rs.p_star / ptr)) > 1e-2
 
 
 def test_hand_built_network():
