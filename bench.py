@@ -17,6 +17,8 @@ import os
 import sys
 import time
 
+import numpy as np
+
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
@@ -52,11 +54,16 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def run_form(T, torch, cfg, precision, steps, warmup, scatter):
+def run_form(T, torch, cfg, precision, steps, warmup, scatter, mlp=None):
     stream = torch.cuda.current_stream()
+    extra = {}
+    if mlp is not None:
+        extra = dict(guess=T.GUESS_MLP, guess_stats=1, guess_gate=mlp["gate"])
     s = T.Solver(device=0, hip_stream=stream.cuda_stream, max_levels=cfg["max_levels"],
-                 order=cfg["order"], precision=precision, scatter=scatter)
+                 order=cfg["order"], precision=precision, scatter=scatter, **extra)
     s.upload(cfg["nodes"], cfg["tets"])
+    if mlp is not None:
+        T.tafv_mlp_set(s.ctx, mlp["theta"])
     s.init(cfg["prim"])
     for _ in range(warmup):
         s.reset()
@@ -86,7 +93,61 @@ def run_form(T, torch, cfg, precision, steps, warmup, scatter):
     cons, lev = s.read()
     s.close()
     return dict(ms=ms, wall_s=wall, updates=updates, faces=faces, newton=newton, prof=prof,
-                stats=st1, cons=cons, levels=lev)
+                stats=st1, cons=cons, levels=lev,
+                gated=st1["guess_faces"] - st0["guess_faces"],
+                gated_newton=st1["guess_newton_updates"] - st0["guess_newton_updates"],
+                used=st1["guess_used"] - st0["guess_used"])
+
+
+def train_guess(T, torch, I, n, train_seeds=(1, 2, 3, 4, 5), rows_per_seed=400000):
+    """Learned p* guess: log face states from blasts with the training seeds
+    (FP64 path, full run each), train on the GPU, choose the gate by the
+    GPU's own Newton-update counters on a training seed.  Returns the
+    parameters, the gate and the training figures."""
+    stream = torch.cuda.current_stream()
+    cfg = I.config_scale(n, train_seeds[0])
+    s = T.Solver(device=0, hip_stream=stream.cuda_stream, max_levels=cfg["max_levels"],
+                 order=cfg["order"], guess_stats=1)
+    s.upload(cfg["nodes"], cfg["tets"])
+    rows = []
+    for seed in train_seeds:
+        prim = I.blast_state(cfg["nodes"], cfg["tets"], centre=I.blast_centre(seed))
+        s.init(prim)
+        T.tafv_facelog_config(s.ctx, rows_per_seed, 0.3, seed)
+        T.tafv_advance(s.ctx, UNITS)
+        rows.append(T.tafv_facelog_read(s.ctx, rows_per_seed))
+    rows = np.concatenate(rows)
+    T.tafv_mlp_set(s.ctx, I.mlp_init(0))
+    t0 = time.perf_counter()
+    loss = T.tafv_mlp_train(s.ctx, rows[:, :6], rows[:, 6], epochs=20, batch=4096, lr=2e-3,
+                            seed=11)
+    train_s = time.perf_counter() - t0
+    theta = T.tafv_mlp_get(s.ctx)
+    # gate: mean Newton updates per inexact-TR face on the first training seed
+    prim = I.blast_state(cfg["nodes"], cfg["tets"], centre=I.blast_centre(train_seeds[0]))
+    T.tafv_facelog_config(s.ctx, 0, 0.0, 0)
+    per_gate = {}
+    for gate in (None, 0.0, 0.01, 0.03, 0.1):
+        if gate is None:
+            T.tafv_guess_config(s.ctx, T.GUESS_TR, 0.0, 1)
+        else:
+            T.tafv_guess_config(s.ctx, T.GUESS_MLP, gate, 1)
+        s.init(prim)
+        st = T.tafv_advance(s.ctx, UNITS)
+        per_gate["tr" if gate is None else gate] = st["guess_newton_updates"] / max(st["guess_faces"], 1)
+    s.close()
+    best = min((g for g in per_gate if g != "tr"), key=lambda g: per_gate[g])
+    return dict(theta=theta, gate=best, rows=int(len(rows)), train_s=round(train_s, 3),
+                loss_first=float(loss[0]), loss_last=float(loss[-1]),
+                newton_per_inexact_face={str(k): round(v, 4) for k, v in per_gate.items()})
+
+
+def l1_errors(cfg, ref, got):
+    p = cfg["nodes"][cfg["tets"]]
+    vol = np.einsum("ij,ij->i", p[:, 1] - p[:, 0], np.cross(p[:, 2] - p[:, 0], p[:, 3] - p[:, 0])) / 6.0
+    e = [float((vol * np.abs(got[:, k] - ref[:, k])).sum() / (vol * np.abs(ref[:, k])).sum())
+         for k in (0, 4)]
+    return e
 
 
 def roofline(prof, bytes_per_item):
@@ -125,6 +186,7 @@ def main():
     ap.add_argument("--n", type=int, default=64, help="hexes per axis")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp32", action="store_true")
+    ap.add_argument("--no-learned", action="store_true")
     ap.add_argument("--scatter", type=int, default=1, help="0 colour, 1 gather")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -132,7 +194,6 @@ def main():
               "(the multi-GPU decomposition is a design, not part of this build)", file=sys.stderr)
         sys.exit(2)
 
-    import numpy as np
     import torch
 
     from paper_1704_01144_amd import inputs as I
@@ -175,12 +236,7 @@ def main():
     if not args.no_fp32:
         r32 = run_form(T, torch, cfg, T.FP32_FLUX, args.steps, args.warmup, args.scatter)
         v32 = r32["updates"] / (r32["ms"] * 1e-3)
-        gm = r64["cons"]
-        p = cfg["nodes"][cfg["tets"]]
-        vol = np.einsum("ij,ij->i", p[:, 1] - p[:, 0],
-                        np.cross(p[:, 2] - p[:, 0], p[:, 3] - p[:, 0])) / 6.0
-        e_rho = float((vol * np.abs(r32["cons"][:, 0] - gm[:, 0])).sum() / (vol * np.abs(gm[:, 0])).sum())
-        e_E = float((vol * np.abs(r32["cons"][:, 4] - gm[:, 4])).sum() / (vol * np.abs(gm[:, 4])).sum())
+        e_rho, e_E = l1_errors(cfg, r64["cons"], r32["cons"])
         _, roof32 = roofline(r32["prof"], bpi["fp32"])
         out["forms"] = {"fp32_flux": {
             "value": round(v32, 1), "ms_per_step": round(r32["ms"] / args.steps, 4),
@@ -188,6 +244,23 @@ def main():
             "l1_reference": "FP64 GPU result of the same run (equal to the oracle within 1e-12)",
             "roofline": roof32}}
         log(f"fp32 flux: {v32 / 1e9:.3f} G/s, L1 rho {e_rho:.2e}, L1 E {e_E:.2e}")
+        if not args.no_learned and args.scatter == 1:
+            log("learned guess: logging seeds 1-5, training, gate choice ...")
+            g = train_guess(T, torch, I, args.n)
+            rl = run_form(T, torch, cfg, T.FP32_FLUX, args.steps, args.warmup, args.scatter, mlp=g)
+            vl = rl["updates"] / (rl["ms"] * 1e-3)
+            el = l1_errors(cfg, r64["cons"], rl["cons"])
+            out["forms"]["fp32_learned"] = {
+                "value": round(vl, 1), "ms_per_step": round(rl["ms"] / args.steps, 4),
+                "speedup_vs_fp64": round(vl / value, 3), "l1_rho": el[0], "l1_E": el[1],
+                "gate": g["gate"], "train_rows": g["rows"], "train_seconds": g["train_s"],
+                "train_loss_first_last": [g["loss_first"], g["loss_last"]],
+                "newton_per_inexact_tr_face_by_gate": g["newton_per_inexact_face"],
+                "eval_newton_per_inexact_face": round(rl["gated_newton"] / max(rl["gated"], 1), 4),
+                "eval_faces_started_by_network": rl["used"],
+                "newton_per_face_all": round(rl["newton"] / max(rl["faces"], 1), 4)}
+            log(f"fp32 + learned: {vl / 1e9:.3f} G/s, gate {g['gate']}, "
+                f"per-gate updates {g['newton_per_inexact_face']}")
     if not args.no_cpu_baseline:
         log("cpu baseline: oracle, 1 thread ...")
         out["cpu_baseline"] = cpu_baseline(cfg)

@@ -228,6 +228,10 @@ tafv_status tafv_checkpoint_write(tafv_ctx* ctx, int32_t mesh_id, const double* 
  * context keeps FP32 master parameters and their BF16 device copy. */
 #define TAFV_MLP_PARAMS 1313
 
+/* Change the guess settings of a context (params.guess, guess_gate,
+ * guess_stats) between tafv_advance() calls. */
+tafv_status tafv_guess_config(tafv_ctx* ctx, int32_t guess, double gate, int32_t stats);
+
 /* Set / read the FP32 parameters (n must be TAFV_MLP_PARAMS).  Setting
  * resets the optimiser state. */
 tafv_status tafv_mlp_set(tafv_ctx* ctx, const float* params, int64_t n);

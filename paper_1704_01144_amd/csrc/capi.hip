@@ -696,6 +696,18 @@ tafv_status tafv_checkpoint_write(tafv_ctx* c, int32_t mesh_id, const double* co
   return TAFV_OK;
 }
 
+tafv_status tafv_guess_config(tafv_ctx* c, int32_t guess, double gate, int32_t stats) {
+  if (!c) return TAFV_E_ARG;
+  if (guess != TAFV_GUESS_TR && guess != TAFV_GUESS_MLP) return fail(c, TAFV_E_ARG, "unknown guess");
+  if (!(gate >= 0.0)) return fail(c, TAFV_E_ARG, "negative guess gate");
+  if (guess == TAFV_GUESS_MLP && (c->prm.gamma != 1.4 || c->prm.scatter != TAFV_SCATTER_GATHER))
+    return fail(c, TAFV_E_ARG, "the learned guess needs gamma 1.4 and gather scatter");
+  c->prm.guess = guess;
+  c->prm.guess_gate = gate;
+  c->prm.guess_stats = stats != 0;
+  return TAFV_OK;
+}
+
 static tafv_status ensure_mlp(tafv_ctx* c) {
   if (c->mlp_th) return TAFV_OK;
   hipError_t e = hipSuccess;

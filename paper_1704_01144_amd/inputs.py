@@ -124,6 +124,17 @@ def sod_state(nodes, tets, x0=0.5, left=(1.0, 0.0, 1.0), right=(0.125, 0.0, 0.1)
     return prim
 
 
+def mlp_init(seed, n_in=6, n_h=32):
+    """He-uniform initial parameters of the 6-32-32-1 guess network (biases
+    0) as float32, in the library's order W1, b1, W2, b2, w3, b3."""
+    rng = np.random.default_rng(seed)
+    lim1, lim2 = np.sqrt(6.0 / n_in), np.sqrt(6.0 / n_h)
+    parts = [rng.uniform(-lim1, lim1, (n_h, n_in)).ravel(), np.zeros(n_h),
+             rng.uniform(-lim2, lim2, (n_h, n_h)).ravel(), np.zeros(n_h),
+             rng.uniform(-lim2, lim2, n_h), np.zeros(1)]
+    return np.concatenate(parts).astype(np.float32)
+
+
 # --- the configurations of the benchmark and the parity tests ------------
 
 def config_small():

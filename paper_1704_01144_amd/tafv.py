@@ -79,6 +79,7 @@ def _load():
         "tafv_checkpoint_write": [P, C.c_int32, dp, dp, i8p, C.c_int32, C.c_int32, C.c_double,
                                   C.c_double],
         "tafv_profile_enable": [P, C.c_int32],
+        "tafv_guess_config": [P, C.c_int32, C.c_double, C.c_int32],
         "tafv_mlp_set": [P, fp, C.c_int64],
         "tafv_mlp_get": [P, fp, C.c_int64],
         "tafv_mlp_forward": [P, fp, C.c_int64, fp],
@@ -103,7 +104,7 @@ lib = _load()
 EXPORTS = ["tafv_params_default", "tafv_create", "tafv_destroy", "tafv_last_error",
            "tafv_mesh_upload", "tafv_mesh_inspect", "tafv_mesh_params", "tafv_state_init", "tafv_state_reset", "tafv_advance",
            "tafv_mesh_stats", "tafv_state_read", "tafv_checkpoint_read", "tafv_checkpoint_write",
-           "tafv_profile_enable", "tafv_profile_read", "tafv_mlp_set", "tafv_mlp_get",
+           "tafv_profile_enable", "tafv_profile_read", "tafv_guess_config", "tafv_mlp_set", "tafv_mlp_get",
            "tafv_mlp_forward", "tafv_mlp_grad", "tafv_mlp_train", "tafv_facelog_config",
            "tafv_facelog_read"]
 MLP_PARAMS = 1313
@@ -230,6 +231,10 @@ def tafv_checkpoint_write(ctx, mesh_id, cons, accum, levels, phase, theta, dt_mi
 
 def _f(a):
     return a.ctypes.data_as(C.POINTER(C.c_float))
+
+
+def tafv_guess_config(ctx, guess, gate=0.0, stats=1):
+    _check(lib.tafv_guess_config(ctx, int(guess), float(gate), int(stats)), ctx)
 
 
 def tafv_mlp_set(ctx, params):
