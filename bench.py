@@ -150,16 +150,49 @@ def l1_errors(cfg, ref, got):
     return e
 
 
-def roofline(prof, bytes_per_item):
+def measured_traffic(kernel, dtype):
+    """HBM bytes per launch of `kernel` from the committed counter record
+    (FETCH_SIZE and WRITE_SIZE scaled by a plain copy), or None when there is
+    no record or the library sources changed after it was taken."""
+    from paper_1704_01144_amd import profile_summary as PS
+    path = os.path.join(ROOT, "profiles", f"{kernel}_graded64_blast_{dtype}_counters.txt")
+    if not os.path.exists(path):
+        return None, "no counter record"
+    rec = PS.read_record(path)
+    if rec.get("sources_sha256") != PS.source_digest():
+        return None, "sources changed since the counters were taken"
+    return int(float(rec["traffic_bytes_per_launch"])), os.path.relpath(path, ROOT)
+
+
+def roofline(prof, bytes_per_item, dtype):
     dom = max((k for k in prof if k in bytes_per_item), key=lambda k: prof[k]["ms"])
     p = prof[dom]
     achieved = bytes_per_item[dom] * p["items"] / (p["ms"] * 1e-3) / 1e9
+    name = "k_flux" if dom == "flux" else "k_" + dom
+    traffic, src = measured_traffic(name, dtype)
+    launches = max(p["launches"], 1)
     return dom, {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-                 "kernel": "k_flux" if dom == "flux" else "k_" + dom,
-                 "avg_launch_us": round(1e3 * p["ms"] / max(p["launches"], 1), 2),
+                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+                 "traffic_unit": "HBM bytes per launch", "traffic_source": src,
+                 "kernel": name,
+                 "avg_launch_us": round(1e3 * p["ms"] / launches, 2),
                  "bytes_per_item": bytes_per_item[dom], "items": p["items"],
-                 "launches": p["launches"]}
+                 "launches": p["launches"],
+                 "algorithmic_bytes_per_launch": int(bytes_per_item[dom] * p["items"] / launches)}
+
+
+def copy_probe():
+    """A plain device-to-device copy of 1 GiB, three times: the known-size
+    kernel that the FETCH_SIZE / WRITE_SIZE counters are scaled by."""
+    import torch
+    n = 2 ** 27
+    x = torch.ones(n, dtype=torch.float64, device="cuda")
+    y = torch.empty_like(x)
+    torch.cuda.synchronize()
+    for _ in range(3):
+        y.copy_(x)
+    torch.cuda.synchronize()
+    log(f"copied {n * 8} bytes three times")
 
 
 def cpu_baseline(cfg, units=8):
@@ -188,11 +221,17 @@ def main():
     ap.add_argument("--no-fp32", action="store_true")
     ap.add_argument("--no-learned", action="store_true")
     ap.add_argument("--scatter", type=int, default=1, help="0 colour, 1 gather")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="only run the 1 GiB copy used to scale the traffic counters")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
               "(the multi-GPU decomposition is a design, not part of this build)", file=sys.stderr)
         sys.exit(2)
+
+    if args.copy_probe:
+        copy_probe()
+        return
 
     import torch
 
@@ -207,7 +246,7 @@ def main():
     value = r64["updates"] / (r64["ms"] * 1e-3)
     log(f"fp64: {r64['ms']:.2f} ms for {args.steps} steps, {value / 1e9:.3f} G cell-updates/s")
     bpi = BYTES_PER_ITEM_GATHER if args.scatter == 1 else BYTES_PER_ITEM
-    dom, roof = roofline(r64["prof"], bpi["fp64"])
+    dom, roof = roofline(r64["prof"], bpi["fp64"], "fp64")
     out = {
         "metric": "cell-updates/s, 1.57M-tet graded mesh: FP64 plain vs FP32+learned @ L1 err",
         "value": round(value, 1),
@@ -237,7 +276,7 @@ def main():
         r32 = run_form(T, torch, cfg, T.FP32_FLUX, args.steps, args.warmup, args.scatter)
         v32 = r32["updates"] / (r32["ms"] * 1e-3)
         e_rho, e_E = l1_errors(cfg, r64["cons"], r32["cons"])
-        _, roof32 = roofline(r32["prof"], bpi["fp32"])
+        _, roof32 = roofline(r32["prof"], bpi["fp32"], "fp32")
         out["forms"] = {"fp32_flux": {
             "value": round(v32, 1), "ms_per_step": round(r32["ms"] / args.steps, 4),
             "speedup_vs_fp64": round(v32 / value, 3), "l1_rho": e_rho, "l1_E": e_E,

@@ -1,0 +1,155 @@
+"""Short text summaries of rocprofv3 output (CSV), for the profile records
+kept with the sources.
+
+  python -m paper_1704_01144_amd.profile_summary stats DIR --command CMD
+      per-kernel calls / total / average duration from DIR/*kernel_stats.csv
+
+  python -m paper_1704_01144_amd.profile_summary counters --kernel SUBSTR \
+      --fetch DIR --write DIR --copy-fetch DIR --copy-write DIR \
+      --copy-bytes N --command CMD [--command CMD ...]
+      mean FETCH_SIZE / WRITE_SIZE per dispatch of the kernels whose name
+      contains SUBSTR, each scaled by what the same counter reads for a plain
+      device-to-device copy of N bytes (the largest copy dispatch of the copy
+      run), and the HBM bytes per launch that follow.  The record also holds
+      the SHA-256 of the library sources, so that a reader can tell whether
+      the kernels changed after the counters were taken.
+"""
+import argparse
+import csv
+import glob
+import hashlib
+import os
+import sys
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+
+
+def source_digest():
+    """SHA-256 over the native sources of the library (sorted by name)."""
+    h = hashlib.sha256()
+    for p in sorted(glob.glob(os.path.join(PKG, "csrc", "*"))):
+        if os.path.isfile(p) and p.endswith((".hip", ".h", ".cpp")):
+            h.update(os.path.basename(p).encode())
+            with open(p, "rb") as f:
+                h.update(f.read())
+    return h.hexdigest()
+
+
+def _one(pattern):
+    hits = glob.glob(pattern)
+    if len(hits) != 1:
+        raise SystemExit(f"expected one file for {pattern}, found {hits}")
+    return hits[0]
+
+
+def _short(name, width=90):
+    name = name.replace("tafv::", "")
+    return name if len(name) <= width else name[: width - 3] + "..."
+
+
+def stats_text(d, command, top=14):
+    rows = list(csv.DictReader(open(_one(os.path.join(d, "*kernel_stats.csv")))))
+    rows.sort(key=lambda r: -float(r["TotalDurationNs"]))
+    total = sum(float(r["TotalDurationNs"]) for r in rows)
+    out = [f"command: {command}", "",
+           f"{'calls':>7} {'total ms':>10} {'avg us':>10} {'share':>6}  kernel"]
+    for r in rows[:top]:
+        out.append(f"{int(r['Calls']):7d} {float(r['TotalDurationNs']) / 1e6:10.3f} "
+                   f"{float(r['AverageNs']) / 1e3:10.2f} {float(r['Percentage']):5.1f}%  "
+                   f"{_short(r['Kernel_Name'] if 'Kernel_Name' in r else r['Name'])}")
+    out.append(f"{'':7} {total / 1e6:10.3f} {'':10} {'':6}  all kernels ({len(rows)} names)")
+    return "\n".join(out) + "\n"
+
+
+def _counter_rows(d, counter):
+    rows = list(csv.DictReader(open(_one(os.path.join(d, "*counter_collection.csv")))))
+    return [r for r in rows if r["Counter_Name"] == counter]
+
+
+def _kernel_mean(d, counter, substr):
+    vals = [float(r["Counter_Value"]) for r in _counter_rows(d, counter)
+            if substr in r["Kernel_Name"]]
+    if not vals:
+        raise SystemExit(f"no {counter} dispatches of a kernel containing {substr!r} in {d}")
+    names = {r["Kernel_Name"] for r in _counter_rows(d, counter) if substr in r["Kernel_Name"]}
+    return sum(vals) / len(vals), len(vals), names
+
+
+def _copy_kib(d, counter):
+    rows = [r for r in _counter_rows(d, counter) if "copyBuffer" in r["Kernel_Name"]]
+    if not rows:
+        raise SystemExit(f"no copy dispatch in {d}")
+    return max(float(r["Counter_Value"]) for r in rows)
+
+
+def counters_text(a):
+    f_kib, n_f, names = _kernel_mean(a.fetch, "FETCH_SIZE", a.kernel)
+    w_kib, n_w, _ = _kernel_mean(a.write, "WRITE_SIZE", a.kernel)
+    cf = _copy_kib(a.copy_fetch, "FETCH_SIZE")
+    cw = _copy_kib(a.copy_write, "WRITE_SIZE")
+    sf = a.copy_bytes / (cf * 1024.0)
+    sw = a.copy_bytes / (cw * 1024.0)
+    fetch_b = f_kib * 1024.0 * sf
+    write_b = w_kib * 1024.0 * sw
+    lines = [f"kernel: {a.kernel}"]
+    lines += [f"kernel_name: {n}" for n in sorted(names)]
+    lines += [f"command: {c}" for c in a.command]
+    lines += [
+        f"sources_sha256: {source_digest()}",
+        f"dispatches_fetch: {n_f}",
+        f"dispatches_write: {n_w}",
+        f"fetch_kib_per_dispatch: {f_kib:.1f}",
+        f"write_kib_per_dispatch: {w_kib:.1f}",
+        f"copy_bytes: {a.copy_bytes}",
+        f"copy_fetch_kib: {cf:.1f}",
+        f"copy_write_kib: {cw:.1f}",
+        f"fetch_scale: {sf:.4f}",
+        f"write_scale: {sw:.4f}",
+        f"traffic_fetch_bytes_per_launch: {fetch_b:.0f}",
+        f"traffic_write_bytes_per_launch: {write_b:.0f}",
+        f"traffic_bytes_per_launch: {fetch_b + write_b:.0f}",
+    ]
+    return "\n".join(lines) + "\n"
+
+
+def read_record(path):
+    """key: value lines of a counter record -> dict (repeated keys -> list)."""
+    out = {}
+    with open(path) as f:
+        for line in f:
+            if ":" not in line:
+                continue
+            k, v = line.split(":", 1)
+            k, v = k.strip(), v.strip()
+            if k in out:
+                out[k] = out[k] if isinstance(out[k], list) else [out[k]]
+                out[k].append(v)
+            else:
+                out[k] = v
+    return out
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser()
+    sub = ap.add_subparsers(dest="what", required=True)
+    s = sub.add_parser("stats")
+    s.add_argument("dir")
+    s.add_argument("--command", required=True)
+    s.add_argument("--top", type=int, default=14)
+    c = sub.add_parser("counters")
+    c.add_argument("--kernel", required=True)
+    c.add_argument("--fetch", required=True)
+    c.add_argument("--write", required=True)
+    c.add_argument("--copy-fetch", required=True)
+    c.add_argument("--copy-write", required=True)
+    c.add_argument("--copy-bytes", type=int, required=True)
+    c.add_argument("--command", action="append", required=True)
+    a = ap.parse_args(argv)
+    if a.what == "stats":
+        sys.stdout.write(stats_text(a.dir, a.command, a.top))
+    else:
+        sys.stdout.write(counters_text(a))
+
+
+if __name__ == "__main__":
+    main()
