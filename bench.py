@@ -142,6 +142,63 @@ def train_guess(T, torch, I, n, train_seeds=(1, 2, 3, 4, 5), rows_per_seed=40000
                 newton_per_inexact_face={str(k): round(v, 4) for k, v in per_gate.items()})
 
 
+BATCH_UNITS = 16
+
+
+def run_batch(T, torch, cases, steps, warmup, precision, mlp=None, graph=1):
+    """The batched form: every mesh of `cases` in one context (params.batch),
+    HIP graphs and the autotuner on; each step restores all initial states
+    on the device and advances 16 dt_min units."""
+    stream = torch.cuda.current_stream()
+    extra = {}
+    if mlp is not None:
+        extra = dict(guess=T.GUESS_MLP, guess_stats=1, guess_gate=mlp["gate"])
+    t0 = time.perf_counter()
+    s = T.Solver(device=0, hip_stream=stream.cuda_stream, batch=1, order=2,
+                 precision=precision, **extra)
+    for c in cases:
+        s.upload(c["nodes"], c["tets"], max_levels=c["max_levels"])
+    T.tafv_batch_config(s.ctx, graph, 1, None)
+    if mlp is not None:
+        T.tafv_mlp_set(s.ctx, mlp["theta"])
+    for k, c in enumerate(cases):
+        s.init(c["prim"], mesh_id=k)
+    setup_s = time.perf_counter() - t0
+    for _ in range(warmup):
+        T.tafv_state_reset(s.ctx, -1)
+        T.tafv_advance(s.ctx, BATCH_UNITS)
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    tot = dict(cell_updates=0, face_solves=0, newton_updates=0, guess_faces=0,
+               guess_newton_updates=0, guess_used=0)
+    torch.cuda.synchronize()
+    ev0.record(stream)
+    for _ in range(steps):
+        T.tafv_state_reset(s.ctx, -1)
+        st = T.tafv_advance(s.ctx, BATCH_UNITS)
+        for k in tot:
+            tot[k] += st[k]
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    ms = ev0.elapsed_time(ev1)
+    info = T.tafv_batch_info(s.ctx)
+    cons = [s.read(k)[0] for k in range(len(cases))]
+    s.close()
+    return dict(ms=ms, setup_s=setup_s, info=info, cons=cons, **tot)
+
+
+def batch_l1(cases, ref, got):
+    worst = 0.0
+    for c, a, b in zip(cases, got, ref):
+        p = c["nodes"][c["tets"]]
+        vol = np.einsum("ij,ij->i", p[:, 1] - p[:, 0],
+                        np.cross(p[:, 2] - p[:, 0], p[:, 3] - p[:, 0])) / 6.0
+        for k in (0, 4):
+            worst = max(worst, float((vol * np.abs(a[:, k] - b[:, k])).sum()
+                                     / (vol * np.abs(b[:, k])).sum()))
+    return worst
+
+
 def l1_errors(cfg, ref, got):
     p = cfg["nodes"][cfg["tets"]]
     vol = np.einsum("ij,ij->i", p[:, 1] - p[:, 0], np.cross(p[:, 2] - p[:, 0], p[:, 3] - p[:, 0])) / 6.0
@@ -221,6 +278,7 @@ def main():
     ap.add_argument("--no-fp32", action="store_true")
     ap.add_argument("--no-learned", action="store_true")
     ap.add_argument("--scatter", type=int, default=1, help="0 colour, 1 gather")
+    ap.add_argument("--no-batch", action="store_true", help="skip the 128-mesh batched form")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run the 1 GiB copy used to scale the traffic counters")
     args = ap.parse_args()
@@ -300,6 +358,30 @@ def main():
                 "newton_per_face_all": round(rl["newton"] / max(rl["faces"], 1), 4)}
             log(f"fp32 + learned: {vl / 1e9:.3f} G/s, gate {g['gate']}, "
                 f"per-gate updates {g['newton_per_inexact_face']}")
+    if not args.no_batch and not args.no_fp32 and not args.no_learned and args.scatter == 1:
+        cases = I.config_batch(128)
+        ncell = sum(len(c["tets"]) for c in cases)
+        log(f"batched form: {len(cases)} meshes, {ncell} cells, {BATCH_UNITS} units ...")
+        b64 = run_batch(T, torch, cases, args.steps, args.warmup, T.FP64)
+        bl = run_batch(T, torch, cases, args.steps, args.warmup, T.FP32_FLUX, mlp=g)
+        v64 = b64["cell_updates"] / (b64["ms"] * 1e-3)
+        vl = bl["cell_updates"] / (bl["ms"] * 1e-3)
+        out["forms"]["batched"] = {
+            "workload": f"{len(cases)} graded tet meshes (5k-400k cells log-uniform, grading "
+                        f"2-32, level cap 1-6, blast per mesh from seeds 1000-1127), "
+                        f"{ncell} cells, {BATCH_UNITS} dt_min units per step",
+            "cells": ncell,
+            "fp32_learned": {"value": round(vl, 1), "ms_per_step": round(bl["ms"] / args.steps, 4),
+                             "cell_updates_per_step": bl["cell_updates"] // args.steps,
+                             "face_solves_per_step": bl["face_solves"] // args.steps,
+                             "faces_started_by_network": bl["guess_used"] // args.steps,
+                             "l1_max_over_meshes_rho_E": batch_l1(cases, b64["cons"], bl["cons"]),
+                             "launch": bl["info"], "setup_s": round(bl["setup_s"], 1)},
+            "fp64": {"value": round(v64, 1), "ms_per_step": round(b64["ms"] / args.steps, 4),
+                     "cell_updates_per_step": b64["cell_updates"] // args.steps,
+                     "launch": b64["info"], "setup_s": round(b64["setup_s"], 1)},
+        }
+        log(f"batched: fp64 {v64 / 1e9:.3f} G/s, fp32 + learned {vl / 1e9:.3f} G/s")
     if not args.no_cpu_baseline:
         log("cpu baseline: oracle, 1 thread ...")
         out["cpu_baseline"] = cpu_baseline(cfg)

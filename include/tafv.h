@@ -83,7 +83,7 @@ enum { TAFV_ORDER_CALLER = 0, TAFV_ORDER_MORTON = 1 };
  * newton_tol 1e-12, level_margin 1e-9, max_levels 5, order 2, precision
  * TAFV_FP64, guess TAFV_GUESS_TR, boundary TAFV_BC_WALL, newton_max_iter
  * 50, reclassify 1, scatter TAFV_SCATTER_GATHER, cell_order TAFV_ORDER_CALLER,
- * guess_stats 0, guess_gate 0. */
+ * guess_stats 0, guess_gate 0, batch 0. */
 typedef struct {
   double gamma;          /* ratio of specific heats, > 1                        */
   double cfl;            /* dt_i = cfl V_i / sum_f (|u_i . n_f| + a_i) |A_f|    */
@@ -110,6 +110,18 @@ typedef struct {
                             is inexact (at least one shock) and their Newton
                             updates, also with TAFV_GUESS_TR                    */
   double guess_gate;     /* |y| threshold of the learned correction (>= 0)      */
+  int32_t batch;         /* 0: tafv_advance() runs the meshes of the context one
+                            after another, the host reading each mesh's level
+                            counts once per iteration.  1: batched form (gather
+                            scatter only): all meshes are merged into one set of
+                            device arrays at the first tafv_state_init(), each
+                            keeps its own levels, dt_min, phase and level cap
+                            in a device-side schedule, and every subiteration
+                            is one fixed sequence of persistent kernels over
+                            all meshes, with no host synchronisation (see
+                            tafv_batch_config()).  Meshes must all be uploaded
+                            before the first tafv_state_init(); checkpoints
+                            and face logging are not available.              */
 } tafv_params;
 
 /* Counters (int64) and schedule state.  Summed over meshes where a call
@@ -184,7 +196,8 @@ tafv_status tafv_state_init(tafv_ctx* ctx, int32_t mesh_id, const double* prim);
 
 /* Restore the state given to the last tafv_state_init() of the mesh from a
  * device-side copy (no host transfer) and reset its schedule (phase 0,
- * t = 0).  Cumulative counters are kept.  TAFV_E_ORDER without a state. */
+ * t = 0).  Cumulative counters are kept.  mesh_id -1: every mesh of the
+ * context.  TAFV_E_ORDER without a state. */
 tafv_status tafv_state_reset(tafv_ctx* ctx, int32_t mesh_id);
 
 /* Run n_dt_min subiterations (Alg. 2) on every mesh of the context.  The
@@ -195,7 +208,10 @@ tafv_status tafv_state_reset(tafv_ctx* ctx, int32_t mesh_id);
  * non-finite (the call stops at that iteration boundary). */
 tafv_status tafv_advance(tafv_ctx* ctx, int64_t n_dt_min, tafv_stats* out);
 
-/* Cumulative counters and schedule state of one mesh since state_init. */
+/* Cumulative counters and schedule state of one mesh since state_init.  In
+ * the batched form the face-solve counters (Newton updates, fallbacks,
+ * vacuum faces, guess counters, wall impulse) are kept for the whole batch
+ * and returned by tafv_advance() only; here they are 0. */
 tafv_status tafv_mesh_stats(tafv_ctx* ctx, int32_t mesh_id, tafv_stats* out);
 
 /* Copy the conserved state to host cons [n_tets][5] = (rho, rho u, rho v,
@@ -262,6 +278,37 @@ tafv_status tafv_mlp_train(tafv_ctx* ctx, const float* x, const float* t, int64_
  * capacity 0 turns logging off.  Reading returns min(rows logged, cap). */
 tafv_status tafv_facelog_config(tafv_ctx* ctx, int64_t capacity, double rate, uint64_t seed);
 tafv_status tafv_facelog_read(tafv_ctx* ctx, float* rows, int64_t cap, int64_t* n_rows);
+
+/* ---- batched form (params.batch = 1) ---------------------------------
+ * Many independent meshes with staggered level schedules advance together:
+ * per subiteration, meshes at an iteration start reclassify (time step,
+ * levels, sweeps, level-sorted lists; Sec. 2.2, Alg. 2) while the others
+ * skip that work, a one-block kernel derives each mesh's subiteration level
+ * and active counts, and the gradient, flux and cell kernels walk the
+ * active prefixes of all meshes as one list of tiles.  Results equal those
+ * of advancing each mesh on its own (the same per-item arithmetic).
+ *
+ * tafv_batch_config: graph = 1 captures the subiteration sequence of a
+ * tafv_advance(n) call as HIP graphs (up to 32 subiterations each, cached
+ * per length) and replays them on the context stream; graph = 0 launches
+ * the kernels directly (per-kernel timing works only then).
+ * autotune = 1 times candidate launch widths (persistent blocks per CU and
+ * tiles taken per grab) of the gradient and cell kernels on the first
+ * subiteration of the first advance (the cell kernel on scratch copies of
+ * the state) and keeps the fastest; the flux kernel takes one tile per
+ * block over the static count of face tiles; tune_cache (NULL: none) names a
+ * text file that stores the choice per (GPU architecture, precision, order,
+ * guess, log2 of the total cell count) and is read before timing.
+ * autotune = 0 uses 4 blocks per CU and one tile per grab.  Defaults:
+ * graph 1, autotune 1, no cache.  Changing the settings drops the captured
+ * graphs.  TAFV_E_ARG on a context without params.batch. */
+tafv_status tafv_batch_config(tafv_ctx* ctx, int32_t graph, int32_t autotune,
+                              const char* tune_cache);
+
+/* Launch settings in use (n >= 7): info[0..5] = blocks and tiles per grab
+ * of the gradient, flux and cell kernels; info[6] = 0 defaults, 1 timed
+ * by the autotuner, 2 read from the cache file. */
+tafv_status tafv_batch_info(tafv_ctx* ctx, int32_t* info, int32_t n);
 
 /* Per-kernel timing: when enabled, tafv_advance() brackets every launch of
  * each kernel class with HIP events on the context stream.

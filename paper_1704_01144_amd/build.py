@@ -9,7 +9,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libtafv.so")
-SOURCES = ["mesh_prep.cpp", "kernels.hip", "mlp.hip", "capi.hip"]
+SOURCES = ["mesh_prep.cpp", "kernels.hip", "mlp.hip", "batch.hip", "capi.hip"]
 ARCH = os.environ.get("TAFV_OFFLOAD_ARCH", "gfx950")
 
 HIPCC_FLAGS = [

@@ -1,0 +1,1249 @@
+// Batched form: many independent tetrahedral meshes, each with its own
+// temporal levels and schedule (Sec. 2.2, Alg. 2), advanced together.
+//
+// The meshes are merged into one set of device arrays (cell, face and
+// half-face ids offset per mesh, every face and cell of a mesh in one
+// contiguous segment).  Each mesh's schedule (level cap, theta, phase,
+// dt_min, list starts, active counts) lives in a device table, so a
+// subiteration is a fixed sequence of launches that a HIP graph can hold:
+//   k_b_begin       meshes at an iteration start are marked to reclassify;
+//   k_b_dt ... keys time step, per-mesh dt_min, levels, neighbour sweeps,
+//                   keys and per-mesh stable partitions by level (only the
+//                   marked meshes do work);
+//   k_b_sched       one block: theta, the subiteration level tau_s, the
+//                   levels whose steps end, active counts and the tile
+//                   prefix of each work class over all meshes;
+//   k_b_grad / k_b_flux* / k_b_gather
+//                   persistent kernels over the active prefixes of all
+//                   meshes, taken as one list of 256-item tiles.
+// The per-item arithmetic is the single-mesh path's (kernels_dev.h), so a
+// mesh advanced in a batch gets the same bits as on its own.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <fstream>
+#include <new>
+#include <sstream>
+#include <string>
+#include <vector>
+
+#include "kernels.h"
+#include "kernels_dev.h"
+#include "mlp.h"
+#include "tafv_internal.h"
+
+namespace tafv {
+namespace {
+
+constexpr int kChunk = 1024;        // partition chunk: 16 waves of 64
+constexpr int kStaticBlocksPerCU = 4;
+constexpr int kGraphSpan = 32;      // subiterations per captured graph
+
+// the mesh whose tiles hold tile t: tp[m] <= t < tp[m + 1] (tp[M] > t)
+__device__ inline int find_mesh(const int32_t* __restrict__ tp, int M, int t) {
+  int lo = 0, hi = M;
+  while (hi - lo > 1) {
+    int mid = (lo + hi) >> 1;
+    if (tp[mid] <= t) lo = mid;
+    else hi = mid;
+  }
+  return lo;
+}
+
+// Tiles of a launch: block b (XCD-remapped rank r) takes tiles
+// [(k G + r) grab, (k G + r + 1) grab) for k = 0, 1, ...  Block-uniform.
+#define TILE_LOOP(total, grab)                                                       \
+  for (int base_ = xcd_block() * (grab); base_ < (total); base_ += gridDim.x * (grab)) \
+    for (int t = base_, tend_ = min(base_ + (grab), (total)); t < tend_; ++t)
+
+// ---- iteration start ----------------------------------------------------
+
+__global__ void k_b_begin(BatchSched* S, int M, int reclassify) {
+  for (int m = threadIdx.x; m < M; m += blockDim.x) {
+    BatchSched& s = S[m];
+    int rc = s.phase == 0 && (reclassify || !s.classified);
+    s.reclass = rc;
+    if (rc) {
+      s.dtbits = 0x7ff0000000000000ull;  // +inf
+      for (int k = 0; k < kMaxKeys; ++k) s.hist[k] = 0;
+    }
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_b_dt(const int32_t* __restrict__ ct, BatchSched* S,
+                                                 int M, int NC, int NF,
+                                                 const double* __restrict__ U,
+                                                 const double* __restrict__ vol,
+                                                 const int* __restrict__ c2f,
+                                                 const double* __restrict__ fA, double gamma,
+                                                 double cfl, double* __restrict__ dt,
+                                                 unsigned long long* flag) {
+  __shared__ double smin[kBlock / 64];
+  const int total = ct[M];
+  TILE_LOOP(total, 1) {
+    int m = find_mesh(ct, M, t);
+    if (!S[m].reclass) continue;
+    int i = S[m].c0 + (t - ct[m]) * kBlock + threadIdx.x;
+    double dti = INFINITY;
+    if (i < S[m].c0 + S[m].nc) {
+      bool bad = false;
+      dti = dt_item(i, NC, NF, U, vol, c2f, fA, gamma, cfl, bad);
+      if (bad) atomicOr(flag, 1ull);
+      dt[i] = dti;
+    }
+    double v = wave_min(dti);
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) smin[threadIdx.x >> 6] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      for (int k = 1; k < kBlock / 64; ++k) v = fmin(v, smin[k]);
+      if (v < INFINITY) atomicMin(&S[m].dtbits, (unsigned long long)__double_as_longlong(v));
+    }
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_b_classify(const int32_t* __restrict__ ct,
+                                                       const BatchSched* S, int M,
+                                                       const double* __restrict__ dt,
+                                                       double margin, int8_t* __restrict__ lev) {
+  const int total = ct[M];
+  TILE_LOOP(total, 1) {
+    int m = find_mesh(ct, M, t);
+    if (!S[m].reclass) continue;
+    int i = S[m].c0 + (t - ct[m]) * kBlock + threadIdx.x;
+    if (i < S[m].c0 + S[m].nc)
+      lev[i] = classify_item(dt[i], __longlong_as_double((long long)S[m].dtbits), margin, S[m].L);
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_b_sweep(const int32_t* __restrict__ ct,
+                                                    const BatchSched* S, int M, int NC,
+                                                    const int* __restrict__ nb,
+                                                    const int8_t* __restrict__ src,
+                                                    int8_t* __restrict__ dst) {
+  const int total = ct[M];
+  TILE_LOOP(total, 1) {
+    int m = find_mesh(ct, M, t);
+    if (!S[m].reclass) continue;
+    int i = S[m].c0 + (t - ct[m]) * kBlock + threadIdx.x;
+    if (i < S[m].c0 + S[m].nc) dst[i] = sweep_item(i, NC, nb, src);
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_b_cell_keys(const int32_t* __restrict__ ct,
+                                                        BatchSched* S, int M, int NC,
+                                                        const int* __restrict__ nb,
+                                                        const int8_t* __restrict__ lev,
+                                                        int8_t* __restrict__ ckey,
+                                                        uint32_t* __restrict__ fpack) {
+  __shared__ int h[kMaxKeys];
+  const int total = ct[M];
+  TILE_LOOP(total, 1) {
+    int m = find_mesh(ct, M, t);
+    if (!S[m].reclass) continue;
+    __syncthreads();
+    for (int k = threadIdx.x; k < kMaxKeys; k += blockDim.x) h[k] = 0;
+    __syncthreads();
+    int i = S[m].c0 + (t - ct[m]) * kBlock + threadIdx.x;
+    if (i < S[m].c0 + S[m].nc) atomicAdd(&h[cell_key_item(i, NC, nb, lev, ckey, fpack)], 1);
+    __syncthreads();
+    for (int k = threadIdx.x; k < kMaxKeys; k += blockDim.x)
+      if (h[k]) atomicAdd(&S[m].hist[k], h[k]);
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_b_face_keys(const int32_t* __restrict__ ft,
+                                                        const BatchSched* S, int M,
+                                                        const int* __restrict__ fhL,
+                                                        const int* __restrict__ fhR,
+                                                        const int8_t* __restrict__ lev,
+                                                        int8_t* __restrict__ fkey) {
+  const int total = ft[M];
+  TILE_LOOP(total, 1) {
+    int m = find_mesh(ft, M, t);
+    if (!S[m].reclass) continue;
+    int f = S[m].f0 + (t - ft[m]) * kBlock + threadIdx.x;
+    if (f < S[m].f0 + S[m].nf) fkey[f] = face_key_item(f, fhL, fhR, nullptr, lev, 0);
+  }
+}
+
+// ---- per-mesh stable partitions by level ----------------------------------
+// Chunk j of mesh m covers segment items [j kChunk, (j + 1) kChunk); the
+// count of key k in that chunk sits at 8 cp[m] + k nch + j (nch chunks in
+// the mesh), so one exclusive scan per mesh, started at the segment's first
+// position, gives every (key, chunk) its first slot in the merged list.
+
+template <typename Key>
+__global__ __launch_bounds__(64) void k_b_part_count(const int32_t* __restrict__ cp,
+                                                     const BatchSched* S, int M, int faces,
+                                                     Key key, int32_t* __restrict__ counts) {
+  __shared__ int cnt[kMaxLevels];
+  const int lane = threadIdx.x;
+  const int total = cp[M];
+  for (int t = xcd_block(); t < total; t += gridDim.x) {
+    int m = find_mesh(cp, M, t);
+    if (!S[m].reclass) continue;
+    int j = t - cp[m], nch = cp[m + 1] - cp[m];
+    int b0 = faces ? S[m].f0 : S[m].c0;
+    int end = b0 + (faces ? S[m].nf : S[m].nc);
+    __syncthreads();
+    if (lane < kMaxLevels) cnt[lane] = 0;
+    __syncthreads();
+    int first = b0 + j * kChunk;
+    for (int step = 0; step < kChunk / 64; ++step) {
+      int i = first + step * 64 + lane;
+      bool valid = i < end;
+      int k_mine = valid ? key(i) : -1;
+      unsigned long long pending = __ballot(valid);
+      while (pending) {
+        int leader = __ffsll(pending) - 1;
+        int k = __shfl(k_mine, leader, 64);
+        unsigned long long msk = __ballot(k_mine == k);
+        if (lane == leader) cnt[k] += __popcll(msk);
+        pending &= ~msk;
+      }
+    }
+    __syncthreads();
+    if (lane < kMaxLevels) counts[kMaxLevels * cp[m] + lane * nch + j] = cnt[lane];
+  }
+}
+
+// one block per mesh: exclusive scan of its counts in place, plus the
+// list starts per level
+__global__ __launch_bounds__(256) void k_b_part_scan(const int32_t* __restrict__ cp,
+                                                     BatchSched* S, int M, int faces,
+                                                     int32_t* __restrict__ counts) {
+  __shared__ int sh[256];
+  const int m = blockIdx.x;
+  if (m >= M || !S[m].reclass) return;
+  const int tid = threadIdx.x;
+  const int nch = cp[m + 1] - cp[m];
+  const int n = kMaxLevels * nch;
+  int32_t* c = counts + kMaxLevels * cp[m];
+  const int b0 = faces ? S[m].f0 : S[m].c0;
+  const int cnt_all = faces ? S[m].nf : S[m].nc;
+  int carry = b0;
+  for (int b = 0; b < n; b += 256) {
+    int x = b + tid < n ? c[b + tid] : 0;
+    sh[tid] = x;
+    __syncthreads();
+    for (int off = 1; off < 256; off <<= 1) {
+      int y = tid >= off ? sh[tid - off] : 0;
+      __syncthreads();
+      sh[tid] += y;
+      __syncthreads();
+    }
+    if (b + tid < n) c[b + tid] = carry + sh[tid] - x;
+    int tot = sh[255];
+    __syncthreads();
+    carry += tot;
+  }
+  int32_t* start = faces ? S[m].fstart : S[m].cstart;
+  if (tid < kMaxLevels) start[tid] = c[tid * nch];
+  if (tid == 0) start[kMaxLevels] = b0 + cnt_all;
+}
+
+template <typename Key, typename Writer>
+__global__ __launch_bounds__(64) void k_b_part_scatter(const int32_t* __restrict__ cp,
+                                                       const BatchSched* S, int M, int faces,
+                                                       Key key,
+                                                       const int32_t* __restrict__ offs,
+                                                       Writer out) {
+  __shared__ int base[kMaxLevels];
+  const int lane = threadIdx.x;
+  const unsigned long long lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+  const int total = cp[M];
+  for (int t = xcd_block(); t < total; t += gridDim.x) {
+    int m = find_mesh(cp, M, t);
+    if (!S[m].reclass) continue;
+    int j = t - cp[m], nch = cp[m + 1] - cp[m];
+    int b0 = faces ? S[m].f0 : S[m].c0;
+    int end = b0 + (faces ? S[m].nf : S[m].nc);
+    __syncthreads();
+    if (lane < kMaxLevels) base[lane] = offs[kMaxLevels * cp[m] + lane * nch + j];
+    __syncthreads();
+    int first = b0 + j * kChunk;
+    for (int step = 0; step < kChunk / 64; ++step) {
+      int i = first + step * 64 + lane;
+      bool valid = i < end;
+      int k_mine = valid ? key(i) : -1;
+      unsigned long long pending = __ballot(valid);
+      while (pending) {
+        int leader = __ffsll(pending) - 1;
+        int k = __shfl(k_mine, leader, 64);
+        unsigned long long msk = __ballot(k_mine == k);
+        int p0 = base[k];
+        if (k_mine == k) out(p0 + __popcll(msk & lt), i, k);
+        __syncthreads();
+        if (lane == leader) base[k] = p0 + __popcll(msk);
+        __syncthreads();
+        pending &= ~msk;
+      }
+    }
+  }
+}
+
+// ---- per-subiteration schedule ------------------------------------------
+// Per mesh (Alg. 2): after a reclassification, dt_min and theta; the
+// subiteration's level tau_s (theta at phase 0, else the largest tau <=
+// theta with 2^tau dividing the phase); cells with tau <= upd = min(theta,
+// ctz(phase + 1)) end their step.  Active counts are prefixes of the
+// level-sorted lists.  Then the tile prefixes of the three work classes.
+__global__ __launch_bounds__(1024) void k_b_sched(BatchSched* S, int M, int order,
+                                                  unsigned long long* flag,
+                                                  int32_t* __restrict__ tp) {
+  __shared__ int sh[3][1024];
+  const int tid = threadIdx.x;
+  const bool err_in = *flag != 0ull;
+  int carry[3] = {0, 0, 0};
+  for (int b = 0; b < M; b += blockDim.x) {
+    int m = b + tid;
+    int tiles[3] = {0, 0, 0};
+    if (m < M) {
+      BatchSched& s = S[m];
+      bool err = err_in;
+      if (s.reclass) {
+        double dtm = __longlong_as_double((long long)s.dtbits);
+        if (!(dtm > 0.0) || !isfinite(dtm)) {
+          err = true;
+          atomicOr(flag, 1ull);
+        }
+        s.dt_min = dtm;
+        s.classified = 1;
+        int theta = 0;
+        for (int u = 0; u < kMaxLevels; ++u) {
+          int64_t n = 0;
+          for (int g = 0; g < kMaxLevels; ++g) n += s.hist[g * kMaxLevels + u];
+          s.cells_per_level[u] = n;
+          if (n > 0) theta = u;
+        }
+        s.theta = theta;
+      }
+      if (err) {
+        s.n_grad = s.n_flux = s.n_gather = 0;
+      } else {
+        const int ph = s.phase, th = s.theta, s1 = ph + 1;
+        const int ts = ph == 0 ? th : min(th, __ffs(ph) - 1);
+        const int up = min(th, __ffs(s1) - 1);
+        s.tau_s = ts;
+        s.upd = up;
+        s.n_flux = s.fstart[ts + 1] - s.fstart[0];
+        s.n_grad = order == 2 ? s.cstart[ts + 1] - s.cstart[0] : 0;
+        s.n_gather = s.cstart[max(ts, up) + 1] - s.cstart[0];
+        int64_t u = 0;
+        for (int k = 0; k <= up; ++k) u += s.cells_per_level[k];
+        s.cell_updates += u;
+        s.face_solves += s.n_flux;
+        s.subiterations += 1;
+        s.phase = s1 & ((1 << th) - 1);
+        s.t += s.dt_min;
+        tiles[0] = (s.n_grad + kBlock - 1) / kBlock;
+        tiles[1] = (s.n_flux + kBlock - 1) / kBlock;
+        tiles[2] = (s.n_gather + kBlock - 1) / kBlock;
+      }
+    }
+    for (int w = 0; w < 3; ++w) sh[w][tid] = tiles[w];
+    __syncthreads();
+    for (int off = 1; off < 1024; off <<= 1) {
+      int y[3];
+      for (int w = 0; w < 3; ++w) y[w] = tid >= off ? sh[w][tid - off] : 0;
+      __syncthreads();
+      for (int w = 0; w < 3; ++w) sh[w][tid] += y[w];
+      __syncthreads();
+    }
+    for (int w = 0; w < 3; ++w) {
+      if (m < M) tp[w * (M + 1) + m] = carry[w] + sh[w][tid] - tiles[w];
+      carry[w] += sh[w][1023];
+    }
+    __syncthreads();
+  }
+  if (tid < 3) tp[tid * (M + 1) + M] = carry[tid];
+}
+
+// ---- work kernels -----------------------------------------------------------
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_b_grad(const int32_t* __restrict__ tp,
+                                                   const BatchSched* S, int M, int grab,
+                                                   GradArgs<T> a) {
+  const int total = tp[M];
+  TILE_LOOP(total, grab) {
+    int m = find_mesh(tp, M, t);
+    int j = (t - tp[m]) * kBlock + threadIdx.x;
+    if (j < S[m].n_grad) grad_item<T>(a, a.list[S[m].c0 + j]);
+  }
+}
+
+// The flux kernels take one tile per block (grid = the static bound of
+// face tiles; blocks past the active total leave at once): a persistent
+// loop around the face solve raised its register count by a quarter and
+// cost a wave of occupancy.
+template <int ORDER, typename T, bool G14>
+__global__ __launch_bounds__(kBlock) void k_b_flux(const int32_t* __restrict__ tp,
+                                                   const BatchSched* S, int M, FluxArgs<T> a) {
+  const int t = xcd_block();
+  if (t >= tp[M]) return;
+  SolveInfo info{0, 0, 0, 0, 0, 0, 0};
+  double i0 = 0, i1 = 0, i2 = 0;
+  int m = find_mesh(tp, M, t);
+  int j = (t - tp[m]) * kBlock + threadIdx.x;
+  if (j < S[m].n_flux)
+    flux_store_item<ORDER, T, G14>(a, a.rec[S[m].f0 + j], S[m].dt_min, info, i0, i1, i2);
+  flush_counters(info, i0, i1, i2, a.dcount, a.dimpulse);
+}
+
+template <int ORDER, typename T, int FEAT>
+__global__ __launch_bounds__(kBlock) void k_b_flux_feat(const int32_t* __restrict__ tp,
+                                                        const BatchSched* S, int M,
+                                                        FluxArgs<T> a) {
+  __shared__ __attribute__((aligned(16))) uint16_t lds[(FEAT & 2) ? (kBlock / 64) * kMlpFwdLds : 8];
+  const int t = xcd_block();
+  if (t >= tp[M]) return;
+  SolveInfo info{0, 0, 0, 0, 0, 0, 0};
+  double i0 = 0, i1 = 0, i2 = 0;
+  int m = find_mesh(tp, M, t);
+  int j = (t - tp[m]) * kBlock + threadIdx.x;
+  const bool valid = j < S[m].n_flux;
+  int4 r = valid ? a.rec[S[m].f0 + j] : make_int4(0, 0, -1, 0);
+  flux_feat_item<ORDER, T, FEAT>(a, valid, r, S[m].dt_min, lds + (threadIdx.x >> 6) * kMlpFwdLds,
+                                 info, i0, i1, i2);
+  flush_counters(info, i0, i1, i2, a.dcount, a.dimpulse);
+}
+
+__global__ __launch_bounds__(kBlock) void k_b_gather(const int32_t* __restrict__ tp,
+                                                     const BatchSched* S, int M, int grab, int NC,
+                                                     const int* __restrict__ list,
+                                                     const uint32_t* __restrict__ fpack,
+                                                     const int* __restrict__ c2f,
+                                                     const double* __restrict__ Q,
+                                                     const double* __restrict__ vol,
+                                                     double* __restrict__ U,
+                                                     double* __restrict__ R,
+                                                     unsigned long long* flag) {
+  const int total = tp[M];
+  TILE_LOOP(total, grab) {
+    int m = find_mesh(tp, M, t);
+    int j = (t - tp[m]) * kBlock + threadIdx.x;
+    if (j < S[m].n_gather)
+      if (!cell_gather_item(list[S[m].c0 + j], NC, fpack, c2f, Q, vol, U, R, S[m].tau_s,
+                            S[m].upd))
+        atomicOr(flag, 1ull);
+  }
+}
+
+// one mesh's schedule entry back to "state just set"; keep_counters keeps
+// the cumulative counters (state reset)
+__global__ void k_b_reset_mesh(BatchSched* S, int m0, int count, int keep_counters) {
+  const int m = m0 + blockIdx.x * blockDim.x + threadIdx.x;
+  if (m >= m0 + count) return;
+  BatchSched& s = S[m];
+  s.phase = 0;
+  s.theta = 0;
+  s.classified = 0;
+  s.reclass = 0;
+  s.dt_min = 0.0;
+  s.t = 0.0;
+  s.n_grad = s.n_flux = s.n_gather = 0;
+  if (!keep_counters) {
+    s.subiterations = 0;
+    s.cell_updates = 0;
+    s.face_solves = 0;
+    for (int k = 0; k < kMaxLevels; ++k) s.cells_per_level[k] = 0;
+  }
+}
+
+__global__ void k_b_set_levels(BatchSched* S, int m, int L) {
+  if (threadIdx.x == 0) {
+    S[m].L = L;
+    S[m].classified = 0;
+  }
+}
+
+__global__ void k_b_zero_rows(double* p, int64_t n) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = 0.0;
+}
+
+// ---- host side ---------------------------------------------------------------
+
+#define B_TRY(c, expr)                                       \
+  do {                                                       \
+    hipError_t e_ = (expr);                                  \
+    if (e_ != hipSuccess) return hip_error((c), e_, #expr); \
+  } while (0)
+
+inline int nblk(int64_t n, int bs) { return (int)((n + bs - 1) / bs); }
+
+int cu_count(tafv_ctx* c) {
+  hipDeviceProp_t p;
+  if (hipGetDeviceProperties(&p, c->device) != hipSuccess) return 256;
+  return std::max(1, p.multiProcessorCount);
+}
+
+std::string arch_name(tafv_ctx* c) {
+  hipDeviceProp_t p;
+  if (hipGetDeviceProperties(&p, c->device) != hipSuccess) return "unknown";
+  std::string a = p.gcnArchName;
+  size_t k = a.find(':');
+  return k == std::string::npos ? a : a.substr(0, k);
+}
+
+// Merge the uploaded meshes: cells, faces and half-face ids offset by each
+// mesh's segment; [k][n] arrays re-laid as [k][N] over the merged counts;
+// boundary markers -(f+1) keep pointing at the mesh's own faces.
+void merge_hosts(const std::vector<HostMesh*>& hs, HostMesh& out, std::vector<int64_t>& c0,
+                 std::vector<int64_t>& f0) {
+  int64_t NC = 0, NF = 0;
+  c0.clear();
+  f0.clear();
+  for (const HostMesh* h : hs) {
+    c0.push_back(NC);
+    f0.push_back(NF);
+    NC += h->nc;
+    NF += h->nf;
+  }
+  out.nc = NC;
+  out.nf = NF;
+  out.nbnd = 0;
+  out.ncolours = 0;
+  out.fhL.resize(NF);
+  out.fhR.resize(NF);
+  out.fcol.resize(NF);
+  out.fA.resize(3 * NF);
+  out.nb.resize(4 * NC);
+  out.c2f.resize(4 * NC);
+  out.lsq.resize(12 * NC);
+  out.rf.resize(12 * NC);
+  out.vol.resize(NC);
+  out.perm.resize(NC);
+  for (size_t q = 0; q < hs.size(); ++q) {
+    const HostMesh& h = *hs[q];
+    const int64_t cb = c0[q], fb = f0[q];
+    out.nbnd += h.nbnd;
+    out.ncolours = std::max(out.ncolours, h.ncolours);
+    for (int64_t f = 0; f < h.nf; ++f) {
+      out.fhL[fb + f] = h.fhL[f] + (int32_t)(4 * cb);
+      out.fhR[fb + f] = h.fhR[f] >= 0 ? h.fhR[f] + (int32_t)(4 * cb) : -1;
+      out.fcol[fb + f] = h.fcol[f];
+      for (int k = 0; k < 3; ++k) out.fA[k * NF + fb + f] = h.fA[k * h.nf + f];
+    }
+    for (int64_t i = 0; i < h.nc; ++i) {
+      for (int m = 0; m < 4; ++m) {
+        int32_t n = h.nb[m * h.nc + i];
+        out.nb[m * NC + cb + i] = n >= 0 ? n + (int32_t)cb : n - (int32_t)fb;
+        out.c2f[m * NC + cb + i] = h.c2f[m * h.nc + i] + (int32_t)fb;
+      }
+      for (int k = 0; k < 12; ++k) {
+        out.lsq[k * NC + cb + i] = h.lsq[k * h.nc + i];
+        out.rf[k * NC + cb + i] = h.rf[k * h.nc + i];
+      }
+      out.vol[cb + i] = h.vol[i];
+      out.perm[cb + i] = h.perm[i];  // local: caller order within the mesh
+    }
+  }
+}
+
+tafv_status build(tafv_ctx* c) {
+  Batch& B = *c->batch;
+  if (B.built) return TAFV_OK;
+  if (B.hosts.empty()) return set_error(c, TAFV_E_ORDER, "no mesh uploaded");
+  B_TRY(c, hipSetDevice(c->device));
+  const int M = (int)B.hosts.size();
+  HostMesh merged;
+  std::vector<int64_t> c0, f0;
+  merge_hosts(B.hosts, merged, c0, f0);
+  if (merged.nc > INT32_MAX / 8 || merged.nf > INT32_MAX / 8)
+    return set_error(c, TAFV_E_ARG, "batch too large for 32-bit ids");
+  DevMesh* dm = nullptr;
+  tafv_status st = upload_host_mesh(c, merged, &dm);
+  if (st != TAFV_OK) return st;
+  B.m = dm;
+  // schedule table and tile prefixes
+  B.hsched.assign(M, BatchSched{});
+  std::vector<int32_t> ct(M + 1), ft(M + 1), cc(M + 1), fc(M + 1);
+  ct[0] = ft[0] = cc[0] = fc[0] = 0;
+  B.lmax = 1;
+  for (int m = 0; m < M; ++m) {
+    BatchSched& s = B.hsched[m];
+    const HostMesh& h = *B.hosts[m];
+    s.c0 = (int32_t)c0[m];
+    s.nc = (int32_t)h.nc;
+    s.f0 = (int32_t)f0[m];
+    s.nf = (int32_t)h.nf;
+    s.L = B.L[m];
+    B.lmax = std::max(B.lmax, (int32_t)B.L[m]);
+    ct[m + 1] = ct[m] + nblk(h.nc, kBlock);
+    ft[m + 1] = ft[m] + nblk(h.nf, kBlock);
+    cc[m + 1] = cc[m] + nblk(h.nc, kChunk);
+    fc[m + 1] = fc[m] + nblk(h.nf, kChunk);
+  }
+  B.n_cc = cc[M];
+  B.n_fc = fc[M];
+  B.n_ft = ft[M];
+  hipError_t e = hipSuccess;
+  auto chk = [&](hipError_t x) {
+    if (e == hipSuccess) e = x;
+  };
+  chk(hipMalloc(&B.dsched, sizeof(BatchSched) * M));
+  for (int32_t** p : {&B.ct, &B.ft, &B.cc, &B.fc}) chk(hipMalloc(p, sizeof(int32_t) * (M + 1)));
+  chk(hipMalloc(&B.tp, sizeof(int32_t) * 3 * (M + 1)));
+  chk(hipMalloc(&B.cnt_c, sizeof(int32_t) * kMaxLevels * std::max(B.n_cc, 1)));
+  chk(hipMalloc(&B.cnt_f, sizeof(int32_t) * kMaxLevels * std::max(B.n_fc, 1)));
+  if (e != hipSuccess) return hip_error(c, e, "batch allocation");
+  B_TRY(c, hipMemcpy(B.dsched, B.hsched.data(), sizeof(BatchSched) * M, hipMemcpyHostToDevice));
+  B_TRY(c, hipMemcpy(B.ct, ct.data(), sizeof(int32_t) * (M + 1), hipMemcpyHostToDevice));
+  B_TRY(c, hipMemcpy(B.ft, ft.data(), sizeof(int32_t) * (M + 1), hipMemcpyHostToDevice));
+  B_TRY(c, hipMemcpy(B.cc, cc.data(), sizeof(int32_t) * (M + 1), hipMemcpyHostToDevice));
+  B_TRY(c, hipMemcpy(B.fc, fc.data(), sizeof(int32_t) * (M + 1), hipMemcpyHostToDevice));
+  B_TRY(c, launch_fill_u64(c->stream, B.m->dcount, 0ull, kCounterWords));
+  B_TRY(c, launch_fill_f64(c->stream, B.m->dimpulse, 0.0, kCounterWords));
+  B_TRY(c, launch_fill_u64(c->stream, B.m->dscal, 0ull, 4));
+  B_TRY(c, launch_fill_f64(c->stream, B.m->U, 0.0, (int64_t)5 * merged.nc));
+  B_TRY(c, launch_fill_f64(c->stream, B.m->R, 0.0, (int64_t)5 * merged.nc));
+  B_TRY(c, hipStreamSynchronize(c->stream));
+  B_TRY(c, hipStreamCreateWithFlags(&B.cap, hipStreamNonBlocking));
+  B.nmesh = M;
+  B.has_state.assign(M, 0);
+  for (HostMesh* h : B.hosts) delete h;
+  B.hosts.clear();
+  B.built = true;
+  const int cu = cu_count(c);
+  for (int w = 0; w < 3; ++w) B.set[w] = LaunchSet{kStaticBlocksPerCU * cu, 1};
+  B.set[1] = LaunchSet{std::max(B.n_ft, 1), 1};
+  return TAFV_OK;
+}
+
+FluxFeatures features(tafv_ctx* c) {
+  FluxFeatures ft;
+  bool mlp = c->prm.guess == TAFV_GUESS_MLP;
+  ft.feat = (c->prm.guess_stats ? 1 : 0) | (mlp ? 2 : 0);
+  ft.mlp = (const MlpDev*)c->mlp_w;
+  ft.guess_gate = (float)c->prm.guess_gate;
+  return ft;
+}
+
+StepArgs step_args(tafv_ctx* c) {
+  StepArgs a;
+  a.gas = make_gas(c->prm.gamma);
+  a.cfl = c->prm.cfl;
+  a.newton_tol = c->prm.newton_tol;
+  a.level_margin = c->prm.level_margin;
+  a.dt_min = 0.0;
+  a.newton_max_iter = c->prm.newton_max_iter;
+  a.boundary = c->prm.boundary;
+  a.max_levels = c->batch->lmax;
+  a.precision = c->prm.precision;
+  a.order = c->prm.order;
+  return a;
+}
+
+// ---- launches of one subiteration ------------------------------------------
+
+struct Ptrs {
+  unsigned long long* dcount;
+  double* dimpulse;
+  double* U;
+  double* R;
+};
+
+hipError_t run_reclass(tafv_ctx* c, hipStream_t s) {
+  Batch& B = *c->batch;
+  DevMesh& m = *B.m;
+  const int M = B.nmesh, G = kStaticBlocksPerCU * cu_count(c);
+  unsigned long long* flag = m.dscal + 2;
+  hipLaunchKernelGGL(k_b_begin, dim3(1), dim3(1024), 0, s, B.dsched, M, c->prm.reclassify);
+  hipLaunchKernelGGL(k_b_dt, dim3(G), dim3(kBlock), 0, s, B.ct, B.dsched, M, m.nc, m.nf, m.U,
+                     m.vol, m.c2f, m.fA, c->prm.gamma, c->prm.cfl, m.dt, flag);
+  hipLaunchKernelGGL(k_b_classify, dim3(G), dim3(kBlock), 0, s, B.ct, B.dsched, M, m.dt,
+                     c->prm.level_margin, m.lev);
+  // lowering sweeps: an even count >= lmax - 1 leaves the result in lev
+  // (sweeps past the fixed point change nothing)
+  int sweeps = B.lmax - 1;
+  sweeps += sweeps & 1;
+  for (int k = 0; k < sweeps; ++k) {
+    const int8_t* src = (k & 1) ? m.lev2 : m.lev;
+    int8_t* dst = (k & 1) ? m.lev : m.lev2;
+    hipLaunchKernelGGL(k_b_sweep, dim3(G), dim3(kBlock), 0, s, B.ct, B.dsched, M, m.nc, m.nb_,
+                       src, dst);
+  }
+  hipLaunchKernelGGL(k_b_cell_keys, dim3(G), dim3(kBlock), 0, s, B.ct, B.dsched, M, m.nc, m.nb_,
+                     m.lev, m.ckey, m.fpack);
+  hipLaunchKernelGGL(k_b_face_keys, dim3(G), dim3(kBlock), 0, s, B.ft, B.dsched, M, m.fhL, m.fhR,
+                     m.lev, m.fkey);
+  const int PG = 4 * G;  // 64-thread blocks
+  hipLaunchKernelGGL(k_b_part_count<ByteKey>, dim3(PG), dim3(64), 0, s, B.fc, B.dsched, M, 1,
+                     ByteKey{m.fkey}, B.cnt_f);
+  hipLaunchKernelGGL(k_b_part_count<ByteKey>, dim3(PG), dim3(64), 0, s, B.cc, B.dsched, M, 0,
+                     ByteKey{m.ckey}, B.cnt_c);
+  hipLaunchKernelGGL(k_b_part_scan, dim3(M), dim3(256), 0, s, B.fc, B.dsched, M, 1, B.cnt_f);
+  hipLaunchKernelGGL(k_b_part_scan, dim3(M), dim3(256), 0, s, B.cc, B.dsched, M, 0, B.cnt_c);
+  hipLaunchKernelGGL((k_b_part_scatter<ByteKey, FaceWriter>), dim3(PG), dim3(64), 0, s, B.fc,
+                     B.dsched, M, 1, ByteKey{m.fkey}, B.cnt_f, FaceWriter{m.frec, m.fhL, m.fhR});
+  hipLaunchKernelGGL((k_b_part_scatter<ByteKey, IndexWriter>), dim3(PG), dim3(64), 0, s, B.cc,
+                     B.dsched, M, 0, ByteKey{m.ckey}, B.cnt_c, IndexWriter{m.pc.list});
+  hipLaunchKernelGGL(k_b_sched, dim3(1), dim3(1024), 0, s, B.dsched, M, c->prm.order, flag, B.tp);
+  return hipGetLastError();
+}
+
+hipError_t run_grad(tafv_ctx* c, hipStream_t s, const LaunchSet& ls) {
+  Batch& B = *c->batch;
+  DevMesh& m = *B.m;
+  if (c->prm.order != 2) return hipSuccess;
+  const int M = B.nmesh;
+  const double gm1 = c->prm.gamma - 1.0;
+  if (c->prm.precision == TAFV_FP32_FLUX) {
+    GradArgs<float> g{m.pc.list, 0, m.nc, m.nf, m.U, m.nb_, m.lsq32, m.rf32, m.fA, (float*)m.Wf,
+                      gm1, c->prm.boundary};
+    hipLaunchKernelGGL(k_b_grad<float>, dim3(ls.grid), dim3(kBlock), 0, s, B.tp, B.dsched, M,
+                       ls.grab, g);
+  } else {
+    GradArgs<double> g{m.pc.list, 0, m.nc, m.nf, m.U, m.nb_, m.lsq, m.rf, m.fA, (double*)m.Wf,
+                       gm1, c->prm.boundary};
+    hipLaunchKernelGGL(k_b_grad<double>, dim3(ls.grid), dim3(kBlock), 0, s, B.tp, B.dsched, M,
+                       ls.grab, g);
+  }
+  return hipGetLastError();
+}
+
+template <typename T>
+void flux_dispatch(hipStream_t s, const Batch& B, int order, int feat, bool g14, int grid,
+                   const FluxArgs<T>& f) {
+  const int32_t* tp = B.tp + (B.nmesh + 1);
+  dim3 g(grid), b(kBlock);
+  const int M = B.nmesh;
+#define B_FEAT(O, F) hipLaunchKernelGGL((k_b_flux_feat<O, T, F>), g, b, 0, s, tp, B.dsched, M, f)
+#define B_PLAIN(O, G) hipLaunchKernelGGL((k_b_flux<O, T, G>), g, b, 0, s, tp, B.dsched, M, f)
+  if (feat && g14) {
+    if (order == 2) {
+      if (feat == 1) B_FEAT(2, 1);
+      else if (feat == 2) B_FEAT(2, 2);
+      else B_FEAT(2, 3);
+    } else {
+      if (feat == 1) B_FEAT(1, 1);
+      else if (feat == 2) B_FEAT(1, 2);
+      else B_FEAT(1, 3);
+    }
+  } else if (g14) {
+    if (order == 2) B_PLAIN(2, true);
+    else B_PLAIN(1, true);
+  } else {
+    if (order == 2) B_PLAIN(2, false);
+    else B_PLAIN(1, false);
+  }
+#undef B_FEAT
+#undef B_PLAIN
+}
+
+hipError_t run_flux(tafv_ctx* c, hipStream_t s, const Ptrs& p) {
+  Batch& B = *c->batch;
+  const int grid = std::max(B.n_ft, 1);
+  DevMesh& m = *B.m;
+  StepArgs a = step_args(c);
+  FluxFeatures ft = features(c);
+  if (c->prm.precision == TAFV_FP32_FLUX) {
+    FluxArgs<float> f{m.frec, 0, m.nf, m.nc, m.fA32, m.U, (const float*)m.Wf, m.R, m.Q,
+                      p.dcount, p.dimpulse, a, ft.mlp, nullptr, nullptr, 0, 0.0, 0, 0,
+                      ft.guess_gate};
+    flux_dispatch<float>(s, B, c->prm.order, ft.feat, a.gas.is14, grid, f);
+  } else {
+    FluxArgs<double> f{m.frec, 0, m.nf, m.nc, m.fA, m.U, (const double*)m.Wf, m.R, m.Q,
+                       p.dcount, p.dimpulse, a, ft.mlp, nullptr, nullptr, 0, 0.0, 0, 0,
+                       ft.guess_gate};
+    flux_dispatch<double>(s, B, c->prm.order, ft.feat, a.gas.is14, grid, f);
+  }
+  return hipGetLastError();
+}
+
+hipError_t run_gather(tafv_ctx* c, hipStream_t s, const LaunchSet& ls, const Ptrs& p) {
+  Batch& B = *c->batch;
+  DevMesh& m = *B.m;
+  const int M = B.nmesh;
+  hipLaunchKernelGGL(k_b_gather, dim3(ls.grid), dim3(kBlock), 0, s, B.tp + 2 * (M + 1), B.dsched,
+                     M, ls.grab, m.nc, m.pc.list, m.fpack, m.c2f, m.Q, m.vol, p.U, p.R,
+                     m.dscal + 2);
+  return hipGetLastError();
+}
+
+Ptrs live_ptrs(Batch& B) { return Ptrs{B.m->dcount, B.m->dimpulse, B.m->U, B.m->R}; }
+
+// one subiteration on stream s (profiling scopes only when s is the
+// context stream and nothing is being captured)
+hipError_t run_subiteration(tafv_ctx* c, hipStream_t s, bool prof) {
+  Batch& B = *c->batch;
+  Ptrs p = live_ptrs(B);
+  hipError_t e;
+  {
+    ProfScope ps(prof ? c : nullptr, P_CLASSIFY, B.m->nc);
+    e = run_reclass(c, s);
+    if (e != hipSuccess) return e;
+  }
+  {
+    ProfScope ps(prof ? c : nullptr, P_GRAD, 0);
+    e = run_grad(c, s, B.set[0]);
+    if (e != hipSuccess) return e;
+  }
+  {
+    ProfScope ps(prof ? c : nullptr, P_FLUX, 0);
+    e = run_flux(c, s, p);
+    if (e != hipSuccess) return e;
+  }
+  ProfScope ps(prof ? c : nullptr, P_GATHER, 0);
+  return run_gather(c, s, B.set[2], p);
+}
+
+// ---- autotuning -------------------------------------------------------------
+
+std::string tune_key(tafv_ctx* c) {
+  Batch& B = *c->batch;
+  int64_t nc = B.m->nc;
+  int bucket = 0;
+  while ((int64_t(1) << (bucket + 1)) <= nc) ++bucket;
+  std::ostringstream o;
+  o << arch_name(c) << ":p" << c->prm.precision << ":o" << c->prm.order << ":g" << c->prm.guess
+    << ":n" << bucket;
+  return o.str();
+}
+
+bool cache_lookup(tafv_ctx* c, const std::string& key) {
+  Batch& B = *c->batch;
+  if (B.cache.empty()) return false;
+  std::ifstream f(B.cache);
+  if (!f) return false;
+  std::string line;
+  bool found = false;
+  LaunchSet got[3];
+  while (std::getline(f, line)) {
+    std::istringstream in(line);
+    std::string k;
+    LaunchSet t[3];
+    if (!(in >> k >> t[0].grid >> t[0].grab >> t[2].grid >> t[2].grab)) continue;
+    if (k != key) continue;
+    bool ok = true;
+    for (int w : {0, 2}) ok &= t[w].grid > 0 && t[w].grid <= 65536 && t[w].grab >= 1 && t[w].grab <= 64;
+    if (!ok) continue;
+    for (int w : {0, 2}) got[w] = t[w];
+    found = true;  // the last matching line wins
+  }
+  if (found)
+    for (int w : {0, 2}) B.set[w] = got[w];
+  return found;
+}
+
+void cache_store(tafv_ctx* c, const std::string& key) {
+  Batch& B = *c->batch;
+  if (B.cache.empty()) return;
+  std::ofstream f(B.cache, std::ios::app);
+  if (!f) return;
+  f << key;
+  for (int w : {0, 2}) f << ' ' << B.set[w].grid << ' ' << B.set[w].grab;
+  f << '\n';
+}
+
+// Times candidate launch widths of one work class (0 gradient, 2 cells) on
+// the current subiteration: the gradient kernel writes only the face values
+// (recomputed by the real launch); the cell kernel, run after the flux
+// kernel, works on copies of U and R.  Three timed runs after one warm-up
+// per candidate.
+tafv_status autotune(tafv_ctx* c, int w) {
+  Batch& B = *c->batch;
+  DevMesh& m = *B.m;
+  hipStream_t s = c->stream;
+  const int cu = cu_count(c);
+  std::vector<LaunchSet> cand;
+  for (int mult : {1, 2, 4, 8})
+    for (int grab : {1, 4}) cand.push_back(LaunchSet{mult * cu, grab});
+  hipEvent_t e0, e1;
+  B_TRY(c, hipEventCreate(&e0));
+  B_TRY(c, hipEventCreate(&e1));
+  double *Us = nullptr, *Rs = nullptr;
+  const size_t rows = (size_t)5 * m.nc;
+  hipError_t e = hipSuccess;
+  if (w == 2) {
+    e = hipMalloc(&Us, rows * sizeof(double));
+    if (e == hipSuccess) e = hipMalloc(&Rs, rows * sizeof(double));
+  }
+  Ptrs scratch{m.dcount, m.dimpulse, Us, Rs};  // the cell kernel's copies
+  if (e == hipSuccess) {
+    float best = 1e30f;
+    for (const LaunchSet& ls : cand) {
+      float tot = 0.f;
+      for (int rep = 0; rep < 4 && e == hipSuccess; ++rep) {
+        if (w == 2) {
+          e = hipMemcpyAsync(Us, m.U, rows * sizeof(double), hipMemcpyDeviceToDevice, s);
+          if (e == hipSuccess)
+            e = hipMemcpyAsync(Rs, m.R, rows * sizeof(double), hipMemcpyDeviceToDevice, s);
+        }
+        if (e == hipSuccess) e = hipEventRecord(e0, s);
+        if (e == hipSuccess)
+          e = w == 0 ? run_grad(c, s, ls) : run_gather(c, s, ls, scratch);
+        if (e == hipSuccess) e = hipEventRecord(e1, s);
+        if (e == hipSuccess) e = hipEventSynchronize(e1);
+        float ms = 0.f;
+        if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+        if (rep > 0) tot += ms;
+      }
+      if (e == hipSuccess && tot < best) {
+        best = tot;
+        B.set[w] = ls;
+      }
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (Us) (void)hipFree(Us);
+  if (Rs) (void)hipFree(Rs);
+  if (e != hipSuccess) return hip_error(c, e, "autotuning");
+  return TAFV_OK;
+}
+
+void drop_graphs(Batch& B) {
+  for (auto& pe : B.execs) (void)hipGraphExecDestroy(pe.second);
+  B.execs.clear();
+  B.exec_key = -1;
+}
+
+int64_t graph_key(tafv_ctx* c) {
+  Batch& B = *c->batch;
+  FluxFeatures ft = features(c);
+  int64_t k = ft.feat;
+  k = k * 16 + B.lmax;
+  k = k * 2 + (c->prm.reclassify ? 1 : 0);
+  for (int w = 0; w < 3; ++w) k = k * 1000003 + B.set[w].grid * 64 + B.set[w].grab;
+  return k;
+}
+
+tafv_status graph_for(tafv_ctx* c, int64_t len, hipGraphExec_t* out) {
+  Batch& B = *c->batch;
+  int64_t key = graph_key(c);
+  if (key != B.exec_key) {
+    drop_graphs(B);
+    B.exec_key = key;
+  }
+  for (auto& pe : B.execs)
+    if (pe.first == len) {
+      *out = pe.second;
+      return TAFV_OK;
+    }
+  // capture on the context's private stream, replay on the context stream
+  B_TRY(c, hipStreamBeginCapture(B.cap, hipStreamCaptureModeThreadLocal));
+  hipError_t e = hipSuccess;
+  for (int64_t k = 0; k < len && e == hipSuccess; ++k) e = run_subiteration(c, B.cap, false);
+  hipGraph_t g = nullptr;
+  hipError_t e2 = hipStreamEndCapture(B.cap, &g);
+  if (e != hipSuccess || e2 != hipSuccess) {
+    if (g) (void)hipGraphDestroy(g);
+    return hip_error(c, e != hipSuccess ? e : e2, "graph capture");
+  }
+  hipGraphExec_t x = nullptr;
+  e = hipGraphInstantiate(&x, g, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(g);
+  if (e != hipSuccess) return hip_error(c, e, "graph instantiation");
+  B.execs.push_back({len, x});
+  *out = x;
+  return TAFV_OK;
+}
+
+tafv_status sync_back(tafv_ctx* c) {
+  Batch& B = *c->batch;
+  B_TRY(c, hipMemcpyAsync(B.hsched.data(), B.dsched, sizeof(BatchSched) * B.nmesh,
+                          hipMemcpyDeviceToHost, c->stream));
+  B_TRY(c, hipMemcpyAsync(c->hpin, B.m->dscal, 4 * sizeof(unsigned long long),
+                          hipMemcpyDeviceToHost, c->stream));
+  B_TRY(c, hipStreamSynchronize(c->stream));
+  return TAFV_OK;
+}
+
+Batch* ready(tafv_ctx* c, int32_t id, tafv_status* st) {
+  *st = TAFV_OK;
+  Batch& B = *c->batch;
+  if (!B.built) {
+    *st = build(c);
+    if (*st != TAFV_OK) return nullptr;
+  }
+  if (id < 0 || id >= B.nmesh) {
+    *st = set_error(c, TAFV_E_ARG, "unknown mesh");
+    return nullptr;
+  }
+  return &B;
+}
+
+}  // namespace
+
+tafv_status batch_upload(tafv_ctx* c, HostMesh* hm, int32_t* mesh_id) {
+  Batch& B = *c->batch;
+  if (B.built) {
+    delete hm;
+    return set_error(c, TAFV_E_ORDER, "batched form: meshes must be uploaded before the first state_init");
+  }
+  *mesh_id = (int32_t)B.hosts.size();
+  B.hosts.push_back(hm);
+  B.L.push_back(c->prm.max_levels);
+  return TAFV_OK;
+}
+
+tafv_status batch_mesh_params(tafv_ctx* c, int32_t id, int32_t L) {
+  Batch& B = *c->batch;
+  if (L < 1 || L > kMaxLevels) return set_error(c, TAFV_E_ARG, "max_levels out of range");
+  if (!B.built) {
+    if (id < 0 || id >= (int32_t)B.hosts.size()) return set_error(c, TAFV_E_ARG, "unknown mesh");
+    B.L[id] = L;
+    return TAFV_OK;
+  }
+  if (id < 0 || id >= B.nmesh) return set_error(c, TAFV_E_ARG, "unknown mesh");
+  B_TRY(c, hipSetDevice(c->device));
+  B.L[id] = L;
+  B.hsched[id].L = L;
+  B.hsched[id].classified = 0;
+  hipLaunchKernelGGL(k_b_set_levels, dim3(1), dim3(64), 0, c->stream, B.dsched, id, L);
+  B_TRY(c, hipGetLastError());
+  int32_t lmax = 1;
+  for (int32_t v : B.L) lmax = std::max(lmax, v);
+  if (lmax != B.lmax) {
+    B.lmax = lmax;
+    drop_graphs(B);
+  }
+  return TAFV_OK;
+}
+
+tafv_status batch_state_init(tafv_ctx* c, int32_t id, const double* prim) {
+  if (!prim) return set_error(c, TAFV_E_ARG, "prim is NULL");
+  tafv_status st;
+  Batch* Bp = ready(c, id, &st);
+  if (!Bp) return st;
+  Batch& B = *Bp;
+  const BatchSched& s = B.hsched[id];
+  for (int64_t i = 0; i < s.nc; ++i) {
+    const double* w = prim + 5 * i;
+    for (int k = 0; k < 5; ++k)
+      if (!std::isfinite(w[k]))
+        return set_error(c, TAFV_E_STATE, "non-finite initial value at cell " + std::to_string(i));
+    if (!(w[0] > 0.0) || !(w[4] > 0.0))
+      return set_error(c, TAFV_E_STATE, "rho <= 0 or p <= 0 at cell " + std::to_string(i));
+  }
+  B_TRY(c, hipSetDevice(c->device));
+  DevMesh& m = *B.m;
+  double* xf = m.xfer + 5 * (size_t)s.c0;
+  B_TRY(c, hipMemcpyAsync(xf, prim, sizeof(double) * 5 * s.nc, hipMemcpyHostToDevice, c->stream));
+  B_TRY(c, launch_state_init_rows(c->stream, s.nc, m.perm + s.c0, xf, c->prm.gamma,
+                                  m.U + 5 * (size_t)s.c0, m.R + 5 * (size_t)s.c0));
+  B_TRY(c, hipMemcpyAsync(m.U0 + 5 * (size_t)s.c0, m.U + 5 * (size_t)s.c0,
+                          sizeof(double) * 5 * s.nc, hipMemcpyDeviceToDevice, c->stream));
+  hipLaunchKernelGGL(k_b_reset_mesh, dim3(1), dim3(64), 0, c->stream, B.dsched, id, 1, 0);
+  B_TRY(c, hipGetLastError());
+  B_TRY(c, launch_fill_u64(c->stream, m.dscal + 2, 0ull, 1));
+  st = sync_back(c);
+  if (st != TAFV_OK) return st;
+  B.has_state[id] = 1;
+  return TAFV_OK;
+}
+
+tafv_status batch_state_reset(tafv_ctx* c, int32_t id) {
+  tafv_status st;
+  if (id == -1) {  // every mesh: one copy of the whole state
+    Batch* Bp = ready(c, 0, &st);
+    if (!Bp) return st;
+    Batch& B = *Bp;
+    for (int m = 0; m < B.nmesh; ++m)
+      if (!B.has_state[m]) return set_error(c, TAFV_E_ORDER, "no state");
+    B_TRY(c, hipSetDevice(c->device));
+    DevMesh& dm = *B.m;
+    B_TRY(c, hipMemcpyAsync(dm.U, dm.U0, sizeof(double) * 5 * (size_t)dm.nc,
+                            hipMemcpyDeviceToDevice, c->stream));
+    hipLaunchKernelGGL(k_b_zero_rows, dim3(nblk((int64_t)5 * dm.nc, 256)), dim3(256), 0,
+                       c->stream, dm.R, (int64_t)5 * dm.nc);
+    hipLaunchKernelGGL(k_b_reset_mesh, dim3(nblk(B.nmesh, 256)), dim3(256), 0, c->stream,
+                       B.dsched, 0, B.nmesh, 1);
+    B_TRY(c, hipGetLastError());
+    B_TRY(c, launch_fill_u64(c->stream, dm.dscal + 2, 0ull, 1));
+    return sync_back(c);
+  }
+  Batch* Bp = ready(c, id, &st);
+  if (!Bp) return st;
+  Batch& B = *Bp;
+  if (!B.has_state[id]) return set_error(c, TAFV_E_ORDER, "no state");
+  B_TRY(c, hipSetDevice(c->device));
+  const BatchSched& s = B.hsched[id];
+  DevMesh& m = *B.m;
+  B_TRY(c, hipMemcpyAsync(m.U + 5 * (size_t)s.c0, m.U0 + 5 * (size_t)s.c0,
+                          sizeof(double) * 5 * s.nc, hipMemcpyDeviceToDevice, c->stream));
+  hipLaunchKernelGGL(k_b_zero_rows, dim3(nblk((int64_t)5 * s.nc, 256)), dim3(256), 0, c->stream,
+                     m.R + 5 * (size_t)s.c0, (int64_t)5 * s.nc);
+  hipLaunchKernelGGL(k_b_reset_mesh, dim3(1), dim3(64), 0, c->stream, B.dsched, id, 1, 1);
+  B_TRY(c, hipGetLastError());
+  B_TRY(c, launch_fill_u64(c->stream, m.dscal + 2, 0ull, 1));
+  return sync_back(c);
+}
+
+tafv_status batch_advance(tafv_ctx* c, int64_t n, tafv_stats* out) {
+  Batch& B = *c->batch;
+  tafv_status st;
+  if (!B.built) return set_error(c, TAFV_E_ORDER, "advance before state_init");
+  for (int m = 0; m < B.nmesh; ++m)
+    if (!B.has_state[m]) return set_error(c, TAFV_E_ORDER, "advance before state_init");
+  if (c->prm.guess == TAFV_GUESS_MLP && !c->mlp_ready)
+    return set_error(c, TAFV_E_MLP, "learned guess selected but no network set");
+  B_TRY(c, hipSetDevice(c->device));
+  int64_t left = n;
+  if (left > 0 && B.autotune && B.tuned == 0) {
+    if (cache_lookup(c, tune_key(c))) {
+      B.tuned = 2;
+    } else {
+      // first subiteration: reclassify, then time the work kernels on it
+      Ptrs p = live_ptrs(B);
+      B_TRY(c, run_reclass(c, c->stream));
+      if (c->prm.order == 2) {
+        st = autotune(c, 0);
+        if (st != TAFV_OK) return st;
+      }
+      B_TRY(c, run_grad(c, c->stream, B.set[0]));
+      B_TRY(c, run_flux(c, c->stream, p));
+      st = autotune(c, 2);
+      if (st != TAFV_OK) return st;
+      if (c->prm.order != 2) B.set[0] = B.set[2];
+      B.tuned = 1;
+      cache_store(c, tune_key(c));
+      B_TRY(c, run_gather(c, c->stream, B.set[2], p));
+      --left;
+    }
+  }
+  const bool use_graph = B.graph && !c->profile;
+  while (left > 0) {
+    int64_t len = std::min<int64_t>(left, kGraphSpan);
+    if (use_graph) {
+      hipGraphExec_t x = nullptr;
+      st = graph_for(c, len, &x);
+      if (st != TAFV_OK) return st;
+      B_TRY(c, hipGraphLaunch(x, c->stream));
+    } else {
+      for (int64_t k = 0; k < len; ++k) B_TRY(c, run_subiteration(c, c->stream, c->profile));
+    }
+    left -= len;
+  }
+  std::vector<BatchSched> before = B.hsched;
+  st = sync_back(c);
+  if (st != TAFV_OK) return st;
+  const unsigned long long* sc = (const unsigned long long*)c->hpin;
+  tafv_stats now{};
+  st = read_slot_counters(c, *B.m, &now);
+  if (st != TAFV_OK) return st;
+  if (out) {
+    tafv_stats acc{};
+    for (int m = 0; m < B.nmesh; ++m) {
+      const BatchSched& a = before[m];
+      const BatchSched& b = B.hsched[m];
+      acc.subiterations = std::max<int64_t>(acc.subiterations, b.subiterations - a.subiterations);
+      acc.cell_updates += b.cell_updates - a.cell_updates;
+      acc.face_solves += b.face_solves - a.face_solves;
+      acc.theta = std::max(acc.theta, b.theta);
+      for (int k = 0; k < kMaxLevels; ++k) acc.cells_per_level[k] += b.cells_per_level[k];
+    }
+    const BatchSched& last = B.hsched[B.nmesh - 1];
+    acc.phase = last.phase;
+    acc.dt_min = last.dt_min;
+    acc.t_reached = last.t;
+    acc.newton_updates = now.newton_updates - B.last.newton_updates;
+    acc.newton_fallbacks = now.newton_fallbacks - B.last.newton_fallbacks;
+    acc.vacuum_faces = now.vacuum_faces - B.last.vacuum_faces;
+    acc.guess_faces = now.guess_faces - B.last.guess_faces;
+    acc.guess_newton_updates = now.guess_newton_updates - B.last.guess_newton_updates;
+    acc.guess_rejected = now.guess_rejected - B.last.guess_rejected;
+    acc.guess_used = now.guess_used - B.last.guess_used;
+    for (int k = 0; k < 3; ++k) acc.wall_impulse[k] = now.wall_impulse[k] - B.last.wall_impulse[k];
+    *out = acc;
+  }
+  B.last = now;
+  if (sc[2]) return set_error(c, TAFV_E_NUMERIC, "non-finite or non-physical cell state");
+  return TAFV_OK;
+}
+
+tafv_status batch_mesh_stats(tafv_ctx* c, int32_t id, tafv_stats* out) {
+  if (!out) return set_error(c, TAFV_E_ARG, "out is NULL");
+  tafv_status st;
+  Batch* Bp = ready(c, id, &st);
+  if (!Bp) return st;
+  const BatchSched& s = Bp->hsched[id];
+  tafv_stats r{};
+  r.subiterations = s.subiterations;
+  r.cell_updates = s.cell_updates;
+  r.face_solves = s.face_solves;
+  for (int k = 0; k < kMaxLevels; ++k) r.cells_per_level[k] = s.cells_per_level[k];
+  r.theta = s.theta;
+  r.phase = s.phase;
+  r.dt_min = s.dt_min;
+  r.t_reached = s.t;
+  *out = r;
+  return TAFV_OK;
+}
+
+tafv_status batch_state_read(tafv_ctx* c, int32_t id, double* cons, int8_t* levels) {
+  if (!cons) return set_error(c, TAFV_E_ARG, "cons is NULL");
+  tafv_status st;
+  Batch* Bp = ready(c, id, &st);
+  if (!Bp) return st;
+  Batch& B = *Bp;
+  if (!B.has_state[id]) return set_error(c, TAFV_E_ORDER, "no state");
+  B_TRY(c, hipSetDevice(c->device));
+  const BatchSched& s = B.hsched[id];
+  DevMesh& m = *B.m;
+  double* xf = m.xfer + 5 * (size_t)s.c0;
+  B_TRY(c, launch_rows_to_caller_f64(c->stream, s.nc, m.perm + s.c0, m.U + 5 * (size_t)s.c0, xf));
+  B_TRY(c, hipMemcpyAsync(cons, xf, sizeof(double) * 5 * s.nc, hipMemcpyDeviceToHost, c->stream));
+  B_TRY(c, hipStreamSynchronize(c->stream));
+  if (levels) {
+    int8_t* stage = (int8_t*)xf;
+    B_TRY(c, launch_rows_to_caller_i8(c->stream, s.nc, m.perm + s.c0, m.lev + s.c0, stage));
+    B_TRY(c, hipMemcpyAsync(levels, stage, s.nc, hipMemcpyDeviceToHost, c->stream));
+    B_TRY(c, hipStreamSynchronize(c->stream));
+  }
+  return TAFV_OK;
+}
+
+tafv_status batch_config(tafv_ctx* c, int32_t graph, int32_t autotune_on, const char* cache) {
+  Batch& B = *c->batch;
+  if ((graph != 0 && graph != 1) || (autotune_on != 0 && autotune_on != 1))
+    return set_error(c, TAFV_E_ARG, "graph and autotune must be 0 or 1");
+  B.graph = graph;
+  B.autotune = autotune_on;
+  B.cache = cache ? cache : "";
+  if (!autotune_on && B.built) {
+    const int cu = cu_count(c);
+    B.set[0] = B.set[2] = LaunchSet{kStaticBlocksPerCU * cu, 1};
+  }
+  B.tuned = 0;
+  drop_graphs(B);
+  return TAFV_OK;
+}
+
+tafv_status batch_info(tafv_ctx* c, int32_t* info, int32_t n) {
+  Batch& B = *c->batch;
+  if (!info || n < 7) return set_error(c, TAFV_E_ARG, "info needs 7 entries");
+  for (int w = 0; w < 3; ++w) {
+    info[2 * w] = B.set[w].grid;
+    info[2 * w + 1] = B.set[w].grab;
+  }
+  info[6] = B.tuned;
+  return TAFV_OK;
+}
+
+void batch_invalidate(tafv_ctx* c) {
+  if (c->batch) drop_graphs(*c->batch);
+}
+
+void batch_free(tafv_ctx* c) {
+  if (!c->batch) return;
+  Batch& B = *c->batch;
+  drop_graphs(B);
+  for (HostMesh* h : B.hosts) delete h;
+  void* ptrs[] = {B.dsched, B.ct, B.ft, B.cc, B.fc, B.cnt_f, B.cnt_c, B.tp};
+  for (void* p : ptrs)
+    if (p) (void)hipFree(p);
+  if (B.m) free_dev_mesh(B.m);
+  if (B.cap) (void)hipStreamDestroy(B.cap);
+  delete c->batch;
+  c->batch = nullptr;
+}
+
+}  // namespace tafv

@@ -17,7 +17,6 @@ using namespace tafv;
 namespace {
 
 const char* kProfNames[] = {"classify", "grad", "flux", "update", "gather"};
-enum { P_CLASSIFY = 0, P_GRAD = 1, P_FLUX = 2, P_UPDATE = 3, P_GATHER = 4, P_N = 5 };
 
 thread_local std::string g_create_err;
 
@@ -83,36 +82,6 @@ int subiteration_level(int64_t s, int theta) {
   }
   return t;
 }
-
-// ---- profiling ----------------------------------------------------------
-
-struct ProfScope {
-  tafv_ctx* c;
-  int cls;
-  int64_t items;
-  hipEvent_t a = nullptr, b = nullptr;
-  ProfScope(tafv_ctx* c_, int cls_, int64_t items_) : c(c_), cls(cls_), items(items_) {
-    if (!c->profile) return;
-    a = take();
-    b = take();
-    (void)hipEventRecord(a, c->stream);
-  }
-  ~ProfScope() {
-    if (!c->profile) return;
-    (void)hipEventRecord(b, c->stream);
-    c->pending.push_back({a, b, cls, items});
-  }
-  hipEvent_t take() {
-    if (!c->event_pool.empty()) {
-      hipEvent_t e = c->event_pool.back();
-      c->event_pool.pop_back();
-      return e;
-    }
-    hipEvent_t e = nullptr;
-    (void)hipEventCreate(&e);
-    return e;
-  }
-};
 
 // ---- classification at an iteration start ------------------------------
 
@@ -248,27 +217,8 @@ tafv_status subiteration(tafv_ctx* c, DevMesh& m, tafv_stats* acc) {
 }
 
 tafv_status read_counters(tafv_ctx* c, DevMesh& m) {
-  std::vector<unsigned long long> cnt(kCounterWords);
-  std::vector<double> imp(kCounterWords);
-  HIP_TRY(c, hipMemcpyAsync(cnt.data(), m.dcount, kCounterWords * sizeof(unsigned long long),
-                            hipMemcpyDeviceToHost, c->stream));
-  HIP_TRY(c, hipMemcpyAsync(imp.data(), m.dimpulse, kCounterWords * sizeof(double),
-                            hipMemcpyDeviceToHost, c->stream));
-  HIP_TRY(c, hipStreamSynchronize(c->stream));
-  unsigned long long tot[7] = {0, 0, 0, 0, 0, 0, 0};
-  double itot[3] = {0, 0, 0};
-  for (int sl = 0; sl < kCounterSlots; ++sl) {
-    for (int k = 0; k < 7; ++k) tot[k] += cnt[sl * kCounterStride + k];
-    for (int k = 0; k < 3; ++k) itot[k] += imp[sl * kCounterStride + k];
-  }
-  m.st.newton_updates = (int64_t)tot[0];
-  m.st.newton_fallbacks = (int64_t)tot[1];
-  m.st.vacuum_faces = (int64_t)tot[2];
-  m.st.guess_faces = (int64_t)tot[3];
-  m.st.guess_newton_updates = (int64_t)tot[4];
-  m.st.guess_rejected = (int64_t)tot[5];
-  m.st.guess_used = (int64_t)tot[6];
-  for (int k = 0; k < 3; ++k) m.st.wall_impulse[k] = itot[k];
+  tafv_status st = read_slot_counters(c, m, &m.st);
+  if (st != TAFV_OK) return st;
   m.st.theta = m.theta;
   m.st.phase = m.phase;
   m.st.dt_min = m.dt_min;
@@ -283,102 +233,47 @@ DevMesh* get_mesh(tafv_ctx* c, int32_t id) {
 
 }  // namespace
 
-extern "C" {
+namespace tafv {
 
-tafv_status tafv_params_default(tafv_params* p) {
-  if (!p) return TAFV_E_ARG;
-  p->gamma = 1.4;
-  p->cfl = 0.5;
-  p->newton_tol = 1e-12;
-  p->level_margin = 1e-9;
-  p->max_levels = 5;
-  p->order = 2;
-  p->precision = TAFV_FP64;
-  p->guess = TAFV_GUESS_TR;
-  p->boundary = TAFV_BC_WALL;
-  p->newton_max_iter = 50;
-  p->reclassify = 1;
-  p->scatter = TAFV_SCATTER_GATHER;
-  p->cell_order = TAFV_ORDER_CALLER;
-  p->guess_stats = 0;
-  p->guess_gate = 0.0;
+tafv_status set_error(tafv_ctx* c, tafv_status st, const std::string& msg) {
+  return fail(c, st, msg);
+}
+
+tafv_status hip_error(tafv_ctx* c, hipError_t e, const char* what) { return hip_fail(c, e, what); }
+
+void free_dev_mesh(DevMesh* m) { free_mesh(m); }
+
+tafv_status read_slot_counters(tafv_ctx* c, DevMesh& m, tafv_stats* st) {
+  std::vector<unsigned long long> cnt(kCounterWords);
+  std::vector<double> imp(kCounterWords);
+  HIP_TRY(c, hipMemcpyAsync(cnt.data(), m.dcount, kCounterWords * sizeof(unsigned long long),
+                            hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(c, hipMemcpyAsync(imp.data(), m.dimpulse, kCounterWords * sizeof(double),
+                            hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  unsigned long long tot[7] = {0, 0, 0, 0, 0, 0, 0};
+  double itot[3] = {0, 0, 0};
+  for (int sl = 0; sl < kCounterSlots; ++sl) {
+    for (int k = 0; k < 7; ++k) tot[k] += cnt[sl * kCounterStride + k];
+    for (int k = 0; k < 3; ++k) itot[k] += imp[sl * kCounterStride + k];
+  }
+  st->newton_updates = (int64_t)tot[0];
+  st->newton_fallbacks = (int64_t)tot[1];
+  st->vacuum_faces = (int64_t)tot[2];
+  st->guess_faces = (int64_t)tot[3];
+  st->guess_newton_updates = (int64_t)tot[4];
+  st->guess_rejected = (int64_t)tot[5];
+  st->guess_used = (int64_t)tot[6];
+  for (int k = 0; k < 3; ++k) st->wall_impulse[k] = itot[k];
   return TAFV_OK;
 }
 
-tafv_status tafv_create(int device, const tafv_params* params, void* hip_stream,
-                        tafv_ctx** out) {
-  if (!out) return fail(nullptr, TAFV_E_ARG, "out is NULL");
+}  // namespace tafv
+
+namespace tafv {
+// device arrays of a preprocessed mesh
+tafv_status upload_host_mesh(tafv_ctx* c, const HostMesh& hm, DevMesh** out) {
   *out = nullptr;
-  if (!params) return fail(nullptr, TAFV_E_ARG, "params is NULL");
-  const tafv_params& p = *params;
-  if (!(p.gamma > 1.0) || !(p.cfl > 0.0) || !(p.newton_tol > 0.0) || p.max_levels < 1 ||
-      p.max_levels > kMaxLevels || (p.order != 1 && p.order != 2) ||
-      (p.precision != TAFV_FP64 && p.precision != TAFV_FP32_FLUX) ||
-      (p.boundary != TAFV_BC_WALL && p.boundary != TAFV_BC_TRANSMIT) || p.newton_max_iter < 1 ||
-      (p.scatter != TAFV_SCATTER_COLOUR && p.scatter != TAFV_SCATTER_GATHER) ||
-      (p.cell_order != TAFV_ORDER_CALLER && p.cell_order != TAFV_ORDER_MORTON) ||
-      !(p.level_margin >= 0.0 && p.level_margin < 0.5))
-    return fail(nullptr, TAFV_E_ARG, "invalid parameters");
-  if (p.guess != TAFV_GUESS_TR && p.guess != TAFV_GUESS_MLP)
-    return fail(nullptr, TAFV_E_ARG, "unknown guess mode");
-  if (!(p.guess_gate >= 0.0)) return fail(nullptr, TAFV_E_ARG, "negative guess gate");
-  if (p.guess == TAFV_GUESS_MLP && (p.gamma != 1.4 || p.scatter != TAFV_SCATTER_GATHER))
-    return fail(nullptr, TAFV_E_ARG, "the learned guess needs gamma 1.4 and gather scatter");
-  int ndev = 0;
-  hipError_t e = hipGetDeviceCount(&ndev);
-  if (e != hipSuccess || ndev == 0) return fail(nullptr, TAFV_E_DEVICE, "no HIP device");
-  if (device < 0 || device >= ndev) return fail(nullptr, TAFV_E_ARG, "device out of range");
-  e = hipSetDevice(device);
-  if (e != hipSuccess) return hip_fail(nullptr, e, "hipSetDevice");
-  tafv_ctx* c = new (std::nothrow) tafv_ctx();
-  if (!c) return fail(nullptr, TAFV_E_OOM, "host allocation failed");
-  c->device = device;
-  c->stream = (hipStream_t)hip_stream;
-  c->prm = p;
-  e = hipHostMalloc((void**)&c->hpin, 4096, hipHostMallocDefault);
-  if (e != hipSuccess) {
-    delete c;
-    return hip_fail(nullptr, e, "hipHostMalloc");
-  }
-  for (int k = 0; k < P_N; ++k) c->prof.push_back(ProfileClass{kProfNames[k]});
-  *out = c;
-  return TAFV_OK;
-}
-
-tafv_status tafv_destroy(tafv_ctx* c) {
-  if (!c) return TAFV_E_ARG;
-  (void)hipSetDevice(c->device);
-  (void)hipStreamSynchronize(c->stream);
-  for (DevMesh* m : c->meshes) free_mesh(m);
-  for (auto& pe : c->pending) {
-    (void)hipEventDestroy(pe.a);
-    (void)hipEventDestroy(pe.b);
-  }
-  for (hipEvent_t e : c->event_pool) (void)hipEventDestroy(e);
-  void* bufs[] = {c->mlp_th, c->mlp_m, c->mlp_v, c->mlp_grad, c->mlp_gpart, c->mlp_lpart,
-                  c->mlp_loss, c->mlp_w, c->log_rows, c->log_count};
-  for (void* b : bufs)
-    if (b) (void)hipFree(b);
-  if (c->hpin) (void)hipHostFree(c->hpin);
-  delete c;
-  return TAFV_OK;
-}
-
-const char* tafv_last_error(const tafv_ctx* c) {
-  return c ? c->err.c_str() : g_create_err.c_str();
-}
-
-tafv_status tafv_mesh_upload(tafv_ctx* c, int64_t n_nodes, const double* xyz, int64_t n_tets,
-                             const int64_t* tets, int32_t* mesh_id) {
-  if (!c) return TAFV_E_ARG;
-  if (!xyz || !tets || !mesh_id || n_nodes < 4 || n_tets < 1)
-    return fail(c, TAFV_E_ARG, "invalid mesh arguments");
-  HIP_TRY(c, hipSetDevice(c->device));
-  HostMesh hm;
-  tafv_status st = build_host_mesh(n_nodes, xyz, n_tets, tets,
-                                   c->prm.scatter == TAFV_SCATTER_COLOUR,
-                                   c->prm.cell_order == TAFV_ORDER_MORTON, &hm, &c->err);
-  if (st != TAFV_OK) return st;
   DevMesh* m = new (std::nothrow) DevMesh();
   if (!m) return fail(c, TAFV_E_OOM, "host allocation failed");
   m->nc = (int32_t)hm.nc;
@@ -462,6 +357,129 @@ tafv_status tafv_mesh_upload(tafv_ctx* c, int64_t n_nodes, const double* xyz, in
     free_mesh(m);
     return hip_fail(c, e, "mesh upload");
   }
+  *out = m;
+  return TAFV_OK;
+}
+}  // namespace tafv
+
+extern "C" {
+
+tafv_status tafv_params_default(tafv_params* p) {
+  if (!p) return TAFV_E_ARG;
+  p->gamma = 1.4;
+  p->cfl = 0.5;
+  p->newton_tol = 1e-12;
+  p->level_margin = 1e-9;
+  p->max_levels = 5;
+  p->order = 2;
+  p->precision = TAFV_FP64;
+  p->guess = TAFV_GUESS_TR;
+  p->boundary = TAFV_BC_WALL;
+  p->newton_max_iter = 50;
+  p->reclassify = 1;
+  p->scatter = TAFV_SCATTER_GATHER;
+  p->cell_order = TAFV_ORDER_CALLER;
+  p->guess_stats = 0;
+  p->guess_gate = 0.0;
+  p->batch = 0;
+  return TAFV_OK;
+}
+
+tafv_status tafv_create(int device, const tafv_params* params, void* hip_stream,
+                        tafv_ctx** out) {
+  if (!out) return fail(nullptr, TAFV_E_ARG, "out is NULL");
+  *out = nullptr;
+  if (!params) return fail(nullptr, TAFV_E_ARG, "params is NULL");
+  const tafv_params& p = *params;
+  if (!(p.gamma > 1.0) || !(p.cfl > 0.0) || !(p.newton_tol > 0.0) || p.max_levels < 1 ||
+      p.max_levels > kMaxLevels || (p.order != 1 && p.order != 2) ||
+      (p.precision != TAFV_FP64 && p.precision != TAFV_FP32_FLUX) ||
+      (p.boundary != TAFV_BC_WALL && p.boundary != TAFV_BC_TRANSMIT) || p.newton_max_iter < 1 ||
+      (p.scatter != TAFV_SCATTER_COLOUR && p.scatter != TAFV_SCATTER_GATHER) ||
+      (p.cell_order != TAFV_ORDER_CALLER && p.cell_order != TAFV_ORDER_MORTON) ||
+      !(p.level_margin >= 0.0 && p.level_margin < 0.5))
+    return fail(nullptr, TAFV_E_ARG, "invalid parameters");
+  if (p.guess != TAFV_GUESS_TR && p.guess != TAFV_GUESS_MLP)
+    return fail(nullptr, TAFV_E_ARG, "unknown guess mode");
+  if (!(p.guess_gate >= 0.0)) return fail(nullptr, TAFV_E_ARG, "negative guess gate");
+  if (p.batch != 0 && p.batch != 1) return fail(nullptr, TAFV_E_ARG, "batch must be 0 or 1");
+  if (p.batch && p.scatter != TAFV_SCATTER_GATHER)
+    return fail(nullptr, TAFV_E_ARG, "the batched form needs gather scatter");
+  if (p.guess == TAFV_GUESS_MLP && (p.gamma != 1.4 || p.scatter != TAFV_SCATTER_GATHER))
+    return fail(nullptr, TAFV_E_ARG, "the learned guess needs gamma 1.4 and gather scatter");
+  int ndev = 0;
+  hipError_t e = hipGetDeviceCount(&ndev);
+  if (e != hipSuccess || ndev == 0) return fail(nullptr, TAFV_E_DEVICE, "no HIP device");
+  if (device < 0 || device >= ndev) return fail(nullptr, TAFV_E_ARG, "device out of range");
+  e = hipSetDevice(device);
+  if (e != hipSuccess) return hip_fail(nullptr, e, "hipSetDevice");
+  tafv_ctx* c = new (std::nothrow) tafv_ctx();
+  if (!c) return fail(nullptr, TAFV_E_OOM, "host allocation failed");
+  c->device = device;
+  c->stream = (hipStream_t)hip_stream;
+  c->prm = p;
+  e = hipHostMalloc((void**)&c->hpin, 4096, hipHostMallocDefault);
+  if (e != hipSuccess) {
+    delete c;
+    return hip_fail(nullptr, e, "hipHostMalloc");
+  }
+  for (int k = 0; k < P_N; ++k) c->prof.push_back(ProfileClass{kProfNames[k]});
+  if (p.batch) {
+    c->batch = new (std::nothrow) Batch();
+    if (!c->batch) {
+      (void)hipHostFree(c->hpin);
+      delete c;
+      return fail(nullptr, TAFV_E_OOM, "host allocation failed");
+    }
+  }
+  *out = c;
+  return TAFV_OK;
+}
+
+tafv_status tafv_destroy(tafv_ctx* c) {
+  if (!c) return TAFV_E_ARG;
+  (void)hipSetDevice(c->device);
+  (void)hipStreamSynchronize(c->stream);
+  batch_free(c);
+  for (DevMesh* m : c->meshes) free_mesh(m);
+  for (auto& pe : c->pending) {
+    (void)hipEventDestroy(pe.a);
+    (void)hipEventDestroy(pe.b);
+  }
+  for (hipEvent_t e : c->event_pool) (void)hipEventDestroy(e);
+  void* bufs[] = {c->mlp_th, c->mlp_m, c->mlp_v, c->mlp_grad, c->mlp_gpart, c->mlp_lpart,
+                  c->mlp_loss, c->mlp_w, c->log_rows, c->log_count};
+  for (void* b : bufs)
+    if (b) (void)hipFree(b);
+  if (c->hpin) (void)hipHostFree(c->hpin);
+  delete c;
+  return TAFV_OK;
+}
+
+const char* tafv_last_error(const tafv_ctx* c) {
+  return c ? c->err.c_str() : g_create_err.c_str();
+}
+
+tafv_status tafv_mesh_upload(tafv_ctx* c, int64_t n_nodes, const double* xyz, int64_t n_tets,
+                             const int64_t* tets, int32_t* mesh_id) {
+  if (!c) return TAFV_E_ARG;
+  if (!xyz || !tets || !mesh_id || n_nodes < 4 || n_tets < 1)
+    return fail(c, TAFV_E_ARG, "invalid mesh arguments");
+  HIP_TRY(c, hipSetDevice(c->device));
+  HostMesh* hm = new (std::nothrow) HostMesh();
+  if (!hm) return fail(c, TAFV_E_OOM, "host allocation failed");
+  tafv_status st = build_host_mesh(n_nodes, xyz, n_tets, tets,
+                                   c->prm.scatter == TAFV_SCATTER_COLOUR,
+                                   c->prm.cell_order == TAFV_ORDER_MORTON, hm, &c->err);
+  if (st != TAFV_OK) {
+    delete hm;
+    return st;
+  }
+  if (c->prm.batch) return batch_upload(c, hm, mesh_id);  // takes hm
+  DevMesh* m = nullptr;
+  st = upload_host_mesh(c, *hm, &m);
+  delete hm;
+  if (st != TAFV_OK) return st;
   *mesh_id = (int32_t)c->meshes.size();
   c->meshes.push_back(m);
   return TAFV_OK;
@@ -499,6 +517,7 @@ tafv_status tafv_mesh_inspect(int64_t n_nodes, const double* xyz, int64_t n_tets
 }
 
 tafv_status tafv_mesh_params(tafv_ctx* c, int32_t mesh_id, int32_t max_levels) {
+  if (c && c->batch) return batch_mesh_params(c, mesh_id, max_levels);
   DevMesh* m = get_mesh(c, mesh_id);
   if (!m) return c ? fail(c, TAFV_E_ARG, "unknown mesh") : TAFV_E_ARG;
   if (max_levels < 1 || max_levels > kMaxLevels) return fail(c, TAFV_E_ARG, "max_levels out of range");
@@ -508,6 +527,7 @@ tafv_status tafv_mesh_params(tafv_ctx* c, int32_t mesh_id, int32_t max_levels) {
 }
 
 tafv_status tafv_state_init(tafv_ctx* c, int32_t mesh_id, const double* prim) {
+  if (c && c->batch) return batch_state_init(c, mesh_id, prim);
   DevMesh* m = get_mesh(c, mesh_id);
   if (!m) return c ? fail(c, TAFV_E_ARG, "unknown mesh") : TAFV_E_ARG;
   if (!prim) return fail(c, TAFV_E_ARG, "prim is NULL");
@@ -542,6 +562,14 @@ tafv_status tafv_state_init(tafv_ctx* c, int32_t mesh_id, const double* prim) {
 }
 
 tafv_status tafv_state_reset(tafv_ctx* c, int32_t mesh_id) {
+  if (c && c->batch) return batch_state_reset(c, mesh_id);
+  if (c && mesh_id == -1) {
+    for (int32_t k = 0; k < (int32_t)c->meshes.size(); ++k) {
+      tafv_status st = tafv_state_reset(c, k);
+      if (st != TAFV_OK) return st;
+    }
+    return TAFV_OK;
+  }
   DevMesh* m = get_mesh(c, mesh_id);
   if (!m) return c ? fail(c, TAFV_E_ARG, "unknown mesh") : TAFV_E_ARG;
   if (!m->has_state) return fail(c, TAFV_E_ORDER, "no state");
@@ -560,6 +588,7 @@ tafv_status tafv_state_reset(tafv_ctx* c, int32_t mesh_id) {
 tafv_status tafv_advance(tafv_ctx* c, int64_t n, tafv_stats* out) {
   if (!c) return TAFV_E_ARG;
   if (n < 0) return fail(c, TAFV_E_ARG, "negative subiteration count");
+  if (c->batch) return batch_advance(c, n, out);
   if (c->meshes.empty()) return fail(c, TAFV_E_ORDER, "no mesh uploaded");
   for (DevMesh* m : c->meshes)
     if (!m->has_state) return fail(c, TAFV_E_ORDER, "advance before state_init");
@@ -600,6 +629,7 @@ tafv_status tafv_advance(tafv_ctx* c, int64_t n, tafv_stats* out) {
 }
 
 tafv_status tafv_mesh_stats(tafv_ctx* c, int32_t mesh_id, tafv_stats* out) {
+  if (c && c->batch) return batch_mesh_stats(c, mesh_id, out);
   DevMesh* m = get_mesh(c, mesh_id);
   if (!m) return c ? fail(c, TAFV_E_ARG, "unknown mesh") : TAFV_E_ARG;
   if (!out) return fail(c, TAFV_E_ARG, "out is NULL");
@@ -611,6 +641,7 @@ tafv_status tafv_mesh_stats(tafv_ctx* c, int32_t mesh_id, tafv_stats* out) {
 }
 
 tafv_status tafv_state_read(tafv_ctx* c, int32_t mesh_id, double* cons, int8_t* levels) {
+  if (c && c->batch) return batch_state_read(c, mesh_id, cons, levels);
   DevMesh* m = get_mesh(c, mesh_id);
   if (!m) return c ? fail(c, TAFV_E_ARG, "unknown mesh") : TAFV_E_ARG;
   if (!cons) return fail(c, TAFV_E_ARG, "cons is NULL");
@@ -631,6 +662,7 @@ tafv_status tafv_state_read(tafv_ctx* c, int32_t mesh_id, double* cons, int8_t* 
 tafv_status tafv_checkpoint_read(tafv_ctx* c, int32_t mesh_id, double* cons, double* accum,
                                  int8_t* levels, int32_t* phase, int32_t* theta, double* dt_min,
                                  double* t) {
+  if (c && c->batch) return fail(c, TAFV_E_ARG, "checkpoints are not available in the batched form");
   DevMesh* m = get_mesh(c, mesh_id);
   if (!m) return c ? fail(c, TAFV_E_ARG, "unknown mesh") : TAFV_E_ARG;
   if (!cons || !accum || !levels || !phase || !theta || !dt_min || !t)
@@ -658,6 +690,7 @@ tafv_status tafv_checkpoint_read(tafv_ctx* c, int32_t mesh_id, double* cons, dou
 tafv_status tafv_checkpoint_write(tafv_ctx* c, int32_t mesh_id, const double* cons,
                                   const double* accum, const int8_t* levels, int32_t phase,
                                   int32_t theta, double dt_min, double t) {
+  if (c && c->batch) return fail(c, TAFV_E_ARG, "checkpoints are not available in the batched form");
   DevMesh* m = get_mesh(c, mesh_id);
   if (!m) return c ? fail(c, TAFV_E_ARG, "unknown mesh") : TAFV_E_ARG;
   if (!cons || !accum || !levels) return fail(c, TAFV_E_ARG, "NULL argument");
@@ -705,6 +738,7 @@ tafv_status tafv_guess_config(tafv_ctx* c, int32_t guess, double gate, int32_t s
   c->prm.guess = guess;
   c->prm.guess_gate = gate;
   c->prm.guess_stats = stats != 0;
+  if (c->batch) batch_invalidate(c);
   return TAFV_OK;
 }
 
@@ -878,6 +912,8 @@ tafv_status tafv_mlp_train(tafv_ctx* c, const float* x, const float* t, int64_t 
 tafv_status tafv_facelog_config(tafv_ctx* c, int64_t capacity, double rate, uint64_t seed) {
   if (!c) return TAFV_E_ARG;
   if (capacity < 0 || !(rate >= 0.0 && rate <= 1.0)) return fail(c, TAFV_E_ARG, "invalid log");
+  if (c->batch && capacity > 0)
+    return fail(c, TAFV_E_ARG, "face logging is not available in the batched form");
   HIP_TRY(c, hipSetDevice(c->device));
   HIP_TRY(c, hipStreamSynchronize(c->stream));
   if (c->log_rows) (void)hipFree(c->log_rows);
@@ -945,6 +981,19 @@ tafv_status tafv_profile_read(tafv_ctx* c, int32_t n, double* ms, int64_t* launc
     c->prof[k].items = 0;
   }
   return TAFV_OK;
+}
+
+tafv_status tafv_batch_config(tafv_ctx* c, int32_t graph, int32_t autotune,
+                              const char* tune_cache) {
+  if (!c) return TAFV_E_ARG;
+  if (!c->batch) return fail(c, TAFV_E_ARG, "not a batched context");
+  return batch_config(c, graph, autotune, tune_cache);
+}
+
+tafv_status tafv_batch_info(tafv_ctx* c, int32_t* info, int32_t n) {
+  if (!c) return TAFV_E_ARG;
+  if (!c->batch) return fail(c, TAFV_E_ARG, "not a batched context");
+  return batch_info(c, info, n);
 }
 
 }  // extern "C"

@@ -15,6 +15,9 @@ struct StepArgs {
 };
 
 hipError_t launch_state_init(hipStream_t s, DevMesh& m, const double* d_prim, double gamma);
+// rows [0, n) of a segment: U[i] from prim[perm[i]], R[i] = 0
+hipError_t launch_state_init_rows(hipStream_t s, int n, const int* perm, const double* d_prim,
+                                  double gamma, double* U, double* R);
 hipError_t launch_dt(hipStream_t s, DevMesh& m, const StepArgs& a);
 hipError_t launch_classify(hipStream_t s, DevMesh& m, const StepArgs& a);
 hipError_t launch_partitions(hipStream_t s, DevMesh& m);
@@ -42,6 +45,11 @@ hipError_t launch_to_caller_f64(hipStream_t s, DevMesh& m, const double* src, do
 hipError_t launch_from_caller_f64(hipStream_t s, DevMesh& m, const double* src, double* dst);
 hipError_t launch_to_caller_i8(hipStream_t s, DevMesh& m, const int8_t* src, int8_t* dst);
 hipError_t launch_from_caller_i8(hipStream_t s, DevMesh& m, const int8_t* src, int8_t* dst);
+// rows [0, n) of a segment to the caller's order: dst[perm[i]] = src[i]
+hipError_t launch_rows_to_caller_f64(hipStream_t s, int n, const int* perm, const double* src,
+                                    double* dst);
+hipError_t launch_rows_to_caller_i8(hipStream_t s, int n, const int* perm, const int8_t* src,
+                                   int8_t* dst);
 hipError_t launch_fill_u64(hipStream_t s, unsigned long long* p, unsigned long long v, int n);
 hipError_t launch_fill_f64(hipStream_t s, double* p, double v, int64_t n);
 

@@ -123,7 +123,20 @@ tafv_status build_host_mesh(int64_t n_nodes, const double* xyz, int64_t n_tets,
       r.slot = s;
     }
   }
-  std::sort(rec.begin(), rec.end(), rec_less);
+  // order by (sorted vertex triple, cell): a counting sort on the lowest
+  // vertex id, then a comparison sort inside each (small) bucket
+  {
+    std::vector<int64_t> bstart(n_nodes + 1, 0);
+    for (const FaceRec& r : rec) ++bstart[r.v[0] + 1];
+    for (int64_t v = 0; v < n_nodes; ++v) bstart[v + 1] += bstart[v];
+    std::vector<FaceRec> sorted(rec.size());
+    std::vector<int64_t> cur(bstart.begin(), bstart.end() - 1);
+    for (const FaceRec& r : rec) sorted[cur[r.v[0]]++] = r;
+    for (int64_t v = 0; v < n_nodes; ++v)
+      if (bstart[v + 1] - bstart[v] > 1)
+        std::sort(sorted.begin() + bstart[v], sorted.begin() + bstart[v + 1], rec_less);
+    rec.swap(sorted);
+  }
 
   // faces in key order: lower cell = L
   struct RawFace {
@@ -166,12 +179,26 @@ tafv_status build_host_mesh(int64_t n_nodes, const double* xyz, int64_t n_tets,
 
   // greedy colouring: faces visited by (L, R); a face takes the lowest
   // colour not yet used by another face of either cell
+  // (a stable order by (L, R): counting sort on L, then a stable insertion
+  // sort on R among the at most 4 faces of each L)
   std::vector<int32_t> order(nf);
-  std::iota(order.begin(), order.end(), 0);
-  std::stable_sort(order.begin(), order.end(), [&](int32_t x, int32_t y) {
-    if (faces[x].L != faces[y].L) return faces[x].L < faces[y].L;
-    return faces[x].R < faces[y].R;
-  });
+  {
+    std::vector<int64_t> lstart(nc + 1, 0);
+    for (int64_t f = 0; f < nf; ++f) ++lstart[faces[f].L + 1];
+    for (int64_t i = 0; i < nc; ++i) lstart[i + 1] += lstart[i];
+    std::vector<int64_t> cur(lstart.begin(), lstart.end() - 1);
+    for (int64_t f = 0; f < nf; ++f) order[cur[faces[f].L]++] = (int32_t)f;
+    for (int64_t i = 0; i < nc; ++i)
+      for (int64_t a = lstart[i] + 1; a < lstart[i + 1]; ++a) {
+        int32_t x = order[a];
+        int64_t b = a;
+        while (b > lstart[i] && faces[order[b - 1]].R > faces[x].R) {
+          order[b] = order[b - 1];
+          --b;
+        }
+        order[b] = x;
+      }
+  }
   std::vector<uint8_t> used(nc, 0);
   std::vector<int8_t> colour(nf);
   int ncol = 0;

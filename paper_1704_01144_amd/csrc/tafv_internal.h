@@ -107,6 +107,61 @@ struct DevMesh {
   tafv_stats st{};
 };
 
+// Per-mesh schedule of the batched form, resident on the device: the
+// segment of the merged arrays, the level cap, Alg. 2's schedule state and
+// the per-subiteration work counts.
+struct BatchSched {
+  int32_t c0, nc, f0, nf;             // cells [c0, c0 + nc), faces [f0, f0 + nf)
+  int32_t L, theta, phase, classified;
+  int32_t reclass, tau_s, upd, n_grad; // this subiteration: classify?, levels, work
+  int32_t n_flux, n_gather, pad0, pad1;
+  double dt_min, t;
+  unsigned long long dtbits;          // running minimum of dt (bit pattern)
+  int64_t subiterations, cell_updates, face_solves;
+  int64_t cells_per_level[kMaxLevels];
+  int32_t fstart[kMaxLevels + 1];     // face list: start of tau_f = k (global position)
+  int32_t cstart[kMaxLevels + 1];     // cell list: start of tau_g = k
+  int32_t hist[kMaxKeys];             // cells per (tau_g, tau)
+};
+
+// Launch settings of one work class of the batched kernels.
+struct LaunchSet {
+  int32_t grid = 0;  // blocks of the persistent launch
+  int32_t grab = 1;  // consecutive tiles a block takes at a time
+};
+
+struct DevMesh;
+struct HostMesh;
+
+// Batched form: the uploaded meshes merged into one set of arrays (cell,
+// face and half-face ids offset per mesh), with a schedule per mesh.
+struct Batch {
+  std::vector<HostMesh*> hosts;       // uploaded, merged at the first use
+  std::vector<int32_t> L;
+  std::vector<uint8_t> has_state;
+  bool built = false;
+  int32_t nmesh = 0;
+  DevMesh* m = nullptr;
+  BatchSched* dsched = nullptr;
+  std::vector<BatchSched> hsched;     // host copy after each call
+  // static tile prefixes [nmesh + 1]: cell tiles and face tiles of kBlock
+  // items, cell chunks and face chunks of the partitions
+  int32_t *ct = nullptr, *ft = nullptr, *cc = nullptr, *fc = nullptr;
+  int32_t n_cc = 0, n_fc = 0, n_ft = 0;
+  int32_t *cnt_f = nullptr, *cnt_c = nullptr;  // [8 * chunks] counts, then offsets
+  int32_t* tp = nullptr;              // [3][nmesh + 1] tiles: gradient, flux, cells
+  int32_t lmax = 1;
+  LaunchSet set[3];                   // gradient, flux (fixed: one tile per
+                                      // block over all face tiles), cells
+  int32_t tuned = 0;                  // 0 defaults, 1 timed here, 2 read from the cache
+  int32_t graph = 1, autotune = 1;
+  std::string cache;
+  hipStream_t cap = nullptr;          // capture stream
+  std::vector<std::pair<int64_t, hipGraphExec_t>> execs;
+  int64_t exec_key = -1;
+  tafv_stats last{};                  // cumulative slot counters at the last call
+};
+
 struct ProfileClass {
   const char* name;
   double ms = 0.0;
@@ -142,4 +197,61 @@ struct tafv_ctx {
   int64_t log_cap = 0;
   double log_rate = 0.0;
   uint64_t log_seed = 0;
+  // batched form (params.batch = 1)
+  tafv::Batch* batch = nullptr;
 };
+
+namespace tafv {
+
+// shared by the C-ABI and the batched driver (capi.hip)
+tafv_status set_error(tafv_ctx* c, tafv_status st, const std::string& msg);
+tafv_status hip_error(tafv_ctx* c, hipError_t e, const char* what);
+tafv_status upload_host_mesh(tafv_ctx* c, const HostMesh& hm, DevMesh** out);
+void free_dev_mesh(DevMesh* m);
+// sums the slot counters of m into st (newton ... guess_used, wall impulse)
+tafv_status read_slot_counters(tafv_ctx* c, DevMesh& m, tafv_stats* st);
+
+// per-kernel-class timing with HIP events on the context stream
+enum { P_CLASSIFY = 0, P_GRAD = 1, P_FLUX = 2, P_UPDATE = 3, P_GATHER = 4, P_N = 5 };
+struct ProfScope {
+  tafv_ctx* c;
+  int cls;
+  int64_t items;
+  hipEvent_t a = nullptr, b = nullptr;
+  ProfScope(tafv_ctx* c_, int cls_, int64_t items_) : c(c_), cls(cls_), items(items_) {
+    if (!c || !c->profile) return;
+    a = take();
+    b = take();
+    (void)hipEventRecord(a, c->stream);
+  }
+  ~ProfScope() {
+    if (!c || !c->profile) return;
+    (void)hipEventRecord(b, c->stream);
+    c->pending.push_back({a, b, cls, items});
+  }
+  hipEvent_t take() {
+    if (!c->event_pool.empty()) {
+      hipEvent_t e = c->event_pool.back();
+      c->event_pool.pop_back();
+      return e;
+    }
+    hipEvent_t e = nullptr;
+    (void)hipEventCreate(&e);
+    return e;
+  }
+};
+
+// batched driver (batch.hip)
+tafv_status batch_upload(tafv_ctx* c, HostMesh* hm, int32_t* mesh_id);
+tafv_status batch_mesh_params(tafv_ctx* c, int32_t mesh_id, int32_t max_levels);
+tafv_status batch_state_init(tafv_ctx* c, int32_t mesh_id, const double* prim);
+tafv_status batch_state_reset(tafv_ctx* c, int32_t mesh_id);
+tafv_status batch_advance(tafv_ctx* c, int64_t n, tafv_stats* out);
+tafv_status batch_mesh_stats(tafv_ctx* c, int32_t mesh_id, tafv_stats* out);
+tafv_status batch_state_read(tafv_ctx* c, int32_t mesh_id, double* cons, int8_t* levels);
+tafv_status batch_config(tafv_ctx* c, int32_t graph, int32_t autotune, const char* cache);
+tafv_status batch_info(tafv_ctx* c, int32_t* info, int32_t n);
+void batch_invalidate(tafv_ctx* c);
+void batch_free(tafv_ctx* c);
+
+}  // namespace tafv

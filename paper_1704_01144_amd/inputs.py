@@ -67,6 +67,13 @@ def kuhn_tet_mesh(xs, ys, zs):
     return nodes, tets
 
 
+def graded_box_mesh(nx, ny, nz, grading):
+    """nx x ny x nz hexes on the unit cube, each axis graded toward 0 with
+    last/first edge ratio `grading`."""
+    return kuhn_tet_mesh(graded_coords(nx, grading), graded_coords(ny, grading),
+                         graded_coords(nz, grading))
+
+
 def graded_cube_mesh(n, grading):
     """n^3 hexes on the unit cube, graded toward the origin in x, y and z."""
     x = graded_coords(n, grading)
@@ -152,3 +159,29 @@ def config_scale(n=64, seed=0):
     return dict(nodes=nodes, tets=tets,
                 prim=blast_state(nodes, tets, centre=blast_centre(seed)),
                 order=2, max_levels=5, units=32)
+
+
+def batch_case(m, seed0=1000, size_range=(5000, 400000), grading_range=(2.0, 32.0),
+               levels=(1, 6)):
+    """Mesh m of the batched workload, from default_rng(seed0 + m): a target
+    size log-uniform in size_range, grading log-uniform in grading_range, a
+    level cap uniform over levels, a blast centre uniform in [0.3, 0.7]^3;
+    n = round(cbrt(size / 6)) hexes along x and y and
+    max(1, round(size / (6 n^2))) along z.  Returns a dict with nodes, tets,
+    prim, max_levels, grading and the seed."""
+    g = np.random.default_rng(seed0 + m)
+    size = float(np.exp(g.uniform(np.log(size_range[0]), np.log(size_range[1]))))
+    grading = float(np.exp(g.uniform(np.log(grading_range[0]), np.log(grading_range[1]))))
+    L = int(g.integers(levels[0], levels[1] + 1))
+    centre = g.uniform(0.3, 0.7, 3)
+    n = max(1, int(round((size / 6.0) ** (1.0 / 3.0))))
+    nz = max(1, int(round(size / (6.0 * n * n))))
+    nodes, tets = graded_box_mesh(n, n, nz, grading)
+    return dict(nodes=nodes, tets=tets, prim=blast_state(nodes, tets, centre=centre),
+                max_levels=L, grading=grading, seed=seed0 + m, dims=(n, n, nz))
+
+
+def config_batch(count=128, seed0=1000, **kw):
+    """The batched workload: `count` meshes from batch_case(m) (128 meshes:
+    about 11 million cells), FP32 flux, 16 dt_min units."""
+    return [batch_case(m, seed0, **kw) for m in range(count)]

@@ -34,7 +34,8 @@ class tafv_params(C.Structure):
                 ("precision", C.c_int32), ("guess", C.c_int32), ("boundary", C.c_int32),
                 ("newton_max_iter", C.c_int32), ("reclassify", C.c_int32),
                 ("scatter", C.c_int32), ("cell_order", C.c_int32),
-                ("guess_stats", C.c_int32), ("guess_gate", C.c_double)]
+                ("guess_stats", C.c_int32), ("guess_gate", C.c_double),
+                ("batch", C.c_int32)]
 
 
 class tafv_stats(C.Structure):
@@ -88,6 +89,8 @@ def _load():
         "tafv_facelog_config": [P, C.c_int64, C.c_double, C.c_uint64],
         "tafv_facelog_read": [P, fp, C.c_int64, i64p],
         "tafv_profile_read": [P, C.c_int32, dp, i64p, i64p, C.POINTER(C.c_char_p), i32p],
+        "tafv_batch_config": [P, C.c_int32, C.c_int32, C.c_char_p],
+        "tafv_batch_info": [P, i32p, C.c_int32],
     }
     for name, args in sig.items():
         fn = getattr(L, name)
@@ -106,7 +109,7 @@ EXPORTS = ["tafv_params_default", "tafv_create", "tafv_destroy", "tafv_last_erro
            "tafv_mesh_stats", "tafv_state_read", "tafv_checkpoint_read", "tafv_checkpoint_write",
            "tafv_profile_enable", "tafv_profile_read", "tafv_guess_config", "tafv_mlp_set", "tafv_mlp_get",
            "tafv_mlp_forward", "tafv_mlp_grad", "tafv_mlp_train", "tafv_facelog_config",
-           "tafv_facelog_read"]
+           "tafv_facelog_read", "tafv_batch_config", "tafv_batch_info"]
 MLP_PARAMS = 1313
 
 
@@ -300,6 +303,21 @@ def tafv_profile_read(ctx):
                                  C.byref(ncls)), ctx)
     return {names[k].decode(): dict(ms=float(ms[k]), launches=int(launches[k]),
                                     items=int(items[k])) for k in range(ncls.value)}
+
+
+def tafv_batch_config(ctx, graph=1, autotune=1, tune_cache=None):
+    path = tune_cache.encode() if tune_cache else None
+    _check(lib.tafv_batch_config(ctx, int(graph), int(autotune), path), ctx)
+
+
+def tafv_batch_info(ctx):
+    """Launch settings of the batched kernels: blocks and tiles per grab of
+    the gradient, flux and cell kernels, and where they came from."""
+    a = (C.c_int32 * 7)()
+    _check(lib.tafv_batch_info(ctx, a, 7), ctx)
+    v = list(a)
+    return dict(grad=(v[0], v[1]), flux=(v[2], v[3]), cells=(v[4], v[5]),
+                source={0: "default", 1: "tuned", 2: "cache"}[v[6]])
 
 
 class Solver:
