@@ -279,6 +279,8 @@ def main():
     ap.add_argument("--no-learned", action="store_true")
     ap.add_argument("--scatter", type=int, default=1, help="0 colour, 1 gather")
     ap.add_argument("--no-batch", action="store_true", help="skip the 128-mesh batched form")
+    ap.add_argument("--batch-only", action="store_true",
+                    help="only the batched form, FP64 and FP32 with the two-rarefaction start")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run the 1 GiB copy used to scale the traffic counters")
     args = ap.parse_args()
@@ -297,6 +299,14 @@ def main():
     from paper_1704_01144_amd import tafv as T
 
     torch.cuda.set_device(0)
+    if args.batch_only:
+        cases = I.config_batch(128)
+        for prec, name in ((T.FP64, "fp64"), (T.FP32_FLUX, "fp32")):
+            r = run_batch(T, torch, cases, args.steps, args.warmup, prec)
+            v = r["cell_updates"] / (r["ms"] * 1e-3)
+            log(f"batched {name}: {v / 1e9:.3f} G cell-updates/s, {r['ms'] / args.steps:.2f} ms "
+                f"per step, launch {r['info']}")
+        return
     cfg = I.config_scale(args.n, 0)
     log(f"workload: {len(cfg['tets'])} cells, order {cfg['order']}, L {cfg['max_levels']}, "
         f"{UNITS} units, steps {args.steps}, warmup {args.warmup}")

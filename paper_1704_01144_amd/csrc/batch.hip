@@ -41,6 +41,7 @@ namespace {
 constexpr int kChunk = 1024;        // partition chunk: 16 waves of 64
 constexpr int kStaticBlocksPerCU = 4;
 constexpr int kGraphSpan = 32;      // subiterations per captured graph
+constexpr int kMaxBatchMeshes = 8192;  // prefix arrays staged in LDS (32 KB)
 
 // the mesh whose tiles hold tile t: tp[m] <= t < tp[m + 1] (tp[M] > t)
 __device__ inline int find_mesh(const int32_t* __restrict__ tp, int M, int t) {
@@ -59,21 +60,62 @@ __device__ inline int find_mesh(const int32_t* __restrict__ tp, int M, int t) {
   for (int base_ = xcd_block() * (grab); base_ < (total); base_ += gridDim.x * (grab)) \
     for (int t = base_, tend_ = min(base_ + (grab), (total)); t < tend_; ++t)
 
-// ---- iteration start ----------------------------------------------------
+// The prefix array of a launch (M + 1 ints) is staged in LDS, where the
+// per-tile binary search over it costs little (dynamic shared memory of
+// (M + 1) * 4 bytes at launch).
+#define STAGE_PREFIX(gp)                                                           \
+  extern __shared__ int32_t s_pre[];                                             \
+  for (int k_ = threadIdx.x; k_ <= M; k_ += blockDim.x) s_pre[k_] = (gp)[k_];    \
+  __syncthreads()
 
-__global__ void k_b_begin(BatchSched* S, int M, int reclassify) {
-  for (int m = threadIdx.x; m < M; m += blockDim.x) {
-    BatchSched& s = S[m];
-    int rc = s.phase == 0 && (reclassify || !s.classified);
-    s.reclass = rc;
-    if (rc) {
-      s.dtbits = 0x7ff0000000000000ull;  // +inf
-      for (int k = 0; k < kMaxKeys; ++k) s.hist[k] = 0;
+// ---- iteration start ----------------------------------------------------
+// Meshes at an iteration start (phase 0) reclassify.  The tiles of the
+// reclassification kernels cover those meshes only: rp[kind][M + 1] are
+// prefix sums over the marked meshes of their static tile counts (kind 0
+// cell tiles, 1 face tiles, 2 cell chunks, 3 face chunks).
+
+__global__ __launch_bounds__(1024) void k_b_begin(BatchSched* S, int M, int reclassify,
+                                                  const int32_t* __restrict__ ct,
+                                                  const int32_t* __restrict__ ft,
+                                                  const int32_t* __restrict__ cc,
+                                                  const int32_t* __restrict__ fc,
+                                                  int32_t* __restrict__ rp) {
+  __shared__ int sh[4][1024];
+  const int tid = threadIdx.x;
+  const int32_t* st[4] = {ct, ft, cc, fc};
+  int carry[4] = {0, 0, 0, 0};
+  for (int b = 0; b < M; b += blockDim.x) {
+    const int m = b + tid;
+    int n[4] = {0, 0, 0, 0};
+    if (m < M) {
+      BatchSched& s = S[m];
+      int rc = s.phase == 0 && (reclassify || !s.classified);
+      s.reclass = rc;
+      if (rc) {
+        s.dtbits = 0x7ff0000000000000ull;  // +inf
+        for (int k = 0; k < kMaxKeys; ++k) s.hist[k] = 0;
+        for (int w = 0; w < 4; ++w) n[w] = st[w][m + 1] - st[w][m];
+      }
     }
+    for (int w = 0; w < 4; ++w) sh[w][tid] = n[w];
+    __syncthreads();
+    for (int off = 1; off < 1024; off <<= 1) {
+      int y[4];
+      for (int w = 0; w < 4; ++w) y[w] = tid >= off ? sh[w][tid - off] : 0;
+      __syncthreads();
+      for (int w = 0; w < 4; ++w) sh[w][tid] += y[w];
+      __syncthreads();
+    }
+    for (int w = 0; w < 4; ++w) {
+      if (m < M) rp[w * (M + 1) + m] = carry[w] + sh[w][tid] - n[w];
+      carry[w] += sh[w][1023];
+    }
+    __syncthreads();
   }
+  if (tid < 4) rp[tid * (M + 1) + M] = carry[tid];
 }
 
-__global__ __launch_bounds__(kBlock) void k_b_dt(const int32_t* __restrict__ ct, BatchSched* S,
+__global__ __launch_bounds__(kBlock) void k_b_dt(const int32_t* __restrict__ rp, BatchSched* S,
                                                  int M, int NC, int NF,
                                                  const double* __restrict__ U,
                                                  const double* __restrict__ vol,
@@ -81,12 +123,12 @@ __global__ __launch_bounds__(kBlock) void k_b_dt(const int32_t* __restrict__ ct,
                                                  const double* __restrict__ fA, double gamma,
                                                  double cfl, double* __restrict__ dt,
                                                  unsigned long long* flag) {
+  STAGE_PREFIX(rp);
   __shared__ double smin[kBlock / 64];
-  const int total = ct[M];
+  const int total = s_pre[M];
   TILE_LOOP(total, 1) {
-    int m = find_mesh(ct, M, t);
-    if (!S[m].reclass) continue;
-    int i = S[m].c0 + (t - ct[m]) * kBlock + threadIdx.x;
+    int m = find_mesh(s_pre, M, t);
+    int i = S[m].c0 + (t - s_pre[m]) * kBlock + threadIdx.x;
     double dti = INFINITY;
     if (i < S[m].c0 + S[m].nc) {
       bool bad = false;
@@ -105,49 +147,51 @@ __global__ __launch_bounds__(kBlock) void k_b_dt(const int32_t* __restrict__ ct,
   }
 }
 
-__global__ __launch_bounds__(kBlock) void k_b_classify(const int32_t* __restrict__ ct,
+__global__ __launch_bounds__(kBlock) void k_b_classify(const int32_t* __restrict__ rp,
                                                        const BatchSched* S, int M,
                                                        const double* __restrict__ dt,
                                                        double margin, int8_t* __restrict__ lev) {
-  const int total = ct[M];
+  STAGE_PREFIX(rp);
+  const int total = s_pre[M];
   TILE_LOOP(total, 1) {
-    int m = find_mesh(ct, M, t);
-    if (!S[m].reclass) continue;
-    int i = S[m].c0 + (t - ct[m]) * kBlock + threadIdx.x;
+    int m = find_mesh(s_pre, M, t);
+    int i = S[m].c0 + (t - s_pre[m]) * kBlock + threadIdx.x;
     if (i < S[m].c0 + S[m].nc)
       lev[i] = classify_item(dt[i], __longlong_as_double((long long)S[m].dtbits), margin, S[m].L);
   }
 }
 
-__global__ __launch_bounds__(kBlock) void k_b_sweep(const int32_t* __restrict__ ct,
-                                                    const BatchSched* S, int M, int NC,
+// sweep k of the even count S: meshes whose own L - 1 sweeps are done copy
+// their levels across instead (further sweeps would change nothing)
+__global__ __launch_bounds__(kBlock) void k_b_sweep(const int32_t* __restrict__ rp,
+                                                    const BatchSched* S, int M, int NC, int k,
                                                     const int* __restrict__ nb,
                                                     const int8_t* __restrict__ src,
                                                     int8_t* __restrict__ dst) {
-  const int total = ct[M];
+  STAGE_PREFIX(rp);
+  const int total = s_pre[M];
   TILE_LOOP(total, 1) {
-    int m = find_mesh(ct, M, t);
-    if (!S[m].reclass) continue;
-    int i = S[m].c0 + (t - ct[m]) * kBlock + threadIdx.x;
-    if (i < S[m].c0 + S[m].nc) dst[i] = sweep_item(i, NC, nb, src);
+    int m = find_mesh(s_pre, M, t);
+    int i = S[m].c0 + (t - s_pre[m]) * kBlock + threadIdx.x;
+    if (i < S[m].c0 + S[m].nc) dst[i] = k < S[m].L - 1 ? sweep_item(i, NC, nb, src) : src[i];
   }
 }
 
-__global__ __launch_bounds__(kBlock) void k_b_cell_keys(const int32_t* __restrict__ ct,
+__global__ __launch_bounds__(kBlock) void k_b_cell_keys(const int32_t* __restrict__ rp,
                                                         BatchSched* S, int M, int NC,
                                                         const int* __restrict__ nb,
                                                         const int8_t* __restrict__ lev,
                                                         int8_t* __restrict__ ckey,
                                                         uint32_t* __restrict__ fpack) {
+  STAGE_PREFIX(rp);
   __shared__ int h[kMaxKeys];
-  const int total = ct[M];
+  const int total = s_pre[M];
   TILE_LOOP(total, 1) {
-    int m = find_mesh(ct, M, t);
-    if (!S[m].reclass) continue;
+    int m = find_mesh(s_pre, M, t);
     __syncthreads();
     for (int k = threadIdx.x; k < kMaxKeys; k += blockDim.x) h[k] = 0;
     __syncthreads();
-    int i = S[m].c0 + (t - ct[m]) * kBlock + threadIdx.x;
+    int i = S[m].c0 + (t - s_pre[m]) * kBlock + threadIdx.x;
     if (i < S[m].c0 + S[m].nc) atomicAdd(&h[cell_key_item(i, NC, nb, lev, ckey, fpack)], 1);
     __syncthreads();
     for (int k = threadIdx.x; k < kMaxKeys; k += blockDim.x)
@@ -155,38 +199,41 @@ __global__ __launch_bounds__(kBlock) void k_b_cell_keys(const int32_t* __restric
   }
 }
 
-__global__ __launch_bounds__(kBlock) void k_b_face_keys(const int32_t* __restrict__ ft,
+__global__ __launch_bounds__(kBlock) void k_b_face_keys(const int32_t* __restrict__ rp,
                                                         const BatchSched* S, int M,
                                                         const int* __restrict__ fhL,
                                                         const int* __restrict__ fhR,
                                                         const int8_t* __restrict__ lev,
                                                         int8_t* __restrict__ fkey) {
-  const int total = ft[M];
+  STAGE_PREFIX(rp);
+  const int total = s_pre[M];
   TILE_LOOP(total, 1) {
-    int m = find_mesh(ft, M, t);
-    if (!S[m].reclass) continue;
-    int f = S[m].f0 + (t - ft[m]) * kBlock + threadIdx.x;
+    int m = find_mesh(s_pre, M, t);
+    int f = S[m].f0 + (t - s_pre[m]) * kBlock + threadIdx.x;
     if (f < S[m].f0 + S[m].nf) fkey[f] = face_key_item(f, fhL, fhR, nullptr, lev, 0);
   }
 }
 
 // ---- per-mesh stable partitions by level ----------------------------------
 // Chunk j of mesh m covers segment items [j kChunk, (j + 1) kChunk); the
-// count of key k in that chunk sits at 8 cp[m] + k nch + j (nch chunks in
-// the mesh), so one exclusive scan per mesh, started at the segment's first
-// position, gives every (key, chunk) its first slot in the merged list.
+// count of key k in that chunk sits at 8 cp[m] + k nch + j (cp: the static
+// chunk prefix, nch chunks in the mesh), so one exclusive scan per mesh,
+// started at the segment's first position, gives every (key, chunk) its
+// first slot in the merged list.  rp: the chunk prefix over the meshes that
+// reclassify.
 
 template <typename Key>
-__global__ __launch_bounds__(64) void k_b_part_count(const int32_t* __restrict__ cp,
+__global__ __launch_bounds__(64) void k_b_part_count(const int32_t* __restrict__ rp,
+                                                     const int32_t* __restrict__ cp,
                                                      const BatchSched* S, int M, int faces,
                                                      Key key, int32_t* __restrict__ counts) {
+  STAGE_PREFIX(rp);
   __shared__ int cnt[kMaxLevels];
   const int lane = threadIdx.x;
-  const int total = cp[M];
+  const int total = s_pre[M];
   for (int t = xcd_block(); t < total; t += gridDim.x) {
-    int m = find_mesh(cp, M, t);
-    if (!S[m].reclass) continue;
-    int j = t - cp[m], nch = cp[m + 1] - cp[m];
+    int m = find_mesh(s_pre, M, t);
+    int j = t - s_pre[m], nch = cp[m + 1] - cp[m];
     int b0 = faces ? S[m].f0 : S[m].c0;
     int end = b0 + (faces ? S[m].nf : S[m].nc);
     __syncthreads();
@@ -247,19 +294,20 @@ __global__ __launch_bounds__(256) void k_b_part_scan(const int32_t* __restrict__
 }
 
 template <typename Key, typename Writer>
-__global__ __launch_bounds__(64) void k_b_part_scatter(const int32_t* __restrict__ cp,
+__global__ __launch_bounds__(64) void k_b_part_scatter(const int32_t* __restrict__ rp,
+                                                       const int32_t* __restrict__ cp,
                                                        const BatchSched* S, int M, int faces,
                                                        Key key,
                                                        const int32_t* __restrict__ offs,
                                                        Writer out) {
+  STAGE_PREFIX(rp);
   __shared__ int base[kMaxLevels];
   const int lane = threadIdx.x;
   const unsigned long long lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-  const int total = cp[M];
+  const int total = s_pre[M];
   for (int t = xcd_block(); t < total; t += gridDim.x) {
-    int m = find_mesh(cp, M, t);
-    if (!S[m].reclass) continue;
-    int j = t - cp[m], nch = cp[m + 1] - cp[m];
+    int m = find_mesh(s_pre, M, t);
+    int j = t - s_pre[m], nch = cp[m + 1] - cp[m];
     int b0 = faces ? S[m].f0 : S[m].c0;
     int end = b0 + (faces ? S[m].nf : S[m].nc);
     __syncthreads();
@@ -369,10 +417,11 @@ template <typename T>
 __global__ __launch_bounds__(kBlock) void k_b_grad(const int32_t* __restrict__ tp,
                                                    const BatchSched* S, int M, int grab,
                                                    GradArgs<T> a) {
-  const int total = tp[M];
+  STAGE_PREFIX(tp);
+  const int total = s_pre[M];
   TILE_LOOP(total, grab) {
-    int m = find_mesh(tp, M, t);
-    int j = (t - tp[m]) * kBlock + threadIdx.x;
+    int m = find_mesh(s_pre, M, t);
+    int j = (t - s_pre[m]) * kBlock + threadIdx.x;
     if (j < S[m].n_grad) grad_item<T>(a, a.list[S[m].c0 + j]);
   }
 }
@@ -423,10 +472,11 @@ __global__ __launch_bounds__(kBlock) void k_b_gather(const int32_t* __restrict__
                                                      double* __restrict__ U,
                                                      double* __restrict__ R,
                                                      unsigned long long* flag) {
-  const int total = tp[M];
+  STAGE_PREFIX(tp);
+  const int total = s_pre[M];
   TILE_LOOP(total, grab) {
-    int m = find_mesh(tp, M, t);
-    int j = (t - tp[m]) * kBlock + threadIdx.x;
+    int m = find_mesh(s_pre, M, t);
+    int j = (t - s_pre[m]) * kBlock + threadIdx.x;
     if (j < S[m].n_gather)
       if (!cell_gather_item(list[S[m].c0 + j], NC, fpack, c2f, Q, vol, U, R, S[m].tau_s,
                             S[m].upd))
@@ -557,6 +607,7 @@ tafv_status build(tafv_ctx* c) {
   merge_hosts(B.hosts, merged, c0, f0);
   if (merged.nc > INT32_MAX / 8 || merged.nf > INT32_MAX / 8)
     return set_error(c, TAFV_E_ARG, "batch too large for 32-bit ids");
+  if (M > kMaxBatchMeshes) return set_error(c, TAFV_E_ARG, "too many meshes in one batch");
   DevMesh* dm = nullptr;
   tafv_status st = upload_host_mesh(c, merged, &dm);
   if (st != TAFV_OK) return st;
@@ -590,6 +641,7 @@ tafv_status build(tafv_ctx* c) {
   chk(hipMalloc(&B.dsched, sizeof(BatchSched) * M));
   for (int32_t** p : {&B.ct, &B.ft, &B.cc, &B.fc}) chk(hipMalloc(p, sizeof(int32_t) * (M + 1)));
   chk(hipMalloc(&B.tp, sizeof(int32_t) * 3 * (M + 1)));
+  chk(hipMalloc(&B.rp, sizeof(int32_t) * 4 * (M + 1)));
   chk(hipMalloc(&B.cnt_c, sizeof(int32_t) * kMaxLevels * std::max(B.n_cc, 1)));
   chk(hipMalloc(&B.cnt_f, sizeof(int32_t) * kMaxLevels * std::max(B.n_fc, 1)));
   if (e != hipSuccess) return hip_error(c, e, "batch allocation");
@@ -653,37 +705,41 @@ hipError_t run_reclass(tafv_ctx* c, hipStream_t s) {
   Batch& B = *c->batch;
   DevMesh& m = *B.m;
   const int M = B.nmesh, G = kStaticBlocksPerCU * cu_count(c);
+  const size_t lds = sizeof(int32_t) * (M + 1);
+  const int32_t *rc = B.rp, *rf = B.rp + (M + 1), *rcc = B.rp + 2 * (M + 1),
+                *rfc = B.rp + 3 * (M + 1);
   unsigned long long* flag = m.dscal + 2;
-  hipLaunchKernelGGL(k_b_begin, dim3(1), dim3(1024), 0, s, B.dsched, M, c->prm.reclassify);
-  hipLaunchKernelGGL(k_b_dt, dim3(G), dim3(kBlock), 0, s, B.ct, B.dsched, M, m.nc, m.nf, m.U,
+  hipLaunchKernelGGL(k_b_begin, dim3(1), dim3(1024), 0, s, B.dsched, M, c->prm.reclassify, B.ct,
+                     B.ft, B.cc, B.fc, B.rp);
+  hipLaunchKernelGGL(k_b_dt, dim3(G), dim3(kBlock), lds, s, rc, B.dsched, M, m.nc, m.nf, m.U,
                      m.vol, m.c2f, m.fA, c->prm.gamma, c->prm.cfl, m.dt, flag);
-  hipLaunchKernelGGL(k_b_classify, dim3(G), dim3(kBlock), 0, s, B.ct, B.dsched, M, m.dt,
+  hipLaunchKernelGGL(k_b_classify, dim3(G), dim3(kBlock), lds, s, rc, B.dsched, M, m.dt,
                      c->prm.level_margin, m.lev);
   // lowering sweeps: an even count >= lmax - 1 leaves the result in lev
-  // (sweeps past the fixed point change nothing)
   int sweeps = B.lmax - 1;
   sweeps += sweeps & 1;
   for (int k = 0; k < sweeps; ++k) {
     const int8_t* src = (k & 1) ? m.lev2 : m.lev;
     int8_t* dst = (k & 1) ? m.lev : m.lev2;
-    hipLaunchKernelGGL(k_b_sweep, dim3(G), dim3(kBlock), 0, s, B.ct, B.dsched, M, m.nc, m.nb_,
-                       src, dst);
+    hipLaunchKernelGGL(k_b_sweep, dim3(G), dim3(kBlock), lds, s, rc, B.dsched, M, m.nc, k,
+                       m.nb_, src, dst);
   }
-  hipLaunchKernelGGL(k_b_cell_keys, dim3(G), dim3(kBlock), 0, s, B.ct, B.dsched, M, m.nc, m.nb_,
+  hipLaunchKernelGGL(k_b_cell_keys, dim3(G), dim3(kBlock), lds, s, rc, B.dsched, M, m.nc, m.nb_,
                      m.lev, m.ckey, m.fpack);
-  hipLaunchKernelGGL(k_b_face_keys, dim3(G), dim3(kBlock), 0, s, B.ft, B.dsched, M, m.fhL, m.fhR,
+  hipLaunchKernelGGL(k_b_face_keys, dim3(G), dim3(kBlock), lds, s, rf, B.dsched, M, m.fhL, m.fhR,
                      m.lev, m.fkey);
   const int PG = 4 * G;  // 64-thread blocks
-  hipLaunchKernelGGL(k_b_part_count<ByteKey>, dim3(PG), dim3(64), 0, s, B.fc, B.dsched, M, 1,
-                     ByteKey{m.fkey}, B.cnt_f);
-  hipLaunchKernelGGL(k_b_part_count<ByteKey>, dim3(PG), dim3(64), 0, s, B.cc, B.dsched, M, 0,
-                     ByteKey{m.ckey}, B.cnt_c);
+  hipLaunchKernelGGL(k_b_part_count<ByteKey>, dim3(PG), dim3(64), lds, s, rfc, B.fc, B.dsched, M,
+                     1, ByteKey{m.fkey}, B.cnt_f);
+  hipLaunchKernelGGL(k_b_part_count<ByteKey>, dim3(PG), dim3(64), lds, s, rcc, B.cc, B.dsched, M,
+                     0, ByteKey{m.ckey}, B.cnt_c);
   hipLaunchKernelGGL(k_b_part_scan, dim3(M), dim3(256), 0, s, B.fc, B.dsched, M, 1, B.cnt_f);
   hipLaunchKernelGGL(k_b_part_scan, dim3(M), dim3(256), 0, s, B.cc, B.dsched, M, 0, B.cnt_c);
-  hipLaunchKernelGGL((k_b_part_scatter<ByteKey, FaceWriter>), dim3(PG), dim3(64), 0, s, B.fc,
-                     B.dsched, M, 1, ByteKey{m.fkey}, B.cnt_f, FaceWriter{m.frec, m.fhL, m.fhR});
-  hipLaunchKernelGGL((k_b_part_scatter<ByteKey, IndexWriter>), dim3(PG), dim3(64), 0, s, B.cc,
-                     B.dsched, M, 0, ByteKey{m.ckey}, B.cnt_c, IndexWriter{m.pc.list});
+  hipLaunchKernelGGL((k_b_part_scatter<ByteKey, FaceWriter>), dim3(PG), dim3(64), lds, s, rfc,
+                     B.fc, B.dsched, M, 1, ByteKey{m.fkey}, B.cnt_f,
+                     FaceWriter{m.frec, m.fhL, m.fhR});
+  hipLaunchKernelGGL((k_b_part_scatter<ByteKey, IndexWriter>), dim3(PG), dim3(64), lds, s, rcc,
+                     B.cc, B.dsched, M, 0, ByteKey{m.ckey}, B.cnt_c, IndexWriter{m.pc.list});
   hipLaunchKernelGGL(k_b_sched, dim3(1), dim3(1024), 0, s, B.dsched, M, c->prm.order, flag, B.tp);
   return hipGetLastError();
 }
@@ -697,13 +753,13 @@ hipError_t run_grad(tafv_ctx* c, hipStream_t s, const LaunchSet& ls) {
   if (c->prm.precision == TAFV_FP32_FLUX) {
     GradArgs<float> g{m.pc.list, 0, m.nc, m.nf, m.U, m.nb_, m.lsq32, m.rf32, m.fA, (float*)m.Wf,
                       gm1, c->prm.boundary};
-    hipLaunchKernelGGL(k_b_grad<float>, dim3(ls.grid), dim3(kBlock), 0, s, B.tp, B.dsched, M,
-                       ls.grab, g);
+    hipLaunchKernelGGL(k_b_grad<float>, dim3(ls.grid), dim3(kBlock), sizeof(int32_t) * (M + 1), s,
+                       B.tp, B.dsched, M, ls.grab, g);
   } else {
     GradArgs<double> g{m.pc.list, 0, m.nc, m.nf, m.U, m.nb_, m.lsq, m.rf, m.fA, (double*)m.Wf,
                        gm1, c->prm.boundary};
-    hipLaunchKernelGGL(k_b_grad<double>, dim3(ls.grid), dim3(kBlock), 0, s, B.tp, B.dsched, M,
-                       ls.grab, g);
+    hipLaunchKernelGGL(k_b_grad<double>, dim3(ls.grid), dim3(kBlock), sizeof(int32_t) * (M + 1),
+                       s, B.tp, B.dsched, M, ls.grab, g);
   }
   return hipGetLastError();
 }
@@ -761,7 +817,8 @@ hipError_t run_gather(tafv_ctx* c, hipStream_t s, const LaunchSet& ls, const Ptr
   Batch& B = *c->batch;
   DevMesh& m = *B.m;
   const int M = B.nmesh;
-  hipLaunchKernelGGL(k_b_gather, dim3(ls.grid), dim3(kBlock), 0, s, B.tp + 2 * (M + 1), B.dsched,
+  hipLaunchKernelGGL(k_b_gather, dim3(ls.grid), dim3(kBlock), sizeof(int32_t) * (M + 1), s,
+                     B.tp + 2 * (M + 1), B.dsched,
                      M, ls.grab, m.nc, m.pc.list, m.fpack, m.c2f, m.Q, m.vol, p.U, p.R,
                      m.dscal + 2);
   return hipGetLastError();
@@ -1237,7 +1294,7 @@ void batch_free(tafv_ctx* c) {
   Batch& B = *c->batch;
   drop_graphs(B);
   for (HostMesh* h : B.hosts) delete h;
-  void* ptrs[] = {B.dsched, B.ct, B.ft, B.cc, B.fc, B.cnt_f, B.cnt_c, B.tp};
+  void* ptrs[] = {B.dsched, B.ct, B.ft, B.cc, B.fc, B.cnt_f, B.cnt_c, B.tp, B.rp};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   if (B.m) free_dev_mesh(B.m);
