@@ -293,7 +293,8 @@ tafv_status tafv_facelog_read(tafv_ctx* ctx, float* rows, int64_t cap, int64_t* 
  * per length) and replays them on the context stream; graph = 0 launches
  * the kernels directly (per-kernel timing works only then).
  * autotune = 1 times candidate launch widths (persistent blocks per CU and
- * tiles taken per grab) of the gradient and cell kernels on the first
+ * tiles taken per grab, or one tile per block over all cell tiles) of the
+ * gradient and cell kernels on the first
  * subiteration of the first advance (the cell kernel on scratch copies of
  * the state) and keeps the fastest; the flux kernel takes one tile per
  * block over the static count of face tiles; tune_cache (NULL: none) names a
@@ -306,8 +307,9 @@ tafv_status tafv_batch_config(tafv_ctx* ctx, int32_t graph, int32_t autotune,
                               const char* tune_cache);
 
 /* Launch settings in use (n >= 7): info[0..5] = blocks and tiles per grab
- * of the gradient, flux and cell kernels; info[6] = 0 defaults, 1 timed
- * by the autotuner, 2 read from the cache file. */
+ * of the gradient, flux and cell kernels (tiles per grab 0: one tile per
+ * block); info[6] = 0 defaults, 1 timed by the autotuner, 2 read from the
+ * cache file. */
 tafv_status tafv_batch_info(tafv_ctx* ctx, int32_t* info, int32_t n);
 
 /* Per-kernel timing: when enabled, tafv_advance() brackets every launch of

@@ -413,15 +413,27 @@ __global__ __launch_bounds__(1024) void k_b_sched(BatchSched* S, int M, int orde
 
 // ---- work kernels -----------------------------------------------------------
 
-template <typename T>
+// Gradient and cell kernels: PERSIST = true walks the tiles with a fixed
+// grid (prefix in LDS); false takes one tile per block over a grid of the
+// static tile count (prefix searched in global memory).  The autotuner
+// picks the faster.
+template <typename T, bool PERSIST>
 __global__ __launch_bounds__(kBlock) void k_b_grad(const int32_t* __restrict__ tp,
                                                    const BatchSched* S, int M, int grab,
                                                    GradArgs<T> a) {
-  STAGE_PREFIX(tp);
-  const int total = s_pre[M];
-  TILE_LOOP(total, grab) {
-    int m = find_mesh(s_pre, M, t);
-    int j = (t - s_pre[m]) * kBlock + threadIdx.x;
+  if (PERSIST) {
+    STAGE_PREFIX(tp);
+    const int total = s_pre[M];
+    TILE_LOOP(total, grab) {
+      int m = find_mesh(s_pre, M, t);
+      int j = (t - s_pre[m]) * kBlock + threadIdx.x;
+      if (j < S[m].n_grad) grad_item<T>(a, a.list[S[m].c0 + j]);
+    }
+  } else {
+    const int t = xcd_block();
+    if (t >= tp[M]) return;
+    int m = find_mesh(tp, M, t);
+    int j = (t - tp[m]) * kBlock + threadIdx.x;
     if (j < S[m].n_grad) grad_item<T>(a, a.list[S[m].c0 + j]);
   }
 }
@@ -462,6 +474,7 @@ __global__ __launch_bounds__(kBlock) void k_b_flux_feat(const int32_t* __restric
   flush_counters(info, i0, i1, i2, a.dcount, a.dimpulse);
 }
 
+template <bool PERSIST>
 __global__ __launch_bounds__(kBlock) void k_b_gather(const int32_t* __restrict__ tp,
                                                      const BatchSched* S, int M, int grab, int NC,
                                                      const int* __restrict__ list,
@@ -472,11 +485,22 @@ __global__ __launch_bounds__(kBlock) void k_b_gather(const int32_t* __restrict__
                                                      double* __restrict__ U,
                                                      double* __restrict__ R,
                                                      unsigned long long* flag) {
-  STAGE_PREFIX(tp);
-  const int total = s_pre[M];
-  TILE_LOOP(total, grab) {
-    int m = find_mesh(s_pre, M, t);
-    int j = (t - s_pre[m]) * kBlock + threadIdx.x;
+  if (PERSIST) {
+    STAGE_PREFIX(tp);
+    const int total = s_pre[M];
+    TILE_LOOP(total, grab) {
+      int m = find_mesh(s_pre, M, t);
+      int j = (t - s_pre[m]) * kBlock + threadIdx.x;
+      if (j < S[m].n_gather)
+        if (!cell_gather_item(list[S[m].c0 + j], NC, fpack, c2f, Q, vol, U, R, S[m].tau_s,
+                              S[m].upd))
+          atomicOr(flag, 1ull);
+    }
+  } else {
+    const int t = xcd_block();
+    if (t >= tp[M]) return;
+    int m = find_mesh(tp, M, t);
+    int j = (t - tp[m]) * kBlock + threadIdx.x;
     if (j < S[m].n_gather)
       if (!cell_gather_item(list[S[m].c0 + j], NC, fpack, c2f, Q, vol, U, R, S[m].tau_s,
                             S[m].upd))
@@ -634,6 +658,7 @@ tafv_status build(tafv_ctx* c) {
   B.n_cc = cc[M];
   B.n_fc = fc[M];
   B.n_ft = ft[M];
+  B.n_ct = ct[M];
   hipError_t e = hipSuccess;
   auto chk = [&](hipError_t x) {
     if (e == hipSuccess) e = x;
@@ -699,6 +724,8 @@ struct Ptrs {
   double* dimpulse;
   double* U;
   double* R;
+  const int32_t* tp;  // work tile prefixes [3][M + 1]
+  const BatchSched* S;
 };
 
 hipError_t run_reclass(tafv_ctx* c, hipStream_t s) {
@@ -744,22 +771,37 @@ hipError_t run_reclass(tafv_ctx* c, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t run_grad(tafv_ctx* c, hipStream_t s, const LaunchSet& ls) {
+// grab 0: one tile per block over the static count of cell tiles
+dim3 work_grid(const Batch& B, const LaunchSet& ls) {
+  return dim3(ls.grab == 0 ? std::max(B.n_ct, 1) : ls.grid);
+}
+
+hipError_t run_grad(tafv_ctx* c, hipStream_t s, const LaunchSet& ls, const Ptrs& p) {
   Batch& B = *c->batch;
   DevMesh& m = *B.m;
   if (c->prm.order != 2) return hipSuccess;
   const int M = B.nmesh;
   const double gm1 = c->prm.gamma - 1.0;
+  const dim3 g = work_grid(B, ls);
+  const size_t lds = ls.grab == 0 ? 0 : sizeof(int32_t) * (M + 1);
   if (c->prm.precision == TAFV_FP32_FLUX) {
-    GradArgs<float> g{m.pc.list, 0, m.nc, m.nf, m.U, m.nb_, m.lsq32, m.rf32, m.fA, (float*)m.Wf,
+    GradArgs<float> a{m.pc.list, 0, m.nc, m.nf, m.U, m.nb_, m.lsq32, m.rf32, m.fA, (float*)m.Wf,
                       gm1, c->prm.boundary};
-    hipLaunchKernelGGL(k_b_grad<float>, dim3(ls.grid), dim3(kBlock), sizeof(int32_t) * (M + 1), s,
-                       B.tp, B.dsched, M, ls.grab, g);
+    if (ls.grab == 0)
+      hipLaunchKernelGGL((k_b_grad<float, false>), g, dim3(kBlock), lds, s, p.tp, p.S, M,
+                         0, a);
+    else
+      hipLaunchKernelGGL((k_b_grad<float, true>), g, dim3(kBlock), lds, s, p.tp, p.S, M,
+                         ls.grab, a);
   } else {
-    GradArgs<double> g{m.pc.list, 0, m.nc, m.nf, m.U, m.nb_, m.lsq, m.rf, m.fA, (double*)m.Wf,
+    GradArgs<double> a{m.pc.list, 0, m.nc, m.nf, m.U, m.nb_, m.lsq, m.rf, m.fA, (double*)m.Wf,
                        gm1, c->prm.boundary};
-    hipLaunchKernelGGL(k_b_grad<double>, dim3(ls.grid), dim3(kBlock), sizeof(int32_t) * (M + 1),
-                       s, B.tp, B.dsched, M, ls.grab, g);
+    if (ls.grab == 0)
+      hipLaunchKernelGGL((k_b_grad<double, false>), g, dim3(kBlock), lds, s, p.tp, p.S, M,
+                         0, a);
+    else
+      hipLaunchKernelGGL((k_b_grad<double, true>), g, dim3(kBlock), lds, s, p.tp, p.S, M,
+                         ls.grab, a);
   }
   return hipGetLastError();
 }
@@ -817,14 +859,21 @@ hipError_t run_gather(tafv_ctx* c, hipStream_t s, const LaunchSet& ls, const Ptr
   Batch& B = *c->batch;
   DevMesh& m = *B.m;
   const int M = B.nmesh;
-  hipLaunchKernelGGL(k_b_gather, dim3(ls.grid), dim3(kBlock), sizeof(int32_t) * (M + 1), s,
-                     B.tp + 2 * (M + 1), B.dsched,
-                     M, ls.grab, m.nc, m.pc.list, m.fpack, m.c2f, m.Q, m.vol, p.U, p.R,
-                     m.dscal + 2);
+  const dim3 g = work_grid(B, ls);
+  const size_t lds = ls.grab == 0 ? 0 : sizeof(int32_t) * (M + 1);
+  const int32_t* tp = p.tp + 2 * (M + 1);
+  if (ls.grab == 0)
+    hipLaunchKernelGGL(k_b_gather<false>, g, dim3(kBlock), lds, s, tp, p.S, M, 0, m.nc,
+                       m.pc.list, m.fpack, m.c2f, m.Q, m.vol, p.U, p.R, m.dscal + 2);
+  else
+    hipLaunchKernelGGL(k_b_gather<true>, g, dim3(kBlock), lds, s, tp, p.S, M, ls.grab, m.nc,
+                       m.pc.list, m.fpack, m.c2f, m.Q, m.vol, p.U, p.R, m.dscal + 2);
   return hipGetLastError();
 }
 
-Ptrs live_ptrs(Batch& B) { return Ptrs{B.m->dcount, B.m->dimpulse, B.m->U, B.m->R}; }
+Ptrs live_ptrs(Batch& B) {
+  return Ptrs{B.m->dcount, B.m->dimpulse, B.m->U, B.m->R, B.tp, B.dsched};
+}
 
 // one subiteration on stream s (profiling scopes only when s is the
 // context stream and nothing is being captured)
@@ -839,7 +888,7 @@ hipError_t run_subiteration(tafv_ctx* c, hipStream_t s, bool prof) {
   }
   {
     ProfScope ps(prof ? c : nullptr, P_GRAD, 0);
-    e = run_grad(c, s, B.set[0]);
+    e = run_grad(c, s, B.set[0], p);
     if (e != hipSuccess) return e;
   }
   {
@@ -879,7 +928,7 @@ bool cache_lookup(tafv_ctx* c, const std::string& key) {
     if (!(in >> k >> t[0].grid >> t[0].grab >> t[2].grid >> t[2].grab)) continue;
     if (k != key) continue;
     bool ok = true;
-    for (int w : {0, 2}) ok &= t[w].grid > 0 && t[w].grid <= 65536 && t[w].grab >= 1 && t[w].grab <= 64;
+    for (int w : {0, 2}) ok &= t[w].grid > 0 && t[w].grab >= 0 && t[w].grab <= 64;
     if (!ok) continue;
     for (int w : {0, 2}) got[w] = t[w];
     found = true;  // the last matching line wins
@@ -899,60 +948,114 @@ void cache_store(tafv_ctx* c, const std::string& key) {
   f << '\n';
 }
 
-// Times candidate launch widths of one work class (0 gradient, 2 cells) on
-// the current subiteration: the gradient kernel writes only the face values
-// (recomputed by the real launch); the cell kernel, run after the flux
-// kernel, works on copies of U and R.  Three timed runs after one warm-up
-// per candidate.
-tafv_status autotune(tafv_ctx* c, int w) {
+tafv_status sync_back(tafv_ctx* c) {
+  Batch& B = *c->batch;
+  B_TRY(c, hipMemcpyAsync(B.hsched.data(), B.dsched, sizeof(BatchSched) * B.nmesh,
+                          hipMemcpyDeviceToHost, c->stream));
+  B_TRY(c, hipMemcpyAsync(c->hpin, B.m->dscal, 4 * sizeof(unsigned long long),
+                          hipMemcpyDeviceToHost, c->stream));
+  B_TRY(c, hipStreamSynchronize(c->stream));
+  return TAFV_OK;
+}
+
+// Times candidate launch widths of the gradient and cell kernels on the
+// first subiteration's lists (after its flux), over synthetic schedules that
+// stand for a whole iteration: for each level tau, every mesh runs its
+// subiteration-level-tau work (tau_s = min(tau, theta_m)), weighted by how
+// often that level comes up (2^-(tau+1), the top level 2^-theta_max).  The
+// gradient kernel rewrites the face values with the same numbers; the cell
+// kernel runs on copies of U and R.  Three timed runs after one warm-up per
+// candidate and level.
+tafv_status autotune(tafv_ctx* c) {
   Batch& B = *c->batch;
   DevMesh& m = *B.m;
   hipStream_t s = c->stream;
+  const int M = B.nmesh;
+  tafv_status st = sync_back(c);  // lists and levels of this iteration
+  if (st != TAFV_OK) return st;
   const int cu = cu_count(c);
   std::vector<LaunchSet> cand;
   for (int mult : {1, 2, 4, 8})
     for (int grab : {1, 4}) cand.push_back(LaunchSet{mult * cu, grab});
-  hipEvent_t e0, e1;
-  B_TRY(c, hipEventCreate(&e0));
-  B_TRY(c, hipEventCreate(&e1));
-  double *Us = nullptr, *Rs = nullptr;
+  cand.push_back(LaunchSet{std::max(B.n_ct, 1), 0});  // one tile per block
+  int theta_max = 0;
+  for (const BatchSched& x : B.hsched) theta_max = std::max(theta_max, x.theta);
   const size_t rows = (size_t)5 * m.nc;
-  hipError_t e = hipSuccess;
-  if (w == 2) {
-    e = hipMalloc(&Us, rows * sizeof(double));
-    if (e == hipSuccess) e = hipMalloc(&Rs, rows * sizeof(double));
-  }
-  Ptrs scratch{m.dcount, m.dimpulse, Us, Rs};  // the cell kernel's copies
-  if (e == hipSuccess) {
-    float best = 1e30f;
-    for (const LaunchSet& ls : cand) {
-      float tot = 0.f;
-      for (int rep = 0; rep < 4 && e == hipSuccess; ++rep) {
-        if (w == 2) {
-          e = hipMemcpyAsync(Us, m.U, rows * sizeof(double), hipMemcpyDeviceToDevice, s);
-          if (e == hipSuccess)
-            e = hipMemcpyAsync(Rs, m.R, rows * sizeof(double), hipMemcpyDeviceToDevice, s);
-        }
-        if (e == hipSuccess) e = hipEventRecord(e0, s);
-        if (e == hipSuccess)
-          e = w == 0 ? run_grad(c, s, ls) : run_gather(c, s, ls, scratch);
-        if (e == hipSuccess) e = hipEventRecord(e1, s);
-        if (e == hipSuccess) e = hipEventSynchronize(e1);
-        float ms = 0.f;
-        if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
-        if (rep > 0) tot += ms;
+  double *Us = nullptr, *Rs = nullptr;
+  BatchSched* St = nullptr;
+  int32_t* tpt = nullptr;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  hipError_t e = hipMalloc(&Us, rows * sizeof(double));
+  if (e == hipSuccess) e = hipMalloc(&Rs, rows * sizeof(double));
+  if (e == hipSuccess) e = hipMalloc(&St, sizeof(BatchSched) * M);
+  if (e == hipSuccess) e = hipMalloc(&tpt, sizeof(int32_t) * 3 * (M + 1));
+  if (e == hipSuccess) e = hipEventCreate(&e0);
+  if (e == hipSuccess) e = hipEventCreate(&e1);
+  std::vector<double> score[2];
+  score[0].assign(cand.size(), 0.0);
+  score[1].assign(cand.size(), 0.0);
+  std::vector<BatchSched> hs;
+  std::vector<int32_t> htp(3 * (M + 1));
+  for (int tau = 0; tau <= theta_max && e == hipSuccess; ++tau) {
+    const double weight = tau < theta_max ? std::ldexp(1.0, -(tau + 1)) : std::ldexp(1.0, -theta_max);
+    hs = B.hsched;
+    int acc[3] = {0, 0, 0};
+    for (int q = 0; q < M; ++q) {
+      BatchSched& x = hs[q];
+      const int ts = std::min(tau, x.theta);
+      const int up = tau == 0 ? std::min(1, x.theta) : 0;
+      x.tau_s = ts;
+      x.upd = up;
+      x.n_grad = c->prm.order == 2 ? x.cstart[ts + 1] - x.cstart[0] : 0;
+      x.n_gather = x.cstart[std::max(ts, up) + 1] - x.cstart[0];
+      const int n[3] = {x.n_grad, 0, x.n_gather};
+      for (int w = 0; w < 3; ++w) {
+        htp[w * (M + 1) + q] = acc[w];
+        acc[w] += (n[w] + kBlock - 1) / kBlock;
       }
-      if (e == hipSuccess && tot < best) {
-        best = tot;
-        B.set[w] = ls;
+    }
+    for (int w = 0; w < 3; ++w) htp[w * (M + 1) + M] = acc[w];
+    e = hipMemcpyAsync(St, hs.data(), sizeof(BatchSched) * M, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(tpt, htp.data(), sizeof(int32_t) * 3 * (M + 1), hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);  // host buffers reused next level
+    Ptrs scratch{m.dcount, m.dimpulse, Us, Rs, tpt, St};
+    for (int w = 0; w < 2 && e == hipSuccess; ++w) {
+      if (w == 0 && c->prm.order != 2) continue;
+      for (size_t k = 0; k < cand.size() && e == hipSuccess; ++k) {
+        float tot = 0.f;
+        for (int r = 0; r < 4 && e == hipSuccess; ++r) {
+          if (w == 1) {
+            e = hipMemcpyAsync(Us, m.U, rows * sizeof(double), hipMemcpyDeviceToDevice, s);
+            if (e == hipSuccess)
+              e = hipMemcpyAsync(Rs, m.R, rows * sizeof(double), hipMemcpyDeviceToDevice, s);
+          }
+          if (e == hipSuccess) e = hipEventRecord(e0, s);
+          if (e == hipSuccess)
+            e = w == 0 ? run_grad(c, s, cand[k], scratch) : run_gather(c, s, cand[k], scratch);
+          if (e == hipSuccess) e = hipEventRecord(e1, s);
+          if (e == hipSuccess) e = hipEventSynchronize(e1);
+          float ms = 0.f;
+          if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+          if (r > 0) tot += ms;
+        }
+        score[w][k] += weight * tot;
       }
     }
   }
-  (void)hipEventDestroy(e0);
-  (void)hipEventDestroy(e1);
-  if (Us) (void)hipFree(Us);
-  if (Rs) (void)hipFree(Rs);
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  for (void* ptr : {(void*)Us, (void*)Rs, (void*)St, (void*)tpt})
+    if (ptr) (void)hipFree(ptr);
   if (e != hipSuccess) return hip_error(c, e, "autotuning");
+  for (int w = 0; w < 2; ++w) {
+    if (w == 0 && c->prm.order != 2) continue;
+    size_t best = 0;
+    for (size_t k = 1; k < cand.size(); ++k)
+      if (score[w][k] < score[w][best]) best = k;
+    B.set[w == 0 ? 0 : 2] = cand[best];
+  }
+  if (c->prm.order != 2) B.set[0] = B.set[2];
   return TAFV_OK;
 }
 
@@ -1003,15 +1106,6 @@ tafv_status graph_for(tafv_ctx* c, int64_t len, hipGraphExec_t* out) {
   return TAFV_OK;
 }
 
-tafv_status sync_back(tafv_ctx* c) {
-  Batch& B = *c->batch;
-  B_TRY(c, hipMemcpyAsync(B.hsched.data(), B.dsched, sizeof(BatchSched) * B.nmesh,
-                          hipMemcpyDeviceToHost, c->stream));
-  B_TRY(c, hipMemcpyAsync(c->hpin, B.m->dscal, 4 * sizeof(unsigned long long),
-                          hipMemcpyDeviceToHost, c->stream));
-  B_TRY(c, hipStreamSynchronize(c->stream));
-  return TAFV_OK;
-}
 
 Batch* ready(tafv_ctx* c, int32_t id, tafv_status* st) {
   *st = TAFV_OK;
@@ -1143,23 +1237,20 @@ tafv_status batch_advance(tafv_ctx* c, int64_t n, tafv_stats* out) {
   if (c->prm.guess == TAFV_GUESS_MLP && !c->mlp_ready)
     return set_error(c, TAFV_E_MLP, "learned guess selected but no network set");
   B_TRY(c, hipSetDevice(c->device));
+  const std::vector<BatchSched> before = B.hsched;
   int64_t left = n;
   if (left > 0 && B.autotune && B.tuned == 0) {
     if (cache_lookup(c, tune_key(c))) {
       B.tuned = 2;
     } else {
-      // first subiteration: reclassify, then time the work kernels on it
+      // first subiteration: reclassify, gradient and flux with the
+      // defaults, time the candidates on its lists, then its cell step
       Ptrs p = live_ptrs(B);
       B_TRY(c, run_reclass(c, c->stream));
-      if (c->prm.order == 2) {
-        st = autotune(c, 0);
-        if (st != TAFV_OK) return st;
-      }
-      B_TRY(c, run_grad(c, c->stream, B.set[0]));
+      B_TRY(c, run_grad(c, c->stream, B.set[0], p));
       B_TRY(c, run_flux(c, c->stream, p));
-      st = autotune(c, 2);
+      st = autotune(c);
       if (st != TAFV_OK) return st;
-      if (c->prm.order != 2) B.set[0] = B.set[2];
       B.tuned = 1;
       cache_store(c, tune_key(c));
       B_TRY(c, run_gather(c, c->stream, B.set[2], p));
@@ -1179,7 +1270,6 @@ tafv_status batch_advance(tafv_ctx* c, int64_t n, tafv_stats* out) {
     }
     left -= len;
   }
-  std::vector<BatchSched> before = B.hsched;
   st = sync_back(c);
   if (st != TAFV_OK) return st;
   const unsigned long long* sc = (const unsigned long long*)c->hpin;
