@@ -192,7 +192,9 @@ __global__ __launch_bounds__(kBlock) void k_b_cell_keys(const int32_t* __restric
     for (int k = threadIdx.x; k < kMaxKeys; k += blockDim.x) h[k] = 0;
     __syncthreads();
     int i = S[m].c0 + (t - s_pre[m]) * kBlock + threadIdx.x;
-    if (i < S[m].c0 + S[m].nc) atomicAdd(&h[cell_key_item(i, NC, nb, lev, ckey, fpack)], 1);
+    const bool in = i < S[m].c0 + S[m].nc;
+    int bin = in ? cell_key_item(i, NC, nb, lev, ckey, fpack) : 0;
+    wave_hist_add(h, in, bin);
     __syncthreads();
     for (int k = threadIdx.x; k < kMaxKeys; k += blockDim.x)
       if (h[k]) atomicAdd(&S[m].hist[k], h[k]);

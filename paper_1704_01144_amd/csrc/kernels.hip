@@ -124,7 +124,8 @@ __global__ __launch_bounds__(kBlock) void k_cell_keys(int nc, const int* __restr
   for (int k = threadIdx.x; k < kMaxKeys; k += blockDim.x) h[k] = 0;
   __syncthreads();
   int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < nc) atomicAdd(&h[cell_key_item(i, nc, nb, lev, ckey, fpack)], 1);
+  int bin = i < nc ? cell_key_item(i, nc, nb, lev, ckey, fpack) : 0;
+  wave_hist_add(h, i < nc, bin);
   __syncthreads();
   for (int k = threadIdx.x; k < kMaxKeys; k += blockDim.x)
     if (h[k]) atomicAdd(&hist[k], h[k]);

@@ -127,6 +127,20 @@ __device__ inline int cell_key_item(int i, int nc, const int* __restrict__ nb,
   return tg * kMaxLevels + ti;
 }
 
+// h[bin] += 1 for every active lane, one LDS atomic per distinct bin of the
+// wave (lanes with equal bins are counted by a ballot): the bins of a
+// histogram by level are few, and per-lane atomics on them serialise
+__device__ inline void wave_hist_add(int* h, bool active, int bin) {
+  unsigned long long pending = __ballot(active);
+  while (pending) {
+    const int leader = __ffsll(pending) - 1;
+    const int b = __shfl(bin, leader, 64);
+    const unsigned long long same = __ballot(active && bin == b);
+    if ((int)(threadIdx.x & 63) == leader) atomicAdd(&h[b], __popcll(same));
+    pending &= ~same;
+  }
+}
+
 // partition keys and list writers
 struct ByteKey {
   const int8_t* key;
