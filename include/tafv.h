@@ -233,9 +233,11 @@ tafv_status tafv_checkpoint_write(tafv_ctx* ctx, int32_t mesh_id, const double* 
                                   double t);
 
 /* ---- learned initial guess of the star pressure ----------------------
- * A 6-32-32-1 ReLU network maps the normalised face states
- * x = (rho_L/rho_m, u_L/a_m, p_L/p_m, rho_R/rho_m, u_R/a_m, p_R/p_m)
- * (normal velocities; rho_m, p_m side averages; a_m = sqrt(g p_m/rho_m)) to
+ * A 6-32-32-1 ReLU network maps the face states, as deviations from the
+ * side averages normalised by them,
+ * x = (rho_L/rho_m - 1, (u_L - u_m)/a_m, p_L/p_m - 1,
+ *      rho_R/rho_m - 1, (u_R - u_m)/a_m, p_R/p_m - 1)
+ * (normal velocities; rho_m, u_m, p_m side averages; a_m = sqrt(g p_m/rho_m)) to
  * a correction y ~ ln(p_star / p_TR) of the two-rarefaction value p_TR,
  * p_star the exact star pressure; the Newton solve starts from
  * p_TR exp(y).  BF16 inputs, weights and activations, FP32 accumulation, on

@@ -3,12 +3,17 @@ of the exact Riemann solve.  TEST INFRASTRUCTURE ONLY (see oracle/__init__).
 
 The network and its inputs (the paper is silent here; these are the readings
 the design notes list):
-  inputs  x = (rho_L/rho_m, u_L/a_m, p_L/p_m, rho_R/rho_m, u_R/a_m, p_R/p_m)
-          with rho_m = (rho_L + rho_R)/2, p_m = (p_L + p_R)/2,
-          a_m = sqrt(gamma p_m / rho_m), u the face-normal velocities.  The
-          Euler equations are invariant under rho -> s rho, u -> c u,
-          p -> s c^2 p, which leaves x and ln(p*/p_m) unchanged, so the
-          target is a function of x alone;
+  inputs  the face states as deviations from their mean, normalised by it:
+          x = (rho_L/rho_m - 1, (u_L - u_m)/a_m, p_L/p_m - 1,
+               rho_R/rho_m - 1, (u_R - u_m)/a_m, p_R/p_m - 1)
+          with rho_m, u_m, p_m the means of the two sides,
+          a_m = sqrt(gamma p_m / rho_m), u the face-normal velocities
+          (x_3 = -x_0, x_4 = -x_1, x_5 = -x_2).  The Euler equations are
+          invariant under rho -> s rho, u -> c u, p -> s c^2 p and under a
+          shift of u, which leave x and ln(p*/p_m) unchanged, so the target
+          is a function of x alone.  Deviations rather than ratios: weak
+          waves differ from the mean by little, and BF16 keeps 8 bits of a
+          small deviation but only 8 bits of a ratio near 1;
   network h1 = relu(W1 x + b1) (32), h2 = relu(W2 h1 + b2) (32),
           y = w3 . h2 + b3, a correction of the two-rarefaction value p_TR
           (Toro, ch. 4): the guess is p0 = p_TR exp(y);
@@ -57,10 +62,11 @@ def features(wl, wr, gamma=1.4):
     wl = np.atleast_2d(np.asarray(wl, dtype=np.float64))
     wr = np.atleast_2d(np.asarray(wr, dtype=np.float64))
     rm = 0.5 * (wl[:, 0] + wr[:, 0])
+    um = 0.5 * (wl[:, 1] + wr[:, 1])
     pm = 0.5 * (wl[:, 2] + wr[:, 2])
     am = np.sqrt(gamma * pm / rm)
-    x = np.stack([wl[:, 0] / rm, wl[:, 1] / am, wl[:, 2] / pm,
-                  wr[:, 0] / rm, wr[:, 1] / am, wr[:, 2] / pm], axis=1)
+    x = np.stack([wl[:, 0] / rm - 1.0, (wl[:, 1] - um) / am, wl[:, 2] / pm - 1.0,
+                  wr[:, 0] / rm - 1.0, (wr[:, 1] - um) / am, wr[:, 2] / pm - 1.0], axis=1)
     return x, rm, pm, am
 
 

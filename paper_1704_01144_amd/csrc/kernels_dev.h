@@ -517,17 +517,19 @@ __device__ inline void flux_feat_item(const FluxArgs<T>& a, bool valid, int4 r, 
         ptr = q3 * q3 * q;
         gate = !wall && ptr > fmin(KL.p, KR.p);
       }
-      if (gate) {
-        double rr = wr[0];
-        double rm = 0.5 * ((double)wl[0] + rr);
+      if (gate) {  // deviations from the face mean, normalised by it
+        double rl = wl[0], rr = wr[0];
+        double rm = 0.5 * (rl + rr);
         pm = 0.5 * (KL.p + KR.p);
         double amean = sqrt(G.g * pm / rm);
-        x[0] = (float)((double)wl[0] / rm);
-        x[1] = (float)((double)unl / amean);
-        x[2] = (float)(KL.p / pm);
-        x[3] = (float)(rr / rm);
-        x[4] = (float)((double)unr / amean);
-        x[5] = (float)(KR.p / pm);
+        double dr = (rl - rr) / (rl + rr), dp = (KL.p - KR.p) / (KL.p + KR.p);
+        double du = 0.5 * ((double)unl - (double)unr) / amean;
+        x[0] = (float)dr;
+        x[1] = (float)du;
+        x[2] = (float)dp;
+        x[3] = (float)-dr;
+        x[4] = (float)-du;
+        x[5] = (float)-dp;
       }
     }
   }

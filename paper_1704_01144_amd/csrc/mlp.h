@@ -1,9 +1,10 @@
 // The small network that proposes the initial star pressure of the exact
 // Riemann solve (the learned guess), device side.
 //
-// Inputs per face (normal frame): x = (rho_L/rho_m, u_L/a_m, p_L/p_m,
-// rho_R/rho_m, u_R/a_m, p_R/p_m), rho_m and p_m the side averages,
-// a_m = sqrt(g p_m / rho_m); network h1 = relu(W1 x + b1), h2 = relu(W2 h1 +
+// Inputs per face (normal frame), deviations from the side averages
+// rho_m, u_m, p_m normalised by them: x = (rho_L/rho_m - 1, (u_L - u_m)/a_m,
+// p_L/p_m - 1, and the same for the right side), a_m = sqrt(g p_m / rho_m);
+// network h1 = relu(W1 x + b1), h2 = relu(W2 h1 +
 // b2) (32 units each), y = w3 . h2 + b3, a correction of the two-rarefaction
 // value: guess p0 = p_TR exp(y).  BF16 inputs, weights and hidden
 // activations (round to nearest even), FP32 accumulation.

@@ -43,13 +43,16 @@ def test_bf16_rounding_matches_torch():
 
 
 def test_features_follow_scaling_symmetry(orc):
+    """Scaling rho -> s rho, u -> c u + v, p -> s c^2 p (a shift v of the
+    velocity: Galilean invariance of the star pressure) leaves the features
+    and the target unchanged."""
     rng = np.random.default_rng(4)
     for _ in range(200):
         wl = np.array([rng.uniform(0.2, 5), rng.uniform(-1, 1), rng.uniform(0.1, 10)])
         wr = np.array([rng.uniform(0.2, 5), rng.uniform(-1, 1), rng.uniform(0.1, 10)])
-        s, c = rng.uniform(0.1, 10), rng.uniform(0.1, 10)
-        sl = np.array([s * wl[0], c * wl[1], s * c * c * wl[2]])
-        sr = np.array([s * wr[0], c * wr[1], s * c * c * wr[2]])
+        s, c, v = rng.uniform(0.1, 10), rng.uniform(0.1, 10), rng.uniform(-3, 3)
+        sl = np.array([s * wl[0], c * wl[1] + v, s * c * c * wl[2]])
+        sr = np.array([s * wr[0], c * wr[1] + v, s * c * c * wr[2]])
         x1, _, pm1, _ = M.features(wl, wr)
         x2, _, pm2, _ = M.features(sl, sr)
         assert np.abs(x1 - x2).max() < 1e-13
