@@ -40,13 +40,13 @@ BYTES_PER_ITEM = {
     "fp32": {"flux": 226, "grad": 236, "update": 172},
 }
 # gather mode: the flux kernel reads a 16-byte face record, the area vector,
-# two reconstructed states and writes one 40-byte flux; the cell kernel reads
-# its index, level, 4 neighbour ids and levels, 4 face ids, the active
-# faces' fluxes (about 2 x 40 per cell), and reads+writes the accumulator,
-# and for ending steps the volume and state.
+# two reconstructed states and writes one flux (5 values in the flux
+# precision); the cell kernel reads its index, its packed level word, 4 face
+# ids, the active faces' fluxes (about 2 per cell), reads+writes the FP64
+# accumulator, and for ending steps the volume and state.
 BYTES_PER_ITEM_GATHER = {
     "fp64": {"flux": 160, "grad": 412, "gather": 270},
-    "fp32": {"flux": 108, "grad": 236, "gather": 270},
+    "fp32": {"flux": 88, "grad": 236, "gather": 230},
 }
 
 

@@ -476,13 +476,13 @@ __global__ __launch_bounds__(kBlock) void k_b_flux_feat(const int32_t* __restric
   flush_counters(info, i0, i1, i2, a.dcount, a.dimpulse);
 }
 
-template <bool PERSIST>
+template <typename T, bool PERSIST>
 __global__ __launch_bounds__(kBlock) void k_b_gather(const int32_t* __restrict__ tp,
                                                      const BatchSched* S, int M, int grab, int NC,
                                                      const int* __restrict__ list,
                                                      const uint32_t* __restrict__ fpack,
                                                      const int* __restrict__ c2f,
-                                                     const double* __restrict__ Q,
+                                                     const T* __restrict__ Q,
                                                      const double* __restrict__ vol,
                                                      double* __restrict__ U,
                                                      double* __restrict__ R,
@@ -494,8 +494,8 @@ __global__ __launch_bounds__(kBlock) void k_b_gather(const int32_t* __restrict__
       int m = find_mesh(s_pre, M, t);
       int j = (t - s_pre[m]) * kBlock + threadIdx.x;
       if (j < S[m].n_gather)
-        if (!cell_gather_item(list[S[m].c0 + j], NC, fpack, c2f, Q, vol, U, R, S[m].tau_s,
-                              S[m].upd))
+        if (!cell_gather_item<T>(list[S[m].c0 + j], NC, fpack, c2f, Q, S[m].dt_min, vol, U, R,
+                                 S[m].tau_s, S[m].upd))
           atomicOr(flag, 1ull);
     }
   } else {
@@ -504,8 +504,8 @@ __global__ __launch_bounds__(kBlock) void k_b_gather(const int32_t* __restrict__
     int m = find_mesh(tp, M, t);
     int j = (t - tp[m]) * kBlock + threadIdx.x;
     if (j < S[m].n_gather)
-      if (!cell_gather_item(list[S[m].c0 + j], NC, fpack, c2f, Q, vol, U, R, S[m].tau_s,
-                            S[m].upd))
+      if (!cell_gather_item<T>(list[S[m].c0 + j], NC, fpack, c2f, Q, S[m].dt_min, vol, U, R,
+                               S[m].tau_s, S[m].upd))
         atomicOr(flag, 1ull);
   }
 }
@@ -844,12 +844,12 @@ hipError_t run_flux(tafv_ctx* c, hipStream_t s, const Ptrs& p) {
   StepArgs a = step_args(c);
   FluxFeatures ft = features(c);
   if (c->prm.precision == TAFV_FP32_FLUX) {
-    FluxArgs<float> f{m.frec, 0, m.nf, m.nc, m.fA32, m.U, (const float*)m.Wf, m.R, m.Q,
+    FluxArgs<float> f{m.frec, 0, m.nf, m.nc, m.fA32, m.U, (const float*)m.Wf, m.R, (float*)m.Q,
                       p.dcount, p.dimpulse, a, ft.mlp, nullptr, nullptr, 0, 0.0, 0, 0,
                       ft.guess_gate};
     flux_dispatch<float>(s, B, c->prm.order, ft.feat, a.gas.is14, grid, f);
   } else {
-    FluxArgs<double> f{m.frec, 0, m.nf, m.nc, m.fA, m.U, (const double*)m.Wf, m.R, m.Q,
+    FluxArgs<double> f{m.frec, 0, m.nf, m.nc, m.fA, m.U, (const double*)m.Wf, m.R, (double*)m.Q,
                        p.dcount, p.dimpulse, a, ft.mlp, nullptr, nullptr, 0, 0.0, 0, 0,
                        ft.guess_gate};
     flux_dispatch<double>(s, B, c->prm.order, ft.feat, a.gas.is14, grid, f);
@@ -864,12 +864,24 @@ hipError_t run_gather(tafv_ctx* c, hipStream_t s, const LaunchSet& ls, const Ptr
   const dim3 g = work_grid(B, ls);
   const size_t lds = ls.grab == 0 ? 0 : sizeof(int32_t) * (M + 1);
   const int32_t* tp = p.tp + 2 * (M + 1);
-  if (ls.grab == 0)
-    hipLaunchKernelGGL(k_b_gather<false>, g, dim3(kBlock), lds, s, tp, p.S, M, 0, m.nc,
-                       m.pc.list, m.fpack, m.c2f, m.Q, m.vol, p.U, p.R, m.dscal + 2);
-  else
-    hipLaunchKernelGGL(k_b_gather<true>, g, dim3(kBlock), lds, s, tp, p.S, M, ls.grab, m.nc,
-                       m.pc.list, m.fpack, m.c2f, m.Q, m.vol, p.U, p.R, m.dscal + 2);
+  unsigned long long* flag = m.dscal + 2;
+  if (c->prm.precision == TAFV_FP32_FLUX) {
+    const float* Q = (const float*)m.Q;
+    if (ls.grab == 0)
+      hipLaunchKernelGGL((k_b_gather<float, false>), g, dim3(kBlock), lds, s, tp, p.S, M, 0, m.nc,
+                         m.pc.list, m.fpack, m.c2f, Q, m.vol, p.U, p.R, flag);
+    else
+      hipLaunchKernelGGL((k_b_gather<float, true>), g, dim3(kBlock), lds, s, tp, p.S, M, ls.grab,
+                         m.nc, m.pc.list, m.fpack, m.c2f, Q, m.vol, p.U, p.R, flag);
+  } else {
+    const double* Q = (const double*)m.Q;
+    if (ls.grab == 0)
+      hipLaunchKernelGGL((k_b_gather<double, false>), g, dim3(kBlock), lds, s, tp, p.S, M, 0,
+                         m.nc, m.pc.list, m.fpack, m.c2f, Q, m.vol, p.U, p.R, flag);
+    else
+      hipLaunchKernelGGL((k_b_gather<double, true>), g, dim3(kBlock), lds, s, tp, p.S, M,
+                         ls.grab, m.nc, m.pc.list, m.fpack, m.c2f, Q, m.vol, p.U, p.R, flag);
+  }
   return hipGetLastError();
 }
 

@@ -201,7 +201,7 @@ tafv_status subiteration(tafv_ctx* c, DevMesh& m, tafv_stats* acc) {
     }
     int ccnt = cells_upto_g(m, std::max(tau_s, upd));
     ProfScope ps(c, P_GATHER, ccnt);
-    HIP_TRY(c, launch_cell_gather(c->stream, m, ccnt, tau_s, upd));
+    HIP_TRY(c, launch_cell_gather(c->stream, m, ccnt, tau_s, upd, m.dt_min, c->prm.precision));
   }
   m.phase = (int32_t)(s % ((int64_t)1 << m.theta));
   m.t += m.dt_min;
@@ -322,7 +322,9 @@ tafv_status upload_host_mesh(tafv_ctx* c, const HostMesh& hm, DevMesh** out) {
     chk(dalloc(&p->start, kMaxKeys + 1));
   }
   chk(dalloc(&m->frec, nf));
-  if (m->scatter == TAFV_SCATTER_GATHER) chk(dalloc(&m->Q, 5 * nf));
+  if (m->scatter == TAFV_SCATTER_GATHER)
+    chk(hipMalloc(&m->Q, (c->prm.precision == TAFV_FP32_FLUX ? sizeof(float) : sizeof(double)) *
+                             5 * std::max<size_t>(nf, 1)));
   chk(dalloc(&m->fkey, nf));
   chk(dalloc(&m->ckey, nc));
   chk(dalloc(&m->fpack, nc));

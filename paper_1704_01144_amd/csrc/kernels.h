@@ -36,7 +36,8 @@ struct FluxFeatures {
 };
 hipError_t launch_flux(hipStream_t s, DevMesh& m, const StepArgs& a, int first, int count,
                        const FluxFeatures& ft);
-hipError_t launch_cell_gather(hipStream_t s, DevMesh& m, int count, int tau_s, int tau_upd);
+hipError_t launch_cell_gather(hipStream_t s, DevMesh& m, int count, int tau_s, int tau_upd,
+                              double dt_min, int precision);
 hipError_t launch_update(hipStream_t s, DevMesh& m, int count, int tau_upd);
 hipError_t launch_pack_readback(hipStream_t s, DevMesh& m, int Kf);
 constexpr int kReadbackInts = 8 + kMaxKeys + 1 + kMaxLevels + 1 + kMaxKeys;

@@ -315,17 +315,18 @@ __global__ __launch_bounds__(kBlock) void k_flux_feat(FluxArgs<T> a) {
   flush_counters(info, i0, i1, i2, a.dcount, a.dimpulse);
 }
 
+template <typename T>
 __global__ __launch_bounds__(kBlock) void k_cell_gather(int count, const int* __restrict__ list,
                                                         int nc, const uint32_t* __restrict__ fpack,
                                                         const int* __restrict__ c2f,
-                                                        const double* __restrict__ Q,
+                                                        const T* __restrict__ Q, double dt_min,
                                                         const double* __restrict__ vol,
                                                         double* __restrict__ U,
                                                         double* __restrict__ R, int tau_s,
                                                         int tau_upd, unsigned long long* dscal) {
   int idx = xcd_block() * kBlock + threadIdx.x;
   if (idx >= count) return;
-  if (!cell_gather_item(list[idx], nc, fpack, c2f, Q, vol, U, R, tau_s, tau_upd))
+  if (!cell_gather_item<T>(list[idx], nc, fpack, c2f, Q, dt_min, vol, U, R, tau_s, tau_upd))
     atomicOr(&dscal[2], 1ull);
 }
 
@@ -515,7 +516,7 @@ hipError_t launch_flux(hipStream_t s, DevMesh& m, const StepArgs& a, int first, 
   if (count <= 0) return hipSuccess;
   const int4* rec = m.frec + first;
   if (a.precision == TAFV_FP32_FLUX) {
-    FluxArgs<float> f{rec, count, m.nf, m.nc, m.fA32, m.U, (const float*)m.Wf, m.R, m.Q, m.dcount,
+    FluxArgs<float> f{rec, count, m.nf, m.nc, m.fA32, m.U, (const float*)m.Wf, m.R, (float*)m.Q, m.dcount,
                       m.dimpulse, a, ft.mlp, ft.log_rows, ft.log_count, ft.log_cap,
                       ft.log_rate, ft.log_seed, ft.subit, ft.guess_gate};
     if (ft.feat && a.gas.is14 && m.scatter == TAFV_SCATTER_GATHER)
@@ -523,7 +524,7 @@ hipError_t launch_flux(hipStream_t s, DevMesh& m, const StepArgs& a, int first, 
     else if (a.gas.is14) flux_launch<float, true>(s, a.order, m.scatter, count, f);
     else flux_launch<float, false>(s, a.order, m.scatter, count, f);
   } else {
-    FluxArgs<double> f{rec, count, m.nf, m.nc, m.fA, m.U, (const double*)m.Wf, m.R, m.Q,
+    FluxArgs<double> f{rec, count, m.nf, m.nc, m.fA, m.U, (const double*)m.Wf, m.R, (double*)m.Q,
                        m.dcount, m.dimpulse, a, ft.mlp, ft.log_rows, ft.log_count, ft.log_cap,
                        ft.log_rate, ft.log_seed, ft.subit, ft.guess_gate};
     if (ft.feat && a.gas.is14 && m.scatter == TAFV_SCATTER_GATHER)
@@ -534,11 +535,17 @@ hipError_t launch_flux(hipStream_t s, DevMesh& m, const StepArgs& a, int first, 
   return hipGetLastError();
 }
 
-hipError_t launch_cell_gather(hipStream_t s, DevMesh& m, int count, int tau_s, int tau_upd) {
+hipError_t launch_cell_gather(hipStream_t s, DevMesh& m, int count, int tau_s, int tau_upd,
+                              double dt_min, int precision) {
   if (count <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_cell_gather, dim3(blocks_for(count)), dim3(kBlock), 0, s, count,
-                     m.pc.list, m.nc, m.fpack, m.c2f, m.Q, m.vol, m.U, m.R, tau_s, tau_upd,
-                     m.dscal);
+  if (precision == TAFV_FP32_FLUX)
+    hipLaunchKernelGGL(k_cell_gather<float>, dim3(blocks_for(count)), dim3(kBlock), 0, s, count,
+                       m.pc.list, m.nc, m.fpack, m.c2f, (const float*)m.Q, dt_min, m.vol, m.U,
+                       m.R, tau_s, tau_upd, m.dscal);
+  else
+    hipLaunchKernelGGL(k_cell_gather<double>, dim3(blocks_for(count)), dim3(kBlock), 0, s, count,
+                       m.pc.list, m.nc, m.fpack, m.c2f, (const double*)m.Q, dt_min, m.vol, m.U,
+                       m.R, tau_s, tau_upd, m.dscal);
   return hipGetLastError();
 }
 

@@ -254,7 +254,7 @@ struct FluxArgs {
   const double* U;
   const T* Wf;
   double* R;        // colour scatter: accumulators
-  double* Q;        // gather mode: per-face time-integrated flux [nf][5]
+  T* Q;             // gather mode: per-face flux |A| F . n [nf][5]
   unsigned long long* dcount;
   double* dimpulse;
   StepArgs s;
@@ -423,8 +423,9 @@ __device__ inline void flush_counters(const SolveInfo& info, double i0, double i
   }
 }
 
-// Gather mode: the time-integrated flux q = 2^tau_f dt_min Phi of one face
-// into Q[f]; the wall impulse is added to (i0, i1, i2).
+// Gather mode: the flux Phi of one face into Q[f], in the flux precision
+// (the cells form q = 2^tau_f dt_min Phi in FP64, the same product the
+// colour scatter forms); the wall impulse q is added to (i0, i1, i2).
 template <int ORDER, typename T, bool G14>
 __device__ inline void flux_store_item(const FluxArgs<T>& a, int4 r, double dt_min,
                                        SolveInfo& acc, double& i0, double& i1, double& i2) {
@@ -432,13 +433,13 @@ __device__ inline void flux_store_item(const FluxArgs<T>& a, int4 r, double dt_m
   T phi[5];
   face_flux<ORDER, T, G14>(a, r, phi, info);
   add_info(acc, info);
-  double dtf = ldexp(dt_min, r.w);
-  double* q = a.Q + 5 * (size_t)r.x;
-  for (int k = 0; k < 5; ++k) q[k] = dtf * (double)phi[k];
+  T* q = a.Q + 5 * (size_t)r.x;
+  for (int k = 0; k < 5; ++k) q[k] = phi[k];
   if (r.z < 0 && a.s.boundary == TAFV_BC_WALL) {
-    i0 += q[1];
-    i1 += q[2];
-    i2 += q[3];
+    double dtf = ldexp(dt_min, r.w);
+    i0 += dtf * (double)phi[1];
+    i1 += dtf * (double)phi[2];
+    i2 += dtf * (double)phi[3];
   }
 }
 
@@ -604,25 +605,27 @@ __device__ inline void flux_feat_item(const FluxArgs<T>& a, bool valid, int4 r, 
         phi[4] = am * us * (E + ps);
       }
     }
-    double dtf = ldexp(dt_min, r.w);
-    double* q = a.Q + 5 * (size_t)r.x;
-    for (int k = 0; k < 5; ++k) q[k] = dtf * (double)phi[k];
+    T* q = a.Q + 5 * (size_t)r.x;
+    for (int k = 0; k < 5; ++k) q[k] = phi[k];
     if (wall) {
-      i0 += q[1];
-      i1 += q[2];
-      i2 += q[3];
+      double dtf = ldexp(dt_min, r.w);
+      i0 += dtf * (double)phi[1];
+      i1 += dtf * (double)phi[2];
+      i2 += dtf * (double)phi[3];
     }
   }
   add_info(acc, info);
 }
 
 // Gather mode, per cell with an active face or whose step ends: add the
-// active faces' fluxes in local face order (-q where the cell is the lower
-// id of the face, +q otherwise), then U += R / V, R = 0 for ending steps.
-// Returns false on a non-finite updated state.
+// active faces' time-integrated fluxes q = 2^tau_f dt_min Phi in local face
+// order (-q where the cell is the lower id of the face, +q otherwise), then
+// U += R / V, R = 0 for ending steps.  Returns false on a non-finite
+// updated state.
+template <typename T>
 __device__ inline bool cell_gather_item(int i, int nc, const uint32_t* __restrict__ fpack,
                                         const int* __restrict__ c2f,
-                                        const double* __restrict__ Q,
+                                        const T* __restrict__ Q, double dt_min,
                                         const double* __restrict__ vol, double* __restrict__ U,
                                         double* __restrict__ R, int tau_s, int tau_upd) {
   uint32_t pk = fpack[i];
@@ -632,16 +635,18 @@ __device__ inline bool cell_gather_item(int i, int nc, const uint32_t* __restric
   double acc[5] = {0, 0, 0, 0, 0};
   double* Ri = R + 5 * (size_t)i;
   for (int m = 0; m < 4; ++m) {
-    if ((int)((pk >> (4 * m)) & 15) > tau_s) continue;
+    const int tf = (int)((pk >> (4 * m)) & 15);
+    if (tf > tau_s) continue;
     if (!touched) {
       for (int k = 0; k < 5; ++k) acc[k] = Ri[k];
       touched = true;
     }
-    const double* q = Q + 5 * (size_t)c2f[m * nc + i];
+    const T* q = Q + 5 * (size_t)c2f[m * nc + i];
+    const double dtf = ldexp(dt_min, tf);
     if (pk & (1u << (16 + m))) {
-      for (int k = 0; k < 5; ++k) acc[k] += q[k];
+      for (int k = 0; k < 5; ++k) acc[k] += dtf * (double)q[k];
     } else {
-      for (int k = 0; k < 5; ++k) acc[k] -= q[k];
+      for (int k = 0; k < 5; ++k) acc[k] -= dtf * (double)q[k];
     }
   }
   if (ends) {

@@ -79,7 +79,9 @@ struct DevMesh {
   int8_t* lev2 = nullptr;  // [nc]
   double* dt = nullptr;    // [nc]
   void* Wf = nullptr;      // [4][5][nc] reconstructed primitives (double or float)
-  double* Q = nullptr;     // [nf][5] gather mode: time-integrated face fluxes
+  void* Q = nullptr;       // [nf][5] gather mode: face fluxes |A| F . n in the flux
+                           // precision (double or float); the cells scale them
+                           // by 2^tau_f dt_min in FP64
   int4* frec = nullptr;    // [nf] face records {f, hL, hR, tau_f} in partition order
   // schedule lists
   Partition pf, pc;        // faces by (colour, tau_f); cells by tau_g
