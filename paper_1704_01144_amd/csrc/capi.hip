@@ -49,7 +49,7 @@ void free_mesh(DevMesh* m) {
                   m->pf.list, m->pf.counts, m->pf.start, m->pc.list, m->pc.counts,
                   m->pc.start, m->dscal, m->dcount, m->dimpulse, m->pf.offs, m->pc.offs,
                   m->pf.scan_tmp, m->pc.scan_tmp, m->Q, m->frec, m->fkey, m->ckey, m->fpack,
-                  m->perm, m->xfer, m->chist, m->rb};
+                  m->perm, m->xfer, m->chist, m->rb, m->dmin};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   delete m;
@@ -329,7 +329,8 @@ tafv_status upload_host_mesh(tafv_ctx* c, const HostMesh& hm, DevMesh** out) {
   chk(dalloc(&m->ckey, nc));
   chk(dalloc(&m->fpack, nc));
   chk(dalloc(&m->perm, nc));
-  chk(dalloc(&m->chist, kMaxKeys));
+  chk(dalloc(&m->chist, (size_t)kCounterSlots * kMaxKeys));
+  chk(dalloc(&m->dmin, kCounterWords));
   chk(dalloc(&m->rb, kReadbackInts));
   chk(dalloc(&m->xfer, 5 * nc));
   chk(dalloc(&m->dscal, 4));
@@ -718,9 +719,11 @@ tafv_status tafv_checkpoint_write(tafv_ctx* c, int32_t mesh_id, const double* co
                             hipMemcpyDeviceToHost, c->stream));
   HIP_TRY(c, hipMemcpyAsync(m->hstart_c, m->pc.start, (kMaxLevels + 1) * sizeof(int32_t),
                             hipMemcpyDeviceToHost, c->stream));
-  HIP_TRY(c, hipMemcpyAsync(m->hhist, m->chist, kMaxKeys * sizeof(int32_t), hipMemcpyDeviceToHost,
-                            c->stream));
+  HIP_TRY(c, launch_pack_readback(c->stream, *m, K));
+  HIP_TRY(c, hipMemcpyAsync(c->hpin, m->rb, kReadbackInts * sizeof(int32_t),
+                            hipMemcpyDeviceToHost, c->stream));
   HIP_TRY(c, hipStreamSynchronize(c->stream));
+  std::memcpy(m->hhist, c->hpin + 8 + kMaxKeys + kMaxLevels + 2, kMaxKeys * sizeof(int32_t));
   level_histogram(*m);
   m->has_state = true;
   m->phase = phase;

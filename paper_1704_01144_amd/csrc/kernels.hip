@@ -61,14 +61,17 @@ __global__ void k_fill_f64(double* p, double v, int64_t n) {
 // ---------------------------------------------------------------------------
 // time step, classification, sweeps (phase 0 of an iteration)
 
-// dscal[0] <- min dt as bits (positive doubles order like their bit
-// patterns); dscal[2] <- 1 on a non-physical state.
+// dmin[slot] <- min dt of the blocks of that slot, as bits (positive
+// doubles order like their bit patterns; one slot per block modulo
+// kCountSlots, so that the blocks' atomics do not serialise on one address);
+// dscal[2] <- 1 on a non-physical state.
 __global__ __launch_bounds__(kBlock) void k_dt(int nc, int nf, const double* __restrict__ U,
                                                const double* __restrict__ vol,
                                                const int* __restrict__ c2f,
                                                const double* __restrict__ fA, double gamma,
                                                double cfl, double* __restrict__ dt,
-                                               unsigned long long* dscal) {
+                                               unsigned long long* dscal,
+                                               unsigned long long* dmin) {
   int i = blockIdx.x * blockDim.x + threadIdx.x;
   double dti = INFINITY;
   if (i < nc) {
@@ -83,8 +86,21 @@ __global__ __launch_bounds__(kBlock) void k_dt(int nc, int nf, const double* __r
   __syncthreads();
   if (threadIdx.x == 0) {
     for (int k = 1; k < (int)(blockDim.x >> 6); ++k) v = fmin(v, smin[k]);
-    if (v < INFINITY) atomicMin(&dscal[0], (unsigned long long)__double_as_longlong(v));
+    if (v < INFINITY)
+      atomicMin(&dmin[(blockIdx.x % kCountSlots) * kSlotStride],
+                (unsigned long long)__double_as_longlong(v));
   }
+}
+
+// dscal[0] <- the minimum over the slots (one wave)
+__global__ void k_min_slots(const unsigned long long* __restrict__ dmin,
+                            unsigned long long* dscal) {
+  unsigned long long v = dmin[threadIdx.x * kSlotStride];
+  for (int off = 32; off > 0; off >>= 1) {
+    unsigned long long o = __shfl_xor(v, off, 64);
+    v = o < v ? o : v;
+  }
+  if (threadIdx.x == 0) dscal[0] = v;
 }
 
 __global__ void k_classify(int nc, const double* __restrict__ dt, const unsigned long long* dscal,
@@ -127,8 +143,9 @@ __global__ __launch_bounds__(kBlock) void k_cell_keys(int nc, const int* __restr
   int bin = i < nc ? cell_key_item(i, nc, nb, lev, ckey, fpack) : 0;
   wave_hist_add(h, i < nc, bin);
   __syncthreads();
+  int* hs = hist + (blockIdx.x % kCountSlots) * kMaxKeys;
   for (int k = threadIdx.x; k < kMaxKeys; k += blockDim.x)
-    if (h[k]) atomicAdd(&hist[k], h[k]);
+    if (h[k]) atomicAdd(&hs[k], h[k]);
 }
 
 // one buffer for the host readback at an iteration start: [0..5] the
@@ -142,7 +159,11 @@ __global__ void k_pack_readback(const unsigned long long* __restrict__ dscal,
   if (t < 6) out[t] = ((const int*)dscal)[t];
   if (t <= Kf) out[8 + t] = fstart[t];
   if (t <= kMaxLevels) out[8 + kMaxKeys + 1 + t] = cstart[t];
-  if (t < kMaxKeys) out[8 + kMaxKeys + kMaxLevels + 2 + t] = hist[t];
+  if (t < kMaxKeys) {
+    int sum = 0;
+    for (int sl = 0; sl < kCountSlots; ++sl) sum += hist[sl * kMaxKeys + t];
+    out[8 + kMaxKeys + kMaxLevels + 2 + t] = sum;
+  }
 }
 
 hipError_t launch_pack_readback(hipStream_t s, DevMesh& m, int Kf) {
@@ -401,8 +422,11 @@ hipError_t launch_fill_f64(hipStream_t s, double* p, double v, int64_t n) {
 }
 
 hipError_t launch_dt(hipStream_t s, DevMesh& m, const StepArgs& a) {
+  hipLaunchKernelGGL(k_fill_u64, dim3(blocks_for(kCounterWords)), dim3(kBlock), 0, s, m.dmin,
+                     0x7ff0000000000000ull, kCounterWords);  // +inf
   hipLaunchKernelGGL(k_dt, dim3(blocks_for(m.nc)), dim3(kBlock), 0, s, m.nc, m.nf, m.U, m.vol,
-                     m.c2f, m.fA, a.gas.g, a.cfl, m.dt, m.dscal);
+                     m.c2f, m.fA, a.gas.g, a.cfl, m.dt, m.dscal, m.dmin);
+  hipLaunchKernelGGL(k_min_slots, dim3(1), dim3(64), 0, s, m.dmin, m.dscal);
   return hipGetLastError();
 }
 
@@ -422,7 +446,8 @@ hipError_t launch_partitions(hipStream_t s, DevMesh& m) {
   int Kf = use_colour ? m.ncolours * kMaxLevels : kMaxLevels;
   hipLaunchKernelGGL(k_face_keys, dim3(blocks_for(m.nf)), dim3(kBlock), 0, s, m.nf, m.fhL, m.fhR,
                      m.fcol, m.lev, use_colour, m.fkey);
-  hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(kMaxKeys), 0, s, m.chist, 0, kMaxKeys);
+  hipLaunchKernelGGL(k_fill_i32, dim3(kCountSlots), dim3(kMaxKeys), 0, s, m.chist, 0,
+                     kCountSlots * kMaxKeys);
   hipLaunchKernelGGL(k_cell_keys, dim3(blocks_for(m.nc)), dim3(kBlock), 0, s, m.nc, m.nb_, m.lev,
                      m.ckey, m.fpack, m.chist);
   hipError_t e = run_partition(s, m.nf, ByteKey{m.fkey}, Kf, m.pf, FaceWriter{m.frec, m.fhL, m.fhR});

@@ -87,7 +87,8 @@ struct DevMesh {
   Partition pf, pc;        // faces by (colour, tau_f); cells by tau_g
   int8_t* fkey = nullptr;  // [nf] partition key of each face
   int8_t* ckey = nullptr;  // [nc] tau_g of each cell
-  int* chist = nullptr;    // [64] cell count per (tau_g, tau)
+  int* chist = nullptr;    // [kCounterSlots][64] cell count per (tau_g, tau), summed
+                           // over the slots by the readback kernel
   int* rb = nullptr;       // packed readback buffer
   uint32_t* fpack = nullptr; // [nc] per local face m: tau_f in bits 4m..4m+3, the cell
                            // is the higher-id side in bit 16+m; tau in bits 20..23
@@ -95,6 +96,8 @@ struct DevMesh {
   double* xfer = nullptr;  // [nc][5] staging for host transfers in caller order
   // device scalars: [0] dt_min bits, [1] theta, [2] non-finite flag
   unsigned long long* dscal = nullptr;
+  // per-block minima of dt (bits), spread over kCounterSlots slots
+  unsigned long long* dmin = nullptr;
   // device counters: newton updates, fallbacks, vacuum; wall impulse x3
   unsigned long long* dcount = nullptr;
   double* dimpulse = nullptr;
