@@ -185,18 +185,17 @@ struct GradArgs {
 // G = sum_m c_m (W_m - W_i); Barth-Jespersen per variable k: the largest
 // psi_k <= 1 keeping W_i + psi_k G_k . r_m inside [min, max] of the cell and
 // its neighbours at all 4 face centroids r_m; output W_i + psi_k G_k . r_m.
-template <typename T>
-__device__ inline void grad_item(const GradArgs<T>& a, int i) {
+// nbw(n, w): the primitive state of neighbour n (from U, or staged)
+template <typename T, typename NbW>
+__device__ inline void grad_item_w(const GradArgs<T>& a, int i, const double* wd, NbW nbw) {
   const int nc = a.nc;
-  double wd[5];
-  cons2prim(a.U + 5 * (size_t)i, a.gm1, wd);
   T wi[5], dw[4][5];
   for (int k = 0; k < 5; ++k) wi[k] = (T)wd[k];
   for (int m = 0; m < 4; ++m) {
     int n = a.nb[m * nc + i];
     if (n >= 0) {
       double t[5];
-      cons2prim(a.U + 5 * (size_t)n, a.gm1, t);
+      nbw(n, t);
       for (int k = 0; k < 5; ++k) dw[m][k] = (T)t[k] - wi[k];
     } else {
       for (int k = 0; k < 5; ++k) dw[m][k] = 0;
@@ -241,6 +240,13 @@ __device__ inline void grad_item(const GradArgs<T>& a, int i) {
     }
     for (int m = 0; m < 4; ++m) out[(size_t)(5 * m + k) * nc] = wi[k] + psi * delta[m];
   }
+}
+
+template <typename T>
+__device__ inline void grad_item(const GradArgs<T>& a, int i) {
+  double wd[5];
+  cons2prim(a.U + 5 * (size_t)i, a.gm1, wd);
+  grad_item_w(a, i, wd, [&](int n, double* t) { cons2prim(a.U + 5 * (size_t)n, a.gm1, t); });
 }
 
 // ---------------------------------------------------------------------------
