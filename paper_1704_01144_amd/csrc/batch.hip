@@ -122,6 +122,7 @@ __global__ __launch_bounds__(kBlock) void k_b_dt(const int32_t* __restrict__ rp,
                                                  const int* __restrict__ c2f,
                                                  const double* __restrict__ fA, double gamma,
                                                  double cfl, double* __restrict__ dt,
+                                                 double* __restrict__ tmin,
                                                  unsigned long long* flag) {
   STAGE_PREFIX(rp);
   __shared__ double smin[kBlock / 64];
@@ -142,8 +143,41 @@ __global__ __launch_bounds__(kBlock) void k_b_dt(const int32_t* __restrict__ rp,
     __syncthreads();
     if (threadIdx.x == 0) {
       for (int k = 1; k < kBlock / 64; ++k) v = fmin(v, smin[k]);
-      if (v < INFINITY) atomicMin(&S[m].dtbits, (unsigned long long)__double_as_longlong(v));
+      tmin[t] = v;  // the tile's minimum; k_b_reduce takes the mesh's
     }
+  }
+}
+
+// Per marked mesh (one block each): dt_min from its tiles' minima (tmin
+// given) or the (tau_g, tau) histogram from its tiles' histograms (thist
+// given), in place of per-tile atomics on the mesh's entry (which
+// serialised on large meshes).
+__global__ __launch_bounds__(256) void k_b_reduce(const int32_t* __restrict__ rp, BatchSched* S,
+                                                  int M, const double* __restrict__ tmin,
+                                                  const int* __restrict__ thist) {
+  __shared__ double sm[256];
+  __shared__ int sh[4][kMaxKeys];
+  const int m = blockIdx.x;
+  if (m >= M || !S[m].reclass) return;
+  const int t0 = rp[m], t1 = rp[m + 1], tid = threadIdx.x;
+  if (tmin) {
+    double v = INFINITY;
+    for (int t = t0 + tid; t < t1; t += 256) v = fmin(v, tmin[t]);
+    sm[tid] = v;
+    __syncthreads();
+    for (int off = 128; off > 0; off >>= 1) {
+      if (tid < off) sm[tid] = fmin(sm[tid], sm[tid + off]);
+      __syncthreads();
+    }
+    if (tid == 0) S[m].dtbits = (unsigned long long)__double_as_longlong(sm[0]);
+  }
+  if (thist) {
+    const int g = tid >> 6, k = tid & 63;  // 4 groups of 64 bins
+    int acc = 0;
+    for (int t = t0 + g; t < t1; t += 4) acc += thist[(size_t)t * kMaxKeys + k];
+    sh[g][k] = acc;
+    __syncthreads();
+    if (tid < kMaxKeys) S[m].hist[tid] = sh[0][tid] + sh[1][tid] + sh[2][tid] + sh[3][tid];
   }
 }
 
@@ -182,7 +216,8 @@ __global__ __launch_bounds__(kBlock) void k_b_cell_keys(const int32_t* __restric
                                                         const int* __restrict__ nb,
                                                         const int8_t* __restrict__ lev,
                                                         int8_t* __restrict__ ckey,
-                                                        uint32_t* __restrict__ fpack) {
+                                                        uint32_t* __restrict__ fpack,
+                                                        int* __restrict__ thist) {
   STAGE_PREFIX(rp);
   __shared__ int h[kMaxKeys];
   const int total = s_pre[M];
@@ -196,8 +231,7 @@ __global__ __launch_bounds__(kBlock) void k_b_cell_keys(const int32_t* __restric
     int bin = in ? cell_key_item(i, NC, nb, lev, ckey, fpack) : 0;
     wave_hist_add(h, in, bin);
     __syncthreads();
-    for (int k = threadIdx.x; k < kMaxKeys; k += blockDim.x)
-      if (h[k]) atomicAdd(&S[m].hist[k], h[k]);
+    for (int k = threadIdx.x; k < kMaxKeys; k += blockDim.x) thist[(size_t)t * kMaxKeys + k] = h[k];
   }
 }
 
@@ -669,6 +703,8 @@ tafv_status build(tafv_ctx* c) {
   for (int32_t** p : {&B.ct, &B.ft, &B.cc, &B.fc}) chk(hipMalloc(p, sizeof(int32_t) * (M + 1)));
   chk(hipMalloc(&B.tp, sizeof(int32_t) * 3 * (M + 1)));
   chk(hipMalloc(&B.rp, sizeof(int32_t) * 4 * (M + 1)));
+  chk(hipMalloc(&B.tmin, sizeof(double) * std::max(B.n_ct, 1)));
+  chk(hipMalloc(&B.thist, sizeof(int) * kMaxKeys * std::max(B.n_ct, 1)));
   chk(hipMalloc(&B.cnt_c, sizeof(int32_t) * kMaxLevels * std::max(B.n_cc, 1)));
   chk(hipMalloc(&B.cnt_f, sizeof(int32_t) * kMaxLevels * std::max(B.n_fc, 1)));
   if (e != hipSuccess) return hip_error(c, e, "batch allocation");
@@ -741,7 +777,9 @@ hipError_t run_reclass(tafv_ctx* c, hipStream_t s) {
   hipLaunchKernelGGL(k_b_begin, dim3(1), dim3(1024), 0, s, B.dsched, M, c->prm.reclassify, B.ct,
                      B.ft, B.cc, B.fc, B.rp);
   hipLaunchKernelGGL(k_b_dt, dim3(G), dim3(kBlock), lds, s, rc, B.dsched, M, m.nc, m.nf, m.U,
-                     m.vol, m.c2f, m.fA, c->prm.gamma, c->prm.cfl, m.dt, flag);
+                     m.vol, m.c2f, m.fA, c->prm.gamma, c->prm.cfl, m.dt, B.tmin, flag);
+  hipLaunchKernelGGL(k_b_reduce, dim3(M), dim3(256), 0, s, rc, B.dsched, M, B.tmin,
+                     (const int*)nullptr);
   hipLaunchKernelGGL(k_b_classify, dim3(G), dim3(kBlock), lds, s, rc, B.dsched, M, m.dt,
                      c->prm.level_margin, m.lev);
   // lowering sweeps: an even count >= lmax - 1 leaves the result in lev
@@ -754,7 +792,8 @@ hipError_t run_reclass(tafv_ctx* c, hipStream_t s) {
                        m.nb_, src, dst);
   }
   hipLaunchKernelGGL(k_b_cell_keys, dim3(G), dim3(kBlock), lds, s, rc, B.dsched, M, m.nc, m.nb_,
-                     m.lev, m.ckey, m.fpack);
+                     m.lev, m.ckey, m.fpack, B.thist);
+  hipLaunchKernelGGL(k_b_reduce, dim3(M), dim3(256), 0, s, rc, B.dsched, M, nullptr, B.thist);
   hipLaunchKernelGGL(k_b_face_keys, dim3(G), dim3(kBlock), lds, s, rf, B.dsched, M, m.fhL, m.fhR,
                      m.lev, m.fkey);
   const int PG = 4 * G;  // 64-thread blocks
@@ -1398,7 +1437,7 @@ void batch_free(tafv_ctx* c) {
   Batch& B = *c->batch;
   drop_graphs(B);
   for (HostMesh* h : B.hosts) delete h;
-  void* ptrs[] = {B.dsched, B.ct, B.ft, B.cc, B.fc, B.cnt_f, B.cnt_c, B.tp, B.rp};
+  void* ptrs[] = {B.dsched, B.ct, B.ft, B.cc, B.fc, B.cnt_f, B.cnt_c, B.tp, B.rp, B.tmin, B.thist};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   if (B.m) free_dev_mesh(B.m);

@@ -157,6 +157,8 @@ struct Batch {
   int32_t *cnt_f = nullptr, *cnt_c = nullptr;  // [8 * chunks] counts, then offsets
   int32_t* tp = nullptr;              // [3][nmesh + 1] tiles: gradient, flux, cells
   int32_t* rp = nullptr;              // [4][nmesh + 1] reclassification tiles and chunks
+  double* tmin = nullptr;             // [cell tiles] per-tile minimum of dt
+  int* thist = nullptr;               // [cell tiles][64] per-tile level histogram
   int32_t lmax = 1;
   LaunchSet set[3];                   // gradient, flux (fixed: one tile per
                                       // block over all face tiles), cells
