@@ -249,6 +249,27 @@ def roofline(prof, bytes_per_item, dtype):
                  "algorithmic_bytes_per_launch": int(bytes_per_item[dom] * p["items"] / launches)}
 
 
+def copy_bandwidth(torch, nbytes=1 << 30, reps=5):
+    """Read + write GB/s of a plain device-to-device copy of nbytes, timed
+    with events: the practical ceiling the kernels' traffic compares to."""
+    x = torch.ones(nbytes // 8, dtype=torch.float64, device="cuda")
+    y = torch.empty_like(x)
+    y.copy_(x)
+    stream = torch.cuda.current_stream()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    ev0.record(stream)
+    for _ in range(reps):
+        y.copy_(x)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    ms = ev0.elapsed_time(ev1) / reps
+    del x, y
+    torch.cuda.empty_cache()
+    return 2.0 * nbytes / (ms * 1e-3) / 1e9
+
+
 def copy_probe():
     """A plain device-to-device copy of 1 GiB, three times: the known-size
     kernel that the FETCH_SIZE / WRITE_SIZE counters are scaled by."""
@@ -326,6 +347,15 @@ def main():
     log(f"fp64: {r64['ms']:.2f} ms for {args.steps} steps, {value / 1e9:.3f} G cell-updates/s")
     bpi = BYTES_PER_ITEM_GATHER if args.scatter == 1 else BYTES_PER_ITEM
     dom, roof = roofline(r64["prof"], bpi["fp64"], "fp64")
+    copy_gbs = copy_bandwidth(torch)
+    roof["copy_gbs_measured"] = round(copy_gbs, 1)
+    roof["frac_of_copy"] = round(roof["achieved"] / copy_gbs, 4)
+    if roof["traffic"] is not None:
+        tgbs = roof["traffic"] / (roof["avg_launch_us"] * 1e-6) / 1e9
+        roof["traffic_gbs"] = round(tgbs, 1)
+        roof["traffic_frac_of_copy"] = round(tgbs / copy_gbs, 4)
+    log(f"copy: {copy_gbs:.0f} GB/s read+write; dominant kernel {roof['kernel']} at "
+        f"{roof['achieved']:.0f} GB/s algorithmic ({roof['frac']:.3f} of 8 TB/s)")
     out = {
         "metric": "cell-updates/s, 1.57M-tet graded mesh: FP64 plain vs FP32+learned @ L1 err",
         "value": round(value, 1),
