@@ -54,11 +54,12 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def run_form(T, torch, cfg, precision, steps, warmup, scatter, mlp=None):
+def run_form(T, torch, cfg, precision, steps, warmup, scatter, mlp=None, stats=0):
     stream = torch.cuda.current_stream()
     extra = {}
     if mlp is not None:
-        extra = dict(guess=T.GUESS_MLP, guess_stats=1, guess_gate=mlp["gate"])
+        extra = dict(guess=T.GUESS_MLP, guess_stats=stats, guess_gate=mlp["gate"],
+                     guess_strength=mlp["strength"])
     s = T.Solver(device=0, hip_stream=stream.cuda_stream, max_levels=cfg["max_levels"],
                  order=cfg["order"], precision=precision, scatter=scatter, **extra)
     s.upload(cfg["nodes"], cfg["tets"])
@@ -107,7 +108,8 @@ def run_form(T, torch, cfg, precision, steps, warmup, scatter, mlp=None):
                 stats=st1, cons=cons, levels=lev,
                 gated=st1["guess_faces"] - st0["guess_faces"],
                 gated_newton=st1["guess_newton_updates"] - st0["guess_newton_updates"],
-                used=st1["guess_used"] - st0["guess_used"])
+                used=st1["guess_used"] - st0["guess_used"],
+                evaluated=st1["guess_evaluated"] - st0["guess_evaluated"])
 
 
 def train_guess(T, torch, I, n, train_seeds=(1, 2, 3, 4, 5), rows_per_seed=400000):
@@ -134,6 +136,12 @@ def train_guess(T, torch, I, n, train_seeds=(1, 2, 3, 4, 5), rows_per_seed=40000
                             seed=11)
     train_s = time.perf_counter() - t0
     theta = T.tafv_mlp_get(s.ctx)
+    # strength pre-gate: the network is worth evaluating where the
+    # two-rarefaction value is off by more than 2%; take the jump strength
+    # |u_R - u_L|/a_m + |p_L - p_R|/p_m that keeps 90% of those training rows
+    strength = 2.0 * (np.abs(rows[:, 1]) + np.abs(rows[:, 2]))
+    useful = np.abs(rows[:, 6]) > 0.02
+    s0 = float(np.quantile(strength[useful], 0.1)) if useful.any() else float("inf")
     # gate: mean Newton updates per inexact-TR face on the first training seed
     prim = I.blast_state(cfg["nodes"], cfg["tets"], centre=I.blast_centre(train_seeds[0]))
     T.tafv_facelog_config(s.ctx, 0, 0.0, 0)
@@ -142,13 +150,14 @@ def train_guess(T, torch, I, n, train_seeds=(1, 2, 3, 4, 5), rows_per_seed=40000
         if gate is None:
             T.tafv_guess_config(s.ctx, T.GUESS_TR, 0.0, 1)
         else:
-            T.tafv_guess_config(s.ctx, T.GUESS_MLP, gate, 1)
+            T.tafv_guess_config(s.ctx, T.GUESS_MLP, gate, 1, strength=s0)
         s.init(prim)
         st = T.tafv_advance(s.ctx, UNITS)
         per_gate["tr" if gate is None else gate] = st["guess_newton_updates"] / max(st["guess_faces"], 1)
     s.close()
     best = min((g for g in per_gate if g != "tr"), key=lambda g: per_gate[g])
-    return dict(theta=theta, gate=best, rows=int(len(rows)), train_s=round(train_s, 3),
+    return dict(theta=theta, gate=best, strength=s0, rows=int(len(rows)),
+                rows_useful=int(useful.sum()), train_s=round(train_s, 3),
                 loss_first=float(loss[0]), loss_last=float(loss[-1]),
                 newton_per_inexact_face={str(k): round(v, 4) for k, v in per_gate.items()})
 
@@ -163,7 +172,7 @@ def run_batch(T, torch, cases, steps, warmup, precision, mlp=None, graph=1):
     stream = torch.cuda.current_stream()
     extra = {}
     if mlp is not None:
-        extra = dict(guess=T.GUESS_MLP, guess_stats=1, guess_gate=mlp["gate"])
+        extra = dict(guess=T.GUESS_MLP, guess_gate=mlp["gate"], guess_strength=mlp["strength"])
     t0 = time.perf_counter()
     s = T.Solver(device=0, hip_stream=stream.cuda_stream, batch=1, order=2,
                  precision=precision, **extra)
@@ -181,7 +190,7 @@ def run_batch(T, torch, cases, steps, warmup, precision, mlp=None, graph=1):
     ev0 = torch.cuda.Event(enable_timing=True)
     ev1 = torch.cuda.Event(enable_timing=True)
     tot = dict(cell_updates=0, face_solves=0, newton_updates=0, guess_faces=0,
-               guess_newton_updates=0, guess_used=0)
+               guess_newton_updates=0, guess_used=0, guess_evaluated=0)
     torch.cuda.synchronize()
     ev0.record(stream)
     for _ in range(steps):
@@ -397,6 +406,9 @@ def main():
             log("learned guess: logging seeds 1-5, training, gate choice ...")
             g = train_guess(T, torch, I, args.n)
             rl = run_form(T, torch, cfg, T.FP32_FLUX, args.steps, args.warmup, args.scatter, mlp=g)
+            # the Newton counts on the faces where two-rarefaction is inexact
+            # come from a run with statistics (they cost a little time)
+            rs = run_form(T, torch, cfg, T.FP32_FLUX, 1, 0, args.scatter, mlp=g, stats=1)
             vl = rl["updates"] / (rl["ms"] * 1e-3)
             el = l1_errors(cfg, r64["cons"], rl["cons"])
             out["forms"]["fp32_learned"] = {
@@ -405,9 +417,11 @@ def main():
                 "gate": g["gate"], "train_rows": g["rows"], "train_seconds": g["train_s"],
                 "train_loss_first_last": [g["loss_first"], g["loss_last"]],
                 "newton_per_inexact_tr_face_by_gate": g["newton_per_inexact_face"],
-                "eval_newton_per_inexact_face": round(rl["gated_newton"] / max(rl["gated"], 1), 4),
-                "eval_faces_started_by_network": rl["used"],
-                "newton_per_face_all": round(rl["newton"] / max(rl["faces"], 1), 4)}
+                "strength_pregate": round(g["strength"], 5), "train_rows_tr_off_2pct": g["rows_useful"],
+                "eval_newton_per_inexact_face": round(rs["gated_newton"] / max(rs["gated"], 1), 4),
+                "eval_faces_network_evaluated_per_step": rs["evaluated"],
+                "eval_faces_started_by_network_per_step": rs["used"],
+                "newton_per_face_all": round(rs["newton"] / max(rs["faces"], 1), 4)}
             log(f"fp32 + learned: {vl / 1e9:.3f} G/s, gate {g['gate']}, "
                 f"per-gate updates {g['newton_per_inexact_face']}")
     if not args.no_batch and not args.no_fp32 and not args.no_learned and args.scatter == 1:
@@ -426,7 +440,8 @@ def main():
             "fp32_learned": {"value": round(vl, 1), "ms_per_step": round(bl["ms"] / args.steps, 4),
                              "cell_updates_per_step": bl["cell_updates"] // args.steps,
                              "face_solves_per_step": bl["face_solves"] // args.steps,
-                             "faces_started_by_network": bl["guess_used"] // args.steps,
+                             "faces_network_evaluated_per_step": bl["guess_evaluated"] // args.steps,
+                             "faces_started_by_network_per_step": bl["guess_used"] // args.steps,
                              "l1_max_over_meshes_rho_E": batch_l1(cases, b64["cons"], bl["cons"]),
                              "launch": bl["info"], "setup_s": round(bl["setup_s"], 1)},
             "fp64": {"value": round(v64, 1), "ms_per_step": round(b64["ms"] / args.steps, 4),

@@ -83,7 +83,7 @@ enum { TAFV_ORDER_CALLER = 0, TAFV_ORDER_MORTON = 1 };
  * newton_tol 1e-12, level_margin 1e-9, max_levels 5, order 2, precision
  * TAFV_FP64, guess TAFV_GUESS_TR, boundary TAFV_BC_WALL, newton_max_iter
  * 50, reclassify 1, scatter TAFV_SCATTER_GATHER, cell_order TAFV_ORDER_CALLER,
- * guess_stats 0, guess_gate 0, batch 0. */
+ * guess_stats 0, guess_gate 0, batch 0, guess_strength 0. */
 typedef struct {
   double gamma;          /* ratio of specific heats, > 1                        */
   double cfl;            /* dt_i = cfl V_i / sum_f (|u_i . n_f| + a_i) |A_f|    */
@@ -122,6 +122,11 @@ typedef struct {
                             tafv_batch_config()).  Meshes must all be uploaded
                             before the first tafv_state_init(); checkpoints
                             and face logging are not available.              */
+  double guess_strength; /* learned guess: the network is evaluated only on
+                            faces whose jump strength |u_R - u_L|/a_m +
+                            |p_L - p_R|/p_m is at least this (>= 0; 0: every
+                            face where p_TR is inexact).  A wave evaluates
+                            the network once if any of its faces qualifies. */
 } tafv_params;
 
 /* Counters (int64) and schedule state.  Summed over meshes where a call
@@ -143,6 +148,7 @@ typedef struct {
   int64_t guess_newton_updates; /* Newton updates on those faces               */
   int64_t guess_rejected;  /* network guesses rejected (non-finite or <= 0)    */
   int64_t guess_used;      /* face solves started from the network's guess     */
+  int64_t guess_evaluated; /* faces the network was evaluated for             */
 } tafv_stats;
 
 /* Fill *p with the defaults listed above. */
@@ -247,8 +253,9 @@ tafv_status tafv_checkpoint_write(tafv_ctx* ctx, int32_t mesh_id, const double* 
 #define TAFV_MLP_PARAMS 1313
 
 /* Change the guess settings of a context (params.guess, guess_gate,
- * guess_stats) between tafv_advance() calls. */
-tafv_status tafv_guess_config(tafv_ctx* ctx, int32_t guess, double gate, int32_t stats);
+ * guess_strength, guess_stats) between tafv_advance() calls. */
+tafv_status tafv_guess_config(tafv_ctx* ctx, int32_t guess, double gate, double strength,
+                              int32_t stats);
 
 /* Set / read the FP32 parameters (n must be TAFV_MLP_PARAMS).  Setting
  * resets the optimiser state. */

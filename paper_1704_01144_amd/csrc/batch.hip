@@ -483,7 +483,7 @@ __global__ __launch_bounds__(kBlock) void k_b_flux(const int32_t* __restrict__ t
                                                    const BatchSched* S, int M, FluxArgs<T> a) {
   const int t = xcd_block();
   if (t >= tp[M]) return;
-  SolveInfo info{0, 0, 0, 0, 0, 0, 0};
+  SolveInfo info{0, 0, 0, 0, 0, 0, 0, 0};
   double i0 = 0, i1 = 0, i2 = 0;
   int m = find_mesh(tp, M, t);
   int j = (t - tp[m]) * kBlock + threadIdx.x;
@@ -499,7 +499,7 @@ __global__ __launch_bounds__(kBlock) void k_b_flux_feat(const int32_t* __restric
   __shared__ __attribute__((aligned(16))) uint16_t lds[(FEAT & 2) ? (kBlock / 64) * kMlpFwdLds : 8];
   const int t = xcd_block();
   if (t >= tp[M]) return;
-  SolveInfo info{0, 0, 0, 0, 0, 0, 0};
+  SolveInfo info{0, 0, 0, 0, 0, 0, 0, 0};
   double i0 = 0, i1 = 0, i2 = 0;
   int m = find_mesh(tp, M, t);
   int j = (t - tp[m]) * kBlock + threadIdx.x;
@@ -737,6 +737,7 @@ FluxFeatures features(tafv_ctx* c) {
   ft.feat = (c->prm.guess_stats ? 1 : 0) | (mlp ? 2 : 0);
   ft.mlp = (const MlpDev*)c->mlp_w;
   ft.guess_gate = (float)c->prm.guess_gate;
+  ft.guess_strength = (float)c->prm.guess_strength;
   return ft;
 }
 
@@ -885,12 +886,12 @@ hipError_t run_flux(tafv_ctx* c, hipStream_t s, const Ptrs& p) {
   if (c->prm.precision == TAFV_FP32_FLUX) {
     FluxArgs<float> f{m.frec, 0, m.nf, m.nc, m.fA32, m.U, (const float*)m.Wf, m.R, (float*)m.Q,
                       p.dcount, p.dimpulse, a, ft.mlp, nullptr, nullptr, 0, 0.0, 0, 0,
-                      ft.guess_gate};
+                      ft.guess_gate, ft.guess_strength};
     flux_dispatch<float>(s, B, c->prm.order, ft.feat, a.gas.is14, grid, f);
   } else {
     FluxArgs<double> f{m.frec, 0, m.nf, m.nc, m.fA, m.U, (const double*)m.Wf, m.R, (double*)m.Q,
                        p.dcount, p.dimpulse, a, ft.mlp, nullptr, nullptr, 0, 0.0, 0, 0,
-                       ft.guess_gate};
+                       ft.guess_gate, ft.guess_strength};
     flux_dispatch<double>(s, B, c->prm.order, ft.feat, a.gas.is14, grid, f);
   }
   return hipGetLastError();
@@ -1351,6 +1352,7 @@ tafv_status batch_advance(tafv_ctx* c, int64_t n, tafv_stats* out) {
     acc.guess_newton_updates = now.guess_newton_updates - B.last.guess_newton_updates;
     acc.guess_rejected = now.guess_rejected - B.last.guess_rejected;
     acc.guess_used = now.guess_used - B.last.guess_used;
+    acc.guess_evaluated = now.guess_evaluated - B.last.guess_evaluated;
     for (int k = 0; k < 3; ++k) acc.wall_impulse[k] = now.wall_impulse[k] - B.last.wall_impulse[k];
     *out = acc;
   }

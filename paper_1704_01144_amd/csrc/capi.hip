@@ -154,6 +154,7 @@ FluxFeatures flux_features(tafv_ctx* c, DevMesh& m) {
   ft.log_seed = c->log_seed;
   ft.subit = (unsigned long long)m.st.subiterations;
   ft.guess_gate = (float)c->prm.guess_gate;
+  ft.guess_strength = (float)c->prm.guess_strength;
   return ft;
 }
 
@@ -251,10 +252,10 @@ tafv_status read_slot_counters(tafv_ctx* c, DevMesh& m, tafv_stats* st) {
   HIP_TRY(c, hipMemcpyAsync(imp.data(), m.dimpulse, kCounterWords * sizeof(double),
                             hipMemcpyDeviceToHost, c->stream));
   HIP_TRY(c, hipStreamSynchronize(c->stream));
-  unsigned long long tot[7] = {0, 0, 0, 0, 0, 0, 0};
+  unsigned long long tot[8] = {0, 0, 0, 0, 0, 0, 0, 0};
   double itot[3] = {0, 0, 0};
   for (int sl = 0; sl < kCounterSlots; ++sl) {
-    for (int k = 0; k < 7; ++k) tot[k] += cnt[sl * kCounterStride + k];
+    for (int k = 0; k < 8; ++k) tot[k] += cnt[sl * kCounterStride + k];
     for (int k = 0; k < 3; ++k) itot[k] += imp[sl * kCounterStride + k];
   }
   st->newton_updates = (int64_t)tot[0];
@@ -264,6 +265,7 @@ tafv_status read_slot_counters(tafv_ctx* c, DevMesh& m, tafv_stats* st) {
   st->guess_newton_updates = (int64_t)tot[4];
   st->guess_rejected = (int64_t)tot[5];
   st->guess_used = (int64_t)tot[6];
+  st->guess_evaluated = (int64_t)tot[7];
   for (int k = 0; k < 3; ++k) st->wall_impulse[k] = itot[k];
   return TAFV_OK;
 }
@@ -385,6 +387,7 @@ tafv_status tafv_params_default(tafv_params* p) {
   p->guess_stats = 0;
   p->guess_gate = 0.0;
   p->batch = 0;
+  p->guess_strength = 0.0;
   return TAFV_OK;
 }
 
@@ -405,6 +408,7 @@ tafv_status tafv_create(int device, const tafv_params* params, void* hip_stream,
   if (p.guess != TAFV_GUESS_TR && p.guess != TAFV_GUESS_MLP)
     return fail(nullptr, TAFV_E_ARG, "unknown guess mode");
   if (!(p.guess_gate >= 0.0)) return fail(nullptr, TAFV_E_ARG, "negative guess gate");
+  if (!(p.guess_strength >= 0.0)) return fail(nullptr, TAFV_E_ARG, "negative guess strength");
   if (p.batch != 0 && p.batch != 1) return fail(nullptr, TAFV_E_ARG, "batch must be 0 or 1");
   if (p.batch && p.scatter != TAFV_SCATTER_GATHER)
     return fail(nullptr, TAFV_E_ARG, "the batched form needs gather scatter");
@@ -624,6 +628,7 @@ tafv_status tafv_advance(tafv_ctx* c, int64_t n, tafv_stats* out) {
       acc.guess_newton_updates += m->st.guess_newton_updates;
       acc.guess_rejected += m->st.guess_rejected;
       acc.guess_used += m->st.guess_used;
+      acc.guess_evaluated += m->st.guess_evaluated;
       for (int k = 0; k < 3; ++k) acc.wall_impulse[k] += m->st.wall_impulse[k];
     }
     *out = acc;
@@ -734,14 +739,17 @@ tafv_status tafv_checkpoint_write(tafv_ctx* c, int32_t mesh_id, const double* co
   return TAFV_OK;
 }
 
-tafv_status tafv_guess_config(tafv_ctx* c, int32_t guess, double gate, int32_t stats) {
+tafv_status tafv_guess_config(tafv_ctx* c, int32_t guess, double gate, double strength,
+                              int32_t stats) {
   if (!c) return TAFV_E_ARG;
   if (guess != TAFV_GUESS_TR && guess != TAFV_GUESS_MLP) return fail(c, TAFV_E_ARG, "unknown guess");
   if (!(gate >= 0.0)) return fail(c, TAFV_E_ARG, "negative guess gate");
+  if (!(strength >= 0.0)) return fail(c, TAFV_E_ARG, "negative guess strength");
   if (guess == TAFV_GUESS_MLP && (c->prm.gamma != 1.4 || c->prm.scatter != TAFV_SCATTER_GATHER))
     return fail(c, TAFV_E_ARG, "the learned guess needs gamma 1.4 and gather scatter");
   c->prm.guess = guess;
   c->prm.guess_gate = gate;
+  c->prm.guess_strength = strength;
   c->prm.guess_stats = stats != 0;
   if (c->batch) batch_invalidate(c);
   return TAFV_OK;

@@ -33,6 +33,7 @@ struct FluxFeatures {
   double log_rate = 0.0;
   unsigned long long log_seed = 0, subit = 0;
   float guess_gate = 0.f;
+  float guess_strength = 0.f;
 };
 hipError_t launch_flux(hipStream_t s, DevMesh& m, const StepArgs& a, int first, int count,
                        const FluxFeatures& ft);

@@ -316,7 +316,7 @@ __global__ __launch_bounds__(kBlock) void k_grad(GradArgs<T> a) {
 template <int ORDER, typename T, bool G14>
 __global__ __launch_bounds__(kBlock) void k_flux_colour(FluxArgs<T> a) {
   int idx = xcd_block() * kBlock + threadIdx.x;
-  SolveInfo info{0, 0, 0, 0, 0, 0, 0};
+  SolveInfo info{0, 0, 0, 0, 0, 0, 0, 0};
   double i0 = 0, i1 = 0, i2 = 0;
   if (idx < a.count) {
     int4 r = a.rec[idx];
@@ -352,7 +352,7 @@ __global__ __launch_bounds__(kBlock) void k_flux_colour(FluxArgs<T> a) {
 template <int ORDER, typename T, bool G14>
 __global__ __launch_bounds__(kBlock) void k_flux_store(FluxArgs<T> a) {
   int idx = xcd_block() * kBlock + threadIdx.x;
-  SolveInfo info{0, 0, 0, 0, 0, 0, 0};
+  SolveInfo info{0, 0, 0, 0, 0, 0, 0, 0};
   double i0 = 0, i1 = 0, i2 = 0;
   if (idx < a.count) flux_store_item<ORDER, T, G14>(a, a.rec[idx], a.s.dt_min, info, i0, i1, i2);
   flush_counters(info, i0, i1, i2, a.dcount, a.dimpulse);
@@ -365,7 +365,7 @@ __global__ __launch_bounds__(kBlock) void k_flux_feat(FluxArgs<T> a) {
   __shared__ __attribute__((aligned(16))) uint16_t lds[(FEAT & 2) ? (kBlock / 64) * kMlpFwdLds : 8];
   int idx = xcd_block() * kBlock + threadIdx.x;
   const bool valid = idx < a.count;
-  SolveInfo info{0, 0, 0, 0, 0, 0, 0};
+  SolveInfo info{0, 0, 0, 0, 0, 0, 0, 0};
   double i0 = 0, i1 = 0, i2 = 0;
   int4 r = valid ? a.rec[idx] : make_int4(0, 0, -1, 0);
   flux_feat_item<ORDER, T, FEAT>(a, valid, r, a.s.dt_min, lds + (threadIdx.x >> 6) * kMlpFwdLds,
@@ -580,7 +580,7 @@ hipError_t launch_flux(hipStream_t s, DevMesh& m, const StepArgs& a, int first, 
   if (a.precision == TAFV_FP32_FLUX) {
     FluxArgs<float> f{rec, count, m.nf, m.nc, m.fA32, m.U, (const float*)m.Wf, m.R, (float*)m.Q, m.dcount,
                       m.dimpulse, a, ft.mlp, ft.log_rows, ft.log_count, ft.log_cap,
-                      ft.log_rate, ft.log_seed, ft.subit, ft.guess_gate};
+                      ft.log_rate, ft.log_seed, ft.subit, ft.guess_gate, ft.guess_strength};
     if (ft.feat && a.gas.is14 && m.scatter == TAFV_SCATTER_GATHER)
       flux_feat_launch<float>(s, a.order, ft.feat, count, f);
     else if (a.gas.is14) flux_launch<float, true>(s, a.order, m.scatter, count, f);
@@ -588,7 +588,7 @@ hipError_t launch_flux(hipStream_t s, DevMesh& m, const StepArgs& a, int first, 
   } else {
     FluxArgs<double> f{rec, count, m.nf, m.nc, m.fA, m.U, (const double*)m.Wf, m.R, (double*)m.Q,
                        m.dcount, m.dimpulse, a, ft.mlp, ft.log_rows, ft.log_count, ft.log_cap,
-                       ft.log_rate, ft.log_seed, ft.subit, ft.guess_gate};
+                       ft.log_rate, ft.log_seed, ft.subit, ft.guess_gate, ft.guess_strength};
     if (ft.feat && a.gas.is14 && m.scatter == TAFV_SCATTER_GATHER)
       flux_feat_launch<double>(s, a.order, ft.feat, count, f);
     else if (a.gas.is14) flux_launch<double, true>(s, a.order, m.scatter, count, f);

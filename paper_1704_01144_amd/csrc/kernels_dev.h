@@ -272,6 +272,7 @@ struct FluxArgs {
   double log_rate;
   unsigned long long log_seed, subit;
   float guess_gate;
+  float guess_strength;  // network only where the jump strength reaches this
 };
 
 template <int ORDER, typename T>
@@ -289,6 +290,7 @@ __device__ inline void load_side(const FluxArgs<T>& a, int h, T* w) {
 struct SolveInfo {
   int iters, fallback, vacuum;
   int gated, gated_iters, rejected, used;  // faces where two-rarefaction is inexact
+  int evaluated;                           // faces the network was evaluated for
 };
 
 __device__ inline void add_info(SolveInfo& a, const SolveInfo& b) {
@@ -299,6 +301,7 @@ __device__ inline void add_info(SolveInfo& a, const SolveInfo& b) {
   a.gated_iters += b.gated_iters;
   a.rejected += b.rejected;
   a.used += b.used;
+  a.evaluated += b.evaluated;
 }
 
 // |A| F(W(0)) . n for one face: reconstructed states, rotation to the face
@@ -394,20 +397,20 @@ __device__ inline void face_flux(const FluxArgs<T>& a, int4 r, T* phi, SolveInfo
 // by all its threads.
 __device__ inline void flush_counters(const SolveInfo& info, double i0, double i1, double i2,
                                       unsigned long long* dcount, double* dimpulse) {
-  __shared__ int s_cnt[7];
+  __shared__ int s_cnt[8];
   __shared__ double s_imp[3];
   __syncthreads();  // a previous call's readers are done
-  if (threadIdx.x < 7) s_cnt[threadIdx.x] = 0;
+  if (threadIdx.x < 8) s_cnt[threadIdx.x] = 0;
   if (threadIdx.x < 3) s_imp[threadIdx.x] = 0.0;
   __syncthreads();
-  int c[7] = {wave_sum(info.iters), wave_sum(info.fallback), wave_sum(info.vacuum),
+  int c[8] = {wave_sum(info.iters), wave_sum(info.fallback), wave_sum(info.vacuum),
               wave_sum(info.gated), wave_sum(info.gated_iters), wave_sum(info.rejected),
-              wave_sum(info.used)};
+              wave_sum(info.used), wave_sum(info.evaluated)};
   i0 = wave_sum(i0);
   i1 = wave_sum(i1);
   i2 = wave_sum(i2);
   if ((threadIdx.x & 63) == 0) {
-    for (int k = 0; k < 7; ++k)
+    for (int k = 0; k < 8; ++k)
       if (c[k]) atomicAdd(&s_cnt[k], c[k]);
     if (i0 != 0.0 || i1 != 0.0 || i2 != 0.0) {
       atomicAdd(&s_imp[0], i0);
@@ -418,7 +421,7 @@ __device__ inline void flush_counters(const SolveInfo& info, double i0, double i
   __syncthreads();
   if (threadIdx.x == 0) {
     unsigned long long* cs = dcount + (blockIdx.x % kCountSlots) * kSlotStride;
-    for (int k = 0; k < 7; ++k)
+    for (int k = 0; k < 8; ++k)
       if (s_cnt[k]) atomicAdd(&cs[k], (unsigned long long)s_cnt[k]);
     if (s_imp[0] != 0.0 || s_imp[1] != 0.0 || s_imp[2] != 0.0) {
       double* d = dimpulse + (blockIdx.x % kCountSlots) * kSlotStride;
@@ -435,7 +438,7 @@ __device__ inline void flush_counters(const SolveInfo& info, double i0, double i
 template <int ORDER, typename T, bool G14>
 __device__ inline void flux_store_item(const FluxArgs<T>& a, int4 r, double dt_min,
                                        SolveInfo& acc, double& i0, double& i1, double& i2) {
-  SolveInfo info{0, 0, 0, 0, 0, 0, 0};
+  SolveInfo info{0, 0, 0, 0, 0, 0, 0, 0};
   T phi[5];
   face_flux<ORDER, T, G14>(a, r, phi, info);
   add_info(acc, info);
@@ -462,11 +465,12 @@ __device__ inline unsigned long long mix64(unsigned long long z) {
 //   FEAT & 1: statistics of the faces where the two-rarefaction start is
 //             inexact (p_TR > min(p_L, p_R), at least one shock) and face
 //             logging of a hashed sample of them (inputs and ln(p*/p_TR));
-//   FEAT & 2: on those faces the network predicts y ~ ln(p*/p_TR); where
-//             |y| exceeds the gate the Newton solve starts from p_TR exp(y)
-//             (a non-finite or non-positive guess falls back to p_TR).  The
-//             network runs once per wave, on the matrix cores, when any lane
-//             of the wave needs it.
+//   FEAT & 2: on those faces whose jump strength |u_R - u_L|/a_m +
+//             |p_L - p_R|/p_m reaches guess_strength, the network predicts
+//             y ~ ln(p*/p_TR); where |y| exceeds the gate the Newton solve
+//             starts from p_TR exp(y) (a non-finite or non-positive guess
+//             falls back to p_TR).  The network runs once per wave, on the
+//             matrix cores, when any lane of the wave needs it.
 // The Newton iteration and its stop test are unchanged, so p* is the same
 // root whichever start is used.  All 64 lanes of a wave must call this
 // together (valid = false for lanes without a face); wave_lds is this
@@ -476,10 +480,10 @@ __device__ inline void flux_feat_item(const FluxArgs<T>& a, bool valid, int4 r, 
                                       uint16_t* wave_lds, SolveInfo& acc, double& i0,
                                       double& i1, double& i2) {
   const Gas& G = a.s.gas;
-  SolveInfo info{0, 0, 0, 0, 0, 0, 0};
+  SolveInfo info{0, 0, 0, 0, 0, 0, 0, 0};
   T wl[5] = {1, 0, 0, 0, 1}, wr[5] = {1, 0, 0, 0, 1};
   T am = 1, nx = 1, ny = 0, nz = 0, unl = 0, unr = 0;
-  bool wall = false, transmit = false, vac = false, gate = false;
+  bool wall = false, transmit = false, vac = false, gate = false, net = false;
   double al = 1, ar = 1, ral = 1, rar = 1, ptr = -1.0, pm = 1.0;
   K14 KL{}, KR{};
   float x[kMlpIn] = {0, 0, 0, 0, 0, 0};
@@ -537,11 +541,12 @@ __device__ inline void flux_feat_item(const FluxArgs<T>& a, bool valid, int4 r, 
         x[3] = (float)-dr;
         x[4] = (float)-du;
         x[5] = (float)-dp;
+        net = 2.f * (fabsf(x[1]) + fabsf(x[2])) >= a.guess_strength;
       }
     }
   }
   float ym = 0.f;
-  if ((FEAT & 2) && __ballot(gate) != 0ull) ym = mlp_wave_forward(*a.mlp, x, wave_lds);
+  if ((FEAT & 2) && __ballot(net) != 0ull) ym = mlp_wave_forward(*a.mlp, x, wave_lds);
   if (valid) {
     T phi[5];
     if (transmit) {
@@ -553,7 +558,8 @@ __device__ inline void flux_feat_item(const FluxArgs<T>& a, bool valid, int4 r, 
       phi[4] = am * unl * (E + wl[4]);
     } else {
       double guess = ptr;
-      if ((FEAT & 2) && gate && fabsf(ym) > a.guess_gate) {
+      if ((FEAT & 2) && net) info.evaluated = 1;
+      if ((FEAT & 2) && net && fabsf(ym) > a.guess_gate) {
         double gm = ptr * exp((double)ym);
         if (gm > 0.0 && isfinite(gm)) {
           guess = gm;

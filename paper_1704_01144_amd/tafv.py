@@ -35,7 +35,7 @@ class tafv_params(C.Structure):
                 ("newton_max_iter", C.c_int32), ("reclassify", C.c_int32),
                 ("scatter", C.c_int32), ("cell_order", C.c_int32),
                 ("guess_stats", C.c_int32), ("guess_gate", C.c_double),
-                ("batch", C.c_int32)]
+                ("batch", C.c_int32), ("guess_strength", C.c_double)]
 
 
 class tafv_stats(C.Structure):
@@ -46,7 +46,7 @@ class tafv_stats(C.Structure):
                 ("dt_min", C.c_double), ("t_reached", C.c_double),
                 ("wall_impulse", C.c_double * 3), ("guess_faces", C.c_int64),
                 ("guess_newton_updates", C.c_int64), ("guess_rejected", C.c_int64),
-                ("guess_used", C.c_int64)]
+                ("guess_used", C.c_int64), ("guess_evaluated", C.c_int64)]
 
     def as_dict(self):
         d = {k: getattr(self, k) for k, _ in self._fields_}
@@ -80,7 +80,7 @@ def _load():
         "tafv_checkpoint_write": [P, C.c_int32, dp, dp, i8p, C.c_int32, C.c_int32, C.c_double,
                                   C.c_double],
         "tafv_profile_enable": [P, C.c_int32],
-        "tafv_guess_config": [P, C.c_int32, C.c_double, C.c_int32],
+        "tafv_guess_config": [P, C.c_int32, C.c_double, C.c_double, C.c_int32],
         "tafv_mlp_set": [P, fp, C.c_int64],
         "tafv_mlp_get": [P, fp, C.c_int64],
         "tafv_mlp_forward": [P, fp, C.c_int64, fp],
@@ -236,8 +236,8 @@ def _f(a):
     return a.ctypes.data_as(C.POINTER(C.c_float))
 
 
-def tafv_guess_config(ctx, guess, gate=0.0, stats=1):
-    _check(lib.tafv_guess_config(ctx, int(guess), float(gate), int(stats)), ctx)
+def tafv_guess_config(ctx, guess, gate=0.0, stats=1, strength=0.0):
+    _check(lib.tafv_guess_config(ctx, int(guess), float(gate), float(strength), int(stats)), ctx)
 
 
 def tafv_mlp_set(ctx, params):
