@@ -293,9 +293,9 @@ def copy_probe():
     log(f"copied {n * 8} bytes three times")
 
 
-def cpu_baseline(cfg, units=8):
+def cpu_baseline(cfg, units=24):
     """The oracle, single-threaded, on the first `units` subiterations of the
-    same workload (one full iteration at theta = 3)."""
+    same workload (three full iterations at theta = 3; about 15 s)."""
     from oracle import core as orc
     m = orc.Mesh(cfg["nodes"], cfg["tets"])
     o = orc.State(m, cfg["prim"], orc.params(max_levels=cfg["max_levels"], order=cfg["order"]))

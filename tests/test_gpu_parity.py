@@ -273,3 +273,48 @@ def test_full_scale_one_subiteration(T, orc, scatter):
         say(f"full scale after {n_before}+1: U err {err:.3e}, accum err {err_r:.3e}")
         assert err <= TOL and err_r <= 1e-11
     s.close()
+
+
+@pytest.fixture(scope="module")
+def full_oracle(orc):
+    """The benchmark workload advanced by the oracle: 64^3 hexes graded 16x
+    (1,572,864 cells), second order, L = 5, 32 dt_min units from t = 0."""
+    cfg = I.config_scale(64, 0)
+    m = orc.Mesh(cfg["nodes"], cfg["tets"])
+    o = orc.State(m, cfg["prim"], orc.params(max_levels=5, order=2))
+    say("oracle: 32 units on the full mesh ...")
+    o.advance(32)
+    u_o, _, lev_o = o.read()
+    return dict(cfg=cfg, cons=u_o, levels=lev_o, stats=o.stats())
+
+
+def test_full_scale_whole_run(T, full_oracle):
+    """The benchmark step itself (32 units from the initial state, the
+    benchmark's launch configuration) against the oracle, every cell:
+    FP64 to 1e-12 normwise with identical levels and counters; the FP32
+    form within the L1 bound."""
+    cfg = full_oracle["cfg"]
+    vol = None
+    for prec in (T.FP64, T.FP32_FLUX):
+        s = T.Solver(max_levels=5, order=2, precision=prec)
+        s.upload(cfg["nodes"], cfg["tets"])
+        s.init(cfg["prim"])
+        st = s.advance(32)
+        cons, lev = s.read()
+        s.close()
+        if prec == T.FP64:
+            err = normwise(cons, full_oracle["cons"])
+            say(f"full run FP64: err {err:.2e}, updates {st['cell_updates']} / "
+                f"{full_oracle['stats']['cell_updates']}")
+            assert err <= TOL
+            assert (lev == full_oracle["levels"]).all()
+            assert st["cell_updates"] == full_oracle["stats"]["cell_updates"]
+            assert st["face_solves"] == full_oracle["stats"]["face_solves"]
+        else:
+            p = cfg["nodes"][cfg["tets"]]
+            vol = np.einsum("ij,ij->i", p[:, 1] - p[:, 0],
+                            np.cross(p[:, 2] - p[:, 0], p[:, 3] - p[:, 0])) / 6.0
+            e_rho = l1_rel(cons[:, 0], full_oracle["cons"][:, 0], vol)
+            e_E = l1_rel(cons[:, 4], full_oracle["cons"][:, 4], vol)
+            say(f"full run FP32 form: L1 rho {e_rho:.2e}, L1 E {e_E:.2e}")
+            assert e_rho <= 1e-5 and e_E <= 1e-5
