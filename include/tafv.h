@@ -301,9 +301,10 @@ tafv_status tafv_facelog_read(tafv_ctx* ctx, float* rows, int64_t cap, int64_t* 
  * tafv_advance(n) call as HIP graphs (up to 32 subiterations each, cached
  * per length) and replays them on the context stream; graph = 0 launches
  * the kernels directly (per-kernel timing works only then).
- * autotune = 1 times candidate launch widths (persistent blocks per CU and
- * tiles taken per grab, or one tile per block over all cell tiles) of the
- * gradient and cell kernels on the first
+ * autotune = 1 times candidate launch shapes of the gradient and cell
+ * kernels (block size 64, 128, 256 or 512 threads; a persistent grid of 8,
+ * 16 or 32 waves per CU taking 1 or 4 groups of wave-sized work units at a
+ * time, or one group per block over all cell units) on the first
  * subiteration of the first advance (the cell kernel on scratch copies of
  * the state) and keeps the fastest; the flux kernel takes one tile per
  * block over the static count of face tiles; tune_cache (NULL: none) names a
@@ -315,10 +316,10 @@ tafv_status tafv_facelog_read(tafv_ctx* ctx, float* rows, int64_t cap, int64_t* 
 tafv_status tafv_batch_config(tafv_ctx* ctx, int32_t graph, int32_t autotune,
                               const char* tune_cache);
 
-/* Launch settings in use (n >= 7): info[0..5] = blocks and tiles per grab
- * of the gradient, flux and cell kernels (tiles per grab 0: one tile per
- * block); info[6] = 0 defaults, 1 timed by the autotuner, 2 read from the
- * cache file. */
+/* Launch settings in use (n >= 10): info[3k..3k+2] = blocks, unit groups
+ * per grab (0: one group per block) and threads per block of the gradient
+ * (k = 0), flux (k = 1) and cell (k = 2) kernels; info[9] = 0 defaults,
+ * 1 timed by the autotuner, 2 read from the cache file. */
 tafv_status tafv_batch_info(tafv_ctx* ctx, int32_t* info, int32_t n);
 
 /* Per-kernel timing: when enabled, tafv_advance() brackets every launch of

@@ -39,6 +39,7 @@ namespace tafv {
 namespace {
 
 constexpr int kChunk = 1024;        // partition chunk: 16 waves of 64
+constexpr int kUnit = 64;           // work unit of the gradient, flux and cell kernels
 constexpr int kStaticBlocksPerCU = 4;
 constexpr int kGraphSpan = 32;      // subiterations per captured graph
 constexpr int kMaxBatchMeshes = 8192;  // prefix arrays staged in LDS (32 KB)
@@ -52,6 +53,14 @@ __device__ inline int find_mesh(const int32_t* __restrict__ tp, int M, int t) {
     else hi = mid;
   }
   return lo;
+}
+
+// the mesh of unit u >= u0 of a block whose first unit u0 lies in mesh m0:
+// one search per block (every wave searches the same u0), then a short walk
+__device__ inline int mesh_after(const int32_t* __restrict__ tp, int m0, int u) {
+  int m = m0;
+  while (u >= tp[m + 1]) ++m;
+  return m;
 }
 
 // Tiles of a launch: block b (XCD-remapped rank r) takes tiles
@@ -424,9 +433,9 @@ __global__ __launch_bounds__(1024) void k_b_sched(BatchSched* S, int M, int orde
         s.subiterations += 1;
         s.phase = s1 & ((1 << th) - 1);
         s.t += s.dt_min;
-        tiles[0] = (s.n_grad + kBlock - 1) / kBlock;
-        tiles[1] = (s.n_flux + kBlock - 1) / kBlock;
-        tiles[2] = (s.n_gather + kBlock - 1) / kBlock;
+        tiles[0] = (s.n_grad + kUnit - 1) / kUnit;
+        tiles[1] = (s.n_flux + kUnit - 1) / kUnit;
+        tiles[2] = (s.n_gather + kUnit - 1) / kUnit;
       }
     }
     for (int w = 0; w < 3; ++w) sh[w][tid] = tiles[w];
@@ -448,47 +457,61 @@ __global__ __launch_bounds__(1024) void k_b_sched(BatchSched* S, int M, int orde
 }
 
 // ---- work kernels -----------------------------------------------------------
+// The active work of a subiteration is counted in units of one wave (64
+// items).  A block of BS threads takes BS / 64 consecutive units at a time;
+// each wave finds the mesh of its unit.  Gradient and cell kernels:
+// PERSIST = true walks the units with a fixed grid (prefix in LDS); false
+// takes one group of units per block over a grid of the static unit count
+// (prefix searched in global memory).  The autotuner picks BS, the grid
+// and the grab.
 
-// Gradient and cell kernels: PERSIST = true walks the tiles with a fixed
-// grid (prefix in LDS); false takes one tile per block over a grid of the
-// static tile count (prefix searched in global memory).  The autotuner
-// picks the faster.
-template <typename T, bool PERSIST>
-__global__ __launch_bounds__(kBlock) void k_b_grad(const int32_t* __restrict__ tp,
-                                                   const BatchSched* S, int M, int grab,
-                                                   GradArgs<T> a) {
+template <typename T, bool PERSIST, int BS>
+__global__ __launch_bounds__(BS) void k_b_grad(const int32_t* __restrict__ tp,
+                                               const BatchSched* S, int M, int grab,
+                                               GradArgs<T> a) {
+  constexpr int Q = BS / kUnit;
+  const int wv = threadIdx.x / kUnit, lane = threadIdx.x % kUnit;
   if (PERSIST) {
     STAGE_PREFIX(tp);
     const int total = s_pre[M];
-    TILE_LOOP(total, grab) {
-      int m = find_mesh(s_pre, M, t);
-      int j = (t - s_pre[m]) * kBlock + threadIdx.x;
-      if (j < S[m].n_grad) grad_item<T>(a, a.list[S[m].c0 + j]);
+    const int groups = (total + Q - 1) / Q;
+    TILE_LOOP(groups, grab) {
+      const int u = t * Q + wv;
+      if (u < total) {
+        int m = find_mesh(s_pre, M, u);
+        int j = (u - s_pre[m]) * kUnit + lane;
+        if (j < S[m].n_grad) grad_item<T>(a, a.list[S[m].c0 + j]);
+      }
     }
   } else {
-    const int t = xcd_block();
-    if (t >= tp[M]) return;
-    int m = find_mesh(tp, M, t);
-    int j = (t - tp[m]) * kBlock + threadIdx.x;
+    const int u0 = xcd_block() * Q, u = u0 + wv;
+    if (u >= tp[M]) return;  // no barrier follows
+    int m = mesh_after(tp, find_mesh(tp, M, u0), u);
+    int j = (u - tp[m]) * kUnit + lane;
     if (j < S[m].n_grad) grad_item<T>(a, a.list[S[m].c0 + j]);
   }
 }
 
-// The flux kernels take one tile per block (grid = the static bound of
-// face tiles; blocks past the active total leave at once): a persistent
-// loop around the face solve raised its register count by a quarter and
-// cost a wave of occupancy.
+// The flux kernels take one group of 4 units per 256-thread block (grid =
+// the static count of face units; waves past the active total skip the
+// solve): a persistent loop around the face solve raised its register count
+// by a quarter and cost a wave of occupancy.
 template <int ORDER, typename T, bool G14>
 __global__ __launch_bounds__(kBlock) void k_b_flux(const int32_t* __restrict__ tp,
                                                    const BatchSched* S, int M, FluxArgs<T> a) {
-  const int t = xcd_block();
-  if (t >= tp[M]) return;
+  constexpr int Q = kBlock / kUnit;
+  const int total = tp[M];
+  const int u0 = xcd_block() * Q;
+  if (u0 >= total) return;  // the whole block
+  const int u = u0 + (int)(threadIdx.x / kUnit);
   SolveInfo info{0, 0, 0, 0, 0, 0, 0, 0};
   double i0 = 0, i1 = 0, i2 = 0;
-  int m = find_mesh(tp, M, t);
-  int j = (t - tp[m]) * kBlock + threadIdx.x;
-  if (j < S[m].n_flux)
-    flux_store_item<ORDER, T, G14>(a, a.rec[S[m].f0 + j], S[m].dt_min, info, i0, i1, i2);
+  if (u < total) {
+    int m = mesh_after(tp, find_mesh(tp, M, u0), u);
+    int j = (u - tp[m]) * kUnit + (int)(threadIdx.x % kUnit);
+    if (j < S[m].n_flux)
+      flux_store_item<ORDER, T, G14>(a, a.rec[S[m].f0 + j], S[m].dt_min, info, i0, i1, i2);
+  }
   flush_counters(info, i0, i1, i2, a.dcount, a.dimpulse);
 }
 
@@ -497,46 +520,56 @@ __global__ __launch_bounds__(kBlock) void k_b_flux_feat(const int32_t* __restric
                                                         const BatchSched* S, int M,
                                                         FluxArgs<T> a) {
   __shared__ __attribute__((aligned(16))) uint16_t lds[(FEAT & 2) ? (kBlock / 64) * kMlpFwdLds : 8];
-  const int t = xcd_block();
-  if (t >= tp[M]) return;
+  constexpr int Q = kBlock / kUnit;
+  const int total = tp[M];
+  const int u0 = xcd_block() * Q;
+  if (u0 >= total) return;  // the whole block
+  const int u = u0 + (int)(threadIdx.x / kUnit);
   SolveInfo info{0, 0, 0, 0, 0, 0, 0, 0};
   double i0 = 0, i1 = 0, i2 = 0;
-  int m = find_mesh(tp, M, t);
-  int j = (t - tp[m]) * kBlock + threadIdx.x;
-  const bool valid = j < S[m].n_flux;
-  int4 r = valid ? a.rec[S[m].f0 + j] : make_int4(0, 0, -1, 0);
-  flux_feat_item<ORDER, T, FEAT>(a, valid, r, S[m].dt_min, lds + (threadIdx.x >> 6) * kMlpFwdLds,
-                                 info, i0, i1, i2);
+  if (u < total) {  // wave-uniform: the network pass sees all 64 lanes
+    int m = mesh_after(tp, find_mesh(tp, M, u0), u);
+    int j = (u - tp[m]) * kUnit + (int)(threadIdx.x % kUnit);
+    const bool valid = j < S[m].n_flux;
+    int4 r = valid ? a.rec[S[m].f0 + j] : make_int4(0, 0, -1, 0);
+    flux_feat_item<ORDER, T, FEAT>(a, valid, r, S[m].dt_min,
+                                   lds + (threadIdx.x >> 6) * kMlpFwdLds, info, i0, i1, i2);
+  }
   flush_counters(info, i0, i1, i2, a.dcount, a.dimpulse);
 }
 
-template <typename T, bool PERSIST>
-__global__ __launch_bounds__(kBlock) void k_b_gather(const int32_t* __restrict__ tp,
-                                                     const BatchSched* S, int M, int grab, int NC,
-                                                     const int* __restrict__ list,
-                                                     const uint32_t* __restrict__ fpack,
-                                                     const int* __restrict__ c2f,
-                                                     const T* __restrict__ Q,
-                                                     const double* __restrict__ vol,
-                                                     double* __restrict__ U,
-                                                     double* __restrict__ R,
-                                                     unsigned long long* flag) {
+template <typename T, bool PERSIST, int BS>
+__global__ __launch_bounds__(BS) void k_b_gather(const int32_t* __restrict__ tp,
+                                                 const BatchSched* S, int M, int grab, int NC,
+                                                 const int* __restrict__ list,
+                                                 const uint32_t* __restrict__ fpack,
+                                                 const int* __restrict__ c2f,
+                                                 const T* __restrict__ Q,
+                                                 const double* __restrict__ vol,
+                                                 double* __restrict__ U, double* __restrict__ R,
+                                                 unsigned long long* flag) {
+  constexpr int QU = BS / kUnit;
+  const int wv = threadIdx.x / kUnit, lane = threadIdx.x % kUnit;
   if (PERSIST) {
     STAGE_PREFIX(tp);
     const int total = s_pre[M];
-    TILE_LOOP(total, grab) {
-      int m = find_mesh(s_pre, M, t);
-      int j = (t - s_pre[m]) * kBlock + threadIdx.x;
-      if (j < S[m].n_gather)
-        if (!cell_gather_item<T>(list[S[m].c0 + j], NC, fpack, c2f, Q, S[m].dt_min, vol, U, R,
-                                 S[m].tau_s, S[m].upd))
-          atomicOr(flag, 1ull);
+    const int groups = (total + QU - 1) / QU;
+    TILE_LOOP(groups, grab) {
+      const int u = t * QU + wv;
+      if (u < total) {
+        int m = find_mesh(s_pre, M, u);
+        int j = (u - s_pre[m]) * kUnit + lane;
+        if (j < S[m].n_gather)
+          if (!cell_gather_item<T>(list[S[m].c0 + j], NC, fpack, c2f, Q, S[m].dt_min, vol, U, R,
+                                   S[m].tau_s, S[m].upd))
+            atomicOr(flag, 1ull);
+      }
     }
   } else {
-    const int t = xcd_block();
-    if (t >= tp[M]) return;
-    int m = find_mesh(tp, M, t);
-    int j = (t - tp[m]) * kBlock + threadIdx.x;
+    const int u0 = xcd_block() * QU, u = u0 + wv;
+    if (u >= tp[M]) return;  // no barrier follows
+    int m = mesh_after(tp, find_mesh(tp, M, u0), u);
+    int j = (u - tp[m]) * kUnit + lane;
     if (j < S[m].n_gather)
       if (!cell_gather_item<T>(list[S[m].c0 + j], NC, fpack, c2f, Q, S[m].dt_min, vol, U, R,
                                S[m].tau_s, S[m].upd))
@@ -695,6 +728,12 @@ tafv_status build(tafv_ctx* c) {
   B.n_fc = fc[M];
   B.n_ft = ft[M];
   B.n_ct = ct[M];
+  B.n_cu = 0;
+  B.n_fu = 0;
+  for (int m = 0; m < M; ++m) {
+    B.n_cu += nblk(B.hsched[m].nc, kUnit);
+    B.n_fu += nblk(B.hsched[m].nf, kUnit);
+  }
   hipError_t e = hipSuccess;
   auto chk = [&](hipError_t x) {
     if (e == hipSuccess) e = x;
@@ -726,8 +765,8 @@ tafv_status build(tafv_ctx* c) {
   B.hosts.clear();
   B.built = true;
   const int cu = cu_count(c);
-  for (int w = 0; w < 3; ++w) B.set[w] = LaunchSet{kStaticBlocksPerCU * cu, 1};
-  B.set[1] = LaunchSet{std::max(B.n_ft, 1), 1};
+  for (int w = 0; w < 3; ++w) B.set[w] = LaunchSet{kStaticBlocksPerCU * cu, 1, kBlock};
+  B.set[1] = LaunchSet{std::max((B.n_fu + kBlock / kUnit - 1) / (kBlock / kUnit), 1), 1, kBlock};
   return TAFV_OK;
 }
 
@@ -813,10 +852,39 @@ hipError_t run_reclass(tafv_ctx* c, hipStream_t s) {
   return hipGetLastError();
 }
 
-// grab 0: one tile per block over the static count of cell tiles
+// grab 0: one group of units per block over the static count of cell units
 dim3 work_grid(const Batch& B, const LaunchSet& ls) {
-  return dim3(ls.grab == 0 ? std::max(B.n_ct, 1) : ls.grid);
+  const int q = ls.bs / kUnit;
+  return dim3(ls.grab == 0 ? std::max((B.n_cu + q - 1) / q, 1) : ls.grid);
 }
+
+// launches kernel template K<PERSIST, BS> for the block size and mode of ls
+template <typename Launch>
+hipError_t by_shape(const LaunchSet& ls, Launch launch) {
+  const bool p = ls.grab != 0;
+  switch (ls.bs) {
+    case 64: p ? launch.template go<true, 64>() : launch.template go<false, 64>(); break;
+    case 128: p ? launch.template go<true, 128>() : launch.template go<false, 128>(); break;
+    case 512: p ? launch.template go<true, 512>() : launch.template go<false, 512>(); break;
+    default: p ? launch.template go<true, 256>() : launch.template go<false, 256>(); break;
+  }
+  return hipGetLastError();
+}
+
+template <typename T>
+struct GradLaunch {
+  hipStream_t s;
+  dim3 g;
+  size_t lds;
+  const int32_t* tp;
+  const BatchSched* S;
+  int M, grab;
+  GradArgs<T> a;
+  template <bool P, int BS>
+  void go() const {
+    hipLaunchKernelGGL((k_b_grad<T, P, BS>), g, dim3(BS), P ? lds : 0, s, tp, S, M, grab, a);
+  }
+};
 
 hipError_t run_grad(tafv_ctx* c, hipStream_t s, const LaunchSet& ls, const Ptrs& p) {
   Batch& B = *c->batch;
@@ -825,27 +893,15 @@ hipError_t run_grad(tafv_ctx* c, hipStream_t s, const LaunchSet& ls, const Ptrs&
   const int M = B.nmesh;
   const double gm1 = c->prm.gamma - 1.0;
   const dim3 g = work_grid(B, ls);
-  const size_t lds = ls.grab == 0 ? 0 : sizeof(int32_t) * (M + 1);
+  const size_t lds = sizeof(int32_t) * (M + 1);
   if (c->prm.precision == TAFV_FP32_FLUX) {
     GradArgs<float> a{m.pc.list, 0, m.nc, m.nf, m.U, m.nb_, m.lsq32, m.rf32, m.fA, (float*)m.Wf,
                       gm1, c->prm.boundary};
-    if (ls.grab == 0)
-      hipLaunchKernelGGL((k_b_grad<float, false>), g, dim3(kBlock), lds, s, p.tp, p.S, M,
-                         0, a);
-    else
-      hipLaunchKernelGGL((k_b_grad<float, true>), g, dim3(kBlock), lds, s, p.tp, p.S, M,
-                         ls.grab, a);
-  } else {
-    GradArgs<double> a{m.pc.list, 0, m.nc, m.nf, m.U, m.nb_, m.lsq, m.rf, m.fA, (double*)m.Wf,
-                       gm1, c->prm.boundary};
-    if (ls.grab == 0)
-      hipLaunchKernelGGL((k_b_grad<double, false>), g, dim3(kBlock), lds, s, p.tp, p.S, M,
-                         0, a);
-    else
-      hipLaunchKernelGGL((k_b_grad<double, true>), g, dim3(kBlock), lds, s, p.tp, p.S, M,
-                         ls.grab, a);
+    return by_shape(ls, GradLaunch<float>{s, g, lds, p.tp, p.S, M, ls.grab, a});
   }
-  return hipGetLastError();
+  GradArgs<double> a{m.pc.list, 0, m.nc, m.nf, m.U, m.nb_, m.lsq, m.rf, m.fA, (double*)m.Wf,
+                     gm1, c->prm.boundary};
+  return by_shape(ls, GradLaunch<double>{s, g, lds, p.tp, p.S, M, ls.grab, a});
 }
 
 template <typename T>
@@ -879,7 +935,7 @@ void flux_dispatch(hipStream_t s, const Batch& B, int order, int feat, bool g14,
 
 hipError_t run_flux(tafv_ctx* c, hipStream_t s, const Ptrs& p) {
   Batch& B = *c->batch;
-  const int grid = std::max(B.n_ft, 1);
+  const int grid = std::max((B.n_fu + kBlock / kUnit - 1) / (kBlock / kUnit), 1);
   DevMesh& m = *B.m;
   StepArgs a = step_args(c);
   FluxFeatures ft = features(c);
@@ -897,32 +953,42 @@ hipError_t run_flux(tafv_ctx* c, hipStream_t s, const Ptrs& p) {
   return hipGetLastError();
 }
 
+template <typename T>
+struct GatherLaunch {
+  hipStream_t s;
+  dim3 g;
+  size_t lds;
+  const int32_t* tp;
+  const BatchSched* S;
+  int M, grab, NC;
+  const int *list, *c2f;
+  const uint32_t* fpack;
+  const T* Q;
+  const double* vol;
+  double *U, *R;
+  unsigned long long* flag;
+  template <bool P, int BS>
+  void go() const {
+    hipLaunchKernelGGL((k_b_gather<T, P, BS>), g, dim3(BS), P ? lds : 0, s, tp, S, M, grab, NC,
+                       list, fpack, c2f, Q, vol, U, R, flag);
+  }
+};
+
 hipError_t run_gather(tafv_ctx* c, hipStream_t s, const LaunchSet& ls, const Ptrs& p) {
   Batch& B = *c->batch;
   DevMesh& m = *B.m;
   const int M = B.nmesh;
   const dim3 g = work_grid(B, ls);
-  const size_t lds = ls.grab == 0 ? 0 : sizeof(int32_t) * (M + 1);
+  const size_t lds = sizeof(int32_t) * (M + 1);
   const int32_t* tp = p.tp + 2 * (M + 1);
   unsigned long long* flag = m.dscal + 2;
-  if (c->prm.precision == TAFV_FP32_FLUX) {
-    const float* Q = (const float*)m.Q;
-    if (ls.grab == 0)
-      hipLaunchKernelGGL((k_b_gather<float, false>), g, dim3(kBlock), lds, s, tp, p.S, M, 0, m.nc,
-                         m.pc.list, m.fpack, m.c2f, Q, m.vol, p.U, p.R, flag);
-    else
-      hipLaunchKernelGGL((k_b_gather<float, true>), g, dim3(kBlock), lds, s, tp, p.S, M, ls.grab,
-                         m.nc, m.pc.list, m.fpack, m.c2f, Q, m.vol, p.U, p.R, flag);
-  } else {
-    const double* Q = (const double*)m.Q;
-    if (ls.grab == 0)
-      hipLaunchKernelGGL((k_b_gather<double, false>), g, dim3(kBlock), lds, s, tp, p.S, M, 0,
-                         m.nc, m.pc.list, m.fpack, m.c2f, Q, m.vol, p.U, p.R, flag);
-    else
-      hipLaunchKernelGGL((k_b_gather<double, true>), g, dim3(kBlock), lds, s, tp, p.S, M,
-                         ls.grab, m.nc, m.pc.list, m.fpack, m.c2f, Q, m.vol, p.U, p.R, flag);
-  }
-  return hipGetLastError();
+  if (c->prm.precision == TAFV_FP32_FLUX)
+    return by_shape(ls, GatherLaunch<float>{s, g, lds, tp, p.S, M, ls.grab, m.nc, m.pc.list,
+                                            m.c2f, m.fpack, (const float*)m.Q, m.vol, p.U, p.R,
+                                            flag});
+  return by_shape(ls, GatherLaunch<double>{s, g, lds, tp, p.S, M, ls.grab, m.nc, m.pc.list,
+                                           m.c2f, m.fpack, (const double*)m.Q, m.vol, p.U, p.R,
+                                           flag});
 }
 
 Ptrs live_ptrs(Batch& B) {
@@ -979,10 +1045,14 @@ bool cache_lookup(tafv_ctx* c, const std::string& key) {
     std::istringstream in(line);
     std::string k;
     LaunchSet t[3];
-    if (!(in >> k >> t[0].grid >> t[0].grab >> t[2].grid >> t[2].grab)) continue;
+    if (!(in >> k >> t[0].grid >> t[0].grab >> t[0].bs >> t[2].grid >> t[2].grab >> t[2].bs))
+      continue;
     if (k != key) continue;
     bool ok = true;
-    for (int w : {0, 2}) ok &= t[w].grid > 0 && t[w].grab >= 0 && t[w].grab <= 64;
+    for (int w : {0, 2})
+      ok &= t[w].grid >= 0 && t[w].grab >= 0 && t[w].grab <= 64 &&
+            (t[w].bs == 64 || t[w].bs == 128 || t[w].bs == 256 || t[w].bs == 512) &&
+            (t[w].grab == 0 || t[w].grid > 0);
     if (!ok) continue;
     for (int w : {0, 2}) got[w] = t[w];
     found = true;  // the last matching line wins
@@ -998,7 +1068,7 @@ void cache_store(tafv_ctx* c, const std::string& key) {
   std::ofstream f(B.cache, std::ios::app);
   if (!f) return;
   f << key;
-  for (int w : {0, 2}) f << ' ' << B.set[w].grid << ' ' << B.set[w].grab;
+  for (int w : {0, 2}) f << ' ' << B.set[w].grid << ' ' << B.set[w].grab << ' ' << B.set[w].bs;
   f << '\n';
 }
 
@@ -1028,10 +1098,14 @@ tafv_status autotune(tafv_ctx* c) {
   tafv_status st = sync_back(c);  // lists and levels of this iteration
   if (st != TAFV_OK) return st;
   const int cu = cu_count(c);
+  // block sizes 64-512; persistent grids of 8, 16 or 32 waves per CU taking
+  // 1 or 4 groups of units at a time, or one group per block
   std::vector<LaunchSet> cand;
-  for (int mult : {1, 2, 4, 8})
-    for (int grab : {1, 4}) cand.push_back(LaunchSet{mult * cu, grab});
-  cand.push_back(LaunchSet{std::max(B.n_ct, 1), 0});  // one tile per block
+  for (int bs : {64, 128, 256, 512}) {
+    for (int wpc : {8, 16, 32})
+      for (int grab : {1, 4}) cand.push_back(LaunchSet{wpc * cu / (bs / kUnit), grab, bs});
+    cand.push_back(LaunchSet{0, 0, bs});
+  }
   int theta_max = 0;
   for (const BatchSched& x : B.hsched) theta_max = std::max(theta_max, x.theta);
   const size_t rows = (size_t)5 * m.nc;
@@ -1065,7 +1139,7 @@ tafv_status autotune(tafv_ctx* c) {
       const int n[3] = {x.n_grad, 0, x.n_gather};
       for (int w = 0; w < 3; ++w) {
         htp[w * (M + 1) + q] = acc[w];
-        acc[w] += (n[w] + kBlock - 1) / kBlock;
+        acc[w] += (n[w] + kUnit - 1) / kUnit;
       }
     }
     for (int w = 0; w < 3; ++w) htp[w * (M + 1) + M] = acc[w];
@@ -1125,7 +1199,8 @@ int64_t graph_key(tafv_ctx* c) {
   int64_t k = ft.feat;
   k = k * 16 + B.lmax;
   k = k * 2 + (c->prm.reclassify ? 1 : 0);
-  for (int w = 0; w < 3; ++w) k = k * 1000003 + B.set[w].grid * 64 + B.set[w].grab;
+  for (int w = 0; w < 3; ++w)
+    k = k * 1000003 + (B.set[w].grid * 64 + B.set[w].grab) * 8 + B.set[w].bs / 64;
   return k;
 }
 
@@ -1412,7 +1487,7 @@ tafv_status batch_config(tafv_ctx* c, int32_t graph, int32_t autotune_on, const 
   B.cache = cache ? cache : "";
   if (!autotune_on && B.built) {
     const int cu = cu_count(c);
-    B.set[0] = B.set[2] = LaunchSet{kStaticBlocksPerCU * cu, 1};
+    B.set[0] = B.set[2] = LaunchSet{kStaticBlocksPerCU * cu, 1, kBlock};
   }
   B.tuned = 0;
   drop_graphs(B);
@@ -1421,12 +1496,14 @@ tafv_status batch_config(tafv_ctx* c, int32_t graph, int32_t autotune_on, const 
 
 tafv_status batch_info(tafv_ctx* c, int32_t* info, int32_t n) {
   Batch& B = *c->batch;
-  if (!info || n < 7) return set_error(c, TAFV_E_ARG, "info needs 7 entries");
+  if (!info || n < 10) return set_error(c, TAFV_E_ARG, "info needs 10 entries");
   for (int w = 0; w < 3; ++w) {
-    info[2 * w] = B.set[w].grid;
-    info[2 * w + 1] = B.set[w].grab;
+    info[3 * w] = B.built ? (int32_t)work_grid(B, B.set[w]).x : B.set[w].grid;
+    if (w == 1) info[3 * w] = B.set[1].grid;
+    info[3 * w + 1] = B.set[w].grab;
+    info[3 * w + 2] = B.set[w].bs;
   }
-  info[6] = B.tuned;
+  info[9] = B.tuned;
   return TAFV_OK;
 }
 

@@ -132,8 +132,9 @@ struct BatchSched {
 // Launch settings of one work class of the batched kernels.
 struct LaunchSet {
   int32_t grid = 0;  // blocks of the persistent launch
-  int32_t grab = 1;  // consecutive tiles a block takes at a time; 0: one tile
-                     // per block, grid = the static tile count
+  int32_t grab = 1;  // consecutive unit groups a block takes at a time; 0: one
+                     // group per block, grid = the static count of groups
+  int32_t bs = 256;  // threads per block (64, 128, 256 or 512)
 };
 
 struct DevMesh;
@@ -153,7 +154,7 @@ struct Batch {
   // static tile prefixes [nmesh + 1]: cell tiles and face tiles of kBlock
   // items, cell chunks and face chunks of the partitions
   int32_t *ct = nullptr, *ft = nullptr, *cc = nullptr, *fc = nullptr;
-  int32_t n_cc = 0, n_fc = 0, n_ft = 0, n_ct = 0;
+  int32_t n_cc = 0, n_fc = 0, n_ft = 0, n_ct = 0, n_cu = 0, n_fu = 0;
   int32_t *cnt_f = nullptr, *cnt_c = nullptr;  // [8 * chunks] counts, then offsets
   int32_t* tp = nullptr;              // [3][nmesh + 1] tiles: gradient, flux, cells
   int32_t* rp = nullptr;              // [4][nmesh + 1] reclassification tiles and chunks

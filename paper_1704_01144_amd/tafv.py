@@ -311,13 +311,14 @@ def tafv_batch_config(ctx, graph=1, autotune=1, tune_cache=None):
 
 
 def tafv_batch_info(ctx):
-    """Launch settings of the batched kernels: blocks and tiles per grab of
-    the gradient, flux and cell kernels, and where they came from."""
-    a = (C.c_int32 * 7)()
-    _check(lib.tafv_batch_info(ctx, a, 7), ctx)
+    """Launch settings of the batched kernels: (blocks, unit groups per grab,
+    threads per block) of the gradient, flux and cell kernels, and where
+    they came from."""
+    a = (C.c_int32 * 10)()
+    _check(lib.tafv_batch_info(ctx, a, 10), ctx)
     v = list(a)
-    return dict(grad=(v[0], v[1]), flux=(v[2], v[3]), cells=(v[4], v[5]),
-                source={0: "default", 1: "tuned", 2: "cache"}[v[6]])
+    return dict(grad=tuple(v[0:3]), flux=tuple(v[3:6]), cells=tuple(v[6:9]),
+                source={0: "default", 1: "tuned", 2: "cache"}[v[9]])
 
 
 class Solver:
