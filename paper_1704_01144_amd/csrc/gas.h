@@ -114,6 +114,9 @@ __device__ inline T pow_p(const Gas& G, T x) {
 struct Star {
   double p, u;
   int iters, fallback, vacuum;
+  // gamma = 1.4 solver: (p/p_K)^(-1/7) of each side at p where that side is
+  // a rarefaction (<= 0 otherwise), for the sampling
+  double zl = -1.0, zr = -1.0;
 };
 
 template <bool G14>
@@ -294,6 +297,41 @@ __device__ inline double side14(double p, const K14& k, double& df) {
   return k.c * fma(x, z6, -1.0);
 }
 
+// One side at p with z = (p/p_K)^(-1/7) carried along: on the rarefaction
+// branch a known z (> 0) is used, an unknown one is computed; on the shock
+// branch z is not needed and is reset.
+__device__ inline double side14z(double p, const K14& k, double& z, double& df) {
+  if (p > k.p) {
+    z = -1.0;
+    return side14(p, k, df);
+  }
+  double x = p * k.ip;
+  if (!(z > 0.0)) z = irt7(x);
+  double z2 = z * z, z6 = z2 * z2 * z2;
+  df = z6 * k.iria;
+  return k.c * fma(x, z6, -1.0);
+}
+
+// The two-rarefaction value p_TR = x^7, x = (a_L + a_R - (g-1)/2 (u_R - u_L))
+// / (a_L w_L + a_R w_R), w_K = p_K^(-1/7).  At p = p_TR the rarefaction
+// variable of side K is (p_TR/p_K)^(-1/7) = 1 / (x w_K), with no root.
+struct TR14 {
+  double x, wl, wr, p;
+};
+
+__device__ inline TR14 tr14(const Gas& G, double ul, double ur, double al, double ar,
+                            const K14& L, const K14& R) {
+  TR14 t;
+  t.wl = irt7(L.p);
+  t.wr = irt7(R.p);
+  double num = al + ar - 0.5 * G.gm1 * (ur - ul);
+  double den = al * t.wl + ar * t.wr;
+  t.x = num * frcp(den);
+  double x2 = t.x * t.x, x3 = x2 * t.x;
+  t.p = x3 * x3 * t.x;
+  return t;
+}
+
 // bisection on [0, hi] with f(0) < 0 < f(hi)
 __device__ inline double bisect14(const K14& L, const K14& R, double du, double tol) {
   double lo = 0.0, hi = fmax(L.p, R.p), dl, dr;
@@ -309,11 +347,14 @@ __device__ inline double bisect14(const K14& L, const K14& R, double du, double 
   return 0.5 * (lo + hi);
 }
 
-// guess <= 0 or not finite: the two-rarefaction value
-// [(a_L + a_R - (g-1)/2 (u_R - u_L)) / (a_L p_L^-z + a_R p_R^-z)]^7
+// guess <= 0 or not finite: the two-rarefaction value (tr, when given,
+// holds it).  The rarefaction variables z = (p/p_K)^(-1/7) are carried from
+// one Newton iterate to the next: exactly at the two-rarefaction start, and
+// across an update p -> p' with |p' - p| < 1e-9 p as z (1 - (p' - p)/(7 p))
+// (the dropped term is below 1e-19 relative); otherwise recomputed.
 __device__ inline Star solve_star14(const Gas& G, double ul, double ur, double al, double ar,
                                     const K14& L, const K14& R, double tol, int max_iter,
-                                    double guess) {
+                                    double guess, const TR14* tr = nullptr) {
   Star s;
   s.iters = 0;
   s.fallback = 0;
@@ -324,33 +365,46 @@ __device__ inline Star solve_star14(const Gas& G, double ul, double ur, double a
     s.u = 0.5 * ((ul + G.two_gm1 * al) + (ur - G.two_gm1 * ar));
     return s;
   }
-  double p = guess;
+  double p = guess, zl = -1.0, zr = -1.0;
   if (!(p > 0.0) || !isfinite(p)) {
-    double num = al + ar - 0.5 * G.gm1 * (ur - ul);
-    double den = al * irt7(L.p) + ar * irt7(R.p);
-    double x = num * frcp(den), x2 = x * x, x3 = x2 * x;
-    p = x3 * x3 * x;
+    TR14 t = tr ? *tr : tr14(G, ul, ur, al, ar, L, R);
+    p = t.p;
+    zl = frcp(t.x * t.wl);
+    zr = frcp(t.x * t.wr);
+  } else if (tr && p == tr->p) {
+    zl = frcp(tr->x * tr->wl);
+    zr = frcp(tr->x * tr->wr);
   }
   const double du = ur - ul;
   bool conv = false;
   for (int k = 1; k <= max_iter; ++k) {
     double dl, dr;
-    double f = side14(p, L, dl) + side14(p, R, dr) + du;
+    double f = side14z(p, L, zl, dl) + side14z(p, R, zr, dr) + du;
     double pn = p - f * frcp(dl + dr);
     if (!(pn > 0.0)) pn = p * 0.0625;
     s.iters = k;
     conv = 2.0 * fabs(pn - p) < tol * (pn + p);
+    if (fabs(pn - p) < 1e-9 * p) {
+      double c = 1.0 - (pn - p) * frcp(7.0 * p);
+      zl *= c;  // an unknown (negative) z stays unknown
+      zr *= c;
+    } else {
+      zl = zr = -1.0;
+    }
     p = pn;
     if (conv) break;
   }
   if (!conv) {
     s.fallback = 1;
     p = bisect14(L, R, du, tol);
+    zl = zr = -1.0;
   }
   double dl, dr;
-  double fl = side14(p, L, dl), fr = side14(p, R, dr);
+  double fl = side14z(p, L, zl, dl), fr = side14z(p, R, zr, dr);
   s.p = p;
   s.u = 0.5 * (ul + ur) + 0.5 * (fr - fl);
+  s.zl = zl;
+  s.zr = zr;
   return s;
 }
 
@@ -359,7 +413,8 @@ __device__ inline Star solve_star14(const Gas& G, double ul, double ur, double a
 // shock rho_K (q + g1)/(g1 q + 1); fan states: rho_K c^5, p_K c^7.
 template <typename T>
 __device__ inline int sample14(const Gas& G, T rl, T ul, T pl, T al, T ipl, T ral, T rr, T ur,
-                               T pr, T ar, T ipr, T rar, T ps, T us, T& r, T& u, T& p) {
+                               T pr, T ar, T ipr, T rar, T ps, T us, T& r, T& u, T& p,
+                               double zl = -1.0, double zr = -1.0) {
   const T g1 = (T)G.g1, ash = (T)G.a_shock, sh1 = (T)G.sh1, sh2 = (T)G.sh2;
   const T hg = (T)(0.5 * G.gm1);
   if (0 <= us) {
@@ -371,7 +426,7 @@ __device__ inline int sample14(const Gas& G, T rl, T ul, T pl, T al, T ipl, T ra
     } else {
       if (0 <= ul - al) { r = rl; u = ul; p = pl; }
       else {
-        T x = ps * ipl, z = irt7(x), z2 = z * z, z6 = z2 * z2 * z2;
+        T x = ps * ipl, z = zl > 0.0 ? (T)zl : irt7(x), z2 = z * z, z6 = z2 * z2 * z2;
         if (0 >= us - al * x * z6) { r = rl * x * z2; u = us; p = ps; }
         else {
           T c = ash + g1 * ral * ul, c2 = c * c, c5 = c2 * c2 * c;
@@ -391,7 +446,7 @@ __device__ inline int sample14(const Gas& G, T rl, T ul, T pl, T al, T ipl, T ra
   } else {
     if (0 >= ur + ar) { r = rr; u = ur; p = pr; }
     else {
-      T x = ps * ipr, z = irt7(x), z2 = z * z, z6 = z2 * z2 * z2;
+      T x = ps * ipr, z = zr > 0.0 ? (T)zr : irt7(x), z2 = z * z, z6 = z2 * z2 * z2;
       if (0 <= us + ar * x * z6) { r = rr * x * z2; u = us; p = ps; }
       else {
         T c = ash - g1 * rar * ur, c2 = c * c, c5 = c2 * c2 * c;

@@ -374,7 +374,7 @@ __device__ inline void face_flux(const FluxArgs<T>& a, int4 r, T* phi, SolveInfo
   int side;
   if (G14 && !st.vacuum)
     side = sample14<T>(G, wl[0], unl, wl[4], (T)al, (T)ipl, (T)ral, wr[0], unr, wr[4], (T)ar,
-                       (T)ipr, (T)rar, (T)st.p, (T)st.u, rs, us, ps);
+                       (T)ipr, (T)rar, (T)st.p, (T)st.u, rs, us, ps, st.zl, st.zr);
   else
     side = sample0<G14, T>(G, wl[0], unl, wl[4], (T)al, wr[0], unr, wr[4], (T)ar, (T)st.p,
                            (T)st.u, st.vacuum, rs, us, ps);
@@ -522,10 +522,7 @@ __device__ inline void flux_feat_item(const FluxArgs<T>& a, bool valid, int4 r, 
       }
       vac = G.two_gm1 * (al + ar) <= (double)unr - (double)unl;
       if (!vac) {
-        double num = al + ar - 0.5 * G.gm1 * ((double)unr - (double)unl);
-        double den = al * irt7(KL.p) + ar * irt7(KR.p);
-        double q = num * frcp(den), q2 = q * q, q3 = q2 * q;
-        ptr = q3 * q3 * q;
+        ptr = tr14(G, unl, unr, al, ar, KL, KR).p;
         gate = !wall && ptr > fmin(KL.p, KR.p);
       }
       if (gate) {  // deviations from the face mean, normalised by it
@@ -568,6 +565,9 @@ __device__ inline void flux_feat_item(const FluxArgs<T>& a, bool valid, int4 r, 
           info.rejected = 1;
         }
       }
+      // (the start's rarefaction roots are not carried in from the
+      // two-rarefaction value here: kept live across the network pass they
+      // would spill registers)
       Star st = solve_star14(G, unl, unr, al, ar, KL, KR, a.s.newton_tol, a.s.newton_max_iter,
                              guess);
       info.iters = st.iters;
@@ -600,7 +600,8 @@ __device__ inline void flux_feat_item(const FluxArgs<T>& a, bool valid, int4 r, 
         int side;
         if (!st.vacuum)
           side = sample14<T>(G, wl[0], unl, wl[4], (T)al, (T)KL.ip, (T)ral, wr[0], unr, wr[4],
-                             (T)ar, (T)KR.ip, (T)rar, (T)st.p, (T)st.u, rs, us, ps);
+                             (T)ar, (T)KR.ip, (T)rar, (T)st.p, (T)st.u, rs, us, ps, st.zl,
+                             st.zr);
         else
           side = sample0<true, T>(G, wl[0], unl, wl[4], (T)al, wr[0], unr, wr[4], (T)ar, (T)st.p,
                                   (T)st.u, st.vacuum, rs, us, ps);
