@@ -27,7 +27,7 @@ class Params(C.Structure):
                 ("newton_tol", C.c_double), ("level_margin", C.c_double),
                 ("max_levels", C.c_int32), ("order", C.c_int32),
                 ("newton_max_iter", C.c_int32), ("boundary", C.c_int32),
-                ("reclassify", C.c_int32)]
+                ("reclassify", C.c_int32), ("time_order", C.c_int32)]
 
 
 class Stats(C.Structure):
@@ -53,9 +53,9 @@ class RiemannOut(C.Structure):
 
 
 def params(gamma=1.4, cfl=0.5, newton_tol=1e-12, level_margin=1e-9, max_levels=3,
-           order=1, newton_max_iter=50, boundary=BC_WALL, reclassify=1):
+           order=1, newton_max_iter=50, boundary=BC_WALL, reclassify=1, time_order=1):
     return Params(gamma, cfl, newton_tol, level_margin, max_levels, order,
-                  newton_max_iter, boundary, reclassify)
+                  newton_max_iter, boundary, reclassify, time_order)
 
 
 _lib = None

@@ -631,6 +631,11 @@ struct orc_state {
   double* glim;   /* [nc][3][5] scratch                                  */
   double* q;      /* [nf][5] scratch: dt_f * flux of active faces        */
   uint8_t* act;   /* [nf] scratch                                        */
+  /* time_order 2 only */
+  double* D;      /* [nc][5] prediction of the cell's current step       */
+  double* Ut;     /* [nc][5] scratch: states at one time inside the steps */
+  double* phi0;   /* [nf][5] predictor flux of the face's current step   */
+  double* phi1;   /* [nf][5] scratch: corrector flux                     */
   int32_t phase, theta, classified;
   double dt_min, t;
   orc_stats st;
@@ -640,6 +645,7 @@ void orc_state_free(orc_state* s) {
   if (!s) return;
   free(s->U); free(s->R); free(s->lev); free(s->dt); free(s->prim);
   free(s->glim); free(s->q); free(s->act);
+  free(s->D); free(s->Ut); free(s->phi0); free(s->phi1);
   free(s);
 }
 
@@ -647,7 +653,8 @@ int orc_state_new(const orc_mesh* m, const orc_params* prm, const double* prim,
                   orc_state** out) {
   if (!m || !prm || !prim || !out) return ORC_E_ARG;
   if (prm->max_levels < 1 || prm->max_levels > 8 || (prm->order != 1 && prm->order != 2) ||
-      !(prm->gamma > 1.0) || !(prm->cfl > 0.0) || prm->newton_max_iter < 1)
+      !(prm->gamma > 1.0) || !(prm->cfl > 0.0) || prm->newton_max_iter < 1 ||
+      (prm->time_order != 1 && prm->time_order != 2))
     return ORC_E_ARG;
   for (int64_t i = 0; i < m->nc; ++i) {
     const double* w = prim + 5 * i;
@@ -670,6 +677,16 @@ int orc_state_new(const orc_mesh* m, const orc_params* prm, const double* prim,
     orc_state_free(s);
     return ORC_E_ARG;
   }
+  if (prm->time_order == 2) {
+    s->D = (double*)calloc((size_t)(5 * m->nc), sizeof(double));
+    s->Ut = (double*)malloc(sizeof(double) * 5 * m->nc);
+    s->phi0 = (double*)calloc((size_t)(5 * m->nf), sizeof(double));
+    s->phi1 = (double*)malloc(sizeof(double) * 5 * m->nf);
+    if (!s->D || !s->Ut || !s->phi0 || !s->phi1) {
+      orc_state_free(s);
+      return ORC_E_ARG;
+    }
+  }
   for (int64_t i = 0; i < m->nc; ++i) prim_to_cons(prm->gamma, prim + 5 * i, s->U + 5 * i);
   *out = s;
   return ORC_OK;
@@ -681,6 +698,7 @@ int orc_state_set(orc_state* s, const double* cons, const double* accum,
   if (!s || !cons || !accum || !levels) return ORC_E_ARG;
   if (theta < 0 || theta >= s->prm.max_levels || phase < 0 || phase >= (1 << theta))
     return ORC_E_ARG;
+  if (s->prm.time_order == 2 && phase != 0) return ORC_E_ARG;
   memcpy(s->U, cons, sizeof(double) * 5 * s->m->nc);
   memcpy(s->R, accum, sizeof(double) * 5 * s->m->nc);
   memcpy(s->lev, levels, (size_t)s->m->nc);
@@ -710,36 +728,27 @@ static int classify_state(orc_state* s) {
   return ORC_OK;
 }
 
-/* One subiteration of Alg. 2 with flux accumulation for the slower side:
- *   1. at the start of an iteration (phase 0) every cell is synchronised;
- *      compute time steps and levels;
- *   2. the level of this subiteration is theta at phase 0, else the largest
- *      tau <= theta with 2^tau dividing the phase;
- *   3. every face whose faster side has level <= that tau is computed from
- *      the current states of both cells and its time-integrated flux
- *      2^tau_f dt_min * flux is added to both cells' accumulators;
- *   4. cells whose level step ends now apply their accumulator. */
-static int subiteration(orc_state* s) {
+/* Godunov fluxes |A| F . n (Sec. 2.1, Eq. (1)) of every face whose faster
+ * side has level <= tau_max, from the cell states cons: primitive
+ * variables, limited least-squares gradients at second order (Alg. 2,
+ * gradient computation and limitation), reconstruction at the face centroid,
+ * exact Riemann solve (Alg. 2, Riemann solver).  act[f] marks the faces
+ * computed; phi of the others is left as it was.  The solve counters are
+ * added to the statistics. */
+static int face_fluxes(orc_state* s, const double* cons, int tau_max, double* phi) {
   const orc_mesh* m = s->m;
   const orc_params* prm = &s->prm;
   double g = prm->gamma;
-  if (s->phase == 0 && (prm->reclassify || !s->classified)) {
-    int rc = classify_state(s);
-    if (rc) return rc;
-  }
-  int tau_s = orc_subiteration_level((int64_t)s->phase + 1, s->theta);
-
-  for (int64_t i = 0; i < m->nc; ++i) cons_to_prim(g, s->U + 5 * i, s->prim + 5 * i);
+  for (int64_t i = 0; i < m->nc; ++i) cons_to_prim(g, cons + 5 * i, s->prim + 5 * i);
   if (prm->order == 2) {
     int rc = orc_gradients(m, prm, s->prim, NULL, s->glim);
     if (rc) return rc;
   }
-
   for (int64_t f = 0; f < m->nf; ++f) {
     int64_t L = m->fL[f], R = m->fR[f];
     int tau_f = s->lev[L];
     if (R >= 0 && s->lev[R] < tau_f) tau_f = s->lev[R];
-    s->act[f] = (uint8_t)(tau_f <= tau_s);
+    s->act[f] = (uint8_t)(tau_f <= tau_max);
     if (!s->act[f]) continue;
     double wl[5], wr[5];
     for (int k = 0; k < 5; ++k) wl[k] = s->prim[5 * L + k];
@@ -756,21 +765,24 @@ static int subiteration(orc_state* s) {
       }
     }
     int kind = (R >= 0) ? 0 : (prm->boundary == ORC_BC_WALL ? 1 : 2);
-    double flux[5];
     orc_riemann_out ro;
     int rc = orc_face_flux(g, wl, wr, m->af + 3 * f, kind, prm->newton_tol,
-                           prm->newton_max_iter, ORC_GUESS_TR, 0.0, flux, &ro);
+                           prm->newton_max_iter, ORC_GUESS_TR, 0.0, phi + 5 * f, &ro);
     if (rc) return ORC_E_NUMERIC;
-    double dtf = ldexp(s->dt_min, tau_f);
-    for (int k = 0; k < 5; ++k) s->q[5 * f + k] = dtf * flux[k];
     s->st.face_solves++;
     s->st.newton_updates += ro.newton_updates;
     s->st.newton_fallbacks += ro.fallback;
     s->st.vacuum_faces += ro.vacuum;
-    if (kind == 1)
-      for (int k = 0; k < 3; ++k) s->st.wall_impulse[k] += s->q[5 * f + 1 + k];
   }
-  /* flow sum on cells: each cell adds its own active faces, local order */
+  return ORC_OK;
+}
+
+/* Flow sum on cells (Alg. 2): each cell adds the time-integrated flux q of
+ * its own computed faces in its local face order, -q where it is the face's
+ * L side (the flux leaves it), +q otherwise; then the cells whose level
+ * step ends at the end of subiteration sub apply their sum. */
+static int flow_sum_and_update(orc_state* s, int64_t sub) {
+  const orc_mesh* m = s->m;
   for (int64_t i = 0; i < m->nc; ++i) {
     for (int j = 0; j < 4; ++j) {
       int64_t f = m->c2f[4 * i + j];
@@ -779,8 +791,6 @@ static int subiteration(orc_state* s) {
       for (int k = 0; k < 5; ++k) s->R[5 * i + k] += sign * s->q[5 * f + k];
     }
   }
-  /* cells whose level step ends at the end of this subiteration */
-  int64_t sub = (int64_t)s->phase + 1;
   for (int64_t i = 0; i < m->nc; ++i) {
     if (sub % ((int64_t)1 << s->lev[i]) != 0) continue;
     for (int k = 0; k < 5; ++k) {
@@ -790,6 +800,123 @@ static int subiteration(orc_state* s) {
     }
     s->st.cell_updates++;
   }
+  return ORC_OK;
+}
+
+static int faster_level(const orc_state* s, int64_t f) {
+  int t = s->lev[s->m->fL[f]];
+  int64_t R = s->m->fR[f];
+  if (R >= 0 && s->lev[R] < t) t = s->lev[R];
+  return t;
+}
+
+/* One subiteration of Alg. 2 with flux accumulation for the slower side,
+ * forward Euler per level step:
+ *   1. at the start of an iteration (phase 0) every cell is synchronised;
+ *      compute time steps and levels;
+ *   2. the level of this subiteration is theta at phase 0, else the largest
+ *      tau <= theta with 2^tau dividing the phase;
+ *   3. every face whose faster side has level <= that tau is computed from
+ *      the current states of both cells and its time-integrated flux
+ *      2^tau_f dt_min * flux is added to both cells' accumulators;
+ *   4. cells whose level step ends now apply their accumulator. */
+static int subiteration(orc_state* s) {
+  const orc_mesh* m = s->m;
+  const orc_params* prm = &s->prm;
+  if (s->phase == 0 && (prm->reclassify || !s->classified)) {
+    int rc = classify_state(s);
+    if (rc) return rc;
+  }
+  int tau_s = orc_subiteration_level((int64_t)s->phase + 1, s->theta);
+  int rc = face_fluxes(s, s->U, tau_s, s->q);
+  if (rc) return rc;
+  for (int64_t f = 0; f < m->nf; ++f) {
+    if (!s->act[f]) continue;
+    double dtf = ldexp(s->dt_min, faster_level(s, f));
+    for (int k = 0; k < 5; ++k) s->q[5 * f + k] *= dtf;
+    if (m->fR[f] < 0 && prm->boundary == ORC_BC_WALL)
+      for (int k = 0; k < 3; ++k) s->st.wall_impulse[k] += s->q[5 * f + 1 + k];
+  }
+  int64_t sub = (int64_t)s->phase + 1;
+  rc = flow_sum_and_update(s, sub);
+  if (rc) return rc;
+  s->phase = (int32_t)(sub % ((int64_t)1 << s->theta));
+  s->t += s->dt_min;
+  s->st.subiterations++;
+  return ORC_OK;
+}
+
+/* States of every cell at dt_min unit k of the iteration, into Ut.  A cell
+ * of level tau is inside its step [a, a + 2^tau) with a a multiple of 2^tau;
+ * its state there is U + w D with w = (k - a) / 2^tau, the elapsed fraction
+ * of the step (Alg. 2, intensive interpolation).  At a step boundary
+ * (k a multiple of 2^tau) the state is U (w = 0) when the step starts at k,
+ * and the prediction U + D (w = 1) when the step ends at k. */
+static void states_at(orc_state* s, int64_t k, int ending) {
+  const orc_mesh* m = s->m;
+  for (int64_t i = 0; i < m->nc; ++i) {
+    int64_t per = (int64_t)1 << s->lev[i];
+    int64_t r = k % per;
+    double w = (r == 0) ? (ending ? 1.0 : 0.0) : (double)r / (double)per;
+    for (int c = 0; c < 5; ++c)
+      s->Ut[5 * i + c] = (w == 0.0) ? s->U[5 * i + c] : s->U[5 * i + c] + w * s->D[5 * i + c];
+  }
+}
+
+/* One subiteration with a predictor and a corrector per level step:
+ *   1. as above: levels at phase 0, the subiteration's level tau_s; the
+ *      cells and faces of levels <= tau_s start a step at unit a = phase;
+ *   2. predictor: fluxes phi0 of the starting faces from the states at a;
+ *      each starting cell of level tau predicts the change of its step,
+ *      D = 2^tau dt_min (sum of its faces' +-phi0) / V (Alg. 2, extensive
+ *      prediction);
+ *   3. corrector: the cells and faces of levels <= upd end a step at unit
+ *      a + 1, upd the largest tau <= theta with 2^tau dividing a + 1;
+ *      fluxes phi1 of those faces from the states at a + 1, the face's
+ *      time-integrated flux q = 2^tau_f dt_min (phi0 + phi1) / 2, added to
+ *      both cells (Alg. 2, flow sum on cells, extensive correction); the
+ *      cells whose step ends apply their sum. */
+static int subiteration2(orc_state* s) {
+  const orc_mesh* m = s->m;
+  const orc_params* prm = &s->prm;
+  if (s->phase == 0 && (prm->reclassify || !s->classified)) {
+    int rc = classify_state(s);
+    if (rc) return rc;
+  }
+  int64_t a = s->phase, sub = a + 1;
+  int tau_s = orc_subiteration_level(sub, s->theta);
+  int upd = 0;
+  while (upd < s->theta && sub % ((int64_t)1 << (upd + 1)) == 0) ++upd;
+
+  /* predictor */
+  states_at(s, a, 0);
+  int rc = face_fluxes(s, s->Ut, tau_s, s->phi0);
+  if (rc) return rc;
+  for (int64_t i = 0; i < m->nc; ++i) {
+    if (s->lev[i] > tau_s) continue;
+    double acc[5] = {0, 0, 0, 0, 0};
+    for (int j = 0; j < 4; ++j) {
+      int64_t f = m->c2f[4 * i + j];
+      double sign = (m->fL[f] == i) ? -1.0 : 1.0;
+      for (int k = 0; k < 5; ++k) acc[k] += sign * s->phi0[5 * f + k];
+    }
+    double dtc = ldexp(s->dt_min, s->lev[i]);
+    for (int k = 0; k < 5; ++k) s->D[5 * i + k] = dtc * acc[k] / m->vol[i];
+  }
+
+  /* corrector */
+  states_at(s, sub, 1);
+  rc = face_fluxes(s, s->Ut, upd, s->phi1);
+  if (rc) return rc;
+  for (int64_t f = 0; f < m->nf; ++f) {
+    if (!s->act[f]) continue;
+    double h = 0.5 * ldexp(s->dt_min, faster_level(s, f));
+    for (int k = 0; k < 5; ++k) s->q[5 * f + k] = h * (s->phi0[5 * f + k] + s->phi1[5 * f + k]);
+    if (m->fR[f] < 0 && prm->boundary == ORC_BC_WALL)
+      for (int k = 0; k < 3; ++k) s->st.wall_impulse[k] += s->q[5 * f + 1 + k];
+  }
+  rc = flow_sum_and_update(s, sub);
+  if (rc) return rc;
   s->phase = (int32_t)(sub % ((int64_t)1 << s->theta));
   s->t += s->dt_min;
   s->st.subiterations++;
@@ -799,7 +926,7 @@ static int subiteration(orc_state* s) {
 int orc_advance(orc_state* s, int64_t n) {
   if (!s || n < 0) return ORC_E_ARG;
   for (int64_t k = 0; k < n; ++k) {
-    int rc = subiteration(s);
+    int rc = s->prm.time_order == 2 ? subiteration2(s) : subiteration(s);
     if (rc) return rc;
   }
   return ORC_OK;

@@ -14,7 +14,14 @@
  *     dt = 2^tau * dt_min, 2^theta subiterations with the level rule of
  *     Alg. 2, neighbours at most one level apart;
  *   - the cost model C(tau) = 2^(theta-tau) |Omega(tau)| of Sec. 2.2, which
- *     is what the cell-update counter counts.
+ *     is what the cell-update counter counts;
+ *   - a predictor/corrector form of every level step (time_order 2),
+ *     following the order of the steps of Alg. 2: predictor fluxes,
+ *     prediction, slower neighbours seen at the interpolated time, corrector
+ *     fluxes, correction.  The paper takes its interface formulas from a
+ *     cited report; the form here is this oracle's own reading (Heun's
+ *     method per level step, linear-in-time prediction of the slower side,
+ *     one shared time-integrated flux per face).
  * Readings where the paper is silent (flux accumulation for the slower side,
  * exact Riemann solver, MUSCL least squares with Barth-Jespersen limiting,
  * CFL formula, level margin) are listed in the project design notes.
@@ -45,6 +52,8 @@ typedef struct {
   int32_t newton_max_iter;
   int32_t boundary;    /* ORC_BC_WALL or ORC_BC_TRANSMIT for every boundary face */
   int32_t reclassify;  /* 1: reclassify at every iteration start; 0: only once */
+  int32_t time_order;  /* 1: forward Euler per level step; 2: predictor and
+                          corrector per level step (see orc_advance) */
 } orc_params;
 
 typedef struct {
@@ -113,10 +122,25 @@ int orc_state_new(const orc_mesh* m, const orc_params* prm,
                   const double* prim, orc_state** out);
 void orc_state_free(orc_state* s);
 /* Overwrite the full schedule state: conserved cons[n][5], accumulators
- * accum[n][5], levels[n], phase, theta, dt_min, time. */
+ * accum[n][5], levels[n], phase, theta, dt_min, time.  With time_order 2
+ * only phase 0 is accepted (mid-iteration the predictions are state too). */
 int orc_state_set(orc_state* s, const double* cons, const double* accum,
                   const int8_t* levels, int32_t phase, int32_t theta,
                   double dt_min, double t);
+/* Run n subiterations of dt_min each.
+ * time_order 1: every face whose faster side starts a step is computed once
+ *   from the current states, and its flux times the faster side's step is
+ *   added to both cells; a cell applies its sum when its own step ends.
+ * time_order 2: each level step [a, a + 2^tau dt_min] is a predictor and a
+ *   corrector.  Predictor, at the step start: fluxes phi0 from the states at
+ *   that time, and the cell's prediction D = 2^tau dt_min sum(+-phi0) / V.
+ *   A cell's state at a time inside its step is U + w D, w the fraction of
+ *   the step elapsed (w = 1 at the step's end): this is how a slower
+ *   neighbour is seen mid-step.  Corrector, at the end of the face's step
+ *   (its faster side's): fluxes phi1 from the states U + w D at that time,
+ *   and q = dt_f (phi0 + phi1) / 2 added to both cells as in time_order 1.
+ *   On one level this is Heun's method; q is shared by both cells, so the
+ *   scheme stays conservative across levels. */
 int orc_advance(orc_state* s, int64_t n_subiterations);
 /* Level tau computed in subiteration s (1-based) of an iteration with
  * levels 0..theta (Alg. 2). */

@@ -119,6 +119,21 @@ def random_state(n, seed, rho=(0.5, 2.0), vel=0.5, p=(0.5, 2.0)):
     return prim
 
 
+def pulse_state(nodes, tets, centre=(0.5, 0.5, 0.5), width=0.2, amp=0.01,
+                velocity=(0.1, 0.0, 0.0), rho=1.0, p=1.0, gamma=1.4):
+    """Smooth state for convergence studies: a Gaussian bump
+    g = exp(-|x - centre|^2 / width^2) of relative amplitude amp in density
+    and gamma * amp in pressure (isentropic to first order) on a uniform
+    flow of the given velocity."""
+    c = tet_centroids(nodes, tets)
+    g = np.exp(-((c - np.asarray(centre, dtype=np.float64)) ** 2).sum(1) / width ** 2)
+    prim = np.zeros((len(tets), 5))
+    prim[:, 0] = rho * (1.0 + amp * g)
+    prim[:, 1:4] = np.asarray(velocity, dtype=np.float64)
+    prim[:, 4] = p * (1.0 + gamma * amp * g)
+    return prim
+
+
 def sod_state(nodes, tets, x0=0.5, left=(1.0, 0.0, 1.0), right=(0.125, 0.0, 0.1)):
     """Shock-tube state along x: (rho, u, p) left of x0, right of it
     (Sod's 1978 data by default), zero transverse velocity."""
