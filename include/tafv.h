@@ -83,7 +83,7 @@ enum { TAFV_ORDER_CALLER = 0, TAFV_ORDER_MORTON = 1 };
  * newton_tol 1e-12, level_margin 1e-9, max_levels 5, order 2, precision
  * TAFV_FP64, guess TAFV_GUESS_TR, boundary TAFV_BC_WALL, newton_max_iter
  * 50, reclassify 1, scatter TAFV_SCATTER_GATHER, cell_order TAFV_ORDER_CALLER,
- * guess_stats 0, guess_gate 0, batch 0, guess_strength 0. */
+ * guess_stats 0, guess_gate 0, batch 0, guess_strength 0, time_order 1. */
 typedef struct {
   double gamma;          /* ratio of specific heats, > 1                        */
   double cfl;            /* dt_i = cfl V_i / sum_f (|u_i . n_f| + a_i) |A_f|    */
@@ -127,6 +127,22 @@ typedef struct {
                             |p_L - p_R|/p_m is at least this (>= 0; 0: every
                             face where p_TR is inexact).  A wave evaluates
                             the network once if any of its faces qualifies. */
+  int32_t time_order;    /* 1: each level step is one forward Euler step; the
+                            faces of a subiteration are computed once, from
+                            the cells' current states.  2: each level step
+                            is a predictor and a corrector (Sec. 2.2, Alg. 2:
+                            predictor, prediction, interpolation of the
+                            slower levels, corrector, correction): predictor
+                            fluxes at the step's start give each starting
+                            cell a predicted change D of its step; a cell is
+                            seen inside its step as U + w D, w the elapsed
+                            fraction; corrector fluxes at the end of each
+                            face's step give q = dt_f (phi0 + phi1) / 2,
+                            added to both cells.  Heun's method on one
+                            level, second order in time across levels,
+                            conservative; two face solves per face step.
+                            Needs TAFV_SCATTER_GATHER and batch 0;
+                            checkpoints are written at phase 0 only.      */
 } tafv_params;
 
 /* Counters (int64) and schedule state.  Summed over meshes where a call

@@ -16,7 +16,7 @@ using namespace tafv;
 
 namespace {
 
-const char* kProfNames[] = {"classify", "grad", "flux", "update", "gather"};
+const char* kProfNames[] = {"classify", "grad", "flux", "update", "gather", "predict"};
 
 thread_local std::string g_create_err;
 
@@ -49,7 +49,7 @@ void free_mesh(DevMesh* m) {
                   m->pf.list, m->pf.counts, m->pf.start, m->pc.list, m->pc.counts,
                   m->pc.start, m->dscal, m->dcount, m->dimpulse, m->pf.offs, m->pc.offs,
                   m->pf.scan_tmp, m->pc.scan_tmp, m->Q, m->frec, m->fkey, m->ckey, m->fpack,
-                  m->perm, m->xfer, m->chist, m->rb, m->dmin};
+                  m->perm, m->xfer, m->chist, m->rb, m->dmin, m->Q0, m->D, m->Ut};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   delete m;
@@ -95,6 +95,16 @@ int level_histogram(DevMesh& m) {
     if (n > 0) theta = t;
   }
   return theta;
+}
+
+// predictor/corrector form: at an iteration start every cell starts a step,
+// so its state for the first predictor is U itself
+hipError_t sync_time_states(tafv_ctx* c, DevMesh& m) {
+  if (!m.Ut) return hipSuccess;
+  hipError_t e = hipMemcpyAsync(m.Ut, m.U, sizeof(double) * 5 * m.nc, hipMemcpyDeviceToDevice,
+                                c->stream);
+  if (e == hipSuccess) e = launch_fill_f64(c->stream, m.D, 0.0, (int64_t)5 * m.nc);
+  return e;
 }
 
 tafv_status classify(tafv_ctx* c, DevMesh& m) {
@@ -158,6 +168,47 @@ FluxFeatures flux_features(tafv_ctx* c, DevMesh& m) {
   return ft;
 }
 
+// Predictor/corrector form of one subiteration (gather mode).  The cells and
+// faces of levels <= tau_s start a step at its beginning, those of levels
+// <= upd end one at its end.  Predictor: gradients and fluxes Q0 of the
+// starting faces from the states Ut at the beginning; predictions D of the
+// starting cells and the states Ut at the end.  Corrector: gradients and
+// fluxes Q of the ending faces from those states; sums q = dt_f (Q0 + Q)/2
+// in the cells; ending cells apply theirs.  The wall impulse is the
+// corrector pass's q of each wall face.
+tafv_status subiteration2(tafv_ctx* c, DevMesh& m, const StepArgs& a, int tau_s, int upd,
+                          int64_t s, int64_t& faces) {
+  const double dt_min = m.dt_min;
+  const int pcnt = m.hstart_f[tau_s + 1], ccnt = m.hstart_f[upd + 1];
+  if (c->prm.order == 2) {
+    ProfScope ps(c, P_GRAD, cells_upto_g(m, tau_s));
+    HIP_TRY(c, launch_grad(c->stream, m, a, cells_upto_g(m, tau_s), m.Ut));
+  }
+  {
+    ProfScope ps(c, P_FLUX, pcnt);
+    HIP_TRY(c, launch_flux(c->stream, m, a, 0, pcnt, flux_features(c, m), m.Ut, m.Q0, 1));
+  }
+  {
+    ProfScope ps(c, P_PREDICT, m.nc);
+    HIP_TRY(c, launch_predict(c->stream, m, tau_s, (int)s, dt_min, c->prm.precision));
+  }
+  if (c->prm.order == 2) {
+    ProfScope ps(c, P_GRAD, cells_upto_g(m, upd));
+    HIP_TRY(c, launch_grad(c->stream, m, a, cells_upto_g(m, upd), m.Ut));
+  }
+  {
+    ProfScope ps(c, P_FLUX, ccnt);
+    HIP_TRY(c, launch_flux(c->stream, m, a, 0, ccnt, flux_features(c, m), m.Ut, m.Q, 2, m.Q0));
+  }
+  {
+    ProfScope ps(c, P_GATHER, cells_upto_g(m, upd));
+    HIP_TRY(c, launch_cell_gather2(c->stream, m, cells_upto_g(m, upd), upd, dt_min,
+                                   c->prm.precision));
+  }
+  faces = (int64_t)pcnt + ccnt;
+  return TAFV_OK;
+}
+
 tafv_status subiteration(tafv_ctx* c, DevMesh& m, tafv_stats* acc) {
   if (m.phase == 0 && (c->prm.reclassify || !m.classified)) {
     tafv_status st = classify(c, m);
@@ -182,7 +233,10 @@ tafv_status subiteration(tafv_ctx* c, DevMesh& m, tafv_stats* acc) {
   }
   int64_t ucnt = cells_upto_tau(m, upd);
   int64_t faces = 0;
-  if (m.scatter == TAFV_SCATTER_COLOUR) {
+  if (c->prm.time_order == 2) {
+    tafv_status st = subiteration2(c, m, a, tau_s, upd, s, faces);
+    if (st != TAFV_OK) return st;
+  } else if (m.scatter == TAFV_SCATTER_COLOUR) {
     for (int col = 0; col < m.ncolours; ++col) {
       int first = m.hstart_f[col * kMaxLevels];
       int cnt = m.hstart_f[col * kMaxLevels + tau_s + 1] - first;
@@ -327,6 +381,12 @@ tafv_status upload_host_mesh(tafv_ctx* c, const HostMesh& hm, DevMesh** out) {
   if (m->scatter == TAFV_SCATTER_GATHER)
     chk(hipMalloc(&m->Q, (c->prm.precision == TAFV_FP32_FLUX ? sizeof(float) : sizeof(double)) *
                              5 * std::max<size_t>(nf, 1)));
+  if (c->prm.time_order == 2) {
+    chk(hipMalloc(&m->Q0, (c->prm.precision == TAFV_FP32_FLUX ? sizeof(float) : sizeof(double)) *
+                              5 * std::max<size_t>(nf, 1)));
+    chk(dalloc(&m->D, 5 * nc));
+    chk(dalloc(&m->Ut, 5 * nc));
+  }
   chk(dalloc(&m->fkey, nf));
   chk(dalloc(&m->ckey, nc));
   chk(dalloc(&m->fpack, nc));
@@ -388,6 +448,7 @@ tafv_status tafv_params_default(tafv_params* p) {
   p->guess_gate = 0.0;
   p->batch = 0;
   p->guess_strength = 0.0;
+  p->time_order = 1;
   return TAFV_OK;
 }
 
@@ -412,6 +473,11 @@ tafv_status tafv_create(int device, const tafv_params* params, void* hip_stream,
   if (p.batch != 0 && p.batch != 1) return fail(nullptr, TAFV_E_ARG, "batch must be 0 or 1");
   if (p.batch && p.scatter != TAFV_SCATTER_GATHER)
     return fail(nullptr, TAFV_E_ARG, "the batched form needs gather scatter");
+  if (p.time_order != 1 && p.time_order != 2)
+    return fail(nullptr, TAFV_E_ARG, "time_order must be 1 or 2");
+  if (p.time_order == 2 && (p.batch || p.scatter != TAFV_SCATTER_GATHER))
+    return fail(nullptr, TAFV_E_ARG,
+                "the predictor/corrector form needs gather scatter and no batch");
   if (p.guess == TAFV_GUESS_MLP && (p.gamma != 1.4 || p.scatter != TAFV_SCATTER_GATHER))
     return fail(nullptr, TAFV_E_ARG, "the learned guess needs gamma 1.4 and gather scatter");
   int ndev = 0;
@@ -553,6 +619,7 @@ tafv_status tafv_state_init(tafv_ctx* c, int32_t mesh_id, const double* prim) {
   if (e == hipSuccess)
     e = hipMemcpyAsync(m->U0, m->U, sizeof(double) * 5 * m->nc, hipMemcpyDeviceToDevice,
                        c->stream);
+  if (e == hipSuccess) e = sync_time_states(c, *m);
   if (e == hipSuccess) e = launch_fill_u64(c->stream, m->dcount, 0ull, kCounterWords);
   if (e == hipSuccess) e = launch_fill_f64(c->stream, m->dimpulse, 0.0, kCounterWords);
   if (e == hipSuccess) e = launch_fill_u64(c->stream, m->dscal, 0ull, 4);
@@ -584,6 +651,7 @@ tafv_status tafv_state_reset(tafv_ctx* c, int32_t mesh_id) {
   HIP_TRY(c, hipMemcpyAsync(m->U, m->U0, sizeof(double) * 5 * m->nc, hipMemcpyDeviceToDevice,
                             c->stream));
   HIP_TRY(c, launch_fill_f64(c->stream, m->R, 0.0, (int64_t)5 * m->nc));
+  HIP_TRY(c, sync_time_states(c, *m));
   m->phase = 0;
   m->theta = 0;
   m->t = 0.0;
@@ -705,6 +773,9 @@ tafv_status tafv_checkpoint_write(tafv_ctx* c, int32_t mesh_id, const double* co
   if (theta < 0 || theta >= m->max_levels || phase < 0 || phase >= (1 << theta) ||
       !(dt_min > 0.0))
     return fail(c, TAFV_E_ARG, "invalid schedule state");
+  if (c->prm.time_order == 2 && phase != 0)
+    return fail(c, TAFV_E_ARG,
+                "predictor/corrector form: checkpoints are written at phase 0 only");
   for (int64_t i = 0; i < m->nc; ++i)
     if (levels[i] < 0 || levels[i] > theta) return fail(c, TAFV_E_ARG, "level out of range");
   HIP_TRY(c, hipSetDevice(c->device));
@@ -715,6 +786,7 @@ tafv_status tafv_checkpoint_write(tafv_ctx* c, int32_t mesh_id, const double* co
   HIP_TRY(c, hipMemcpyAsync(m->xfer, accum, sizeof(double) * 5 * m->nc, hipMemcpyHostToDevice,
                             c->stream));
   HIP_TRY(c, launch_from_caller_f64(c->stream, *m, m->xfer, m->R));
+  HIP_TRY(c, sync_time_states(c, *m));
   HIP_TRY(c, hipStreamSynchronize(c->stream));
   HIP_TRY(c, hipMemcpyAsync(m->xfer, levels, m->nc, hipMemcpyHostToDevice, c->stream));
   HIP_TRY(c, launch_from_caller_i8(c->stream, *m, (const int8_t*)m->xfer, m->lev));

@@ -21,7 +21,9 @@ hipError_t launch_state_init_rows(hipStream_t s, int n, const int* perm, const d
 hipError_t launch_dt(hipStream_t s, DevMesh& m, const StepArgs& a);
 hipError_t launch_classify(hipStream_t s, DevMesh& m, const StepArgs& a);
 hipError_t launch_partitions(hipStream_t s, DevMesh& m);
-hipError_t launch_grad(hipStream_t s, DevMesh& m, const StepArgs& a, int count);
+// U: the cell states the pass reads (default: the mesh's U)
+hipError_t launch_grad(hipStream_t s, DevMesh& m, const StepArgs& a, int count,
+                       const double* U = nullptr);
 // optional flux features: feat bit 0 = gate statistics and face logging,
 // bit 1 = learned guess (gamma = 1.4, gather mode)
 struct FluxFeatures {
@@ -35,11 +37,24 @@ struct FluxFeatures {
   float guess_gate = 0.f;
   float guess_strength = 0.f;
 };
+// U: the cell states read at first order; Q: where gather mode stores the
+// face fluxes (defaults: the mesh's U and Q); impulse_mode and Qpred: the
+// wall impulse of the predictor/corrector form (see FluxArgs)
 hipError_t launch_flux(hipStream_t s, DevMesh& m, const StepArgs& a, int first, int count,
-                       const FluxFeatures& ft);
+                       const FluxFeatures& ft, const double* U = nullptr, void* Q = nullptr,
+                       int impulse_mode = 0, const void* Qpred = nullptr);
 hipError_t launch_cell_gather(hipStream_t s, DevMesh& m, int count, int tau_s, int tau_upd,
                               double dt_min, int precision);
 hipError_t launch_update(hipStream_t s, DevMesh& m, int count, int tau_upd);
+// predictor/corrector form (gather mode): predictions D of the cells whose
+// step starts (tau <= tau_s) from the predictor fluxes Q0, and the states Ut
+// of every cell at the end of subiteration `sub`; then the corrector sums
+// of the first `count` listed cells for the faces whose step ends (tau_f <=
+// tau_upd), ending cells applied to U and Ut
+hipError_t launch_predict(hipStream_t s, DevMesh& m, int tau_s, int sub, double dt_min,
+                          int precision);
+hipError_t launch_cell_gather2(hipStream_t s, DevMesh& m, int count, int tau_upd, double dt_min,
+                               int precision);
 hipError_t launch_pack_readback(hipStream_t s, DevMesh& m, int Kf);
 constexpr int kReadbackInts = 8 + kMaxKeys + 1 + kMaxLevels + 1 + kMaxKeys;
 // host-transfer staging: rows of 5 doubles or 1 byte, caller <-> internal order

@@ -389,6 +389,36 @@ __global__ __launch_bounds__(kBlock) void k_cell_gather(int count, const int* __
 }
 
 
+// predictor/corrector form: predictions of the starting cells and the
+// states of every cell at the end of the subiteration
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_predict(int nc, const uint32_t* __restrict__ fpack,
+                                                    const int* __restrict__ c2f,
+                                                    const T* __restrict__ Q0, double dt_min,
+                                                    const double* __restrict__ vol,
+                                                    const double* __restrict__ U,
+                                                    double* __restrict__ D,
+                                                    double* __restrict__ Ut, int tau_s, int s) {
+  int i = xcd_block() * kBlock + threadIdx.x;
+  if (i >= nc) return;
+  predict_item<T>(i, nc, fpack, c2f, Q0, dt_min, vol, U, D, Ut, tau_s, s);
+}
+
+// predictor/corrector form: corrector sums of the listed cells
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_cell_gather2(
+    int count, const int* __restrict__ list, int nc, const uint32_t* __restrict__ fpack,
+    const int* __restrict__ c2f, const T* __restrict__ Q0, const T* __restrict__ Q1,
+    double dt_min, const double* __restrict__ vol, double* __restrict__ U,
+    double* __restrict__ Ut, double* __restrict__ R, int tau_upd,
+    unsigned long long* dscal) {
+  int idx = xcd_block() * kBlock + threadIdx.x;
+  if (idx >= count) return;
+  if (!cell_gather2_item<T>(list[idx], nc, fpack, c2f, Q0, Q1, dt_min, vol, U, Ut, R, tau_upd))
+    atomicOr(&dscal[2], 1ull);
+}
+
+
 // ---------------------------------------------------------------------------
 // cells whose level step ends: U += R / V, R = 0
 
@@ -531,14 +561,16 @@ hipError_t launch_from_caller_i8(hipStream_t s, DevMesh& m, const int8_t* src, i
   return rows_from_caller<int8_t>(s, m, 1, src, dst);
 }
 
-hipError_t launch_grad(hipStream_t s, DevMesh& m, const StepArgs& a, int count) {
+hipError_t launch_grad(hipStream_t s, DevMesh& m, const StepArgs& a, int count,
+                       const double* U) {
   if (count <= 0) return hipSuccess;
+  if (!U) U = m.U;
   if (a.precision == TAFV_FP32_FLUX) {
-    GradArgs<float> g{m.pc.list, count, m.nc, m.nf, m.U, m.nb_, m.lsq32, m.rf32, m.fA,
+    GradArgs<float> g{m.pc.list, count, m.nc, m.nf, U, m.nb_, m.lsq32, m.rf32, m.fA,
                       (float*)m.Wf, a.gas.gm1, a.boundary};
     hipLaunchKernelGGL(k_grad<float>, dim3(blocks_for(count)), dim3(kBlock), 0, s, g);
   } else {
-    GradArgs<double> g{m.pc.list, count, m.nc, m.nf, m.U, m.nb_, m.lsq, m.rf, m.fA,
+    GradArgs<double> g{m.pc.list, count, m.nc, m.nf, U, m.nb_, m.lsq, m.rf, m.fA,
                        (double*)m.Wf, a.gas.gm1, a.boundary};
     hipLaunchKernelGGL(k_grad<double>, dim3(blocks_for(count)), dim3(kBlock), 0, s, g);
   }
@@ -574,21 +606,26 @@ static void flux_feat_launch(hipStream_t s, int order, int feat, int count, cons
 }
 
 hipError_t launch_flux(hipStream_t s, DevMesh& m, const StepArgs& a, int first, int count,
-                       const FluxFeatures& ft) {
+                       const FluxFeatures& ft, const double* U, void* Q, int impulse_mode,
+                       const void* Qpred) {
   if (count <= 0) return hipSuccess;
   const int4* rec = m.frec + first;
+  if (!U) U = m.U;
+  if (!Q) Q = m.Q;
   if (a.precision == TAFV_FP32_FLUX) {
-    FluxArgs<float> f{rec, count, m.nf, m.nc, m.fA32, m.U, (const float*)m.Wf, m.R, (float*)m.Q, m.dcount,
+    FluxArgs<float> f{rec, count, m.nf, m.nc, m.fA32, U, (const float*)m.Wf, m.R, (float*)Q, m.dcount,
                       m.dimpulse, a, ft.mlp, ft.log_rows, ft.log_count, ft.log_cap,
-                      ft.log_rate, ft.log_seed, ft.subit, ft.guess_gate, ft.guess_strength};
+                      ft.log_rate, ft.log_seed, ft.subit, ft.guess_gate, ft.guess_strength,
+                      impulse_mode, (const float*)Qpred};
     if (ft.feat && a.gas.is14 && m.scatter == TAFV_SCATTER_GATHER)
       flux_feat_launch<float>(s, a.order, ft.feat, count, f);
     else if (a.gas.is14) flux_launch<float, true>(s, a.order, m.scatter, count, f);
     else flux_launch<float, false>(s, a.order, m.scatter, count, f);
   } else {
-    FluxArgs<double> f{rec, count, m.nf, m.nc, m.fA, m.U, (const double*)m.Wf, m.R, (double*)m.Q,
+    FluxArgs<double> f{rec, count, m.nf, m.nc, m.fA, U, (const double*)m.Wf, m.R, (double*)Q,
                        m.dcount, m.dimpulse, a, ft.mlp, ft.log_rows, ft.log_count, ft.log_cap,
-                       ft.log_rate, ft.log_seed, ft.subit, ft.guess_gate, ft.guess_strength};
+                       ft.log_rate, ft.log_seed, ft.subit, ft.guess_gate, ft.guess_strength,
+                       impulse_mode, (const double*)Qpred};
     if (ft.feat && a.gas.is14 && m.scatter == TAFV_SCATTER_GATHER)
       flux_feat_launch<double>(s, a.order, ft.feat, count, f);
     else if (a.gas.is14) flux_launch<double, true>(s, a.order, m.scatter, count, f);
@@ -608,6 +645,34 @@ hipError_t launch_cell_gather(hipStream_t s, DevMesh& m, int count, int tau_s, i
     hipLaunchKernelGGL(k_cell_gather<double>, dim3(blocks_for(count)), dim3(kBlock), 0, s, count,
                        m.pc.list, m.nc, m.fpack, m.c2f, (const double*)m.Q, dt_min, m.vol, m.U,
                        m.R, tau_s, tau_upd, m.dscal);
+  return hipGetLastError();
+}
+
+hipError_t launch_predict(hipStream_t s, DevMesh& m, int tau_s, int sub, double dt_min,
+                          int precision) {
+  if (m.nc <= 0) return hipSuccess;
+  if (precision == TAFV_FP32_FLUX)
+    hipLaunchKernelGGL(k_predict<float>, dim3(blocks_for(m.nc)), dim3(kBlock), 0, s, m.nc,
+                       m.fpack, m.c2f, (const float*)m.Q0, dt_min, m.vol, m.U, m.D, m.Ut,
+                       tau_s, sub);
+  else
+    hipLaunchKernelGGL(k_predict<double>, dim3(blocks_for(m.nc)), dim3(kBlock), 0, s, m.nc,
+                       m.fpack, m.c2f, (const double*)m.Q0, dt_min, m.vol, m.U, m.D, m.Ut,
+                       tau_s, sub);
+  return hipGetLastError();
+}
+
+hipError_t launch_cell_gather2(hipStream_t s, DevMesh& m, int count, int tau_upd, double dt_min,
+                               int precision) {
+  if (count <= 0) return hipSuccess;
+  if (precision == TAFV_FP32_FLUX)
+    hipLaunchKernelGGL(k_cell_gather2<float>, dim3(blocks_for(count)), dim3(kBlock), 0, s,
+                       count, m.pc.list, m.nc, m.fpack, m.c2f, (const float*)m.Q0,
+                       (const float*)m.Q, dt_min, m.vol, m.U, m.Ut, m.R, tau_upd, m.dscal);
+  else
+    hipLaunchKernelGGL(k_cell_gather2<double>, dim3(blocks_for(count)), dim3(kBlock), 0, s,
+                       count, m.pc.list, m.nc, m.fpack, m.c2f, (const double*)m.Q0,
+                       (const double*)m.Q, dt_min, m.vol, m.U, m.Ut, m.R, tau_upd, m.dscal);
   return hipGetLastError();
 }
 

@@ -273,7 +273,31 @@ struct FluxArgs {
   unsigned long long log_seed, subit;
   float guess_gate;
   float guess_strength;  // network only where the jump strength reaches this
+  // wall impulse of gather mode: 0 = dt_f phi (one pass per face step);
+  // predictor/corrector form: 1 = none (predictor pass), 2 = the face step's
+  // q = dt_f (Qpred + phi) / 2 (corrector pass, Qpred the predictor fluxes)
+  int impulse_mode;
+  const T* Qpred;
 };
+
+// the wall impulse of one wall face's time-integrated flux, gather mode
+template <typename T>
+__device__ inline void add_wall_impulse(const FluxArgs<T>& a, int4 r, double dt_min,
+                                        const T* phi, double& i0, double& i1, double& i2) {
+  if (a.impulse_mode == 1) return;
+  if (a.impulse_mode == 2) {
+    const T* p0 = a.Qpred + 5 * (size_t)r.x;
+    const double h = ldexp(dt_min, r.w - 1);
+    i0 += h * ((double)p0[1] + (double)phi[1]);
+    i1 += h * ((double)p0[2] + (double)phi[2]);
+    i2 += h * ((double)p0[3] + (double)phi[3]);
+    return;
+  }
+  const double dtf = ldexp(dt_min, r.w);
+  i0 += dtf * (double)phi[1];
+  i1 += dtf * (double)phi[2];
+  i2 += dtf * (double)phi[3];
+}
 
 template <int ORDER, typename T>
 __device__ inline void load_side(const FluxArgs<T>& a, int h, T* w) {
@@ -444,12 +468,7 @@ __device__ inline void flux_store_item(const FluxArgs<T>& a, int4 r, double dt_m
   add_info(acc, info);
   T* q = a.Q + 5 * (size_t)r.x;
   for (int k = 0; k < 5; ++k) q[k] = phi[k];
-  if (r.z < 0 && a.s.boundary == TAFV_BC_WALL) {
-    double dtf = ldexp(dt_min, r.w);
-    i0 += dtf * (double)phi[1];
-    i1 += dtf * (double)phi[2];
-    i2 += dtf * (double)phi[3];
-  }
+  if (r.z < 0 && a.s.boundary == TAFV_BC_WALL) add_wall_impulse(a, r, dt_min, phi, i0, i1, i2);
 }
 
 // splitmix64 output function (Steele, Lea, Flood 2014): a counter-based
@@ -620,12 +639,7 @@ __device__ inline void flux_feat_item(const FluxArgs<T>& a, bool valid, int4 r, 
     }
     T* q = a.Q + 5 * (size_t)r.x;
     for (int k = 0; k < 5; ++k) q[k] = phi[k];
-    if (wall) {
-      double dtf = ldexp(dt_min, r.w);
-      i0 += dtf * (double)phi[1];
-      i1 += dtf * (double)phi[2];
-      i2 += dtf * (double)phi[3];
-    }
+    if (wall) add_wall_impulse(a, r, dt_min, phi, i0, i1, i2);
   }
   add_info(acc, info);
 }
@@ -670,6 +684,106 @@ __device__ inline bool cell_gather_item(int i, int nc, const uint32_t* __restric
     for (int k = 0; k < 5; ++k) {
       double u = U[5 * (size_t)i + k] + acc[k] / v;
       U[5 * (size_t)i + k] = u;
+      Ri[k] = 0.0;
+      bad |= !isfinite(u);
+    }
+    return !bad;
+  } else if (touched) {
+    for (int k = 0; k < 5; ++k) Ri[k] = acc[k];
+  }
+  return true;
+}
+
+// ---------------------------------------------------------------------------
+// predictor/corrector form of the level steps (Sec. 2.2, Alg. 2: predictor,
+// extensive prediction, interpolation of the slower levels, corrector,
+// extensive correction).  Per cell: U the state at its step start, D the
+// change its predictor forecasts for the step, Ut its state at the time the
+// next face pass looks at: U + w D, w the elapsed fraction of its step.
+
+// After the predictor fluxes phi0 of a subiteration are stored, per cell of
+// the mesh: a cell whose step starts now (tau <= tau_s) forms
+// D = 2^tau dt_min (sum of its faces' +-phi0, local order) / V; then every
+// cell's state at the end of the subiteration, unit s of the iteration, is
+// written to Ut, with w = (s mod 2^tau) / 2^tau, or 1 where its step ends.
+template <typename T>
+__device__ inline void predict_item(int i, int nc, const uint32_t* __restrict__ fpack,
+                                    const int* __restrict__ c2f, const T* __restrict__ Q0,
+                                    double dt_min, const double* __restrict__ vol,
+                                    const double* __restrict__ U, double* __restrict__ D,
+                                    double* __restrict__ Ut, int tau_s, int s) {
+  const uint32_t pk = fpack[i];
+  const int ti = (pk >> 20) & 15;
+  double d[5];
+  double* Di = D + 5 * (size_t)i;
+  if (ti <= tau_s) {
+    double acc[5] = {0, 0, 0, 0, 0};
+    for (int m = 0; m < 4; ++m) {
+      const T* q = Q0 + 5 * (size_t)c2f[m * nc + i];
+      if (pk & (1u << (16 + m))) {
+        for (int k = 0; k < 5; ++k) acc[k] += (double)q[k];
+      } else {
+        for (int k = 0; k < 5; ++k) acc[k] -= (double)q[k];
+      }
+    }
+    const double dtc = ldexp(dt_min, ti), v = vol[i];
+    for (int k = 0; k < 5; ++k) {
+      d[k] = dtc * acc[k] / v;
+      Di[k] = d[k];
+    }
+  } else {
+    for (int k = 0; k < 5; ++k) d[k] = Di[k];
+  }
+  const int per = 1 << ti, r = s & (per - 1);
+  const double w = r == 0 ? 1.0 : (double)r / (double)per;
+  const double* Ui = U + 5 * (size_t)i;
+  double* Uti = Ut + 5 * (size_t)i;
+  for (int k = 0; k < 5; ++k) Uti[k] = Ui[k] + w * d[k];
+}
+
+// Corrector gather, per cell with a face whose step ends now (tau_f <= upd):
+// add those faces' q = 2^tau_f dt_min (phi0 + phi1) / 2 in local face order;
+// a cell whose own step ends applies its sum, U += R / V, and its state for
+// the next predictor is the new U.  Returns false on a non-finite state.
+template <typename T>
+__device__ inline bool cell_gather2_item(int i, int nc, const uint32_t* __restrict__ fpack,
+                                         const int* __restrict__ c2f,
+                                         const T* __restrict__ Q0, const T* __restrict__ Q1,
+                                         double dt_min, const double* __restrict__ vol,
+                                         double* __restrict__ U, double* __restrict__ Ut,
+                                         double* __restrict__ R, int tau_upd) {
+  const uint32_t pk = fpack[i];
+  const int ti = (pk >> 20) & 15;
+  const bool ends = ti <= tau_upd;
+  bool touched = false;
+  double acc[5] = {0, 0, 0, 0, 0};
+  double* Ri = R + 5 * (size_t)i;
+  for (int m = 0; m < 4; ++m) {
+    const int tf = (int)((pk >> (4 * m)) & 15);
+    if (tf > tau_upd) continue;
+    if (!touched) {
+      for (int k = 0; k < 5; ++k) acc[k] = Ri[k];
+      touched = true;
+    }
+    const size_t f = (size_t)c2f[m * nc + i];
+    const T* q0 = Q0 + 5 * f;
+    const T* q1 = Q1 + 5 * f;
+    const double h = ldexp(dt_min, tf - 1);
+    if (pk & (1u << (16 + m))) {
+      for (int k = 0; k < 5; ++k) acc[k] += h * ((double)q0[k] + (double)q1[k]);
+    } else {
+      for (int k = 0; k < 5; ++k) acc[k] -= h * ((double)q0[k] + (double)q1[k]);
+    }
+  }
+  if (ends) {
+    if (!touched)
+      for (int k = 0; k < 5; ++k) acc[k] = Ri[k];
+    const double v = vol[i];
+    bool bad = false;
+    for (int k = 0; k < 5; ++k) {
+      const double u = U[5 * (size_t)i + k] + acc[k] / v;
+      U[5 * (size_t)i + k] = u;
+      Ut[5 * (size_t)i + k] = u;
       Ri[k] = 0.0;
       bad |= !isfinite(u);
     }

@@ -82,6 +82,11 @@ struct DevMesh {
   void* Q = nullptr;       // [nf][5] gather mode: face fluxes |A| F . n in the flux
                            // precision (double or float); the cells scale them
                            // by 2^tau_f dt_min in FP64
+  // predictor/corrector form only (time order 2)
+  void* Q0 = nullptr;      // [nf][5] predictor flux of each face's current step (flux
+                           // precision)
+  double* D = nullptr;     // [nc][5] predicted change of each cell's current step
+  double* Ut = nullptr;    // [nc][5] cell states at the time the next face pass reads
   int4* frec = nullptr;    // [nf] face records {f, hL, hR, tau_f} in partition order
   // schedule lists
   Partition pf, pc;        // faces by (colour, tau_f); cells by tau_g
@@ -222,7 +227,7 @@ void free_dev_mesh(DevMesh* m);
 tafv_status read_slot_counters(tafv_ctx* c, DevMesh& m, tafv_stats* st);
 
 // per-kernel-class timing with HIP events on the context stream
-enum { P_CLASSIFY = 0, P_GRAD = 1, P_FLUX = 2, P_UPDATE = 3, P_GATHER = 4, P_N = 5 };
+enum { P_CLASSIFY = 0, P_GRAD = 1, P_FLUX = 2, P_UPDATE = 3, P_GATHER = 4, P_PREDICT = 5, P_N = 6 };
 struct ProfScope {
   tafv_ctx* c;
   int cls;

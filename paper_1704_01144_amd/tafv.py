@@ -35,7 +35,8 @@ class tafv_params(C.Structure):
                 ("newton_max_iter", C.c_int32), ("reclassify", C.c_int32),
                 ("scatter", C.c_int32), ("cell_order", C.c_int32),
                 ("guess_stats", C.c_int32), ("guess_gate", C.c_double),
-                ("batch", C.c_int32), ("guess_strength", C.c_double)]
+                ("batch", C.c_int32), ("guess_strength", C.c_double),
+                ("time_order", C.c_int32)]
 
 
 class tafv_stats(C.Structure):
