@@ -54,14 +54,15 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def run_form(T, torch, cfg, precision, steps, warmup, scatter, mlp=None, stats=0):
+def run_form(T, torch, cfg, precision, steps, warmup, scatter, mlp=None, stats=0, time_order=1):
     stream = torch.cuda.current_stream()
     extra = {}
     if mlp is not None:
         extra = dict(guess=T.GUESS_MLP, guess_stats=stats, guess_gate=mlp["gate"],
                      guess_strength=mlp["strength"])
     s = T.Solver(device=0, hip_stream=stream.cuda_stream, max_levels=cfg["max_levels"],
-                 order=cfg["order"], precision=precision, scatter=scatter, **extra)
+                 order=cfg["order"], precision=precision, scatter=scatter, time_order=time_order,
+                 **extra)
     s.upload(cfg["nodes"], cfg["tets"])
     if mlp is not None:
         T.tafv_mlp_set(s.ctx, mlp["theta"])
@@ -320,6 +321,8 @@ def main():
     ap.add_argument("--no-learned", action="store_true")
     ap.add_argument("--scatter", type=int, default=1, help="0 colour, 1 gather")
     ap.add_argument("--no-batch", action="store_true", help="skip the 128-mesh batched form")
+    ap.add_argument("--no-time2", action="store_true",
+                    help="skip the predictor/corrector form (second order in time)")
     ap.add_argument("--batch-only", action="store_true",
                     help="only the batched form, FP64 and FP32 with the two-rarefaction start")
     ap.add_argument("--copy-probe", action="store_true",
@@ -424,6 +427,25 @@ def main():
                 "newton_per_face_all": round(rs["newton"] / max(rs["faces"], 1), 4)}
             log(f"fp32 + learned: {vl / 1e9:.3f} G/s, gate {g['gate']}, "
                 f"per-gate updates {g['newton_per_inexact_face']}")
+    if not args.no_time2 and args.scatter == 1:
+        forms = out.setdefault("forms", {})
+        for prec, name in ((T.FP64, "fp64"), (T.FP32_FLUX, "fp32_flux")):
+            if prec == T.FP32_FLUX and args.no_fp32:
+                continue
+            rt = run_form(T, torch, cfg, prec, args.steps, args.warmup, args.scatter, time_order=2)
+            vt = rt["updates"] / (rt["ms"] * 1e-3)
+            entry = {"value": round(vt, 1), "ms_per_step": round(rt["ms"] / args.steps, 4),
+                     "cost_vs_time_order_1": round(rt["ms"] / r64["ms"], 3),
+                     "cell_updates_per_step": rt["updates"] // args.steps,
+                     "face_solves_per_step": rt["faces"] // args.steps,
+                     "kernels_ms": {k: round(v["ms"], 3) for k, v in rt["prof"].items()}}
+            if prec == T.FP64:
+                rt64 = rt
+            else:
+                entry["l1_rho"], entry["l1_E"] = l1_errors(cfg, rt64["cons"], rt["cons"])
+            forms[f"time_order_2_{name}"] = entry
+            log(f"time order 2, {name}: {vt / 1e9:.3f} G cell-updates/s, "
+                f"{rt['ms'] / args.steps:.2f} ms per step")
     if not args.no_batch and not args.no_fp32 and not args.no_learned and args.scatter == 1:
         cases = I.config_batch(128)
         ncell = sum(len(c["tets"]) for c in cases)

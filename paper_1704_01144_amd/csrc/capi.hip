@@ -173,9 +173,9 @@ FluxFeatures flux_features(tafv_ctx* c, DevMesh& m) {
 // <= upd end one at its end.  Predictor: gradients and fluxes Q0 of the
 // starting faces from the states Ut at the beginning; predictions D of the
 // starting cells and the states Ut at the end.  Corrector: gradients and
-// fluxes Q of the ending faces from those states; sums q = dt_f (Q0 + Q)/2
-// in the cells; ending cells apply theirs.  The wall impulse is the
-// corrector pass's q of each wall face.
+// fluxes of the ending faces from those states, stored as Q = Q0 + phi1;
+// sums q = dt_f Q / 2 in the cells; ending cells apply theirs.  The wall
+// impulse is the corrector pass's q of each wall face.
 tafv_status subiteration2(tafv_ctx* c, DevMesh& m, const StepArgs& a, int tau_s, int upd,
                           int64_t s, int64_t& faces) {
   const double dt_min = m.dt_min;
@@ -216,7 +216,7 @@ tafv_status subiteration(tafv_ctx* c, DevMesh& m, tafv_stats* acc) {
   }
   StepArgs a = step_args(c, m);
   int tau_s = subiteration_level((int64_t)m.phase + 1, m.theta);
-  if (c->prm.order == 2) {
+  if (c->prm.order == 2 && c->prm.time_order == 1) {
     int cnt = cells_upto_g(m, tau_s);
     ProfScope ps(c, P_GRAD, cnt);
     HIP_TRY(c, launch_grad(c->stream, m, a, cnt));

@@ -38,11 +38,11 @@ struct FluxFeatures {
   float guess_strength = 0.f;
 };
 // U: the cell states read at first order; Q: where gather mode stores the
-// face fluxes (defaults: the mesh's U and Q); impulse_mode and Qpred: the
-// wall impulse of the predictor/corrector form (see FluxArgs)
+// face fluxes (defaults: the mesh's U and Q); pass_mode and Qpred: the
+// passes of the predictor/corrector form (see FluxArgs)
 hipError_t launch_flux(hipStream_t s, DevMesh& m, const StepArgs& a, int first, int count,
                        const FluxFeatures& ft, const double* U = nullptr, void* Q = nullptr,
-                       int impulse_mode = 0, const void* Qpred = nullptr);
+                       int pass_mode = 0, const void* Qpred = nullptr);
 hipError_t launch_cell_gather(hipStream_t s, DevMesh& m, int count, int tau_s, int tau_upd,
                               double dt_min, int precision);
 hipError_t launch_update(hipStream_t s, DevMesh& m, int count, int tau_upd);
@@ -50,7 +50,7 @@ hipError_t launch_update(hipStream_t s, DevMesh& m, int count, int tau_upd);
 // step starts (tau <= tau_s) from the predictor fluxes Q0, and the states Ut
 // of every cell at the end of subiteration `sub`; then the corrector sums
 // of the first `count` listed cells for the faces whose step ends (tau_f <=
-// tau_upd), ending cells applied to U and Ut
+// tau_upd, Q holding phi0 + phi1), ending cells applied to U and Ut
 hipError_t launch_predict(hipStream_t s, DevMesh& m, int tau_s, int sub, double dt_min,
                           int precision);
 hipError_t launch_cell_gather2(hipStream_t s, DevMesh& m, int count, int tau_upd, double dt_min,

@@ -408,13 +408,13 @@ __global__ __launch_bounds__(kBlock) void k_predict(int nc, const uint32_t* __re
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_cell_gather2(
     int count, const int* __restrict__ list, int nc, const uint32_t* __restrict__ fpack,
-    const int* __restrict__ c2f, const T* __restrict__ Q0, const T* __restrict__ Q1,
-    double dt_min, const double* __restrict__ vol, double* __restrict__ U,
+    const int* __restrict__ c2f, const T* __restrict__ Q, double dt_min,
+    const double* __restrict__ vol, double* __restrict__ U,
     double* __restrict__ Ut, double* __restrict__ R, int tau_upd,
     unsigned long long* dscal) {
   int idx = xcd_block() * kBlock + threadIdx.x;
   if (idx >= count) return;
-  if (!cell_gather2_item<T>(list[idx], nc, fpack, c2f, Q0, Q1, dt_min, vol, U, Ut, R, tau_upd))
+  if (!cell_gather2_item<T>(list[idx], nc, fpack, c2f, Q, dt_min, vol, U, Ut, R, tau_upd))
     atomicOr(&dscal[2], 1ull);
 }
 
@@ -606,7 +606,7 @@ static void flux_feat_launch(hipStream_t s, int order, int feat, int count, cons
 }
 
 hipError_t launch_flux(hipStream_t s, DevMesh& m, const StepArgs& a, int first, int count,
-                       const FluxFeatures& ft, const double* U, void* Q, int impulse_mode,
+                       const FluxFeatures& ft, const double* U, void* Q, int pass_mode,
                        const void* Qpred) {
   if (count <= 0) return hipSuccess;
   const int4* rec = m.frec + first;
@@ -616,7 +616,7 @@ hipError_t launch_flux(hipStream_t s, DevMesh& m, const StepArgs& a, int first, 
     FluxArgs<float> f{rec, count, m.nf, m.nc, m.fA32, U, (const float*)m.Wf, m.R, (float*)Q, m.dcount,
                       m.dimpulse, a, ft.mlp, ft.log_rows, ft.log_count, ft.log_cap,
                       ft.log_rate, ft.log_seed, ft.subit, ft.guess_gate, ft.guess_strength,
-                      impulse_mode, (const float*)Qpred};
+                      pass_mode, (const float*)Qpred};
     if (ft.feat && a.gas.is14 && m.scatter == TAFV_SCATTER_GATHER)
       flux_feat_launch<float>(s, a.order, ft.feat, count, f);
     else if (a.gas.is14) flux_launch<float, true>(s, a.order, m.scatter, count, f);
@@ -625,7 +625,7 @@ hipError_t launch_flux(hipStream_t s, DevMesh& m, const StepArgs& a, int first, 
     FluxArgs<double> f{rec, count, m.nf, m.nc, m.fA, U, (const double*)m.Wf, m.R, (double*)Q,
                        m.dcount, m.dimpulse, a, ft.mlp, ft.log_rows, ft.log_count, ft.log_cap,
                        ft.log_rate, ft.log_seed, ft.subit, ft.guess_gate, ft.guess_strength,
-                       impulse_mode, (const double*)Qpred};
+                       pass_mode, (const double*)Qpred};
     if (ft.feat && a.gas.is14 && m.scatter == TAFV_SCATTER_GATHER)
       flux_feat_launch<double>(s, a.order, ft.feat, count, f);
     else if (a.gas.is14) flux_launch<double, true>(s, a.order, m.scatter, count, f);
@@ -667,12 +667,12 @@ hipError_t launch_cell_gather2(hipStream_t s, DevMesh& m, int count, int tau_upd
   if (count <= 0) return hipSuccess;
   if (precision == TAFV_FP32_FLUX)
     hipLaunchKernelGGL(k_cell_gather2<float>, dim3(blocks_for(count)), dim3(kBlock), 0, s,
-                       count, m.pc.list, m.nc, m.fpack, m.c2f, (const float*)m.Q0,
-                       (const float*)m.Q, dt_min, m.vol, m.U, m.Ut, m.R, tau_upd, m.dscal);
+                       count, m.pc.list, m.nc, m.fpack, m.c2f, (const float*)m.Q, dt_min,
+                       m.vol, m.U, m.Ut, m.R, tau_upd, m.dscal);
   else
     hipLaunchKernelGGL(k_cell_gather2<double>, dim3(blocks_for(count)), dim3(kBlock), 0, s,
-                       count, m.pc.list, m.nc, m.fpack, m.c2f, (const double*)m.Q0,
-                       (const double*)m.Q, dt_min, m.vol, m.U, m.Ut, m.R, tau_upd, m.dscal);
+                       count, m.pc.list, m.nc, m.fpack, m.c2f, (const double*)m.Q, dt_min,
+                       m.vol, m.U, m.Ut, m.R, tau_upd, m.dscal);
   return hipGetLastError();
 }
 

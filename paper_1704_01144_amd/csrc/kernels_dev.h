@@ -273,30 +273,34 @@ struct FluxArgs {
   unsigned long long log_seed, subit;
   float guess_gate;
   float guess_strength;  // network only where the jump strength reaches this
-  // wall impulse of gather mode: 0 = dt_f phi (one pass per face step);
-  // predictor/corrector form: 1 = none (predictor pass), 2 = the face step's
-  // q = dt_f (Qpred + phi) / 2 (corrector pass, Qpred the predictor fluxes)
-  int impulse_mode;
+  // gather mode, predictor/corrector form: 0 = one pass per face step (store
+  // phi; wall impulse dt_f phi); 1 = predictor pass (store phi, no impulse);
+  // 2 = corrector pass: store phi0 + phi1 with phi0 from Qpred, the
+  // predictor fluxes; wall impulse q = dt_f (phi0 + phi1) / 2
+  int pass_mode;
   const T* Qpred;
 };
 
-// the wall impulse of one wall face's time-integrated flux, gather mode
+// gather mode: the face's stored flux and the wall impulse of its
+// time-integrated flux (phi is replaced by phi0 + phi1 in a corrector pass)
 template <typename T>
-__device__ inline void add_wall_impulse(const FluxArgs<T>& a, int4 r, double dt_min,
-                                        const T* phi, double& i0, double& i1, double& i2) {
-  if (a.impulse_mode == 1) return;
-  if (a.impulse_mode == 2) {
+__device__ inline void store_face_flux(const FluxArgs<T>& a, int4 r, double dt_min, T* phi,
+                                       bool wall, double& i0, double& i1, double& i2) {
+  double s = 0.0;
+  if (a.pass_mode == 2) {
     const T* p0 = a.Qpred + 5 * (size_t)r.x;
-    const double h = ldexp(dt_min, r.w - 1);
-    i0 += h * ((double)p0[1] + (double)phi[1]);
-    i1 += h * ((double)p0[2] + (double)phi[2]);
-    i2 += h * ((double)p0[3] + (double)phi[3]);
-    return;
+    for (int k = 0; k < 5; ++k) phi[k] = (T)((double)p0[k] + (double)phi[k]);
+    s = ldexp(dt_min, r.w - 1);
+  } else if (a.pass_mode == 0) {
+    s = ldexp(dt_min, r.w);
   }
-  const double dtf = ldexp(dt_min, r.w);
-  i0 += dtf * (double)phi[1];
-  i1 += dtf * (double)phi[2];
-  i2 += dtf * (double)phi[3];
+  T* q = a.Q + 5 * (size_t)r.x;
+  for (int k = 0; k < 5; ++k) q[k] = phi[k];
+  if (wall && a.pass_mode != 1) {
+    i0 += s * (double)phi[1];
+    i1 += s * (double)phi[2];
+    i2 += s * (double)phi[3];
+  }
 }
 
 template <int ORDER, typename T>
@@ -466,9 +470,7 @@ __device__ inline void flux_store_item(const FluxArgs<T>& a, int4 r, double dt_m
   T phi[5];
   face_flux<ORDER, T, G14>(a, r, phi, info);
   add_info(acc, info);
-  T* q = a.Q + 5 * (size_t)r.x;
-  for (int k = 0; k < 5; ++k) q[k] = phi[k];
-  if (r.z < 0 && a.s.boundary == TAFV_BC_WALL) add_wall_impulse(a, r, dt_min, phi, i0, i1, i2);
+  store_face_flux(a, r, dt_min, phi, r.z < 0 && a.s.boundary == TAFV_BC_WALL, i0, i1, i2);
 }
 
 // splitmix64 output function (Steele, Lea, Flood 2014): a counter-based
@@ -637,9 +639,7 @@ __device__ inline void flux_feat_item(const FluxArgs<T>& a, bool valid, int4 r, 
         phi[4] = am * us * (E + ps);
       }
     }
-    T* q = a.Q + 5 * (size_t)r.x;
-    for (int k = 0; k < 5; ++k) q[k] = phi[k];
-    if (wall) add_wall_impulse(a, r, dt_min, phi, i0, i1, i2);
+    store_face_flux(a, r, dt_min, phi, wall, i0, i1, i2);
   }
   add_info(acc, info);
 }
@@ -742,13 +742,13 @@ __device__ inline void predict_item(int i, int nc, const uint32_t* __restrict__ 
 }
 
 // Corrector gather, per cell with a face whose step ends now (tau_f <= upd):
-// add those faces' q = 2^tau_f dt_min (phi0 + phi1) / 2 in local face order;
+// add those faces' q = 2^tau_f dt_min (phi0 + phi1) / 2 in local face order
+// (the corrector pass stored phi0 + phi1);
 // a cell whose own step ends applies its sum, U += R / V, and its state for
 // the next predictor is the new U.  Returns false on a non-finite state.
 template <typename T>
 __device__ inline bool cell_gather2_item(int i, int nc, const uint32_t* __restrict__ fpack,
-                                         const int* __restrict__ c2f,
-                                         const T* __restrict__ Q0, const T* __restrict__ Q1,
+                                         const int* __restrict__ c2f, const T* __restrict__ Q,
                                          double dt_min, const double* __restrict__ vol,
                                          double* __restrict__ U, double* __restrict__ Ut,
                                          double* __restrict__ R, int tau_upd) {
@@ -765,14 +765,12 @@ __device__ inline bool cell_gather2_item(int i, int nc, const uint32_t* __restri
       for (int k = 0; k < 5; ++k) acc[k] = Ri[k];
       touched = true;
     }
-    const size_t f = (size_t)c2f[m * nc + i];
-    const T* q0 = Q0 + 5 * f;
-    const T* q1 = Q1 + 5 * f;
+    const T* q = Q + 5 * (size_t)c2f[m * nc + i];
     const double h = ldexp(dt_min, tf - 1);
     if (pk & (1u << (16 + m))) {
-      for (int k = 0; k < 5; ++k) acc[k] += h * ((double)q0[k] + (double)q1[k]);
+      for (int k = 0; k < 5; ++k) acc[k] += h * (double)q[k];
     } else {
-      for (int k = 0; k < 5; ++k) acc[k] -= h * ((double)q0[k] + (double)q1[k]);
+      for (int k = 0; k < 5; ++k) acc[k] -= h * (double)q[k];
     }
   }
   if (ends) {
