@@ -121,7 +121,8 @@ typedef struct {
                             all meshes, with no host synchronisation (see
                             tafv_batch_config()).  Meshes must all be uploaded
                             before the first tafv_state_init(); checkpoints
-                            and face logging are not available.              */
+                            are read only (tafv_checkpoint_write() is not
+                            available) and face logging is not available.  */
   double guess_strength; /* learned guess: the network is evaluated only on
                             faces whose jump strength |u_R - u_L|/a_m +
                             |p_L - p_R|/p_m is at least this (>= 0; 0: every
@@ -237,7 +238,15 @@ tafv_status tafv_advance(tafv_ctx* ctx, int64_t n_dt_min, tafv_stats* out);
 tafv_status tafv_mesh_stats(tafv_ctx* ctx, int32_t mesh_id, tafv_stats* out);
 
 /* Copy the conserved state to host cons [n_tets][5] = (rho, rho u, rho v,
- * rho w, E) and, if levels is not NULL, the levels to host [n_tets]. */
+ * rho w, E) and, if levels is not NULL, the levels to host [n_tets].
+ * Mid-iteration (phase != 0) a cell shows the state at the start of its
+ * current level step, except that with TAFV_SCATTER_GATHER and time_order 1
+ * a cell whose faces are all on its own level -- and, at second order,
+ * none of whose neighbours has a face on a faster level -- shows the state
+ * at the end of its current step: all fluxes of its step are known at the
+ * step's start and nothing reads its state before the step ends, so it
+ * applies them then.  The accumulator of such a cell is 0.  cons + accum /
+ * V is the state at the end of each cell's current step in every case. */
 tafv_status tafv_state_read(tafv_ctx* ctx, int32_t mesh_id, double* cons,
                             int8_t* levels);
 

@@ -244,6 +244,22 @@ __global__ __launch_bounds__(kBlock) void k_b_cell_keys(const int32_t* __restric
   }
 }
 
+// cells that apply their fluxes at their step's start (kEarlyBit)
+__global__ __launch_bounds__(kBlock) void k_b_cell_early(const int32_t* __restrict__ rp,
+                                                         BatchSched* S, int M, int NC,
+                                                         const int* __restrict__ nb,
+                                                         const int8_t* __restrict__ lev,
+                                                         const int8_t* __restrict__ ckey,
+                                                         uint32_t* __restrict__ fpack, int order) {
+  STAGE_PREFIX(rp);
+  const int total = s_pre[M];
+  TILE_LOOP(total, 1) {
+    int m = find_mesh(s_pre, M, t);
+    int i = S[m].c0 + (t - s_pre[m]) * kBlock + threadIdx.x;
+    if (i < S[m].c0 + S[m].nc) cell_early_item(i, NC, nb, lev, ckey, fpack, order);
+  }
+}
+
 __global__ __launch_bounds__(kBlock) void k_b_face_keys(const int32_t* __restrict__ rp,
                                                         const BatchSched* S, int M,
                                                         const int* __restrict__ fhL,
@@ -833,6 +849,8 @@ hipError_t run_reclass(tafv_ctx* c, hipStream_t s) {
   }
   hipLaunchKernelGGL(k_b_cell_keys, dim3(G), dim3(kBlock), lds, s, rc, B.dsched, M, m.nc, m.nb_,
                      m.lev, m.ckey, m.fpack, B.thist);
+  hipLaunchKernelGGL(k_b_cell_early, dim3(G), dim3(kBlock), lds, s, rc, B.dsched, M, m.nc, m.nb_,
+                     m.lev, m.ckey, m.fpack, c->prm.order);
   hipLaunchKernelGGL(k_b_reduce, dim3(M), dim3(256), 0, s, rc, B.dsched, M, nullptr, B.thist);
   hipLaunchKernelGGL(k_b_face_keys, dim3(G), dim3(kBlock), lds, s, rf, B.dsched, M, m.fhL, m.fhR,
                      m.lev, m.fkey);
@@ -1475,6 +1493,27 @@ tafv_status batch_state_read(tafv_ctx* c, int32_t id, double* cons, int8_t* leve
     B_TRY(c, hipMemcpyAsync(levels, stage, s.nc, hipMemcpyDeviceToHost, c->stream));
     B_TRY(c, hipStreamSynchronize(c->stream));
   }
+  return TAFV_OK;
+}
+
+tafv_status batch_checkpoint_read(tafv_ctx* c, int32_t id, double* cons, double* accum,
+                                  int8_t* levels, int32_t* phase, int32_t* theta,
+                                  double* dt_min, double* t) {
+  if (!accum || !levels || !phase || !theta || !dt_min || !t)
+    return set_error(c, TAFV_E_ARG, "NULL argument");
+  tafv_status st = batch_state_read(c, id, cons, levels);
+  if (st != TAFV_OK) return st;
+  Batch& B = *c->batch;
+  const BatchSched& s = B.hsched[id];
+  DevMesh& m = *B.m;
+  double* xf = m.xfer + 5 * (size_t)s.c0;
+  B_TRY(c, launch_rows_to_caller_f64(c->stream, s.nc, m.perm + s.c0, m.R + 5 * (size_t)s.c0, xf));
+  B_TRY(c, hipMemcpyAsync(accum, xf, sizeof(double) * 5 * s.nc, hipMemcpyDeviceToHost, c->stream));
+  B_TRY(c, hipStreamSynchronize(c->stream));
+  *phase = s.phase;
+  *theta = s.theta;
+  *dt_min = s.dt_min;
+  *t = s.t;
   return TAFV_OK;
 }
 

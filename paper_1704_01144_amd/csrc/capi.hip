@@ -107,6 +107,12 @@ hipError_t sync_time_states(tafv_ctx* c, DevMesh& m) {
   return e;
 }
 
+// cells applying their fluxes at their step's start: gather mode with one
+// face pass per step (the spatial order decides which neighbours matter)
+int early_order(const tafv_ctx* c, const DevMesh& m) {
+  return (m.scatter == TAFV_SCATTER_GATHER && c->prm.time_order == 1) ? c->prm.order : 0;
+}
+
 tafv_status classify(tafv_ctx* c, DevMesh& m) {
   StepArgs a = step_args(c, m);
   {
@@ -114,7 +120,7 @@ tafv_status classify(tafv_ctx* c, DevMesh& m) {
     HIP_TRY(c, launch_fill_u64(c->stream, m.dscal, 0x7ff0000000000000ull, 1));  // +inf
     HIP_TRY(c, launch_dt(c->stream, m, a));
     HIP_TRY(c, launch_classify(c->stream, m, a));
-    HIP_TRY(c, launch_partitions(c->stream, m));
+    HIP_TRY(c, launch_partitions(c->stream, m, early_order(c, m)));
   }
   // read back: dt_min, flag, list starts
   int K = m.scatter == TAFV_SCATTER_COLOUR ? m.ncolours * kMaxLevels : kMaxLevels;
@@ -738,7 +744,8 @@ tafv_status tafv_state_read(tafv_ctx* c, int32_t mesh_id, double* cons, int8_t* 
 tafv_status tafv_checkpoint_read(tafv_ctx* c, int32_t mesh_id, double* cons, double* accum,
                                  int8_t* levels, int32_t* phase, int32_t* theta, double* dt_min,
                                  double* t) {
-  if (c && c->batch) return fail(c, TAFV_E_ARG, "checkpoints are not available in the batched form");
+  if (c && c->batch)
+    return batch_checkpoint_read(c, mesh_id, cons, accum, levels, phase, theta, dt_min, t);
   DevMesh* m = get_mesh(c, mesh_id);
   if (!m) return c ? fail(c, TAFV_E_ARG, "unknown mesh") : TAFV_E_ARG;
   if (!cons || !accum || !levels || !phase || !theta || !dt_min || !t)
@@ -790,7 +797,7 @@ tafv_status tafv_checkpoint_write(tafv_ctx* c, int32_t mesh_id, const double* co
   HIP_TRY(c, hipStreamSynchronize(c->stream));
   HIP_TRY(c, hipMemcpyAsync(m->xfer, levels, m->nc, hipMemcpyHostToDevice, c->stream));
   HIP_TRY(c, launch_from_caller_i8(c->stream, *m, (const int8_t*)m->xfer, m->lev));
-  HIP_TRY(c, launch_partitions(c->stream, *m));
+  HIP_TRY(c, launch_partitions(c->stream, *m, early_order(c, *m)));
   int K = m->scatter == TAFV_SCATTER_COLOUR ? m->ncolours * kMaxLevels : kMaxLevels;
   HIP_TRY(c, hipMemcpyAsync(m->hstart_f, m->pf.start, (K + 1) * sizeof(int32_t),
                             hipMemcpyDeviceToHost, c->stream));

@@ -20,7 +20,10 @@ hipError_t launch_state_init_rows(hipStream_t s, int n, const int* perm, const d
                                   double gamma, double* U, double* R);
 hipError_t launch_dt(hipStream_t s, DevMesh& m, const StepArgs& a);
 hipError_t launch_classify(hipStream_t s, DevMesh& m, const StepArgs& a);
-hipError_t launch_partitions(hipStream_t s, DevMesh& m);
+// early_order: 1 or 2 marks the cells that apply their fluxes at their
+// step's start (gather mode, one pass per face step) for that spatial order;
+// 0 marks none
+hipError_t launch_partitions(hipStream_t s, DevMesh& m, int early_order);
 // U: the cell states the pass reads (default: the mesh's U)
 hipError_t launch_grad(hipStream_t s, DevMesh& m, const StepArgs& a, int count,
                        const double* U = nullptr);

@@ -131,6 +131,16 @@ __global__ void k_face_keys(int nf, const int* __restrict__ fhL, const int* __re
 
 // cell keys, packed face words, and the histogram hist[tau_g * 8 + tau]
 // (block-local in LDS, then one atomic per bin and block)
+// cells that apply their fluxes at their step's start (kEarlyBit); order
+// 0 marks none
+__global__ __launch_bounds__(kBlock) void k_cell_early(int nc, const int* __restrict__ nb,
+                                                       const int8_t* __restrict__ lev,
+                                                       const int8_t* __restrict__ ckey,
+                                                       uint32_t* __restrict__ fpack, int order) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < nc) cell_early_item(i, nc, nb, lev, ckey, fpack, order);
+}
+
 __global__ __launch_bounds__(kBlock) void k_cell_keys(int nc, const int* __restrict__ nb,
                                                       const int8_t* __restrict__ lev,
                                                       int8_t* __restrict__ ckey,
@@ -508,7 +518,7 @@ hipError_t launch_classify(hipStream_t s, DevMesh& m, const StepArgs& a) {
   return hipGetLastError();
 }
 
-hipError_t launch_partitions(hipStream_t s, DevMesh& m) {
+hipError_t launch_partitions(hipStream_t s, DevMesh& m, int early_order) {
   int use_colour = m.scatter == TAFV_SCATTER_COLOUR;
   int Kf = use_colour ? m.ncolours * kMaxLevels : kMaxLevels;
   hipLaunchKernelGGL(k_face_keys, dim3(blocks_for(m.nf)), dim3(kBlock), 0, s, m.nf, m.fhL, m.fhR,
@@ -517,6 +527,9 @@ hipError_t launch_partitions(hipStream_t s, DevMesh& m) {
                      kCountSlots * kMaxKeys);
   hipLaunchKernelGGL(k_cell_keys, dim3(blocks_for(m.nc)), dim3(kBlock), 0, s, m.nc, m.nb_, m.lev,
                      m.ckey, m.fpack, m.chist);
+  if (early_order)
+    hipLaunchKernelGGL(k_cell_early, dim3(blocks_for(m.nc)), dim3(kBlock), 0, s, m.nc, m.nb_,
+                       m.lev, m.ckey, m.fpack, early_order);
   hipError_t e = run_partition(s, m.nf, ByteKey{m.fkey}, Kf, m.pf, FaceWriter{m.frec, m.fhL, m.fhR});
   if (e != hipSuccess) return e;
   return run_partition(s, m.nc, ByteKey{m.ckey}, kMaxLevels, m.pc, IndexWriter{m.pc.list});

@@ -127,6 +127,30 @@ __device__ inline int cell_key_item(int i, int nc, const int* __restrict__ nb,
   return tg * kMaxLevels + ti;
 }
 
+// Bit of the packed face word marking a cell that applies its fluxes at its
+// step's start: all its faces are on its own level (tau_g = tau), so all the
+// fluxes of one of its steps are computed at that step's start, and nothing
+// reads its state before the step ends -- no face of it is computed mid-step
+// and, at second order, no neighbour has a face on a faster level (which
+// would compute the neighbour's gradient from this cell's state mid-step).
+// Applying them at the start gives the same bits as accumulating them and
+// applying the sum at the end.
+constexpr uint32_t kEarlyBit = 1u << 24;
+
+__device__ inline void cell_early_item(int i, int nc, const int* __restrict__ nb,
+                                       const int8_t* __restrict__ lev,
+                                       const int8_t* __restrict__ ckey,
+                                       uint32_t* __restrict__ fpack, int order) {
+  const int t = lev[i];
+  bool e = ckey[i] == t;
+  if (e && order == 2)
+    for (int m = 0; m < 4; ++m) {
+      const int n = nb[m * nc + i];
+      if (n >= 0 && ckey[n] < t) e = false;
+    }
+  if (e) fpack[i] |= kEarlyBit;
+}
+
 // h[bin] += 1 for every active lane, one LDS atomic per distinct bin of the
 // wave (lanes with equal bins are counted by a ballot): the bins of a
 // histogram by level are few, and per-lane atomics on them serialise
@@ -647,8 +671,9 @@ __device__ inline void flux_feat_item(const FluxArgs<T>& a, bool valid, int4 r, 
 // Gather mode, per cell with an active face or whose step ends: add the
 // active faces' time-integrated fluxes q = 2^tau_f dt_min Phi in local face
 // order (-q where the cell is the lower id of the face, +q otherwise), then
-// U += R / V, R = 0 for ending steps.  Returns false on a non-finite
-// updated state.
+// U += R / V, R = 0 for ending steps.  A cell with kEarlyBit applies the
+// sum of its faces at its step's start instead (its accumulator stays 0).
+// Returns false on a non-finite updated state.
 template <typename T>
 __device__ inline bool cell_gather_item(int i, int nc, const uint32_t* __restrict__ fpack,
                                         const int* __restrict__ c2f,
@@ -657,9 +682,29 @@ __device__ inline bool cell_gather_item(int i, int nc, const uint32_t* __restric
                                         double* __restrict__ R, int tau_s, int tau_upd) {
   uint32_t pk = fpack[i];
   int ti = (pk >> 20) & 15;
+  double acc[5] = {0, 0, 0, 0, 0};
+  if (pk & kEarlyBit) {
+    if (ti > tau_s) return true;  // applied at the step's start
+    const double dtf = ldexp(dt_min, ti);
+    for (int m = 0; m < 4; ++m) {
+      const T* q = Q + 5 * (size_t)c2f[m * nc + i];
+      if (pk & (1u << (16 + m))) {
+        for (int k = 0; k < 5; ++k) acc[k] += dtf * (double)q[k];
+      } else {
+        for (int k = 0; k < 5; ++k) acc[k] -= dtf * (double)q[k];
+      }
+    }
+    const double v = vol[i];
+    bool bad = false;
+    for (int k = 0; k < 5; ++k) {
+      const double u = U[5 * (size_t)i + k] + acc[k] / v;
+      U[5 * (size_t)i + k] = u;
+      bad |= !isfinite(u);
+    }
+    return !bad;
+  }
   bool ends = ti <= tau_upd;
   bool touched = false;
-  double acc[5] = {0, 0, 0, 0, 0};
   double* Ri = R + 5 * (size_t)i;
   for (int m = 0; m < 4; ++m) {
     const int tf = (int)((pk >> (4 * m)) & 15);

@@ -264,6 +264,9 @@ tafv_status batch_state_reset(tafv_ctx* c, int32_t mesh_id);
 tafv_status batch_advance(tafv_ctx* c, int64_t n, tafv_stats* out);
 tafv_status batch_mesh_stats(tafv_ctx* c, int32_t mesh_id, tafv_stats* out);
 tafv_status batch_state_read(tafv_ctx* c, int32_t mesh_id, double* cons, int8_t* levels);
+tafv_status batch_checkpoint_read(tafv_ctx* c, int32_t mesh_id, double* cons, double* accum,
+                                  int8_t* levels, int32_t* phase, int32_t* theta,
+                                  double* dt_min, double* t);
 tafv_status batch_config(tafv_ctx* c, int32_t graph, int32_t autotune, const char* cache);
 tafv_status batch_info(tafv_ctx* c, int32_t* info, int32_t n);
 void batch_invalidate(tafv_ctx* c);
