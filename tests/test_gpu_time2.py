@@ -251,3 +251,29 @@ def test_full_scale_whole_run(T, full_oracle2):
     assert (lev == full_oracle2["levels"]).all()
     assert st["cell_updates"] == full_oracle2["stats"]["cell_updates"]
     assert st["face_solves"] == full_oracle2["stats"]["face_solves"]
+
+
+def test_learned_start_same_result(T):
+    """The learned start changes only where the Newton iteration begins; the
+    predictor/corrector result equals the two-rarefaction start's."""
+    from oracle import mlp_ref as M
+    nodes, tets = I.graded_cube_mesh(16, 16.0)
+    prim = I.blast_state(nodes, tets, centre=I.blast_centre(4))
+    th = (M.he_uniform(7) + np.random.default_rng(8).normal(0, 0.05, M.N_PARAMS)).astype(np.float32)
+    out = []
+    for guess in (T.GUESS_TR, T.GUESS_MLP):
+        s = T.Solver(max_levels=5, order=2, time_order=2, guess=guess, guess_stats=1)
+        s.upload(nodes, tets)
+        if guess == T.GUESS_MLP:
+            T.tafv_mlp_set(s.ctx, th)
+        s.init(prim)
+        st = s.advance(16)
+        out.append((s.checkpoint(), st))
+        s.close()
+    (a, sa), (b, sb) = out
+    err = normwise(b["cons"], a["cons"])
+    say(f"time order 2, learned start: err {err:.2e}, network start on {sb['guess_used']} of "
+        f"{sb['guess_faces']} faces")
+    assert err <= TOL and (a["levels"] == b["levels"]).all()
+    assert sb["guess_used"] > 0 and sb["newton_fallbacks"] == 0
+    assert sa["face_solves"] == sb["face_solves"]
