@@ -82,6 +82,10 @@ def lib():
         L.orc_face_flux.argtypes = [C.c_double, dp, dp, dp, C.c_int32, C.c_double,
                                     C.c_int32, C.c_int32, C.c_double, dp,
                                     C.POINTER(RiemannOut)]
+        L.orc_face_flux_moving.argtypes = [C.c_double, dp, dp, dp, C.c_double, C.c_int32,
+                                           C.c_double, C.c_int32, dp, C.POINTER(RiemannOut)]
+        L.orc_state_motion.argtypes = [P, dp]
+        L.orc_state_volumes.argtypes = [P, dp]
         L.orc_gradients.argtypes = [P, C.POINTER(Params), dp, dp, dp]
         L.orc_classify.argtypes = [P, C.POINTER(Params), dp, dp, i8p, dp,
                                    C.POINTER(C.c_int32)]
@@ -182,6 +186,17 @@ def face_flux(wl, wr, area, kind=KIND_INTERIOR, gamma=1.4, tol=1e-12, max_iter=5
     return flux, out
 
 
+def face_flux_moving(wl, wr, area, xi, kind=KIND_INTERIOR, gamma=1.4, tol=1e-12, max_iter=50):
+    wl = np.ascontiguousarray(wl, dtype=np.float64)
+    wr = np.ascontiguousarray(wr if wr is not None else wl, dtype=np.float64)
+    area = np.ascontiguousarray(area, dtype=np.float64)
+    flux = np.empty(5)
+    out = RiemannOut()
+    _check(lib().orc_face_flux_moving(gamma, _d(wl), _d(wr), _d(area), float(xi), kind, tol,
+                                      max_iter, _d(flux), C.byref(out)), "orc_face_flux_moving")
+    return flux, out
+
+
 def gradients(mesh, prim, prm=None):
     prm = prm or params(order=2)
     prim = np.ascontiguousarray(prim, dtype=np.float64)
@@ -238,6 +253,17 @@ class State:
         lev = np.empty(n, np.int8)
         _check(lib().orc_state_read(self._h, _d(cons), _d(accum), _i8(lev)), "orc_state_read")
         return cons, accum, lev
+
+    def motion(self, node_vel):
+        """Node velocities [n_nodes][3] of a moving mesh (ALE, geometric
+        conservation law)."""
+        v = np.ascontiguousarray(node_vel, dtype=np.float64)
+        _check(lib().orc_state_motion(self._h, _d(v)), "orc_state_motion")
+
+    def volumes(self):
+        vol = np.empty(self.mesh.n_cells)
+        _check(lib().orc_state_volumes(self._h, _d(vol)), "orc_state_volumes")
+        return vol
 
     def stats(self):
         st = Stats()

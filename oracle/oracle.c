@@ -40,6 +40,8 @@ struct orc_mesh {
   double* af;      /* [nf][3]     area vector, pointing out of fL       */
   double* xf;      /* [nf][3]     face centroid                         */
   int64_t* c2f;    /* [nc][4]     face opposite local vertex m          */
+  int64_t nn;      /* node count                                        */
+  int64_t* fn;     /* [nf][3]     sorted node ids of the face           */
 };
 
 typedef struct {
@@ -80,7 +82,7 @@ static void cross3(const double* a, const double* b, double* c) {
 void orc_mesh_free(orc_mesh* m) {
   if (!m) return;
   free(m->vol); free(m->xc); free(m->fL); free(m->fR);
-  free(m->af); free(m->xf); free(m->c2f);
+  free(m->af); free(m->xf); free(m->c2f); free(m->fn);
   free(m);
 }
 
@@ -141,11 +143,15 @@ int orc_mesh_build(int64_t n_nodes, const double* xyz, int64_t n_tets,
   }
   m->nf = nf;
   m->nb = nb;
+  m->nn = n_nodes;
   m->fL = (int64_t*)malloc(sizeof(int64_t) * nf);
   m->fR = (int64_t*)malloc(sizeof(int64_t) * nf);
   m->af = (double*)malloc(sizeof(double) * 3 * nf);
   m->xf = (double*)malloc(sizeof(double) * 3 * nf);
-  if (!m->fL || !m->fR || !m->af || !m->xf) { free(rec); orc_mesh_free(m); return ORC_E_ARG; }
+  m->fn = (int64_t*)malloc(sizeof(int64_t) * 3 * nf);
+  if (!m->fL || !m->fR || !m->af || !m->xf || !m->fn) {
+    free(rec); orc_mesh_free(m); return ORC_E_ARG;
+  }
   int64_t f = 0;
   for (int64_t i = 0; i < 4 * n_tets;) {
     int64_t j = i + 1;
@@ -156,6 +162,7 @@ int orc_mesh_build(int64_t n_nodes, const double* xyz, int64_t n_tets,
     m->fR[f] = (j - i == 2) ? rec[i + 1].cell : -1;
     m->c2f[4 * rec[i].cell + rec[i].local] = f;
     if (j - i == 2) m->c2f[4 * rec[i + 1].cell + rec[i + 1].local] = f;
+    for (int k = 0; k < 3; ++k) m->fn[3 * f + k] = rec[i].v[k];
     const double* a = xyz + 3 * rec[i].v[0];
     const double* b = xyz + 3 * rec[i].v[1];
     const double* c = xyz + 3 * rec[i].v[2];
@@ -461,6 +468,58 @@ int orc_face_flux(double g, const double* wl, const double* wr, const double* ar
   return ORC_OK;
 }
 
+/* ALE form of the face flux (Sec. 2.1: the face's own velocity enters the
+ * flux of a moving mesh): the face moves with normal speed xi along the
+ * unit normal n = A/|A|; the Riemann problem of the normal frame is sampled
+ * on the face's path, x/t = xi, and the flux through the moving face is
+ * |A| (F(W(xi)) . n - xi U(W(xi))).  A wall moves with the face: its mirror
+ * state has normal velocity 2 xi - u_nL, so the contact follows the wall,
+ * no mass crosses it, the star pressure pushes (p* n |A|) and does the
+ * work p* xi |A|.  A transmissive face takes W = W_L.  xi = 0 gives the
+ * fluxes of orc_face_flux up to rounding. */
+int orc_face_flux_moving(double g, const double* wl, const double* wr, const double* area,
+                         double xi, int32_t kind, double tol, int32_t max_iter,
+                         double* flux, orc_riemann_out* out) {
+  orc_riemann_out dummy;
+  if (!out) out = &dummy;
+  memset(out, 0, sizeof(*out));
+  double amag = sqrt(dot3(area, area));
+  if (!(amag > 0.0)) return ORC_E_ARG;
+  double n[3] = {area[0] / amag, area[1] / amag, area[2] / amag};
+  double w[5];
+  if (kind == 2) {
+    for (int k = 0; k < 5; ++k) w[k] = wl[k];
+  } else {
+    double unl = wl[1] * n[0] + wl[2] * n[1] + wl[3] * n[2];
+    double nl[3] = {wl[0], unl, wl[4]};
+    if (kind == 1) {
+      double nr[3] = {wl[0], 2.0 * xi - unl, wl[4]};
+      int rc = orc_riemann_solve(g, nl, nr, tol, max_iter, ORC_GUESS_TR, 0.0, out);
+      if (rc) return rc;
+      flux[0] = 0.0;
+      for (int k = 0; k < 3; ++k) flux[1 + k] = amag * out->p_star * n[k];
+      flux[4] = amag * out->p_star * xi;
+      return ORC_OK;
+    }
+    double unr = wr[1] * n[0] + wr[2] * n[1] + wr[3] * n[2];
+    double nr[3] = {wr[0], unr, wr[4]};
+    int rc = orc_riemann_solve(g, nl, nr, tol, max_iter, ORC_GUESS_TR, 0.0, out);
+    if (rc) return rc;
+    double ws[3];
+    int side = orc_riemann_sample(g, nl, nr, out, xi, ws);
+    const double* src = side == 0 ? wl : wr;
+    double un_src = side == 0 ? unl : unr;
+    w[0] = ws[0];
+    for (int k = 0; k < 3; ++k) w[1 + k] = ws[1] * n[k] + (src[1 + k] - un_src * n[k]);
+    w[4] = ws[2];
+  }
+  double F[5], U[5];
+  euler_flux(g, w, n, F);
+  prim_to_cons(g, w, U);
+  for (int k = 0; k < 5; ++k) flux[k] = amag * (F[k] - xi * U[k]);
+  return ORC_OK;
+}
+
 /* ====================================================================== */
 /* Least-squares gradients and Barth-Jespersen limiter                     */
 /* ====================================================================== */
@@ -469,8 +528,10 @@ int orc_face_flux(double g, const double* wl, const double* wr, const double* ar
  * state.  A boundary face gives the mirror ghost: the cell centroid
  * reflected in the face plane, with the normal velocity reversed on a wall
  * and the state copied on a transmissive boundary. */
-static void neighbour(const orc_mesh* m, int32_t bc, const double* prim, int64_t i,
-                      int mloc, double* pos, double* w) {
+/* On a moving mesh (sF not NULL) a wall moves with its face: the ghost's
+ * normal velocity is 2 xi - u_n, xi = sF / |A| the face's normal speed. */
+static void neighbour(const orc_mesh* m, int32_t bc, const double* sF, const double* prim,
+                      int64_t i, int mloc, double* pos, double* w) {
   int64_t f = m->c2f[4 * i + mloc];
   if (m->fR[f] >= 0) {
     int64_t j = (m->fL[f] == i) ? m->fR[f] : m->fL[f];
@@ -489,6 +550,7 @@ static void neighbour(const orc_mesh* m, int32_t bc, const double* prim, int64_t
   for (int k = 0; k < 5; ++k) w[k] = wi[k];
   if (bc == ORC_BC_WALL) {
     double un = wi[1] * n[0] + wi[2] * n[1] + wi[3] * n[2];
+    if (sF) un -= sF[f] / amag;
     for (int k = 0; k < 3; ++k) w[1 + k] = wi[1 + k] - 2.0 * un * n[k];
   }
 }
@@ -506,9 +568,8 @@ static int invert_sym3(const double* M, double* Minv) {
   return ORC_OK;
 }
 
-int orc_gradients(const orc_mesh* m, const orc_params* prm, const double* prim,
-                  double* grad_raw, double* grad_lim) {
-  if (!m || !prm || !prim) return ORC_E_ARG;
+static int gradients_core(const orc_mesh* m, const orc_params* prm, const double* sF,
+                          const double* prim, double* grad_raw, double* grad_lim) {
   for (int64_t i = 0; i < m->nc; ++i) {
     const double* xi = m->xc + 3 * i;
     const double* wi = prim + 5 * i;
@@ -516,7 +577,7 @@ int orc_gradients(const orc_mesh* m, const orc_params* prm, const double* prim,
     double M[9] = {0}, b[3][5];
     memset(b, 0, sizeof(b));
     for (int j = 0; j < 4; ++j) {
-      neighbour(m, prm->boundary, prim, i, j, pos[j], wn[j]);
+      neighbour(m, prm->boundary, sF, prim, i, j, pos[j], wn[j]);
       double d[3] = {pos[j][0] - xi[0], pos[j][1] - xi[1], pos[j][2] - xi[2]};
       double wgt = 1.0 / dot3(d, d);
       for (int r = 0; r < 3; ++r)
@@ -557,14 +618,23 @@ int orc_gradients(const orc_mesh* m, const orc_params* prm, const double* prim,
   return ORC_OK;
 }
 
+int orc_gradients(const orc_mesh* m, const orc_params* prm, const double* prim,
+                  double* grad_raw, double* grad_lim) {
+  if (!m || !prm || !prim) return ORC_E_ARG;
+  return gradients_core(m, prm, NULL, prim, grad_raw, grad_lim);
+}
+
 /* ====================================================================== */
 /* Time step and levels (Sec. 2.2, Alg. 2: time step computation,          */
 /* classification; neighbour levels differ by at most one)                 */
 /* ====================================================================== */
 
-int orc_classify(const orc_mesh* m, const orc_params* prm, const double* cons,
-                 double* dt, int8_t* levels, double* dt_min_out, int32_t* theta_out) {
-  if (!m || !prm || !cons || !dt || !levels) return ORC_E_ARG;
+/* vol: the cell volumes; sF (NULL on a fixed mesh): per face the rate
+ * w_f . A_f of the volume it sweeps, so that its normal speed is
+ * sF / |A| and the wave speeds are taken relative to it */
+static int classify_core(const orc_mesh* m, const orc_params* prm, const double* cons,
+                         const double* vol, const double* sF, double* dt, int8_t* levels,
+                         double* dt_min_out, int32_t* theta_out) {
   double g = prm->gamma;
   double dtmin = INFINITY;
   for (int64_t i = 0; i < m->nc; ++i) {
@@ -577,9 +647,10 @@ int orc_classify(const orc_mesh* m, const orc_params* prm, const double* cons,
       const double* A = m->af + 3 * m->c2f[4 * i + j];
       double amag = sqrt(dot3(A, A));
       double un = (w[1] * A[0] + w[2] * A[1] + w[3] * A[2]) / amag;
+      if (sF) un -= sF[m->c2f[4 * i + j]] / amag;
       s += (fabs(un) + a) * amag;
     }
-    dt[i] = prm->cfl * m->vol[i] / s;
+    dt[i] = prm->cfl * vol[i] / s;
     if (dt[i] < dtmin) dtmin = dt[i];
   }
   int L = prm->max_levels;
@@ -616,6 +687,12 @@ int orc_classify(const orc_mesh* m, const orc_params* prm, const double* cons,
   return ORC_OK;
 }
 
+int orc_classify(const orc_mesh* m, const orc_params* prm, const double* cons,
+                 double* dt, int8_t* levels, double* dt_min_out, int32_t* theta_out) {
+  if (!m || !prm || !cons || !dt || !levels) return ORC_E_ARG;
+  return classify_core(m, prm, cons, m->vol, NULL, dt, levels, dt_min_out, theta_out);
+}
+
 /* ====================================================================== */
 /* Solver state and the subiteration loop (Alg. 2)                         */
 /* ====================================================================== */
@@ -636,6 +713,12 @@ struct orc_state {
   double* Ut;     /* [nc][5] scratch: states at one time inside the steps */
   double* phi0;   /* [nf][5] predictor flux of the face's current step   */
   double* phi1;   /* [nf][5] scratch: corrector flux                     */
+  /* moving mesh only (orc_state_motion) */
+  int32_t moving;
+  double* V;      /* [nc] cell volumes                                   */
+  double* RV;     /* [nc] swept volume accumulated since the cell moved   */
+  double* sF;     /* [nf] volume rate w_f . A_f of each face              */
+  double* qv;     /* [nf] scratch: -dt_f sF of the computed faces         */
   int32_t phase, theta, classified;
   double dt_min, t;
   orc_stats st;
@@ -646,6 +729,7 @@ void orc_state_free(orc_state* s) {
   free(s->U); free(s->R); free(s->lev); free(s->dt); free(s->prim);
   free(s->glim); free(s->q); free(s->act);
   free(s->D); free(s->Ut); free(s->phi0); free(s->phi1);
+  free(s->V); free(s->RV); free(s->sF); free(s->qv);
   free(s);
 }
 
@@ -699,6 +783,7 @@ int orc_state_set(orc_state* s, const double* cons, const double* accum,
   if (theta < 0 || theta >= s->prm.max_levels || phase < 0 || phase >= (1 << theta))
     return ORC_E_ARG;
   if (s->prm.time_order == 2 && phase != 0) return ORC_E_ARG;
+  if (s->moving) return ORC_E_ARG;
   memcpy(s->U, cons, sizeof(double) * 5 * s->m->nc);
   memcpy(s->R, accum, sizeof(double) * 5 * s->m->nc);
   memcpy(s->lev, levels, (size_t)s->m->nc);
@@ -720,7 +805,9 @@ int32_t orc_subiteration_level(int64_t s, int32_t theta) {
 }
 
 static int classify_state(orc_state* s) {
-  int rc = orc_classify(s->m, &s->prm, s->U, s->dt, s->lev, &s->dt_min, &s->theta);
+  int rc = s->moving ? classify_core(s->m, &s->prm, s->U, s->V, s->sF, s->dt, s->lev,
+                                     &s->dt_min, &s->theta)
+                     : orc_classify(s->m, &s->prm, s->U, s->dt, s->lev, &s->dt_min, &s->theta);
   if (rc) return rc;
   for (int k = 0; k < 8; ++k) s->st.cells_per_level[k] = 0;
   for (int64_t i = 0; i < s->m->nc; ++i) s->st.cells_per_level[s->lev[i]]++;
@@ -741,7 +828,7 @@ static int face_fluxes(orc_state* s, const double* cons, int tau_max, double* ph
   double g = prm->gamma;
   for (int64_t i = 0; i < m->nc; ++i) cons_to_prim(g, cons + 5 * i, s->prim + 5 * i);
   if (prm->order == 2) {
-    int rc = orc_gradients(m, prm, s->prim, NULL, s->glim);
+    int rc = gradients_core(m, prm, s->moving ? s->sF : NULL, s->prim, NULL, s->glim);
     if (rc) return rc;
   }
   for (int64_t f = 0; f < m->nf; ++f) {
@@ -766,8 +853,16 @@ static int face_fluxes(orc_state* s, const double* cons, int tau_max, double* ph
     }
     int kind = (R >= 0) ? 0 : (prm->boundary == ORC_BC_WALL ? 1 : 2);
     orc_riemann_out ro;
-    int rc = orc_face_flux(g, wl, wr, m->af + 3 * f, kind, prm->newton_tol,
-                           prm->newton_max_iter, ORC_GUESS_TR, 0.0, phi + 5 * f, &ro);
+    int rc;
+    if (s->moving) {
+      const double* A = m->af + 3 * f;
+      double xi = s->sF[f] / sqrt(dot3(A, A));
+      rc = orc_face_flux_moving(g, wl, wr, A, xi, kind, prm->newton_tol, prm->newton_max_iter,
+                                phi + 5 * f, &ro);
+    } else {
+      rc = orc_face_flux(g, wl, wr, m->af + 3 * f, kind, prm->newton_tol,
+                         prm->newton_max_iter, ORC_GUESS_TR, 0.0, phi + 5 * f, &ro);
+    }
     if (rc) return ORC_E_NUMERIC;
     s->st.face_solves++;
     s->st.newton_updates += ro.newton_updates;
@@ -789,14 +884,29 @@ static int flow_sum_and_update(orc_state* s, int64_t sub) {
       if (!s->act[f]) continue;
       double sign = (m->fL[f] == i) ? -1.0 : 1.0;
       for (int k = 0; k < 5; ++k) s->R[5 * i + k] += sign * s->q[5 * f + k];
+      if (s->moving) s->RV[i] += sign * s->qv[f];
     }
   }
   for (int64_t i = 0; i < m->nc; ++i) {
     if (sub % ((int64_t)1 << s->lev[i]) != 0) continue;
-    for (int k = 0; k < 5; ++k) {
-      s->U[5 * i + k] += s->R[5 * i + k] / m->vol[i];
-      s->R[5 * i + k] = 0.0;
-      if (!isfinite(s->U[5 * i + k])) return ORC_E_NUMERIC;
+    if (s->moving) {
+      /* geometric conservation: the cell's content V U changes by its flux
+       * sum, its volume by the volume its faces swept */
+      double v = s->V[i], vn = v + s->RV[i];
+      if (!(vn > 0.0)) return ORC_E_NUMERIC;
+      for (int k = 0; k < 5; ++k) {
+        s->U[5 * i + k] = (v * s->U[5 * i + k] + s->R[5 * i + k]) / vn;
+        s->R[5 * i + k] = 0.0;
+        if (!isfinite(s->U[5 * i + k])) return ORC_E_NUMERIC;
+      }
+      s->V[i] = vn;
+      s->RV[i] = 0.0;
+    } else {
+      for (int k = 0; k < 5; ++k) {
+        s->U[5 * i + k] += s->R[5 * i + k] / m->vol[i];
+        s->R[5 * i + k] = 0.0;
+        if (!isfinite(s->U[5 * i + k])) return ORC_E_NUMERIC;
+      }
     }
     s->st.cell_updates++;
   }
@@ -834,6 +944,7 @@ static int subiteration(orc_state* s) {
     if (!s->act[f]) continue;
     double dtf = ldexp(s->dt_min, faster_level(s, f));
     for (int k = 0; k < 5; ++k) s->q[5 * f + k] *= dtf;
+    if (s->moving) s->qv[f] = -dtf * s->sF[f];
     if (m->fR[f] < 0 && prm->boundary == ORC_BC_WALL)
       for (int k = 0; k < 3; ++k) s->st.wall_impulse[k] += s->q[5 * f + 1 + k];
   }
@@ -929,6 +1040,46 @@ int orc_advance(orc_state* s, int64_t n) {
     int rc = s->prm.time_order == 2 ? subiteration2(s) : subiteration(s);
     if (rc) return rc;
   }
+  return ORC_OK;
+}
+
+/* Moving mesh (ALE with the geometric conservation law, Sec. 2.1): node
+ * velocities node_vel [n_nodes][3]; each face moves with the mean velocity
+ * of its three nodes, w_f = (v_a + v_b + v_c) / 3 (sorted node ids), and
+ * sweeps volume at the rate sF = w_f . A_f.  The face geometry (areas,
+ * centroids, reconstruction weights) stays that of the uploaded mesh; the
+ * cell volumes evolve by the swept volumes (the conservation law of the
+ * geometry), and the fluxes are those of orc_face_flux_moving.  Forward
+ * Euler level steps (time_order 1) only.  Takes effect at the next
+ * subiteration; pass zeros to stop the motion. */
+int orc_state_motion(orc_state* s, const double* node_vel) {
+  if (!s || !node_vel || s->prm.time_order != 1) return ORC_E_ARG;
+  const orc_mesh* m = s->m;
+  for (int64_t k = 0; k < 3 * m->nn; ++k)
+    if (!isfinite(node_vel[k])) return ORC_E_ARG;
+  if (!s->sF) {
+    s->sF = (double*)malloc(sizeof(double) * m->nf);
+    s->qv = (double*)calloc((size_t)m->nf, sizeof(double));
+    s->V = (double*)malloc(sizeof(double) * m->nc);
+    s->RV = (double*)calloc((size_t)m->nc, sizeof(double));
+    if (!s->sF || !s->qv || !s->V || !s->RV) return ORC_E_ARG;
+    memcpy(s->V, m->vol, sizeof(double) * m->nc);
+  }
+  for (int64_t f = 0; f < m->nf; ++f) {
+    const double* va = node_vel + 3 * m->fn[3 * f];
+    const double* vb = node_vel + 3 * m->fn[3 * f + 1];
+    const double* vc = node_vel + 3 * m->fn[3 * f + 2];
+    double w[3];
+    for (int k = 0; k < 3; ++k) w[k] = (va[k] + vb[k] + vc[k]) / 3.0;
+    s->sF[f] = dot3(w, m->af + 3 * f);
+  }
+  s->moving = 1;
+  return ORC_OK;
+}
+
+int orc_state_volumes(const orc_state* s, double* vol) {
+  if (!s || !vol) return ORC_E_ARG;
+  memcpy(vol, s->moving ? s->V : s->m->vol, sizeof(double) * s->m->nc);
   return ORC_OK;
 }
 

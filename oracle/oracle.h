@@ -15,6 +15,10 @@
  *     Alg. 2, neighbours at most one level apart;
  *   - the cost model C(tau) = 2^(theta-tau) |Omega(tau)| of Sec. 2.2, which
  *     is what the cell-update counter counts;
+ *   - moving meshes (ALE): fluxes through faces moving with their nodes,
+ *     and cell volumes that follow the swept volumes (the geometric
+ *     conservation law), with the face geometry kept fixed -- the form
+ *     Sec. 2.1 describes for slow relative motion;
  *   - a predictor/corrector form of every level step (time_order 2),
  *     following the order of the steps of Alg. 2: predictor fluxes,
  *     prediction, slower neighbours seen at the interpolated time, corrector
@@ -107,6 +111,14 @@ int orc_face_flux(double gamma, const double* wl, const double* wr,
                   int32_t max_iter, int32_t guess_mode, double guess,
                   double* flux, orc_riemann_out* out);
 
+/* ALE flux through a face moving with normal speed xi along area/|area|:
+ * the Riemann problem sampled at x/t = xi, flux |A| (F(W) . n - xi U(W));
+ * a wall moves with the face (no mass through it, momentum p* n |A|, work
+ * p* xi |A|). */
+int orc_face_flux_moving(double gamma, const double* wl, const double* wr,
+                         const double* area, double xi, int32_t kind, double tol,
+                         int32_t max_iter, double* flux, orc_riemann_out* out);
+
 /* --- reconstruction --------------------------------------------------- */
 /* Unlimited and limited least-squares gradients of the primitive
  * variables, grad[n_cells][3][5] (d/dx, d/dy, d/dz of rho,u,v,w,p). */
@@ -148,6 +160,14 @@ int32_t orc_subiteration_level(int64_t s, int32_t theta);
 int orc_state_read(const orc_state* s, double* cons, double* accum,
                    int8_t* levels);
 int orc_state_stats(const orc_state* s, orc_stats* out);
+/* Moving mesh: node velocities [n_nodes][3]; faces move with the mean of
+ * their nodes, sweep volume w_f . A_f; the face geometry stays fixed and
+ * the cell volumes follow the swept volumes (geometric conservation law);
+ * a cell ending its step sets V' = V + swept, U' = (V U + flux sum) / V'.
+ * time_order 1 only; checkpoints (orc_state_set) are refused afterwards. */
+int orc_state_motion(orc_state* s, const double* node_vel);
+/* current cell volumes [n_cells] */
+int orc_state_volumes(const orc_state* s, double* vol);
 
 #ifdef __cplusplus
 }
