@@ -212,6 +212,34 @@ tafv_status tafv_mesh_inspect(int64_t n_nodes, const double* xyz, int64_t n_tets
 /* Per-mesh level cap (1..8), overriding params.max_levels for that mesh. */
 tafv_status tafv_mesh_params(tafv_ctx* ctx, int32_t mesh_id, int32_t max_levels);
 
+/* Moving mesh (Sec. 2.1: an ALE formulation in which the flux through a face
+ * takes the face's own velocity into account, and cell volumes that follow
+ * the geometric conservation law instead of a recomputed geometry, as for
+ * slow relative motion).  node_vel [n_nodes][3] (host, the uploaded node
+ * order) are the node velocities; each face moves with the mean velocity w_f
+ * of its three nodes and sweeps volume at the rate w_f . A_f.  The face
+ * geometry (area vectors, centroids, reconstruction weights) stays that of
+ * the uploaded mesh.  From the next subiteration on:
+ *   - the Riemann problem of a face is solved in the face's frame and
+ *     sampled on the face's path: flux |A| (F(W) . n - xi U(W)), xi the
+ *     face's normal speed; a wall moves with its face (no mass through it,
+ *     momentum p* n |A|, work p* xi |A|), and so do the wall ghosts of the
+ *     gradient;
+ *   - a cell ending its step sets V' = V + (volume its faces swept, the
+ *     slower side accumulating it like the flux) and U' = (V U + flux sum)
+ *     / V';
+ *   - time steps use the wave speeds relative to the faces and the current
+ *     volumes.
+ * The motion is kept until changed (zeros stop it); tafv_state_init() and
+ * tafv_state_reset() restore the uploaded volumes.  Needs time_order 1,
+ * TAFV_SCATTER_GATHER, the two-rarefaction start without statistics or face
+ * logging, and no batch (TAFV_E_ARG otherwise); checkpoints are not written
+ * for a moving mesh.  TAFV_E_NUMERIC if a volume becomes non-positive. */
+tafv_status tafv_mesh_motion(tafv_ctx* ctx, int32_t mesh_id, const double* node_vel);
+/* Current cell volumes, host vol [n_tets] in the caller's order (the
+ * uploaded volumes on a fixed mesh). */
+tafv_status tafv_volume_read(tafv_ctx* ctx, int32_t mesh_id, double* vol);
+
 /* Set the initial state of a mesh from host prim [n_tets][5] =
  * (rho, u, v, w, p) and reset its schedule (phase 0, t = 0, counters 0).
  * TAFV_E_STATE if rho <= 0, p <= 0 or a value is not finite. */

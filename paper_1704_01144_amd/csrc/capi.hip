@@ -49,7 +49,8 @@ void free_mesh(DevMesh* m) {
                   m->pf.list, m->pf.counts, m->pf.start, m->pc.list, m->pc.counts,
                   m->pc.start, m->dscal, m->dcount, m->dimpulse, m->pf.offs, m->pc.offs,
                   m->pf.scan_tmp, m->pc.scan_tmp, m->Q, m->frec, m->fkey, m->ckey, m->fpack,
-                  m->perm, m->xfer, m->chist, m->rb, m->dmin, m->Q0, m->D, m->Ut};
+                  m->perm, m->xfer, m->chist, m->rb, m->dmin, m->Q0, m->D, m->Ut,
+                  m->vol0, m->fnode, m->sF, m->Rv};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   delete m;
@@ -95,6 +96,16 @@ int level_histogram(DevMesh& m) {
     if (n > 0) theta = t;
   }
   return theta;
+}
+
+// moving mesh: a new or reset state starts from the uploaded geometry's
+// volumes, with no swept volume pending (the motion itself is kept)
+hipError_t reset_volumes(tafv_ctx* c, DevMesh& m) {
+  if (!m.moving) return hipSuccess;
+  hipError_t e = hipMemcpyAsync(m.vol, m.vol0, sizeof(double) * m.nc, hipMemcpyDeviceToDevice,
+                                c->stream);
+  if (e == hipSuccess) e = launch_fill_f64(c->stream, m.Rv, 0.0, m.nc);
+  return e;
 }
 
 // predictor/corrector form: at an iteration start every cell starts a step,
@@ -287,6 +298,12 @@ tafv_status read_counters(tafv_ctx* c, DevMesh& m) {
   return TAFV_OK;
 }
 
+bool any_moving(const tafv_ctx* c) {
+  for (const DevMesh* m : c->meshes)
+    if (m->moving) return true;
+  return false;
+}
+
 DevMesh* get_mesh(tafv_ctx* c, int32_t id) {
   if (!c || id < 0 || id >= (int32_t)c->meshes.size()) return nullptr;
   return c->meshes[id];
@@ -366,6 +383,8 @@ tafv_status upload_host_mesh(tafv_ctx* c, const HostMesh& hm, DevMesh** out) {
   chk(dalloc(&m->lsq32, 12 * nc));
   chk(dalloc(&m->rf32, 12 * nc));
   chk(dalloc(&m->vol, nc));
+  chk(dalloc(&m->vol0, nc));
+  chk(dalloc(&m->fnode, 3 * nf));
   chk(dalloc(&m->U, 5 * nc));
   chk(dalloc(&m->U0, 5 * nc));
   chk(dalloc(&m->R, 5 * nc));
@@ -423,6 +442,9 @@ tafv_status upload_host_mesh(tafv_ctx* c, const HostMesh& hm, DevMesh** out) {
   f32.assign(hm.rf.begin(), hm.rf.end());
   chk(up(m->rf32, f32));
   chk(up(m->vol, hm.vol));
+  chk(up(m->vol0, hm.vol));
+  chk(up(m->fnode, hm.fnode));
+  m->n_nodes = hm.n_nodes;
   chk(up(m->perm, hm.perm));
   if (e != hipSuccess) {
     free_mesh(m);
@@ -626,6 +648,7 @@ tafv_status tafv_state_init(tafv_ctx* c, int32_t mesh_id, const double* prim) {
     e = hipMemcpyAsync(m->U0, m->U, sizeof(double) * 5 * m->nc, hipMemcpyDeviceToDevice,
                        c->stream);
   if (e == hipSuccess) e = sync_time_states(c, *m);
+  if (e == hipSuccess) e = reset_volumes(c, *m);
   if (e == hipSuccess) e = launch_fill_u64(c->stream, m->dcount, 0ull, kCounterWords);
   if (e == hipSuccess) e = launch_fill_f64(c->stream, m->dimpulse, 0.0, kCounterWords);
   if (e == hipSuccess) e = launch_fill_u64(c->stream, m->dscal, 0ull, 4);
@@ -658,6 +681,7 @@ tafv_status tafv_state_reset(tafv_ctx* c, int32_t mesh_id) {
                             c->stream));
   HIP_TRY(c, launch_fill_f64(c->stream, m->R, 0.0, (int64_t)5 * m->nc));
   HIP_TRY(c, sync_time_states(c, *m));
+  HIP_TRY(c, reset_volumes(c, *m));
   m->phase = 0;
   m->theta = 0;
   m->t = 0.0;
@@ -783,6 +807,8 @@ tafv_status tafv_checkpoint_write(tafv_ctx* c, int32_t mesh_id, const double* co
   if (c->prm.time_order == 2 && phase != 0)
     return fail(c, TAFV_E_ARG,
                 "predictor/corrector form: checkpoints are written at phase 0 only");
+  if (m->moving)
+    return fail(c, TAFV_E_ARG, "checkpoints are not written on moving meshes");
   for (int64_t i = 0; i < m->nc; ++i)
     if (levels[i] < 0 || levels[i] > theta) return fail(c, TAFV_E_ARG, "level out of range");
   HIP_TRY(c, hipSetDevice(c->device));
@@ -826,11 +852,59 @@ tafv_status tafv_guess_config(tafv_ctx* c, int32_t guess, double gate, double st
   if (!(strength >= 0.0)) return fail(c, TAFV_E_ARG, "negative guess strength");
   if (guess == TAFV_GUESS_MLP && (c->prm.gamma != 1.4 || c->prm.scatter != TAFV_SCATTER_GATHER))
     return fail(c, TAFV_E_ARG, "the learned guess needs gamma 1.4 and gather scatter");
+  if ((guess != TAFV_GUESS_TR || stats) && any_moving(c))
+    return fail(c, TAFV_E_ARG, "moving meshes take the two-rarefaction start without statistics");
   c->prm.guess = guess;
   c->prm.guess_gate = gate;
   c->prm.guess_strength = strength;
   c->prm.guess_stats = stats != 0;
   if (c->batch) batch_invalidate(c);
+  return TAFV_OK;
+}
+
+tafv_status tafv_mesh_motion(tafv_ctx* c, int32_t mesh_id, const double* node_vel) {
+  if (!c) return TAFV_E_ARG;
+  if (c->batch) return fail(c, TAFV_E_ARG, "moving meshes are not available in the batched form");
+  DevMesh* m = get_mesh(c, mesh_id);
+  if (!m) return fail(c, TAFV_E_ARG, "unknown mesh");
+  if (!node_vel) return fail(c, TAFV_E_ARG, "node_vel is NULL");
+  if (c->prm.time_order != 1 || m->scatter != TAFV_SCATTER_GATHER)
+    return fail(c, TAFV_E_ARG, "moving meshes need time_order 1 and gather scatter");
+  if (c->prm.guess != TAFV_GUESS_TR || c->prm.guess_stats || c->log_cap > 0)
+    return fail(c, TAFV_E_ARG,
+                "moving meshes take the two-rarefaction start, without statistics or logging");
+  for (int64_t k = 0; k < 3 * m->n_nodes; ++k)
+    if (!std::isfinite(node_vel[k])) return fail(c, TAFV_E_ARG, "non-finite node velocity");
+  HIP_TRY(c, hipSetDevice(c->device));
+  if (!m->sF) {
+    HIP_TRY(c, dalloc(&m->sF, std::max<int64_t>(m->nf, 1)));
+    HIP_TRY(c, dalloc(&m->Rv, std::max<int64_t>(m->nc, 1)));
+    HIP_TRY(c, launch_fill_f64(c->stream, m->Rv, 0.0, m->nc));
+  }
+  double* dvel = nullptr;
+  const size_t bytes = sizeof(double) * 3 * (size_t)std::max<int64_t>(m->n_nodes, 1);
+  HIP_TRY(c, hipMalloc(&dvel, bytes));
+  hipError_t e = hipMemcpyAsync(dvel, node_vel, sizeof(double) * 3 * m->n_nodes,
+                                hipMemcpyHostToDevice, c->stream);
+  if (e == hipSuccess) e = launch_face_speed(c->stream, *m, dvel);
+  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  (void)hipFree(dvel);
+  if (e != hipSuccess) return hip_fail(c, e, "mesh motion");
+  m->moving = true;
+  return TAFV_OK;
+}
+
+tafv_status tafv_volume_read(tafv_ctx* c, int32_t mesh_id, double* vol) {
+  if (!c) return TAFV_E_ARG;
+  if (c->batch) return fail(c, TAFV_E_ARG, "moving meshes are not available in the batched form");
+  DevMesh* m = get_mesh(c, mesh_id);
+  if (!m) return fail(c, TAFV_E_ARG, "unknown mesh");
+  if (!vol) return fail(c, TAFV_E_ARG, "vol is NULL");
+  HIP_TRY(c, hipSetDevice(c->device));
+  HIP_TRY(c, launch_vol_to_caller(c->stream, *m, m->vol, m->xfer));
+  HIP_TRY(c, hipMemcpyAsync(vol, m->xfer, sizeof(double) * m->nc, hipMemcpyDeviceToHost,
+                            c->stream));
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
   return TAFV_OK;
 }
 
@@ -1006,6 +1080,8 @@ tafv_status tafv_facelog_config(tafv_ctx* c, int64_t capacity, double rate, uint
   if (capacity < 0 || !(rate >= 0.0 && rate <= 1.0)) return fail(c, TAFV_E_ARG, "invalid log");
   if (c->batch && capacity > 0)
     return fail(c, TAFV_E_ARG, "face logging is not available in the batched form");
+  if (capacity > 0 && any_moving(c))
+    return fail(c, TAFV_E_ARG, "face logging is not available on moving meshes");
   HIP_TRY(c, hipSetDevice(c->device));
   HIP_TRY(c, hipStreamSynchronize(c->stream));
   if (c->log_rows) (void)hipFree(c->log_rows);

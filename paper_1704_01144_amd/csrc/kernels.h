@@ -49,6 +49,10 @@ hipError_t launch_flux(hipStream_t s, DevMesh& m, const StepArgs& a, int first, 
 hipError_t launch_cell_gather(hipStream_t s, DevMesh& m, int count, int tau_s, int tau_upd,
                               double dt_min, int precision);
 hipError_t launch_update(hipStream_t s, DevMesh& m, int count, int tau_upd);
+// moving mesh: face volume rates sF from node velocities d_vel [n_nodes][3]
+hipError_t launch_face_speed(hipStream_t s, DevMesh& m, const double* d_vel);
+// one double per cell to the caller's order
+hipError_t launch_vol_to_caller(hipStream_t s, DevMesh& m, const double* src, double* dst);
 // predictor/corrector form (gather mode): predictions D of the cells whose
 // step starts (tau <= tau_s) from the predictor fluxes Q0, and the states Ut
 // of every cell at the end of subiteration `sub`; then the corrector sums

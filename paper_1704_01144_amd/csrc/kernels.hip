@@ -71,12 +71,13 @@ __global__ __launch_bounds__(kBlock) void k_dt(int nc, int nf, const double* __r
                                                const double* __restrict__ fA, double gamma,
                                                double cfl, double* __restrict__ dt,
                                                unsigned long long* dscal,
-                                               unsigned long long* dmin) {
+                                               unsigned long long* dmin,
+                                               const double* __restrict__ sF) {
   int i = blockIdx.x * blockDim.x + threadIdx.x;
   double dti = INFINITY;
   if (i < nc) {
     bool bad = false;
-    dti = dt_item(i, nc, nf, U, vol, c2f, fA, gamma, cfl, bad);
+    dti = dt_item(i, nc, nf, U, vol, c2f, fA, gamma, cfl, bad, sF);
     if (bad) atomicOr(&dscal[2], 1ull);
     dt[i] = dti;
   }
@@ -359,12 +360,14 @@ __global__ __launch_bounds__(kBlock) void k_flux_colour(FluxArgs<T> a) {
 
 // Gather mode: store the time-integrated flux of each active face; the
 // cells add their faces afterwards (k_cell_gather).
-template <int ORDER, typename T, bool G14>
+// MOVE: through faces moving with their nodes (ALE form, see face_flux)
+template <int ORDER, typename T, bool G14, bool MOVE = false>
 __global__ __launch_bounds__(kBlock) void k_flux_store(FluxArgs<T> a) {
   int idx = xcd_block() * kBlock + threadIdx.x;
   SolveInfo info{0, 0, 0, 0, 0, 0, 0, 0};
   double i0 = 0, i1 = 0, i2 = 0;
-  if (idx < a.count) flux_store_item<ORDER, T, G14>(a, a.rec[idx], a.s.dt_min, info, i0, i1, i2);
+  if (idx < a.count)
+    flux_store_item<ORDER, T, G14, MOVE>(a, a.rec[idx], a.s.dt_min, info, i0, i1, i2);
   flush_counters(info, i0, i1, i2, a.dcount, a.dimpulse);
 }
 
@@ -398,6 +401,36 @@ __global__ __launch_bounds__(kBlock) void k_cell_gather(int count, const int* __
     atomicOr(&dscal[2], 1ull);
 }
 
+// moving mesh: the same with the swept volumes and the cell volumes
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_cell_gather_move(
+    int count, const int* __restrict__ list, int nc, const uint32_t* __restrict__ fpack,
+    const int* __restrict__ c2f, const T* __restrict__ Q, double dt_min,
+    double* __restrict__ vol, double* __restrict__ U, double* __restrict__ R, int tau_s,
+    int tau_upd, const double* __restrict__ sF, double* __restrict__ Rv,
+    unsigned long long* dscal) {
+  int idx = xcd_block() * kBlock + threadIdx.x;
+  if (idx >= count) return;
+  if (!cell_gather_item<T, true>(list[idx], nc, fpack, c2f, Q, dt_min, vol, U, R, tau_s, tau_upd,
+                                 sF, Rv, vol))
+    atomicOr(&dscal[2], 1ull);
+}
+
+
+// moving mesh: each face moves with the mean velocity of its three nodes and
+// sweeps volume at the rate sF = w_f . A_f (node velocities [n_nodes][3])
+__global__ void k_face_speed(int nf, const int* __restrict__ fnode, const double* __restrict__ fA,
+                             const double* __restrict__ vel, double* __restrict__ sF) {
+  int f = blockIdx.x * blockDim.x + threadIdx.x;
+  if (f >= nf) return;
+  const double* va = vel + 3 * (size_t)fnode[f];
+  const double* vb = vel + 3 * (size_t)fnode[nf + f];
+  const double* vc = vel + 3 * (size_t)fnode[2 * (size_t)nf + f];
+  double w0 = (va[0] + vb[0] + vc[0]) / 3.0;
+  double w1 = (va[1] + vb[1] + vc[1]) / 3.0;
+  double w2 = (va[2] + vb[2] + vc[2]) / 3.0;
+  sF[f] = w0 * fA[f] + w1 * fA[nf + f] + w2 * fA[2 * (size_t)nf + f];
+}
 
 // predictor/corrector form: predictions of the starting cells and the
 // states of every cell at the end of the subiteration
@@ -502,7 +535,8 @@ hipError_t launch_dt(hipStream_t s, DevMesh& m, const StepArgs& a) {
   hipLaunchKernelGGL(k_fill_u64, dim3(blocks_for(kCounterWords)), dim3(kBlock), 0, s, m.dmin,
                      0x7ff0000000000000ull, kCounterWords);  // +inf
   hipLaunchKernelGGL(k_dt, dim3(blocks_for(m.nc)), dim3(kBlock), 0, s, m.nc, m.nf, m.U, m.vol,
-                     m.c2f, m.fA, a.gas.g, a.cfl, m.dt, m.dscal, m.dmin);
+                     m.c2f, m.fA, a.gas.g, a.cfl, m.dt, m.dscal, m.dmin,
+                     m.moving ? m.sF : nullptr);
   hipLaunchKernelGGL(k_min_slots, dim3(1), dim3(64), 0, s, m.dmin, m.dscal);
   return hipGetLastError();
 }
@@ -580,11 +614,11 @@ hipError_t launch_grad(hipStream_t s, DevMesh& m, const StepArgs& a, int count,
   if (!U) U = m.U;
   if (a.precision == TAFV_FP32_FLUX) {
     GradArgs<float> g{m.pc.list, count, m.nc, m.nf, U, m.nb_, m.lsq32, m.rf32, m.fA,
-                      (float*)m.Wf, a.gas.gm1, a.boundary};
+                      (float*)m.Wf, a.gas.gm1, a.boundary, m.moving ? m.sF : nullptr};
     hipLaunchKernelGGL(k_grad<float>, dim3(blocks_for(count)), dim3(kBlock), 0, s, g);
   } else {
     GradArgs<double> g{m.pc.list, count, m.nc, m.nf, U, m.nb_, m.lsq, m.rf, m.fA,
-                       (double*)m.Wf, a.gas.gm1, a.boundary};
+                       (double*)m.Wf, a.gas.gm1, a.boundary, m.moving ? m.sF : nullptr};
     hipLaunchKernelGGL(k_grad<double>, dim3(blocks_for(count)), dim3(kBlock), 0, s, g);
   }
   return hipGetLastError();
@@ -593,6 +627,11 @@ hipError_t launch_grad(hipStream_t s, DevMesh& m, const StepArgs& a, int count,
 template <typename T, bool G14>
 static void flux_launch(hipStream_t s, int order, int scatter, int count, const FluxArgs<T>& f) {
   dim3 g(blocks_for(count)), b(kBlock);
+  if (f.sF) {  // moving mesh (gather mode)
+    if (order == 2) hipLaunchKernelGGL((k_flux_store<2, T, G14, true>), g, b, 0, s, f);
+    else hipLaunchKernelGGL((k_flux_store<1, T, G14, true>), g, b, 0, s, f);
+    return;
+  }
   if (scatter == TAFV_SCATTER_COLOUR) {
     if (order == 2) hipLaunchKernelGGL((k_flux_colour<2, T, G14>), g, b, 0, s, f);
     else hipLaunchKernelGGL((k_flux_colour<1, T, G14>), g, b, 0, s, f);
@@ -629,8 +668,8 @@ hipError_t launch_flux(hipStream_t s, DevMesh& m, const StepArgs& a, int first, 
     FluxArgs<float> f{rec, count, m.nf, m.nc, m.fA32, U, (const float*)m.Wf, m.R, (float*)Q, m.dcount,
                       m.dimpulse, a, ft.mlp, ft.log_rows, ft.log_count, ft.log_cap,
                       ft.log_rate, ft.log_seed, ft.subit, ft.guess_gate, ft.guess_strength,
-                      pass_mode, (const float*)Qpred};
-    if (ft.feat && a.gas.is14 && m.scatter == TAFV_SCATTER_GATHER)
+                      pass_mode, (const float*)Qpred, m.moving ? m.sF : nullptr};
+    if (ft.feat && a.gas.is14 && m.scatter == TAFV_SCATTER_GATHER && !m.moving)
       flux_feat_launch<float>(s, a.order, ft.feat, count, f);
     else if (a.gas.is14) flux_launch<float, true>(s, a.order, m.scatter, count, f);
     else flux_launch<float, false>(s, a.order, m.scatter, count, f);
@@ -638,8 +677,8 @@ hipError_t launch_flux(hipStream_t s, DevMesh& m, const StepArgs& a, int first, 
     FluxArgs<double> f{rec, count, m.nf, m.nc, m.fA, U, (const double*)m.Wf, m.R, (double*)Q,
                        m.dcount, m.dimpulse, a, ft.mlp, ft.log_rows, ft.log_count, ft.log_cap,
                        ft.log_rate, ft.log_seed, ft.subit, ft.guess_gate, ft.guess_strength,
-                       pass_mode, (const double*)Qpred};
-    if (ft.feat && a.gas.is14 && m.scatter == TAFV_SCATTER_GATHER)
+                       pass_mode, (const double*)Qpred, m.moving ? m.sF : nullptr};
+    if (ft.feat && a.gas.is14 && m.scatter == TAFV_SCATTER_GATHER && !m.moving)
       flux_feat_launch<double>(s, a.order, ft.feat, count, f);
     else if (a.gas.is14) flux_launch<double, true>(s, a.order, m.scatter, count, f);
     else flux_launch<double, false>(s, a.order, m.scatter, count, f);
@@ -650,6 +689,17 @@ hipError_t launch_flux(hipStream_t s, DevMesh& m, const StepArgs& a, int first, 
 hipError_t launch_cell_gather(hipStream_t s, DevMesh& m, int count, int tau_s, int tau_upd,
                               double dt_min, int precision) {
   if (count <= 0) return hipSuccess;
+  if (m.moving) {
+    if (precision == TAFV_FP32_FLUX)
+      hipLaunchKernelGGL(k_cell_gather_move<float>, dim3(blocks_for(count)), dim3(kBlock), 0, s,
+                         count, m.pc.list, m.nc, m.fpack, m.c2f, (const float*)m.Q, dt_min,
+                         m.vol, m.U, m.R, tau_s, tau_upd, m.sF, m.Rv, m.dscal);
+    else
+      hipLaunchKernelGGL(k_cell_gather_move<double>, dim3(blocks_for(count)), dim3(kBlock), 0, s,
+                         count, m.pc.list, m.nc, m.fpack, m.c2f, (const double*)m.Q, dt_min,
+                         m.vol, m.U, m.R, tau_s, tau_upd, m.sF, m.Rv, m.dscal);
+    return hipGetLastError();
+  }
   if (precision == TAFV_FP32_FLUX)
     hipLaunchKernelGGL(k_cell_gather<float>, dim3(blocks_for(count)), dim3(kBlock), 0, s, count,
                        m.pc.list, m.nc, m.fpack, m.c2f, (const float*)m.Q, dt_min, m.vol, m.U,
@@ -687,6 +737,17 @@ hipError_t launch_cell_gather2(hipStream_t s, DevMesh& m, int count, int tau_upd
                        count, m.pc.list, m.nc, m.fpack, m.c2f, (const double*)m.Q, dt_min,
                        m.vol, m.U, m.Ut, m.R, tau_upd, m.dscal);
   return hipGetLastError();
+}
+
+hipError_t launch_face_speed(hipStream_t s, DevMesh& m, const double* d_vel) {
+  if (m.nf <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_face_speed, dim3(blocks_for(m.nf)), dim3(kBlock), 0, s, m.nf, m.fnode,
+                     m.fA, d_vel, m.sF);
+  return hipGetLastError();
+}
+
+hipError_t launch_vol_to_caller(hipStream_t s, DevMesh& m, const double* src, double* dst) {
+  return rows_to_caller<double>(s, m, 1, src, dst);
 }
 
 hipError_t launch_update(hipStream_t s, DevMesh& m, int count, int tau_upd) {

@@ -51,12 +51,13 @@ __device__ inline void cons2prim(const double* U, double gm1, double* w) {
 // ---------------------------------------------------------------------------
 // time step, classification, sweeps, keys (phase 0 of an iteration)
 
-// dt_i = cfl V_i / sum_f (|u_i . n_f| + a_i) |A_f|; infinity and bad = true
-// on a non-physical state
+// dt_i = cfl V_i / sum_f (|u_i . n_f - xi_f| + a_i) |A_f|, xi_f = sF_f / |A_f|
+// the normal speed of a moving face (sF null: a fixed mesh); infinity and
+// bad = true on a non-physical state
 __device__ inline double dt_item(int i, int nc, int nf, const double* __restrict__ U,
                                  const double* __restrict__ vol, const int* __restrict__ c2f,
                                  const double* __restrict__ fA, double gamma, double cfl,
-                                 bool& bad) {
+                                 bool& bad, const double* __restrict__ sF = nullptr) {
   double w[5];
   cons2prim(U + 5 * (size_t)i, gamma - 1.0, w);
   if (!(w[0] > 0.0) || !(w[4] > 0.0) || !isfinite(w[4])) {
@@ -70,6 +71,7 @@ __device__ inline double dt_item(int i, int nc, int nf, const double* __restrict
     double ax = fA[f], ay = fA[nf + f], az = fA[2 * (size_t)nf + f];
     double am = sqrt(ax * ax + ay * ay + az * az);
     double un = (w[1] * ax + w[2] * ay + w[3] * az) / am;
+    if (sF) un -= sF[f] / am;
     s += (fabs(un) + a) * am;
   }
   return cfl * vol[i] / s;
@@ -203,6 +205,7 @@ struct GradArgs {
   T* Wf;  // [4][5][nc]
   double gm1;
   int boundary;
+  const double* sF;  // moving mesh: face volume rates (walls move with them)
 };
 
 // Least squares over the 4 face neighbours (mirror ghosts on the boundary):
@@ -228,7 +231,9 @@ __device__ inline void grad_item_w(const GradArgs<T>& a, int i, const double* wd
         T ax = (T)a.fA[f], ay = (T)a.fA[a.nf + f], az = (T)a.fA[2 * (size_t)a.nf + f];
         T ia = frsq(ax * ax + ay * ay + az * az);
         T nx = ax * ia, ny = ay * ia, nz = az * ia;
-        T un2 = 2 * (wi[1] * nx + wi[2] * ny + wi[3] * nz);
+        T un = wi[1] * nx + wi[2] * ny + wi[3] * nz;
+        if (a.sF) un -= (T)a.sF[f] * ia;  // the wall moves with the face
+        T un2 = 2 * un;
         dw[m][1] = -un2 * nx;
         dw[m][2] = -un2 * ny;
         dw[m][3] = -un2 * nz;
@@ -303,6 +308,7 @@ struct FluxArgs {
   // predictor fluxes; wall impulse q = dt_f (phi0 + phi1) / 2
   int pass_mode;
   const T* Qpred;
+  const double* sF;  // moving mesh: face volume rates w_f . A_f
 };
 
 // gather mode: the face's stored flux and the wall impulse of its
@@ -358,7 +364,13 @@ __device__ inline void add_info(SolveInfo& a, const SolveInfo& b) {
 
 // |A| F(W(0)) . n for one face: reconstructed states, rotation to the face
 // normal, exact Riemann solve (p* in FP64), sampling at x/t = 0, flux.
-template <int ORDER, typename T, bool G14>
+// MOVE: the face moves with normal speed xi = sF / |A| (ALE form): the
+// Riemann problem is solved in the face's frame (normal velocities minus
+// xi; a wall's mirror state follows the face), sampled at its origin, and
+// the flux through the moving face is |A| (F(W) . n - xi U(W)): the
+// convective terms take the relative normal velocity, the pressure work the
+// absolute one (+ |A| p xi in the energy flux).
+template <int ORDER, typename T, bool G14, bool MOVE = false>
 __device__ inline void face_flux(const FluxArgs<T>& a, int4 r, T* phi, SolveInfo& info) {
   const Gas& G = a.s.gas;
   const int f = r.x, hL = r.y, hR = r.z;
@@ -371,6 +383,11 @@ __device__ inline void face_flux(const FluxArgs<T>& a, int4 r, T* phi, SolveInfo
   T am = a2 * ia;
   T nx = ax * ia, ny = ay * ia, nz = az * ia;
   T unl = wl[1] * nx + wl[2] * ny + wl[3] * nz;
+  T xi = 0;
+  if (MOVE) {
+    xi = (T)a.sF[f] * ia;
+    unl -= xi;
+  }
   if (hR < 0 && a.s.boundary != TAFV_BC_WALL) {  // transmissive: F(W_L)
     T E = wl[4] * (T)(1.0 / G.gm1) + (T)0.5 * wl[0] * (wl[1] * wl[1] + wl[2] * wl[2] + wl[3] * wl[3]);
     phi[0] = am * wl[0] * unl;
@@ -378,10 +395,12 @@ __device__ inline void face_flux(const FluxArgs<T>& a, int4 r, T* phi, SolveInfo
     phi[2] = am * (wl[0] * unl * wl[2] + wl[4] * ny);
     phi[3] = am * (wl[0] * unl * wl[3] + wl[4] * nz);
     phi[4] = am * unl * (E + wl[4]);
+    if (MOVE) phi[4] += am * wl[4] * xi;
     return;
   }
   const bool wall = hR < 0;
   T unr = wall ? -unl : wr[1] * nx + wr[2] * ny + wr[3] * nz;
+  if (MOVE && !wall) unr -= xi;
   const double rl = wl[0], pl = wl[4];
   const double rr = wall ? rl : (double)wr[0], pr = wall ? pl : (double)wr[4];
   Star st;
@@ -419,7 +438,7 @@ __device__ inline void face_flux(const FluxArgs<T>& a, int4 r, T* phi, SolveInfo
     phi[1] = ps * am * nx;
     phi[2] = ps * am * ny;
     phi[3] = ps * am * nz;
-    phi[4] = 0;
+    phi[4] = MOVE ? ps * am * xi : (T)0;  // a moving wall works on the gas
     return;
   }
   T rs, us, ps;
@@ -441,6 +460,7 @@ __device__ inline void face_flux(const FluxArgs<T>& a, int4 r, T* phi, SolveInfo
   phi[2] = am * (rs * us * vy + ps * ny);
   phi[3] = am * (rs * us * vz + ps * nz);
   phi[4] = am * us * (E + ps);
+  if (MOVE) phi[4] += am * ps * xi;
 }
 
 // Counters are spread over kCountSlots slots 128 bytes apart (slot = block
@@ -487,12 +507,12 @@ __device__ inline void flush_counters(const SolveInfo& info, double i0, double i
 // Gather mode: the flux Phi of one face into Q[f], in the flux precision
 // (the cells form q = 2^tau_f dt_min Phi in FP64, the same product the
 // colour scatter forms); the wall impulse q is added to (i0, i1, i2).
-template <int ORDER, typename T, bool G14>
+template <int ORDER, typename T, bool G14, bool MOVE = false>
 __device__ inline void flux_store_item(const FluxArgs<T>& a, int4 r, double dt_min,
                                        SolveInfo& acc, double& i0, double& i1, double& i2) {
   SolveInfo info{0, 0, 0, 0, 0, 0, 0, 0};
   T phi[5];
-  face_flux<ORDER, T, G14>(a, r, phi, info);
+  face_flux<ORDER, T, G14, MOVE>(a, r, phi, info);
   add_info(acc, info);
   store_face_flux(a, r, dt_min, phi, r.z < 0 && a.s.boundary == TAFV_BC_WALL, i0, i1, i2);
 }
@@ -668,40 +688,71 @@ __device__ inline void flux_feat_item(const FluxArgs<T>& a, bool valid, int4 r, 
   add_info(acc, info);
 }
 
+// A cell ending its step applies its flux sum acc: U += acc / V on a fixed
+// mesh; on a moving mesh its content and volume change together (geometric
+// conservation), V' = V + accv, U' = (V U + acc) / V'.  Returns false on a
+// non-finite state or a non-positive volume.
+// (Vw: the writable volume array of a moving mesh, null otherwise)
+template <bool MOVE>
+__device__ inline bool apply_cell(int i, const double* acc, double accv,
+                                  const double* __restrict__ vol, double* __restrict__ Vw,
+                                  double* __restrict__ U) {
+  bool bad = false;
+  if (MOVE) {
+    double* V = Vw;
+    const double v = V[i], vn = v + accv;
+    for (int k = 0; k < 5; ++k) {
+      const double u = (v * U[5 * (size_t)i + k] + acc[k]) / vn;
+      U[5 * (size_t)i + k] = u;
+      bad |= !isfinite(u);
+    }
+    V[i] = vn;
+    bad |= !(vn > 0.0);
+  } else {
+    const double v = vol[i];
+    for (int k = 0; k < 5; ++k) {
+      const double u = U[5 * (size_t)i + k] + acc[k] / v;
+      U[5 * (size_t)i + k] = u;
+      bad |= !isfinite(u);
+    }
+  }
+  return !bad;
+}
+
 // Gather mode, per cell with an active face or whose step ends: add the
 // active faces' time-integrated fluxes q = 2^tau_f dt_min Phi in local face
 // order (-q where the cell is the lower id of the face, +q otherwise), then
 // U += R / V, R = 0 for ending steps.  A cell with kEarlyBit applies the
 // sum of its faces at its step's start instead (its accumulator stays 0).
 // Returns false on a non-finite updated state.
-template <typename T>
+template <typename T, bool MOVE = false>
 __device__ inline bool cell_gather_item(int i, int nc, const uint32_t* __restrict__ fpack,
                                         const int* __restrict__ c2f,
                                         const T* __restrict__ Q, double dt_min,
                                         const double* __restrict__ vol, double* __restrict__ U,
-                                        double* __restrict__ R, int tau_s, int tau_upd) {
+                                        double* __restrict__ R, int tau_s, int tau_upd,
+                                        const double* __restrict__ sF = nullptr,
+                                        double* __restrict__ Rv = nullptr,
+                                        double* __restrict__ Vw = nullptr) {
   uint32_t pk = fpack[i];
   int ti = (pk >> 20) & 15;
   double acc[5] = {0, 0, 0, 0, 0};
+  double accv = 0.0;  // moving mesh: swept volume, -dt_f sF per face as the flux
   if (pk & kEarlyBit) {
     if (ti > tau_s) return true;  // applied at the step's start
     const double dtf = ldexp(dt_min, ti);
     for (int m = 0; m < 4; ++m) {
-      const T* q = Q + 5 * (size_t)c2f[m * nc + i];
+      const int f = c2f[m * nc + i];
+      const T* q = Q + 5 * (size_t)f;
       if (pk & (1u << (16 + m))) {
         for (int k = 0; k < 5; ++k) acc[k] += dtf * (double)q[k];
+        if (MOVE) accv += -dtf * sF[f];
       } else {
         for (int k = 0; k < 5; ++k) acc[k] -= dtf * (double)q[k];
+        if (MOVE) accv -= -dtf * sF[f];
       }
     }
-    const double v = vol[i];
-    bool bad = false;
-    for (int k = 0; k < 5; ++k) {
-      const double u = U[5 * (size_t)i + k] + acc[k] / v;
-      U[5 * (size_t)i + k] = u;
-      bad |= !isfinite(u);
-    }
-    return !bad;
+    return apply_cell<MOVE>(i, acc, accv, vol, Vw, U);
   }
   bool ends = ti <= tau_upd;
   bool touched = false;
@@ -711,30 +762,31 @@ __device__ inline bool cell_gather_item(int i, int nc, const uint32_t* __restric
     if (tf > tau_s) continue;
     if (!touched) {
       for (int k = 0; k < 5; ++k) acc[k] = Ri[k];
+      if (MOVE) accv = Rv[i];
       touched = true;
     }
-    const T* q = Q + 5 * (size_t)c2f[m * nc + i];
+    const int f = c2f[m * nc + i];
+    const T* q = Q + 5 * (size_t)f;
     const double dtf = ldexp(dt_min, tf);
     if (pk & (1u << (16 + m))) {
       for (int k = 0; k < 5; ++k) acc[k] += dtf * (double)q[k];
+      if (MOVE) accv += -dtf * sF[f];
     } else {
       for (int k = 0; k < 5; ++k) acc[k] -= dtf * (double)q[k];
+      if (MOVE) accv -= -dtf * sF[f];
     }
   }
   if (ends) {
-    if (!touched)
+    if (!touched) {
       for (int k = 0; k < 5; ++k) acc[k] = Ri[k];
-    double v = vol[i];
-    bool bad = false;
-    for (int k = 0; k < 5; ++k) {
-      double u = U[5 * (size_t)i + k] + acc[k] / v;
-      U[5 * (size_t)i + k] = u;
-      Ri[k] = 0.0;
-      bad |= !isfinite(u);
+      if (MOVE) accv = Rv[i];
     }
-    return !bad;
+    for (int k = 0; k < 5; ++k) Ri[k] = 0.0;
+    if (MOVE) Rv[i] = 0.0;
+    return apply_cell<MOVE>(i, acc, accv, vol, Vw, U);
   } else if (touched) {
     for (int k = 0; k < 5; ++k) Ri[k] = acc[k];
+    if (MOVE) Rv[i] = accv;
   }
   return true;
 }

@@ -49,6 +49,10 @@ tafv_status build_host_mesh(int64_t n_nodes, const double* xyz, int64_t n_tets,
     *err = "mesh too large: at most 2^29 tets";
     return TAFV_E_ARG;
   }
+  if (n_nodes >= (int64_t(1) << 31)) {
+    *err = "mesh too large: at most 2^31 - 1 nodes";
+    return TAFV_E_ARG;
+  }
   const int64_t nc = n_tets;
   auto node = [&](int64_t id) { return V3{xyz[3 * id], xyz[3 * id + 1], xyz[3 * id + 2]}; };
   // validate and measure in the caller's order
@@ -142,6 +146,7 @@ tafv_status build_host_mesh(int64_t n_nodes, const double* xyz, int64_t n_tets,
   struct RawFace {
     int32_t L, R;
     int8_t sL, sR;
+    int32_t v[3];
     V3 A, xf;
   };
   std::vector<RawFace> faces;
@@ -157,6 +162,7 @@ tafv_status build_host_mesh(int64_t n_nodes, const double* xyz, int64_t n_tets,
     RawFace f;
     f.L = rec[i].cell;
     f.sL = (int8_t)rec[i].slot;
+    for (int k = 0; k < 3; ++k) f.v[k] = (int32_t)rec[i].v[k];
     if (j - i == 2) {
       f.R = rec[i + 1].cell;
       f.sR = (int8_t)rec[i + 1].slot;
@@ -229,6 +235,8 @@ tafv_status build_host_mesh(int64_t n_nodes, const double* xyz, int64_t n_tets,
   out->fhR.resize(nf);
   out->fcol.resize(nf);
   out->fA.resize(3 * nf);
+  out->fnode.resize(3 * nf);
+  out->n_nodes = n_nodes;
   out->nb.assign(4 * nc, 0);
   out->c2f.assign(4 * nc, 0);
   std::vector<V3> xf_new(nf);
@@ -244,6 +252,7 @@ tafv_status build_host_mesh(int64_t n_nodes, const double* xyz, int64_t n_tets,
     out->fA[k] = f.A.x;
     out->fA[nf + k] = f.A.y;
     out->fA[2 * nf + k] = f.A.z;
+    for (int q = 0; q < 3; ++q) out->fnode[q * nf + k] = f.v[q];
     xf_new[k] = f.xf;
     out->c2f[f.sL * nc + f.L] = (int32_t)k;
     out->nb[f.sL * nc + f.L] = f.R >= 0 ? f.R : -(int32_t)(k + 1);

@@ -28,6 +28,8 @@ struct HostMesh {
   std::vector<int32_t> fhL, fhR;   // half-face ids 4*cell + slot; fhR = -1 on the boundary
   std::vector<int8_t> fcol;        // colour of each face
   std::vector<double> fA;          // [3][nf] area vector out of the lower cell
+  std::vector<int32_t> fnode;      // [3][nf] the face's node ids, ascending
+  int64_t n_nodes = 0;
   // cells
   std::vector<int32_t> nb;         // [4][nc] neighbour across slot m, or -(face+1)
   std::vector<int32_t> c2f;        // [4][nc] face of slot m
@@ -70,6 +72,9 @@ struct DevMesh {
   float* fA32 = nullptr;
   int32_t *nb_ = nullptr, *c2f = nullptr;
   double *lsq = nullptr, *rf = nullptr, *vol = nullptr;
+  double* vol0 = nullptr;   // [nc] volumes of the uploaded geometry
+  int32_t* fnode = nullptr; // [3][nf] node ids of each face, ascending
+  int64_t n_nodes = 0;
   float *lsq32 = nullptr, *rf32 = nullptr;
   // state
   double* U = nullptr;     // [nc][5]
@@ -82,6 +87,12 @@ struct DevMesh {
   void* Q = nullptr;       // [nf][5] gather mode: face fluxes |A| F . n in the flux
                            // precision (double or float); the cells scale them
                            // by 2^tau_f dt_min in FP64
+  // moving mesh only: per face the volume rate sF = w_f . A_f it sweeps,
+  // per cell the swept volume not yet applied; vol then holds the current
+  // cell volumes
+  bool moving = false;
+  double* sF = nullptr;    // [nf]
+  double* Rv = nullptr;    // [nc]
   // predictor/corrector form only (time order 2)
   void* Q0 = nullptr;      // [nf][5] predictor flux of each face's current step (flux
                            // precision)

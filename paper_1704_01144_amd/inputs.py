@@ -134,6 +134,22 @@ def pulse_state(nodes, tets, centre=(0.5, 0.5, 0.5), width=0.2, amp=0.01,
     return prim
 
 
+def motion_field(nodes, amp=0.05, seed=0, modes=3):
+    """Smooth node velocities [n_nodes][3] for moving-mesh runs: per
+    component a sum of `modes` plane sine waves amp * a * sin(2 pi k . x + c)
+    with k, a, c drawn from default_rng(seed) (|k| up to 2, a in [-1, 1])."""
+    rng = np.random.default_rng(seed)
+    x = np.asarray(nodes, dtype=np.float64)
+    v = np.zeros_like(x)
+    for d in range(3):
+        for _ in range(modes):
+            k = rng.uniform(-2.0, 2.0, 3)
+            a = rng.uniform(-1.0, 1.0)
+            c = rng.uniform(0.0, 2.0 * np.pi)
+            v[:, d] += amp * a * np.sin(2.0 * np.pi * (x @ k) + c)
+    return v
+
+
 def sod_state(nodes, tets, x0=0.5, left=(1.0, 0.0, 1.0), right=(0.125, 0.0, 0.1)):
     """Shock-tube state along x: (rho, u, p) left of x0, right of it
     (Sod's 1978 data by default), zero transverse velocity."""

@@ -70,6 +70,8 @@ def _load():
         "tafv_destroy": [P],
         "tafv_mesh_upload": [P, C.c_int64, dp, C.c_int64, i64p, i32p],
         "tafv_mesh_params": [P, C.c_int32, C.c_int32],
+        "tafv_mesh_motion": [P, C.c_int32, dp],
+        "tafv_volume_read": [P, C.c_int32, dp],
         "tafv_mesh_inspect": [C.c_int64, dp, C.c_int64, i64p, i64p, i64p, i32p, i32p, i8p, dp,
                               i32p],
         "tafv_state_init": [P, C.c_int32, dp],
@@ -110,7 +112,8 @@ EXPORTS = ["tafv_params_default", "tafv_create", "tafv_destroy", "tafv_last_erro
            "tafv_mesh_stats", "tafv_state_read", "tafv_checkpoint_read", "tafv_checkpoint_write",
            "tafv_profile_enable", "tafv_profile_read", "tafv_guess_config", "tafv_mlp_set", "tafv_mlp_get",
            "tafv_mlp_forward", "tafv_mlp_grad", "tafv_mlp_train", "tafv_facelog_config",
-           "tafv_facelog_read", "tafv_batch_config", "tafv_batch_info"]
+           "tafv_facelog_read", "tafv_batch_config", "tafv_batch_info", "tafv_mesh_motion",
+           "tafv_volume_read"]
 MLP_PARAMS = 1313
 
 
@@ -288,6 +291,17 @@ def tafv_facelog_read(ctx, cap):
     return rows[:n.value]
 
 
+def tafv_mesh_motion(ctx, mesh_id, node_vel):
+    v = np.ascontiguousarray(node_vel, dtype=np.float64)
+    _check(lib.tafv_mesh_motion(ctx, mesh_id, _d(v)), ctx)
+
+
+def tafv_volume_read(ctx, mesh_id, n_cells):
+    vol = np.empty(n_cells)
+    _check(lib.tafv_volume_read(ctx, mesh_id, _d(vol)), ctx)
+    return vol
+
+
 def tafv_profile_enable(ctx, on=True):
     _check(lib.tafv_profile_enable(ctx, 1 if on else 0), ctx)
 
@@ -351,6 +365,12 @@ class Solver:
 
     def stats(self, mesh_id=0):
         return tafv_mesh_stats(self.ctx, mesh_id)
+
+    def motion(self, node_vel, mesh_id=0):
+        tafv_mesh_motion(self.ctx, mesh_id, node_vel)
+
+    def volumes(self, mesh_id=0):
+        return tafv_volume_read(self.ctx, mesh_id, self.n_cells[mesh_id])
 
     def checkpoint(self, mesh_id=0):
         return tafv_checkpoint_read(self.ctx, mesh_id, self.n_cells[mesh_id])
