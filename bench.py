@@ -54,7 +54,8 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def run_form(T, torch, cfg, precision, steps, warmup, scatter, mlp=None, stats=0, time_order=1):
+def run_form(T, torch, cfg, precision, steps, warmup, scatter, mlp=None, stats=0, time_order=1,
+             motion=None):
     stream = torch.cuda.current_stream()
     extra = {}
     if mlp is not None:
@@ -67,6 +68,8 @@ def run_form(T, torch, cfg, precision, steps, warmup, scatter, mlp=None, stats=0
     if mlp is not None:
         T.tafv_mlp_set(s.ctx, mlp["theta"])
     s.init(cfg["prim"])
+    if motion is not None:
+        s.motion(motion)  # kept across the resets; each reset restores the volumes
     for _ in range(warmup):
         s.reset()
         T.tafv_advance_async(s.ctx, UNITS)
@@ -323,6 +326,7 @@ def main():
     ap.add_argument("--no-batch", action="store_true", help="skip the 128-mesh batched form")
     ap.add_argument("--no-time2", action="store_true",
                     help="skip the predictor/corrector form (second order in time)")
+    ap.add_argument("--no-moving", action="store_true", help="skip the moving-mesh form")
     ap.add_argument("--batch-only", action="store_true",
                     help="only the batched form, FP64 and FP32 with the two-rarefaction start")
     ap.add_argument("--copy-probe", action="store_true",
@@ -446,6 +450,20 @@ def main():
             forms[f"time_order_2_{name}"] = entry
             log(f"time order 2, {name}: {vt / 1e9:.3f} G cell-updates/s, "
                 f"{rt['ms'] / args.steps:.2f} ms per step")
+    if not args.no_moving and args.scatter == 1:
+        forms = out.setdefault("forms", {})
+        vel = I.motion_field(cfg["nodes"], 0.05, seed=0)
+        rm = run_form(T, torch, cfg, T.FP64, args.steps, args.warmup, args.scatter, motion=vel)
+        vm = rm["updates"] / (rm["ms"] * 1e-3)
+        forms["moving_mesh_fp64"] = {
+            "value": round(vm, 1), "ms_per_step": round(rm["ms"] / args.steps, 4),
+            "cost_vs_fixed_mesh": round(rm["ms"] / r64["ms"], 3),
+            "motion": "inputs.motion_field(nodes, 0.05, seed=0): node velocities, faces move "
+                      "with their nodes, volumes by the geometric conservation law",
+            "cell_updates_per_step": rm["updates"] // args.steps,
+            "kernels_ms": {k: round(v["ms"], 3) for k, v in rm["prof"].items()}}
+        log(f"moving mesh, fp64: {vm / 1e9:.3f} G cell-updates/s, "
+            f"{rm['ms'] / args.steps:.2f} ms per step")
     if not args.no_batch and not args.no_fp32 and not args.no_learned and args.scatter == 1:
         cases = I.config_batch(128)
         ncell = sum(len(c["tets"]) for c in cases)
