@@ -54,6 +54,9 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+CELL_ORDER = 0  # internal cell order of the single-mesh runs (set from --cell-order)
+
+
 def run_form(T, torch, cfg, precision, steps, warmup, scatter, mlp=None, stats=0, time_order=1,
              motion=None):
     stream = torch.cuda.current_stream()
@@ -63,7 +66,7 @@ def run_form(T, torch, cfg, precision, steps, warmup, scatter, mlp=None, stats=0
                      guess_strength=mlp["strength"])
     s = T.Solver(device=0, hip_stream=stream.cuda_stream, max_levels=cfg["max_levels"],
                  order=cfg["order"], precision=precision, scatter=scatter, time_order=time_order,
-                 **extra)
+                 cell_order=CELL_ORDER, **extra)
     s.upload(cfg["nodes"], cfg["tets"])
     if mlp is not None:
         T.tafv_mlp_set(s.ctx, mlp["theta"])
@@ -327,6 +330,8 @@ def main():
     ap.add_argument("--no-time2", action="store_true",
                     help="skip the predictor/corrector form (second order in time)")
     ap.add_argument("--no-moving", action="store_true", help="skip the moving-mesh form")
+    ap.add_argument("--cell-order", type=int, default=0,
+                    help="internal cell order: 0 the mesh's own, 1 Morton order of the centroids")
     ap.add_argument("--batch-only", action="store_true",
                     help="only the batched form, FP64 and FP32 with the two-rarefaction start")
     ap.add_argument("--copy-probe", action="store_true",
@@ -340,6 +345,8 @@ def main():
     if args.copy_probe:
         copy_probe()
         return
+    global CELL_ORDER
+    CELL_ORDER = args.cell_order
 
     import torch
 

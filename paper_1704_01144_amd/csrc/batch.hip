@@ -486,7 +486,9 @@ __global__ __launch_bounds__(BS) void k_b_grad(const int32_t* __restrict__ tp,
                                                const BatchSched* S, int M, int grab,
                                                GradArgs<T> a) {
   constexpr int Q = BS / kUnit;
+  __shared__ T sStage[Q][kStageVals];
   const int wv = threadIdx.x / kUnit, lane = threadIdx.x % kUnit;
+  // a unit's lane 0 always has an item; the other lanes without one repeat it
   if (PERSIST) {
     STAGE_PREFIX(tp);
     const int total = s_pre[M];
@@ -495,16 +497,18 @@ __global__ __launch_bounds__(BS) void k_b_grad(const int32_t* __restrict__ tp,
       const int u = t * Q + wv;
       if (u < total) {
         int m = find_mesh(s_pre, M, u);
-        int j = (u - s_pre[m]) * kUnit + lane;
-        if (j < S[m].n_grad) grad_item<T>(a, a.list[S[m].c0 + j]);
+        int j0 = (u - s_pre[m]) * kUnit, j = j0 + lane;
+        bool valid = j < S[m].n_grad;
+        grad_item<T>(a, a.list[S[m].c0 + (valid ? j : j0)], valid, sStage[wv]);
       }
     }
   } else {
     const int u0 = xcd_block() * Q, u = u0 + wv;
     if (u >= tp[M]) return;  // no barrier follows
     int m = mesh_after(tp, find_mesh(tp, M, u0), u);
-    int j = (u - tp[m]) * kUnit + lane;
-    if (j < S[m].n_grad) grad_item<T>(a, a.list[S[m].c0 + j]);
+    int j0 = (u - tp[m]) * kUnit, j = j0 + lane;
+    bool valid = j < S[m].n_grad;
+    grad_item<T>(a, a.list[S[m].c0 + (valid ? j : j0)], valid, sStage[wv]);
   }
 }
 

@@ -5,8 +5,8 @@
 //            gradient of the primitive variables over the 4 face neighbours
 //            (mirror ghosts on the boundary), Barth-Jespersen limiter, and
 //            the reconstructed value at each of the cell's 4 face centroids
-//            (stored per half-face as [slot][variable][cell], so a face reads
-//            2 x 5 values);
+//            (stored as [slot][cell][variable], so a face reads 2 runs of 5
+//            values);
 //   k_flux   once per face colour: active faces (faster side's level <= the
 //            subiteration's level), exact Riemann flux, dt_f = 2^tau_f dt_min,
 //            and a plain read-modify-write of both cells' FP64 accumulators;
@@ -273,48 +273,17 @@ static hipError_t run_partition(hipStream_t s, int n, Key key, int K, Partition&
 // ---------------------------------------------------------------------------
 // least-squares gradient + Barth-Jespersen limiter + face reconstruction
 
-constexpr int kGradWin = 512;     // cells of the staged window
-constexpr int kGradMargin = 128;  // ids staged beyond the block's own range
-
-// The block stages the primitive states of a window of cell ids around its
-// own cells in LDS (when the window fits), so that neighbours inside it are
-// read from LDS instead of through a dependent global gather.
+// Each wave stages its face values in LDS for coalesced stores (see
+// FaceValueWriter); neighbour states are read through the global gather.
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_grad(GradArgs<T> a) {
-  __shared__ double sW[5][kGradWin];
-  __shared__ int s_lo, s_n;
+  __shared__ T sStage[kBlock / 64][kStageVals];
   const int b0 = xcd_block() * kBlock;
-  if (b0 >= a.count) return;
-  if (threadIdx.x == 0) {
-    const int bend = min(b0 + kBlock, a.count);
-    const int c0 = a.list[b0], c1 = a.list[bend - 1];
-    int lo = max(0, min(c0, c1) - kGradMargin), hi = min(a.nc - 1, max(c0, c1) + kGradMargin);
-    if (hi - lo + 1 > kGradWin) hi = lo - 1;  // too wide: no staging
-    s_lo = lo;
-    s_n = hi - lo + 1;
-  }
-  __syncthreads();
-  const int lo = s_lo, nw = s_n;
-  for (int k = threadIdx.x; k < nw; k += kBlock) {
-    double w[5];
-    cons2prim(a.U + 5 * (size_t)(lo + k), a.gm1, w);
-    for (int v = 0; v < 5; ++v) sW[v][k] = w[v];
-  }
-  __syncthreads();
   const int idx = b0 + threadIdx.x;
-  if (idx >= a.count) return;
-  const int i = a.list[idx];
-  auto fetch = [&](int n, double* t) {
-    const unsigned off = (unsigned)(n - lo);
-    if (off < (unsigned)nw) {
-      for (int v = 0; v < 5; ++v) t[v] = sW[v][off];
-    } else {
-      cons2prim(a.U + 5 * (size_t)n, a.gm1, t);
-    }
-  };
-  double wd[5];
-  fetch(i, wd);
-  grad_item_w(a, i, wd, fetch);
+  const int w0 = b0 + (threadIdx.x & ~63);  // the wave's first item
+  if (w0 >= a.count) return;                // the whole wave is past the end
+  const bool valid = idx < a.count;
+  grad_item<T>(a, a.list[valid ? idx : w0], valid, sStage[threadIdx.x >> 6]);
 }
 
 // ---------------------------------------------------------------------------

@@ -208,14 +208,47 @@ struct GradArgs {
   const double* sF;  // moving mesh: face volume rates (walls move with them)
 };
 
+// Face values are stored per slot and cell with the 5 values of a half-face
+// contiguous: Wf[(slot * nc + cell) * 5 + variable], so that the flux kernel
+// reads one short run per side.  A wave stages its 4 x 5 x 64 values in LDS
+// and then writes each slot with 5 store instructions that cover 64
+// consecutive values of the wave's (mostly consecutive) cells, instead of
+// 20 instructions whose 64 values lie 40 bytes apart.  All 64 lanes of the
+// wave take part; lanes without a cell (valid = false) compute a copy of
+// another lane's cell and store nothing.
+constexpr int kStageVals = 4 * 5 * 64;  // staging values per wave
+
+template <typename T>
+struct FaceValueWriter {
+  T* st;  // this wave's staging area, [slot][lane][variable]
+  int mine;
+  __device__ FaceValueWriter(T* stage, int i, bool valid) : st(stage), mine(valid ? i : -1) {}
+  __device__ void put(int m, int k, T v) { st[m * 320 + 5 * (threadIdx.x & 63) + k] = v; }
+  __device__ void flush(T* __restrict__ Wf, int nc) {
+    const int lane = threadIdx.x & 63;
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    for (int j = 0; j < 5; ++j) {
+      const int d = 64 * j + lane, src = d / 5, kk = d - 5 * src;
+      const int cell = __shfl(mine, src, 64);
+      if (cell < 0) continue;
+      for (int m = 0; m < 4; ++m) Wf[((size_t)m * nc + cell) * 5 + kk] = st[m * 320 + d];
+    }
+  }
+};
+
 // Least squares over the 4 face neighbours (mirror ghosts on the boundary):
 // G = sum_m c_m (W_m - W_i); Barth-Jespersen per variable k: the largest
 // psi_k <= 1 keeping W_i + psi_k G_k . r_m inside [min, max] of the cell and
 // its neighbours at all 4 face centroids r_m; output W_i + psi_k G_k . r_m.
-// nbw(n, w): the primitive state of neighbour n (from U, or staged)
+// nbw(n, w): the primitive state of neighbour n.  All 64 lanes of a wave
+// call this together (see FaceValueWriter); stage: kStageVals values.
 template <typename T, typename NbW>
-__device__ inline void grad_item_w(const GradArgs<T>& a, int i, const double* wd, NbW nbw) {
+__device__ inline void grad_item_w(const GradArgs<T>& a, int i, bool valid, const double* wd,
+                                   NbW nbw, T* stage) {
   const int nc = a.nc;
+  FaceValueWriter<T> out(stage, i, valid);
   T wi[5], dw[4][5];
   for (int k = 0; k < 5; ++k) wi[k] = (T)wd[k];
   for (int m = 0; m < 4; ++m) {
@@ -246,7 +279,6 @@ __device__ inline void grad_item_w(const GradArgs<T>& a, int i, const double* wd
       r[m][q] = a.rf[(3 * m + q) * nc + i];
       c[m][q] = a.lsq[(3 * m + q) * nc + i];
     }
-  T* __restrict__ out = a.Wf + i;  // [slot][variable][cell]
   for (int k = 0; k < 5; ++k) {
     T g0 = 0, g1 = 0, g2 = 0, hi = 0, lo = 0;
     for (int m = 0; m < 4; ++m) {
@@ -267,15 +299,17 @@ __device__ inline void grad_item_w(const GradArgs<T>& a, int i, const double* wd
       else if (d < 0) phi = lo > d ? lo * frcp(d) : (T)1;
       psi = phi < psi ? phi : psi;
     }
-    for (int m = 0; m < 4; ++m) out[(size_t)(5 * m + k) * nc] = wi[k] + psi * delta[m];
+    for (int m = 0; m < 4; ++m) out.put(m, k, wi[k] + psi * delta[m]);
   }
+  out.flush(a.Wf, nc);
 }
 
 template <typename T>
-__device__ inline void grad_item(const GradArgs<T>& a, int i) {
+__device__ inline void grad_item(const GradArgs<T>& a, int i, bool valid, T* stage) {
   double wd[5];
   cons2prim(a.U + 5 * (size_t)i, a.gm1, wd);
-  grad_item_w(a, i, wd, [&](int n, double* t) { cons2prim(a.U + 5 * (size_t)n, a.gm1, t); });
+  grad_item_w(a, i, valid, wd, [&](int n, double* t) { cons2prim(a.U + 5 * (size_t)n, a.gm1, t); },
+              stage);
 }
 
 // ---------------------------------------------------------------------------
@@ -335,9 +369,9 @@ __device__ inline void store_face_flux(const FluxArgs<T>& a, int4 r, double dt_m
 
 template <int ORDER, typename T>
 __device__ inline void load_side(const FluxArgs<T>& a, int h, T* w) {
-  if (ORDER == 2) {
-    const T* p = a.Wf + (size_t)(5 * (h & 3)) * a.nc + (h >> 2);
-    for (int k = 0; k < 5; ++k) w[k] = p[(size_t)k * a.nc];
+  if (ORDER == 2) {  // Wf[(slot * nc + cell) * 5 + variable]
+    const T* p = a.Wf + 5 * ((size_t)(h & 3) * a.nc + (h >> 2));
+    for (int k = 0; k < 5; ++k) w[k] = p[k];
   } else {
     double t[5];
     cons2prim(a.U + 5 * (size_t)(h >> 2), a.s.gas.gm1, t);
