@@ -50,7 +50,7 @@ void free_mesh(DevMesh* m) {
                   m->pc.start, m->dscal, m->dcount, m->dimpulse, m->pf.offs, m->pc.offs,
                   m->pf.scan_tmp, m->pc.scan_tmp, m->Q, m->frec, m->fkey, m->ckey, m->fpack,
                   m->perm, m->xfer, m->chist, m->rb, m->dmin, m->Q0, m->D, m->Ut,
-                  m->vol0, m->fnode, m->sF, m->Rv};
+                  m->vol0, m->fnode, m->sF, m->Rv, m->sweepf};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   delete m;
@@ -390,6 +390,7 @@ tafv_status upload_host_mesh(tafv_ctx* c, const HostMesh& hm, DevMesh** out) {
   chk(dalloc(&m->R, 5 * nc));
   chk(dalloc(&m->lev, nc));
   chk(dalloc(&m->lev2, nc));
+  chk(dalloc(&m->sweepf, kMaxLevels));
   chk(dalloc(&m->dt, nc));
   size_t wfbytes = (c->prm.precision == TAFV_FP32_FLUX ? sizeof(float) : sizeof(double)) * 20 * nc;
   if (c->prm.order == 2) chk(hipMalloc(&m->Wf, wfbytes));

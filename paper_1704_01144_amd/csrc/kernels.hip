@@ -14,7 +14,7 @@
 //            summation order;
 //   k_update cells whose level step ends: U += R / V, R = 0.
 // At every iteration start (phase 0): k_dt (per-cell time step and its
-// minimum), k_classify (levels from the dt ratio), k_sweep (neighbour
+// minimum), k_classify (levels from the dt ratio), k_sweep_inplace (neighbour
 // levels at most one apart), and three ballot-based stable partitions that
 // order faces by (colour, tau_f) and cells by tau_g / tau so that the
 // active set of any subiteration is a prefix of each list.
@@ -112,11 +112,30 @@ __global__ void k_classify(int nc, const double* __restrict__ dt, const unsigned
   lev[i] = classify_item(dt[i], dtmin, margin, L);
 }
 
-__global__ void k_sweep(int nc, const int* __restrict__ nb, const int8_t* __restrict__ src,
-                        int8_t* __restrict__ dst) {
+// One lowering sweep in place, tau_i <- min(tau_i, tau_j + 1): a neighbour
+// read while it is being lowered gives its old or its new level, both at or
+// above the final one, so the levels after L-1 sweeps are the Jacobi
+// sweeps' (the largest levels below the classification with neighbours at
+// most one apart).  A sweep that lowers nothing has reached them: the next
+// sweeps return at once (changed[k] marks sweep k lowering a level).
+__global__ void k_sweep_inplace(int nc, const int* __restrict__ nb, int8_t* lev,
+                                unsigned* changed, int k) {
+  if (k > 0 && changed[k - 1] == 0u) return;
   int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= nc) return;
-  dst[i] = sweep_item(i, nc, nb, src);
+  bool low = false;
+  if (i < nc) {
+    const int t0 = lev[i];
+    int t = t0;
+    for (int m = 0; m < 4; ++m) {
+      const int n = nb[m * nc + i];
+      if (n >= 0) t = min(t, (int)lev[n] + 1);
+    }
+    if (t < t0) {
+      lev[i] = (int8_t)t;
+      low = true;
+    }
+  }
+  if (__ballot(low) != 0ull && (threadIdx.x & 63) == 0) changed[k] = 1u;
 }
 
 // ---------------------------------------------------------------------------
@@ -513,11 +532,12 @@ hipError_t launch_dt(hipStream_t s, DevMesh& m, const StepArgs& a) {
 hipError_t launch_classify(hipStream_t s, DevMesh& m, const StepArgs& a) {
   hipLaunchKernelGGL(k_classify, dim3(blocks_for(m.nc)), dim3(kBlock), 0, s, m.nc, m.dt,
                      m.dscal, a.level_margin, m.max_levels, m.lev);
-  for (int k = 0; k < m.max_levels - 1; ++k) {
-    hipLaunchKernelGGL(k_sweep, dim3(blocks_for(m.nc)), dim3(kBlock), 0, s, m.nc, m.nb_, m.lev,
-                       m.lev2);
-    std::swap(m.lev, m.lev2);
-  }
+  if (m.max_levels > 1)
+    hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(kMaxLevels), 0, s, (int*)m.sweepf, 0,
+                       kMaxLevels);
+  for (int k = 0; k < m.max_levels - 1; ++k)
+    hipLaunchKernelGGL(k_sweep_inplace, dim3(blocks_for(m.nc)), dim3(kBlock), 0, s, m.nc, m.nb_,
+                       m.lev, m.sweepf, k);
   return hipGetLastError();
 }
 

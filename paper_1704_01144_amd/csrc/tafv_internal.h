@@ -81,7 +81,8 @@ struct DevMesh {
   double* U0 = nullptr;    // [nc][5] state of the last state_init
   double* R = nullptr;     // [nc][5]
   int8_t* lev = nullptr;   // [nc]
-  int8_t* lev2 = nullptr;  // [nc]
+  int8_t* lev2 = nullptr;  // [nc] (batched form: ping-pong sweeps)
+  unsigned* sweepf = nullptr;  // [kMaxLevels] lowering sweep k changed a level
   double* dt = nullptr;    // [nc]
   void* Wf = nullptr;      // [4][5][nc] reconstructed primitives (double or float)
   void* Q = nullptr;       // [nf][5] gather mode: face fluxes |A| F . n in the flux
