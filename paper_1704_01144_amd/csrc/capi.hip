@@ -50,7 +50,8 @@ void free_mesh(DevMesh* m) {
                   m->pc.start, m->dscal, m->dcount, m->dimpulse, m->pf.offs, m->pc.offs,
                   m->pf.scan_tmp, m->pc.scan_tmp, m->Q, m->frec, m->fkey, m->ckey, m->fpack,
                   m->perm, m->xfer, m->chist, m->rb, m->dmin, m->Q0, m->D, m->Ut,
-                  m->vol0, m->fnode, m->sF, m->Rv, m->sweepf};
+                  m->vol0, m->fnode, m->sF, m->Rv, m->sweepf, m->lkey, m->pg.list,
+                  m->pg.counts, m->pg.start, m->pg.offs, m->pg.scan_tmp};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   delete m;
@@ -148,17 +149,37 @@ tafv_status classify(tafv_ctx* c, DevMesh& m) {
   if (!(dtmin > 0.0) || !std::isfinite(dtmin))
     return fail(c, TAFV_E_NUMERIC, "no valid time step");
   m.dt_min = dtmin;
-  std::memcpy(m.hstart_f, h + 8, (K + 1) * sizeof(int32_t));
-  std::memcpy(m.hstart_c, h + 8 + kMaxKeys + 1, (kMaxLevels + 1) * sizeof(int32_t));
-  std::memcpy(m.hhist, h + 8 + kMaxKeys + kMaxLevels + 2, kMaxKeys * sizeof(int32_t));
+  std::memcpy(m.hstart_f, h + kRbFace, (K + 1) * sizeof(int32_t));
+  std::memcpy(m.hstart_c, h + kRbCell, (kMaxLevels + 1) * sizeof(int32_t));
+  std::memcpy(m.hstart_g, h + kRbGather, (kCellKeys + 1) * sizeof(int32_t));
+  std::memcpy(m.hhist, h + kRbHist, kMaxKeys * sizeof(int32_t));
   int theta = level_histogram(m);
   m.theta = theta;
   m.classified = true;
   return TAFV_OK;
 }
 
-// cells listed by tau_g: count of cells with tau_g <= g
-int cells_upto_g(const DevMesh& m, int g) { return m.hstart_c[g + 1]; }
+// cells with an active face when levels <= g start a step (tau_g <= g):
+// a prefix of the list sorted by tau_g
+CellRange cells_active(const DevMesh& m, int g) {
+  CellRange r;
+  r.n1 = m.hstart_c[g + 1];
+  return r;
+}
+
+// The gather's cells, from its own list: cells that apply their fluxes at
+// their step's start sorted by level (keys 0..7), then the others sorted by
+// tau_g (keys kMaxLevels + g).  It takes the cells with an active face
+// (those first keys up to tau_s, the others with tau_g <= tau_s) and the
+// accumulating cells whose step ends (tau <= upd, so tau_g <= upd): a cell
+// that applies at its step's start has nothing left at its end.
+CellRange cells_gather(const DevMesh& m, int tau_s, int upd) {
+  CellRange r;
+  r.n1 = m.hstart_g[tau_s + 1];
+  r.off2 = m.hstart_g[kMaxLevels];
+  r.n2 = m.hstart_g[kMaxLevels + std::max(tau_s, upd) + 1] - r.off2;
+  return r;
+}
 
 // cells with tau <= t
 int64_t cells_upto_tau(const DevMesh& m, int t) {
@@ -198,8 +219,9 @@ tafv_status subiteration2(tafv_ctx* c, DevMesh& m, const StepArgs& a, int tau_s,
   const double dt_min = m.dt_min;
   const int pcnt = m.hstart_f[tau_s + 1], ccnt = m.hstart_f[upd + 1];
   if (c->prm.order == 2) {
-    ProfScope ps(c, P_GRAD, cells_upto_g(m, tau_s));
-    HIP_TRY(c, launch_grad(c->stream, m, a, cells_upto_g(m, tau_s), m.Ut));
+    const CellRange r = cells_active(m, tau_s);
+    ProfScope ps(c, P_GRAD, r.count());
+    HIP_TRY(c, launch_grad(c->stream, m, a, r, m.Ut));
   }
   {
     ProfScope ps(c, P_FLUX, pcnt);
@@ -210,17 +232,18 @@ tafv_status subiteration2(tafv_ctx* c, DevMesh& m, const StepArgs& a, int tau_s,
     HIP_TRY(c, launch_predict(c->stream, m, tau_s, (int)s, dt_min, c->prm.precision));
   }
   if (c->prm.order == 2) {
-    ProfScope ps(c, P_GRAD, cells_upto_g(m, upd));
-    HIP_TRY(c, launch_grad(c->stream, m, a, cells_upto_g(m, upd), m.Ut));
+    const CellRange r = cells_active(m, upd);
+    ProfScope ps(c, P_GRAD, r.count());
+    HIP_TRY(c, launch_grad(c->stream, m, a, r, m.Ut));
   }
   {
     ProfScope ps(c, P_FLUX, ccnt);
     HIP_TRY(c, launch_flux(c->stream, m, a, 0, ccnt, flux_features(c, m), m.Ut, m.Q, 2, m.Q0));
   }
   {
-    ProfScope ps(c, P_GATHER, cells_upto_g(m, upd));
-    HIP_TRY(c, launch_cell_gather2(c->stream, m, cells_upto_g(m, upd), upd, dt_min,
-                                   c->prm.precision));
+    const CellRange r = cells_active(m, upd);
+    ProfScope ps(c, P_GATHER, r.count());
+    HIP_TRY(c, launch_cell_gather2(c->stream, m, r, upd, dt_min, c->prm.precision));
   }
   faces = (int64_t)pcnt + ccnt;
   return TAFV_OK;
@@ -234,9 +257,9 @@ tafv_status subiteration(tafv_ctx* c, DevMesh& m, tafv_stats* acc) {
   StepArgs a = step_args(c, m);
   int tau_s = subiteration_level((int64_t)m.phase + 1, m.theta);
   if (c->prm.order == 2 && c->prm.time_order == 1) {
-    int cnt = cells_upto_g(m, tau_s);
-    ProfScope ps(c, P_GRAD, cnt);
-    HIP_TRY(c, launch_grad(c->stream, m, a, cnt));
+    const CellRange r = cells_active(m, tau_s);
+    ProfScope ps(c, P_GRAD, r.count());
+    HIP_TRY(c, launch_grad(c->stream, m, a, r));
   }
   int64_t s = (int64_t)m.phase + 1;
   // cells whose step ends after this subiteration: tau_i <= min(theta, ctz(s))
@@ -261,9 +284,9 @@ tafv_status subiteration(tafv_ctx* c, DevMesh& m, tafv_stats* acc) {
       ProfScope ps(c, P_FLUX, cnt);
       HIP_TRY(c, launch_flux(c->stream, m, a, first, cnt, FluxFeatures{}));
     }
-    int ulist = cells_upto_g(m, upd);
-    ProfScope ps(c, P_UPDATE, ulist);
-    HIP_TRY(c, launch_update(c->stream, m, ulist, upd));
+    const CellRange r = cells_active(m, upd);
+    ProfScope ps(c, P_UPDATE, r.count());
+    HIP_TRY(c, launch_update(c->stream, m, r, upd));
   } else {
     int cnt = m.hstart_f[tau_s + 1];
     faces = cnt;
@@ -271,9 +294,9 @@ tafv_status subiteration(tafv_ctx* c, DevMesh& m, tafv_stats* acc) {
       ProfScope ps(c, P_FLUX, cnt);
       HIP_TRY(c, launch_flux(c->stream, m, a, 0, cnt, flux_features(c, m)));
     }
-    int ccnt = cells_upto_g(m, std::max(tau_s, upd));
-    ProfScope ps(c, P_GATHER, ccnt);
-    HIP_TRY(c, launch_cell_gather(c->stream, m, ccnt, tau_s, upd, m.dt_min, c->prm.precision));
+    const CellRange r = cells_gather(m, tau_s, upd);
+    ProfScope ps(c, P_GATHER, r.count());
+    HIP_TRY(c, launch_cell_gather(c->stream, m, r, tau_s, upd, m.dt_min, c->prm.precision));
   }
   m.phase = (int32_t)(s % ((int64_t)1 << m.theta));
   m.t += m.dt_min;
@@ -394,7 +417,7 @@ tafv_status upload_host_mesh(tafv_ctx* c, const HostMesh& hm, DevMesh** out) {
   chk(dalloc(&m->dt, nc));
   size_t wfbytes = (c->prm.precision == TAFV_FP32_FLUX ? sizeof(float) : sizeof(double)) * 20 * nc;
   if (c->prm.order == 2) chk(hipMalloc(&m->Wf, wfbytes));
-  for (Partition* p : {&m->pf, &m->pc}) {
+  for (Partition* p : {&m->pf, &m->pc, &m->pg}) {
     int64_t n = (p == &m->pf) ? (int64_t)nf : (int64_t)nc;
     p->scan_bytes = partition_scan_bytes(n);
     chk(hipMalloc(&p->scan_tmp, std::max<size_t>(p->scan_bytes, 16)));
@@ -415,6 +438,7 @@ tafv_status upload_host_mesh(tafv_ctx* c, const HostMesh& hm, DevMesh** out) {
   }
   chk(dalloc(&m->fkey, nf));
   chk(dalloc(&m->ckey, nc));
+  chk(dalloc(&m->lkey, nc));
   chk(dalloc(&m->fpack, nc));
   chk(dalloc(&m->perm, nc));
   chk(dalloc(&m->chist, (size_t)kCounterSlots * kMaxKeys));
@@ -830,11 +854,13 @@ tafv_status tafv_checkpoint_write(tafv_ctx* c, int32_t mesh_id, const double* co
                             hipMemcpyDeviceToHost, c->stream));
   HIP_TRY(c, hipMemcpyAsync(m->hstart_c, m->pc.start, (kMaxLevels + 1) * sizeof(int32_t),
                             hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(c, hipMemcpyAsync(m->hstart_g, m->pg.start, (kCellKeys + 1) * sizeof(int32_t),
+                            hipMemcpyDeviceToHost, c->stream));
   HIP_TRY(c, launch_pack_readback(c->stream, *m, K));
   HIP_TRY(c, hipMemcpyAsync(c->hpin, m->rb, kReadbackInts * sizeof(int32_t),
                             hipMemcpyDeviceToHost, c->stream));
   HIP_TRY(c, hipStreamSynchronize(c->stream));
-  std::memcpy(m->hhist, c->hpin + 8 + kMaxKeys + kMaxLevels + 2, kMaxKeys * sizeof(int32_t));
+  std::memcpy(m->hhist, c->hpin + kRbHist, kMaxKeys * sizeof(int32_t));
   level_histogram(*m);
   m->has_state = true;
   m->phase = phase;

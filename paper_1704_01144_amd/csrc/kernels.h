@@ -7,6 +7,13 @@
 
 namespace tafv {
 
+// The cells a launch takes from a cell list: the first n1 entries, then n2
+// entries from off2 on (see list_cell).
+struct CellRange {
+  int n1 = 0, off2 = 0, n2 = 0;
+  int count() const { return n1 + n2; }
+};
+
 // Per-launch parameters shared by the face and cell kernels.
 struct StepArgs {
   Gas gas;
@@ -25,7 +32,7 @@ hipError_t launch_classify(hipStream_t s, DevMesh& m, const StepArgs& a);
 // 0 marks none
 hipError_t launch_partitions(hipStream_t s, DevMesh& m, int early_order);
 // U: the cell states the pass reads (default: the mesh's U)
-hipError_t launch_grad(hipStream_t s, DevMesh& m, const StepArgs& a, int count,
+hipError_t launch_grad(hipStream_t s, DevMesh& m, const StepArgs& a, CellRange r,
                        const double* U = nullptr);
 // optional flux features: feat bit 0 = gate statistics and face logging,
 // bit 1 = learned guess (gamma = 1.4, gather mode)
@@ -46,9 +53,9 @@ struct FluxFeatures {
 hipError_t launch_flux(hipStream_t s, DevMesh& m, const StepArgs& a, int first, int count,
                        const FluxFeatures& ft, const double* U = nullptr, void* Q = nullptr,
                        int pass_mode = 0, const void* Qpred = nullptr);
-hipError_t launch_cell_gather(hipStream_t s, DevMesh& m, int count, int tau_s, int tau_upd,
+hipError_t launch_cell_gather(hipStream_t s, DevMesh& m, CellRange r, int tau_s, int tau_upd,
                               double dt_min, int precision);
-hipError_t launch_update(hipStream_t s, DevMesh& m, int count, int tau_upd);
+hipError_t launch_update(hipStream_t s, DevMesh& m, CellRange r, int tau_upd);
 // moving mesh: face volume rates sF from node velocities d_vel [n_nodes][3]
 hipError_t launch_face_speed(hipStream_t s, DevMesh& m, const double* d_vel);
 // one double per cell to the caller's order
@@ -60,10 +67,14 @@ hipError_t launch_vol_to_caller(hipStream_t s, DevMesh& m, const double* src, do
 // tau_upd, Q holding phi0 + phi1), ending cells applied to U and Ut
 hipError_t launch_predict(hipStream_t s, DevMesh& m, int tau_s, int sub, double dt_min,
                           int precision);
-hipError_t launch_cell_gather2(hipStream_t s, DevMesh& m, int count, int tau_upd, double dt_min,
-                               int precision);
+hipError_t launch_cell_gather2(hipStream_t s, DevMesh& m, CellRange r, int tau_upd,
+                               double dt_min, int precision);
 hipError_t launch_pack_readback(hipStream_t s, DevMesh& m, int Kf);
-constexpr int kReadbackInts = 8 + kMaxKeys + 1 + kMaxLevels + 1 + kMaxKeys;
+constexpr int kCellKeys = 2 * kMaxLevels;  // keys of the gather's cell list
+// scalars 8, face starts kMaxKeys + 1, cell starts kMaxLevels + 1, gather-list
+// starts kCellKeys + 1, the (tau_g, tau) histogram kMaxKeys
+constexpr int kRbFace = 8, kRbCell = kRbFace + kMaxKeys + 1, kRbGather = kRbCell + kMaxLevels + 1,
+              kRbHist = kRbGather + kCellKeys + 1, kReadbackInts = kRbHist + kMaxKeys;
 // host-transfer staging: rows of 5 doubles or 1 byte, caller <-> internal order
 hipError_t launch_to_caller_f64(hipStream_t s, DevMesh& m, const double* src, double* dst);
 hipError_t launch_from_caller_f64(hipStream_t s, DevMesh& m, const double* src, double* dst);

@@ -151,14 +151,18 @@ __global__ void k_face_keys(int nf, const int* __restrict__ fhL, const int* __re
 
 // cell keys, packed face words, and the histogram hist[tau_g * 8 + tau]
 // (block-local in LDS, then one atomic per bin and block)
-// cells that apply their fluxes at their step's start (kEarlyBit); order
-// 0 marks none
-__global__ __launch_bounds__(kBlock) void k_cell_early(int nc, const int* __restrict__ nb,
-                                                       const int8_t* __restrict__ lev,
-                                                       const int8_t* __restrict__ ckey,
-                                                       uint32_t* __restrict__ fpack, int order) {
+// cells that apply their fluxes at their step's start (kEarlyBit; order 0
+// marks none) and the key of the cell list: the level for those cells,
+// kMaxLevels + tau_g for the others
+__global__ __launch_bounds__(kBlock) void k_cell_list_keys(int nc, const int* __restrict__ nb,
+                                                           const int8_t* __restrict__ lev,
+                                                           const int8_t* __restrict__ ckey,
+                                                           uint32_t* __restrict__ fpack,
+                                                           int8_t* __restrict__ lkey, int order) {
   int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < nc) cell_early_item(i, nc, nb, lev, ckey, fpack, order);
+  if (i >= nc) return;
+  const bool e = cell_early_item(i, nc, nb, lev, ckey, fpack, order);
+  lkey[i] = e ? lev[i] : (int8_t)(kMaxLevels + ckey[i]);
 }
 
 __global__ __launch_bounds__(kBlock) void k_cell_keys(int nc, const int* __restrict__ nb,
@@ -183,22 +187,23 @@ __global__ __launch_bounds__(kBlock) void k_cell_keys(int nc, const int* __restr
 // starts, [8+65..] cell list starts, [8+65+9..] the (tau_g, tau) histogram
 __global__ void k_pack_readback(const unsigned long long* __restrict__ dscal,
                                 const int* __restrict__ fstart, int Kf,
-                                const int* __restrict__ cstart, const int* __restrict__ hist,
-                                int* __restrict__ out) {
+                                const int* __restrict__ cstart, const int* __restrict__ gstart,
+                                const int* __restrict__ hist, int* __restrict__ out) {
   int t = threadIdx.x;
   if (t < 6) out[t] = ((const int*)dscal)[t];
-  if (t <= Kf) out[8 + t] = fstart[t];
-  if (t <= kMaxLevels) out[8 + kMaxKeys + 1 + t] = cstart[t];
+  if (t <= Kf) out[kRbFace + t] = fstart[t];
+  if (t <= kMaxLevels) out[kRbCell + t] = cstart[t];
+  if (t <= kCellKeys) out[kRbGather + t] = gstart[t];
   if (t < kMaxKeys) {
     int sum = 0;
     for (int sl = 0; sl < kCountSlots; ++sl) sum += hist[sl * kMaxKeys + t];
-    out[8 + kMaxKeys + kMaxLevels + 2 + t] = sum;
+    out[kRbHist + t] = sum;
   }
 }
 
 hipError_t launch_pack_readback(hipStream_t s, DevMesh& m, int Kf) {
   hipLaunchKernelGGL(k_pack_readback, dim3(1), dim3(128), 0, s, m.dscal, m.pf.start, Kf,
-                     m.pc.start, m.chist, m.rb);
+                     m.pc.start, m.pg.start, m.chist, m.rb);
   return hipGetLastError();
 }
 
@@ -302,7 +307,8 @@ __global__ __launch_bounds__(kBlock) void k_grad(GradArgs<T> a) {
   const int w0 = b0 + (threadIdx.x & ~63);  // the wave's first item
   if (w0 >= a.count) return;                // the whole wave is past the end
   const bool valid = idx < a.count;
-  grad_item<T>(a, a.list[valid ? idx : w0], valid, sStage[threadIdx.x >> 6]);
+  grad_item<T>(a, list_cell(a.list, a.n1, a.off2, valid ? idx : w0), valid,
+               sStage[threadIdx.x >> 6]);
 }
 
 // ---------------------------------------------------------------------------
@@ -376,6 +382,7 @@ __global__ __launch_bounds__(kBlock) void k_flux_feat(FluxArgs<T> a) {
 
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_cell_gather(int count, const int* __restrict__ list,
+                                                        int n1, int off2,
                                                         int nc, const uint32_t* __restrict__ fpack,
                                                         const int* __restrict__ c2f,
                                                         const T* __restrict__ Q, double dt_min,
@@ -385,22 +392,24 @@ __global__ __launch_bounds__(kBlock) void k_cell_gather(int count, const int* __
                                                         int tau_upd, unsigned long long* dscal) {
   int idx = xcd_block() * kBlock + threadIdx.x;
   if (idx >= count) return;
-  if (!cell_gather_item<T>(list[idx], nc, fpack, c2f, Q, dt_min, vol, U, R, tau_s, tau_upd))
+  if (!cell_gather_item<T>(list_cell(list, n1, off2, idx), nc, fpack, c2f, Q, dt_min, vol, U, R,
+                           tau_s, tau_upd))
     atomicOr(&dscal[2], 1ull);
 }
 
 // moving mesh: the same with the swept volumes and the cell volumes
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_cell_gather_move(
-    int count, const int* __restrict__ list, int nc, const uint32_t* __restrict__ fpack,
-    const int* __restrict__ c2f, const T* __restrict__ Q, double dt_min,
-    double* __restrict__ vol, double* __restrict__ U, double* __restrict__ R, int tau_s,
+    int count, const int* __restrict__ list, int n1, int off2, int nc,
+    const uint32_t* __restrict__ fpack, const int* __restrict__ c2f, const T* __restrict__ Q,
+    double dt_min, double* __restrict__ vol, double* __restrict__ U, double* __restrict__ R,
+    int tau_s,
     int tau_upd, const double* __restrict__ sF, double* __restrict__ Rv,
     unsigned long long* dscal) {
   int idx = xcd_block() * kBlock + threadIdx.x;
   if (idx >= count) return;
-  if (!cell_gather_item<T, true>(list[idx], nc, fpack, c2f, Q, dt_min, vol, U, R, tau_s, tau_upd,
-                                 sF, Rv, vol))
+  if (!cell_gather_item<T, true>(list_cell(list, n1, off2, idx), nc, fpack, c2f, Q, dt_min, vol, U,
+                                 R, tau_s, tau_upd, sF, Rv, vol))
     atomicOr(&dscal[2], 1ull);
 }
 
@@ -438,14 +447,15 @@ __global__ __launch_bounds__(kBlock) void k_predict(int nc, const uint32_t* __re
 // predictor/corrector form: corrector sums of the listed cells
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_cell_gather2(
-    int count, const int* __restrict__ list, int nc, const uint32_t* __restrict__ fpack,
-    const int* __restrict__ c2f, const T* __restrict__ Q, double dt_min,
-    const double* __restrict__ vol, double* __restrict__ U,
+    int count, const int* __restrict__ list, int n1, int off2, int nc,
+    const uint32_t* __restrict__ fpack, const int* __restrict__ c2f, const T* __restrict__ Q,
+    double dt_min, const double* __restrict__ vol, double* __restrict__ U,
     double* __restrict__ Ut, double* __restrict__ R, int tau_upd,
     unsigned long long* dscal) {
   int idx = xcd_block() * kBlock + threadIdx.x;
   if (idx >= count) return;
-  if (!cell_gather2_item<T>(list[idx], nc, fpack, c2f, Q, dt_min, vol, U, Ut, R, tau_upd))
+  if (!cell_gather2_item<T>(list_cell(list, n1, off2, idx), nc, fpack, c2f, Q, dt_min, vol, U,
+                            Ut, R, tau_upd))
     atomicOr(&dscal[2], 1ull);
 }
 
@@ -454,13 +464,14 @@ __global__ __launch_bounds__(kBlock) void k_cell_gather2(
 // cells whose level step ends: U += R / V, R = 0
 
 __global__ __launch_bounds__(kBlock) void k_update(int count, const int* __restrict__ list,
+                                                   int n1, int off2,
                                                    const int8_t* __restrict__ lev, int tau_upd,
                                                    const double* __restrict__ vol,
                                                    double* __restrict__ U, double* __restrict__ R,
                                                    unsigned long long* dscal) {
   int idx = xcd_block() * kBlock + threadIdx.x;
   if (idx >= count) return;
-  int i = list[idx];
+  int i = list_cell(list, n1, off2, idx);
   if (lev[i] > tau_upd) return;
   double v = vol[i];
   bool bad = false;
@@ -551,11 +562,13 @@ hipError_t launch_partitions(hipStream_t s, DevMesh& m, int early_order) {
   hipLaunchKernelGGL(k_cell_keys, dim3(blocks_for(m.nc)), dim3(kBlock), 0, s, m.nc, m.nb_, m.lev,
                      m.ckey, m.fpack, m.chist);
   if (early_order)
-    hipLaunchKernelGGL(k_cell_early, dim3(blocks_for(m.nc)), dim3(kBlock), 0, s, m.nc, m.nb_,
-                       m.lev, m.ckey, m.fpack, early_order);
+    hipLaunchKernelGGL(k_cell_list_keys, dim3(blocks_for(m.nc)), dim3(kBlock), 0, s, m.nc, m.nb_,
+                       m.lev, m.ckey, m.fpack, m.lkey, early_order);
   hipError_t e = run_partition(s, m.nf, ByteKey{m.fkey}, Kf, m.pf, FaceWriter{m.frec, m.fhL, m.fhR});
   if (e != hipSuccess) return e;
-  return run_partition(s, m.nc, ByteKey{m.ckey}, kMaxLevels, m.pc, IndexWriter{m.pc.list});
+  e = run_partition(s, m.nc, ByteKey{m.ckey}, kMaxLevels, m.pc, IndexWriter{m.pc.list});
+  if (e != hipSuccess || !early_order) return e;  // the gather's list serves time order 1 only
+  return run_partition(s, m.nc, ByteKey{m.lkey}, kCellKeys, m.pg, IndexWriter{m.pg.list});
 }
 
 template <typename T>
@@ -597,17 +610,20 @@ hipError_t launch_from_caller_i8(hipStream_t s, DevMesh& m, const int8_t* src, i
   return rows_from_caller<int8_t>(s, m, 1, src, dst);
 }
 
-hipError_t launch_grad(hipStream_t s, DevMesh& m, const StepArgs& a, int count,
+hipError_t launch_grad(hipStream_t s, DevMesh& m, const StepArgs& a, CellRange r,
                        const double* U) {
+  const int count = r.count();
   if (count <= 0) return hipSuccess;
   if (!U) U = m.U;
   if (a.precision == TAFV_FP32_FLUX) {
     GradArgs<float> g{m.pc.list, count, m.nc, m.nf, U, m.nb_, m.lsq32, m.rf32, m.fA,
-                      (float*)m.Wf, a.gas.gm1, a.boundary, m.moving ? m.sF : nullptr};
+                      (float*)m.Wf, a.gas.gm1, a.boundary, m.moving ? m.sF : nullptr,
+                      r.n1, r.off2};
     hipLaunchKernelGGL(k_grad<float>, dim3(blocks_for(count)), dim3(kBlock), 0, s, g);
   } else {
     GradArgs<double> g{m.pc.list, count, m.nc, m.nf, U, m.nb_, m.lsq, m.rf, m.fA,
-                       (double*)m.Wf, a.gas.gm1, a.boundary, m.moving ? m.sF : nullptr};
+                       (double*)m.Wf, a.gas.gm1, a.boundary, m.moving ? m.sF : nullptr,
+                       r.n1, r.off2};
     hipLaunchKernelGGL(k_grad<double>, dim3(blocks_for(count)), dim3(kBlock), 0, s, g);
   }
   return hipGetLastError();
@@ -675,28 +691,31 @@ hipError_t launch_flux(hipStream_t s, DevMesh& m, const StepArgs& a, int first, 
   return hipGetLastError();
 }
 
-hipError_t launch_cell_gather(hipStream_t s, DevMesh& m, int count, int tau_s, int tau_upd,
+hipError_t launch_cell_gather(hipStream_t s, DevMesh& m, CellRange r, int tau_s, int tau_upd,
                               double dt_min, int precision) {
+  const int count = r.count();
   if (count <= 0) return hipSuccess;
   if (m.moving) {
     if (precision == TAFV_FP32_FLUX)
       hipLaunchKernelGGL(k_cell_gather_move<float>, dim3(blocks_for(count)), dim3(kBlock), 0, s,
-                         count, m.pc.list, m.nc, m.fpack, m.c2f, (const float*)m.Q, dt_min,
-                         m.vol, m.U, m.R, tau_s, tau_upd, m.sF, m.Rv, m.dscal);
+                         count, m.pg.list, r.n1, r.off2, m.nc, m.fpack, m.c2f,
+                         (const float*)m.Q, dt_min, m.vol, m.U, m.R, tau_s, tau_upd, m.sF, m.Rv,
+                         m.dscal);
     else
       hipLaunchKernelGGL(k_cell_gather_move<double>, dim3(blocks_for(count)), dim3(kBlock), 0, s,
-                         count, m.pc.list, m.nc, m.fpack, m.c2f, (const double*)m.Q, dt_min,
-                         m.vol, m.U, m.R, tau_s, tau_upd, m.sF, m.Rv, m.dscal);
+                         count, m.pg.list, r.n1, r.off2, m.nc, m.fpack, m.c2f,
+                         (const double*)m.Q, dt_min, m.vol, m.U, m.R, tau_s, tau_upd, m.sF, m.Rv,
+                         m.dscal);
     return hipGetLastError();
   }
   if (precision == TAFV_FP32_FLUX)
     hipLaunchKernelGGL(k_cell_gather<float>, dim3(blocks_for(count)), dim3(kBlock), 0, s, count,
-                       m.pc.list, m.nc, m.fpack, m.c2f, (const float*)m.Q, dt_min, m.vol, m.U,
-                       m.R, tau_s, tau_upd, m.dscal);
+                       m.pg.list, r.n1, r.off2, m.nc, m.fpack, m.c2f, (const float*)m.Q, dt_min,
+                       m.vol, m.U, m.R, tau_s, tau_upd, m.dscal);
   else
     hipLaunchKernelGGL(k_cell_gather<double>, dim3(blocks_for(count)), dim3(kBlock), 0, s, count,
-                       m.pc.list, m.nc, m.fpack, m.c2f, (const double*)m.Q, dt_min, m.vol, m.U,
-                       m.R, tau_s, tau_upd, m.dscal);
+                       m.pg.list, r.n1, r.off2, m.nc, m.fpack, m.c2f, (const double*)m.Q, dt_min,
+                       m.vol, m.U, m.R, tau_s, tau_upd, m.dscal);
   return hipGetLastError();
 }
 
@@ -714,17 +733,18 @@ hipError_t launch_predict(hipStream_t s, DevMesh& m, int tau_s, int sub, double 
   return hipGetLastError();
 }
 
-hipError_t launch_cell_gather2(hipStream_t s, DevMesh& m, int count, int tau_upd, double dt_min,
-                               int precision) {
+hipError_t launch_cell_gather2(hipStream_t s, DevMesh& m, CellRange r, int tau_upd,
+                               double dt_min, int precision) {
+  const int count = r.count();
   if (count <= 0) return hipSuccess;
   if (precision == TAFV_FP32_FLUX)
     hipLaunchKernelGGL(k_cell_gather2<float>, dim3(blocks_for(count)), dim3(kBlock), 0, s,
-                       count, m.pc.list, m.nc, m.fpack, m.c2f, (const float*)m.Q, dt_min,
-                       m.vol, m.U, m.Ut, m.R, tau_upd, m.dscal);
+                       count, m.pc.list, r.n1, r.off2, m.nc, m.fpack, m.c2f, (const float*)m.Q,
+                       dt_min, m.vol, m.U, m.Ut, m.R, tau_upd, m.dscal);
   else
     hipLaunchKernelGGL(k_cell_gather2<double>, dim3(blocks_for(count)), dim3(kBlock), 0, s,
-                       count, m.pc.list, m.nc, m.fpack, m.c2f, (const double*)m.Q, dt_min,
-                       m.vol, m.U, m.Ut, m.R, tau_upd, m.dscal);
+                       count, m.pc.list, r.n1, r.off2, m.nc, m.fpack, m.c2f, (const double*)m.Q,
+                       dt_min, m.vol, m.U, m.Ut, m.R, tau_upd, m.dscal);
   return hipGetLastError();
 }
 
@@ -739,10 +759,11 @@ hipError_t launch_vol_to_caller(hipStream_t s, DevMesh& m, const double* src, do
   return rows_to_caller<double>(s, m, 1, src, dst);
 }
 
-hipError_t launch_update(hipStream_t s, DevMesh& m, int count, int tau_upd) {
+hipError_t launch_update(hipStream_t s, DevMesh& m, CellRange r, int tau_upd) {
+  const int count = r.count();
   if (count <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_update, dim3(blocks_for(count)), dim3(kBlock), 0, s, count, m.pc.list,
-                     m.lev, tau_upd, m.vol, m.U, m.R, m.dscal);
+                     r.n1, r.off2, m.lev, tau_upd, m.vol, m.U, m.R, m.dscal);
   return hipGetLastError();
 }
 

@@ -139,10 +139,11 @@ __device__ inline int cell_key_item(int i, int nc, const int* __restrict__ nb,
 // applying the sum at the end.
 constexpr uint32_t kEarlyBit = 1u << 24;
 
-__device__ inline void cell_early_item(int i, int nc, const int* __restrict__ nb,
+__device__ inline bool cell_early_item(int i, int nc, const int* __restrict__ nb,
                                        const int8_t* __restrict__ lev,
                                        const int8_t* __restrict__ ckey,
                                        uint32_t* __restrict__ fpack, int order) {
+  if (order == 0) return false;
   const int t = lev[i];
   bool e = ckey[i] == t;
   if (e && order == 2)
@@ -151,6 +152,16 @@ __device__ inline void cell_early_item(int i, int nc, const int* __restrict__ nb
       if (n >= 0 && ckey[n] < t) e = false;
     }
   if (e) fpack[i] |= kEarlyBit;
+  return e;
+}
+
+// The gather's cell list (single-mesh form) holds first the cells of
+// kEarlyBit sorted by their level (keys 0..7), then the others sorted by
+// tau_g (keys 8..15); the other cell list is sorted by tau_g alone.  A launch
+// takes the first n1 entries and the entries from off2 on: item idx is
+// list[idx] for idx < n1, else list[off2 + idx - n1].
+__device__ inline int list_cell(const int* __restrict__ list, int n1, int off2, int idx) {
+  return idx < n1 ? list[idx] : list[off2 + (idx - n1)];
 }
 
 // h[bin] += 1 for every active lane, one LDS atomic per distinct bin of the
@@ -206,6 +217,7 @@ struct GradArgs {
   double gm1;
   int boundary;
   const double* sF;  // moving mesh: face volume rates (walls move with them)
+  int n1, off2;      // the items are list[0, n1) then list[off2, ...) (see list_cell)
 };
 
 // Face values are stored per slot and cell with the 5 values of a half-face

@@ -101,9 +101,11 @@ struct DevMesh {
   double* Ut = nullptr;    // [nc][5] cell states at the time the next face pass reads
   int4* frec = nullptr;    // [nf] face records {f, hL, hR, tau_f} in partition order
   // schedule lists
-  Partition pf, pc;        // faces by (colour, tau_f); cells by tau_g
+  Partition pf, pc, pg;    // faces by (colour, tau_f); cells by tau_g; the gather's
+                           // cell list (see cells_gather)
   int8_t* fkey = nullptr;  // [nf] partition key of each face
   int8_t* ckey = nullptr;  // [nc] tau_g of each cell
+  int8_t* lkey = nullptr;  // [nc] key of the gather's cell list (see list_cell)
   int* chist = nullptr;    // [kCounterSlots][64] cell count per (tau_g, tau), summed
                            // over the slots by the readback kernel
   int* rb = nullptr;       // packed readback buffer
@@ -124,6 +126,7 @@ struct DevMesh {
   double dt_min = 0.0, t = 0.0;
   int32_t hstart_f[kMaxKeys + 1] = {0};
   int32_t hstart_c[kMaxLevels + 1] = {0};
+  int32_t hstart_g[2 * kMaxLevels + 1] = {0};  // starts of the gather list's keys
   int32_t hhist[kMaxKeys] = {0};
   bool classified = false;
   tafv_stats st{};
