@@ -167,17 +167,16 @@ CellRange cells_active(const DevMesh& m, int g) {
   return r;
 }
 
-// The gather's cells, from its own list: cells that apply their fluxes at
-// their step's start sorted by level (keys 0..7), then the others sorted by
-// tau_g (keys kMaxLevels + g).  It takes the cells with an active face
-// (those first keys up to tau_s, the others with tau_g <= tau_s) and the
-// accumulating cells whose step ends (tau <= upd, so tau_g <= upd): a cell
-// that applies at its step's start has nothing left at its end.
-CellRange cells_gather(const DevMesh& m, int tau_s, int upd) {
-  CellRange r;
-  r.n1 = m.hstart_g[tau_s + 1];
-  r.off2 = m.hstart_g[kMaxLevels];
-  r.n2 = m.hstart_g[kMaxLevels + std::max(tau_s, upd) + 1] - r.off2;
+// The gather's cells, from its own list sorted by 2 k + b (k = the level of
+// a cell that applies its fluxes at its step's start, b = 0; k = tau_g of
+// the others, b = 1): the cells with an active face (keys up to 2 tau_s + 1)
+// and the accumulating cells whose step ends (tau <= upd, so tau_g <= upd:
+// keys 2 k + 1 for tau_s < k <= upd); a cell that applies at its step's
+// start has nothing left at its end.
+ListRanges cells_gather(const DevMesh& m, int tau_s, int upd) {
+  ListRanges r;
+  r.add(0, m.hstart_g[2 * tau_s + 2]);
+  for (int k = tau_s + 1; k <= upd; ++k) r.add(m.hstart_g[2 * k + 1], m.hstart_g[2 * k + 2]);
   return r;
 }
 
@@ -294,7 +293,7 @@ tafv_status subiteration(tafv_ctx* c, DevMesh& m, tafv_stats* acc) {
       ProfScope ps(c, P_FLUX, cnt);
       HIP_TRY(c, launch_flux(c->stream, m, a, 0, cnt, flux_features(c, m)));
     }
-    const CellRange r = cells_gather(m, tau_s, upd);
+    const ListRanges r = cells_gather(m, tau_s, upd);
     ProfScope ps(c, P_GATHER, r.count());
     HIP_TRY(c, launch_cell_gather(c->stream, m, r, tau_s, upd, m.dt_min, c->prm.precision));
   }

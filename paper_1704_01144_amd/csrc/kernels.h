@@ -14,6 +14,25 @@ struct CellRange {
   int count() const { return n1 + n2; }
 };
 
+// Up to kMaxLevels + 1 ranges of a cell list: range r holds items
+// cum[r] .. cum[r + 1] - 1, at list[off[r] + item - cum[r]] (see range_cell).
+struct ListRanges {
+  int n = 0;
+  int off[kMaxLevels + 1] = {0};
+  int cum[kMaxLevels + 2] = {0};
+  void add(int a, int b) {  // entries [a, b) of the list
+    if (b <= a) return;
+    if (n > 0 && off[n - 1] + (cum[n] - cum[n - 1]) == a) {
+      cum[n] += b - a;  // continues the previous range
+      return;
+    }
+    off[n] = a;
+    cum[n + 1] = cum[n] + (b - a);
+    ++n;
+  }
+  int count() const { return cum[n]; }
+};
+
 // Per-launch parameters shared by the face and cell kernels.
 struct StepArgs {
   Gas gas;
@@ -53,8 +72,8 @@ struct FluxFeatures {
 hipError_t launch_flux(hipStream_t s, DevMesh& m, const StepArgs& a, int first, int count,
                        const FluxFeatures& ft, const double* U = nullptr, void* Q = nullptr,
                        int pass_mode = 0, const void* Qpred = nullptr);
-hipError_t launch_cell_gather(hipStream_t s, DevMesh& m, CellRange r, int tau_s, int tau_upd,
-                              double dt_min, int precision);
+hipError_t launch_cell_gather(hipStream_t s, DevMesh& m, const ListRanges& r, int tau_s,
+                              int tau_upd, double dt_min, int precision);
 hipError_t launch_update(hipStream_t s, DevMesh& m, CellRange r, int tau_upd);
 // moving mesh: face volume rates sF from node velocities d_vel [n_nodes][3]
 hipError_t launch_face_speed(hipStream_t s, DevMesh& m, const double* d_vel);

@@ -152,8 +152,8 @@ __global__ void k_face_keys(int nf, const int* __restrict__ fhL, const int* __re
 // cell keys, packed face words, and the histogram hist[tau_g * 8 + tau]
 // (block-local in LDS, then one atomic per bin and block)
 // cells that apply their fluxes at their step's start (kEarlyBit; order 0
-// marks none) and the key of the cell list: the level for those cells,
-// kMaxLevels + tau_g for the others
+// marks none) and the key of the gather's cell list: 2 tau for those cells,
+// 2 tau_g + 1 for the others
 __global__ __launch_bounds__(kBlock) void k_cell_list_keys(int nc, const int* __restrict__ nb,
                                                            const int8_t* __restrict__ lev,
                                                            const int8_t* __restrict__ ckey,
@@ -162,7 +162,7 @@ __global__ __launch_bounds__(kBlock) void k_cell_list_keys(int nc, const int* __
   int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= nc) return;
   const bool e = cell_early_item(i, nc, nb, lev, ckey, fpack, order);
-  lkey[i] = e ? lev[i] : (int8_t)(kMaxLevels + ckey[i]);
+  lkey[i] = (int8_t)(e ? 2 * lev[i] : 2 * ckey[i] + 1);
 }
 
 __global__ __launch_bounds__(kBlock) void k_cell_keys(int nc, const int* __restrict__ nb,
@@ -382,7 +382,7 @@ __global__ __launch_bounds__(kBlock) void k_flux_feat(FluxArgs<T> a) {
 
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_cell_gather(int count, const int* __restrict__ list,
-                                                        int n1, int off2,
+                                                        ListRanges rg,
                                                         int nc, const uint32_t* __restrict__ fpack,
                                                         const int* __restrict__ c2f,
                                                         const T* __restrict__ Q, double dt_min,
@@ -392,7 +392,7 @@ __global__ __launch_bounds__(kBlock) void k_cell_gather(int count, const int* __
                                                         int tau_upd, unsigned long long* dscal) {
   int idx = xcd_block() * kBlock + threadIdx.x;
   if (idx >= count) return;
-  if (!cell_gather_item<T>(list_cell(list, n1, off2, idx), nc, fpack, c2f, Q, dt_min, vol, U, R,
+  if (!cell_gather_item<T>(range_cell(list, rg, idx), nc, fpack, c2f, Q, dt_min, vol, U, R,
                            tau_s, tau_upd))
     atomicOr(&dscal[2], 1ull);
 }
@@ -400,7 +400,7 @@ __global__ __launch_bounds__(kBlock) void k_cell_gather(int count, const int* __
 // moving mesh: the same with the swept volumes and the cell volumes
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_cell_gather_move(
-    int count, const int* __restrict__ list, int n1, int off2, int nc,
+    int count, const int* __restrict__ list, ListRanges rg, int nc,
     const uint32_t* __restrict__ fpack, const int* __restrict__ c2f, const T* __restrict__ Q,
     double dt_min, double* __restrict__ vol, double* __restrict__ U, double* __restrict__ R,
     int tau_s,
@@ -408,7 +408,7 @@ __global__ __launch_bounds__(kBlock) void k_cell_gather_move(
     unsigned long long* dscal) {
   int idx = xcd_block() * kBlock + threadIdx.x;
   if (idx >= count) return;
-  if (!cell_gather_item<T, true>(list_cell(list, n1, off2, idx), nc, fpack, c2f, Q, dt_min, vol, U,
+  if (!cell_gather_item<T, true>(range_cell(list, rg, idx), nc, fpack, c2f, Q, dt_min, vol, U,
                                  R, tau_s, tau_upd, sF, Rv, vol))
     atomicOr(&dscal[2], 1ull);
 }
@@ -691,30 +691,30 @@ hipError_t launch_flux(hipStream_t s, DevMesh& m, const StepArgs& a, int first, 
   return hipGetLastError();
 }
 
-hipError_t launch_cell_gather(hipStream_t s, DevMesh& m, CellRange r, int tau_s, int tau_upd,
-                              double dt_min, int precision) {
+hipError_t launch_cell_gather(hipStream_t s, DevMesh& m, const ListRanges& r, int tau_s,
+                              int tau_upd, double dt_min, int precision) {
   const int count = r.count();
   if (count <= 0) return hipSuccess;
   if (m.moving) {
     if (precision == TAFV_FP32_FLUX)
       hipLaunchKernelGGL(k_cell_gather_move<float>, dim3(blocks_for(count)), dim3(kBlock), 0, s,
-                         count, m.pg.list, r.n1, r.off2, m.nc, m.fpack, m.c2f,
+                         count, m.pg.list, r, m.nc, m.fpack, m.c2f,
                          (const float*)m.Q, dt_min, m.vol, m.U, m.R, tau_s, tau_upd, m.sF, m.Rv,
                          m.dscal);
     else
       hipLaunchKernelGGL(k_cell_gather_move<double>, dim3(blocks_for(count)), dim3(kBlock), 0, s,
-                         count, m.pg.list, r.n1, r.off2, m.nc, m.fpack, m.c2f,
+                         count, m.pg.list, r, m.nc, m.fpack, m.c2f,
                          (const double*)m.Q, dt_min, m.vol, m.U, m.R, tau_s, tau_upd, m.sF, m.Rv,
                          m.dscal);
     return hipGetLastError();
   }
   if (precision == TAFV_FP32_FLUX)
     hipLaunchKernelGGL(k_cell_gather<float>, dim3(blocks_for(count)), dim3(kBlock), 0, s, count,
-                       m.pg.list, r.n1, r.off2, m.nc, m.fpack, m.c2f, (const float*)m.Q, dt_min,
+                       m.pg.list, r, m.nc, m.fpack, m.c2f, (const float*)m.Q, dt_min,
                        m.vol, m.U, m.R, tau_s, tau_upd, m.dscal);
   else
     hipLaunchKernelGGL(k_cell_gather<double>, dim3(blocks_for(count)), dim3(kBlock), 0, s, count,
-                       m.pg.list, r.n1, r.off2, m.nc, m.fpack, m.c2f, (const double*)m.Q, dt_min,
+                       m.pg.list, r, m.nc, m.fpack, m.c2f, (const double*)m.Q, dt_min,
                        m.vol, m.U, m.R, tau_s, tau_upd, m.dscal);
   return hipGetLastError();
 }

@@ -155,13 +155,20 @@ __device__ inline bool cell_early_item(int i, int nc, const int* __restrict__ nb
   return e;
 }
 
-// The gather's cell list (single-mesh form) holds first the cells of
-// kEarlyBit sorted by their level (keys 0..7), then the others sorted by
-// tau_g (keys 8..15); the other cell list is sorted by tau_g alone.  A launch
-// takes the first n1 entries and the entries from off2 on: item idx is
-// list[idx] for idx < n1, else list[off2 + idx - n1].
+// A launch over the first n1 entries of a cell list and the entries from
+// off2 on: item idx is list[idx] for idx < n1, else list[off2 + idx - n1].
 __device__ inline int list_cell(const int* __restrict__ list, int n1, int off2, int idx) {
   return idx < n1 ? list[idx] : list[off2 + (idx - n1)];
+}
+
+// The gather's cell list (single-mesh form) is sorted by the key 2 k + b:
+// k = the level for a cell of kEarlyBit (b = 0), k = tau_g for the others
+// (b = 1).  Its cells keep the spatial order of the tau_g list, and a launch
+// takes a few ranges of it (ListRanges): item idx of range r.
+__device__ inline int range_cell(const int* __restrict__ list, const ListRanges& R, int idx) {
+  int r = 0;
+  while (r + 1 < R.n && idx >= R.cum[r + 1]) ++r;
+  return list[R.off[r] + (idx - R.cum[r])];
 }
 
 // h[bin] += 1 for every active lane, one LDS atomic per distinct bin of the
