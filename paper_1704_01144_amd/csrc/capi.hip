@@ -416,7 +416,7 @@ tafv_status upload_host_mesh(tafv_ctx* c, const HostMesh& hm, DevMesh** out) {
   chk(dalloc(&m->dt, nc));
   size_t wfbytes = (c->prm.precision == TAFV_FP32_FLUX ? sizeof(float) : sizeof(double)) * 20 * nc;
   if (c->prm.order == 2) chk(hipMalloc(&m->Wf, wfbytes));
-  for (Partition* p : {&m->pf, &m->pc, &m->pg}) {
+  for (Partition* p : {&m->pf, &m->pc}) {  // the gather's list is scanned with the tau_g list
     int64_t n = (p == &m->pf) ? (int64_t)nf : (int64_t)nc;
     p->scan_bytes = partition_scan_bytes(n);
     chk(hipMalloc(&p->scan_tmp, std::max<size_t>(p->scan_bytes, 16)));
@@ -425,6 +425,8 @@ tafv_status upload_host_mesh(tafv_ctx* c, const HostMesh& hm, DevMesh** out) {
     chk(dalloc(&p->counts, (size_t)kMaxKeys * partition_blocks(n)));
     chk(dalloc(&p->start, kMaxKeys + 1));
   }
+  chk(dalloc(&m->pg.list, nc));
+  chk(dalloc(&m->pg.start, kMaxKeys + 1));
   chk(dalloc(&m->frec, nf));
   if (m->scatter == TAFV_SCATTER_GATHER)
     chk(hipMalloc(&m->Q, (c->prm.precision == TAFV_FP32_FLUX ? sizeof(float) : sizeof(double)) *

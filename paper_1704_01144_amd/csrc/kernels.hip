@@ -212,64 +212,88 @@ __global__ void k_fill_i32(int* p, int v, int n) {
   if (i < n) p[i] = v;
 }
 
+// Stable partitions of an index range [0, n) by byte keys.  Blocks of
+// kPartChunk items count their keys into counts[key][block], one exclusive
+// scan turns the counts into slots, and the scatter writes each item at its
+// slot, so the items of one key keep their index order.  Two keys over the
+// same range (the two cell lists) share one pass: the second key's counts
+// follow the first's ([K1 + K2][nblocks]) and its slots therefore start at n.
+
+// adds one wave's keys (k_mine < 0: no item) to the block's counters
+__device__ inline void wave_count_keys(int* cnt, bool valid, int k_mine) {
+  const int lane = threadIdx.x & 63;
+  unsigned long long pending = __ballot(valid);
+  while (pending) {
+    int leader = __ffsll(pending) - 1;
+    int k = __shfl(k_mine, leader, 64);
+    unsigned long long m = __ballot(k_mine == k);
+    if (lane == leader) cnt[k] += __popcll(m);
+    pending &= ~m;
+  }
+}
+
+// writes one wave's items at base[key] onwards in lane order; the writer is
+// given the slot less pofs and the key less kofs
+template <typename Writer>
+__device__ inline void wave_scatter_keys(int* base, bool valid, int k_mine, int i, int kofs,
+                                         int pofs, const Writer& out) {
+  const int lane = threadIdx.x & 63;
+  const unsigned long long lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+  unsigned long long pending = __ballot(valid);
+  while (pending) {
+    int leader = __ffsll(pending) - 1;
+    int k = __shfl(k_mine, leader, 64);
+    unsigned long long m = __ballot(k_mine == k);
+    int b0 = base[k];
+    if (k_mine == k) out(b0 + __popcll(m & lt) - pofs, i, k - kofs);
+    __syncthreads();
+    if (lane == leader) base[k] = b0 + __popcll(m);
+    __syncthreads();
+    pending &= ~m;
+  }
+}
+
 template <typename Key>
-__global__ __launch_bounds__(64) void k_part_count(int n, Key key, int K, int nblocks,
-                                                   int* __restrict__ counts) {
+__global__ __launch_bounds__(64) void k_part_count(int n, Key key1, int K1, Key key2, int K2,
+                                                   int nblocks, int* __restrict__ counts) {
   __shared__ int cnt[kMaxKeys];
-  int lane = threadIdx.x;
+  const int lane = threadIdx.x, K = K1 + K2;
   for (int k = lane; k < K; k += 64) cnt[k] = 0;
   __syncthreads();
-  int base = blockIdx.x * kPartChunk;
+  const int first = blockIdx.x * kPartChunk;
   for (int step = 0; step < kPartChunk / 64; ++step) {
-    int i = base + step * 64 + lane;
-    bool valid = i < n;
-    int k_mine = valid ? key(i) : -1;
-    unsigned long long pending = __ballot(valid);
-    while (pending) {
-      int leader = __ffsll(pending) - 1;
-      int k = __shfl(k_mine, leader, 64);
-      unsigned long long m = __ballot(k_mine == k);
-      if (lane == leader) cnt[k] += __popcll(m);
-      pending &= ~m;
-    }
+    const int i = first + step * 64 + lane;
+    const bool valid = i < n;
+    wave_count_keys(cnt, valid, valid ? key1(i) : -1);
+    if (K2 > 0) wave_count_keys(cnt, valid, valid ? K1 + key2(i) : -1);
   }
   __syncthreads();
   for (int k = lane; k < K; k += 64) counts[k * nblocks + blockIdx.x] = cnt[k];
 }
 
-// start[k] = first slot of key k (offsets are scanned in (key, block) order)
-__global__ void k_part_starts(int K, int nblocks, int n, const int* __restrict__ offs,
-                              int* __restrict__ start) {
-  int k = threadIdx.x;
-  if (k < K) start[k] = offs[k * nblocks];
-  if (k == K) start[K] = n;
-}
-
-template <typename Key, typename Writer>
-__global__ __launch_bounds__(64) void k_part_scatter(int n, Key key, int K, int nblocks,
-                                                     const int* __restrict__ offs, Writer out) {
+// Block 0 also writes each list's key starts (start[k] = first slot of key
+// k, start[K] = n), which the host reads back.
+template <typename Key, typename W1, typename W2>
+__global__ __launch_bounds__(64) void k_part_scatter(int n, Key key1, int K1, W1 out1,
+                                                     int* __restrict__ start1, Key key2, int K2,
+                                                     W2 out2, int* __restrict__ start2,
+                                                     int nblocks, const int* __restrict__ offs) {
   __shared__ int base[kMaxKeys];
-  int lane = threadIdx.x;
+  const int lane = threadIdx.x, K = K1 + K2;
   for (int k = lane; k < K; k += 64) base[k] = offs[k * nblocks + blockIdx.x];
+  if (blockIdx.x == 0) {
+    for (int k = lane; k < K1; k += 64) start1[k] = offs[k * nblocks];
+    for (int k = lane; k < K2; k += 64) start2[k] = offs[(K1 + k) * nblocks] - n;
+    if (lane == 0) start1[K1] = n;
+    if (lane == 0 && K2 > 0) start2[K2] = n;
+  }
   __syncthreads();
-  unsigned long long lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-  int first = blockIdx.x * kPartChunk;
+  const int first = blockIdx.x * kPartChunk;
   for (int step = 0; step < kPartChunk / 64; ++step) {
-    int i = first + step * 64 + lane;
-    bool valid = i < n;
-    int k_mine = valid ? key(i) : -1;
-    unsigned long long pending = __ballot(valid);
-    while (pending) {
-      int leader = __ffsll(pending) - 1;
-      int k = __shfl(k_mine, leader, 64);
-      unsigned long long m = __ballot(k_mine == k);
-      int b0 = base[k];
-      if (k_mine == k) out(b0 + __popcll(m & lt), i, k);
-      __syncthreads();
-      if (lane == leader) base[k] = b0 + __popcll(m);
-      __syncthreads();
-      pending &= ~m;
-    }
+    const int i = first + step * 64 + lane;
+    const bool valid = i < n;
+    wave_scatter_keys(base, valid, valid ? key1(i) : -1, i, 0, 0, out1);
+    if (K2 > 0) wave_scatter_keys(base, valid, valid ? K1 + key2(i) : -1, i, K1, n, out2);
   }
 }
 
@@ -281,16 +305,22 @@ size_t partition_scan_bytes(int64_t n) {
   return bytes;
 }
 
-template <typename Key, typename Writer>
-static hipError_t run_partition(hipStream_t s, int n, Key key, int K, Partition& p, Writer w) {
-  int nb = partition_blocks(n);
-  hipLaunchKernelGGL(k_part_count<Key>, dim3(nb), dim3(64), 0, s, n, key, K, nb, p.counts);
-  size_t bytes = p.scan_bytes;
-  hipError_t e = hipcub::DeviceScan::ExclusiveSum(p.scan_tmp, bytes, p.counts, p.offs, K * nb, s);
+// One key (K2 = 0) or two keys over the same range; the scan runs in p1's
+// scratch, whose counts hold kMaxKeys >= K1 + K2 keys per block.
+template <typename W1, typename W2 = IndexWriter>
+static hipError_t run_partition(hipStream_t s, int n, Partition& p1, ByteKey key1, int K1, W1 out1,
+                                Partition* p2 = nullptr, ByteKey key2 = {nullptr}, int K2 = 0,
+                                W2 out2 = {nullptr}) {
+  if (K1 + K2 > kMaxKeys || (K2 > 0 && !p2)) return hipErrorInvalidValue;
+  const int nb = partition_blocks(n);
+  hipLaunchKernelGGL(k_part_count<ByteKey>, dim3(nb), dim3(64), 0, s, n, key1, K1, key2, K2, nb,
+                     p1.counts);
+  size_t bytes = p1.scan_bytes;
+  hipError_t e =
+      hipcub::DeviceScan::ExclusiveSum(p1.scan_tmp, bytes, p1.counts, p1.offs, (K1 + K2) * nb, s);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_part_starts, dim3(1), dim3(kMaxKeys + 1), 0, s, K, nb, n, p.offs, p.start);
-  hipLaunchKernelGGL((k_part_scatter<Key, Writer>), dim3(nb), dim3(64), 0, s, n, key, K, nb,
-                     p.offs, w);
+  hipLaunchKernelGGL((k_part_scatter<ByteKey, W1, W2>), dim3(nb), dim3(64), 0, s, n, key1, K1,
+                     out1, p1.start, key2, K2, out2, p2 ? p2->start : nullptr, nb, p1.offs);
   return hipGetLastError();
 }
 
@@ -553,6 +583,7 @@ hipError_t launch_classify(hipStream_t s, DevMesh& m, const StepArgs& a) {
 }
 
 hipError_t launch_partitions(hipStream_t s, DevMesh& m, int early_order) {
+  static_assert(kMaxLevels + kCellKeys <= kMaxKeys, "the two cell lists share one scan");
   int use_colour = m.scatter == TAFV_SCATTER_COLOUR;
   int Kf = use_colour ? m.ncolours * kMaxLevels : kMaxLevels;
   hipLaunchKernelGGL(k_face_keys, dim3(blocks_for(m.nf)), dim3(kBlock), 0, s, m.nf, m.fhL, m.fhR,
@@ -564,11 +595,13 @@ hipError_t launch_partitions(hipStream_t s, DevMesh& m, int early_order) {
   if (early_order)
     hipLaunchKernelGGL(k_cell_list_keys, dim3(blocks_for(m.nc)), dim3(kBlock), 0, s, m.nc, m.nb_,
                        m.lev, m.ckey, m.fpack, m.lkey, early_order);
-  hipError_t e = run_partition(s, m.nf, ByteKey{m.fkey}, Kf, m.pf, FaceWriter{m.frec, m.fhL, m.fhR});
+  hipError_t e =
+      run_partition(s, m.nf, m.pf, ByteKey{m.fkey}, Kf, FaceWriter{m.frec, m.fhL, m.fhR});
   if (e != hipSuccess) return e;
-  e = run_partition(s, m.nc, ByteKey{m.ckey}, kMaxLevels, m.pc, IndexWriter{m.pc.list});
-  if (e != hipSuccess || !early_order) return e;  // the gather's list serves time order 1 only
-  return run_partition(s, m.nc, ByteKey{m.lkey}, kCellKeys, m.pg, IndexWriter{m.pg.list});
+  if (!early_order)  // the gather's list serves time order 1 only
+    return run_partition(s, m.nc, m.pc, ByteKey{m.ckey}, kMaxLevels, IndexWriter{m.pc.list});
+  return run_partition(s, m.nc, m.pc, ByteKey{m.ckey}, kMaxLevels, IndexWriter{m.pc.list}, &m.pg,
+                       ByteKey{m.lkey}, kCellKeys, IndexWriter{m.pg.list});
 }
 
 template <typename T>
