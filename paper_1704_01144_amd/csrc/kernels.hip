@@ -124,12 +124,13 @@ __global__ void k_sweep_inplace(int nc, const int* __restrict__ nb, int8_t* lev,
   int i = blockIdx.x * blockDim.x + threadIdx.x;
   bool low = false;
   if (i < nc) {
+    int n[4], tn[4];
+    for (int m = 0; m < 4; ++m) n[m] = nb[m * nc + i];
+    for (int m = 0; m < 4; ++m) tn[m] = lev[n[m] >= 0 ? n[m] : i];
     const int t0 = lev[i];
     int t = t0;
-    for (int m = 0; m < 4; ++m) {
-      const int n = nb[m * nc + i];
-      if (n >= 0) t = min(t, (int)lev[n] + 1);
-    }
+    for (int m = 0; m < 4; ++m)
+      if (n[m] >= 0) t = min(t, tn[m] + 1);
     if (t < t0) {
       lev[i] = (int8_t)t;
       low = true;

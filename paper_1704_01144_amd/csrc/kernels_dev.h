@@ -58,23 +58,33 @@ __device__ inline double dt_item(int i, int nc, int nf, const double* __restrict
                                  const double* __restrict__ vol, const int* __restrict__ c2f,
                                  const double* __restrict__ fA, double gamma, double cfl,
                                  bool& bad, const double* __restrict__ sF = nullptr) {
+  // the face ids, then all 4 area vectors, are requested together
+  int f[4];
+  for (int m = 0; m < 4; ++m) f[m] = c2f[m * nc + i];
   double w[5];
   cons2prim(U + 5 * (size_t)i, gamma - 1.0, w);
-  if (!(w[0] > 0.0) || !(w[4] > 0.0) || !isfinite(w[4])) {
-    bad = true;
-    return INFINITY;
-  }
+  double A[4][3];
+  for (int m = 0; m < 4; ++m)
+    for (int q = 0; q < 3; ++q) A[m][q] = fA[(size_t)q * nf + f[m]];
+  double xs[4] = {0, 0, 0, 0};
+  if (sF)
+    for (int m = 0; m < 4; ++m) xs[m] = sF[f[m]];
+  const bool ok = w[0] > 0.0 && w[4] > 0.0 && isfinite(w[4]);
   double a = sqrt(gamma * w[4] / w[0]);
   double s = 0.0;
   for (int m = 0; m < 4; ++m) {
-    int f = c2f[m * nc + i];
-    double ax = fA[f], ay = fA[nf + f], az = fA[2 * (size_t)nf + f];
+    const double ax = A[m][0], ay = A[m][1], az = A[m][2];
     double am = sqrt(ax * ax + ay * ay + az * az);
     double un = (w[1] * ax + w[2] * ay + w[3] * az) / am;
-    if (sF) un -= sF[f] / am;
+    if (sF) un -= xs[m] / am;
     s += (fabs(un) + a) * am;
   }
-  return cfl * vol[i] / s;
+  const double dti = cfl * vol[i] / s;
+  if (!ok) {
+    bad = true;
+    return INFINITY;
+  }
+  return dti;
 }
 
 // tau_i = clamp(floor(log2(dt_i (1 - margin) / dt_min)), 0, L-1) by frexp
@@ -88,13 +98,16 @@ __device__ inline int8_t classify_item(double dti, double dtmin, double margin, 
 }
 
 // one lowering Jacobi sweep: tau_i <- min(tau_i, min_j tau_j + 1)
+// (the neighbour ids, then their levels, are requested together; a boundary
+// slot reads the cell's own level and is not used)
 __device__ inline int8_t sweep_item(int i, int nc, const int* __restrict__ nb,
                                     const int8_t* __restrict__ src) {
+  int n[4], tn[4];
+  for (int m = 0; m < 4; ++m) n[m] = nb[m * nc + i];
+  for (int m = 0; m < 4; ++m) tn[m] = src[n[m] >= 0 ? n[m] : i];
   int t = src[i];
-  for (int m = 0; m < 4; ++m) {
-    int n = nb[m * nc + i];
-    if (n >= 0) t = min(t, (int)src[n] + 1);
-  }
+  for (int m = 0; m < 4; ++m)
+    if (n[m] >= 0) t = min(t, tn[m] + 1);
   return (int8_t)t;
 }
 
@@ -103,9 +116,10 @@ __device__ inline int8_t face_key_item(int f, const int* __restrict__ fhL,
                                        const int* __restrict__ fhR,
                                        const int8_t* __restrict__ fcol,
                                        const int8_t* __restrict__ lev, int use_colour) {
-  int t = lev[fhL[f] >> 2];
-  int h = fhR[f];
-  if (h >= 0) t = min(t, (int)lev[h >> 2]);
+  const int hl = fhL[f], h = fhR[f];
+  int t = lev[hl >> 2];
+  const int tr = lev[(h >= 0 ? h : hl) >> 2];
+  if (h >= 0) t = min(t, tr);
   return (int8_t)(use_colour ? fcol[f] * kMaxLevels + t : t);
 }
 
@@ -115,11 +129,14 @@ __device__ inline int8_t face_key_item(int f, const int* __restrict__ fhL,
 __device__ inline int cell_key_item(int i, int nc, const int* __restrict__ nb,
                                     const int8_t* __restrict__ lev, int8_t* __restrict__ ckey,
                                     uint32_t* __restrict__ fpack) {
+  int n4[4], tn[4];
+  for (int m = 0; m < 4; ++m) n4[m] = nb[m * nc + i];
+  for (int m = 0; m < 4; ++m) tn[m] = lev[n4[m] >= 0 ? n4[m] : i];
   int ti = lev[i], tg = ti;
   uint32_t pk = (uint32_t)ti << 20;
   for (int m = 0; m < 4; ++m) {
-    int n = nb[m * nc + i];
-    int tf = n >= 0 ? min(ti, (int)lev[n]) : ti;
+    int n = n4[m];
+    int tf = n >= 0 ? min(ti, tn[m]) : ti;
     tg = min(tg, tf);
     pk |= (uint32_t)tf << (4 * m);
     if (n >= 0 && n < i) pk |= 1u << (16 + m);
@@ -146,11 +163,13 @@ __device__ inline bool cell_early_item(int i, int nc, const int* __restrict__ nb
   if (order == 0) return false;
   const int t = lev[i];
   bool e = ckey[i] == t;
-  if (e && order == 2)
-    for (int m = 0; m < 4; ++m) {
-      const int n = nb[m * nc + i];
-      if (n >= 0 && ckey[n] < t) e = false;
-    }
+  if (order == 2) {
+    int n[4], kn[4];
+    for (int m = 0; m < 4; ++m) n[m] = nb[m * nc + i];
+    for (int m = 0; m < 4; ++m) kn[m] = ckey[n[m] >= 0 ? n[m] : i];
+    for (int m = 0; m < 4; ++m)
+      if (n[m] >= 0 && kn[m] < t) e = false;
+  }
   if (e) fpack[i] |= kEarlyBit;
   return e;
 }
@@ -164,11 +183,15 @@ __device__ inline int list_cell(const int* __restrict__ list, int n1, int off2, 
 // The gather's cell list (single-mesh form) is sorted by the key 2 k + b:
 // k = the level for a cell of kEarlyBit (b = 0), k = tau_g for the others
 // (b = 1).  Its cells keep the spatial order of the tau_g list, and a launch
-// takes a few ranges of it (ListRanges): item idx of range r.
+// takes a few ranges of it (ListRanges): item idx lies in the last range r
+// with cum[r] <= idx.  The scan is unrolled over the fixed number of slots so
+// that the ranges stay in scalar registers.
 __device__ inline int range_cell(const int* __restrict__ list, const ListRanges& R, int idx) {
-  int r = 0;
-  while (r + 1 < R.n && idx >= R.cum[r + 1]) ++r;
-  return list[R.off[r] + (idx - R.cum[r])];
+  int base = R.off[0];
+#pragma unroll
+  for (int r = 1; r < kMaxLevels + 1; ++r)
+    if (r < R.n && idx >= R.cum[r]) base = R.off[r] - R.cum[r];
+  return list[base + idx];
 }
 
 // h[bin] += 1 for every active lane, one LDS atomic per distinct bin of the
@@ -257,78 +280,103 @@ struct FaceValueWriter {
   }
 };
 
+// Element at byte offset byte_off of a column that starts at col, the same
+// address for the whole wave: the base goes through scalar registers (the
+// wave reads it from its first lane) and the load takes one 32-bit offset
+// register that all columns of an item share.  Needs byte_off < 2^32, which
+// the cell and face counts (< 2^29) guarantee for 8-byte elements.
+template <typename T>
+__device__ inline T col_load(const T* __restrict__ col, uint32_t byte_off) {
+  const uint64_t b = reinterpret_cast<uint64_t>(col);
+  const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)b);
+  const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(b >> 32));
+  typedef const __attribute__((address_space(1))) char gchar;
+  typedef const __attribute__((address_space(1))) T gT;
+  gchar* base = (gchar*)(((uint64_t)hi << 32) | lo);
+  return *(gT*)(base + byte_off);
+}
+
 // Least squares over the 4 face neighbours (mirror ghosts on the boundary):
 // G = sum_m c_m (W_m - W_i); Barth-Jespersen per variable k: the largest
 // psi_k <= 1 keeping W_i + psi_k G_k . r_m inside [min, max] of the cell and
 // its neighbours at all 4 face centroids r_m; output W_i + psi_k G_k . r_m.
-// nbw(n, w): the primitive state of neighbour n.  All 64 lanes of a wave
-// call this together (see FaceValueWriter); stage: kStageVals values.
-template <typename T, typename NbW>
-__device__ inline void grad_item_w(const GradArgs<T>& a, int i, bool valid, const double* wd,
-                                   NbW nbw, T* stage) {
+// All 64 lanes of a wave call this together (see FaceValueWriter); stage:
+// kStageVals values.
+//
+// The loads are grouped so that a cell waits on three dependent trips to
+// memory (its list entry; its neighbour ids with its own state and LSQ
+// coefficients; the 4 neighbour states together), and a fourth for the face
+// offsets, rather than on two per neighbour: a boundary slot loads the
+// cell's own state, which the mirror ghost then replaces, so no branch
+// separates the neighbour loads.  G and the limiter's bounds accumulate
+// neighbour by neighbour, in the order m = 0..3 of the least-squares sum.
+template <typename T>
+__device__ inline void grad_item(const GradArgs<T>& a, int i, bool valid, T* stage) {
   const int nc = a.nc;
   FaceValueWriter<T> out(stage, i, valid);
-  T wi[5], dw[4][5];
-  for (int k = 0; k < 5; ++k) wi[k] = (T)wd[k];
+  const uint32_t o4 = (uint32_t)i * 4u, oT = (uint32_t)i * (uint32_t)sizeof(T);
+  int nb[4];
+  for (int m = 0; m < 4; ++m) nb[m] = col_load(a.nb + (size_t)m * nc, o4);
+  double ui[5];
+  for (int k = 0; k < 5; ++k) ui[k] = a.U[5 * (size_t)i + k];
+  double un[4][5];
   for (int m = 0; m < 4; ++m) {
-    int n = a.nb[m * nc + i];
-    if (n >= 0) {
-      double t[5];
-      nbw(n, t);
-      for (int k = 0; k < 5; ++k) dw[m][k] = (T)t[k] - wi[k];
-    } else {
-      for (int k = 0; k < 5; ++k) dw[m][k] = 0;
-      if (a.boundary == TAFV_BC_WALL) {
-        int f = -n - 1;
-        T ax = (T)a.fA[f], ay = (T)a.fA[a.nf + f], az = (T)a.fA[2 * (size_t)a.nf + f];
-        T ia = frsq(ax * ax + ay * ay + az * az);
-        T nx = ax * ia, ny = ay * ia, nz = az * ia;
-        T un = wi[1] * nx + wi[2] * ny + wi[3] * nz;
-        if (a.sF) un -= (T)a.sF[f] * ia;  // the wall moves with the face
-        T un2 = 2 * un;
-        dw[m][1] = -un2 * nx;
-        dw[m][2] = -un2 * ny;
-        dw[m][3] = -un2 * nz;
-      }
+    const size_t src = 5 * (size_t)(nb[m] >= 0 ? nb[m] : i);
+    for (int k = 0; k < 5; ++k) un[m][k] = a.U[src + k];
+  }
+  T c[4][3];
+  for (int m = 0; m < 4; ++m)
+    for (int q = 0; q < 3; ++q) c[m][q] = col_load(a.lsq + (size_t)(3 * m + q) * nc, oT);
+  double wd[5];
+  cons2prim(ui, a.gm1, wd);
+  T wi[5];
+  for (int k = 0; k < 5; ++k) wi[k] = (T)wd[k];
+  T g[5][3], hi[5], lo[5];
+  for (int k = 0; k < 5; ++k) g[k][0] = g[k][1] = g[k][2] = hi[k] = lo[k] = 0;
+  for (int m = 0; m < 4; ++m) {
+    T dw[5];
+    double t[5];
+    cons2prim(un[m], a.gm1, t);
+    for (int k = 0; k < 5; ++k) dw[k] = nb[m] >= 0 ? (T)t[k] - wi[k] : (T)0;
+    if (nb[m] < 0 && a.boundary == TAFV_BC_WALL) {
+      int f = -nb[m] - 1;
+      T ax = (T)a.fA[f], ay = (T)a.fA[a.nf + f], az = (T)a.fA[2 * (size_t)a.nf + f];
+      T ia = frsq(ax * ax + ay * ay + az * az);
+      T nx = ax * ia, ny = ay * ia, nz = az * ia;
+      T vn = wi[1] * nx + wi[2] * ny + wi[3] * nz;
+      if (a.sF) vn -= (T)a.sF[f] * ia;  // the wall moves with the face
+      T vn2 = 2 * vn;
+      dw[1] = -vn2 * nx;
+      dw[2] = -vn2 * ny;
+      dw[3] = -vn2 * nz;
+    }
+    for (int k = 0; k < 5; ++k) {
+      T d = dw[k];
+      g[k][0] += c[m][0] * d;
+      g[k][1] += c[m][1] * d;
+      g[k][2] += c[m][2] * d;
+      hi[k] = d > hi[k] ? d : hi[k];
+      lo[k] = d < lo[k] ? d : lo[k];
     }
   }
-  T r[4][3], c[4][3];
+  T r[4][3];
   for (int m = 0; m < 4; ++m)
-    for (int q = 0; q < 3; ++q) {
-      r[m][q] = a.rf[(3 * m + q) * nc + i];
-      c[m][q] = a.lsq[(3 * m + q) * nc + i];
-    }
+    for (int q = 0; q < 3; ++q) r[m][q] = col_load(a.rf + (size_t)(3 * m + q) * nc, oT);
   for (int k = 0; k < 5; ++k) {
-    T g0 = 0, g1 = 0, g2 = 0, hi = 0, lo = 0;
-    for (int m = 0; m < 4; ++m) {
-      T d = dw[m][k];
-      g0 += c[m][0] * d;
-      g1 += c[m][1] * d;
-      g2 += c[m][2] * d;
-      hi = d > hi ? d : hi;
-      lo = d < lo ? d : lo;
-    }
+    const T g0 = g[k][0], g1 = g[k][1], g2 = g[k][2];
     T delta[4];
     T psi = 1;
     for (int m = 0; m < 4; ++m) {
       T d = g0 * r[m][0] + g1 * r[m][1] + g2 * r[m][2];
       delta[m] = d;
       T phi = 1;
-      if (d > 0) phi = hi < d ? hi * frcp(d) : (T)1;
-      else if (d < 0) phi = lo > d ? lo * frcp(d) : (T)1;
+      if (d > 0) phi = hi[k] < d ? hi[k] * frcp(d) : (T)1;
+      else if (d < 0) phi = lo[k] > d ? lo[k] * frcp(d) : (T)1;
       psi = phi < psi ? phi : psi;
     }
     for (int m = 0; m < 4; ++m) out.put(m, k, wi[k] + psi * delta[m]);
   }
   out.flush(a.Wf, nc);
-}
-
-template <typename T>
-__device__ inline void grad_item(const GradArgs<T>& a, int i, bool valid, T* stage) {
-  double wd[5];
-  cons2prim(a.U + 5 * (size_t)i, a.gm1, wd);
-  grad_item_w(a, i, valid, wd, [&](int n, double* t) { cons2prim(a.U + 5 * (size_t)n, a.gm1, t); },
-              stage);
 }
 
 // ---------------------------------------------------------------------------
@@ -741,6 +789,43 @@ __device__ inline void flux_feat_item(const FluxArgs<T>& a, bool valid, int4 r, 
   add_info(acc, info);
 }
 
+// Adds s_m q_m to acc for the faces m of cell i whose bit is set in act
+// (act != 0), in local face order: q_m the face's stored flux, s_m = +h_m
+// where the cell is the higher id of the face (bit 16 + m of pk), -h_m
+// otherwise; a moving mesh also adds -s_m sF to accv.  The 4 face ids, then
+// the fluxes of all the active faces, are requested together (an inactive
+// slot reads an active face's flux again and adds nothing), so the sum waits
+// on two trips to memory rather than two per face.
+template <typename T, bool MOVE>
+__device__ inline void add_face_fluxes(int i, int nc, uint32_t pk, unsigned act, const double* h,
+                                       const int* __restrict__ c2f, const T* __restrict__ Q,
+                                       const double* __restrict__ sF, double* acc,
+                                       double& accv) {
+  int f[4];
+  for (int m = 0; m < 4; ++m) f[m] = c2f[m * nc + i];
+  const int fa = (act & 1u) ? f[0] : (act & 2u) ? f[1] : (act & 4u) ? f[2] : f[3];
+  T q[4][5];
+  double sv[4];
+  for (int m = 0; m < 4; ++m) {
+    const int fm = ((act >> m) & 1u) ? f[m] : fa;
+    const T* p = Q + 5 * (size_t)fm;
+    for (int k = 0; k < 5; ++k) q[m][k] = p[k];
+    if (MOVE) sv[m] = sF[fm];
+  }
+  for (int m = 0; m < 4; ++m) {
+    const bool on = (act >> m) & 1u;
+    const double sm = (pk & (1u << (16 + m))) ? h[m] : -h[m];
+    for (int k = 0; k < 5; ++k) {
+      const double a = acc[k] + sm * (double)q[m][k];
+      acc[k] = on ? a : acc[k];
+    }
+    if (MOVE) {
+      const double a = accv + (-sm) * sv[m];
+      accv = on ? a : accv;
+    }
+  }
+}
+
 // A cell ending its step applies its flux sum acc: U += acc / V on a fixed
 // mesh; on a moving mesh its content and volume change together (geometric
 // conservation), V' = V + accv, U' = (V U + acc) / V'.  Returns false on a
@@ -787,60 +872,37 @@ __device__ inline bool cell_gather_item(int i, int nc, const uint32_t* __restric
                                         const double* __restrict__ sF = nullptr,
                                         double* __restrict__ Rv = nullptr,
                                         double* __restrict__ Vw = nullptr) {
-  uint32_t pk = fpack[i];
-  int ti = (pk >> 20) & 15;
+  const uint32_t pk = fpack[i];
+  const int ti = (pk >> 20) & 15;
   double acc[5] = {0, 0, 0, 0, 0};
   double accv = 0.0;  // moving mesh: swept volume, -dt_f sF per face as the flux
   if (pk & kEarlyBit) {
     if (ti > tau_s) return true;  // applied at the step's start
     const double dtf = ldexp(dt_min, ti);
-    for (int m = 0; m < 4; ++m) {
-      const int f = c2f[m * nc + i];
-      const T* q = Q + 5 * (size_t)f;
-      if (pk & (1u << (16 + m))) {
-        for (int k = 0; k < 5; ++k) acc[k] += dtf * (double)q[k];
-        if (MOVE) accv += -dtf * sF[f];
-      } else {
-        for (int k = 0; k < 5; ++k) acc[k] -= dtf * (double)q[k];
-        if (MOVE) accv -= -dtf * sF[f];
-      }
-    }
+    const double h[4] = {dtf, dtf, dtf, dtf};
+    add_face_fluxes<T, MOVE>(i, nc, pk, 0xfu, h, c2f, Q, sF, acc, accv);
     return apply_cell<MOVE>(i, acc, accv, vol, Vw, U);
   }
-  bool ends = ti <= tau_upd;
-  bool touched = false;
-  double* Ri = R + 5 * (size_t)i;
+  unsigned act = 0;
+  double h[4];
   for (int m = 0; m < 4; ++m) {
     const int tf = (int)((pk >> (4 * m)) & 15);
-    if (tf > tau_s) continue;
-    if (!touched) {
-      for (int k = 0; k < 5; ++k) acc[k] = Ri[k];
-      if (MOVE) accv = Rv[i];
-      touched = true;
-    }
-    const int f = c2f[m * nc + i];
-    const T* q = Q + 5 * (size_t)f;
-    const double dtf = ldexp(dt_min, tf);
-    if (pk & (1u << (16 + m))) {
-      for (int k = 0; k < 5; ++k) acc[k] += dtf * (double)q[k];
-      if (MOVE) accv += -dtf * sF[f];
-    } else {
-      for (int k = 0; k < 5; ++k) acc[k] -= dtf * (double)q[k];
-      if (MOVE) accv -= -dtf * sF[f];
-    }
+    h[m] = ldexp(dt_min, tf);
+    act |= (unsigned)(tf <= tau_s) << m;
   }
+  const bool ends = ti <= tau_upd;
+  if (!act && !ends) return true;
+  double* Ri = R + 5 * (size_t)i;
+  for (int k = 0; k < 5; ++k) acc[k] = Ri[k];
+  if (MOVE) accv = Rv[i];
+  if (act) add_face_fluxes<T, MOVE>(i, nc, pk, act, h, c2f, Q, sF, acc, accv);
   if (ends) {
-    if (!touched) {
-      for (int k = 0; k < 5; ++k) acc[k] = Ri[k];
-      if (MOVE) accv = Rv[i];
-    }
     for (int k = 0; k < 5; ++k) Ri[k] = 0.0;
     if (MOVE) Rv[i] = 0.0;
     return apply_cell<MOVE>(i, acc, accv, vol, Vw, U);
-  } else if (touched) {
-    for (int k = 0; k < 5; ++k) Ri[k] = acc[k];
-    if (MOVE) Rv[i] = accv;
   }
+  for (int k = 0; k < 5; ++k) Ri[k] = acc[k];
+  if (MOVE) Rv[i] = accv;
   return true;
 }
 
@@ -867,15 +929,9 @@ __device__ inline void predict_item(int i, int nc, const uint32_t* __restrict__ 
   double d[5];
   double* Di = D + 5 * (size_t)i;
   if (ti <= tau_s) {
-    double acc[5] = {0, 0, 0, 0, 0};
-    for (int m = 0; m < 4; ++m) {
-      const T* q = Q0 + 5 * (size_t)c2f[m * nc + i];
-      if (pk & (1u << (16 + m))) {
-        for (int k = 0; k < 5; ++k) acc[k] += (double)q[k];
-      } else {
-        for (int k = 0; k < 5; ++k) acc[k] -= (double)q[k];
-      }
-    }
+    double acc[5] = {0, 0, 0, 0, 0}, accv = 0.0;
+    const double one[4] = {1.0, 1.0, 1.0, 1.0};
+    add_face_fluxes<T, false>(i, nc, pk, 0xfu, one, c2f, Q0, nullptr, acc, accv);
     const double dtc = ldexp(dt_min, ti), v = vol[i];
     for (int k = 0; k < 5; ++k) {
       d[k] = dtc * acc[k] / v;
@@ -905,27 +961,19 @@ __device__ inline bool cell_gather2_item(int i, int nc, const uint32_t* __restri
   const uint32_t pk = fpack[i];
   const int ti = (pk >> 20) & 15;
   const bool ends = ti <= tau_upd;
-  bool touched = false;
-  double acc[5] = {0, 0, 0, 0, 0};
-  double* Ri = R + 5 * (size_t)i;
+  unsigned act = 0;
+  double h[4];
   for (int m = 0; m < 4; ++m) {
     const int tf = (int)((pk >> (4 * m)) & 15);
-    if (tf > tau_upd) continue;
-    if (!touched) {
-      for (int k = 0; k < 5; ++k) acc[k] = Ri[k];
-      touched = true;
-    }
-    const T* q = Q + 5 * (size_t)c2f[m * nc + i];
-    const double h = ldexp(dt_min, tf - 1);
-    if (pk & (1u << (16 + m))) {
-      for (int k = 0; k < 5; ++k) acc[k] += h * (double)q[k];
-    } else {
-      for (int k = 0; k < 5; ++k) acc[k] -= h * (double)q[k];
-    }
+    h[m] = ldexp(dt_min, tf - 1);
+    act |= (unsigned)(tf <= tau_upd) << m;
   }
+  if (!act && !ends) return true;
+  double acc[5], accv = 0.0;
+  double* Ri = R + 5 * (size_t)i;
+  for (int k = 0; k < 5; ++k) acc[k] = Ri[k];
+  if (act) add_face_fluxes<T, false>(i, nc, pk, act, h, c2f, Q, nullptr, acc, accv);
   if (ends) {
-    if (!touched)
-      for (int k = 0; k < 5; ++k) acc[k] = Ri[k];
     const double v = vol[i];
     bool bad = false;
     for (int k = 0; k < 5; ++k) {
@@ -936,9 +984,8 @@ __device__ inline bool cell_gather2_item(int i, int nc, const uint32_t* __restri
       bad |= !isfinite(u);
     }
     return !bad;
-  } else if (touched) {
-    for (int k = 0; k < 5; ++k) Ri[k] = acc[k];
   }
+  for (int k = 0; k < 5; ++k) Ri[k] = acc[k];
   return true;
 }
 
