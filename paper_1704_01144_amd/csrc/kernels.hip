@@ -28,7 +28,7 @@
 
 namespace tafv {
 
-constexpr int kPartChunk = 1024;  // elements per partition block (16 waves of 64)
+constexpr int kPartChunk = 256;  // items per partition block (one wave, 64 items a step)
 
 // ---------------------------------------------------------------------------
 // state init and small fills
