@@ -1,23 +1,31 @@
 // Device kernels of the temporal-adaptive finite-volume path (gfx950).
 //
-// One subiteration of Alg. 2 (Sec. 2.2) on the device:
-//   k_grad   (second order) cells that touch an active face: least-squares
-//            gradient of the primitive variables over the 4 face neighbours
-//            (mirror ghosts on the boundary), Barth-Jespersen limiter, and
-//            the reconstructed value at each of the cell's 4 face centroids
-//            (stored as [slot][cell][variable], so a face reads 2 runs of 5
-//            values);
-//   k_flux   once per face colour: active faces (faster side's level <= the
-//            subiteration's level), exact Riemann flux, dt_f = 2^tau_f dt_min,
-//            and a plain read-modify-write of both cells' FP64 accumulators;
-//            no two faces of a colour share a cell, so no atomics and a fixed
-//            summation order;
-//   k_update cells whose level step ends: U += R / V, R = 0.
+// One subiteration of Alg. 2 (Sec. 2.2) on the device, gather mode (the
+// default):
+//   k_grad         (second order) cells that touch an active face:
+//                  least-squares gradient of the primitive variables over the
+//                  4 face neighbours (mirror ghosts on the boundary),
+//                  Barth-Jespersen limiter, and the reconstructed value at
+//                  each of the cell's 4 face centroids (stored as
+//                  [slot][cell][variable], so a face reads 2 runs of 5 values);
+//   k_flux_store   active faces (faster side's level <= the subiteration's
+//                  level): exact Riemann flux |A| F . n, stored per face;
+//   k_cell_gather  cells with an active face or an ending step: the active
+//                  faces' q = 2^tau_f dt_min Phi summed in local face order
+//                  into the FP64 accumulator, U += R / V, R = 0 when the
+//                  cell's level step ends (cells whose faces are all on their
+//                  own level apply the whole step's sum at its start).
+// Colour mode instead runs k_flux_colour once per face colour (a plain
+// read-modify-write of both cells' accumulators; no two faces of a colour
+// share a cell) and then k_update.  The predictor/corrector form adds
+// k_predict and k_cell_gather2, a moving mesh k_face_speed and
+// k_cell_gather_move.
 // At every iteration start (phase 0): k_dt (per-cell time step and its
 // minimum), k_classify (levels from the dt ratio), k_sweep_inplace (neighbour
-// levels at most one apart), and three ballot-based stable partitions that
-// order faces by (colour, tau_f) and cells by tau_g / tau so that the
-// active set of any subiteration is a prefix of each list.
+// levels at most one apart), the face and cell keys, and ballot-based stable
+// partitions (faces by (colour, tau_f); cells by tau_g and, in the same pass,
+// by the gather's key) so that the active set of any subiteration is a
+// prefix, or a few ranges, of each list.
 #include <hip/hip_runtime.h>
 
 #include <hipcub/hipcub.hpp>
