@@ -220,7 +220,7 @@ tafv_status subiteration2(tafv_ctx* c, DevMesh& m, const StepArgs& a, int tau_s,
   if (c->prm.order == 2) {
     const CellRange r = cells_active(m, tau_s);
     ProfScope ps(c, P_GRAD, r.count());
-    HIP_TRY(c, launch_grad(c->stream, m, a, r, m.Ut));
+    HIP_TRY(c, launch_grad(c->stream, m, a, r, tau_s, m.Ut));
   }
   {
     ProfScope ps(c, P_FLUX, pcnt);
@@ -233,7 +233,7 @@ tafv_status subiteration2(tafv_ctx* c, DevMesh& m, const StepArgs& a, int tau_s,
   if (c->prm.order == 2) {
     const CellRange r = cells_active(m, upd);
     ProfScope ps(c, P_GRAD, r.count());
-    HIP_TRY(c, launch_grad(c->stream, m, a, r, m.Ut));
+    HIP_TRY(c, launch_grad(c->stream, m, a, r, upd, m.Ut));
   }
   {
     ProfScope ps(c, P_FLUX, ccnt);
@@ -258,7 +258,7 @@ tafv_status subiteration(tafv_ctx* c, DevMesh& m, tafv_stats* acc) {
   if (c->prm.order == 2 && c->prm.time_order == 1) {
     const CellRange r = cells_active(m, tau_s);
     ProfScope ps(c, P_GRAD, r.count());
-    HIP_TRY(c, launch_grad(c->stream, m, a, r));
+    HIP_TRY(c, launch_grad(c->stream, m, a, r, tau_s));
   }
   int64_t s = (int64_t)m.phase + 1;
   // cells whose step ends after this subiteration: tau_i <= min(theta, ctz(s))

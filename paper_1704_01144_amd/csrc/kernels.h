@@ -50,8 +50,9 @@ hipError_t launch_classify(hipStream_t s, DevMesh& m, const StepArgs& a);
 // step's start (gather mode, one pass per face step) for that spatial order;
 // 0 marks none
 hipError_t launch_partitions(hipStream_t s, DevMesh& m, int early_order);
-// U: the cell states the pass reads (default: the mesh's U)
-hipError_t launch_grad(hipStream_t s, DevMesh& m, const StepArgs& a, CellRange r,
+// r: the cells with tau_g <= tau_g of the tau_g list (a prefix); U: the cell
+// states the pass reads (default: the mesh's U)
+hipError_t launch_grad(hipStream_t s, DevMesh& m, const StepArgs& a, CellRange r, int tau_g,
                        const double* U = nullptr);
 // optional flux features: feat bit 0 = gate statistics and face logging,
 // bit 1 = learned guess (gamma = 1.4, gather mode)

@@ -37,6 +37,7 @@
 namespace tafv {
 
 constexpr int kPartChunk = 256;  // items per partition block (one wave, 64 items a step)
+constexpr int kWholeMeshPct = 75;  // whole-mesh launches from this share of the cells on
 
 // ---------------------------------------------------------------------------
 // state init and small fills
@@ -345,9 +346,17 @@ __global__ __launch_bounds__(kBlock) void k_grad(GradArgs<T> a) {
   const int idx = b0 + threadIdx.x;
   const int w0 = b0 + (threadIdx.x & ~63);  // the wave's first item
   if (w0 >= a.count) return;                // the whole wave is past the end
-  const bool valid = idx < a.count;
-  grad_item<T>(a, list_cell(a.list, a.n1, a.off2, valid ? idx : w0), valid,
-               sStage[threadIdx.x >> 6]);
+  if (a.list) {
+    const bool valid = idx < a.count;
+    grad_item<T>(a, list_cell(a.list, a.n1, a.off2, valid ? idx : w0), valid,
+                 sStage[threadIdx.x >> 6]);
+    return;
+  }
+  // whole mesh in its own order: cells outside the key range are skipped
+  const bool in = idx < a.count && a.key[idx] <= a.key_max;
+  const unsigned long long act = __ballot(in);
+  if (act == 0ull) return;  // the wave has no cell in range
+  grad_item<T>(a, in ? idx : w0 + (__ffsll(act) - 1), in, sStage[threadIdx.x >> 6]);
 }
 
 // ---------------------------------------------------------------------------
@@ -652,20 +661,31 @@ hipError_t launch_from_caller_i8(hipStream_t s, DevMesh& m, const int8_t* src, i
   return rows_from_caller<int8_t>(s, m, 1, src, dst);
 }
 
-hipError_t launch_grad(hipStream_t s, DevMesh& m, const StepArgs& a, CellRange r,
+// A launch that covers most of the mesh visits it in its own order (a
+// whole-mesh launch) rather than through a level-sorted list: neighbours are
+// then close in time, and their states and shared face fluxes are still in
+// L2 when read again.
+static bool whole_mesh(int64_t count, int64_t nc) { return count * 100 >= kWholeMeshPct * nc; }
+
+hipError_t launch_grad(hipStream_t s, DevMesh& m, const StepArgs& a, CellRange r, int tau_g,
                        const double* U) {
-  const int count = r.count();
+  int count = r.count();
   if (count <= 0) return hipSuccess;
   if (!U) U = m.U;
+  const int* list = m.pc.list;
+  if (r.n2 == 0 && whole_mesh(count, m.nc)) {  // the cells of tau_g <= tau_g, in mesh order
+    list = nullptr;
+    count = m.nc;
+  }
   if (a.precision == TAFV_FP32_FLUX) {
-    GradArgs<float> g{m.pc.list, count, m.nc, m.nf, U, m.nb_, m.lsq32, m.rf32, m.fA,
+    GradArgs<float> g{list, count, m.nc, m.nf, U, m.nb_, m.lsq32, m.rf32, m.fA,
                       (float*)m.Wf, a.gas.gm1, a.boundary, m.moving ? m.sF : nullptr,
-                      r.n1, r.off2};
+                      r.n1, r.off2, m.ckey, tau_g};
     hipLaunchKernelGGL(k_grad<float>, dim3(blocks_for(count)), dim3(kBlock), 0, s, g);
   } else {
-    GradArgs<double> g{m.pc.list, count, m.nc, m.nf, U, m.nb_, m.lsq, m.rf, m.fA,
+    GradArgs<double> g{list, count, m.nc, m.nf, U, m.nb_, m.lsq, m.rf, m.fA,
                        (double*)m.Wf, a.gas.gm1, a.boundary, m.moving ? m.sF : nullptr,
-                       r.n1, r.off2};
+                       r.n1, r.off2, m.ckey, tau_g};
     hipLaunchKernelGGL(k_grad<double>, dim3(blocks_for(count)), dim3(kBlock), 0, s, g);
   }
   return hipGetLastError();
@@ -735,28 +755,34 @@ hipError_t launch_flux(hipStream_t s, DevMesh& m, const StepArgs& a, int first, 
 
 hipError_t launch_cell_gather(hipStream_t s, DevMesh& m, const ListRanges& r, int tau_s,
                               int tau_upd, double dt_min, int precision) {
-  const int count = r.count();
+  int count = r.count();
   if (count <= 0) return hipSuccess;
+  // a whole-mesh launch: the cells outside the ranges find nothing to do
+  const int* list = m.pg.list;
+  if (whole_mesh(count, m.nc)) {
+    list = nullptr;
+    count = m.nc;
+  }
   if (m.moving) {
     if (precision == TAFV_FP32_FLUX)
       hipLaunchKernelGGL(k_cell_gather_move<float>, dim3(blocks_for(count)), dim3(kBlock), 0, s,
-                         count, m.pg.list, r, m.nc, m.fpack, m.c2f,
+                         count, list, r, m.nc, m.fpack, m.c2f,
                          (const float*)m.Q, dt_min, m.vol, m.U, m.R, tau_s, tau_upd, m.sF, m.Rv,
                          m.dscal);
     else
       hipLaunchKernelGGL(k_cell_gather_move<double>, dim3(blocks_for(count)), dim3(kBlock), 0, s,
-                         count, m.pg.list, r, m.nc, m.fpack, m.c2f,
+                         count, list, r, m.nc, m.fpack, m.c2f,
                          (const double*)m.Q, dt_min, m.vol, m.U, m.R, tau_s, tau_upd, m.sF, m.Rv,
                          m.dscal);
     return hipGetLastError();
   }
   if (precision == TAFV_FP32_FLUX)
     hipLaunchKernelGGL(k_cell_gather<float>, dim3(blocks_for(count)), dim3(kBlock), 0, s, count,
-                       m.pg.list, r, m.nc, m.fpack, m.c2f, (const float*)m.Q, dt_min,
+                       list, r, m.nc, m.fpack, m.c2f, (const float*)m.Q, dt_min,
                        m.vol, m.U, m.R, tau_s, tau_upd, m.dscal);
   else
     hipLaunchKernelGGL(k_cell_gather<double>, dim3(blocks_for(count)), dim3(kBlock), 0, s, count,
-                       m.pg.list, r, m.nc, m.fpack, m.c2f, (const double*)m.Q, dt_min,
+                       list, r, m.nc, m.fpack, m.c2f, (const double*)m.Q, dt_min,
                        m.vol, m.U, m.R, tau_s, tau_upd, m.dscal);
   return hipGetLastError();
 }

@@ -187,6 +187,7 @@ __device__ inline int list_cell(const int* __restrict__ list, int n1, int off2, 
 // with cum[r] <= idx.  The scan is unrolled over the fixed number of slots so
 // that the ranges stay in scalar registers.
 __device__ inline int range_cell(const int* __restrict__ list, const ListRanges& R, int idx) {
+  if (!list) return idx;  // a launch over the whole mesh in its own order
   int base = R.off[0];
 #pragma unroll
   for (int r = 1; r < kMaxLevels + 1; ++r)
@@ -248,6 +249,10 @@ struct GradArgs {
   int boundary;
   const double* sF;  // moving mesh: face volume rates (walls move with them)
   int n1, off2;      // the items are list[0, n1) then list[off2, ...) (see list_cell)
+  // list null: the items are the cells i < count with key[i] <= key_max,
+  // visited in mesh order
+  const int8_t* key;
+  int key_max;
 };
 
 // Face values are stored per slot and cell with the 5 values of a half-face
