@@ -31,13 +31,13 @@ HBM_PEAK_GBS = 8000.0
 #     levels 2, two reconstructed states 80 (40), read+write of two FP64
 #     accumulators 160;
 #   grad (per cell): index 4, own state 40, neighbour ids 16,
-#     least-squares coefficients 96 (48), face offsets 96 (48),
-#     4 reconstructed face states 160 (80);
+#     reconstruction coefficients 96 (48), 4 reconstructed face states
+#     160 (80);
 #   update (per cell): index 4, volume 8, state read+write 80, accumulator
 #     read+write 80.
 BYTES_PER_ITEM = {
-    "fp64": {"flux": 278, "grad": 412, "update": 172},
-    "fp32": {"flux": 226, "grad": 236, "update": 172},
+    "fp64": {"flux": 278, "grad": 316, "update": 172},
+    "fp32": {"flux": 226, "grad": 188, "update": 172},
 }
 # gather mode: the flux kernel reads a 16-byte face record, the area vector,
 # two reconstructed states and writes one flux (5 values in the flux
@@ -45,8 +45,8 @@ BYTES_PER_ITEM = {
 # ids, the active faces' fluxes (about 2 per cell), reads+writes the FP64
 # accumulator, and for ending steps the volume and state.
 BYTES_PER_ITEM_GATHER = {
-    "fp64": {"flux": 160, "grad": 412, "gather": 270},
-    "fp32": {"flux": 88, "grad": 236, "gather": 230},
+    "fp64": {"flux": 160, "grad": 316, "gather": 270},
+    "fp32": {"flux": 88, "grad": 188, "gather": 230},
 }
 
 

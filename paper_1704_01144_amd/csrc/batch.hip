@@ -678,8 +678,7 @@ void merge_hosts(const std::vector<HostMesh*>& hs, HostMesh& out, std::vector<in
   out.fA.resize(3 * NF);
   out.nb.resize(4 * NC);
   out.c2f.resize(4 * NC);
-  out.lsq.resize(12 * NC);
-  out.rf.resize(12 * NC);
+  out.grc.resize(12 * NC);
   out.vol.resize(NC);
   out.perm.resize(NC);
   for (size_t q = 0; q < hs.size(); ++q) {
@@ -699,10 +698,7 @@ void merge_hosts(const std::vector<HostMesh*>& hs, HostMesh& out, std::vector<in
         out.nb[m * NC + cb + i] = n >= 0 ? n + (int32_t)cb : n - (int32_t)fb;
         out.c2f[m * NC + cb + i] = h.c2f[m * h.nc + i] + (int32_t)fb;
       }
-      for (int k = 0; k < 12; ++k) {
-        out.lsq[k * NC + cb + i] = h.lsq[k * h.nc + i];
-        out.rf[k * NC + cb + i] = h.rf[k * h.nc + i];
-      }
+      for (int k = 0; k < 12; ++k) out.grc[k * NC + cb + i] = h.grc[k * h.nc + i];
       out.vol[cb + i] = h.vol[i];
       out.perm[cb + i] = h.perm[i];  // local: caller order within the mesh
     }
@@ -917,11 +913,11 @@ hipError_t run_grad(tafv_ctx* c, hipStream_t s, const LaunchSet& ls, const Ptrs&
   const dim3 g = work_grid(B, ls);
   const size_t lds = sizeof(int32_t) * (M + 1);
   if (c->prm.precision == TAFV_FP32_FLUX) {
-    GradArgs<float> a{m.pc.list, 0, m.nc, m.nf, m.U, m.nb_, m.lsq32, m.rf32, m.fA, (float*)m.Wf,
+    GradArgs<float> a{m.pc.list, 0, m.nc, m.nf, m.U, m.nb_, m.grc32, m.fA, (float*)m.Wf,
                       gm1, c->prm.boundary};
     return by_shape(ls, GradLaunch<float>{s, g, lds, p.tp, p.S, M, ls.grab, a});
   }
-  GradArgs<double> a{m.pc.list, 0, m.nc, m.nf, m.U, m.nb_, m.lsq, m.rf, m.fA, (double*)m.Wf,
+  GradArgs<double> a{m.pc.list, 0, m.nc, m.nf, m.U, m.nb_, m.grc, m.fA, (double*)m.Wf,
                      gm1, c->prm.boundary};
   return by_shape(ls, GradLaunch<double>{s, g, lds, p.tp, p.S, M, ls.grab, a});
 }

@@ -44,8 +44,8 @@ hipError_t dalloc(T** p, size_t n) {
 
 void free_mesh(DevMesh* m) {
   if (!m) return;
-  void* ptrs[] = {m->fhL, m->fhR, m->fcol, m->fA, m->fA32, m->nb_, m->c2f, m->lsq, m->rf,
-                  m->vol, m->lsq32, m->rf32, m->U, m->U0, m->R, m->lev, m->lev2, m->dt, m->Wf,
+  void* ptrs[] = {m->fhL, m->fhR, m->fcol, m->fA, m->fA32, m->nb_, m->c2f, m->grc,
+                  m->vol, m->grc32, m->U, m->U0, m->R, m->lev, m->lev2, m->dt, m->Wf,
                   m->pf.list, m->pf.counts, m->pf.start, m->pc.list, m->pc.counts,
                   m->pc.start, m->dscal, m->dcount, m->dimpulse, m->pf.offs, m->pc.offs,
                   m->pf.scan_tmp, m->pc.scan_tmp, m->Q, m->frec, m->fkey, m->ckey, m->fpack,
@@ -400,10 +400,8 @@ tafv_status upload_host_mesh(tafv_ctx* c, const HostMesh& hm, DevMesh** out) {
   chk(dalloc(&m->fA32, 3 * nf));
   chk(dalloc(&m->nb_, 4 * nc));
   chk(dalloc(&m->c2f, 4 * nc));
-  chk(dalloc(&m->lsq, 12 * nc));
-  chk(dalloc(&m->rf, 12 * nc));
-  chk(dalloc(&m->lsq32, 12 * nc));
-  chk(dalloc(&m->rf32, 12 * nc));
+  chk(dalloc(&m->grc, 12 * nc));
+  chk(dalloc(&m->grc32, 12 * nc));
   chk(dalloc(&m->vol, nc));
   chk(dalloc(&m->vol0, nc));
   chk(dalloc(&m->fnode, 3 * nf));
@@ -461,12 +459,9 @@ tafv_status upload_host_mesh(tafv_ctx* c, const HostMesh& hm, DevMesh** out) {
   chk(up(m->fA32, f32));
   chk(up(m->nb_, hm.nb));
   chk(up(m->c2f, hm.c2f));
-  chk(up(m->lsq, hm.lsq));
-  chk(up(m->rf, hm.rf));
-  f32.assign(hm.lsq.begin(), hm.lsq.end());
-  chk(up(m->lsq32, f32));
-  f32.assign(hm.rf.begin(), hm.rf.end());
-  chk(up(m->rf32, f32));
+  chk(up(m->grc, hm.grc));
+  f32.assign(hm.grc.begin(), hm.grc.end());
+  chk(up(m->grc32, f32));
   chk(up(m->vol, hm.vol));
   chk(up(m->vol0, hm.vol));
   chk(up(m->fnode, hm.fnode));

@@ -678,12 +678,12 @@ hipError_t launch_grad(hipStream_t s, DevMesh& m, const StepArgs& a, CellRange r
     count = m.nc;
   }
   if (a.precision == TAFV_FP32_FLUX) {
-    GradArgs<float> g{list, count, m.nc, m.nf, U, m.nb_, m.lsq32, m.rf32, m.fA,
+    GradArgs<float> g{list, count, m.nc, m.nf, U, m.nb_, m.grc32, m.fA,
                       (float*)m.Wf, a.gas.gm1, a.boundary, m.moving ? m.sF : nullptr,
                       r.n1, r.off2, m.ckey, tau_g};
     hipLaunchKernelGGL(k_grad<float>, dim3(blocks_for(count)), dim3(kBlock), 0, s, g);
   } else {
-    GradArgs<double> g{list, count, m.nc, m.nf, U, m.nb_, m.lsq, m.rf, m.fA,
+    GradArgs<double> g{list, count, m.nc, m.nf, U, m.nb_, m.grc, m.fA,
                        (double*)m.Wf, a.gas.gm1, a.boundary, m.moving ? m.sF : nullptr,
                        r.n1, r.off2, m.ckey, tau_g};
     hipLaunchKernelGGL(k_grad<double>, dim3(blocks_for(count)), dim3(kBlock), 0, s, g);

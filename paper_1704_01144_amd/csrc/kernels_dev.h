@@ -241,8 +241,7 @@ struct GradArgs {
   int count, nc, nf;
   const double* U;
   const int* nb;
-  const T* lsq;  // [12][nc]
-  const T* rf;   // [12][nc]
+  const T* grc;  // [12][nc] a_mj = c_j . r_m at (4 m + j) nc + cell, m < 3
   const double* fA;
   T* Wf;  // [4][5][nc]
   double gm1;
@@ -302,49 +301,51 @@ __device__ inline T col_load(const T* __restrict__ col, uint32_t byte_off) {
 }
 
 // Least squares over the 4 face neighbours (mirror ghosts on the boundary):
-// G = sum_m c_m (W_m - W_i); Barth-Jespersen per variable k: the largest
-// psi_k <= 1 keeping W_i + psi_k G_k . r_m inside [min, max] of the cell and
-// its neighbours at all 4 face centroids r_m; output W_i + psi_k G_k . r_m.
+// G = sum_j c_j (W_j - W_i), used only through its change to the face
+// centroids, delta_m = G . r_m = sum_j a_mj (W_j - W_i) with a_mj = c_j . r_m
+// (delta_3 = -(delta_0 + delta_1 + delta_2): the offsets r_m of a
+// tetrahedron sum to zero).  Barth-Jespersen per variable k: the largest
+// psi_k <= 1 keeping W_i + psi_k delta_m inside [min, max] of the cell and
+// its neighbours at all 4 face centroids; output W_i + psi_k delta_m.
 // All 64 lanes of a wave call this together (see FaceValueWriter); stage:
 // kStageVals values.
 //
 // The loads are grouped so that a cell waits on three dependent trips to
-// memory (its list entry; its neighbour ids with its own state and LSQ
-// coefficients; the 4 neighbour states together), and a fourth for the face
-// offsets, rather than on two per neighbour: a boundary slot loads the
-// cell's own state, which the mirror ghost then replaces, so no branch
-// separates the neighbour loads.  G and the limiter's bounds accumulate
-// neighbour by neighbour, in the order m = 0..3 of the least-squares sum.
+// memory (its list entry; its neighbour ids with its own state and the
+// coefficients; the 4 neighbour states together) rather than on two per
+// neighbour: a boundary slot loads the cell's own state, which the mirror
+// ghost then replaces, so no branch separates the neighbour loads.  The
+// sums accumulate neighbour by neighbour, j = 0..3.
 template <typename T>
 __device__ inline void grad_item(const GradArgs<T>& a, int i, bool valid, T* stage) {
   const int nc = a.nc;
   FaceValueWriter<T> out(stage, i, valid);
   const uint32_t o4 = (uint32_t)i * 4u, oT = (uint32_t)i * (uint32_t)sizeof(T);
   int nb[4];
-  for (int m = 0; m < 4; ++m) nb[m] = col_load(a.nb + (size_t)m * nc, o4);
+  for (int j = 0; j < 4; ++j) nb[j] = col_load(a.nb + (size_t)j * nc, o4);
   double ui[5];
   for (int k = 0; k < 5; ++k) ui[k] = a.U[5 * (size_t)i + k];
   double un[4][5];
-  for (int m = 0; m < 4; ++m) {
-    const size_t src = 5 * (size_t)(nb[m] >= 0 ? nb[m] : i);
-    for (int k = 0; k < 5; ++k) un[m][k] = a.U[src + k];
+  for (int j = 0; j < 4; ++j) {
+    const size_t src = 5 * (size_t)(nb[j] >= 0 ? nb[j] : i);
+    for (int k = 0; k < 5; ++k) un[j][k] = a.U[src + k];
   }
-  T c[4][3];
-  for (int m = 0; m < 4; ++m)
-    for (int q = 0; q < 3; ++q) c[m][q] = col_load(a.lsq + (size_t)(3 * m + q) * nc, oT);
+  T cr[3][4];
+  for (int m = 0; m < 3; ++m)
+    for (int j = 0; j < 4; ++j) cr[m][j] = col_load(a.grc + (size_t)(4 * m + j) * nc, oT);
   double wd[5];
   cons2prim(ui, a.gm1, wd);
   T wi[5];
   for (int k = 0; k < 5; ++k) wi[k] = (T)wd[k];
-  T g[5][3], hi[5], lo[5];
-  for (int k = 0; k < 5; ++k) g[k][0] = g[k][1] = g[k][2] = hi[k] = lo[k] = 0;
-  for (int m = 0; m < 4; ++m) {
+  T dl[3][5], hi[5], lo[5];
+  for (int k = 0; k < 5; ++k) dl[0][k] = dl[1][k] = dl[2][k] = hi[k] = lo[k] = 0;
+  for (int j = 0; j < 4; ++j) {
     T dw[5];
     double t[5];
-    cons2prim(un[m], a.gm1, t);
-    for (int k = 0; k < 5; ++k) dw[k] = nb[m] >= 0 ? (T)t[k] - wi[k] : (T)0;
-    if (nb[m] < 0 && a.boundary == TAFV_BC_WALL) {
-      int f = -nb[m] - 1;
+    cons2prim(un[j], a.gm1, t);
+    for (int k = 0; k < 5; ++k) dw[k] = nb[j] >= 0 ? (T)t[k] - wi[k] : (T)0;
+    if (nb[j] < 0 && a.boundary == TAFV_BC_WALL) {
+      int f = -nb[j] - 1;
       T ax = (T)a.fA[f], ay = (T)a.fA[a.nf + f], az = (T)a.fA[2 * (size_t)a.nf + f];
       T ia = frsq(ax * ax + ay * ay + az * az);
       T nx = ax * ia, ny = ay * ia, nz = az * ia;
@@ -356,24 +357,19 @@ __device__ inline void grad_item(const GradArgs<T>& a, int i, bool valid, T* sta
       dw[3] = -vn2 * nz;
     }
     for (int k = 0; k < 5; ++k) {
-      T d = dw[k];
-      g[k][0] += c[m][0] * d;
-      g[k][1] += c[m][1] * d;
-      g[k][2] += c[m][2] * d;
+      const T d = dw[k];
+      dl[0][k] += cr[0][j] * d;
+      dl[1][k] += cr[1][j] * d;
+      dl[2][k] += cr[2][j] * d;
       hi[k] = d > hi[k] ? d : hi[k];
       lo[k] = d < lo[k] ? d : lo[k];
     }
   }
-  T r[4][3];
-  for (int m = 0; m < 4; ++m)
-    for (int q = 0; q < 3; ++q) r[m][q] = col_load(a.rf + (size_t)(3 * m + q) * nc, oT);
   for (int k = 0; k < 5; ++k) {
-    const T g0 = g[k][0], g1 = g[k][1], g2 = g[k][2];
-    T delta[4];
+    const T delta[4] = {dl[0][k], dl[1][k], dl[2][k], -(dl[0][k] + dl[1][k] + dl[2][k])};
     T psi = 1;
     for (int m = 0; m < 4; ++m) {
-      T d = g0 * r[m][0] + g1 * r[m][1] + g2 * r[m][2];
-      delta[m] = d;
+      const T d = delta[m];
       T phi = 1;
       if (d > 0) phi = hi[k] < d ? hi[k] * frcp(d) : (T)1;
       else if (d < 0) phi = lo[k] > d ? lo[k] * frcp(d) : (T)1;

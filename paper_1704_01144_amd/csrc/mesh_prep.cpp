@@ -263,19 +263,21 @@ tafv_status build_host_mesh(int64_t n_nodes, const double* xyz, int64_t n_tets,
   }
 
   // least squares: neighbour (or mirror ghost) offsets d_m, weights
-  // 1/|d_m|^2, M = sum w d d^T, coefficient vectors M^-1 w_m d_m
-  out->lsq.assign(12 * nc, 0.0);
-  out->rf.assign(12 * nc, 0.0);
+  // 1/|d_m|^2, M = sum w d d^T, coefficient vectors c_j = M^-1 w_j d_j.
+  // The gradient is only used through its change to the face centroids,
+  // G . r_m = sum_j (c_j . r_m) (W_j - W_i), r_m = x_f(m) - x_i, so the
+  // coefficients stored are c_j . r_m; the 4 offsets of a tetrahedron sum
+  // to zero (each vertex is in 3 of its faces), so m = 3 follows from the
+  // others and only m < 3 is stored.
+  out->grc.assign(12 * nc, 0.0);
   for (int64_t i = 0; i < nc; ++i) {
-    V3 d[4];
+    V3 d[4], rm[4];
     double M[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
     for (int m = 0; m < 4; ++m) {
       int32_t f = out->c2f[m * nc + i];
       int32_t other = out->nb[m * nc + i];
       V3 r = sub(xf_new[f], xc[i]);
-      out->rf[(3 * m + 0) * nc + i] = r.x;
-      out->rf[(3 * m + 1) * nc + i] = r.y;
-      out->rf[(3 * m + 2) * nc + i] = r.z;
+      rm[m] = r;
       if (other >= 0) {
         d[m] = sub(xc[other], xc[i]);
       } else {
@@ -308,12 +310,16 @@ tafv_status build_host_mesh(int64_t n_nodes, const double* xyz, int64_t n_tets,
     inv[0][2] = (M[0][1] * M[1][2] - M[0][2] * M[1][1]) / det;
     inv[1][2] = (M[0][2] * M[1][0] - M[0][0] * M[1][2]) / det;
     inv[2][2] = (M[0][0] * M[1][1] - M[0][1] * M[1][0]) / det;
-    for (int m = 0; m < 4; ++m) {
-      double w = 1.0 / dot(d[m], d[m]);
-      double dv[3] = {w * d[m].x, w * d[m].y, w * d[m].z};
-      for (int a = 0; a < 3; ++a)
-        out->lsq[(3 * m + a) * nc + i] = inv[a][0] * dv[0] + inv[a][1] * dv[1] + inv[a][2] * dv[2];
+    V3 c[4];
+    for (int j = 0; j < 4; ++j) {
+      double w = 1.0 / dot(d[j], d[j]);
+      double dv[3] = {w * d[j].x, w * d[j].y, w * d[j].z};
+      double cv[3];
+      for (int a = 0; a < 3; ++a) cv[a] = inv[a][0] * dv[0] + inv[a][1] * dv[1] + inv[a][2] * dv[2];
+      c[j] = {cv[0], cv[1], cv[2]};
     }
+    for (int m = 0; m < 3; ++m)
+      for (int j = 0; j < 4; ++j) out->grc[(4 * m + j) * nc + i] = dot(c[j], rm[m]);
   }
   return TAFV_OK;
 }

@@ -33,8 +33,7 @@ struct HostMesh {
   // cells
   std::vector<int32_t> nb;         // [4][nc] neighbour across slot m, or -(face+1)
   std::vector<int32_t> c2f;        // [4][nc] face of slot m
-  std::vector<double> lsq;         // [12][nc] least-squares coefficient vectors
-  std::vector<double> rf;          // [12][nc] face centroid minus cell centroid
+  std::vector<double> grc;         // [12][nc] reconstruction coefficients c_j . r_m, m < 3
   std::vector<double> vol;         // [nc]
   std::vector<int32_t> perm;       // [nc] internal cell -> caller cell
 };
@@ -71,11 +70,11 @@ struct DevMesh {
   double* fA = nullptr;
   float* fA32 = nullptr;
   int32_t *nb_ = nullptr, *c2f = nullptr;
-  double *lsq = nullptr, *rf = nullptr, *vol = nullptr;
+  double *grc = nullptr, *vol = nullptr;
   double* vol0 = nullptr;   // [nc] volumes of the uploaded geometry
   int32_t* fnode = nullptr; // [3][nf] node ids of each face, ascending
   int64_t n_nodes = 0;
-  float *lsq32 = nullptr, *rf32 = nullptr;
+  float *grc32 = nullptr;
   // state
   double* U = nullptr;     // [nc][5]
   double* U0 = nullptr;    // [nc][5] state of the last state_init
