@@ -352,11 +352,15 @@ __global__ __launch_bounds__(kBlock) void k_grad(GradArgs<T> a) {
                  sStage[threadIdx.x >> 6]);
     return;
   }
-  // whole mesh in its own order: cells outside the key range are skipped
+  // whole mesh in its own order: cells outside the key range are skipped.
+  // A lane requests its cell's own data together with the cell's key (one
+  // trip to memory for both); a lane out of range computes its cell and
+  // stores nothing.
+  const int ic = idx < a.count ? idx : a.count - 1;
+  const GradIn<T> g = grad_load<T>(a, ic);
   const bool in = idx < a.count && a.key[idx] <= a.key_max;
-  const unsigned long long act = __ballot(in);
-  if (act == 0ull) return;  // the wave has no cell in range
-  grad_item<T>(a, in ? idx : w0 + (__ffsll(act) - 1), in, sStage[threadIdx.x >> 6]);
+  if (__ballot(in) == 0ull) return;  // the wave has no cell in range
+  grad_compute<T>(a, ic, in, sStage[threadIdx.x >> 6], g);
 }
 
 // ---------------------------------------------------------------------------

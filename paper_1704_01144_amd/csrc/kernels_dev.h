@@ -316,23 +316,39 @@ __device__ inline T col_load(const T* __restrict__ col, uint32_t byte_off) {
 // neighbour: a boundary slot loads the cell's own state, which the mirror
 // ghost then replaces, so no branch separates the neighbour loads.  The
 // sums accumulate neighbour by neighbour, j = 0..3.
+// What a cell reads by its own index: neighbour ids, state, coefficients.
 template <typename T>
-__device__ inline void grad_item(const GradArgs<T>& a, int i, bool valid, T* stage) {
+struct GradIn {
+  int nb[4];
+  double ui[5];
+  T cr[3][4];
+};
+
+template <typename T>
+__device__ inline GradIn<T> grad_load(const GradArgs<T>& a, int i) {
+  const int nc = a.nc;
+  const uint32_t o4 = (uint32_t)i * 4u, oT = (uint32_t)i * (uint32_t)sizeof(T);
+  GradIn<T> g;
+  for (int j = 0; j < 4; ++j) g.nb[j] = col_load(a.nb + (size_t)j * nc, o4);
+  for (int k = 0; k < 5; ++k) g.ui[k] = a.U[5 * (size_t)i + k];
+  for (int m = 0; m < 3; ++m)
+    for (int j = 0; j < 4; ++j) g.cr[m][j] = col_load(a.grc + (size_t)(4 * m + j) * nc, oT);
+  return g;
+}
+
+template <typename T>
+__device__ inline void grad_compute(const GradArgs<T>& a, int i, bool valid, T* stage,
+                                    const GradIn<T>& g) {
   const int nc = a.nc;
   FaceValueWriter<T> out(stage, i, valid);
-  const uint32_t o4 = (uint32_t)i * 4u, oT = (uint32_t)i * (uint32_t)sizeof(T);
-  int nb[4];
-  for (int j = 0; j < 4; ++j) nb[j] = col_load(a.nb + (size_t)j * nc, o4);
-  double ui[5];
-  for (int k = 0; k < 5; ++k) ui[k] = a.U[5 * (size_t)i + k];
+  const int* nb = g.nb;
+  const double* ui = g.ui;
   double un[4][5];
   for (int j = 0; j < 4; ++j) {
     const size_t src = 5 * (size_t)(nb[j] >= 0 ? nb[j] : i);
     for (int k = 0; k < 5; ++k) un[j][k] = a.U[src + k];
   }
-  T cr[3][4];
-  for (int m = 0; m < 3; ++m)
-    for (int j = 0; j < 4; ++j) cr[m][j] = col_load(a.grc + (size_t)(4 * m + j) * nc, oT);
+  const auto& cr = g.cr;
   double wd[5];
   cons2prim(ui, a.gm1, wd);
   T wi[5];
@@ -378,6 +394,11 @@ __device__ inline void grad_item(const GradArgs<T>& a, int i, bool valid, T* sta
     for (int m = 0; m < 4; ++m) out.put(m, k, wi[k] + psi * delta[m]);
   }
   out.flush(a.Wf, nc);
+}
+
+template <typename T>
+__device__ inline void grad_item(const GradArgs<T>& a, int i, bool valid, T* stage) {
+  grad_compute<T>(a, i, valid, stage, grad_load<T>(a, i));
 }
 
 // ---------------------------------------------------------------------------
@@ -790,20 +811,17 @@ __device__ inline void flux_feat_item(const FluxArgs<T>& a, bool valid, int4 r, 
   add_info(acc, info);
 }
 
-// Adds s_m q_m to acc for the faces m of cell i whose bit is set in act
-// (act != 0), in local face order: q_m the face's stored flux, s_m = +h_m
-// where the cell is the higher id of the face (bit 16 + m of pk), -h_m
-// otherwise; a moving mesh also adds -s_m sF to accv.  The 4 face ids, then
-// the fluxes of all the active faces, are requested together (an inactive
-// slot reads an active face's flux again and adds nothing), so the sum waits
-// on two trips to memory rather than two per face.
+// Adds s_m q_m to acc for the faces m of a cell whose bit is set in act
+// (act != 0), in local face order: f the cell's 4 face ids, q_m the face's
+// stored flux, s_m = +h_m where the cell is the higher id of the face
+// (bit 16 + m of pk), -h_m otherwise; a moving mesh also adds -s_m sF to
+// accv.  The fluxes of all the active faces are requested together (an
+// inactive slot reads an active face's flux again and adds nothing), so the
+// sum waits on one trip to memory rather than one per face.
 template <typename T, bool MOVE>
-__device__ inline void add_face_fluxes(int i, int nc, uint32_t pk, unsigned act, const double* h,
-                                       const int* __restrict__ c2f, const T* __restrict__ Q,
-                                       const double* __restrict__ sF, double* acc,
-                                       double& accv) {
-  int f[4];
-  for (int m = 0; m < 4; ++m) f[m] = c2f[m * nc + i];
+__device__ inline void add_face_fluxes(const int* f, uint32_t pk, unsigned act, const double* h,
+                                       const T* __restrict__ Q, const double* __restrict__ sF,
+                                       double* acc, double& accv) {
   const int fa = (act & 1u) ? f[0] : (act & 2u) ? f[1] : (act & 4u) ? f[2] : f[3];
   T q[4][5];
   double sv[4];
@@ -827,30 +845,29 @@ __device__ inline void add_face_fluxes(int i, int nc, uint32_t pk, unsigned act,
   }
 }
 
-// A cell ending its step applies its flux sum acc: U += acc / V on a fixed
-// mesh; on a moving mesh its content and volume change together (geometric
-// conservation), V' = V + accv, U' = (V U + acc) / V'.  Returns false on a
-// non-finite state or a non-positive volume.
+
+// A cell ending its step applies its flux sum acc to its state u0 and
+// volume v (both already loaded): U += acc / V on a fixed mesh; on a moving
+// mesh its content and volume change together (geometric conservation),
+// V' = V + accv, U' = (V U + acc) / V'.  Returns false on a non-finite state
+// or a non-positive volume.
 // (Vw: the writable volume array of a moving mesh, null otherwise)
 template <bool MOVE>
-__device__ inline bool apply_cell(int i, const double* acc, double accv,
-                                  const double* __restrict__ vol, double* __restrict__ Vw,
-                                  double* __restrict__ U) {
+__device__ inline bool apply_cell(int i, const double* acc, double accv, const double* u0,
+                                  double v, double* __restrict__ Vw, double* __restrict__ U) {
   bool bad = false;
   if (MOVE) {
-    double* V = Vw;
-    const double v = V[i], vn = v + accv;
+    const double vn = v + accv;
     for (int k = 0; k < 5; ++k) {
-      const double u = (v * U[5 * (size_t)i + k] + acc[k]) / vn;
+      const double u = (v * u0[k] + acc[k]) / vn;
       U[5 * (size_t)i + k] = u;
       bad |= !isfinite(u);
     }
-    V[i] = vn;
+    Vw[i] = vn;
     bad |= !(vn > 0.0);
   } else {
-    const double v = vol[i];
     for (int k = 0; k < 5; ++k) {
-      const double u = U[5 * (size_t)i + k] + acc[k] / v;
+      const double u = u0[k] + acc[k] / v;
       U[5 * (size_t)i + k] = u;
       bad |= !isfinite(u);
     }
@@ -873,7 +890,15 @@ __device__ inline bool cell_gather_item(int i, int nc, const uint32_t* __restric
                                         const double* __restrict__ sF = nullptr,
                                         double* __restrict__ Rv = nullptr,
                                         double* __restrict__ Vw = nullptr) {
+  // everything indexed by the cell alone is requested in one trip: the
+  // packed word, the face ids, the state and the volume (the last two are
+  // read whether or not the cell applies a sum now)
   const uint32_t pk = fpack[i];
+  int f[4];
+  for (int m = 0; m < 4; ++m) f[m] = c2f[m * nc + i];
+  double u0[5];
+  for (int k = 0; k < 5; ++k) u0[k] = U[5 * (size_t)i + k];
+  const double v0 = MOVE ? Vw[i] : vol[i];
   const int ti = (pk >> 20) & 15;
   double acc[5] = {0, 0, 0, 0, 0};
   double accv = 0.0;  // moving mesh: swept volume, -dt_f sF per face as the flux
@@ -881,8 +906,8 @@ __device__ inline bool cell_gather_item(int i, int nc, const uint32_t* __restric
     if (ti > tau_s) return true;  // applied at the step's start
     const double dtf = ldexp(dt_min, ti);
     const double h[4] = {dtf, dtf, dtf, dtf};
-    add_face_fluxes<T, MOVE>(i, nc, pk, 0xfu, h, c2f, Q, sF, acc, accv);
-    return apply_cell<MOVE>(i, acc, accv, vol, Vw, U);
+    add_face_fluxes<T, MOVE>(f, pk, 0xfu, h, Q, sF, acc, accv);
+    return apply_cell<MOVE>(i, acc, accv, u0, v0, Vw, U);
   }
   unsigned act = 0;
   double h[4];
@@ -896,11 +921,11 @@ __device__ inline bool cell_gather_item(int i, int nc, const uint32_t* __restric
   double* Ri = R + 5 * (size_t)i;
   for (int k = 0; k < 5; ++k) acc[k] = Ri[k];
   if (MOVE) accv = Rv[i];
-  if (act) add_face_fluxes<T, MOVE>(i, nc, pk, act, h, c2f, Q, sF, acc, accv);
+  if (act) add_face_fluxes<T, MOVE>(f, pk, act, h, Q, sF, acc, accv);
   if (ends) {
     for (int k = 0; k < 5; ++k) Ri[k] = 0.0;
     if (MOVE) Rv[i] = 0.0;
-    return apply_cell<MOVE>(i, acc, accv, vol, Vw, U);
+    return apply_cell<MOVE>(i, acc, accv, u0, v0, Vw, U);
   }
   for (int k = 0; k < 5; ++k) Ri[k] = acc[k];
   if (MOVE) Rv[i] = accv;
@@ -930,9 +955,11 @@ __device__ inline void predict_item(int i, int nc, const uint32_t* __restrict__ 
   double d[5];
   double* Di = D + 5 * (size_t)i;
   if (ti <= tau_s) {
+    int f[4];
+    for (int m = 0; m < 4; ++m) f[m] = c2f[m * nc + i];
     double acc[5] = {0, 0, 0, 0, 0}, accv = 0.0;
     const double one[4] = {1.0, 1.0, 1.0, 1.0};
-    add_face_fluxes<T, false>(i, nc, pk, 0xfu, one, c2f, Q0, nullptr, acc, accv);
+    add_face_fluxes<T, false>(f, pk, 0xfu, one, Q0, nullptr, acc, accv);
     const double dtc = ldexp(dt_min, ti), v = vol[i];
     for (int k = 0; k < 5; ++k) {
       d[k] = dtc * acc[k] / v;
@@ -959,7 +986,17 @@ __device__ inline bool cell_gather2_item(int i, int nc, const uint32_t* __restri
                                          double dt_min, const double* __restrict__ vol,
                                          double* __restrict__ U, double* __restrict__ Ut,
                                          double* __restrict__ R, int tau_upd) {
+  // the packed word, face ids, accumulator, state and volume in one trip
   const uint32_t pk = fpack[i];
+  int f[4];
+  for (int m = 0; m < 4; ++m) f[m] = c2f[m * nc + i];
+  double* Ri = R + 5 * (size_t)i;
+  double acc[5], u0[5], accv = 0.0;
+  for (int k = 0; k < 5; ++k) {
+    acc[k] = Ri[k];
+    u0[k] = U[5 * (size_t)i + k];
+  }
+  const double v = vol[i];
   const int ti = (pk >> 20) & 15;
   const bool ends = ti <= tau_upd;
   unsigned act = 0;
@@ -970,15 +1007,11 @@ __device__ inline bool cell_gather2_item(int i, int nc, const uint32_t* __restri
     act |= (unsigned)(tf <= tau_upd) << m;
   }
   if (!act && !ends) return true;
-  double acc[5], accv = 0.0;
-  double* Ri = R + 5 * (size_t)i;
-  for (int k = 0; k < 5; ++k) acc[k] = Ri[k];
-  if (act) add_face_fluxes<T, false>(i, nc, pk, act, h, c2f, Q, nullptr, acc, accv);
+  if (act) add_face_fluxes<T, false>(f, pk, act, h, Q, nullptr, acc, accv);
   if (ends) {
-    const double v = vol[i];
     bool bad = false;
     for (int k = 0; k < 5; ++k) {
-      const double u = U[5 * (size_t)i + k] + acc[k] / v;
+      const double u = u0[k] + acc[k] / v;
       U[5 * (size_t)i + k] = u;
       Ut[5 * (size_t)i + k] = u;
       Ri[k] = 0.0;
