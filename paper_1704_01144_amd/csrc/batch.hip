@@ -536,9 +536,8 @@ __global__ __launch_bounds__(kBlock) void k_b_flux(const int32_t* __restrict__ t
 }
 
 template <int ORDER, typename T, int FEAT>
-__global__ __launch_bounds__(kBlock) void k_b_flux_feat(const int32_t* __restrict__ tp,
-                                                        const BatchSched* S, int M,
-                                                        FluxArgs<T> a) {
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(kFeatWaves<T>)))
+void k_b_flux_feat(const int32_t* __restrict__ tp, const BatchSched* S, int M, FluxArgs<T> a) {
   __shared__ __attribute__((aligned(16))) uint16_t lds[(FEAT & 2) ? (kBlock / 64) * kMlpFwdLds : 8];
   constexpr int Q = kBlock / kUnit;
   const int total = tp[M];

@@ -420,7 +420,8 @@ __global__ __launch_bounds__(kBlock) void k_flux_store(FluxArgs<T> a) {
 // gamma = 1.4 flux with the optional features (statistics and face logging,
 // learned guess)
 template <int ORDER, typename T, int FEAT>
-__global__ __launch_bounds__(kBlock) void k_flux_feat(FluxArgs<T> a) {
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(kFeatWaves<T>)))
+void k_flux_feat(FluxArgs<T> a) {
   __shared__ __attribute__((aligned(16))) uint16_t lds[(FEAT & 2) ? (kBlock / 64) * kMlpFwdLds : 8];
   int idx = xcd_block() * kBlock + threadIdx.x;
   const bool valid = idx < a.count;

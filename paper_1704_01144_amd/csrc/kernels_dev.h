@@ -658,22 +658,31 @@ __device__ inline unsigned long long mix64(unsigned long long z) {
 //             y ~ ln(p*/p_TR); where |y| exceeds the gate the Newton solve
 //             starts from p_TR exp(y) (a non-finite or non-positive guess
 //             falls back to p_TR).  The network runs once per wave, on the
-//             matrix cores, when any lane of the wave needs it.
+//             matrix cores, when any face of the wave passes the strength
+//             pre-gate; that test needs only the two states, so only they
+//             and the inputs are kept across the network pass, and the
+//             two-rarefaction value is formed after it.
 // The Newton iteration and its stop test are unchanged, so p* is the same
 // root whichever start is used.  All 64 lanes of a wave must call this
 // together (valid = false for lanes without a face); wave_lds is this
 // wave's kMlpFwdLds elements of LDS.
+// Waves per SIMD asked of the kernels that call flux_feat_item: left to
+// itself the compiler parks live values in accumulator registers around the
+// network pass and settles at 4; the FP32 forms fit 5 without spilling.
+template <typename T>
+constexpr int kFeatWaves = sizeof(T) == 4 ? 5 : 4;
+
 template <int ORDER, typename T, int FEAT>
 __device__ inline void flux_feat_item(const FluxArgs<T>& a, bool valid, int4 r, double dt_min,
                                       uint16_t* wave_lds, SolveInfo& acc, double& i0,
                                       double& i1, double& i2) {
   const Gas& G = a.s.gas;
   SolveInfo info{0, 0, 0, 0, 0, 0, 0, 0};
+  // 1. the face's states and normal, the network's inputs and the strength
+  // pre-gate: all that is kept across the wave's network pass
   T wl[5] = {1, 0, 0, 0, 1}, wr[5] = {1, 0, 0, 0, 1};
   T am = 1, nx = 1, ny = 0, nz = 0, unl = 0, unr = 0;
-  bool wall = false, transmit = false, vac = false, gate = false, net = false;
-  double al = 1, ar = 1, ral = 1, rar = 1, ptr = -1.0, pm = 1.0;
-  K14 KL{}, KR{};
+  bool wall = false, transmit = false, net = false;
   float x[kMlpIn] = {0, 0, 0, 0, 0, 0};
   if (valid) {
     const int f = r.x;
@@ -689,49 +698,27 @@ __device__ inline void flux_feat_item(const FluxArgs<T>& a, bool valid, int4 r, 
     ny = ay * ia;
     nz = az * ia;
     unl = wl[1] * nx + wl[2] * ny + wl[3] * nz;
-    if (!transmit) {
-      double rl = wl[0], pl = wl[4];
-      double irl = frcp(rl), a2l = G.g * pl * irl;
-      ral = frsq(a2l);
-      al = a2l * ral;
-      KL = make_k14(G, pl, al, irl, ral);
-      if (wall) {
-        unr = -unl;
-        ar = al;
-        rar = ral;
-        KR = KL;
-      } else {
-        unr = wr[1] * nx + wr[2] * ny + wr[3] * nz;
-        double rr = wr[0], pr = wr[4];
-        double irr = frcp(rr), a2r = G.g * pr * irr;
-        rar = frsq(a2r);
-        ar = a2r * rar;
-        KR = make_k14(G, pr, ar, irr, rar);
-      }
-      vac = G.two_gm1 * (al + ar) <= (double)unr - (double)unl;
-      if (!vac) {
-        ptr = tr14(G, unl, unr, al, ar, KL, KR).p;
-        gate = !wall && ptr > fmin(KL.p, KR.p);
-      }
-      if (gate) {  // deviations from the face mean, normalised by it
-        double rl = wl[0], rr = wr[0];
-        double rm = 0.5 * (rl + rr);
-        pm = 0.5 * (KL.p + KR.p);
-        double amean = sqrt(G.g * pm / rm);
-        double dr = (rl - rr) / (rl + rr), dp = (KL.p - KR.p) / (KL.p + KR.p);
-        double du = 0.5 * ((double)unl - (double)unr) / amean;
-        x[0] = (float)dr;
-        x[1] = (float)du;
-        x[2] = (float)dp;
-        x[3] = (float)-dr;
-        x[4] = (float)-du;
-        x[5] = (float)-dp;
-        net = 2.f * (fabsf(x[1]) + fabsf(x[2])) >= a.guess_strength;
-      }
+    unr = wall ? -unl : wr[1] * nx + wr[2] * ny + wr[3] * nz;
+    if (r.z >= 0) {  // deviations from the face mean, normalised by it
+      double rl = wl[0], rr = wr[0], pl = wl[4], pr = wr[4];
+      double rm = 0.5 * (rl + rr), pm = 0.5 * (pl + pr);
+      double amean = sqrt(G.g * pm / rm);
+      double dr = (rl - rr) / (rl + rr), dp = (pl - pr) / (pl + pr);
+      double du = 0.5 * ((double)unl - (double)unr) / amean;
+      x[0] = (float)dr;
+      x[1] = (float)du;
+      x[2] = (float)dp;
+      x[3] = (float)-dr;
+      x[4] = (float)-du;
+      x[5] = (float)-dp;
+      net = (FEAT & 2) && 2.f * (fabsf(x[1]) + fabsf(x[2])) >= a.guess_strength;
     }
   }
+  // 2. the network, once per wave, where any face passes the pre-gate
   float ym = 0.f;
   if ((FEAT & 2) && __ballot(net) != 0ull) ym = mlp_wave_forward(*a.mlp, x, wave_lds);
+  // 3. the face solve: two-rarefaction value, the network's start where the
+  // two-rarefaction value is inexact, Newton, sampling, flux
   if (valid) {
     T phi[5];
     if (transmit) {
@@ -742,22 +729,43 @@ __device__ inline void flux_feat_item(const FluxArgs<T>& a, bool valid, int4 r, 
       phi[3] = am * (wl[0] * unl * wl[3] + wl[4] * nz);
       phi[4] = am * unl * (E + wl[4]);
     } else {
-      double guess = ptr;
-      if ((FEAT & 2) && net) info.evaluated = 1;
-      if ((FEAT & 2) && net && fabsf(ym) > a.guess_gate) {
-        double gm = ptr * exp((double)ym);
-        if (gm > 0.0 && isfinite(gm)) {
-          guess = gm;
-          info.used = 1;
-        } else {
-          info.rejected = 1;
+      const double rl = wl[0], pl = wl[4];
+      const double rr = wall ? rl : (double)wr[0], pr = wall ? pl : (double)wr[4];
+      double irl = frcp(rl), a2l = G.g * pl * irl;
+      const double ral = frsq(a2l), al = a2l * ral;
+      const K14 KL = make_k14(G, pl, al, irl, ral);
+      double ar = al, rar = ral;
+      K14 KR = KL;
+      if (!wall) {
+        double irr = frcp(rr), a2r = G.g * pr * irr;
+        rar = frsq(a2r);
+        ar = a2r * rar;
+        KR = make_k14(G, pr, ar, irr, rar);
+      }
+      const bool vac = G.two_gm1 * (al + ar) <= (double)unr - (double)unl;
+      TR14 tr{};
+      double guess = -1.0;  // the two-rarefaction value
+      bool gate = false;
+      if (!vac) {
+        tr = tr14(G, unl, unr, al, ar, KL, KR);
+        gate = !wall && tr.p > fmin(KL.p, KR.p);
+        guess = tr.p;
+      }
+      if ((FEAT & 2) && gate && net) {
+        info.evaluated = 1;
+        if (fabsf(ym) > a.guess_gate) {
+          double gm = tr.p * exp((double)ym);
+          if (gm > 0.0 && isfinite(gm)) {
+            guess = gm;
+            info.used = 1;
+          } else {
+            info.rejected = 1;
+          }
         }
       }
-      // (the start's rarefaction roots are not carried in from the
-      // two-rarefaction value here: kept live across the network pass they
-      // would spill registers)
+      // (with vacuum data the solver returns before it looks at tr)
       Star st = solve_star14(G, unl, unr, al, ar, KL, KR, a.s.newton_tol, a.s.newton_max_iter,
-                             guess);
+                             guess, &tr);
       info.iters = st.iters;
       info.fallback = st.fallback;
       info.vacuum = st.vacuum;
@@ -771,7 +779,7 @@ __device__ inline void flux_feat_item(const FluxArgs<T>& a, bool valid, int4 r, 
             if (slot < (unsigned long long)a.log_cap) {
               float* row = a.log_rows + 7 * slot;
               for (int k = 0; k < kMlpIn; ++k) row[k] = x[k];
-              row[6] = (float)log(st.p / ptr);
+              row[6] = (float)log(st.p / tr.p);
             }
           }
         }
