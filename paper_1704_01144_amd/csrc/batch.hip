@@ -530,7 +530,8 @@ __global__ __launch_bounds__(kBlock) void k_b_flux(const int32_t* __restrict__ t
     int m = mesh_after(tp, find_mesh(tp, M, u0), u);
     int j = (u - tp[m]) * kUnit + (int)(threadIdx.x % kUnit);
     if (j < S[m].n_flux)
-      flux_store_item<ORDER, T, G14>(a, a.rec[S[m].f0 + j], S[m].dt_min, info, i0, i1, i2);
+      flux_store_item<ORDER, T, G14>(a, nt_rec(a.rec + S[m].f0 + j), S[m].dt_min, info, i0, i1,
+                                     i2);
   }
   flush_counters(info, i0, i1, i2, a.dcount, a.dimpulse);
 }
@@ -550,7 +551,7 @@ void k_b_flux_feat(const int32_t* __restrict__ tp, const BatchSched* S, int M, F
     int m = mesh_after(tp, find_mesh(tp, M, u0), u);
     int j = (u - tp[m]) * kUnit + (int)(threadIdx.x % kUnit);
     const bool valid = j < S[m].n_flux;
-    int4 r = valid ? a.rec[S[m].f0 + j] : make_int4(0, 0, -1, 0);
+    int4 r = valid ? nt_rec(a.rec + S[m].f0 + j) : make_int4(0, 0, -1, 0);
     flux_feat_item<ORDER, T, FEAT>(a, valid, r, S[m].dt_min,
                                    lds + (threadIdx.x >> 6) * kMlpFwdLds, info, i0, i1, i2);
   }

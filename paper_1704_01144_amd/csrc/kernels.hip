@@ -413,7 +413,7 @@ __global__ __launch_bounds__(kBlock) void k_flux_store(FluxArgs<T> a) {
   SolveInfo info{0, 0, 0, 0, 0, 0, 0, 0};
   double i0 = 0, i1 = 0, i2 = 0;
   if (idx < a.count)
-    flux_store_item<ORDER, T, G14, MOVE>(a, a.rec[idx], a.s.dt_min, info, i0, i1, i2);
+    flux_store_item<ORDER, T, G14, MOVE>(a, nt_rec(a.rec + idx), a.s.dt_min, info, i0, i1, i2);
   flush_counters(info, i0, i1, i2, a.dcount, a.dimpulse);
 }
 
@@ -427,7 +427,7 @@ void k_flux_feat(FluxArgs<T> a) {
   const bool valid = idx < a.count;
   SolveInfo info{0, 0, 0, 0, 0, 0, 0, 0};
   double i0 = 0, i1 = 0, i2 = 0;
-  int4 r = valid ? a.rec[idx] : make_int4(0, 0, -1, 0);
+  int4 r = valid ? nt_rec(a.rec + idx) : make_int4(0, 0, -1, 0);
   flux_feat_item<ORDER, T, FEAT>(a, valid, r, a.s.dt_min, lds + (threadIdx.x >> 6) * kMlpFwdLds,
                                  info, i0, i1, i2);
   flush_counters(info, i0, i1, i2, a.dcount, a.dimpulse);

@@ -279,7 +279,10 @@ struct FaceValueWriter {
       const int d = 64 * j + lane, src = d / 5, kk = d - 5 * src;
       const int cell = __shfl(mine, src, 64);
       if (cell < 0) continue;
-      for (int m = 0; m < 4; ++m) Wf[((size_t)m * nc + cell) * 5 + kk] = st[m * 320 + d];
+      // non-temporal: the face values are read once, by the next kernel;
+      // kept out of the way of the neighbour states in L2
+      for (int m = 0; m < 4; ++m)
+        __builtin_nontemporal_store(st[m * 320 + d], &Wf[((size_t)m * nc + cell) * 5 + kk]);
     }
   }
 };
@@ -327,12 +330,14 @@ struct GradIn {
 template <typename T>
 __device__ inline GradIn<T> grad_load(const GradArgs<T>& a, int i) {
   const int nc = a.nc;
-  const uint32_t o4 = (uint32_t)i * 4u, oT = (uint32_t)i * (uint32_t)sizeof(T);
+  const uint32_t o4 = (uint32_t)i * 4u;
   GradIn<T> g;
   for (int j = 0; j < 4; ++j) g.nb[j] = col_load(a.nb + (size_t)j * nc, o4);
   for (int k = 0; k < 5; ++k) g.ui[k] = a.U[5 * (size_t)i + k];
+  // the coefficients are read once per item: non-temporal
   for (int m = 0; m < 3; ++m)
-    for (int j = 0; j < 4; ++j) g.cr[m][j] = col_load(a.grc + (size_t)(4 * m + j) * nc, oT);
+    for (int j = 0; j < 4; ++j)
+      g.cr[m][j] = __builtin_nontemporal_load(a.grc + (size_t)(4 * m + j) * nc + i);
   return g;
 }
 
@@ -468,6 +473,20 @@ __device__ inline void load_side(const FluxArgs<T>& a, int h, T* w) {
   }
 }
 
+// Non-temporal loads of what a kernel reads once (face records, face
+// areas): they do not displace the states and face values other items of
+// the launch read again.  (Face values themselves are read once too, but
+// loading them non-temporally made the flux kernel slower.)
+template <typename T>
+__device__ inline T nt_load(const T* p) {
+  return __builtin_nontemporal_load(p);
+}
+typedef int tafv_i4v __attribute__((ext_vector_type(4)));
+__device__ inline int4 nt_rec(const int4* p) {
+  const tafv_i4v v = __builtin_nontemporal_load(reinterpret_cast<const tafv_i4v*>(p));
+  return make_int4(v.x, v.y, v.z, v.w);
+}
+
 struct SolveInfo {
   int iters, fallback, vacuum;
   int gated, gated_iters, rejected, used;  // faces where two-rarefaction is inexact
@@ -497,7 +516,8 @@ template <int ORDER, typename T, bool G14, bool MOVE = false>
 __device__ inline void face_flux(const FluxArgs<T>& a, int4 r, T* phi, SolveInfo& info) {
   const Gas& G = a.s.gas;
   const int f = r.x, hL = r.y, hR = r.z;
-  T ax = a.fA[f], ay = a.fA[a.nf + f], az = a.fA[2 * (size_t)a.nf + f];
+  T ax = nt_load(a.fA + f), ay = nt_load(a.fA + a.nf + f);
+  T az = nt_load(a.fA + 2 * (size_t)a.nf + f);
   T wl[5], wr[5];
   load_side<ORDER, T>(a, hL, wl);
   if (hR >= 0) load_side<ORDER, T>(a, hR, wr);
@@ -686,7 +706,8 @@ __device__ inline void flux_feat_item(const FluxArgs<T>& a, bool valid, int4 r, 
   float x[kMlpIn] = {0, 0, 0, 0, 0, 0};
   if (valid) {
     const int f = r.x;
-    T ax = a.fA[f], ay = a.fA[a.nf + f], az = a.fA[2 * (size_t)a.nf + f];
+    T ax = nt_load(a.fA + f), ay = nt_load(a.fA + a.nf + f);
+    T az = nt_load(a.fA + 2 * (size_t)a.nf + f);
     load_side<ORDER, T>(a, r.y, wl);
     wall = r.z < 0 && a.s.boundary == TAFV_BC_WALL;
     transmit = r.z < 0 && !wall;
