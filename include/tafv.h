@@ -337,7 +337,9 @@ tafv_status tafv_mlp_train(tafv_ctx* ctx, const float* x, const float* t, int64_
  * hash of seed, face and subiteration) of the face solves where the
  * two-rarefaction start is inexact writes a row of 7 floats (the 6 network
  * inputs and the target ln(p_star / p_TR)) until `capacity` rows are held.
- * capacity 0 turns logging off.  Reading returns min(rows logged, cap). */
+ * capacity 0 turns logging off.  Reading returns min(rows logged, cap)
+ * rows, in an order fixed by their contents (sorted by their bytes), not
+ * by which wave logged them first. */
 tafv_status tafv_facelog_config(tafv_ctx* ctx, int64_t capacity, double rate, uint64_t seed);
 tafv_status tafv_facelog_read(tafv_ctx* ctx, float* rows, int64_t cap, int64_t* n_rows);
 

@@ -7,6 +7,7 @@
 #include <cstring>
 #include <new>
 #include <string>
+#include <vector>
 
 #include "kernels.h"
 #include "mlp_kernels.h"
@@ -1129,11 +1130,24 @@ tafv_status tafv_facelog_read(tafv_ctx* c, float* rows, int64_t cap, int64_t* n_
   unsigned long long cnt = 0;
   HIP_TRY(c, hipMemcpyAsync(&cnt, c->log_count, sizeof(cnt), hipMemcpyDeviceToHost, c->stream));
   HIP_TRY(c, hipStreamSynchronize(c->stream));
-  int64_t k = std::min<int64_t>((int64_t)std::min<unsigned long long>(cnt, (unsigned long long)c->log_cap), cap);
+  // The waves take row slots in the order they reach the counter, which
+  // varies from run to run; the rows held are returned sorted by their
+  // bytes, so that a run's rows (and what is trained on them) do not
+  // depend on it.
+  const int64_t held = (int64_t)std::min<unsigned long long>(cnt, (unsigned long long)c->log_cap);
+  const int64_t k = std::min<int64_t>(held, cap);
   if (k > 0) {
-    HIP_TRY(c, hipMemcpyAsync(rows, c->log_rows, (size_t)k * 7 * sizeof(float),
+    std::vector<float> all((size_t)held * 7);
+    HIP_TRY(c, hipMemcpyAsync(all.data(), c->log_rows, all.size() * sizeof(float),
                               hipMemcpyDeviceToHost, c->stream));
     HIP_TRY(c, hipStreamSynchronize(c->stream));
+    std::vector<int64_t> order((size_t)held);
+    for (int64_t r = 0; r < held; ++r) order[(size_t)r] = r;
+    std::sort(order.begin(), order.end(), [&](int64_t a, int64_t b) {
+      return std::memcmp(&all[(size_t)a * 7], &all[(size_t)b * 7], 7 * sizeof(float)) < 0;
+    });
+    for (int64_t r = 0; r < k; ++r)
+      std::memcpy(rows + (size_t)r * 7, &all[(size_t)order[(size_t)r] * 7], 7 * sizeof(float));
   }
   *n_rows = k;
   return TAFV_OK;

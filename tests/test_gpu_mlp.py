@@ -134,6 +134,31 @@ def test_face_log_rows_are_exact(T, orc, trained):
         assert abs(np.log(rs.p_star / ptr) - r[6]) < 2e-5 * (1 + abs(r[6]))
 
 
+def test_face_log_and_training_reproducible(T):
+    """Two runs log the same rows in the same order (the rows are sorted by
+    their bytes on readback, whichever wave took which slot), and training
+    on them twice gives the same network bit for bit."""
+    nodes, tets = I.graded_cube_mesh(16, 16.0)
+    prim = I.blast_state(nodes, tets, centre=I.blast_centre(2))
+    logs, thetas = [], []
+    for _ in range(2):
+        s = T.Solver(max_levels=5, order=2, guess_stats=1)
+        s.upload(nodes, tets)
+        s.init(prim)
+        T.tafv_facelog_config(s.ctx, 100000, 0.5, 7)
+        s.advance(8)
+        rows = T.tafv_facelog_read(s.ctx, 100000)
+        T.tafv_mlp_set(s.ctx, M.he_uniform(3).astype(np.float32))
+        T.tafv_mlp_train(s.ctx, rows[:, :6], rows[:, 6], epochs=3, batch=1024, lr=2e-3, seed=5)
+        thetas.append(T.tafv_mlp_get(s.ctx))
+        logs.append(rows)
+        s.close()
+    say(f"reproducible face log: {len(logs[0])} rows")
+    assert len(logs[0]) > 100
+    assert np.array_equal(logs[0].view(np.uint32), logs[1].view(np.uint32))
+    assert np.array_equal(thetas[0].view(np.uint32), thetas[1].view(np.uint32))
+
+
 def _newton_updates(orc, rows, y, gate):
     """Newton updates on the oracle's solver from p_TR, or from p_TR exp(y)
     where |y| > gate."""
