@@ -606,18 +606,13 @@ __device__ inline void face_flux(const FluxArgs<T>& a, int4 r, T* phi, SolveInfo
   if (MOVE) phi[4] += am * ps * xi;
 }
 
-// Counters are spread over kCountSlots slots 128 bytes apart (slot = block
+// Counters are spread over kCountSlots slots 128 bytes apart (slot = wave
 // index modulo kCountSlots) so that the waves of a launch do not all
-// serialise on one address; the host sums the slots.  Called once per block
-// by all its threads.
+// serialise on one address; the host sums the slots.  Called by all lanes
+// of a wave; each wave adds its sums with its first lane, so the waves of a
+// block do not wait for each other.
 __device__ inline void flush_counters(const SolveInfo& info, double i0, double i1, double i2,
                                       unsigned long long* dcount, double* dimpulse) {
-  __shared__ int s_cnt[8];
-  __shared__ double s_imp[3];
-  __syncthreads();  // a previous call's readers are done
-  if (threadIdx.x < 8) s_cnt[threadIdx.x] = 0;
-  if (threadIdx.x < 3) s_imp[threadIdx.x] = 0.0;
-  __syncthreads();
   int c[8] = {wave_sum(info.iters), wave_sum(info.fallback), wave_sum(info.vacuum),
               wave_sum(info.gated), wave_sum(info.gated_iters), wave_sum(info.rejected),
               wave_sum(info.used), wave_sum(info.evaluated)};
@@ -625,24 +620,15 @@ __device__ inline void flush_counters(const SolveInfo& info, double i0, double i
   i1 = wave_sum(i1);
   i2 = wave_sum(i2);
   if ((threadIdx.x & 63) == 0) {
+    const int slot = (int)((blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6)) % kCountSlots);
+    unsigned long long* cs = dcount + slot * kSlotStride;
     for (int k = 0; k < 8; ++k)
-      if (c[k]) atomicAdd(&s_cnt[k], c[k]);
+      if (c[k]) atomicAdd(&cs[k], (unsigned long long)c[k]);
     if (i0 != 0.0 || i1 != 0.0 || i2 != 0.0) {
-      atomicAdd(&s_imp[0], i0);
-      atomicAdd(&s_imp[1], i1);
-      atomicAdd(&s_imp[2], i2);
-    }
-  }
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    unsigned long long* cs = dcount + (blockIdx.x % kCountSlots) * kSlotStride;
-    for (int k = 0; k < 8; ++k)
-      if (s_cnt[k]) atomicAdd(&cs[k], (unsigned long long)s_cnt[k]);
-    if (s_imp[0] != 0.0 || s_imp[1] != 0.0 || s_imp[2] != 0.0) {
-      double* d = dimpulse + (blockIdx.x % kCountSlots) * kSlotStride;
-      atomicAdd(&d[0], s_imp[0]);
-      atomicAdd(&d[1], s_imp[1]);
-      atomicAdd(&d[2], s_imp[2]);
+      double* d = dimpulse + slot * kSlotStride;
+      atomicAdd(&d[0], i0);
+      atomicAdd(&d[1], i1);
+      atomicAdd(&d[2], i2);
     }
   }
 }
