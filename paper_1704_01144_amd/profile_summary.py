@@ -13,6 +13,12 @@ kept with the sources.
       run), and the HBM bytes per launch that follow.  The record also holds
       the SHA-256 of the library sources, so that a reader can tell whether
       the kernels changed after the counters were taken.
+
+  python -m paper_1704_01144_amd.profile_summary sq --kernel SUBSTR \
+      --dir DIR [--dir DIR ...] --command CMD [--command CMD ...]
+      per-wave means of SQ counters (each divided by SQ_WAVES of the same
+      dispatches) for each kernel whose name contains a SUBSTR, from one
+      or more --pmc runs that each also collected SQ_WAVES.
 """
 import argparse
 import csv
@@ -112,6 +118,33 @@ def counters_text(a):
     return "\n".join(lines) + "\n"
 
 
+def sq_text(a):
+    """Per-wave SQ counter means of the named kernels over the given runs."""
+    per = {}  # kernel -> counter -> [sum, dispatches]; waves per run
+    for d in a.dir:
+        rows = list(csv.DictReader(open(_one(os.path.join(d, "*counter_collection.csv")))))
+        for sub in a.kernel:
+            sel = [r for r in rows if sub in r["Kernel_Name"]]
+            waves = sum(float(r["Counter_Value"]) for r in sel if r["Counter_Name"] == "SQ_WAVES")
+            if not sel or waves == 0:
+                raise SystemExit(f"no SQ_WAVES for a kernel containing {sub!r} in {d}")
+            k = per.setdefault(sub, {})
+            k.setdefault("SQ_WAVES", sum(1 for r in sel if r["Counter_Name"] == "SQ_WAVES"))
+            for r in sel:
+                if r["Counter_Name"] != "SQ_WAVES":
+                    k[r["Counter_Name"]] = k.get(r["Counter_Name"], 0.0) + \
+                        float(r["Counter_Value"]) / waves
+    lines = [f"command: {c}" for c in a.command]
+    lines.append(f"sources_sha256: {source_digest()}")
+    lines.append("per-wave means (counter / SQ_WAVES over the same dispatches)")
+    for sub in a.kernel:
+        k = per[sub]
+        lines.append(f"kernel: {sub} ({k['SQ_WAVES']} dispatches per run)")
+        for name in sorted(x for x in k if x != "SQ_WAVES"):
+            lines.append(f"  {name}: {k[name]:.1f}")
+    return "\n".join(lines) + "\n"
+
+
 def read_record(path):
     """key: value lines of a counter record -> dict (repeated keys -> list)."""
     out = {}
@@ -144,9 +177,15 @@ def main(argv=None):
     c.add_argument("--copy-write", required=True)
     c.add_argument("--copy-bytes", type=int, required=True)
     c.add_argument("--command", action="append", required=True)
+    q = sub.add_parser("sq")
+    q.add_argument("--kernel", action="append", required=True)
+    q.add_argument("--dir", action="append", required=True)
+    q.add_argument("--command", action="append", required=True)
     a = ap.parse_args(argv)
     if a.what == "stats":
         sys.stdout.write(stats_text(a.dir, a.command, a.top))
+    elif a.what == "sq":
+        sys.stdout.write(sq_text(a))
     else:
         sys.stdout.write(counters_text(a))
 

@@ -59,6 +59,30 @@ def test_stats_summary(tmp_path, capsys):
     assert "all kernels (2 names)" in out[-1]
 
 
+def test_sq_per_wave_means(tmp_path, capsys):
+    d = str(tmp_path)
+    # two dispatches of one kernel: 100 + 300 waves, 1000 + 5000 VALU
+    # instructions -> 15 per wave; a second run adds another counter
+    _counter_csv(f"{d}/a", [("void k_grad<double>(x)", "SQ_WAVES", 100.0),
+                            ("void k_grad<double>(x)", "SQ_INSTS_VALU", 1000.0),
+                            ("void k_grad<double>(x)", "SQ_WAVES", 300.0),
+                            ("void k_grad<double>(x)", "SQ_INSTS_VALU", 5000.0),
+                            ("void k_flux(x)", "SQ_WAVES", 7.0),
+                            ("void k_flux(x)", "SQ_INSTS_VALU", 70000.0)])
+    _counter_csv(f"{d}/b", [("void k_grad<double>(x)", "SQ_WAVES", 100.0),
+                            ("void k_grad<double>(x)", "SQ_WAIT_INST_ANY", 500.0),
+                            ("void k_grad<double>(x)", "SQ_WAVES", 300.0),
+                            ("void k_grad<double>(x)", "SQ_WAIT_INST_ANY", 1500.0)])
+    P.main(["sq", "--kernel", "k_grad<double", "--dir", f"{d}/a", "--dir", f"{d}/b",
+            "--command", "run a", "--command", "run b"])
+    out = capsys.readouterr().out
+    assert "  SQ_INSTS_VALU: 15.0" in out and "  SQ_WAIT_INST_ANY: 5.0" in out
+    assert "kernel: k_grad<double (2 dispatches per run)" in out
+    assert "command: run a" in out and "command: run b" in out
+    with pytest.raises(SystemExit):
+        P.main(["sq", "--kernel", "k_none", "--dir", f"{d}/a", "--command", "x"])
+
+
 def test_roofline_arithmetic():
     import bench
     prof = {"grad": dict(ms=10.0, launches=100, items=1000000),
