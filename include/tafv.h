@@ -203,11 +203,17 @@ tafv_status tafv_mesh_upload(tafv_ctx* ctx, int64_t n_nodes, const double* xyz,
  * library's face order (colour-major), face_colour [n_faces],
  * face_area [n_faces][3] (area vector out of the lower cell),
  * cell_neighbours [n_tets][4] (cell across local face m = the face opposite
- * vertex m, -1 on the boundary).  Errors as tafv_mesh_upload. */
+ * vertex m, -1 on the boundary), recon_coef [n_tets][3][4] (a_mj = c_j . r_m
+ * for m < 3: c_j the least-squares coefficient vector of neighbour j, or of
+ * its mirror ghost, and r_m the offset of face centroid m from the cell
+ * centroid; the reconstruction's change to face centroid m is
+ * sum_j a_mj (W_j - W_i), and to face 3 minus the sum of the other three,
+ * Sec. 2.1).  Errors as tafv_mesh_upload. */
 tafv_status tafv_mesh_inspect(int64_t n_nodes, const double* xyz, int64_t n_tets,
                               const int64_t* tets, int64_t* n_faces, int64_t* n_boundary,
                               int32_t* n_colours, int32_t* face_cells, int8_t* face_colour,
-                              double* face_area, int32_t* cell_neighbours);
+                              double* face_area, int32_t* cell_neighbours,
+                              double* recon_coef);
 
 /* Per-mesh level cap (1..8), overriding params.max_levels for that mesh. */
 tafv_status tafv_mesh_params(tafv_ctx* ctx, int32_t mesh_id, int32_t max_levels);

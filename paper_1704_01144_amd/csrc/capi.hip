@@ -611,7 +611,8 @@ tafv_status tafv_mesh_upload(tafv_ctx* c, int64_t n_nodes, const double* xyz, in
 tafv_status tafv_mesh_inspect(int64_t n_nodes, const double* xyz, int64_t n_tets,
                               const int64_t* tets, int64_t* n_faces, int64_t* n_boundary,
                               int32_t* n_colours, int32_t* face_cells, int8_t* face_colour,
-                              double* face_area, int32_t* cell_neighbours) {
+                              double* face_area, int32_t* cell_neighbours,
+                              double* recon_coef) {
   if (!xyz || !tets || n_nodes < 4 || n_tets < 1) return fail(nullptr, TAFV_E_ARG, "invalid mesh");
   HostMesh hm;
   std::string err;
@@ -636,6 +637,9 @@ tafv_status tafv_mesh_inspect(int64_t n_nodes, const double* xyz, int64_t n_tets
         int32_t n = hm.nb[m * hm.nc + i];
         cell_neighbours[4 * (int64_t)perm[i] + m] = n >= 0 ? perm[n] : -1;
       }
+  if (recon_coef)
+    for (int64_t i = 0; i < hm.nc; ++i)
+      for (int k = 0; k < 12; ++k) recon_coef[12 * (int64_t)perm[i] + k] = hm.grc[k * hm.nc + i];
   return TAFV_OK;
 }
 

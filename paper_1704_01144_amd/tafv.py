@@ -73,7 +73,7 @@ def _load():
         "tafv_mesh_motion": [P, C.c_int32, dp],
         "tafv_volume_read": [P, C.c_int32, dp],
         "tafv_mesh_inspect": [C.c_int64, dp, C.c_int64, i64p, i64p, i64p, i32p, i32p, i8p, dp,
-                              i32p],
+                              i32p, dp],
         "tafv_state_init": [P, C.c_int32, dp],
         "tafv_advance": [P, C.c_int64, C.POINTER(tafv_stats)],
         "tafv_state_reset": [P, C.c_int32],
@@ -162,18 +162,19 @@ def tafv_mesh_inspect(nodes, tets):
     t64 = tets.ctypes.data_as(C.POINTER(C.c_int64))
     nf, nb, ncol = C.c_int64(), C.c_int64(), C.c_int32()
     _check(lib.tafv_mesh_inspect(nodes.shape[0], _d(nodes), tets.shape[0], t64, C.byref(nf),
-                                 C.byref(nb), C.byref(ncol), None, None, None, None))
+                                 C.byref(nb), C.byref(ncol), None, None, None, None, None))
     fc = np.empty((nf.value, 2), np.int32)
     col = np.empty(nf.value, np.int8)
     area = np.empty((nf.value, 3))
     nbr = np.empty((tets.shape[0], 4), np.int32)
+    coef = np.empty((tets.shape[0], 3, 4))
     _check(lib.tafv_mesh_inspect(nodes.shape[0], _d(nodes), tets.shape[0], t64, C.byref(nf),
                                  C.byref(nb), C.byref(ncol),
                                  fc.ctypes.data_as(C.POINTER(C.c_int32)),
                                  col.ctypes.data_as(C.POINTER(C.c_int8)), _d(area),
-                                 nbr.ctypes.data_as(C.POINTER(C.c_int32))))
+                                 nbr.ctypes.data_as(C.POINTER(C.c_int32)), _d(coef)))
     return dict(n_faces=nf.value, n_boundary=nb.value, n_colours=ncol.value, face_cells=fc,
-                face_colour=col, face_area=area, cell_neighbours=nbr)
+                face_colour=col, face_area=area, cell_neighbours=nbr, recon_coef=coef)
 
 
 def tafv_mesh_params(ctx, mesh_id, max_levels):

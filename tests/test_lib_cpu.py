@@ -66,6 +66,40 @@ def test_mesh_prep_matches_oracle(T, orc, n, grading):
     assert (r["cell_neighbours"] == nb_orc).all()
 
 
+@pytest.mark.parametrize("n,grading", [(3, 1.0), (8, 16.0)])
+def test_reconstruction_coefficients_match_oracle_gradient(T, orc, n, grading):
+    """The library stores a_mj = c_j . r_m (m < 3) per cell; the change of a
+    variable to face centroid m is sum_j a_mj (W_j - W_i), and to face 3
+    minus the sum of the other three (the offsets of a tetrahedron's face
+    centroids from its centroid sum to zero).  For the density, whose wall
+    ghost equals the cell's own value, that must be the oracle's unlimited
+    least-squares gradient G dotted with r_m, at every cell and face."""
+    nodes, tets = I.graded_cube_mesh(n, grading)
+    r = T.tafv_mesh_inspect(nodes, tets)
+    m = orc.Mesh(nodes, tets)
+    g = m.geometry()
+    prim = I.random_state(len(tets), 5)
+    raw, _ = orc.gradients(m, prim)  # [cell][xyz][variable]
+    rho = prim[:, 0]
+    nbr = r["cell_neighbours"]
+    dw = np.where(nbr >= 0, rho[np.maximum(nbr, 0)] - rho[:, None], 0.0)  # [cell][j]
+    d3 = np.einsum("imj,ij->im", r["recon_coef"], dw)
+    ours = np.concatenate([d3, -d3.sum(1, keepdims=True)], axis=1)  # [cell][m]
+    rm = g["face_centroid"][g["cell_faces"]] - g["centroid"][:, None, :]
+    theirs = np.einsum("imx,ix->im", rm, raw[:, :, 0])
+    scale = np.abs(theirs).max()
+    assert scale > 0
+    assert np.abs(ours - theirs).max() <= 1e-12 * scale
+    # a linear density is reproduced exactly on cells with 4 neighbours
+    b = np.array([0.3, -0.7, 1.1])
+    lin = g["centroid"] @ b
+    dl = np.where(nbr >= 0, lin[np.maximum(nbr, 0)] - lin[:, None], 0.0)
+    d3 = np.einsum("imj,ij->im", r["recon_coef"], dl)
+    inner = (nbr >= 0).all(1)
+    assert inner.any()
+    assert np.abs(d3[inner] - (rm[inner, :3] @ b)).max() <= 1e-12
+
+
 @pytest.mark.parametrize("n,grading", [(4, 1.0), (12, 4.0), (20, 16.0)])
 def test_colouring_is_valid(T, n, grading):
     nodes, tets = I.graded_cube_mesh(n, grading)
