@@ -24,7 +24,9 @@ row-major, b2 [32], w3 [32], b3.
 
 The BF16-emulating forward rounds inputs (after an FP32 rounding of the
 features), weights, biases and the two hidden activations to BF16 with
-round-to-nearest-even, and accumulates in FP64.
+round-to-nearest-even, and accumulates in FP64; the BF16-emulating backward
+also rounds the back-propagated gradients dz2 and dz1 to BF16 (the operands
+of the training products).
 """
 import numpy as np
 
@@ -114,7 +116,14 @@ def loss(theta, x, t, emulate_bf16=False):
 
 def backward(theta, x, t, emulate_bf16=False):
     """Gradient of the mean squared error with respect to the parameter
-    vector (chain rule through the ReLU network, FP64)."""
+    vector (chain rule through the ReLU network, FP64).
+
+    With emulate_bf16 the forward pass is the BF16 one above, and the two
+    back-propagated pre-activation gradients dz2 and dz1 are rounded to BF16
+    once formed (after the ReLU mask), because they are operands of the
+    BF16-in / FP32-accumulate products of training (dW2 = dz2^T h1,
+    dh1 = dz2 W2, dW1 = dz1^T x); the bias gradients are sums of those
+    rounded values.  dy and the last layer's products stay unrounded."""
     y, a = forward(theta, x, emulate_bf16)
     p = a["p"]
     n = len(y)
@@ -123,9 +132,13 @@ def backward(theta, x, t, emulate_bf16=False):
     g["w3"] = a["h2"].T @ dy
     g["b3"] = dy.sum()
     dz2 = np.outer(dy, p["w3"]) * (a["z2"] > 0)
+    if emulate_bf16:
+        dz2 = bf16(dz2)
     g["W2"] = dz2.T @ a["h1"]
     g["b2"] = dz2.sum(0)
     dz1 = (dz2 @ p["W2"]) * (a["z1"] > 0)
+    if emulate_bf16:
+        dz1 = bf16(dz1)
     g["W1"] = dz1.T @ a["x"]
     g["b1"] = dz1.sum(0)
     return pack(g)

@@ -44,7 +44,25 @@ def shock_faces(orc, n, seed):
     return x, t, wl, wr
 
 
+def near_bf16_tie(z, mag, rel=4 * 2.0 ** -24):
+    """True where a positive pre-activation z lies within rel * mag of a
+    midpoint between two BF16 values: there FP32 and FP64 sums (mag the sum
+    of the absolute terms; a few FP32 roundings of partial sums bounded by
+    it) may round the activation to different BF16 neighbours."""
+    z = np.asarray(z, dtype=np.float64)
+    pos = z > 0
+    e = np.floor(np.log2(np.where(pos, z, 1.0)))
+    ulp = 2.0 ** (e - 7)
+    frac = np.mod(z / ulp, 1.0)
+    dist = np.abs(frac - 0.5) * ulp
+    return pos & (dist <= rel * mag)
+
+
 def test_forward_matches_bf16_emulation(T, orc):
+    """Rows whose hidden activations are away from BF16 ties: the GPU
+    output equals the BF16-emulating reference to 1e-5 (the FP32 sums of
+    the GPU against the FP64 sums of the reference).  The excluded rows are
+    counted and must be few."""
     s = T.Solver(max_levels=2, order=1)
     th = M.he_uniform(1) + np.random.default_rng(2).normal(0, 0.05, M.N_PARAMS)
     th32 = th.astype(np.float32)
@@ -53,16 +71,24 @@ def test_forward_matches_bf16_emulation(T, orc):
     x, t, _, _ = shock_faces(orc, 3000, 3)
     x32 = x.astype(np.float32)
     y = T.tafv_mlp_forward(s.ctx, x32)
-    yref, _ = M.forward(th32.astype(np.float64), x32.astype(np.float64), emulate_bf16=True)
+    yref, a = M.forward(th32.astype(np.float64), x32.astype(np.float64), emulate_bf16=True)
+    p = a["p"]
+    mag1 = np.abs(a["x"]) @ np.abs(p["W1"]).T + np.abs(p["b1"])
+    mag2 = np.abs(a["h1"]) @ np.abs(p["W2"]).T + np.abs(p["b2"])
+    tie = near_bf16_tie(a["z1"], mag1).any(1) | near_bf16_tie(a["z2"], mag2).any(1)
     err = np.abs(y - yref)
-    say(f"forward: median {np.median(err):.2e} q99 {np.quantile(err, 0.99):.2e} max {err.max():.2e}")
-    # FP32 (GPU) and FP64 (reference) sums differ in the last bits; a hidden
-    # activation can then round to a neighbouring BF16 value
-    assert np.quantile(err, 0.99) < 1e-4 and err.max() < 3e-2
+    say(f"forward: {int(tie.sum())} of {len(y)} rows near a BF16 tie excluded; others: "
+        f"median {np.median(err[~tie]):.2e} max {err[~tie].max():.2e}; all rows max {err.max():.2e}")
+    assert tie.sum() <= 0.12 * len(y)
+    assert err[~tie].max() <= 1e-5
     s.close()
 
 
 def test_gradient_matches_reference(T, orc):
+    """The training kernels' gradient against the BF16-emulating reference
+    backward (BF16 forward activations, dz2 and dz1 rounded to BF16 as the
+    operands of the training products): normwise <= 1e-3, and per
+    parameter group."""
     s = T.Solver(max_levels=2, order=1)
     th32 = (M.he_uniform(4) + np.random.default_rng(5).normal(0, 0.05, M.N_PARAMS)).astype(np.float32)
     T.tafv_mlp_set(s.ctx, th32)
@@ -74,14 +100,16 @@ def test_gradient_matches_reference(T, orc):
     lref = M.loss(th32.astype(np.float64), x32.astype(np.float64), t32.astype(np.float64),
                   emulate_bf16=True)
     rel = np.linalg.norm(g - gref) / np.linalg.norm(gref)
-    say(f"gradient: normwise rel err {rel:.2e}, loss {loss:.6f} vs {lref:.6f}")
-    assert rel < 2e-2
-    assert abs(loss - lref) < 1e-3 * lref
-    # per parameter group
-    parts = [(0, 192), (192, 224), (224, 1248), (1248, 1280), (1280, 1312), (1312, 1313)]
-    for a, b in parts:
-        ra = np.linalg.norm(g[a:b] - gref[a:b]) / max(np.linalg.norm(gref[a:b]), 1e-12)
-        assert ra < 5e-2, (a, b, ra)
+    parts = {"W1": (0, 192), "b1": (192, 224), "W2": (224, 1248), "b2": (1248, 1280),
+             "w3": (1280, 1312), "b3": (1312, 1313)}
+    rg = {k: np.linalg.norm(g[a:b] - gref[a:b]) / max(np.linalg.norm(gref[a:b]), 1e-12)
+          for k, (a, b) in parts.items()}
+    say(f"gradient: normwise rel err {rel:.2e}, loss {loss:.6f} vs {lref:.6f}; per group " +
+        ", ".join(f"{k} {v:.1e}" for k, v in rg.items()))
+    assert rel <= 1e-3
+    assert abs(loss - lref) < 1e-4 * lref
+    for k, v in rg.items():
+        assert v <= 3e-3, (k, v)
     s.close()
 
 

@@ -4,7 +4,11 @@
   * the input normalisation against the scaling symmetry of the Euler
     equations: scaled face states give the same features and the same
     target ln(p*/p_m) from the (separately pinned) exact Riemann solver;
-  * a hand-built network whose output has a closed form.
+  * a hand-built network whose output has a closed form;
+  * the BF16 emulation of the backward pass: two single-path networks whose
+    emulated gradients have closed forms (dz2 and dz1 rounded to BF16, dy
+    not), and a network whose intermediates are all BF16 values, where the
+    emulated gradient equals the FP64 one bit for bit.
 """
 import numpy as np
 import pytest
@@ -108,3 +112,85 @@ def test_hand_built_network():
     yb, _ = M.forward(th, xb, emulate_bf16=True)
     rb = np.maximum(xb, 0)
     assert np.allclose(yb, rb[:, 0] + rb[:, 1] + rb[:, 2] - rb[:, 3] + 0.5, rtol=0, atol=1e-15)
+
+
+def _single_path(dy, w2, x0=1.0):
+    """One row through hidden unit 0 of both layers: x0 -> h1_0 = x0 ->
+    h2_0 = w2 x0 -> y = h2_0 (w3_0 = 1, everything else 0), with the target
+    set so that dy = 2 (y - t) takes the given value."""
+    p = {"W1": np.zeros((32, 6)), "b1": np.zeros(32), "W2": np.zeros((32, 32)),
+         "b2": np.zeros(32), "w3": np.zeros(32), "b3": 0.0}
+    p["W1"][0, 0] = 1.0
+    p["W2"][0, 0] = w2
+    p["w3"][0] = 1.0
+    x = np.zeros((1, 6))
+    x[0, 0] = x0
+    y = w2 * x0
+    t = np.array([y - dy / 2.0])
+    return M.pack(p), x, t
+
+
+def test_bf16_backward_rounds_dz2_closed_form():
+    """dy = 1 + 2^-10 is not a BF16 value: the emulated backward rounds
+    dz2 = dy w3 to 1 (the spacing of BF16 at 1 is 2^-7), so the gradients
+    of W2, b2, W1 and b1 see 1, while w3 and b3 see dy itself."""
+    dy = 1.0 + 2.0 ** -10
+    th, x, t = _single_path(dy, 1.0)
+    g64 = M.unpack(M.backward(th, x, t))
+    g16 = M.unpack(M.backward(th, x, t, emulate_bf16=True))
+    assert g64["W2"][0, 0] == dy and g16["W2"][0, 0] == 1.0
+    assert g64["b2"][0] == dy and g16["b2"][0] == 1.0
+    assert g64["W1"][0, 0] == dy and g16["W1"][0, 0] == 1.0
+    assert g64["b1"][0] == dy and g16["b1"][0] == 1.0
+    assert g64["w3"][0] == dy and g16["w3"][0] == dy
+    assert g64["b3"] == dy and g16["b3"] == dy
+
+
+def test_bf16_backward_rounds_dz1_closed_form():
+    """dz2 = dy = 1.5 is a BF16 value, W2 = 1 + 2^-7 too, but their product
+    1.51171875 (binary 1.10000011) is not: it ties between 1.1000001 and
+    1.1000010 and rounds to the even one, 1.515625.  That is dz1, and the
+    gradients of W1 and b1 (x0 = 1) under emulation."""
+    th, x, t = _single_path(1.5, 1.0 + 2.0 ** -7)
+    g64 = M.unpack(M.backward(th, x, t))
+    g16 = M.unpack(M.backward(th, x, t, emulate_bf16=True))
+    assert g64["W1"][0, 0] == 1.51171875 and g16["W1"][0, 0] == 1.515625
+    assert g64["b1"][0] == 1.51171875 and g16["b1"][0] == 1.515625
+    # dz2 is exact, so the second layer's gradient is the same in both
+    assert g64["W2"][0, 0] == g16["W2"][0, 0] == 1.5
+
+
+def _sparse_dyadic_network(rng):
+    """Parameters with at most two non-zeros per row and column of each
+    layer, all small dyadic values, so every forward and backward
+    intermediate of eight rows of dyadic inputs is a short dyadic number."""
+    p = {"W1": np.zeros((32, 6)), "b1": np.zeros(32), "W2": np.zeros((32, 32)),
+         "b2": np.zeros(32), "w3": np.zeros(32), "b3": 0.25}
+    vals = np.array([-1.0, -0.5, 0.5, 1.0])
+    for j in range(32):
+        p["W1"][j, j % 6] = rng.choice(vals)
+        p["W2"][j, j] = rng.choice(vals)
+        p["W2"][j, (j + 1) % 32] = rng.choice(vals)
+    p["b1"] = rng.choice([0.0, 0.25, -0.25], 32)
+    p["b2"] = rng.choice([0.0, 0.125, 0.5], 32)
+    p["w3"] = rng.choice([-1.0, -0.5, -0.25, 0.25, 0.5, 1.0], 32)
+    x = rng.choice([-1.375, -0.59375, 0.0, 0.8125, 1.1875, 1.5], (8, 6))
+    return M.pack(p), x
+
+
+def test_bf16_backward_exact_when_values_are_bf16():
+    """When every intermediate is a BF16 value, the rounding in the
+    emulated forward and backward changes nothing: the emulated gradient
+    equals the FP64 gradient bit for bit.  The gradients themselves (sums
+    over rows) are not all BF16 values, so rounding a sum would show."""
+    rng = np.random.default_rng(21)
+    th, x = _sparse_dyadic_network(rng)
+    y, a = M.forward(th, x)
+    for key in ("x", "z1", "h1", "z2", "h2"):
+        assert np.array_equal(M.bf16(a[key]), a[key]), key
+    t = y - rng.choice([-1.0, -0.5, 0.5, 1.0], len(y))  # y - t is a short dyadic
+    g64 = M.backward(th, x, t)
+    g16 = M.backward(th, x, t, emulate_bf16=True)
+    assert np.array_equal(g64, g16)
+    assert (M.bf16(g64) != g64).sum() >= 5
+    assert np.count_nonzero(g64) > 100
