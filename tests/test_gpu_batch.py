@@ -9,7 +9,8 @@ sequence per subiteration.
     single-mesh path, bit for bit, in FP32 with the learned guess;
   * HIP-graph replays equal direct launches, bit for bit, call after call,
     with host reads in between; the autotuner's choice and its cache file;
-  * the batched workload at full size (128 meshes): the smallest meshes
+  * the batched workload at full size (128 meshes): the three smallest and
+    three largest meshes and the largest mesh at the highest level cap
     against the oracle in FP64, and FP32 + learned guess against FP64 by
     L1 error on every mesh;
   * error codes of the batched calls.
@@ -286,9 +287,19 @@ def full_fp64(T, full_batch):
     return out
 
 
+def full_batch_sample(cases):
+    """The three smallest and the three largest meshes, and the largest
+    mesh with the highest level cap (the largest merged offsets, tile
+    prefixes and level counts of the batch)."""
+    size = np.array([len(c["tets"]) for c in cases])
+    order = np.argsort(size)
+    cap = max(c["max_levels"] for c in cases)
+    top_cap = max((k for k, c in enumerate(cases) if c["max_levels"] == cap), key=lambda k: size[k])
+    return list(dict.fromkeys([*order[:3], *order[-3:], top_cap]))
+
+
 def test_full_batch_fp64_against_oracle_sample(orc, full_batch, full_fp64):
-    order = np.argsort([len(c["tets"]) for c in full_batch])[:3]
-    for k in order:
+    for k in full_batch_sample(full_batch):
         c = full_batch[k]
         om = orc.Mesh(c["nodes"], c["tets"])
         o = orc.State(om, c["prim"], orc.params(max_levels=c["max_levels"], order=2))
@@ -299,7 +310,9 @@ def test_full_batch_fp64_against_oracle_sample(orc, full_batch, full_fp64):
         say(f"  mesh {k}: {len(c['tets'])} cells, L {c['max_levels']}, err {err:.2e}")
         assert err <= TOL
         assert (full_fp64["levels"][k] == lev_o).all()
-        assert full_fp64["mesh_stats"][k]["cell_updates"] == o.stats()["cell_updates"]
+        ms, os_ = full_fp64["mesh_stats"][k], o.stats()
+        for key in ("cell_updates", "face_solves", "theta", "phase"):
+            assert ms[key] == os_[key], (k, key, ms[key], os_[key])
 
 
 def test_full_batch_fp32_learned_l1(T, full_batch, full_fp64):
