@@ -7,7 +7,9 @@ Barth-Jespersen), exact Riemann flux with Newton on p* (tol 1e-12), up to 5
 temporal levels, a spherical blast (rho = 1, u = 0, p = 10 within 0.2 of a
 centre drawn from seed 0 in [0.3, 0.7]^3, p = 1 elsewhere), reflective
 walls, advanced 32 dt_min units from the initial state (the state is
-restored on the device before every step).  FP64 throughout.
+restored on the device before every step).  FP64 throughout.  Device memory
+comes from PyTorch's caching allocator (tafv_set_allocator); the library
+launches its own kernels on PyTorch's current stream.
 
 Prints one JSON line on stdout; progress goes to stderr.
 """
@@ -66,7 +68,7 @@ def run_form(T, torch, cfg, precision, steps, warmup, scatter, mlp=None, stats=0
                      guess_strength=mlp["strength"])
     s = T.Solver(device=0, hip_stream=stream.cuda_stream, max_levels=cfg["max_levels"],
                  order=cfg["order"], precision=precision, scatter=scatter, time_order=time_order,
-                 cell_order=CELL_ORDER, **extra)
+                 cell_order=CELL_ORDER, allocator=T.torch_allocator(0, stream), **extra)
     s.upload(cfg["nodes"], cfg["tets"])
     if mlp is not None:
         T.tafv_mlp_set(s.ctx, mlp["theta"])
@@ -127,7 +129,7 @@ def train_guess(T, torch, I, n, train_seeds=(1, 2, 3, 4, 5), rows_per_seed=40000
     stream = torch.cuda.current_stream()
     cfg = I.config_scale(n, train_seeds[0])
     s = T.Solver(device=0, hip_stream=stream.cuda_stream, max_levels=cfg["max_levels"],
-                 order=cfg["order"], guess_stats=1)
+                 order=cfg["order"], guess_stats=1, allocator=T.torch_allocator(0, stream))
     s.upload(cfg["nodes"], cfg["tets"])
     rows = []
     for seed in train_seeds:
@@ -182,7 +184,7 @@ def run_batch(T, torch, cases, steps, warmup, precision, mlp=None, graph=1):
         extra = dict(guess=T.GUESS_MLP, guess_gate=mlp["gate"], guess_strength=mlp["strength"])
     t0 = time.perf_counter()
     s = T.Solver(device=0, hip_stream=stream.cuda_stream, batch=1, order=2,
-                 precision=precision, **extra)
+                 precision=precision, allocator=T.torch_allocator(0, stream), **extra)
     for c in cases:
         s.upload(c["nodes"], c["tets"], max_levels=c["max_levels"])
     T.tafv_batch_config(s.ctx, graph, 1, None)
@@ -300,20 +302,46 @@ def copy_probe():
     log(f"copied {n * 8} bytes three times")
 
 
-def cpu_baseline(cfg, units=24):
-    """The oracle, single-threaded, on the first `units` subiterations of the
-    same workload (three full iterations at theta = 3; about 15 s)."""
+def host_cpu():
+    """CPU model and logical core count of the host the oracle runs on."""
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return model, os.cpu_count()
+
+
+def cpu_baseline(cfg, units=24, variant="seq"):
+    """The oracle on the first `units` subiterations of the same workload:
+    variant "seq" is the sequential parity reference (one thread; 24 units,
+    three full iterations at theta = 3, about 15 s), "omp" the same source
+    built with OpenMP (same bits, per-cell and per-face loops on all the
+    host threads that OMP_NUM_THREADS allows)."""
     from oracle import core as orc
-    m = orc.Mesh(cfg["nodes"], cfg["tets"])
-    o = orc.State(m, cfg["prim"], orc.params(max_levels=cfg["max_levels"], order=cfg["order"]))
-    t0 = time.perf_counter()
-    o.advance(units)
-    dt = time.perf_counter() - t0
-    st = o.stats()
-    return {"value": round(st["cell_updates"] / dt, 1), "unit": "cell-updates/s", "cores": 1,
-            "kind": "oracle",
+    orc.select(variant)
+    try:
+        m = orc.Mesh(cfg["nodes"], cfg["tets"])
+        o = orc.State(m, cfg["prim"], orc.params(max_levels=cfg["max_levels"], order=cfg["order"]))
+        threads = orc.threads()
+        t0 = time.perf_counter()
+        o.advance(units)
+        dt = time.perf_counter() - t0
+        st = o.stats()
+    finally:
+        orc.select("seq")
+    model, ncpu = host_cpu()
+    return {"value": round(st["cell_updates"] / dt, 1), "unit": "cell-updates/s",
+            "cores": threads, "kind": "oracle",
             "sample": f"first {units} of {UNITS} dt_min units (cell updates {st['cell_updates']}, "
-                      f"{dt:.1f} s) on the same 1,572,864-cell mesh and state, FP64, 1 thread"}
+                      f"{dt:.1f} s) on the same 1,572,864-cell mesh and state, FP64, "
+                      f"{threads} thread{'s' if threads > 1 else ''}"
+                      + (" (OpenMP build of the same source, bit-identical)" if threads > 1 else ""),
+            "host_cpu": model, "host_logical_cpus": ncpu}
 
 
 def main():
@@ -500,6 +528,10 @@ def main():
         log("cpu baseline: oracle, 1 thread ...")
         out["cpu_baseline"] = cpu_baseline(cfg)
         log(f"cpu baseline: {out['cpu_baseline']['value']:.0f} cell-updates/s")
+        log("cpu baseline: oracle, OpenMP build on the host threads ...")
+        out["cpu_baseline_all_cores"] = cpu_baseline(cfg, UNITS, "omp")
+        cb = out["cpu_baseline_all_cores"]
+        log(f"cpu baseline, {cb['cores']} threads: {cb['value']:.0f} cell-updates/s")
     print(json.dumps(out), flush=True)
 
 

@@ -58,13 +58,29 @@ def params(gamma=1.4, cfl=0.5, newton_tol=1e-12, level_margin=1e-9, max_levels=3
                   newton_max_iter, boundary, reclassify, time_order)
 
 
-_lib = None
+_libs = {}
+_variant = "seq"
 
 
-def lib():
-    global _lib
-    if _lib is None:
-        path = _build.build(force=False)
+def select(variant):
+    """Library for the objects made from now on: "seq" (the sequential
+    parity reference, the default) or "omp" (the same source built with
+    OpenMP: same bits, all host threads; for timing the CPU baseline)."""
+    global _variant
+    if variant not in ("seq", "omp"):
+        raise ValueError(variant)
+    _variant = variant
+
+
+def threads():
+    """Threads the selected library's loops run on."""
+    return int(lib().orc_threads())
+
+
+def lib(variant=None):
+    variant = variant or _variant
+    if variant not in _libs:
+        path = _build.build(force=False, openmp=(variant == "omp"))
         L = C.CDLL(path)
         P = C.c_void_p
         dp = C.POINTER(C.c_double)
@@ -99,8 +115,10 @@ def lib():
         L.orc_state_stats.argtypes = [P, C.POINTER(Stats)]
         L.orc_subiteration_level.argtypes = [C.c_int64, C.c_int32]
         L.orc_subiteration_level.restype = C.c_int32
-        _lib = L
-    return _lib
+        L.orc_threads.argtypes = []
+        L.orc_threads.restype = C.c_int32
+        _libs[variant] = L
+    return _libs[variant]
 
 
 def _d(a):
@@ -126,18 +144,19 @@ class Mesh:
     def __init__(self, nodes, tets):
         nodes = np.ascontiguousarray(nodes, dtype=np.float64)
         tets = np.ascontiguousarray(tets, dtype=np.int64)
+        self._L = lib()
         h = C.c_void_p()
-        _check(lib().orc_mesh_build(nodes.shape[0], _d(nodes), tets.shape[0], _i64(tets),
+        _check(self._L.orc_mesh_build(nodes.shape[0], _d(nodes), tets.shape[0], _i64(tets),
                                     C.byref(h)), "orc_mesh_build")
         self._h = h
         nc, nf, nb = C.c_int64(), C.c_int64(), C.c_int64()
-        lib().orc_mesh_counts(h, C.byref(nc), C.byref(nf), C.byref(nb))
+        self._L.orc_mesh_counts(h, C.byref(nc), C.byref(nf), C.byref(nb))
         self.n_cells, self.n_faces, self.n_boundary = nc.value, nf.value, nb.value
 
     def __del__(self):
         h = getattr(self, "_h", None)
-        if h is not None and h.value and _lib is not None:
-            _lib.orc_mesh_free(h)
+        if h is not None and h.value:
+            self._L.orc_mesh_free(h)
             self._h = None
 
     def geometry(self):
@@ -146,7 +165,7 @@ class Mesh:
                  face_L=np.empty(nf, np.int64), face_R=np.empty(nf, np.int64),
                  face_area=np.empty((nf, 3)), face_centroid=np.empty((nf, 3)),
                  cell_faces=np.empty((nc, 4), np.int64))
-        _check(lib().orc_mesh_geometry(self._h, _d(g["vol"]), _d(g["centroid"]),
+        _check(self._L.orc_mesh_geometry(self._h, _d(g["vol"]), _d(g["centroid"]),
                                        _i64(g["face_L"]), _i64(g["face_R"]),
                                        _d(g["face_area"]), _d(g["face_centroid"]),
                                        _i64(g["cell_faces"])), "orc_mesh_geometry")
@@ -202,7 +221,7 @@ def gradients(mesh, prim, prm=None):
     prim = np.ascontiguousarray(prim, dtype=np.float64)
     raw = np.empty((mesh.n_cells, 3, 5))
     lim = np.empty((mesh.n_cells, 3, 5))
-    _check(lib().orc_gradients(mesh._h, C.byref(prm), _d(prim), _d(raw), _d(lim)),
+    _check(mesh._L.orc_gradients(mesh._h, C.byref(prm), _d(prim), _d(raw), _d(lim)),
            "orc_gradients")
     return raw, lim
 
@@ -213,7 +232,7 @@ def classify(mesh, cons, prm):
     lev = np.empty(mesh.n_cells, np.int8)
     dtmin = C.c_double()
     theta = C.c_int32()
-    _check(lib().orc_classify(mesh._h, C.byref(prm), _d(cons), _d(dt), _i8(lev),
+    _check(mesh._L.orc_classify(mesh._h, C.byref(prm), _d(cons), _d(dt), _i8(lev),
                               C.byref(dtmin), C.byref(theta)), "orc_classify")
     return dt, lev, dtmin.value, theta.value
 
@@ -225,49 +244,50 @@ class State:
         self.mesh = mesh
         self.prm = prm
         prim = np.ascontiguousarray(prim, dtype=np.float64)
+        self._L = mesh._L
         h = C.c_void_p()
-        _check(lib().orc_state_new(mesh._h, C.byref(prm), _d(prim), C.byref(h)),
+        _check(self._L.orc_state_new(mesh._h, C.byref(prm), _d(prim), C.byref(h)),
                "orc_state_new")
         self._h = h
 
     def __del__(self):
         h = getattr(self, "_h", None)
-        if h is not None and h.value and _lib is not None:
-            _lib.orc_state_free(h)
+        if h is not None and h.value:
+            self._L.orc_state_free(h)
             self._h = None
 
     def set(self, cons, accum, levels, phase, theta, dt_min, t=0.0):
         cons = np.ascontiguousarray(cons, dtype=np.float64)
         accum = np.ascontiguousarray(accum, dtype=np.float64)
         levels = np.ascontiguousarray(levels, dtype=np.int8)
-        _check(lib().orc_state_set(self._h, _d(cons), _d(accum), _i8(levels), phase, theta,
+        _check(self._L.orc_state_set(self._h, _d(cons), _d(accum), _i8(levels), phase, theta,
                                    dt_min, t), "orc_state_set")
 
     def advance(self, n):
-        _check(lib().orc_advance(self._h, int(n)), "orc_advance")
+        _check(self._L.orc_advance(self._h, int(n)), "orc_advance")
 
     def read(self):
         n = self.mesh.n_cells
         cons = np.empty((n, 5))
         accum = np.empty((n, 5))
         lev = np.empty(n, np.int8)
-        _check(lib().orc_state_read(self._h, _d(cons), _d(accum), _i8(lev)), "orc_state_read")
+        _check(self._L.orc_state_read(self._h, _d(cons), _d(accum), _i8(lev)), "orc_state_read")
         return cons, accum, lev
 
     def motion(self, node_vel):
         """Node velocities [n_nodes][3] of a moving mesh (ALE, geometric
         conservation law)."""
         v = np.ascontiguousarray(node_vel, dtype=np.float64)
-        _check(lib().orc_state_motion(self._h, _d(v)), "orc_state_motion")
+        _check(self._L.orc_state_motion(self._h, _d(v)), "orc_state_motion")
 
     def volumes(self):
         vol = np.empty(self.mesh.n_cells)
-        _check(lib().orc_state_volumes(self._h, _d(vol)), "orc_state_volumes")
+        _check(self._L.orc_state_volumes(self._h, _d(vol)), "orc_state_volumes")
         return vol
 
     def stats(self):
         st = Stats()
-        _check(lib().orc_state_stats(self._h, C.byref(st)), "orc_state_stats")
+        _check(self._L.orc_state_stats(self._h, C.byref(st)), "orc_state_stats")
         return st.as_dict()
 
 

@@ -20,12 +20,36 @@
  *     Solvers and Numerical Methods for Fluid Dynamics", 3rd ed., ch. 4;
  *   least-squares gradients and the limiter: T. J. Barth, D. C. Jespersen,
  *     AIAA paper 89-0366 (1989).
+ *
+ * Timing build: compiled with -fopenmp, the per-cell and per-face loops
+ * marked ORC_PARALLEL_FOR or ORC_OMP run on all host threads.  Each
+ * iteration of such a loop writes only its own cell's or face's entries and
+ * every floating-point sum keeps its sequential order (a cell adds its faces
+ * in local face order; the reductions are of integers and flags; dt_min is
+ * a minimum), so the timing build computes the same bits as the sequential
+ * one.  The wall-impulse sum stays sequential.
  */
 #include "oracle.h"
 
 #include <math.h>
 #include <stdlib.h>
 #include <string.h>
+
+#ifdef _OPENMP
+#include <omp.h>
+#define ORC_OMP(x) _Pragma(#x)
+#else
+#define ORC_OMP(x)
+#endif
+#define ORC_PARALLEL_FOR ORC_OMP(omp parallel for schedule(static))
+
+int32_t orc_threads(void) {
+#ifdef _OPENMP
+  return (int32_t)omp_get_max_threads();
+#else
+  return 1;
+#endif
+}
 
 /* ====================================================================== */
 /* Mesh and geometry                                                       */
@@ -570,6 +594,8 @@ static int invert_sym3(const double* M, double* Minv) {
 
 static int gradients_core(const orc_mesh* m, const orc_params* prm, const double* sF,
                           const double* prim, double* grad_raw, double* grad_lim) {
+  int bad = 0;
+  ORC_OMP(omp parallel for schedule(static) reduction(| : bad))
   for (int64_t i = 0; i < m->nc; ++i) {
     const double* xi = m->xc + 3 * i;
     const double* wi = prim + 5 * i;
@@ -586,7 +612,10 @@ static int gradients_core(const orc_mesh* m, const orc_params* prm, const double
         for (int k = 0; k < 5; ++k) b[r][k] += wgt * d[r] * (wn[j][k] - wi[k]);
     }
     double Minv[9];
-    if (invert_sym3(M, Minv)) return ORC_E_MESH;
+    if (invert_sym3(M, Minv)) {
+      bad = 1;
+      continue;
+    }
     double G[3][5];
     for (int r = 0; r < 3; ++r)
       for (int k = 0; k < 5; ++k)
@@ -615,7 +644,7 @@ static int gradients_core(const orc_mesh* m, const orc_params* prm, const double
       for (int r = 0; r < 3; ++r) grad_lim[15 * i + 5 * r + k] = psi * G[r][k];
     }
   }
-  return ORC_OK;
+  return bad ? ORC_E_MESH : ORC_OK;
 }
 
 int orc_gradients(const orc_mesh* m, const orc_params* prm, const double* prim,
@@ -637,10 +666,16 @@ static int classify_core(const orc_mesh* m, const orc_params* prm, const double*
                          double* dt_min_out, int32_t* theta_out) {
   double g = prm->gamma;
   double dtmin = INFINITY;
+  int bad = 0;
+  ORC_OMP(omp parallel for schedule(static) reduction(| : bad))
   for (int64_t i = 0; i < m->nc; ++i) {
     double w[5];
     cons_to_prim(g, cons + 5 * i, w);
-    if (!(w[0] > 0.0) || !(w[4] > 0.0)) return ORC_E_NUMERIC;
+    if (!(w[0] > 0.0) || !(w[4] > 0.0)) {
+      bad = 1;
+      dt[i] = INFINITY;
+      continue;
+    }
     double a = sqrt(g * w[4] / w[0]);
     double s = 0.0;
     for (int j = 0; j < 4; ++j) {
@@ -651,9 +686,12 @@ static int classify_core(const orc_mesh* m, const orc_params* prm, const double*
       s += (fabs(un) + a) * amag;
     }
     dt[i] = prm->cfl * vol[i] / s;
-    if (dt[i] < dtmin) dtmin = dt[i];
   }
+  if (bad) return ORC_E_NUMERIC;
+  for (int64_t i = 0; i < m->nc; ++i)
+    if (dt[i] < dtmin) dtmin = dt[i];
   int L = prm->max_levels;
+  ORC_PARALLEL_FOR
   for (int64_t i = 0; i < m->nc; ++i) {
     int e;
     double q = dt[i] * (1.0 - prm->level_margin) / dtmin;
@@ -667,6 +705,7 @@ static int classify_core(const orc_mesh* m, const orc_params* prm, const double*
   int8_t* tmp = (int8_t*)malloc((size_t)m->nc);
   if (!tmp) return ORC_E_ARG;
   for (int sweep = 0; sweep < L - 1; ++sweep) {
+    ORC_PARALLEL_FOR
     for (int64_t i = 0; i < m->nc; ++i) {
       int t = levels[i];
       for (int j = 0; j < 4; ++j) {
@@ -826,11 +865,16 @@ static int face_fluxes(orc_state* s, const double* cons, int tau_max, double* ph
   const orc_mesh* m = s->m;
   const orc_params* prm = &s->prm;
   double g = prm->gamma;
+  ORC_PARALLEL_FOR
   for (int64_t i = 0; i < m->nc; ++i) cons_to_prim(g, cons + 5 * i, s->prim + 5 * i);
   if (prm->order == 2) {
     int rc = gradients_core(m, prm, s->moving ? s->sF : NULL, s->prim, NULL, s->glim);
     if (rc) return rc;
   }
+  int64_t n_solves = 0, n_newton = 0, n_fallback = 0, n_vacuum = 0;
+  int bad = 0;
+  ORC_OMP(omp parallel for schedule(dynamic, 1024)
+          reduction(+ : n_newton, n_fallback, n_vacuum) reduction(| : bad))
   for (int64_t f = 0; f < m->nf; ++f) {
     int64_t L = m->fL[f], R = m->fR[f];
     int tau_f = s->lev[L];
@@ -863,12 +907,20 @@ static int face_fluxes(orc_state* s, const double* cons, int tau_max, double* ph
       rc = orc_face_flux(g, wl, wr, m->af + 3 * f, kind, prm->newton_tol,
                          prm->newton_max_iter, ORC_GUESS_TR, 0.0, phi + 5 * f, &ro);
     }
-    if (rc) return ORC_E_NUMERIC;
-    s->st.face_solves++;
-    s->st.newton_updates += ro.newton_updates;
-    s->st.newton_fallbacks += ro.fallback;
-    s->st.vacuum_faces += ro.vacuum;
+    if (rc) {
+      bad = 1;
+      continue;
+    }
+    n_newton += ro.newton_updates;
+    n_fallback += ro.fallback;
+    n_vacuum += ro.vacuum;
   }
+  if (bad) return ORC_E_NUMERIC;
+  for (int64_t f = 0; f < m->nf; ++f) n_solves += s->act[f];
+  s->st.face_solves += n_solves;
+  s->st.newton_updates += n_newton;
+  s->st.newton_fallbacks += n_fallback;
+  s->st.vacuum_faces += n_vacuum;
   return ORC_OK;
 }
 
@@ -878,6 +930,7 @@ static int face_fluxes(orc_state* s, const double* cons, int tau_max, double* ph
  * step ends at the end of subiteration sub apply their sum. */
 static int flow_sum_and_update(orc_state* s, int64_t sub) {
   const orc_mesh* m = s->m;
+  ORC_PARALLEL_FOR
   for (int64_t i = 0; i < m->nc; ++i) {
     for (int j = 0; j < 4; ++j) {
       int64_t f = m->c2f[4 * i + j];
@@ -887,17 +940,23 @@ static int flow_sum_and_update(orc_state* s, int64_t sub) {
       if (s->moving) s->RV[i] += sign * s->qv[f];
     }
   }
+  int64_t updates = 0;
+  int bad = 0;
+  ORC_OMP(omp parallel for schedule(static) reduction(+ : updates) reduction(| : bad))
   for (int64_t i = 0; i < m->nc; ++i) {
     if (sub % ((int64_t)1 << s->lev[i]) != 0) continue;
     if (s->moving) {
       /* geometric conservation: the cell's content V U changes by its flux
        * sum, its volume by the volume its faces swept */
       double v = s->V[i], vn = v + s->RV[i];
-      if (!(vn > 0.0)) return ORC_E_NUMERIC;
+      if (!(vn > 0.0)) {
+        bad = 1;
+        continue;
+      }
       for (int k = 0; k < 5; ++k) {
         s->U[5 * i + k] = (v * s->U[5 * i + k] + s->R[5 * i + k]) / vn;
         s->R[5 * i + k] = 0.0;
-        if (!isfinite(s->U[5 * i + k])) return ORC_E_NUMERIC;
+        if (!isfinite(s->U[5 * i + k])) bad = 1;
       }
       s->V[i] = vn;
       s->RV[i] = 0.0;
@@ -905,12 +964,13 @@ static int flow_sum_and_update(orc_state* s, int64_t sub) {
       for (int k = 0; k < 5; ++k) {
         s->U[5 * i + k] += s->R[5 * i + k] / m->vol[i];
         s->R[5 * i + k] = 0.0;
-        if (!isfinite(s->U[5 * i + k])) return ORC_E_NUMERIC;
+        if (!isfinite(s->U[5 * i + k])) bad = 1;
       }
     }
-    s->st.cell_updates++;
+    updates++;
   }
-  return ORC_OK;
+  s->st.cell_updates += updates;
+  return bad ? ORC_E_NUMERIC : ORC_OK;
 }
 
 static int faster_level(const orc_state* s, int64_t f) {

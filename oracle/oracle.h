@@ -157,6 +157,10 @@ int orc_advance(orc_state* s, int64_t n_subiterations);
 /* Level tau computed in subiteration s (1-based) of an iteration with
  * levels 0..theta (Alg. 2). */
 int32_t orc_subiteration_level(int64_t s, int32_t theta);
+
+/* Threads the per-cell and per-face loops run on: 1 in the plain build,
+ * the OpenMP thread count in the timing build (same bits either way). */
+int32_t orc_threads(void);
 int orc_state_read(const orc_state* s, double* cons, double* accum,
                    int8_t* levels);
 int orc_state_stats(const orc_state* s, orc_stats* out);
