@@ -27,7 +27,8 @@
  *     tafv_last_error() returns a message for the last failure on a context.
  *   Ownership: the caller owns every host array; the library copies inputs
  *     during the call and keeps no caller pointer.  The context owns all
- *     device memory it allocates and frees it in tafv_destroy().
+ *     device memory it allocates (with hipMalloc, or with the caller's
+ *     allocator: tafv_set_allocator) and frees it in tafv_destroy().
  *   Streams: all device work of a context is enqueued on the HIP stream
  *     given to tafv_create() (NULL: the null stream).  Calls that return
  *     data to the host synchronise that stream; tafv_advance() does not wait
@@ -183,6 +184,35 @@ tafv_status tafv_destroy(tafv_ctx* ctx);
 /* Message of the last failed call on ctx (or of tafv_create when ctx is
  * NULL); the string lives until the next call on the context. */
 const char* tafv_last_error(const tafv_ctx* ctx);
+
+/* Device memory of the context.  By default the library allocates with
+ * hipMalloc and frees with hipFree.  tafv_set_allocator routes every device
+ * buffer of the context (mesh arrays, state, schedule lists, face fluxes,
+ * network, face log, batch tables, and the temporary buffers of single
+ * calls) through the caller's functions instead, for instance a framework's
+ * caching allocator, so that the caller owns the memory policy and the
+ * library only uses HIP for kernels, copies and the stream:
+ *   alloc(bytes, user) returns device memory of the context's device, at
+ *     least `bytes` long and 256-byte aligned, usable in stream order on the
+ *     context's stream; NULL when it cannot, which the failing call reports
+ *     as TAFV_E_OOM after handing back whatever it took (the context stays
+ *     usable and can be destroyed);
+ *   dealloc(ptr, user) takes back a pointer alloc returned.  The library
+ *     calls it once for every such pointer: for a call's temporary buffer
+ *     when the call returns, for the context's buffers in tafv_destroy()
+ *     (after synchronising the context's stream) or when a buffer is
+ *     replaced (network partial sums, face log).
+ * A misaligned pointer is handed back and the call fails with
+ * TAFV_E_DEVICE.  alloc and dealloc are both given or both NULL (NULL
+ * restores hipMalloc / hipFree); TAFV_E_ARG otherwise.  The allocator can
+ * only be set or changed while the context holds no device memory: right
+ * after tafv_create() (or once everything was freed), else TAFV_E_ORDER. */
+tafv_status tafv_set_allocator(tafv_ctx* ctx, void* (*alloc)(size_t bytes, void* user),
+                               void (*dealloc)(void* ptr, void* user), void* user);
+
+/* Number of device buffers the context holds (-1 for NULL): the pointers
+ * its allocator gave out and has not had back. */
+int64_t tafv_device_buffers(const tafv_ctx* ctx);
 
 /* Upload a tetrahedral mesh.  xyz: host [n_nodes][3] node coordinates;
  * tets: host [n_tets][4] node ids, each tet positively oriented

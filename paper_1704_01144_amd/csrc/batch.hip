@@ -705,9 +705,24 @@ void merge_hosts(const std::vector<HostMesh*>& hs, HostMesh& out, std::vector<in
   }
 }
 
-tafv_status build(tafv_ctx* c) {
+// The merged mesh, schedule table, tile prefixes and capture stream of a
+// batch; after a failed build they are released, so that a later call can
+// build again.
+void release_tables(tafv_ctx* c, Batch& B) {
+  for (void** p : {(void**)&B.dsched, (void**)&B.ct, (void**)&B.ft, (void**)&B.cc, (void**)&B.fc,
+                   (void**)&B.cnt_f, (void**)&B.cnt_c, (void**)&B.tp, (void**)&B.rp,
+                   (void**)&B.tmin, (void**)&B.thist}) {
+    dev_free(c, *p);
+    *p = nullptr;
+  }
+  if (B.m) free_dev_mesh(c, B.m);
+  B.m = nullptr;
+  if (B.cap) (void)hipStreamDestroy(B.cap);
+  B.cap = nullptr;
+}
+
+tafv_status build_merged(tafv_ctx* c) {
   Batch& B = *c->batch;
-  if (B.built) return TAFV_OK;
   if (B.hosts.empty()) return set_error(c, TAFV_E_ORDER, "no mesh uploaded");
   B_TRY(c, hipSetDevice(c->device));
   const int M = (int)B.hosts.size();
@@ -754,14 +769,14 @@ tafv_status build(tafv_ctx* c) {
   auto chk = [&](hipError_t x) {
     if (e == hipSuccess) e = x;
   };
-  chk(hipMalloc(&B.dsched, sizeof(BatchSched) * M));
-  for (int32_t** p : {&B.ct, &B.ft, &B.cc, &B.fc}) chk(hipMalloc(p, sizeof(int32_t) * (M + 1)));
-  chk(hipMalloc(&B.tp, sizeof(int32_t) * 3 * (M + 1)));
-  chk(hipMalloc(&B.rp, sizeof(int32_t) * 4 * (M + 1)));
-  chk(hipMalloc(&B.tmin, sizeof(double) * std::max(B.n_ct, 1)));
-  chk(hipMalloc(&B.thist, sizeof(int) * kMaxKeys * std::max(B.n_ct, 1)));
-  chk(hipMalloc(&B.cnt_c, sizeof(int32_t) * kMaxLevels * std::max(B.n_cc, 1)));
-  chk(hipMalloc(&B.cnt_f, sizeof(int32_t) * kMaxLevels * std::max(B.n_fc, 1)));
+  chk(dev_alloc(c, &B.dsched, sizeof(BatchSched) * M));
+  for (int32_t** p : {&B.ct, &B.ft, &B.cc, &B.fc}) chk(dev_alloc(c, p, sizeof(int32_t) * (M + 1)));
+  chk(dev_alloc(c, &B.tp, sizeof(int32_t) * 3 * (M + 1)));
+  chk(dev_alloc(c, &B.rp, sizeof(int32_t) * 4 * (M + 1)));
+  chk(dev_alloc(c, &B.tmin, sizeof(double) * std::max(B.n_ct, 1)));
+  chk(dev_alloc(c, &B.thist, sizeof(int) * kMaxKeys * std::max(B.n_ct, 1)));
+  chk(dev_alloc(c, &B.cnt_c, sizeof(int32_t) * kMaxLevels * std::max(B.n_cc, 1)));
+  chk(dev_alloc(c, &B.cnt_f, sizeof(int32_t) * kMaxLevels * std::max(B.n_fc, 1)));
   if (e != hipSuccess) return hip_error(c, e, "batch allocation");
   B_TRY(c, hipMemcpy(B.dsched, B.hsched.data(), sizeof(BatchSched) * M, hipMemcpyHostToDevice));
   B_TRY(c, hipMemcpy(B.ct, ct.data(), sizeof(int32_t) * (M + 1), hipMemcpyHostToDevice));
@@ -784,6 +799,13 @@ tafv_status build(tafv_ctx* c) {
   for (int w = 0; w < 3; ++w) B.set[w] = LaunchSet{kStaticBlocksPerCU * cu, 1, kBlock};
   B.set[1] = LaunchSet{std::max((B.n_fu + kBlock / kUnit - 1) / (kBlock / kUnit), 1), 1, kBlock};
   return TAFV_OK;
+}
+
+tafv_status build(tafv_ctx* c) {
+  if (c->batch->built) return TAFV_OK;
+  tafv_status st = build_merged(c);
+  if (st != TAFV_OK) release_tables(c, *c->batch);
+  return st;
 }
 
 FluxFeatures features(tafv_ctx* c) {
@@ -1131,10 +1153,10 @@ tafv_status autotune(tafv_ctx* c) {
   BatchSched* St = nullptr;
   int32_t* tpt = nullptr;
   hipEvent_t e0 = nullptr, e1 = nullptr;
-  hipError_t e = hipMalloc(&Us, rows * sizeof(double));
-  if (e == hipSuccess) e = hipMalloc(&Rs, rows * sizeof(double));
-  if (e == hipSuccess) e = hipMalloc(&St, sizeof(BatchSched) * M);
-  if (e == hipSuccess) e = hipMalloc(&tpt, sizeof(int32_t) * 3 * (M + 1));
+  hipError_t e = dev_alloc(c, &Us, rows * sizeof(double));
+  if (e == hipSuccess) e = dev_alloc(c, &Rs, rows * sizeof(double));
+  if (e == hipSuccess) e = dev_alloc(c, &St, sizeof(BatchSched) * M);
+  if (e == hipSuccess) e = dev_alloc(c, &tpt, sizeof(int32_t) * 3 * (M + 1));
   if (e == hipSuccess) e = hipEventCreate(&e0);
   if (e == hipSuccess) e = hipEventCreate(&e1);
   std::vector<double> score[2];
@@ -1191,8 +1213,7 @@ tafv_status autotune(tafv_ctx* c) {
   }
   if (e0) (void)hipEventDestroy(e0);
   if (e1) (void)hipEventDestroy(e1);
-  for (void* ptr : {(void*)Us, (void*)Rs, (void*)St, (void*)tpt})
-    if (ptr) (void)hipFree(ptr);
+  for (void* ptr : {(void*)Us, (void*)Rs, (void*)St, (void*)tpt}) dev_free(c, ptr);
   if (e != hipSuccess) return hip_error(c, e, "autotuning");
   for (int w = 0; w < 2; ++w) {
     if (w == 0 && c->prm.order != 2) continue;
@@ -1555,11 +1576,7 @@ void batch_free(tafv_ctx* c) {
   Batch& B = *c->batch;
   drop_graphs(B);
   for (HostMesh* h : B.hosts) delete h;
-  void* ptrs[] = {B.dsched, B.ct, B.ft, B.cc, B.fc, B.cnt_f, B.cnt_c, B.tp, B.rp, B.tmin, B.thist};
-  for (void* p : ptrs)
-    if (p) (void)hipFree(p);
-  if (B.m) free_dev_mesh(B.m);
-  if (B.cap) (void)hipStreamDestroy(B.cap);
+  release_tables(c, B);
   delete c->batch;
   c->batch = nullptr;
 }

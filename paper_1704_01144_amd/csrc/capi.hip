@@ -17,7 +17,8 @@ using namespace tafv;
 
 namespace {
 
-const char* kProfNames[] = {"classify", "grad", "flux", "update", "gather", "predict"};
+const char* kProfNames[] = {"classify", "grad",    "flux",          "update",
+                            "gather",   "predict", "flux_corrector"};
 
 thread_local std::string g_create_err;
 
@@ -39,11 +40,11 @@ tafv_status hip_fail(tafv_ctx* c, hipError_t e, const char* what) {
   } while (0)
 
 template <typename T>
-hipError_t dalloc(T** p, size_t n) {
-  return hipMalloc((void**)p, std::max<size_t>(n, 1) * sizeof(T));
+hipError_t dalloc(tafv_ctx* c, T** p, size_t n) {
+  return dev_malloc(c, (void**)p, std::max<size_t>(n, 1) * sizeof(T));
 }
 
-void free_mesh(DevMesh* m) {
+void free_mesh(tafv_ctx* c, DevMesh* m) {
   if (!m) return;
   void* ptrs[] = {m->fhL, m->fhR, m->fcol, m->fA, m->fA32, m->nb_, m->c2f, m->grc,
                   m->vol, m->grc32, m->U, m->U0, m->R, m->lev, m->lev2, m->dt, m->Wf,
@@ -53,8 +54,7 @@ void free_mesh(DevMesh* m) {
                   m->perm, m->xfer, m->chist, m->rb, m->dmin, m->Q0, m->D, m->Ut,
                   m->vol0, m->fnode, m->sF, m->Rv, m->sweepf, m->lkey, m->pg.list,
                   m->pg.counts, m->pg.start, m->pg.offs, m->pg.scan_tmp};
-  for (void* p : ptrs)
-    if (p) (void)hipFree(p);
+  for (void* p : ptrs) dev_free(c, p);
   delete m;
 }
 
@@ -342,7 +342,40 @@ tafv_status set_error(tafv_ctx* c, tafv_status st, const std::string& msg) {
 
 tafv_status hip_error(tafv_ctx* c, hipError_t e, const char* what) { return hip_fail(c, e, what); }
 
-void free_dev_mesh(DevMesh* m) { free_mesh(m); }
+void free_dev_mesh(tafv_ctx* c, DevMesh* m) { free_mesh(c, m); }
+
+// Buffers must be at least 256-byte aligned: the kernels use 16-byte vector
+// accesses and the counter slots are 128 bytes apart.
+constexpr uintptr_t kAllocAlign = 256;
+
+hipError_t dev_malloc(tafv_ctx* c, void** p, size_t bytes) {
+  *p = nullptr;
+  bytes = std::max<size_t>(bytes, 1);
+  if (c->alloc_fn) {
+    void* q = c->alloc_fn(bytes, c->alloc_user);
+    if (!q) return hipErrorOutOfMemory;
+    if ((uintptr_t)q % kAllocAlign) {
+      c->dealloc_fn(q, c->alloc_user);
+      return hipErrorInvalidValue;
+    }
+    *p = q;
+  } else {
+    hipError_t e = hipMalloc(p, bytes);
+    if (e != hipSuccess) {
+      *p = nullptr;
+      return e;
+    }
+  }
+  ++c->live_buffers;
+  return hipSuccess;
+}
+
+void dev_free(tafv_ctx* c, void* p) {
+  if (!p) return;
+  if (c->alloc_fn) c->dealloc_fn(p, c->alloc_user);
+  else (void)hipFree(p);
+  --c->live_buffers;
+}
 
 tafv_status read_slot_counters(tafv_ctx* c, DevMesh& m, tafv_stats* st) {
   std::vector<unsigned long long> cnt(kCounterWords);
@@ -394,62 +427,62 @@ tafv_status upload_host_mesh(tafv_ctx* c, const HostMesh& hm, DevMesh** out) {
   auto chk = [&](hipError_t x) {
     if (e == hipSuccess) e = x;
   };
-  chk(dalloc(&m->fhL, nf));
-  chk(dalloc(&m->fhR, nf));
-  chk(dalloc(&m->fcol, nf));
-  chk(dalloc(&m->fA, 3 * nf));
-  chk(dalloc(&m->fA32, 3 * nf));
-  chk(dalloc(&m->nb_, 4 * nc));
-  chk(dalloc(&m->c2f, 4 * nc));
-  chk(dalloc(&m->grc, 12 * nc));
-  chk(dalloc(&m->grc32, 12 * nc));
-  chk(dalloc(&m->vol, nc));
-  chk(dalloc(&m->vol0, nc));
-  chk(dalloc(&m->fnode, 3 * nf));
-  chk(dalloc(&m->U, 5 * nc));
-  chk(dalloc(&m->U0, 5 * nc));
-  chk(dalloc(&m->R, 5 * nc));
-  chk(dalloc(&m->lev, nc));
-  chk(dalloc(&m->lev2, nc));
-  chk(dalloc(&m->sweepf, kMaxLevels));
-  chk(dalloc(&m->dt, nc));
+  chk(dalloc(c, &m->fhL, nf));
+  chk(dalloc(c, &m->fhR, nf));
+  chk(dalloc(c, &m->fcol, nf));
+  chk(dalloc(c, &m->fA, 3 * nf));
+  chk(dalloc(c, &m->fA32, 3 * nf));
+  chk(dalloc(c, &m->nb_, 4 * nc));
+  chk(dalloc(c, &m->c2f, 4 * nc));
+  chk(dalloc(c, &m->grc, 12 * nc));
+  chk(dalloc(c, &m->grc32, 12 * nc));
+  chk(dalloc(c, &m->vol, nc));
+  chk(dalloc(c, &m->vol0, nc));
+  chk(dalloc(c, &m->fnode, 3 * nf));
+  chk(dalloc(c, &m->U, 5 * nc));
+  chk(dalloc(c, &m->U0, 5 * nc));
+  chk(dalloc(c, &m->R, 5 * nc));
+  chk(dalloc(c, &m->lev, nc));
+  chk(dalloc(c, &m->lev2, nc));
+  chk(dalloc(c, &m->sweepf, kMaxLevels));
+  chk(dalloc(c, &m->dt, nc));
   size_t wfbytes = (c->prm.precision == TAFV_FP32_FLUX ? sizeof(float) : sizeof(double)) * 20 * nc;
-  if (c->prm.order == 2) chk(hipMalloc(&m->Wf, wfbytes));
+  if (c->prm.order == 2) chk(dev_malloc(c, &m->Wf, wfbytes));
   for (Partition* p : {&m->pf, &m->pc}) {  // the gather's list is scanned with the tau_g list
     int64_t n = (p == &m->pf) ? (int64_t)nf : (int64_t)nc;
     p->scan_bytes = partition_scan_bytes(n);
-    chk(hipMalloc(&p->scan_tmp, std::max<size_t>(p->scan_bytes, 16)));
-    chk(dalloc(&p->offs, (size_t)kMaxKeys * partition_blocks(n)));
-    chk(dalloc(&p->list, n));
-    chk(dalloc(&p->counts, (size_t)kMaxKeys * partition_blocks(n)));
-    chk(dalloc(&p->start, kMaxKeys + 1));
+    chk(dev_malloc(c, &p->scan_tmp, std::max<size_t>(p->scan_bytes, 16)));
+    chk(dalloc(c, &p->offs, (size_t)kMaxKeys * partition_blocks(n)));
+    chk(dalloc(c, &p->list, n));
+    chk(dalloc(c, &p->counts, (size_t)kMaxKeys * partition_blocks(n)));
+    chk(dalloc(c, &p->start, kMaxKeys + 1));
   }
-  chk(dalloc(&m->pg.list, nc));
-  chk(dalloc(&m->pg.start, kMaxKeys + 1));
-  chk(dalloc(&m->frec, nf));
+  chk(dalloc(c, &m->pg.list, nc));
+  chk(dalloc(c, &m->pg.start, kMaxKeys + 1));
+  chk(dalloc(c, &m->frec, nf));
   if (m->scatter == TAFV_SCATTER_GATHER)
-    chk(hipMalloc(&m->Q, (c->prm.precision == TAFV_FP32_FLUX ? sizeof(float) : sizeof(double)) *
+    chk(dev_malloc(c, &m->Q, (c->prm.precision == TAFV_FP32_FLUX ? sizeof(float) : sizeof(double)) *
                              5 * std::max<size_t>(nf, 1)));
   if (c->prm.time_order == 2) {
-    chk(hipMalloc(&m->Q0, (c->prm.precision == TAFV_FP32_FLUX ? sizeof(float) : sizeof(double)) *
+    chk(dev_malloc(c, &m->Q0, (c->prm.precision == TAFV_FP32_FLUX ? sizeof(float) : sizeof(double)) *
                               5 * std::max<size_t>(nf, 1)));
-    chk(dalloc(&m->D, 5 * nc));
-    chk(dalloc(&m->Ut, 5 * nc));
+    chk(dalloc(c, &m->D, 5 * nc));
+    chk(dalloc(c, &m->Ut, 5 * nc));
   }
-  chk(dalloc(&m->fkey, nf));
-  chk(dalloc(&m->ckey, nc));
-  chk(dalloc(&m->lkey, nc));
-  chk(dalloc(&m->fpack, nc));
-  chk(dalloc(&m->perm, nc));
-  chk(dalloc(&m->chist, (size_t)kCounterSlots * kMaxKeys));
-  chk(dalloc(&m->dmin, kCounterWords));
-  chk(dalloc(&m->rb, kReadbackInts));
-  chk(dalloc(&m->xfer, 5 * nc));
-  chk(dalloc(&m->dscal, 4));
-  chk(dalloc(&m->dcount, kCounterWords));
-  chk(dalloc(&m->dimpulse, kCounterWords));
+  chk(dalloc(c, &m->fkey, nf));
+  chk(dalloc(c, &m->ckey, nc));
+  chk(dalloc(c, &m->lkey, nc));
+  chk(dalloc(c, &m->fpack, nc));
+  chk(dalloc(c, &m->perm, nc));
+  chk(dalloc(c, &m->chist, (size_t)kCounterSlots * kMaxKeys));
+  chk(dalloc(c, &m->dmin, kCounterWords));
+  chk(dalloc(c, &m->rb, kReadbackInts));
+  chk(dalloc(c, &m->xfer, 5 * nc));
+  chk(dalloc(c, &m->dscal, 4));
+  chk(dalloc(c, &m->dcount, kCounterWords));
+  chk(dalloc(c, &m->dimpulse, kCounterWords));
   if (e != hipSuccess) {
-    free_mesh(m);
+    free_mesh(c, m);
     return hip_fail(c, e, "device allocation for the mesh");
   }
   chk(up(m->fhL, hm.fhL));
@@ -469,7 +502,7 @@ tafv_status upload_host_mesh(tafv_ctx* c, const HostMesh& hm, DevMesh** out) {
   m->n_nodes = hm.n_nodes;
   chk(up(m->perm, hm.perm));
   if (e != hipSuccess) {
-    free_mesh(m);
+    free_mesh(c, m);
     return hip_fail(c, e, "mesh upload");
   }
   *out = m;
@@ -564,7 +597,7 @@ tafv_status tafv_destroy(tafv_ctx* c) {
   (void)hipSetDevice(c->device);
   (void)hipStreamSynchronize(c->stream);
   batch_free(c);
-  for (DevMesh* m : c->meshes) free_mesh(m);
+  for (DevMesh* m : c->meshes) free_mesh(c, m);
   for (auto& pe : c->pending) {
     (void)hipEventDestroy(pe.a);
     (void)hipEventDestroy(pe.b);
@@ -572,8 +605,7 @@ tafv_status tafv_destroy(tafv_ctx* c) {
   for (hipEvent_t e : c->event_pool) (void)hipEventDestroy(e);
   void* bufs[] = {c->mlp_th, c->mlp_m, c->mlp_v, c->mlp_grad, c->mlp_gpart, c->mlp_lpart,
                   c->mlp_loss, c->mlp_w, c->log_rows, c->log_count};
-  for (void* b : bufs)
-    if (b) (void)hipFree(b);
+  for (void* b : bufs) dev_free(c, b);
   if (c->hpin) (void)hipHostFree(c->hpin);
   delete c;
   return TAFV_OK;
@@ -582,6 +614,22 @@ tafv_status tafv_destroy(tafv_ctx* c) {
 const char* tafv_last_error(const tafv_ctx* c) {
   return c ? c->err.c_str() : g_create_err.c_str();
 }
+
+tafv_status tafv_set_allocator(tafv_ctx* c, void* (*alloc)(size_t, void*),
+                               void (*dealloc)(void*, void*), void* user) {
+  if (!c) return TAFV_E_ARG;
+  if ((alloc == nullptr) != (dealloc == nullptr))
+    return fail(c, TAFV_E_ARG, "give both alloc and dealloc, or neither");
+  if (c->live_buffers != 0)
+    return fail(c, TAFV_E_ORDER, "the allocator can only change while the context holds no "
+                                 "device memory");
+  c->alloc_fn = alloc;
+  c->dealloc_fn = dealloc;
+  c->alloc_user = alloc ? user : nullptr;
+  return TAFV_OK;
+}
+
+int64_t tafv_device_buffers(const tafv_ctx* c) { return c ? c->live_buffers : -1; }
 
 tafv_status tafv_mesh_upload(tafv_ctx* c, int64_t n_nodes, const double* xyz, int64_t n_tets,
                              const int64_t* tets, int32_t* mesh_id) {
@@ -905,18 +953,18 @@ tafv_status tafv_mesh_motion(tafv_ctx* c, int32_t mesh_id, const double* node_ve
     if (!std::isfinite(node_vel[k])) return fail(c, TAFV_E_ARG, "non-finite node velocity");
   HIP_TRY(c, hipSetDevice(c->device));
   if (!m->sF) {
-    HIP_TRY(c, dalloc(&m->sF, std::max<int64_t>(m->nf, 1)));
-    HIP_TRY(c, dalloc(&m->Rv, std::max<int64_t>(m->nc, 1)));
+    HIP_TRY(c, dalloc(c, &m->sF, std::max<int64_t>(m->nf, 1)));
+    HIP_TRY(c, dalloc(c, &m->Rv, std::max<int64_t>(m->nc, 1)));
     HIP_TRY(c, launch_fill_f64(c->stream, m->Rv, 0.0, m->nc));
   }
   double* dvel = nullptr;
   const size_t bytes = sizeof(double) * 3 * (size_t)std::max<int64_t>(m->n_nodes, 1);
-  HIP_TRY(c, hipMalloc(&dvel, bytes));
+  HIP_TRY(c, dev_alloc(c, &dvel, bytes));
   hipError_t e = hipMemcpyAsync(dvel, node_vel, sizeof(double) * 3 * m->n_nodes,
                                 hipMemcpyHostToDevice, c->stream);
   if (e == hipSuccess) e = launch_face_speed(c->stream, *m, dvel);
   if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
-  (void)hipFree(dvel);
+  dev_free(c, dvel);
   if (e != hipSuccess) return hip_fail(c, e, "mesh motion");
   m->moving = true;
   return TAFV_OK;
@@ -942,36 +990,44 @@ static tafv_status ensure_mlp(tafv_ctx* c) {
   auto chk = [&](hipError_t x) {
     if (e == hipSuccess) e = x;
   };
-  chk(hipMalloc(&c->mlp_th, kMlpParams * sizeof(float)));
-  chk(hipMalloc(&c->mlp_m, kMlpParams * sizeof(float)));
-  chk(hipMalloc(&c->mlp_v, kMlpParams * sizeof(float)));
-  chk(hipMalloc(&c->mlp_grad, kMlpParams * sizeof(float)));
-  chk(hipMalloc(&c->mlp_loss, 4096 * sizeof(float)));
-  chk(hipMalloc(&c->mlp_w, sizeof(MlpDev)));
-  if (e != hipSuccess) return hip_fail(c, e, "network allocation");
+  chk(dev_alloc(c, &c->mlp_th, kMlpParams * sizeof(float)));
+  chk(dev_alloc(c, &c->mlp_m, kMlpParams * sizeof(float)));
+  chk(dev_alloc(c, &c->mlp_v, kMlpParams * sizeof(float)));
+  chk(dev_alloc(c, &c->mlp_grad, kMlpParams * sizeof(float)));
+  chk(dev_alloc(c, &c->mlp_loss, 4096 * sizeof(float)));
+  chk(dev_alloc(c, &c->mlp_w, sizeof(MlpDev)));
+  if (e != hipSuccess) {  // all or nothing: the next call starts over
+    for (float** q : {&c->mlp_th, &c->mlp_m, &c->mlp_v, &c->mlp_grad, &c->mlp_loss}) {
+      dev_free(c, *q);
+      *q = nullptr;
+    }
+    dev_free(c, c->mlp_w);
+    c->mlp_w = nullptr;
+    return hip_fail(c, e, "network allocation");
+  }
   return TAFV_OK;
 }
 
 static tafv_status ensure_gpart(tafv_ctx* c, int64_t rows) {
   int64_t nb = (rows + 63) / 64;
   if (nb <= c->mlp_gpart_blocks) return TAFV_OK;
-  if (c->mlp_gpart) (void)hipFree(c->mlp_gpart);
-  if (c->mlp_lpart) (void)hipFree(c->mlp_lpart);
+  dev_free(c, c->mlp_gpart);
+  dev_free(c, c->mlp_lpart);
   c->mlp_gpart = nullptr;
   c->mlp_lpart = nullptr;
   c->mlp_gpart_blocks = 0;
-  HIP_TRY(c, hipMalloc(&c->mlp_gpart, (size_t)nb * kMlpParams * sizeof(float)));
-  HIP_TRY(c, hipMalloc(&c->mlp_lpart, (size_t)nb * sizeof(float)));
+  HIP_TRY(c, dev_alloc(c, &c->mlp_gpart, (size_t)nb * kMlpParams * sizeof(float)));
+  HIP_TRY(c, dev_alloc(c, &c->mlp_lpart, (size_t)nb * sizeof(float)));
   c->mlp_gpart_blocks = nb;
   return TAFV_OK;
 }
 
 // device copies of host rows for the network calls, freed on scope exit
 struct DevBuf {
+  tafv_ctx* c;
   void* p = nullptr;
-  ~DevBuf() {
-    if (p) (void)hipFree(p);
-  }
+  explicit DevBuf(tafv_ctx* c_) : c(c_) {}
+  ~DevBuf() { dev_free(c, p); }
 };
 
 tafv_status tafv_mlp_set(tafv_ctx* c, const float* params, int64_t n) {
@@ -1010,9 +1066,9 @@ tafv_status tafv_mlp_forward(tafv_ctx* c, const float* x, int64_t n, float* y) {
   if (!c->mlp_ready) return fail(c, TAFV_E_MLP, "no network set");
   if (n == 0) return TAFV_OK;
   HIP_TRY(c, hipSetDevice(c->device));
-  DevBuf dx, dy;
-  HIP_TRY(c, hipMalloc(&dx.p, n * kMlpIn * sizeof(float)));
-  HIP_TRY(c, hipMalloc(&dy.p, n * sizeof(float)));
+  DevBuf dx(c), dy(c);
+  HIP_TRY(c, dev_malloc(c, &dx.p, n * kMlpIn * sizeof(float)));
+  HIP_TRY(c, dev_malloc(c, &dy.p, n * sizeof(float)));
   HIP_TRY(c, hipMemcpyAsync(dx.p, x, n * kMlpIn * sizeof(float), hipMemcpyHostToDevice, c->stream));
   HIP_TRY(c, mlp_forward(c->stream, (int)n, (const float*)dx.p, (const MlpDev*)c->mlp_w,
                          (float*)dy.p));
@@ -1029,9 +1085,9 @@ tafv_status tafv_mlp_grad(tafv_ctx* c, const float* x, const float* t, int64_t n
   HIP_TRY(c, hipSetDevice(c->device));
   tafv_status st = ensure_gpart(c, n);
   if (st != TAFV_OK) return st;
-  DevBuf dx, dt;
-  HIP_TRY(c, hipMalloc(&dx.p, n * kMlpIn * sizeof(float)));
-  HIP_TRY(c, hipMalloc(&dt.p, n * sizeof(float)));
+  DevBuf dx(c), dt(c);
+  HIP_TRY(c, dev_malloc(c, &dx.p, n * kMlpIn * sizeof(float)));
+  HIP_TRY(c, dev_malloc(c, &dt.p, n * sizeof(float)));
   HIP_TRY(c, hipMemcpyAsync(dx.p, x, n * kMlpIn * sizeof(float), hipMemcpyHostToDevice, c->stream));
   HIP_TRY(c, hipMemcpyAsync(dt.p, t, n * sizeof(float), hipMemcpyHostToDevice, c->stream));
   HIP_TRY(c, mlp_fill(c->stream, c->mlp_loss, 0.f, 1));
@@ -1074,9 +1130,9 @@ tafv_status tafv_mlp_train(tafv_ctx* c, const float* x, const float* t, int64_t 
   HIP_TRY(c, hipSetDevice(c->device));
   tafv_status st = ensure_gpart(c, std::min<int64_t>(batch, n));
   if (st != TAFV_OK) return st;
-  DevBuf dx, dt;
-  HIP_TRY(c, hipMalloc(&dx.p, n * kMlpIn * sizeof(float)));
-  HIP_TRY(c, hipMalloc(&dt.p, n * sizeof(float)));
+  DevBuf dx(c), dt(c);
+  HIP_TRY(c, dev_malloc(c, &dx.p, n * kMlpIn * sizeof(float)));
+  HIP_TRY(c, dev_malloc(c, &dt.p, n * sizeof(float)));
   HIP_TRY(c, hipMemcpyAsync(dx.p, x, n * kMlpIn * sizeof(float), hipMemcpyHostToDevice, c->stream));
   HIP_TRY(c, hipMemcpyAsync(dt.p, t, n * sizeof(float), hipMemcpyHostToDevice, c->stream));
   HIP_TRY(c, mlp_fill(c->stream, c->mlp_loss, 0.f, std::max(epochs, 1)));
@@ -1112,12 +1168,12 @@ tafv_status tafv_facelog_config(tafv_ctx* c, int64_t capacity, double rate, uint
     return fail(c, TAFV_E_ARG, "face logging is not available on moving meshes");
   HIP_TRY(c, hipSetDevice(c->device));
   HIP_TRY(c, hipStreamSynchronize(c->stream));
-  if (c->log_rows) (void)hipFree(c->log_rows);
+  dev_free(c, c->log_rows);
   c->log_rows = nullptr;
   c->log_cap = 0;
-  if (!c->log_count) HIP_TRY(c, hipMalloc(&c->log_count, sizeof(unsigned long long)));
+  if (!c->log_count) HIP_TRY(c, dev_alloc(c, &c->log_count, sizeof(unsigned long long)));
   HIP_TRY(c, launch_fill_u64(c->stream, c->log_count, 0ull, 1));
-  if (capacity > 0) HIP_TRY(c, hipMalloc(&c->log_rows, (size_t)capacity * 7 * sizeof(float)));
+  if (capacity > 0) HIP_TRY(c, dev_alloc(c, &c->log_rows, (size_t)capacity * 7 * sizeof(float)));
   HIP_TRY(c, hipStreamSynchronize(c->stream));
   c->log_cap = capacity;
   c->log_rate = rate;

@@ -228,6 +228,13 @@ struct tafv_ctx {
   uint64_t log_seed = 0;
   // batched form (params.batch = 1)
   tafv::Batch* batch = nullptr;
+  // device memory: the caller's allocator (tafv_set_allocator) or, when
+  // none is set, hipMalloc / hipFree; live_buffers counts what the context
+  // holds, so the allocator can only change while it holds nothing
+  void* (*alloc_fn)(size_t, void*) = nullptr;
+  void (*dealloc_fn)(void*, void*) = nullptr;
+  void* alloc_user = nullptr;
+  int64_t live_buffers = 0;
 };
 
 namespace tafv {
@@ -236,7 +243,15 @@ namespace tafv {
 tafv_status set_error(tafv_ctx* c, tafv_status st, const std::string& msg);
 tafv_status hip_error(tafv_ctx* c, hipError_t e, const char* what);
 tafv_status upload_host_mesh(tafv_ctx* c, const HostMesh& hm, DevMesh** out);
-void free_dev_mesh(DevMesh* m);
+void free_dev_mesh(tafv_ctx* c, DevMesh* m);
+// every device buffer of a context goes through these two; dev_malloc
+// returns hipErrorOutOfMemory when the allocator returns NULL
+hipError_t dev_malloc(tafv_ctx* c, void** p, size_t bytes);
+void dev_free(tafv_ctx* c, void* p);
+template <typename T>
+hipError_t dev_alloc(tafv_ctx* c, T** p, size_t bytes) {
+  return dev_malloc(c, reinterpret_cast<void**>(p), bytes);
+}
 // sums the slot counters of m into st (newton ... guess_used, wall impulse)
 tafv_status read_slot_counters(tafv_ctx* c, DevMesh& m, tafv_stats* st);
 

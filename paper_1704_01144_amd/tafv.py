@@ -22,6 +22,10 @@ SCATTER_COLOUR, SCATTER_GATHER = 0, 1
 ORDER_CALLER, ORDER_MORTON = 0, 1
 
 
+ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p)
+DEALLOC_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p)
+
+
 class TafvError(RuntimeError):
     def __init__(self, code, msg):
         super().__init__(f"tafv error {code}: {msg}")
@@ -56,9 +60,22 @@ class tafv_stats(C.Structure):
         return d
 
 
+def _one_hip_runtime():
+    """PyTorch's ROCm wheels carry their own HIP runtime, whose library has
+    the same soname as the system's.  Loaded before PyTorch, libtafv.so
+    would bring in the system runtime, PyTorch would then load its own next
+    to it, and the second runtime to initialise finds no device.  Loading
+    PyTorch first (when it is installed) makes libtafv.so bind to PyTorch's
+    runtime, so that the process has one."""
+    import importlib.util
+    if importlib.util.find_spec("torch") is not None:
+        import torch  # noqa: F401
+
+
 def _load():
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is not built; run __graft_entry__.build()")
+    _one_hip_runtime()
     L = C.CDLL(LIB_PATH)
     P = C.c_void_p
     dp, i64p, i8p, i32p = (C.POINTER(C.c_double), C.POINTER(C.c_int64), C.POINTER(C.c_int8),
@@ -68,6 +85,7 @@ def _load():
         "tafv_params_default": [C.POINTER(tafv_params)],
         "tafv_create": [C.c_int, C.POINTER(tafv_params), P, C.POINTER(P)],
         "tafv_destroy": [P],
+        "tafv_set_allocator": [P, ALLOC_FN, DEALLOC_FN, P],
         "tafv_mesh_upload": [P, C.c_int64, dp, C.c_int64, i64p, i32p],
         "tafv_mesh_params": [P, C.c_int32, C.c_int32],
         "tafv_mesh_motion": [P, C.c_int32, dp],
@@ -101,6 +119,8 @@ def _load():
         fn.restype = C.c_int
     L.tafv_last_error.argtypes = [P]
     L.tafv_last_error.restype = C.c_char_p
+    L.tafv_device_buffers.argtypes = [P]
+    L.tafv_device_buffers.restype = C.c_int64
     return L
 
 
@@ -108,10 +128,12 @@ lib = _load()
 
 # every symbol the header declares (checked by the CPU tests)
 EXPORTS = ["tafv_params_default", "tafv_create", "tafv_destroy", "tafv_last_error",
+           "tafv_set_allocator", "tafv_device_buffers",
            "tafv_mesh_upload", "tafv_mesh_inspect", "tafv_mesh_params", "tafv_state_init", "tafv_state_reset", "tafv_advance",
            "tafv_mesh_stats", "tafv_state_read", "tafv_checkpoint_read", "tafv_checkpoint_write",
            "tafv_profile_enable", "tafv_profile_read", "tafv_guess_config", "tafv_mlp_set", "tafv_mlp_get",
-           "tafv_mlp_forward", "tafv_mlp_grad", "tafv_mlp_train", "tafv_facelog_config",
+           "tafv_mlp_forward", "tafv_mlp_grad", "tafv_mlp_train",
+           "tafv_facelog_config",
            "tafv_facelog_read", "tafv_batch_config", "tafv_batch_info", "tafv_mesh_motion",
            "tafv_volume_read"]
 MLP_PARAMS = 1313
@@ -144,6 +166,53 @@ def tafv_create(device=0, params=None, hip_stream=None):
 
 def tafv_destroy(ctx):
     _check(lib.tafv_destroy(ctx))
+
+
+def tafv_set_allocator(ctx, alloc=None, dealloc=None):
+    """Route the context's device memory through Python callables:
+    alloc(nbytes) -> device pointer as an int (0 when it cannot) and
+    dealloc(ptr).  Both None restores hipMalloc / hipFree.  Returns the
+    ctypes wrappers, which must stay alive as long as the context."""
+    if (alloc is None) != (dealloc is None):
+        raise ValueError("give both alloc and dealloc, or neither")
+    if alloc is None:
+        _check(lib.tafv_set_allocator(ctx, ALLOC_FN(), DEALLOC_FN(), None), ctx)
+        return None
+
+    def _alloc(n, _user):
+        try:
+            return int(alloc(int(n)) or 0)
+        except Exception:  # an exception must not cross into the library
+            return 0
+
+    def _dealloc(ptr, _user):
+        dealloc(int(ptr))
+
+    keep = (ALLOC_FN(_alloc), DEALLOC_FN(_dealloc))
+    _check(lib.tafv_set_allocator(ctx, keep[0], keep[1], None), ctx)
+    return keep
+
+
+def torch_allocator(device=0, stream=None):
+    """alloc/dealloc callables over PyTorch's caching allocator on `device`
+    and `stream` (a torch.cuda.Stream or raw stream handle; None: the
+    current stream), for tafv_set_allocator."""
+    import torch
+
+    def alloc(n):
+        try:
+            return torch.cuda.caching_allocator_alloc(n, device, stream)
+        except RuntimeError:  # out of memory
+            return 0
+
+    def dealloc(ptr):
+        torch.cuda.caching_allocator_delete(ptr)
+
+    return alloc, dealloc
+
+
+def tafv_device_buffers(ctx):
+    return int(lib.tafv_device_buffers(ctx))
 
 
 def tafv_mesh_upload(ctx, nodes, tets):
@@ -340,10 +409,19 @@ def tafv_batch_info(ctx):
 class Solver:
     """One context with one or more meshes."""
 
-    def __init__(self, device=0, hip_stream=None, **params):
+    def __init__(self, device=0, hip_stream=None, allocator=None, **params):
+        """allocator: None (hipMalloc), or (alloc, dealloc) callables for
+        tafv_set_allocator, e.g. torch_allocator(device, stream)."""
         self.params = tafv_params_default(**params)
         self.ctx = tafv_create(device, self.params, hip_stream)
         self.n_cells = []
+        self._alloc_keep = None
+        if allocator is not None:
+            try:
+                self._alloc_keep = tafv_set_allocator(self.ctx, *allocator)
+            except Exception:
+                self.close()
+                raise
 
     def upload(self, nodes, tets, max_levels=None):
         mid = tafv_mesh_upload(self.ctx, nodes, tets)

@@ -20,7 +20,7 @@ def T():
 
 def test_exports_every_declared_symbol(T):
     hdr = open(os.path.join(ROOT, "include", "tafv.h")).read()
-    declared = set(re.findall(r"^\s*(?:const\s+char\s*\*|tafv_status)\s+(tafv_\w+)\s*\(", hdr,
+    declared = set(re.findall(r"^\s*(?:const\s+char\s*\*|tafv_status|int64_t)\s+(tafv_\w+)\s*\(", hdr,
                               re.M))
     assert len(declared) >= 15
     for name in declared:
