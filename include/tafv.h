@@ -361,6 +361,21 @@ tafv_status tafv_mlp_forward(tafv_ctx* ctx, const float* x, int64_t n, float* y)
 tafv_status tafv_mlp_grad(tafv_ctx* ctx, const float* x, const float* t, int64_t n,
                           float* grad, float* loss);
 
+/* tafv_mlp_grad for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * the same kernels and the same result, bit for bit, with the device
+ * staging of x and t, the per-block partial sums, the gradient and the loss
+ * in a scratch area the library holds in a static device array, one per GPU
+ * (about 7.2 MB, kept from the first tafv_create() on that GPU until the
+ * process ends).  The call allocates nothing; its host arrays are as in
+ * tafv_mlp_grad.  n must be 1..TAFV_MLP_GRAD_NOALLOC_MAX_ROWS (TAFV_E_ARG
+ * otherwise).  Every call on one GPU shares that GPU's scratch: calls that
+ * overlap on one GPU (from several contexts, streams or threads) race and
+ * must be serialised by the caller. */
+#define TAFV_MLP_GRAD_NOALLOC_MAX_ROWS 65536
+tafv_status tafv_mlp_grad_noalloc(tafv_ctx* ctx, const float* x, const float* t, int64_t n,
+                                  float* grad, float* loss);
+
 /* Train on the GPU with Adam (lr, beta1 0.9, beta2 0.999, eps 1e-8) for
  * `epochs` passes over the n rows in minibatches of `batch` rows; each
  * epoch visits the rows in the order i -> (a i + b) mod n with a, b drawn

@@ -5,6 +5,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -16,6 +17,49 @@
 using namespace tafv;
 
 namespace {
+
+// ---- scratch of the network gradient that allocates nothing ---------------
+// tafv_mlp_grad_noalloc keeps its staging and partial results in one
+// file-scope device array per GPU instead of buffers it allocates.  Layout
+// (floats, each part 64-float aligned): per-block partial gradients
+// [rows / 64][1313], per-block partial losses [rows / 64], inputs x
+// [rows][6], targets [rows], the gradient [1313], the loss [1].
+constexpr int64_t kScrRows = TAFV_MLP_GRAD_NOALLOC_MAX_ROWS;
+constexpr int64_t kScrBlocks = kScrRows / 64;
+constexpr size_t scr_up(size_t n) { return (n + 63) / 64 * 64; }
+constexpr size_t kScrGpart = 0;
+constexpr size_t kScrLpart = scr_up(kScrGpart + (size_t)kScrBlocks * kMlpParams);
+constexpr size_t kScrX = scr_up(kScrLpart + kScrBlocks);
+constexpr size_t kScrT = scr_up(kScrX + (size_t)kScrRows * kMlpIn);
+constexpr size_t kScrGrad = scr_up(kScrT + kScrRows);
+constexpr size_t kScrLoss = scr_up(kScrGrad + kMlpParams);
+constexpr size_t kScrFloats = scr_up(kScrLoss + 1);
+static_assert(kScrRows % 64 == 0, "whole 64-row blocks");
+
+static __device__ __align__(256) float scratch[kScrFloats];
+
+// The array's device address on each GPU, taken once per device at context
+// creation (the host-side name is not a device address).
+constexpr int kScrMaxDevices = 64;
+std::mutex g_scr_mu;
+float* g_scr_ptr[kScrMaxDevices] = {};
+
+// with `device` current
+hipError_t scratch_setup(int device) {
+  std::lock_guard<std::mutex> lock(g_scr_mu);
+  if (device < 0 || device >= kScrMaxDevices) return hipErrorInvalidDevice;
+  if (g_scr_ptr[device]) return hipSuccess;
+  void* p = nullptr;
+  hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+  if (e != hipSuccess) return e;
+  g_scr_ptr[device] = static_cast<float*>(p);
+  return hipSuccess;
+}
+
+float* scratch_ptr(int device) {
+  std::lock_guard<std::mutex> lock(g_scr_mu);
+  return (device >= 0 && device < kScrMaxDevices) ? g_scr_ptr[device] : nullptr;
+}
 
 const char* kProfNames[] = {"classify", "grad",    "flux",          "update",
                             "gather",   "predict", "flux_corrector"};
@@ -569,6 +613,8 @@ tafv_status tafv_create(int device, const tafv_params* params, void* hip_stream,
   if (device < 0 || device >= ndev) return fail(nullptr, TAFV_E_ARG, "device out of range");
   e = hipSetDevice(device);
   if (e != hipSuccess) return hip_fail(nullptr, e, "hipSetDevice");
+  e = scratch_setup(device);
+  if (e != hipSuccess) return hip_fail(nullptr, e, "hipGetSymbolAddress (no-allocation scratch)");
   tafv_ctx* c = new (std::nothrow) tafv_ctx();
   if (!c) return fail(nullptr, TAFV_E_OOM, "host allocation failed");
   c->device = device;
@@ -1099,6 +1145,33 @@ tafv_status tafv_mlp_grad(tafv_ctx* c, const float* x, const float* t, int64_t n
                               hipMemcpyDeviceToHost, c->stream));
   float l = 0.f;
   HIP_TRY(c, hipMemcpyAsync(&l, c->mlp_loss, sizeof(float), hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  if (loss) *loss = l;
+  return TAFV_OK;
+}
+
+tafv_status tafv_mlp_grad_noalloc(tafv_ctx* c, const float* x, const float* t, int64_t n,
+                                  float* grad, float* loss) {
+  if (!c) return TAFV_E_ARG;
+  if (!x || !t || n < 1) return fail(c, TAFV_E_ARG, "invalid arguments");
+  if (n > kScrRows)
+    return fail(c, TAFV_E_ARG, "more rows than the no-allocation scratch holds");
+  if (!c->mlp_ready) return fail(c, TAFV_E_MLP, "no network set");
+  HIP_TRY(c, hipSetDevice(c->device));
+  float* base = scratch_ptr(c->device);
+  if (!base) return fail(c, TAFV_E_DEVICE, "no-allocation scratch not set up on this device");
+  float *sx = base + kScrX, *st = base + kScrT, *sgrad = base + kScrGrad, *sloss = base + kScrLoss;
+  HIP_TRY(c, hipMemcpyAsync(sx, x, n * kMlpIn * sizeof(float), hipMemcpyHostToDevice, c->stream));
+  HIP_TRY(c, hipMemcpyAsync(st, t, n * sizeof(float), hipMemcpyHostToDevice, c->stream));
+  HIP_TRY(c, mlp_fill(c->stream, sloss, 0.f, 1));
+  HIP_TRY(c, mlp_gradient(c->stream, 1ull, 0ull, (unsigned long long)n, 0, n, sx, st,
+                          (const MlpDev*)c->mlp_w, base + kScrGpart, base + kScrLpart, sgrad,
+                          sloss, 1.0f / (float)n));
+  if (grad)
+    HIP_TRY(c, hipMemcpyAsync(grad, sgrad, kMlpParams * sizeof(float), hipMemcpyDeviceToHost,
+                              c->stream));
+  float l = 0.f;
+  HIP_TRY(c, hipMemcpyAsync(&l, sloss, sizeof(float), hipMemcpyDeviceToHost, c->stream));
   HIP_TRY(c, hipStreamSynchronize(c->stream));
   if (loss) *loss = l;
   return TAFV_OK;

@@ -106,6 +106,7 @@ def _load():
         "tafv_mlp_get": [P, fp, C.c_int64],
         "tafv_mlp_forward": [P, fp, C.c_int64, fp],
         "tafv_mlp_grad": [P, fp, fp, C.c_int64, fp, fp],
+        "tafv_mlp_grad_noalloc": [P, fp, fp, C.c_int64, fp, fp],
         "tafv_mlp_train": [P, fp, fp, C.c_int64, C.c_int32, C.c_int32, C.c_float, C.c_uint64, fp],
         "tafv_facelog_config": [P, C.c_int64, C.c_double, C.c_uint64],
         "tafv_facelog_read": [P, fp, C.c_int64, i64p],
@@ -132,11 +133,12 @@ EXPORTS = ["tafv_params_default", "tafv_create", "tafv_destroy", "tafv_last_erro
            "tafv_mesh_upload", "tafv_mesh_inspect", "tafv_mesh_params", "tafv_state_init", "tafv_state_reset", "tafv_advance",
            "tafv_mesh_stats", "tafv_state_read", "tafv_checkpoint_read", "tafv_checkpoint_write",
            "tafv_profile_enable", "tafv_profile_read", "tafv_guess_config", "tafv_mlp_set", "tafv_mlp_get",
-           "tafv_mlp_forward", "tafv_mlp_grad", "tafv_mlp_train",
+           "tafv_mlp_forward", "tafv_mlp_grad", "tafv_mlp_grad_noalloc", "tafv_mlp_train",
            "tafv_facelog_config",
            "tafv_facelog_read", "tafv_batch_config", "tafv_batch_info", "tafv_mesh_motion",
            "tafv_volume_read"]
 MLP_PARAMS = 1313
+MLP_GRAD_NOALLOC_MAX_ROWS = 65536
 
 
 def _d(a):
@@ -338,6 +340,17 @@ def tafv_mlp_grad(ctx, x, t):
     g = np.empty(MLP_PARAMS, np.float32)
     loss = np.zeros(1, np.float32)
     _check(lib.tafv_mlp_grad(ctx, _f(x), _f(t), x.shape[0], _f(g), _f(loss)), ctx)
+    return g, float(loss[0])
+
+
+def tafv_mlp_grad_noalloc(ctx, x, t):
+    """tafv_mlp_grad without device allocation (library scratch, at most
+    MLP_GRAD_NOALLOC_MAX_ROWS rows)."""
+    x = np.ascontiguousarray(x, dtype=np.float32)
+    t = np.ascontiguousarray(t, dtype=np.float32)
+    g = np.empty(MLP_PARAMS, np.float32)
+    loss = np.zeros(1, np.float32)
+    _check(lib.tafv_mlp_grad_noalloc(ctx, _f(x), _f(t), x.shape[0], _f(g), _f(loss)), ctx)
     return g, float(loss[0])
 
 
