@@ -50,6 +50,23 @@ BYTES_PER_ITEM_GATHER = {
     "fp64": {"flux": 160, "grad": 316, "gather": 270},
     "fp32": {"flux": 88, "grad": 188, "gather": 230},
 }
+# the other forms (gather mode): the predictor/corrector form's corrector
+# pass also reads the predictor flux (5 values in the flux precision) and its
+# cell kernel also writes the corrected state to the interpolated-state array
+# (40 bytes); a moving mesh's flux kernel also reads the face's volume rate
+# (8) and its cell kernel about two volume rates (16) and the pending swept
+# volume read + write (16).
+BYTES_PER_ITEM_FORM = {
+    "fp64": BYTES_PER_ITEM_GATHER["fp64"],
+    "fp32": BYTES_PER_ITEM_GATHER["fp32"],
+    "fp32_learned": BYTES_PER_ITEM_GATHER["fp32"],
+    "time2_fp64": {"flux": 160, "flux_corrector": 200, "grad": 316, "gather": 310},
+    "time2_fp32": {"flux": 88, "flux_corrector": 108, "grad": 188, "gather": 270},
+    "moving_fp64": {"flux": 168, "grad": 316, "gather": 302},
+}
+# kernel of each timing class, by form (names of the counter records)
+KERNEL_OF_CLASS = {"flux": "k_flux", "flux_corrector": "k_flux", "grad": "k_grad",
+                   "gather": "k_gather", "update": "k_update"}
 
 
 def log(*a):
@@ -216,6 +233,52 @@ def run_batch(T, torch, cases, steps, warmup, precision, mlp=None, graph=1):
     return dict(ms=ms, setup_s=setup_s, info=info, cons=cons, **tot)
 
 
+def run_group(T, torch, cases, steps, warmup, precision, mlp=None, workers=8, nstreams=8):
+    """The batched workload run the task-based way: one single-mesh context
+    per mesh, contexts spread over `nstreams` streams, all advanced together
+    by tafv_advance_group with `workers` host threads (each mesh's
+    subiterations are chained on its stream; no mesh waits for another at a
+    subiteration boundary).  Timed on the host clock between two device
+    synchronisations (several streams)."""
+    extra = {}
+    if mlp is not None:
+        extra = dict(guess=T.GUESS_MLP, guess_gate=mlp["gate"], guess_strength=mlp["strength"])
+    streams = [torch.cuda.Stream() for _ in range(nstreams)]
+    t0 = time.perf_counter()
+    ss = []
+    for k, c in enumerate(cases):
+        st = streams[k % nstreams]
+        s = T.Solver(device=0, hip_stream=st.cuda_stream, order=2, precision=precision,
+                     max_levels=c["max_levels"], allocator=T.torch_allocator(0, st), **extra)
+        s.upload(c["nodes"], c["tets"])
+        if mlp is not None:
+            T.tafv_mlp_set(s.ctx, mlp["theta"])
+        s.init(c["prim"])
+        ss.append(s)
+    setup_s = time.perf_counter() - t0
+    ctxs = [s.ctx for s in ss]
+
+    def step():
+        for s in ss:
+            T.tafv_state_reset(s.ctx, 0)
+        T.tafv_advance_group(ctxs, BATCH_UNITS, workers, stats=False)
+
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    u0 = sum(s.stats()["cell_updates"] for s in ss)
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        step()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    u1 = sum(s.stats()["cell_updates"] for s in ss)
+    cons = [s.read()[0] for s in ss]
+    for s in ss:
+        s.close()
+    return dict(ms=wall * 1e3, setup_s=setup_s, cell_updates=u1 - u0, cons=cons)
+
+
 def batch_l1(cases, ref, got):
     worst = 0.0
     for c, a, b in zip(cases, got, ref):
@@ -236,12 +299,12 @@ def l1_errors(cfg, ref, got):
     return e
 
 
-def measured_traffic(kernel, dtype):
-    """HBM bytes per launch of `kernel` from the committed counter record
-    (FETCH_SIZE and WRITE_SIZE scaled by a plain copy), or None when there is
-    no record or the library sources changed after it was taken."""
+def measured_traffic(kernel, form):
+    """HBM bytes per launch of `kernel` in `form` from the committed counter
+    record (FETCH_SIZE and WRITE_SIZE scaled by a plain copy), or None when
+    there is no record or the library sources changed after it was taken."""
     from paper_1704_01144_amd import profile_summary as PS
-    path = os.path.join(ROOT, "profiles", f"{kernel}_graded64_blast_{dtype}_counters.txt")
+    path = os.path.join(ROOT, "profiles", f"{kernel}_graded64_blast_{form}_counters.txt")
     if not os.path.exists(path):
         return None, "no counter record"
     rec = PS.read_record(path)
@@ -250,17 +313,20 @@ def measured_traffic(kernel, dtype):
     return int(float(rec["traffic_bytes_per_launch"])), os.path.relpath(path, ROOT)
 
 
-def roofline(prof, bytes_per_item, dtype):
-    dom = max((k for k in prof if k in bytes_per_item), key=lambda k: prof[k]["ms"])
+def roofline(prof, bytes_per_item, form):
+    """Roofline entry of the longest kernel class of a run with a known
+    algorithmic byte count per item."""
+    dom = max((k for k in prof if k in bytes_per_item and prof[k]["items"] > 0),
+              key=lambda k: prof[k]["ms"])
     p = prof[dom]
     achieved = bytes_per_item[dom] * p["items"] / (p["ms"] * 1e-3) / 1e9
-    name = "k_flux" if dom == "flux" else "k_" + dom
-    traffic, src = measured_traffic(name, dtype)
+    name = KERNEL_OF_CLASS[dom] + ("_corrector" if dom == "flux_corrector" else "")
+    traffic, src = measured_traffic(name, form)
     launches = max(p["launches"], 1)
     return dom, {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                  "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                  "traffic_unit": "HBM bytes per launch", "traffic_source": src,
-                 "kernel": name,
+                 "kernel": name, "timing_class": dom,
                  "avg_launch_us": round(1e3 * p["ms"] / launches, 2),
                  "bytes_per_item": bytes_per_item[dom], "items": p["items"],
                  "launches": p["launches"],
@@ -316,32 +382,58 @@ def host_cpu():
     return model, os.cpu_count()
 
 
-def cpu_baseline(cfg, units=24, variant="seq"):
-    """The oracle on the first `units` subiterations of the same workload:
-    variant "seq" is the sequential parity reference (one thread; 24 units,
-    three full iterations at theta = 3, about 15 s), "omp" the same source
-    built with OpenMP (same bits, per-cell and per-face loops on all the
-    host threads that OMP_NUM_THREADS allows)."""
+def cpu_baseline(cfg, units=24, variant="seq", repeats=1):
+    """The oracle on the first `units` subiterations of the same workload,
+    `repeats` times from the initial state: variant "seq" is the sequential
+    parity reference (one thread; 24 units, three full iterations at
+    theta = 3, about 15 s), "omp" the same source built with OpenMP (same
+    bits, per-cell and per-face loops on all the host threads that
+    OMP_NUM_THREADS allows)."""
     from oracle import core as orc
     orc.select(variant)
     try:
         m = orc.Mesh(cfg["nodes"], cfg["tets"])
-        o = orc.State(m, cfg["prim"], orc.params(max_levels=cfg["max_levels"], order=cfg["order"]))
+        prm = orc.params(max_levels=cfg["max_levels"], order=cfg["order"])
         threads = orc.threads()
-        t0 = time.perf_counter()
-        o.advance(units)
-        dt = time.perf_counter() - t0
-        st = o.stats()
+        dt, updates = 0.0, 0
+        for _ in range(repeats):
+            o = orc.State(m, cfg["prim"], prm)
+            t0 = time.perf_counter()
+            o.advance(units)
+            dt += time.perf_counter() - t0
+            updates += o.stats()["cell_updates"]
     finally:
         orc.select("seq")
     model, ncpu = host_cpu()
-    return {"value": round(st["cell_updates"] / dt, 1), "unit": "cell-updates/s",
+    what = f"first {units} of {UNITS} dt_min units" if units < UNITS else f"{UNITS} dt_min units"
+    return {"value": round(updates / dt, 1), "unit": "cell-updates/s",
             "cores": threads, "kind": "oracle",
-            "sample": f"first {units} of {UNITS} dt_min units (cell updates {st['cell_updates']}, "
-                      f"{dt:.1f} s) on the same 1,572,864-cell mesh and state, FP64, "
+            "sample": f"{what}{f', {repeats} times' if repeats > 1 else ''} (cell updates "
+                      f"{updates}, {dt:.1f} s) on the same 1,572,864-cell mesh and state, FP64, "
                       f"{threads} thread{'s' if threads > 1 else ''}"
                       + (" (OpenMP build of the same source, bit-identical)" if threads > 1 else ""),
             "host_cpu": model, "host_logical_cpus": ncpu}
+
+
+FORMS = ("fp64", "fp32_flux", "fp32_learned", "time_order_2_fp64", "time_order_2_fp32_flux",
+         "moving_mesh_fp64", "batched")
+
+
+def with_roofline(entry, run, bpi, form, copy_gbs):
+    """Adds the roofline of the run's longest kernel (algorithmic bytes per
+    launch over its average launch time, from HIP events on the library's
+    stream), its share of a plain copy's bandwidth and the kernel times."""
+    _, roof = roofline(run["prof"], bpi, form)
+    if copy_gbs:
+        roof["copy_gbs_measured"] = round(copy_gbs, 1)
+        roof["frac_of_copy"] = round(roof["achieved"] / copy_gbs, 4)
+        if roof["traffic"] is not None:
+            tgbs = roof["traffic"] / (roof["avg_launch_us"] * 1e-6) / 1e9
+            roof["traffic_gbs"] = round(tgbs, 1)
+            roof["traffic_frac_of_copy"] = round(tgbs / copy_gbs, 4)
+    entry["roofline"] = roof
+    entry["kernels_ms"] = {k: round(v["ms"], 3) for k, v in run["prof"].items()}
+    return entry
 
 
 def main():
@@ -358,6 +450,8 @@ def main():
     ap.add_argument("--no-time2", action="store_true",
                     help="skip the predictor/corrector form (second order in time)")
     ap.add_argument("--no-moving", action="store_true", help="skip the moving-mesh form")
+    ap.add_argument("--only", choices=FORMS,
+                    help="run this form alone (for profiling); prints its entry as the JSON line")
     ap.add_argument("--cell-order", type=int, default=0,
                     help="internal cell order: 0 the mesh's own, 1 Morton order of the centroids")
     ap.add_argument("--batch-only", action="store_true",
@@ -367,7 +461,7 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
-              "(the multi-GPU decomposition is a design, not part of this build)", file=sys.stderr)
+              "(the multi-GPU decomposition is not implemented)", file=sys.stderr)
         sys.exit(2)
 
     if args.copy_probe:
@@ -390,116 +484,141 @@ def main():
             log(f"batched {name}: {v / 1e9:.3f} G cell-updates/s, {r['ms'] / args.steps:.2f} ms "
                 f"per step, launch {r['info']}")
         return
+    want = (lambda f: f == args.only) if args.only else (lambda f: True)
+    if args.only:  # a single form: no reference run, baseline or copy timing
+        args.no_cpu_baseline = True
     cfg = I.config_scale(args.n, 0)
     log(f"workload: {len(cfg['tets'])} cells, order {cfg['order']}, L {cfg['max_levels']}, "
         f"{UNITS} units, steps {args.steps}, warmup {args.warmup}")
-    r64 = run_form(T, torch, cfg, T.FP64, args.steps, args.warmup, args.scatter)
-    value = r64["updates"] / (r64["ms"] * 1e-3)
-    log(f"fp64: {r64['ms']:.2f} ms for {args.steps} steps, {value / 1e9:.3f} G cell-updates/s")
     bpi = BYTES_PER_ITEM_GATHER if args.scatter == 1 else BYTES_PER_ITEM
-    dom, roof = roofline(r64["prof"], bpi["fp64"], "fp64")
-    copy_gbs = copy_bandwidth(torch)
-    roof["copy_gbs_measured"] = round(copy_gbs, 1)
-    roof["frac_of_copy"] = round(roof["achieved"] / copy_gbs, 4)
-    if roof["traffic"] is not None:
-        tgbs = roof["traffic"] / (roof["avg_launch_us"] * 1e-6) / 1e9
-        roof["traffic_gbs"] = round(tgbs, 1)
-        roof["traffic_frac_of_copy"] = round(tgbs / copy_gbs, 4)
-    log(f"copy: {copy_gbs:.0f} GB/s read+write; dominant kernel {roof['kernel']} at "
-        f"{roof['achieved']:.0f} GB/s algorithmic ({roof['frac']:.3f} of 8 TB/s)")
-    out = {
-        "metric": "cell-updates/s, 1.57M-tet graded mesh: FP64 plain vs FP32+learned @ L1 err",
-        "value": round(value, 1),
-        "unit": "cell-updates/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": round(r64["ms"] / args.steps, 4),
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "f64",
-        "data": "synthetic",
-        "config": {"workload": f"graded blast, {args.n}^3 hexes x 6 tets "
-                               f"({len(cfg['tets'])} cells), grading 16, MUSCL-LSQ + "
-                               f"Barth-Jespersen, exact Riemann (Newton tol 1e-12), <= 5 "
-                               f"levels, {UNITS} dt_min units, walls, seed 0",
-                   "cells": len(cfg["tets"]), "units": UNITS,
-                   "cell_updates_per_step": r64["updates"] // args.steps,
-                   "face_solves_per_step": r64["faces"] // args.steps,
-                   "newton_updates_per_face": round(r64["newton"] / max(r64["faces"], 1), 3),
-                   "levels_t0": r64["stats"]["cells_per_level"][:5]},
-        "roofline": roof,
-        "kernels_ms": {k: round(v["ms"], 3) for k, v in r64["prof"].items()},
-        "profiled_pass_ms_per_step": round(r64["ms_prof"] / args.steps, 4),
-    }
-    if not args.no_fp32:
+    copy_gbs = None if args.only else copy_bandwidth(torch)
+    out = {}
+    forms = {}
+    r64 = None
+    if want("fp64") or not args.only:
+        r64 = run_form(T, torch, cfg, T.FP64, args.steps, args.warmup, args.scatter)
+        value = r64["updates"] / (r64["ms"] * 1e-3)
+        log(f"fp64: {r64['ms']:.2f} ms for {args.steps} steps, {value / 1e9:.3f} G cell-updates/s")
+        head = with_roofline({}, r64, bpi["fp64"], "fp64", copy_gbs)
+        roof = head["roofline"]
+        log(f"dominant kernel {roof['kernel']} at {roof['achieved']:.0f} GB/s algorithmic "
+            f"({roof['frac']:.3f} of 8 TB/s)" +
+            (f"; copy {copy_gbs:.0f} GB/s read+write" if copy_gbs else ""))
+        out = {
+            "metric": "cell-updates/s, 1.57M-tet graded mesh: FP64 plain vs FP32+learned @ L1 err",
+            "value": round(value, 1),
+            "unit": "cell-updates/s",
+            "n_gpus": 1,
+            "steps": args.steps,
+            "warmup": args.warmup,
+            "ms_per_step": round(r64["ms"] / args.steps, 4),
+            "higher_is_better": True,
+            "scaling": "weak",
+            "vs_baseline": None,
+            "dtype": "f64",
+            "data": "synthetic",
+            "config": {"workload": f"graded blast, {args.n}^3 hexes x 6 tets "
+                                   f"({len(cfg['tets'])} cells), grading 16, MUSCL-LSQ + "
+                                   f"Barth-Jespersen, exact Riemann (Newton tol 1e-12), <= 5 "
+                                   f"levels, {UNITS} dt_min units, walls, seed 0",
+                       "cells": len(cfg["tets"]), "units": UNITS,
+                       "cell_updates_per_step": r64["updates"] // args.steps,
+                       "face_solves_per_step": r64["faces"] // args.steps,
+                       "newton_updates_per_face": round(r64["newton"] / max(r64["faces"], 1), 3),
+                       "levels_t0": r64["stats"]["cells_per_level"][:5]},
+            "roofline": roof,
+            "kernels_ms": head["kernels_ms"],
+            "profiled_pass_ms_per_step": round(r64["ms_prof"] / args.steps, 4),
+        }
+
+    def l1_vs_fp64(entry, run, ref=None):
+        ref = ref if ref is not None else r64
+        if ref is not None:
+            entry["l1_rho"], entry["l1_E"] = l1_errors(cfg, ref["cons"], run["cons"])
+
+    def rate(run):
+        return run["updates"] / (run["ms"] * 1e-3)
+
+    if not args.no_fp32 and want("fp32_flux"):
         r32 = run_form(T, torch, cfg, T.FP32_FLUX, args.steps, args.warmup, args.scatter)
-        v32 = r32["updates"] / (r32["ms"] * 1e-3)
-        e_rho, e_E = l1_errors(cfg, r64["cons"], r32["cons"])
-        _, roof32 = roofline(r32["prof"], bpi["fp32"], "fp32")
-        out["forms"] = {"fp32_flux": {
-            "value": round(v32, 1), "ms_per_step": round(r32["ms"] / args.steps, 4),
-            "speedup_vs_fp64": round(v32 / value, 3), "l1_rho": e_rho, "l1_E": e_E,
-            "l1_reference": "FP64 GPU result of the same run (equal to the oracle within 1e-12)",
-            "roofline": roof32}}
-        log(f"fp32 flux: {v32 / 1e9:.3f} G/s, L1 rho {e_rho:.2e}, L1 E {e_E:.2e}")
-        if not args.no_learned and args.scatter == 1:
-            log("learned guess: logging seeds 1-5, training, gate choice ...")
-            g = train_guess(T, torch, I, args.n)
-            rl = run_form(T, torch, cfg, T.FP32_FLUX, args.steps, args.warmup, args.scatter, mlp=g)
-            # the Newton counts on the faces where two-rarefaction is inexact
-            # come from a run with statistics (they cost a little time)
-            rs = run_form(T, torch, cfg, T.FP32_FLUX, 1, 0, args.scatter, mlp=g, stats=1)
-            vl = rl["updates"] / (rl["ms"] * 1e-3)
-            el = l1_errors(cfg, r64["cons"], rl["cons"])
-            out["forms"]["fp32_learned"] = {
-                "value": round(vl, 1), "ms_per_step": round(rl["ms"] / args.steps, 4),
-                "speedup_vs_fp64": round(vl / value, 3), "l1_rho": el[0], "l1_E": el[1],
-                "gate": g["gate"], "train_rows": g["rows"], "train_seconds": g["train_s"],
-                "train_loss_first_last": [g["loss_first"], g["loss_last"]],
-                "newton_per_inexact_tr_face_by_gate": g["newton_per_inexact_face"],
-                "strength_pregate": round(g["strength"], 5), "train_rows_tr_off_2pct": g["rows_useful"],
-                "eval_newton_per_inexact_face": round(rs["gated_newton"] / max(rs["gated"], 1), 4),
-                "eval_faces_network_evaluated_per_step": rs["evaluated"],
-                "eval_faces_started_by_network_per_step": rs["used"],
-                "newton_per_face_all": round(rs["newton"] / max(rs["faces"], 1), 4)}
-            log(f"fp32 + learned: {vl / 1e9:.3f} G/s, gate {g['gate']}, "
-                f"per-gate updates {g['newton_per_inexact_face']}")
+        v32 = rate(r32)
+        e = {"value": round(v32, 1), "ms_per_step": round(r32["ms"] / args.steps, 4)}
+        if r64 is not None:
+            e["speedup_vs_fp64"] = round(v32 / out["value"], 3)
+            e["l1_reference"] = "FP64 GPU result of the same run (equal to the oracle within 1e-12)"
+        l1_vs_fp64(e, r32)
+        forms["fp32_flux"] = with_roofline(e, r32, bpi["fp32"], "fp32", copy_gbs)
+        log(f"fp32 flux: {v32 / 1e9:.3f} G/s, L1 rho {e.get('l1_rho', float('nan')):.2e}, "
+            f"L1 E {e.get('l1_E', float('nan')):.2e}")
+    g = None
+    need_net = want("fp32_learned") or (want("batched") and not args.no_batch)
+    if not args.no_fp32 and not args.no_learned and args.scatter == 1 and need_net:
+        log("learned guess: logging seeds 1-5, training, gate choice ...")
+        g = train_guess(T, torch, I, args.n)
+    if g is not None and want("fp32_learned"):
+        rl = run_form(T, torch, cfg, T.FP32_FLUX, args.steps, args.warmup, args.scatter, mlp=g)
+        # the Newton counts on the faces where two-rarefaction is inexact
+        # come from a run with statistics (they cost a little time)
+        rs = run_form(T, torch, cfg, T.FP32_FLUX, 1, 0, args.scatter, mlp=g, stats=1)
+        vl = rate(rl)
+        e = {"value": round(vl, 1), "ms_per_step": round(rl["ms"] / args.steps, 4)}
+        if r64 is not None:
+            e["speedup_vs_fp64"] = round(vl / out["value"], 3)
+        if "fp32_flux" in forms:
+            e["speedup_vs_fp32_flux"] = round(vl / forms["fp32_flux"]["value"], 4)
+        l1_vs_fp64(e, rl)
+        e.update({
+            "gate": g["gate"], "train_rows": g["rows"], "train_seconds": g["train_s"],
+            "train_loss_first_last": [g["loss_first"], g["loss_last"]],
+            "newton_per_inexact_tr_face_by_gate": g["newton_per_inexact_face"],
+            "strength_pregate": round(g["strength"], 5), "train_rows_tr_off_2pct": g["rows_useful"],
+            "eval_newton_per_inexact_face": round(rs["gated_newton"] / max(rs["gated"], 1), 4),
+            "eval_faces_network_evaluated_per_step": rs["evaluated"],
+            "eval_faces_started_by_network_per_step": rs["used"],
+            "newton_per_face_all": round(rs["newton"] / max(rs["faces"], 1), 4)})
+        forms["fp32_learned"] = with_roofline(e, rl, BYTES_PER_ITEM_FORM["fp32_learned"],
+                                              "fp32_learned", copy_gbs)
+        log(f"fp32 + learned: {vl / 1e9:.3f} G/s, gate {g['gate']}, "
+            f"per-gate updates {g['newton_per_inexact_face']}")
     if not args.no_time2 and args.scatter == 1:
-        forms = out.setdefault("forms", {})
-        for prec, name in ((T.FP64, "fp64"), (T.FP32_FLUX, "fp32_flux")):
+        rt64 = None
+        for prec, name, tag in ((T.FP64, "fp64", "time2_fp64"),
+                                (T.FP32_FLUX, "fp32_flux", "time2_fp32")):
             if prec == T.FP32_FLUX and args.no_fp32:
                 continue
+            if not want(f"time_order_2_{name}"):
+                continue
             rt = run_form(T, torch, cfg, prec, args.steps, args.warmup, args.scatter, time_order=2)
-            vt = rt["updates"] / (rt["ms"] * 1e-3)
-            entry = {"value": round(vt, 1), "ms_per_step": round(rt["ms"] / args.steps, 4),
-                     "cost_vs_time_order_1": round(rt["ms"] / r64["ms"], 3),
-                     "cell_updates_per_step": rt["updates"] // args.steps,
-                     "face_solves_per_step": rt["faces"] // args.steps,
-                     "kernels_ms": {k: round(v["ms"], 3) for k, v in rt["prof"].items()}}
+            vt = rate(rt)
+            e = {"value": round(vt, 1), "ms_per_step": round(rt["ms"] / args.steps, 4),
+                 "cell_updates_per_step": rt["updates"] // args.steps,
+                 "face_solves_per_step": rt["faces"] // args.steps}
+            if r64 is not None:
+                e["cost_vs_time_order_1"] = round(rt["ms"] / r64["ms"], 3)
             if prec == T.FP64:
                 rt64 = rt
-            else:
-                entry["l1_rho"], entry["l1_E"] = l1_errors(cfg, rt64["cons"], rt["cons"])
-            forms[f"time_order_2_{name}"] = entry
+            elif rt64 is not None:
+                l1_vs_fp64(e, rt, rt64)
+            forms[f"time_order_2_{name}"] = with_roofline(e, rt, BYTES_PER_ITEM_FORM[tag], tag,
+                                                          copy_gbs)
             log(f"time order 2, {name}: {vt / 1e9:.3f} G cell-updates/s, "
                 f"{rt['ms'] / args.steps:.2f} ms per step")
-    if not args.no_moving and args.scatter == 1:
-        forms = out.setdefault("forms", {})
+    if not args.no_moving and args.scatter == 1 and want("moving_mesh_fp64"):
         vel = I.motion_field(cfg["nodes"], 0.05, seed=0)
         rm = run_form(T, torch, cfg, T.FP64, args.steps, args.warmup, args.scatter, motion=vel)
-        vm = rm["updates"] / (rm["ms"] * 1e-3)
-        forms["moving_mesh_fp64"] = {
-            "value": round(vm, 1), "ms_per_step": round(rm["ms"] / args.steps, 4),
-            "cost_vs_fixed_mesh": round(rm["ms"] / r64["ms"], 3),
-            "motion": "inputs.motion_field(nodes, 0.05, seed=0): node velocities, faces move "
-                      "with their nodes, volumes by the geometric conservation law",
-            "cell_updates_per_step": rm["updates"] // args.steps,
-            "kernels_ms": {k: round(v["ms"], 3) for k, v in rm["prof"].items()}}
+        vm = rate(rm)
+        e = {"value": round(vm, 1), "ms_per_step": round(rm["ms"] / args.steps, 4),
+             "motion": "inputs.motion_field(nodes, 0.05, seed=0): node velocities, faces move "
+                       "with their nodes, volumes by the geometric conservation law",
+             "cell_updates_per_step": rm["updates"] // args.steps}
+        if r64 is not None:
+            e["cost_vs_fixed_mesh"] = round(rm["ms"] / r64["ms"], 3)
+        forms["moving_mesh_fp64"] = with_roofline(e, rm, BYTES_PER_ITEM_FORM["moving_fp64"],
+                                                  "moving_fp64", copy_gbs)
         log(f"moving mesh, fp64: {vm / 1e9:.3f} G cell-updates/s, "
             f"{rm['ms'] / args.steps:.2f} ms per step")
-    if not args.no_batch and not args.no_fp32 and not args.no_learned and args.scatter == 1:
+    if (not args.no_batch and not args.no_fp32 and not args.no_learned and args.scatter == 1
+            and g is not None and want("batched")):
         cases = I.config_batch(128)
         ncell = sum(len(c["tets"]) for c in cases)
         log(f"batched form: {len(cases)} meshes, {ncell} cells, {BATCH_UNITS} units ...")
@@ -507,7 +626,7 @@ def main():
         bl = run_batch(T, torch, cases, args.steps, args.warmup, T.FP32_FLUX, mlp=g)
         v64 = b64["cell_updates"] / (b64["ms"] * 1e-3)
         vl = bl["cell_updates"] / (bl["ms"] * 1e-3)
-        out["forms"]["batched"] = {
+        forms["batched"] = {
             "workload": f"{len(cases)} graded tet meshes (5k-400k cells log-uniform, grading "
                         f"2-32, level cap 1-6, blast per mesh from seeds 1000-1127), "
                         f"{ncell} cells, {BATCH_UNITS} dt_min units per step",
@@ -524,12 +643,36 @@ def main():
                      "launch": b64["info"], "setup_s": round(b64["setup_s"], 1)},
         }
         log(f"batched: fp64 {v64 / 1e9:.3f} G/s, fp32 + learned {vl / 1e9:.3f} G/s")
+        # the same workload advanced task-wise: a context per mesh on 8
+        # streams, 8 host workers (tafv_advance_group)
+        grp = {}
+        for name, prec, net, ref in (("fp64", T.FP64, None, b64), ("fp32_learned", T.FP32_FLUX, g, bl)):
+            rg = run_group(T, torch, cases, args.steps, args.warmup, prec, mlp=net)
+            vg = rg["cell_updates"] / (rg["ms"] * 1e-3)
+            vb = ref["cell_updates"] / (ref["ms"] * 1e-3)
+            grp[name] = {"value": round(vg, 1), "ms_per_step": round(rg["ms"] / args.steps, 4),
+                         "cell_updates_per_step": rg["cell_updates"] // args.steps,
+                         "vs_batched": round(vg / vb, 4),
+                         "max_abs_diff_vs_batched": float(max(np.abs(a - b).max() for a, b in
+                                                              zip(rg["cons"], ref["cons"]))),
+                         "setup_s": round(rg["setup_s"], 1)}
+            log(f"task group {name}: {vg / 1e9:.3f} G/s ({vg / vb:.3f} of the batched form)")
+        forms["batched"]["task_group"] = {
+            "how": "one single-mesh context per mesh on 8 streams, advanced together by "
+                   "tafv_advance_group with 8 host workers (host clock, device synchronised)",
+            **grp}
+    if args.only:
+        entry = out if args.only == "fp64" else forms.get(args.only, {})
+        print(json.dumps({"form": args.only, **entry}), flush=True)
+        return
+    if forms:
+        out["forms"] = forms
     if not args.no_cpu_baseline:
         log("cpu baseline: oracle, 1 thread ...")
         out["cpu_baseline"] = cpu_baseline(cfg)
         log(f"cpu baseline: {out['cpu_baseline']['value']:.0f} cell-updates/s")
         log("cpu baseline: oracle, OpenMP build on the host threads ...")
-        out["cpu_baseline_all_cores"] = cpu_baseline(cfg, UNITS, "omp")
+        out["cpu_baseline_all_cores"] = cpu_baseline(cfg, UNITS, "omp", repeats=6)
         cb = out["cpu_baseline_all_cores"]
         log(f"cpu baseline, {cb['cores']} threads: {cb['value']:.0f} cell-updates/s")
     print(json.dumps(out), flush=True)

@@ -295,6 +295,28 @@ tafv_status tafv_state_reset(tafv_ctx* ctx, int32_t mesh_id);
  * non-finite (the call stops at that iteration boundary). */
 tafv_status tafv_advance(tafv_ctx* ctx, int64_t n_dt_min, tafv_stats* out);
 
+/* Advance several contexts together, each by n_dt_min subiterations: the
+ * same bits as calling tafv_advance() on each in turn, with the work of all
+ * of them in flight at once.  This is the task-based execution of Sec. 3
+ * and 4 of the paper on one GPU, with a context (its meshes) as the
+ * subdomain: `workers` host threads (at most n) each drive contexts w,
+ * w + workers, ..., enqueueing one subiteration of each in turn on the
+ * context's own stream, so that a context never waits for the others at a
+ * subiteration boundary, a quiet context runs ahead of a busy one, and the
+ * GPU keeps queued work from other contexts while one waits for the
+ * readback of its iteration start.  Contexts must be distinct, not batched
+ * (params.batch = 0) and ready to advance; give them different streams for
+ * their kernels to overlap on the GPU (contexts on one stream are
+ * serialised there).  No other call may use these contexts meanwhile.
+ * out (nullable) receives the counters summed over the contexts (cell
+ * updates, face solves and subiterations of this call; the device counters
+ * since each state_init), the largest theta, and the schedule state of the
+ * last context.  On an error the call stops at a subiteration boundary and
+ * returns the first failing context's status (its tafv_last_error() has the
+ * message; TAFV_E_ARG for the arguments themselves: tafv_last_error(NULL)). */
+tafv_status tafv_advance_group(tafv_ctx* const* ctxs, int32_t n, int64_t n_dt_min,
+                               int32_t workers, tafv_stats* out);
+
 /* Cumulative counters and schedule state of one mesh since state_init.  In
  * the batched form the face-solve counters (Newton updates, fallbacks,
  * vacuum faces, guess counters, wall impulse) are kept for the whole batch

@@ -5,9 +5,12 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <atomic>
 #include <mutex>
 #include <new>
+#include <set>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "kernels.h"
@@ -61,6 +64,8 @@ float* scratch_ptr(int device) {
   return (device >= 0 && device < kScrMaxDevices) ? g_scr_ptr[device] : nullptr;
 }
 
+// per-kernel timing classes; "flux_corrector" is the corrector pass of the
+// predictor/corrector form (it also reads the predictor flux)
 const char* kProfNames[] = {"classify", "grad",    "flux",          "update",
                             "gather",   "predict", "flux_corrector"};
 
@@ -94,10 +99,10 @@ void free_mesh(tafv_ctx* c, DevMesh* m) {
                   m->vol, m->grc32, m->U, m->U0, m->R, m->lev, m->lev2, m->dt, m->Wf,
                   m->pf.list, m->pf.counts, m->pf.start, m->pc.list, m->pc.counts,
                   m->pc.start, m->dscal, m->dcount, m->dimpulse, m->pf.offs, m->pc.offs,
-                  m->pf.scan_tmp, m->pc.scan_tmp, m->Q, m->frec, m->fkey, m->ckey, m->fpack,
+                  m->pf.tot, m->pc.tot, m->Q, m->frec, m->fkey, m->ckey, m->fpack,
                   m->perm, m->xfer, m->chist, m->rb, m->dmin, m->Q0, m->D, m->Ut,
                   m->vol0, m->fnode, m->sF, m->Rv, m->sweepf, m->lkey, m->pg.list,
-                  m->pg.counts, m->pg.start, m->pg.offs, m->pg.scan_tmp};
+                  m->pg.counts, m->pg.start, m->pg.offs, m->pg.tot};
   for (void* p : ptrs) dev_free(c, p);
   delete m;
 }
@@ -170,22 +175,30 @@ int early_order(const tafv_ctx* c, const DevMesh& m) {
   return (m.scatter == TAFV_SCATTER_GATHER && c->prm.time_order == 1) ? c->prm.order : 0;
 }
 
-tafv_status classify(tafv_ctx* c, DevMesh& m) {
+// Enqueues the classification at an iteration start (time steps, levels,
+// sweeps, keys, lists) and the copy of its results to the pinned host
+// buffer; c->rb_event marks the copy's end.
+tafv_status classify_enqueue(tafv_ctx* c, DevMesh& m) {
   StepArgs a = step_args(c, m);
   {
     ProfScope ps(c, P_CLASSIFY, m.nc);
-    HIP_TRY(c, launch_fill_u64(c->stream, m.dscal, 0x7ff0000000000000ull, 1));  // +inf
     HIP_TRY(c, launch_dt(c->stream, m, a));
     HIP_TRY(c, launch_classify(c->stream, m, a));
     HIP_TRY(c, launch_partitions(c->stream, m, early_order(c, m)));
   }
-  // read back: dt_min, flag, list starts
-  int K = m.scatter == TAFV_SCATTER_COLOUR ? m.ncolours * kMaxLevels : kMaxLevels;
-  int32_t* h = c->hpin;
-  HIP_TRY(c, launch_pack_readback(c->stream, m, K));
-  HIP_TRY(c, hipMemcpyAsync(h, m.rb, kReadbackInts * sizeof(int32_t), hipMemcpyDeviceToHost,
-                            c->stream));
-  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  // dt_min, flag, list starts, histogram (packed by the partitions)
+  HIP_TRY(c, hipMemcpyAsync(c->hpin, m.rb, kReadbackInts * sizeof(int32_t),
+                            hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(c, hipEventRecord(c->rb_event, c->stream));
+  return TAFV_OK;
+}
+
+// Waits for the readback of classify_enqueue and takes over dt_min, theta,
+// the list starts and the level histogram.
+tafv_status classify_finish(tafv_ctx* c, DevMesh& m) {
+  HIP_TRY(c, hipEventSynchronize(c->rb_event));
+  const int K = m.scatter == TAFV_SCATTER_COLOUR ? m.ncolours * kMaxLevels : kMaxLevels;
+  const int32_t* h = c->hpin;
   unsigned long long bits[3];
   std::memcpy(bits, h, sizeof(bits));
   if (bits[2]) return fail(c, TAFV_E_NUMERIC, "non-finite or non-physical cell state");
@@ -202,6 +215,11 @@ tafv_status classify(tafv_ctx* c, DevMesh& m) {
   m.theta = theta;
   m.classified = true;
   return TAFV_OK;
+}
+
+tafv_status classify(tafv_ctx* c, DevMesh& m) {
+  tafv_status st = classify_enqueue(c, m);
+  return st != TAFV_OK ? st : classify_finish(c, m);
 }
 
 // cells with an active face when levels <= g start a step (tau_g <= g):
@@ -281,7 +299,7 @@ tafv_status subiteration2(tafv_ctx* c, DevMesh& m, const StepArgs& a, int tau_s,
     HIP_TRY(c, launch_grad(c->stream, m, a, r, upd, m.Ut));
   }
   {
-    ProfScope ps(c, P_FLUX, ccnt);
+    ProfScope ps(c, P_FLUX_CORR, ccnt);
     HIP_TRY(c, launch_flux(c->stream, m, a, 0, ccnt, flux_features(c, m), m.Ut, m.Q, 2, m.Q0));
   }
   {
@@ -293,9 +311,63 @@ tafv_status subiteration2(tafv_ctx* c, DevMesh& m, const StepArgs& a, int tau_s,
   return TAFV_OK;
 }
 
+// Host bookkeeping at the end of subiteration s (counters, phase, time).
+void end_subiteration(DevMesh& m, tafv_stats* acc, int64_t s, int64_t ucnt, int64_t faces) {
+  m.phase = (int32_t)(s % ((int64_t)1 << m.theta));
+  m.t += m.dt_min;
+  m.st.subiterations++;
+  m.st.cell_updates += ucnt;
+  m.st.face_solves += faces;
+  if (acc) {
+    acc->subiterations++;
+    acc->cell_updates += ucnt;
+    acc->face_solves += faces;
+  }
+}
+
+// Gather mode with one face pass per level step on a fixed mesh: the first
+// subiteration of an iteration runs at tau_s = theta, so every face and
+// every cell take part, and cells of level 0 end their step.  Its launches
+// need neither theta nor the list starts (they cover the whole lists, with
+// the levels compared against the largest one), and its kernels read dt_min
+// on the device; so they are enqueued behind the classification before the
+// host waits for its readback, and the GPU computes while the host reads.
+bool first_subiteration_ahead(const tafv_ctx* c, const DevMesh& m) {
+  return m.scatter == TAFV_SCATTER_GATHER && c->prm.time_order == 1 && !m.moving;
+}
+
+tafv_status first_subiteration(tafv_ctx* c, DevMesh& m, tafv_stats* acc) {
+  StepArgs a = step_args(c, m);
+  const int all = kMaxLevels - 1;  // at least theta
+  if (c->prm.order == 2) {
+    CellRange r;
+    r.n1 = m.nc;
+    ProfScope ps(c, P_GRAD, m.nc);
+    HIP_TRY(c, launch_grad(c->stream, m, a, r, all));
+  }
+  {
+    ProfScope ps(c, P_FLUX, m.nf);
+    HIP_TRY(c, launch_flux(c->stream, m, a, 0, m.nf, flux_features(c, m), nullptr, nullptr, 0,
+                           nullptr, true));
+  }
+  {
+    ListRanges r;
+    r.add(0, m.nc);
+    ProfScope ps(c, P_GATHER, m.nc);
+    HIP_TRY(c, launch_cell_gather(c->stream, m, r, all, 0, 0.0, c->prm.precision, true));
+  }
+  tafv_status st = classify_finish(c, m);
+  if (st != TAFV_OK) return st;
+  end_subiteration(m, acc, 1, cells_upto_tau(m, 0), m.nf);
+  return TAFV_OK;
+}
+
 tafv_status subiteration(tafv_ctx* c, DevMesh& m, tafv_stats* acc) {
   if (m.phase == 0 && (c->prm.reclassify || !m.classified)) {
-    tafv_status st = classify(c, m);
+    tafv_status st = classify_enqueue(c, m);
+    if (st != TAFV_OK) return st;
+    if (first_subiteration_ahead(c, m)) return first_subiteration(c, m, acc);
+    st = classify_finish(c, m);
     if (st != TAFV_OK) return st;
   }
   StepArgs a = step_args(c, m);
@@ -342,16 +414,7 @@ tafv_status subiteration(tafv_ctx* c, DevMesh& m, tafv_stats* acc) {
     ProfScope ps(c, P_GATHER, r.count());
     HIP_TRY(c, launch_cell_gather(c->stream, m, r, tau_s, upd, m.dt_min, c->prm.precision));
   }
-  m.phase = (int32_t)(s % ((int64_t)1 << m.theta));
-  m.t += m.dt_min;
-  m.st.subiterations++;
-  m.st.cell_updates += ucnt;
-  m.st.face_solves += faces;
-  if (acc) {
-    acc->subiterations++;
-    acc->cell_updates += ucnt;
-    acc->face_solves += faces;
-  }
+  end_subiteration(m, acc, s, ucnt, faces);
   return TAFV_OK;
 }
 
@@ -494,8 +557,7 @@ tafv_status upload_host_mesh(tafv_ctx* c, const HostMesh& hm, DevMesh** out) {
   if (c->prm.order == 2) chk(dev_malloc(c, &m->Wf, wfbytes));
   for (Partition* p : {&m->pf, &m->pc}) {  // the gather's list is scanned with the tau_g list
     int64_t n = (p == &m->pf) ? (int64_t)nf : (int64_t)nc;
-    p->scan_bytes = partition_scan_bytes(n);
-    chk(dev_malloc(c, &p->scan_tmp, std::max<size_t>(p->scan_bytes, 16)));
+    chk(dalloc(c, &p->tot, kMaxKeys));
     chk(dalloc(c, &p->offs, (size_t)kMaxKeys * partition_blocks(n)));
     chk(dalloc(c, &p->list, n));
     chk(dalloc(c, &p->counts, (size_t)kMaxKeys * partition_blocks(n)));
@@ -545,6 +607,10 @@ tafv_status upload_host_mesh(tafv_ctx* c, const HostMesh& hm, DevMesh** out) {
   chk(up(m->fnode, hm.fnode));
   m->n_nodes = hm.n_nodes;
   chk(up(m->perm, hm.perm));
+  // the time-step minimum slots start at +inf (each classification sets
+  // them back once it has read them)
+  chk(launch_fill_u64(c->stream, m->dmin, 0x7ff0000000000000ull, kCounterWords));
+  chk(hipStreamSynchronize(c->stream));
   if (e != hipSuccess) {
     free_mesh(c, m);
     return hip_fail(c, e, "mesh upload");
@@ -625,10 +691,17 @@ tafv_status tafv_create(int device, const tafv_params* params, void* hip_stream,
     delete c;
     return hip_fail(nullptr, e, "hipHostMalloc");
   }
+  e = hipEventCreateWithFlags(&c->rb_event, hipEventDisableTiming);
+  if (e != hipSuccess) {
+    (void)hipHostFree(c->hpin);
+    delete c;
+    return hip_fail(nullptr, e, "hipEventCreateWithFlags");
+  }
   for (int k = 0; k < P_N; ++k) c->prof.push_back(ProfileClass{kProfNames[k]});
   if (p.batch) {
     c->batch = new (std::nothrow) Batch();
     if (!c->batch) {
+      (void)hipEventDestroy(c->rb_event);
       (void)hipHostFree(c->hpin);
       delete c;
       return fail(nullptr, TAFV_E_OOM, "host allocation failed");
@@ -649,6 +722,7 @@ tafv_status tafv_destroy(tafv_ctx* c) {
     (void)hipEventDestroy(pe.b);
   }
   for (hipEvent_t e : c->event_pool) (void)hipEventDestroy(e);
+  if (c->rb_event) (void)hipEventDestroy(c->rb_event);
   void* bufs[] = {c->mlp_th, c->mlp_m, c->mlp_v, c->mlp_grad, c->mlp_gpart, c->mlp_lpart,
                   c->mlp_loss, c->mlp_w, c->log_rows, c->log_count};
   for (void* b : bufs) dev_free(c, b);
@@ -810,15 +884,33 @@ tafv_status tafv_state_reset(tafv_ctx* c, int32_t mesh_id) {
   return TAFV_OK;
 }
 
-tafv_status tafv_advance(tafv_ctx* c, int64_t n, tafv_stats* out) {
-  if (!c) return TAFV_E_ARG;
-  if (n < 0) return fail(c, TAFV_E_ARG, "negative subiteration count");
-  if (c->batch) return batch_advance(c, n, out);
+}  // extern "C"
+
+namespace {
+
+tafv_status call_stats(tafv_ctx* c, tafv_stats acc, tafv_stats* out);
+
+// a single-mesh-path context that can advance
+tafv_status advance_ready(tafv_ctx* c) {
+  if (c->batch) return fail(c, TAFV_E_ARG, "a batched context advances on its own");
   if (c->meshes.empty()) return fail(c, TAFV_E_ORDER, "no mesh uploaded");
   for (DevMesh* m : c->meshes)
     if (!m->has_state) return fail(c, TAFV_E_ORDER, "advance before state_init");
   if (c->prm.guess == TAFV_GUESS_MLP && !c->mlp_ready)
     return fail(c, TAFV_E_MLP, "learned guess selected but no network set");
+  return TAFV_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+tafv_status tafv_advance(tafv_ctx* c, int64_t n, tafv_stats* out) {
+  if (!c) return TAFV_E_ARG;
+  if (n < 0) return fail(c, TAFV_E_ARG, "negative subiteration count");
+  if (c->batch) return batch_advance(c, n, out);
+  tafv_status rdy = advance_ready(c);
+  if (rdy != TAFV_OK) return rdy;
   HIP_TRY(c, hipSetDevice(c->device));
   tafv_stats acc{};
   for (int64_t k = 0; k < n; ++k) {
@@ -827,11 +919,98 @@ tafv_status tafv_advance(tafv_ctx* c, int64_t n, tafv_stats* out) {
       if (st != TAFV_OK) return st;
     }
   }
-  if (out) {
-    for (DevMesh* m : c->meshes) {
-      tafv_status st = read_counters(c, *m);
-      if (st != TAFV_OK) return st;
-    }
+  return out ? call_stats(c, acc, out) : TAFV_OK;
+}
+
+tafv_status tafv_advance_group(tafv_ctx* const* ctxs, int32_t n, int64_t n_dt_min,
+                               int32_t workers, tafv_stats* out) {
+  if (!ctxs || n < 1 || n_dt_min < 0 || workers < 1)
+    return fail(nullptr, TAFV_E_ARG, "invalid group arguments");
+  std::set<const tafv_ctx*> seen;
+  for (int32_t i = 0; i < n; ++i) {
+    tafv_ctx* c = ctxs[i];
+    if (!c || !seen.insert(c).second)
+      return fail(nullptr, TAFV_E_ARG, "a group needs distinct non-NULL contexts");
+    tafv_status st = advance_ready(c);
+    if (st != TAFV_OK) return st;
+  }
+  workers = std::min(workers, n);
+  std::atomic<bool> stop{false};
+  std::vector<tafv_status> res(n, TAFV_OK);
+  std::vector<tafv_stats> acc(n, tafv_stats{});
+  // worker w drives contexts w, w + workers, ...: one subiteration of each
+  // in turn, so every context's stream keeps queued work while one of them
+  // waits for its iteration-start readback, and no context waits for the
+  // others at a subiteration boundary
+  auto work = [&](int w) {
+    for (int64_t k = 0; k < n_dt_min && !stop.load(std::memory_order_relaxed); ++k)
+      for (int32_t i = w; i < n; i += workers) {
+        tafv_ctx* c = ctxs[i];
+        hipError_t e = hipSetDevice(c->device);
+        tafv_status st = e == hipSuccess ? TAFV_OK : hip_fail(c, e, "hipSetDevice");
+        for (DevMesh* m : c->meshes)
+          if (st == TAFV_OK) st = subiteration(c, *m, &acc[i]);
+        if (st != TAFV_OK) {
+          res[i] = st;
+          stop.store(true);
+          return;
+        }
+      }
+  };
+  std::vector<std::thread> pool;
+  try {
+    for (int w = 1; w < workers; ++w) pool.emplace_back(work, w);
+  } catch (...) {  // fewer threads: the ones started and this one share the work
+    stop.store(true);
+  }
+  if (!stop.load()) work(0);
+  for (std::thread& t : pool) t.join();
+  if (pool.size() + 1 < (size_t)workers && std::all_of(res.begin(), res.end(), [](tafv_status x) {
+        return x == TAFV_OK;
+      }))
+    return fail(nullptr, TAFV_E_ARG, "could not start the worker threads");
+  for (int32_t i = 0; i < n; ++i)
+    if (res[i] != TAFV_OK) return res[i];
+  if (!out) return TAFV_OK;
+  tafv_stats tot{};
+  for (int32_t i = 0; i < n; ++i) {
+    tafv_stats one{};
+    tafv_status st = call_stats(ctxs[i], acc[i], &one);
+    if (st != TAFV_OK) return st;
+    tot.subiterations += one.subiterations;
+    tot.cell_updates += one.cell_updates;
+    tot.face_solves += one.face_solves;
+    tot.newton_updates += one.newton_updates;
+    tot.newton_fallbacks += one.newton_fallbacks;
+    tot.vacuum_faces += one.vacuum_faces;
+    tot.guess_faces += one.guess_faces;
+    tot.guess_newton_updates += one.guess_newton_updates;
+    tot.guess_rejected += one.guess_rejected;
+    tot.guess_used += one.guess_used;
+    tot.guess_evaluated += one.guess_evaluated;
+    for (int k = 0; k < 3; ++k) tot.wall_impulse[k] += one.wall_impulse[k];
+    for (int t = 0; t < kMaxLevels; ++t) tot.cells_per_level[t] += one.cells_per_level[t];
+    tot.theta = std::max(tot.theta, one.theta);
+    tot.phase = one.phase;
+    tot.dt_min = one.dt_min;
+    tot.t_reached = one.t_reached;
+  }
+  *out = tot;
+  return TAFV_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+// The counters of one tafv_advance call (acc) completed with the device
+// counters of the context's meshes and the schedule state of its last mesh.
+tafv_status call_stats(tafv_ctx* c, tafv_stats acc, tafv_stats* out) {
+  for (DevMesh* m : c->meshes) {
+    tafv_status st = read_counters(c, *m);
+    if (st != TAFV_OK) return st;
+  }
+  {
     DevMesh* last = c->meshes.back();
     acc.theta = last->theta;
     acc.phase = last->phase;
@@ -853,6 +1032,10 @@ tafv_status tafv_advance(tafv_ctx* c, int64_t n, tafv_stats* out) {
   }
   return TAFV_OK;
 }
+
+}  // namespace
+
+extern "C" {
 
 tafv_status tafv_mesh_stats(tafv_ctx* c, int32_t mesh_id, tafv_stats* out) {
   if (c && c->batch) return batch_mesh_stats(c, mesh_id, out);
@@ -943,6 +1126,12 @@ tafv_status tafv_checkpoint_write(tafv_ctx* c, int32_t mesh_id, const double* co
   HIP_TRY(c, hipStreamSynchronize(c->stream));
   HIP_TRY(c, hipMemcpyAsync(m->xfer, levels, m->nc, hipMemcpyHostToDevice, c->stream));
   HIP_TRY(c, launch_from_caller_i8(c->stream, *m, (const int8_t*)m->xfer, m->lev));
+  // the level histogram starts from zero; the kernels read dt_min on the device
+  HIP_TRY(c, launch_fill_u64(c->stream, (unsigned long long*)m->chist, 0ull,
+                             kCounterSlots * kMaxKeys / 2));
+  unsigned long long dbits;
+  std::memcpy(&dbits, &dt_min, sizeof(dbits));
+  HIP_TRY(c, launch_fill_u64(c->stream, m->dscal, dbits, 1));
   HIP_TRY(c, launch_partitions(c->stream, *m, early_order(c, *m)));
   int K = m->scatter == TAFV_SCATTER_COLOUR ? m->ncolours * kMaxLevels : kMaxLevels;
   HIP_TRY(c, hipMemcpyAsync(m->hstart_f, m->pf.start, (K + 1) * sizeof(int32_t),
@@ -951,7 +1140,6 @@ tafv_status tafv_checkpoint_write(tafv_ctx* c, int32_t mesh_id, const double* co
                             hipMemcpyDeviceToHost, c->stream));
   HIP_TRY(c, hipMemcpyAsync(m->hstart_g, m->pg.start, (kCellKeys + 1) * sizeof(int32_t),
                             hipMemcpyDeviceToHost, c->stream));
-  HIP_TRY(c, launch_pack_readback(c->stream, *m, K));
   HIP_TRY(c, hipMemcpyAsync(c->hpin, m->rb, kReadbackInts * sizeof(int32_t),
                             hipMemcpyDeviceToHost, c->stream));
   HIP_TRY(c, hipStreamSynchronize(c->stream));

@@ -70,11 +70,15 @@ struct FluxFeatures {
 // U: the cell states read at first order; Q: where gather mode stores the
 // face fluxes (defaults: the mesh's U and Q); pass_mode and Qpred: the
 // passes of the predictor/corrector form (see FluxArgs)
+// dt_min_on_device: the kernels read dt_min from the device scalars (its
+// bits in m.dscal[0]) instead of the host's value
 hipError_t launch_flux(hipStream_t s, DevMesh& m, const StepArgs& a, int first, int count,
                        const FluxFeatures& ft, const double* U = nullptr, void* Q = nullptr,
-                       int pass_mode = 0, const void* Qpred = nullptr);
+                       int pass_mode = 0, const void* Qpred = nullptr,
+                       bool dt_min_on_device = false);
 hipError_t launch_cell_gather(hipStream_t s, DevMesh& m, const ListRanges& r, int tau_s,
-                              int tau_upd, double dt_min, int precision);
+                              int tau_upd, double dt_min, int precision,
+                              bool dt_min_on_device = false);
 hipError_t launch_update(hipStream_t s, DevMesh& m, CellRange r, int tau_upd);
 // moving mesh: face volume rates sF from node velocities d_vel [n_nodes][3]
 hipError_t launch_face_speed(hipStream_t s, DevMesh& m, const double* d_vel);
@@ -89,7 +93,6 @@ hipError_t launch_predict(hipStream_t s, DevMesh& m, int tau_s, int sub, double 
                           int precision);
 hipError_t launch_cell_gather2(hipStream_t s, DevMesh& m, CellRange r, int tau_upd,
                                double dt_min, int precision);
-hipError_t launch_pack_readback(hipStream_t s, DevMesh& m, int Kf);
 constexpr int kCellKeys = 2 * kMaxLevels;  // keys of the gather's cell list
 // scalars 8, face starts kMaxKeys + 1, cell starts kMaxLevels + 1, gather-list
 // starts kCellKeys + 1, the (tau_g, tau) histogram kMaxKeys
@@ -110,6 +113,5 @@ hipError_t launch_fill_f64(hipStream_t s, double* p, double v, int64_t n);
 
 // partition scratch sizes
 int partition_blocks(int64_t n);
-size_t partition_scan_bytes(int64_t n);
 
 }  // namespace tafv

@@ -21,14 +21,14 @@
 // k_predict and k_cell_gather2, a moving mesh k_face_speed and
 // k_cell_gather_move.
 // At every iteration start (phase 0): k_dt (per-cell time step and its
-// minimum), k_classify (levels from the dt ratio), k_sweep_inplace (neighbour
-// levels at most one apart), the face and cell keys, and ballot-based stable
-// partitions (faces by (colour, tau_f); cells by tau_g and, in the same pass,
-// by the gather's key) so that the active set of any subiteration is a
+// minimum), k_classify_sweep (levels from the dt ratio and the first
+// neighbour sweep), k_sweep_inplace (neighbour levels at most one apart),
+// k_keys (face and cell keys, counted per block), k_cell_list_keys (the
+// gather's key), k_part_scan and k_part_scatter (ballot-based stable
+// partitions: faces by (colour, tau_f); cells by tau_g and, in the same pass,
+// by the gather's key), so that the active set of any subiteration is a
 // prefix, or a few ranges, of each list.
 #include <hip/hip_runtime.h>
-
-#include <hipcub/hipcub.hpp>
 
 #include "kernels.h"
 #include "kernels_dev.h"
@@ -102,23 +102,47 @@ __global__ __launch_bounds__(kBlock) void k_dt(int nc, int nf, const double* __r
   }
 }
 
-// dscal[0] <- the minimum over the slots (one wave)
-__global__ void k_min_slots(const unsigned long long* __restrict__ dmin,
-                            unsigned long long* dscal) {
+// dscal[0] <- the minimum over the slots (one wave), which are set back to
+// +inf for the next classification; the sweep flags and the level histogram
+// of this classification start at zero
+__global__ void k_min_slots(unsigned long long* __restrict__ dmin, unsigned long long* dscal,
+                            unsigned* __restrict__ sweepf, int* __restrict__ chist) {
   unsigned long long v = dmin[threadIdx.x * kSlotStride];
+  dmin[threadIdx.x * kSlotStride] = 0x7ff0000000000000ull;
   for (int off = 32; off > 0; off >>= 1) {
     unsigned long long o = __shfl_xor(v, off, 64);
     v = o < v ? o : v;
   }
   if (threadIdx.x == 0) dscal[0] = v;
+  if (threadIdx.x < kMaxLevels) sweepf[threadIdx.x] = 0u;
+  for (int k = threadIdx.x; k < kCountSlots * kMaxKeys; k += 64) chist[k] = 0;
 }
 
-__global__ void k_classify(int nc, const double* __restrict__ dt, const unsigned long long* dscal,
-                           double margin, int L, int8_t* __restrict__ lev) {
+// Levels from the time steps, with the first lowering sweep taken at once
+// (a Jacobi sweep: the neighbours' levels are classified from their own time
+// steps): tau_i <- min(tau_i, tau_j + 1); changed[0] marks a lowered level.
+__global__ __launch_bounds__(kBlock) void k_classify_sweep(int nc, const double* __restrict__ dt,
+                                                           const unsigned long long* dscal,
+                                                           double margin, int L,
+                                                           const int* __restrict__ nb,
+                                                           int8_t* __restrict__ lev,
+                                                           unsigned* changed) {
   int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= nc) return;
-  double dtmin = __longlong_as_double((long long)dscal[0]);
-  lev[i] = classify_item(dt[i], dtmin, margin, L);
+  bool low = false;
+  if (i < nc) {
+    const double dtmin = __longlong_as_double((long long)dscal[0]);
+    int n[4];
+    double dn[4];
+    for (int m = 0; m < 4; ++m) n[m] = nb[m * nc + i];
+    for (int m = 0; m < 4; ++m) dn[m] = dt[n[m] >= 0 ? n[m] : i];
+    const int t0 = classify_item(dt[i], dtmin, margin, L);
+    int t = t0;
+    for (int m = 0; m < 4; ++m)
+      if (n[m] >= 0) t = min(t, classify_item(dn[m], dtmin, margin, L) + 1);
+    lev[i] = (int8_t)t;
+    low = t < t0;
+  }
+  if (__ballot(low) != 0ull && (threadIdx.x & 63) == 0) changed[0] = 1u;
 }
 
 // One lowering sweep in place, tau_i <- min(tau_i, tau_j + 1): a neighbour
@@ -151,70 +175,127 @@ __global__ void k_sweep_inplace(int nc, const int* __restrict__ nb, int8_t* lev,
 // ---------------------------------------------------------------------------
 // stable partition of indices by a small key, with wavefront ballots
 
-__global__ void k_face_keys(int nf, const int* __restrict__ fhL, const int* __restrict__ fhR,
-                            const int8_t* __restrict__ fcol, const int8_t* __restrict__ lev,
-                            int use_colour, int8_t* __restrict__ fkey) {
-  int f = blockIdx.x * blockDim.x + threadIdx.x;
-  if (f >= nf) return;
-  fkey[f] = face_key_item(f, fhL, fhR, fcol, lev, use_colour);
-}
-
-// cell keys, packed face words, and the histogram hist[tau_g * 8 + tau]
-// (block-local in LDS, then one atomic per bin and block)
-// cells that apply their fluxes at their step's start (kEarlyBit; order 0
-// marks none) and the key of the gather's cell list: 2 tau for those cells,
-// 2 tau_g + 1 for the others
-__global__ __launch_bounds__(kBlock) void k_cell_list_keys(int nc, const int* __restrict__ nb,
-                                                           const int8_t* __restrict__ lev,
-                                                           const int8_t* __restrict__ ckey,
-                                                           uint32_t* __restrict__ fpack,
-                                                           int8_t* __restrict__ lkey, int order) {
-  int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= nc) return;
-  const bool e = cell_early_item(i, nc, nb, lev, ckey, fpack, order);
-  lkey[i] = (int8_t)(e ? 2 * lev[i] : 2 * ckey[i] + 1);
-}
-
-__global__ __launch_bounds__(kBlock) void k_cell_keys(int nc, const int* __restrict__ nb,
-                                                      const int8_t* __restrict__ lev,
-                                                      int8_t* __restrict__ ckey,
-                                                      uint32_t* __restrict__ fpack,
-                                                      int* __restrict__ hist) {
-  __shared__ int h[kMaxKeys];
-  for (int k = threadIdx.x; k < kMaxKeys; k += blockDim.x) h[k] = 0;
-  __syncthreads();
-  int i = blockIdx.x * blockDim.x + threadIdx.x;
-  int bin = i < nc ? cell_key_item(i, nc, nb, lev, ckey, fpack) : 0;
-  wave_hist_add(h, i < nc, bin);
-  __syncthreads();
-  int* hs = hist + (blockIdx.x % kCountSlots) * kMaxKeys;
-  for (int k = threadIdx.x; k < kMaxKeys; k += blockDim.x)
-    if (h[k]) atomicAdd(&hs[k], h[k]);
-}
-
-// one buffer for the host readback at an iteration start: [0..5] the
-// scalars (dt_min bits, theta slot, non-finite flag), [8..8+Kf] face list
-// starts, [8+65..] cell list starts, [8+65+9..] the (tau_g, tau) histogram
-__global__ void k_pack_readback(const unsigned long long* __restrict__ dscal,
-                                const int* __restrict__ fstart, int Kf,
-                                const int* __restrict__ cstart, const int* __restrict__ gstart,
-                                const int* __restrict__ hist, int* __restrict__ out) {
-  int t = threadIdx.x;
-  if (t < 6) out[t] = ((const int*)dscal)[t];
-  if (t <= Kf) out[kRbFace + t] = fstart[t];
-  if (t <= kMaxLevels) out[kRbCell + t] = cstart[t];
-  if (t <= kCellKeys) out[kRbGather + t] = gstart[t];
-  if (t < kMaxKeys) {
-    int sum = 0;
-    for (int sl = 0; sl < kCountSlots; ++sl) sum += hist[sl * kMaxKeys + t];
-    out[kRbHist + t] = sum;
+// adds one wave's keys (k_mine < 0: no item) to the block's counters (LDS
+// atomics: the waves of a block count into the same bins)
+__device__ inline void block_count_keys(int* cnt, bool valid, int k_mine) {
+  const int lane = threadIdx.x & 63;
+  unsigned long long pending = __ballot(valid);
+  while (pending) {
+    int leader = __ffsll(pending) - 1;
+    int k = __shfl(k_mine, leader, 64);
+    unsigned long long m = __ballot(valid && k_mine == k);
+    if (lane == leader) atomicAdd(&cnt[k], __popcll(m));
+    pending &= ~m;
   }
 }
 
-hipError_t launch_pack_readback(hipStream_t s, DevMesh& m, int Kf) {
-  hipLaunchKernelGGL(k_pack_readback, dim3(1), dim3(128), 0, s, m.dscal, m.pf.start, Kf,
-                     m.pc.start, m.pg.start, m.chist, m.rb);
-  return hipGetLastError();
+// Keys of one classification, one item per thread, with the partition
+// counts of each block of kPartChunk (= kBlock) items: blocks [0, nbf) take
+// the faces (tau_f, or (colour, tau_f)) into fcounts[key][block]; blocks
+// [nbf, nbf + nbc) the cells: tau_g and the packed face word, the
+// (tau_g, tau) histogram, and, unless the gather's list is built too
+// (count_cells = 0; k_cell_list_keys then counts both cell keys), the tau_g
+// counts into ccounts[key][block].
+__global__ __launch_bounds__(kBlock) void k_keys(int nf, int nbf, const int* __restrict__ fhL,
+                                                 const int* __restrict__ fhR,
+                                                 const int8_t* __restrict__ fcol, int use_colour,
+                                                 int Kf, int8_t* __restrict__ fkey,
+                                                 int* __restrict__ fcounts, int nc, int nbc,
+                                                 const int* __restrict__ nb,
+                                                 const int8_t* __restrict__ lev,
+                                                 int8_t* __restrict__ ckey,
+                                                 uint32_t* __restrict__ fpack,
+                                                 int* __restrict__ hist, int count_cells,
+                                                 int* __restrict__ ccounts) {
+  __shared__ int cnt[kMaxKeys];
+  __shared__ int h[kMaxKeys];
+  for (int k = threadIdx.x; k < kMaxKeys; k += blockDim.x) cnt[k] = h[k] = 0;
+  __syncthreads();
+  if ((int)blockIdx.x < nbf) {
+    const int f = blockIdx.x * kBlock + threadIdx.x;
+    const bool valid = f < nf;
+    int key = -1;
+    if (valid) {
+      key = face_key_item(f, fhL, fhR, fcol, lev, use_colour);
+      fkey[f] = (int8_t)key;
+    }
+    block_count_keys(cnt, valid, key);
+    __syncthreads();
+    for (int k = threadIdx.x; k < Kf; k += blockDim.x) fcounts[k * nbf + blockIdx.x] = cnt[k];
+    return;
+  }
+  const int b = blockIdx.x - nbf;
+  const int i = b * kBlock + threadIdx.x;
+  const bool valid = i < nc;
+  const int bin = valid ? cell_key_item(i, nc, nb, lev, ckey, fpack) : 0;
+  wave_hist_add(h, valid, bin);
+  if (count_cells) block_count_keys(cnt, valid, valid ? bin / kMaxLevels : -1);
+  __syncthreads();
+  int* hs = hist + (b % kCountSlots) * kMaxKeys;
+  for (int k = threadIdx.x; k < kMaxKeys; k += blockDim.x)
+    if (h[k]) atomicAdd(&hs[k], h[k]);
+  if (count_cells)
+    for (int k = threadIdx.x; k < kMaxLevels; k += blockDim.x) ccounts[k * nbc + b] = cnt[k];
+}
+
+// cells that apply their fluxes at their step's start (kEarlyBit; order 0
+// marks none) and the key of the gather's cell list: 2 tau for those cells,
+// 2 tau_g + 1 for the others; with the partition counts of both cell keys
+// per block, tau_g in ccounts[0..7][block], the gather's key in
+// ccounts[8..23][block]
+__global__ __launch_bounds__(kBlock) void k_cell_list_keys(int nc, int nbc,
+                                                           const int* __restrict__ nb,
+                                                           const int8_t* __restrict__ lev,
+                                                           const int8_t* __restrict__ ckey,
+                                                           uint32_t* __restrict__ fpack,
+                                                           int8_t* __restrict__ lkey, int order,
+                                                           int* __restrict__ ccounts) {
+  __shared__ int cnt[kMaxLevels + kCellKeys];
+  for (int k = threadIdx.x; k < kMaxLevels + kCellKeys; k += blockDim.x) cnt[k] = 0;
+  __syncthreads();
+  const int i = blockIdx.x * kBlock + threadIdx.x;
+  const bool valid = i < nc;
+  int k1 = -1, k2 = -1;
+  if (valid) {
+    const bool e = cell_early_item(i, nc, nb, lev, ckey, fpack, order);
+    k1 = ckey[i];
+    k2 = e ? 2 * lev[i] : 2 * k1 + 1;
+    lkey[i] = (int8_t)k2;
+  }
+  block_count_keys(cnt, valid, k1);
+  block_count_keys(cnt, valid, valid ? kMaxLevels + k2 : -1);
+  __syncthreads();
+  for (int k = threadIdx.x; k < kMaxLevels + kCellKeys; k += blockDim.x)
+    ccounts[k * nbc + blockIdx.x] = cnt[k];
+}
+
+// One buffer for the host readback at an iteration start: [0..5] the
+// scalars (dt_min bits, theta slot, non-finite flag), [8..8+Kf] face list
+// starts, [8+65..] cell list starts, [8+65+9..] the gather list's starts,
+// then the (tau_g, tau) histogram.  Written by one block after both lists
+// have their starts.
+struct Readback {
+  const unsigned long long* dscal;
+  const int* fstart;
+  int Kf;
+  const int* cstart;
+  const int* gstart;  // nullptr without the gather's list
+  const int* hist;
+  int* out;
+};
+
+__device__ inline void pack_readback(const Readback& r) {
+  for (int t = threadIdx.x; t <= kMaxKeys; t += blockDim.x) {
+    if (t < 6) r.out[t] = ((const int*)r.dscal)[t];
+    if (t <= r.Kf) r.out[kRbFace + t] = r.fstart[t];
+    if (t <= kMaxLevels) r.out[kRbCell + t] = r.cstart[t];
+    if (t <= kCellKeys) r.out[kRbGather + t] = r.gstart ? r.gstart[t] : 0;
+    if (t < kMaxKeys) {
+      int sum = 0;
+      for (int sl = 0; sl < kCountSlots; ++sl) sum += r.hist[sl * kMaxKeys + t];
+      r.out[kRbHist + t] = sum;
+    }
+  }
 }
 
 __global__ void k_fill_i32(int* p, int v, int n) {
@@ -222,25 +303,14 @@ __global__ void k_fill_i32(int* p, int v, int n) {
   if (i < n) p[i] = v;
 }
 
-// Stable partitions of an index range [0, n) by byte keys.  Blocks of
-// kPartChunk items count their keys into counts[key][block], one exclusive
-// scan turns the counts into slots, and the scatter writes each item at its
-// slot, so the items of one key keep their index order.  Two keys over the
-// same range (the two cell lists) share one pass: the second key's counts
-// follow the first's ([K1 + K2][nblocks]) and its slots therefore start at n.
-
-// adds one wave's keys (k_mine < 0: no item) to the block's counters
-__device__ inline void wave_count_keys(int* cnt, bool valid, int k_mine) {
-  const int lane = threadIdx.x & 63;
-  unsigned long long pending = __ballot(valid);
-  while (pending) {
-    int leader = __ffsll(pending) - 1;
-    int k = __shfl(k_mine, leader, 64);
-    unsigned long long m = __ballot(k_mine == k);
-    if (lane == leader) cnt[k] += __popcll(m);
-    pending &= ~m;
-  }
-}
+// Stable partitions of an index range [0, n) by byte keys.  The key kernels
+// count each block's (kPartChunk items) keys into counts[key][block];
+// k_part_scan turns every key's row of counts into offsets within the row
+// and a row total; the scatter adds the total of the keys before (so the
+// list holds the keys in order) and writes each item at its slot, so the
+// items of one key keep their index order.  Two keys over the same range (the
+// two cell lists) share one pass: the second key's counts follow the
+// first's ([K1 + K2][nblocks]) and its slots therefore start at n.
 
 // writes one wave's items at base[key] onwards in lane order; the writer is
 // given the slot less pofs and the key less kofs
@@ -263,37 +333,85 @@ __device__ inline void wave_scatter_keys(int* base, bool valid, int k_mine, int 
   }
 }
 
-template <typename Key>
-__global__ __launch_bounds__(64) void k_part_count(int n, Key key1, int K1, Key key2, int K2,
-                                                   int nblocks, int* __restrict__ counts) {
-  __shared__ int cnt[kMaxKeys];
-  const int lane = threadIdx.x, K = K1 + K2;
-  for (int k = lane; k < K; k += 64) cnt[k] = 0;
+// One block per key row (blocks [0, Kf) the face partition's rows, the rest
+// the cell partition's): the exclusive scan of the row's counts, each thread
+// summing a run of consecutive blocks, and the row total.
+constexpr int kScanThreads = 1024;
+__global__ __launch_bounds__(kScanThreads) void k_part_scan(int Kf, int nbf,
+                                                            const int* __restrict__ fcounts,
+                                                            int* __restrict__ foffs,
+                                                            int* __restrict__ ftot, int nbc,
+                                                            const int* __restrict__ ccounts,
+                                                            int* __restrict__ coffs,
+                                                            int* __restrict__ ctot) {
+  __shared__ int wsum[kScanThreads / 64];
+  const bool face = (int)blockIdx.x < Kf;
+  const int k = face ? blockIdx.x : blockIdx.x - Kf;
+  const int nb = face ? nbf : nbc;
+  const int* in = (face ? fcounts : ccounts) + (size_t)k * nb;
+  int* out = (face ? foffs : coffs) + (size_t)k * nb;
+  const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+  const int per = (nb + kScanThreads - 1) / kScanThreads;
+  const int b0 = min(t * per, nb), b1 = min(b0 + per, nb);
+  int sum = 0;
+  for (int b = b0; b < b1; ++b) sum += in[b];
+  // exclusive scan of the thread sums: within the wave, then over the waves
+  int inc = sum;
+  for (int off = 1; off < 64; off <<= 1) {
+    int y = __shfl_up(inc, off, 64);
+    if (lane >= off) inc += y;
+  }
+  if (lane == 63) wsum[w] = inc;
   __syncthreads();
-  const int first = blockIdx.x * kPartChunk;
-  for (int step = 0; step < kPartChunk / 64; ++step) {
-    const int i = first + step * 64 + lane;
-    const bool valid = i < n;
-    wave_count_keys(cnt, valid, valid ? key1(i) : -1);
-    if (K2 > 0) wave_count_keys(cnt, valid, valid ? K1 + key2(i) : -1);
+  if (w == 0) {
+    int x = lane < kScanThreads / 64 ? wsum[lane] : 0, xi = x;
+    for (int off = 1; off < 64; off <<= 1) {
+      int y = __shfl_up(xi, off, 64);
+      if (lane >= off) xi += y;
+    }
+    if (lane < kScanThreads / 64) wsum[lane] = xi - x;  // exclusive over the waves
+    if (lane == kScanThreads / 64 - 1) (face ? ftot : ctot)[k] = xi;
   }
   __syncthreads();
-  for (int k = lane; k < K; k += 64) counts[k * nblocks + blockIdx.x] = cnt[k];
+  int run = wsum[w] + inc - sum;
+  for (int b = b0; b < b1; ++b) {
+    const int c = in[b];
+    out[b] = run;
+    run += c;
+  }
+}
+
+// base[k] <- the first slot of key k: the row totals of the keys before it
+// (tot has K <= 64 entries; one wave)
+__device__ inline void key_starts(const int* __restrict__ tot, int K, int* start) {
+  const int lane = threadIdx.x;
+  if (lane >= 64) return;
+  int x = lane < K ? tot[lane] : 0, xi = x;
+  for (int off = 1; off < 64; off <<= 1) {
+    int y = __shfl_up(xi, off, 64);
+    if (lane >= off) xi += y;
+  }
+  if (lane < K) start[lane] = xi - x;
 }
 
 // Block 0 also writes each list's key starts (start[k] = first slot of key
-// k, start[K] = n), which the host reads back.
+// k, start[K] = n), which the host reads back, and, given rb.out, packs the
+// readback buffer.
 template <typename Key, typename W1, typename W2>
 __global__ __launch_bounds__(64) void k_part_scatter(int n, Key key1, int K1, W1 out1,
                                                      int* __restrict__ start1, Key key2, int K2,
                                                      W2 out2, int* __restrict__ start2,
-                                                     int nblocks, const int* __restrict__ offs) {
+                                                     int nblocks, const int* __restrict__ offs,
+                                                     const int* __restrict__ tot, Readback rb) {
+  __shared__ int ks[kMaxKeys];
   __shared__ int base[kMaxKeys];
   const int lane = threadIdx.x, K = K1 + K2;
-  for (int k = lane; k < K; k += 64) base[k] = offs[k * nblocks + blockIdx.x];
+  key_starts(tot, K, ks);
+  __syncthreads();
+  for (int k = lane; k < K; k += 64) base[k] = ks[k] + offs[k * nblocks + blockIdx.x];
   if (blockIdx.x == 0) {
-    for (int k = lane; k < K1; k += 64) start1[k] = offs[k * nblocks];
-    for (int k = lane; k < K2; k += 64) start2[k] = offs[(K1 + k) * nblocks] - n;
+    for (int k = lane; k < K1; k += 64) start1[k] = ks[k];
+    for (int k = lane; k < K2; k += 64) start2[k] = ks[K1 + k] - n;
     if (lane == 0) start1[K1] = n;
     if (lane == 0 && K2 > 0) start2[K2] = n;
   }
@@ -305,33 +423,11 @@ __global__ __launch_bounds__(64) void k_part_scatter(int n, Key key1, int K1, W1
     wave_scatter_keys(base, valid, valid ? key1(i) : -1, i, 0, 0, out1);
     if (K2 > 0) wave_scatter_keys(base, valid, valid ? K1 + key2(i) : -1, i, K1, n, out2);
   }
-}
-
-size_t partition_scan_bytes(int64_t n) {
-  int nb = partition_blocks(n);
-  size_t bytes = 0;
-  (void)hipcub::DeviceScan::ExclusiveSum(nullptr, bytes, (const int*)nullptr, (int*)nullptr,
-                                         kMaxKeys * nb);
-  return bytes;
-}
-
-// One key (K2 = 0) or two keys over the same range; the scan runs in p1's
-// scratch, whose counts hold kMaxKeys >= K1 + K2 keys per block.
-template <typename W1, typename W2 = IndexWriter>
-static hipError_t run_partition(hipStream_t s, int n, Partition& p1, ByteKey key1, int K1, W1 out1,
-                                Partition* p2 = nullptr, ByteKey key2 = {nullptr}, int K2 = 0,
-                                W2 out2 = {nullptr}) {
-  if (K1 + K2 > kMaxKeys || (K2 > 0 && !p2)) return hipErrorInvalidValue;
-  const int nb = partition_blocks(n);
-  hipLaunchKernelGGL(k_part_count<ByteKey>, dim3(nb), dim3(64), 0, s, n, key1, K1, key2, K2, nb,
-                     p1.counts);
-  size_t bytes = p1.scan_bytes;
-  hipError_t e =
-      hipcub::DeviceScan::ExclusiveSum(p1.scan_tmp, bytes, p1.counts, p1.offs, (K1 + K2) * nb, s);
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL((k_part_scatter<ByteKey, W1, W2>), dim3(nb), dim3(64), 0, s, n, key1, K1,
-                     out1, p1.start, key2, K2, out2, p2 ? p2->start : nullptr, nb, p1.offs);
-  return hipGetLastError();
+  if (blockIdx.x == 0 && rb.out) {
+    __threadfence_block();
+    __syncthreads();
+    pack_readback(rb);
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -413,7 +509,8 @@ __global__ __launch_bounds__(kBlock) void k_flux_store(FluxArgs<T> a) {
   SolveInfo info{0, 0, 0, 0, 0, 0, 0, 0};
   double i0 = 0, i1 = 0, i2 = 0;
   if (idx < a.count)
-    flux_store_item<ORDER, T, G14, MOVE>(a, nt_rec(a.rec + idx), a.s.dt_min, info, i0, i1, i2);
+    flux_store_item<ORDER, T, G14, MOVE>(a, nt_rec(a.rec + idx), flux_dt_min(a), info, i0, i1,
+                                         i2);
   flush_counters(info, i0, i1, i2, a.dcount, a.dimpulse);
 }
 
@@ -428,7 +525,7 @@ void k_flux_feat(FluxArgs<T> a) {
   SolveInfo info{0, 0, 0, 0, 0, 0, 0, 0};
   double i0 = 0, i1 = 0, i2 = 0;
   int4 r = valid ? nt_rec(a.rec + idx) : make_int4(0, 0, -1, 0);
-  flux_feat_item<ORDER, T, FEAT>(a, valid, r, a.s.dt_min, lds + (threadIdx.x >> 6) * kMlpFwdLds,
+  flux_feat_item<ORDER, T, FEAT>(a, valid, r, flux_dt_min(a), lds + (threadIdx.x >> 6) * kMlpFwdLds,
                                  info, i0, i1, i2);
   flush_counters(info, i0, i1, i2, a.dcount, a.dimpulse);
 }
@@ -442,9 +539,12 @@ __global__ __launch_bounds__(kBlock) void k_cell_gather(int count, const int* __
                                                         const double* __restrict__ vol,
                                                         double* __restrict__ U,
                                                         double* __restrict__ R, int tau_s,
-                                                        int tau_upd, unsigned long long* dscal) {
+                                                        int tau_upd, unsigned long long* dscal,
+                                                        int dt_min_on_device) {
   int idx = xcd_block() * kBlock + threadIdx.x;
   if (idx >= count) return;
+  // dt_min_on_device: a launch enqueued before the host read dt_min back
+  if (dt_min_on_device) dt_min = __longlong_as_double((long long)dscal[0]);
   if (!cell_gather_item<T>(range_cell(list, rg, idx), nc, fpack, c2f, Q, dt_min, vol, U, R,
                            tau_s, tau_upd))
     atomicOr(&dscal[2], 1ull);
@@ -584,47 +684,58 @@ hipError_t launch_fill_f64(hipStream_t s, double* p, double v, int64_t n) {
 }
 
 hipError_t launch_dt(hipStream_t s, DevMesh& m, const StepArgs& a) {
-  hipLaunchKernelGGL(k_fill_u64, dim3(blocks_for(kCounterWords)), dim3(kBlock), 0, s, m.dmin,
-                     0x7ff0000000000000ull, kCounterWords);  // +inf
   hipLaunchKernelGGL(k_dt, dim3(blocks_for(m.nc)), dim3(kBlock), 0, s, m.nc, m.nf, m.U, m.vol,
                      m.c2f, m.fA, a.gas.g, a.cfl, m.dt, m.dscal, m.dmin,
                      m.moving ? m.sF : nullptr);
-  hipLaunchKernelGGL(k_min_slots, dim3(1), dim3(64), 0, s, m.dmin, m.dscal);
+  hipLaunchKernelGGL(k_min_slots, dim3(1), dim3(64), 0, s, m.dmin, m.dscal, m.sweepf, m.chist);
   return hipGetLastError();
 }
 
 hipError_t launch_classify(hipStream_t s, DevMesh& m, const StepArgs& a) {
-  hipLaunchKernelGGL(k_classify, dim3(blocks_for(m.nc)), dim3(kBlock), 0, s, m.nc, m.dt,
-                     m.dscal, a.level_margin, m.max_levels, m.lev);
-  if (m.max_levels > 1)
-    hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(kMaxLevels), 0, s, (int*)m.sweepf, 0,
-                       kMaxLevels);
-  for (int k = 0; k < m.max_levels - 1; ++k)
+  hipLaunchKernelGGL(k_classify_sweep, dim3(blocks_for(m.nc)), dim3(kBlock), 0, s, m.nc, m.dt,
+                     m.dscal, a.level_margin, m.max_levels, m.nb_, m.lev, m.sweepf);
+  // the classification took the first of the L - 1 sweeps
+  for (int k = 1; k < m.max_levels - 1; ++k)
     hipLaunchKernelGGL(k_sweep_inplace, dim3(blocks_for(m.nc)), dim3(kBlock), 0, s, m.nc, m.nb_,
                        m.lev, m.sweepf, k);
   return hipGetLastError();
 }
 
+// Keys, counts, scans and scatters of the face list and the cell lists; the
+// cell scatter's first block then packs the host readback buffer m.rb.
 hipError_t launch_partitions(hipStream_t s, DevMesh& m, int early_order) {
   static_assert(kMaxLevels + kCellKeys <= kMaxKeys, "the two cell lists share one scan");
-  int use_colour = m.scatter == TAFV_SCATTER_COLOUR;
-  int Kf = use_colour ? m.ncolours * kMaxLevels : kMaxLevels;
-  hipLaunchKernelGGL(k_face_keys, dim3(blocks_for(m.nf)), dim3(kBlock), 0, s, m.nf, m.fhL, m.fhR,
-                     m.fcol, m.lev, use_colour, m.fkey);
-  hipLaunchKernelGGL(k_fill_i32, dim3(kCountSlots), dim3(kMaxKeys), 0, s, m.chist, 0,
-                     kCountSlots * kMaxKeys);
-  hipLaunchKernelGGL(k_cell_keys, dim3(blocks_for(m.nc)), dim3(kBlock), 0, s, m.nc, m.nb_, m.lev,
-                     m.ckey, m.fpack, m.chist);
+  static_assert(kPartChunk == kBlock, "the key kernels count one block of items each");
+  const int use_colour = m.scatter == TAFV_SCATTER_COLOUR;
+  const int Kf = use_colour ? m.ncolours * kMaxLevels : kMaxLevels;
+  const int Kc = early_order ? kMaxLevels + kCellKeys : kMaxLevels;
+  const int nbf = partition_blocks(m.nf), nbc = partition_blocks(m.nc);
+  hipLaunchKernelGGL(k_keys, dim3(nbf + nbc), dim3(kBlock), 0, s, m.nf, nbf, m.fhL, m.fhR,
+                     m.fcol, use_colour, Kf, m.fkey, m.pf.counts, m.nc, nbc, m.nb_, m.lev,
+                     m.ckey, m.fpack, m.chist, early_order ? 0 : 1, m.pc.counts);
   if (early_order)
-    hipLaunchKernelGGL(k_cell_list_keys, dim3(blocks_for(m.nc)), dim3(kBlock), 0, s, m.nc, m.nb_,
-                       m.lev, m.ckey, m.fpack, m.lkey, early_order);
-  hipError_t e =
-      run_partition(s, m.nf, m.pf, ByteKey{m.fkey}, Kf, FaceWriter{m.frec, m.fhL, m.fhR});
-  if (e != hipSuccess) return e;
-  if (!early_order)  // the gather's list serves time order 1 only
-    return run_partition(s, m.nc, m.pc, ByteKey{m.ckey}, kMaxLevels, IndexWriter{m.pc.list});
-  return run_partition(s, m.nc, m.pc, ByteKey{m.ckey}, kMaxLevels, IndexWriter{m.pc.list}, &m.pg,
-                       ByteKey{m.lkey}, kCellKeys, IndexWriter{m.pg.list});
+    hipLaunchKernelGGL(k_cell_list_keys, dim3(nbc), dim3(kBlock), 0, s, m.nc, nbc, m.nb_, m.lev,
+                       m.ckey, m.fpack, m.lkey, early_order, m.pc.counts);
+  hipLaunchKernelGGL(k_part_scan, dim3(Kf + Kc), dim3(kScanThreads), 0, s, Kf, nbf, m.pf.counts,
+                     m.pf.offs, m.pf.tot, nbc, m.pc.counts, m.pc.offs, m.pc.tot);
+  const Readback none{nullptr, nullptr, 0, nullptr, nullptr, nullptr, nullptr};
+  hipLaunchKernelGGL((k_part_scatter<ByteKey, FaceWriter, IndexWriter>), dim3(nbf), dim3(64), 0,
+                     s, m.nf, ByteKey{m.fkey}, Kf, FaceWriter{m.frec, m.fhL, m.fhR}, m.pf.start,
+                     ByteKey{nullptr}, 0, IndexWriter{nullptr}, nullptr, nbf, m.pf.offs,
+                     m.pf.tot, none);
+  const Readback rb{m.dscal, m.pf.start, Kf, m.pc.start, early_order ? m.pg.start : nullptr,
+                    m.chist, m.rb};
+  if (early_order)
+    hipLaunchKernelGGL((k_part_scatter<ByteKey, IndexWriter, IndexWriter>), dim3(nbc), dim3(64),
+                       0, s, m.nc, ByteKey{m.ckey}, kMaxLevels, IndexWriter{m.pc.list},
+                       m.pc.start, ByteKey{m.lkey}, kCellKeys, IndexWriter{m.pg.list},
+                       m.pg.start, nbc, m.pc.offs, m.pc.tot, rb);
+  else  // the gather's list serves time order 1 only
+    hipLaunchKernelGGL((k_part_scatter<ByteKey, IndexWriter, IndexWriter>), dim3(nbc), dim3(64),
+                       0, s, m.nc, ByteKey{m.ckey}, kMaxLevels, IndexWriter{m.pc.list},
+                       m.pc.start, ByteKey{nullptr}, 0, IndexWriter{nullptr}, nullptr, nbc,
+                       m.pc.offs, m.pc.tot, rb);
+  return hipGetLastError();
 }
 
 template <typename T>
@@ -731,7 +842,7 @@ static void flux_feat_launch(hipStream_t s, int order, int feat, int count, cons
 
 hipError_t launch_flux(hipStream_t s, DevMesh& m, const StepArgs& a, int first, int count,
                        const FluxFeatures& ft, const double* U, void* Q, int pass_mode,
-                       const void* Qpred) {
+                       const void* Qpred, bool dt_min_on_device) {
   if (count <= 0) return hipSuccess;
   const int4* rec = m.frec + first;
   if (!U) U = m.U;
@@ -740,7 +851,8 @@ hipError_t launch_flux(hipStream_t s, DevMesh& m, const StepArgs& a, int first, 
     FluxArgs<float> f{rec, count, m.nf, m.nc, m.fA32, U, (const float*)m.Wf, m.R, (float*)Q, m.dcount,
                       m.dimpulse, a, ft.mlp, ft.log_rows, ft.log_count, ft.log_cap,
                       ft.log_rate, ft.log_seed, ft.subit, ft.guess_gate, ft.guess_strength,
-                      pass_mode, (const float*)Qpred, m.moving ? m.sF : nullptr};
+                      pass_mode, (const float*)Qpred, m.moving ? m.sF : nullptr,
+                      dt_min_on_device ? m.dscal : nullptr};
     if (ft.feat && a.gas.is14 && m.scatter == TAFV_SCATTER_GATHER && !m.moving)
       flux_feat_launch<float>(s, a.order, ft.feat, count, f);
     else if (a.gas.is14) flux_launch<float, true>(s, a.order, m.scatter, count, f);
@@ -749,7 +861,8 @@ hipError_t launch_flux(hipStream_t s, DevMesh& m, const StepArgs& a, int first, 
     FluxArgs<double> f{rec, count, m.nf, m.nc, m.fA, U, (const double*)m.Wf, m.R, (double*)Q,
                        m.dcount, m.dimpulse, a, ft.mlp, ft.log_rows, ft.log_count, ft.log_cap,
                        ft.log_rate, ft.log_seed, ft.subit, ft.guess_gate, ft.guess_strength,
-                       pass_mode, (const double*)Qpred, m.moving ? m.sF : nullptr};
+                       pass_mode, (const double*)Qpred, m.moving ? m.sF : nullptr,
+                       dt_min_on_device ? m.dscal : nullptr};
     if (ft.feat && a.gas.is14 && m.scatter == TAFV_SCATTER_GATHER && !m.moving)
       flux_feat_launch<double>(s, a.order, ft.feat, count, f);
     else if (a.gas.is14) flux_launch<double, true>(s, a.order, m.scatter, count, f);
@@ -759,7 +872,7 @@ hipError_t launch_flux(hipStream_t s, DevMesh& m, const StepArgs& a, int first, 
 }
 
 hipError_t launch_cell_gather(hipStream_t s, DevMesh& m, const ListRanges& r, int tau_s,
-                              int tau_upd, double dt_min, int precision) {
+                              int tau_upd, double dt_min, int precision, bool dt_min_on_device) {
   int count = r.count();
   if (count <= 0) return hipSuccess;
   // a whole-mesh launch: the cells outside the ranges find nothing to do
@@ -784,11 +897,11 @@ hipError_t launch_cell_gather(hipStream_t s, DevMesh& m, const ListRanges& r, in
   if (precision == TAFV_FP32_FLUX)
     hipLaunchKernelGGL(k_cell_gather<float>, dim3(blocks_for(count)), dim3(kBlock), 0, s, count,
                        list, r, m.nc, m.fpack, m.c2f, (const float*)m.Q, dt_min,
-                       m.vol, m.U, m.R, tau_s, tau_upd, m.dscal);
+                       m.vol, m.U, m.R, tau_s, tau_upd, m.dscal, dt_min_on_device ? 1 : 0);
   else
     hipLaunchKernelGGL(k_cell_gather<double>, dim3(blocks_for(count)), dim3(kBlock), 0, s, count,
                        list, r, m.nc, m.fpack, m.c2f, (const double*)m.Q, dt_min,
-                       m.vol, m.U, m.R, tau_s, tau_upd, m.dscal);
+                       m.vol, m.U, m.R, tau_s, tau_upd, m.dscal, dt_min_on_device ? 1 : 0);
   return hipGetLastError();
 }
 

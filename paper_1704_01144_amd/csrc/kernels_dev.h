@@ -437,7 +437,15 @@ struct FluxArgs {
   int pass_mode;
   const T* Qpred;
   const double* sF;  // moving mesh: face volume rates w_f . A_f
+  // when set, dt_min is read here on the device (its bit pattern) instead of
+  // from s.dt_min: a launch enqueued before the host knows dt_min
+  const unsigned long long* dtmin_dev = nullptr;
 };
+
+template <typename T>
+__device__ inline double flux_dt_min(const FluxArgs<T>& a) {
+  return a.dtmin_dev ? __longlong_as_double((long long)*a.dtmin_dev) : a.s.dt_min;
+}
 
 // gather mode: the face's stored flux and the wall impulse of its
 // time-integrated flux (phi is replaced by phi0 + phi1 in a corrector pass)
@@ -665,9 +673,10 @@ __device__ inline unsigned long long mix64(unsigned long long z) {
 //             starts from p_TR exp(y) (a non-finite or non-positive guess
 //             falls back to p_TR).  The network runs once per wave, on the
 //             matrix cores, when any face of the wave passes the strength
-//             pre-gate; that test needs only the two states, so only they
-//             and the inputs are kept across the network pass, and the
-//             two-rarefaction value is formed after it.
+//             pre-gate (a few FP32 operations on the two states); only the
+//             states are kept across the network pass, the network's inputs
+//             are formed for that pass alone, and the two-rarefaction value
+//             is formed after it.
 // The Newton iteration and its stop test are unchanged, so p* is the same
 // root whichever start is used.  All 64 lanes of a wave must call this
 // together (valid = false for lanes without a face); wave_lds is this
@@ -678,14 +687,48 @@ __device__ inline unsigned long long mix64(unsigned long long z) {
 template <typename T>
 constexpr int kFeatWaves = sizeof(T) == 4 ? 5 : 4;
 
+// The network's inputs for one interior face: the two states' deviations
+// from their means, normalised by them (density, normal velocity over the
+// mean sound speed, pressure).
+template <typename T>
+__device__ inline void face_features(const Gas& G, const T* wl, const T* wr, T unl, T unr,
+                                     float* x) {
+  double rl = wl[0], rr = wr[0], pl = wl[4], pr = wr[4];
+  double rm = 0.5 * (rl + rr), pm = 0.5 * (pl + pr);
+  double amean = sqrt(G.g * pm / rm);
+  double dr = (rl - rr) / (rl + rr), dp = (pl - pr) / (pl + pr);
+  double du = 0.5 * ((double)unl - (double)unr) / amean;
+  x[0] = (float)dr;
+  x[1] = (float)du;
+  x[2] = (float)dp;
+  x[3] = (float)-dr;
+  x[4] = (float)-du;
+  x[5] = (float)-dp;
+}
+
+// The strength pre-gate |u_R - u_L| / a_m + |p_L - p_R| / p_m >= s of an
+// interior face, in FP32 and without a square root: with
+// d = s - |p_L - p_R| / p_m, it holds where d <= 0 or
+// (u_R - u_L)^2 >= d^2 a_m^2, a_m^2 = g p_m / rho_m.
+template <typename T>
+__device__ inline bool strength_pregate(const Gas& G, const T* wl, const T* wr, T unl, T unr,
+                                        float s) {
+  const float rm = 0.5f * ((float)wl[0] + (float)wr[0]);
+  const float pm = 0.5f * ((float)wl[4] + (float)wr[4]);
+  const float d = s - fabsf((float)wl[4] - (float)wr[4]) / pm;
+  if (d <= 0.f) return true;
+  const float du = (float)unr - (float)unl;
+  return du * du >= d * d * ((float)G.g * pm / rm);
+}
+
 template <int ORDER, typename T, int FEAT>
 __device__ inline void flux_feat_item(const FluxArgs<T>& a, bool valid, int4 r, double dt_min,
                                       uint16_t* wave_lds, SolveInfo& acc, double& i0,
                                       double& i1, double& i2) {
   const Gas& G = a.s.gas;
   SolveInfo info{0, 0, 0, 0, 0, 0, 0, 0};
-  // 1. the face's states and normal, the network's inputs and the strength
-  // pre-gate: all that is kept across the wave's network pass
+  // 1. the face's states and normal and the strength pre-gate: all that is
+  // kept across the wave's network pass
   T wl[5] = {1, 0, 0, 0, 1}, wr[5] = {1, 0, 0, 0, 1};
   T am = 1, nx = 1, ny = 0, nz = 0, unl = 0, unr = 0;
   bool wall = false, transmit = false, net = false;
@@ -706,24 +749,15 @@ __device__ inline void flux_feat_item(const FluxArgs<T>& a, bool valid, int4 r, 
     nz = az * ia;
     unl = wl[1] * nx + wl[2] * ny + wl[3] * nz;
     unr = wall ? -unl : wr[1] * nx + wr[2] * ny + wr[3] * nz;
-    if (r.z >= 0) {  // deviations from the face mean, normalised by it
-      double rl = wl[0], rr = wr[0], pl = wl[4], pr = wr[4];
-      double rm = 0.5 * (rl + rr), pm = 0.5 * (pl + pr);
-      double amean = sqrt(G.g * pm / rm);
-      double dr = (rl - rr) / (rl + rr), dp = (pl - pr) / (pl + pr);
-      double du = 0.5 * ((double)unl - (double)unr) / amean;
-      x[0] = (float)dr;
-      x[1] = (float)du;
-      x[2] = (float)dp;
-      x[3] = (float)-dr;
-      x[4] = (float)-du;
-      x[5] = (float)-dp;
-      net = (FEAT & 2) && 2.f * (fabsf(x[1]) + fabsf(x[2])) >= a.guess_strength;
-    }
+    if ((FEAT & 2) && r.z >= 0) net = strength_pregate<T>(G, wl, wr, unl, unr, a.guess_strength);
   }
-  // 2. the network, once per wave, where any face passes the pre-gate
+  // 2. the network, once per wave, where any face passes the pre-gate (the
+  // inputs are formed only then)
   float ym = 0.f;
-  if ((FEAT & 2) && __ballot(net) != 0ull) ym = mlp_wave_forward(*a.mlp, x, wave_lds);
+  if ((FEAT & 2) && __ballot(net) != 0ull) {
+    if (valid && r.z >= 0) face_features<T>(G, wl, wr, unl, unr, x);
+    ym = mlp_wave_forward(*a.mlp, x, wave_lds);
+  }
   // 3. the face solve: two-rarefaction value, the network's start where the
   // two-rarefaction value is inexact, Newton, sampling, flux
   if (valid) {
@@ -785,6 +819,7 @@ __device__ inline void flux_feat_item(const FluxArgs<T>& a, bool valid, int4 r, 
             unsigned long long slot = atomicAdd(a.log_count, 1ull);
             if (slot < (unsigned long long)a.log_cap) {
               float* row = a.log_rows + 7 * slot;
+              face_features<T>(G, wl, wr, unl, unr, x);
               for (int k = 0; k < kMlpIn; ++k) row[k] = x[k];
               row[6] = (float)log(st.p / tr.p);
             }

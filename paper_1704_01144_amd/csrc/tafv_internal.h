@@ -51,9 +51,8 @@ tafv_status build_host_mesh(int64_t n_nodes, const double* xyz, int64_t n_tets,
 struct Partition {
   int32_t* list = nullptr;     // [n] indices sorted by key, stable
   int32_t* counts = nullptr;   // [kMaxKeys][nblocks]
-  int32_t* offs = nullptr;     // [kMaxKeys][nblocks] exclusive scan of counts
-  void* scan_tmp = nullptr;    // device scan scratch
-  size_t scan_bytes = 0;
+  int32_t* offs = nullptr;     // [kMaxKeys][nblocks] exclusive scan of each key's counts
+  int32_t* tot = nullptr;      // [kMaxKeys] count of each key
   int32_t* start = nullptr;    // [kMaxKeys + 1] device
   int32_t nblocks = 0;
 };
@@ -205,8 +204,9 @@ struct tafv_ctx {
   tafv_params prm{};
   std::vector<tafv::DevMesh*> meshes;
   std::string err;
-  // host pinned readback buffer
+  // host pinned readback buffer, and the event that marks the readback's copy
   int32_t* hpin = nullptr;
+  hipEvent_t rb_event = nullptr;
   // profiling
   bool profile = false;
   std::vector<tafv::ProfileClass> prof;
@@ -256,7 +256,8 @@ hipError_t dev_alloc(tafv_ctx* c, T** p, size_t bytes) {
 tafv_status read_slot_counters(tafv_ctx* c, DevMesh& m, tafv_stats* st);
 
 // per-kernel-class timing with HIP events on the context stream
-enum { P_CLASSIFY = 0, P_GRAD = 1, P_FLUX = 2, P_UPDATE = 3, P_GATHER = 4, P_PREDICT = 5, P_N = 6 };
+enum { P_CLASSIFY = 0, P_GRAD = 1, P_FLUX = 2, P_UPDATE = 3, P_GATHER = 4, P_PREDICT = 5,
+       P_FLUX_CORR = 6, P_N = 7 };
 struct ProfScope {
   tafv_ctx* c;
   int cls;

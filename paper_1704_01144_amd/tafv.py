@@ -94,6 +94,8 @@ def _load():
                               i32p, dp],
         "tafv_state_init": [P, C.c_int32, dp],
         "tafv_advance": [P, C.c_int64, C.POINTER(tafv_stats)],
+        "tafv_advance_group": [C.POINTER(P), C.c_int32, C.c_int64, C.c_int32,
+                               C.POINTER(tafv_stats)],
         "tafv_state_reset": [P, C.c_int32],
         "tafv_mesh_stats": [P, C.c_int32, C.POINTER(tafv_stats)],
         "tafv_state_read": [P, C.c_int32, dp, i8p],
@@ -130,7 +132,8 @@ lib = _load()
 # every symbol the header declares (checked by the CPU tests)
 EXPORTS = ["tafv_params_default", "tafv_create", "tafv_destroy", "tafv_last_error",
            "tafv_set_allocator", "tafv_device_buffers",
-           "tafv_mesh_upload", "tafv_mesh_inspect", "tafv_mesh_params", "tafv_state_init", "tafv_state_reset", "tafv_advance",
+           "tafv_mesh_upload", "tafv_mesh_inspect", "tafv_mesh_params", "tafv_state_init",
+           "tafv_state_reset", "tafv_advance", "tafv_advance_group",
            "tafv_mesh_stats", "tafv_state_read", "tafv_checkpoint_read", "tafv_checkpoint_write",
            "tafv_profile_enable", "tafv_profile_read", "tafv_guess_config", "tafv_mlp_set", "tafv_mlp_get",
            "tafv_mlp_forward", "tafv_mlp_grad", "tafv_mlp_grad_noalloc", "tafv_mlp_train",
@@ -265,6 +268,24 @@ def tafv_advance(ctx, n):
     st = tafv_stats()
     _check(lib.tafv_advance(ctx, int(n), C.byref(st)), ctx)
     return st.as_dict()
+
+
+def tafv_advance_group(ctxs, n, workers=4, stats=True):
+    """Advance the contexts together (one host worker per `workers` share of
+    them); returns the summed counters, or None with stats=False."""
+    arr = (C.c_void_p * len(ctxs))(*[c.value if isinstance(c, C.c_void_p) else c for c in ctxs])
+    st = tafv_stats() if stats else None
+    rc = lib.tafv_advance_group(arr, len(ctxs), int(n), int(workers),
+                                C.byref(st) if stats else None)
+    if rc != OK:
+        bad = None
+        for c in ctxs:  # the failing context holds the message
+            msg = lib.tafv_last_error(c)
+            if msg:
+                bad = msg
+                break
+        raise TafvError(rc, (bad or lib.tafv_last_error(None) or b"").decode())
+    return st.as_dict() if stats else None
 
 
 def tafv_advance_async(ctx, n):
