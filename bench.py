@@ -66,7 +66,22 @@ BYTES_PER_ITEM_FORM = {
 }
 # kernel of each timing class, by form (names of the counter records)
 KERNEL_OF_CLASS = {"flux": "k_flux", "flux_corrector": "k_flux", "grad": "k_grad",
-                   "gather": "k_gather", "update": "k_update"}
+                   "gather": "k_gather", "update": "k_update", "grad_flux": "k_grad_flux"}
+# Whole-mesh gradient launches that also compute the faces local to a chunk
+# of 256 cells (k_grad_flux): per cell in range the gradient's bytes less
+# the face values kept on chip (160 FP64, 80 FP32, times the share f of
+# half-faces local to a chunk), per local face its entry of the chunk's list
+# (8), its area vector (24; 12), the lower cell's packed level word (4) and
+# its flux (40; 20).
+GRAD_FLUX_BYTES = {"fp64": (316, 160, 76), "fp32": (188, 80, 44)}
+
+
+def local_half_face_share(T, cfg):
+    """Share of half-faces whose other side lies in the same chunk of 256
+    cells of the mesh order (boundary half-faces included)."""
+    nb = T.tafv_mesh_inspect(cfg["nodes"], cfg["tets"])["cell_neighbours"]
+    i = np.arange(len(nb))[:, None]
+    return float(((nb < 0) | (nb // 256 == i // 256)).mean())
 
 
 def log(*a):
@@ -74,6 +89,7 @@ def log(*a):
 
 
 CELL_ORDER = 0  # internal cell order of the single-mesh runs (set from --cell-order)
+FUSE_FACES = 0  # chunk-local faces computed by the gradient launches (set from --fuse-faces)
 
 
 def run_form(T, torch, cfg, precision, steps, warmup, scatter, mlp=None, stats=0, time_order=1,
@@ -85,7 +101,8 @@ def run_form(T, torch, cfg, precision, steps, warmup, scatter, mlp=None, stats=0
                      guess_strength=mlp["strength"])
     s = T.Solver(device=0, hip_stream=stream.cuda_stream, max_levels=cfg["max_levels"],
                  order=cfg["order"], precision=precision, scatter=scatter, time_order=time_order,
-                 cell_order=CELL_ORDER, allocator=T.torch_allocator(0, stream), **extra)
+                 cell_order=CELL_ORDER, fuse_faces=FUSE_FACES,
+                 allocator=T.torch_allocator(0, stream), **extra)
     s.upload(cfg["nodes"], cfg["tets"])
     if mlp is not None:
         T.tafv_mlp_set(s.ctx, mlp["theta"])
@@ -313,13 +330,17 @@ def measured_traffic(kernel, form):
     return int(float(rec["traffic_bytes_per_launch"])), os.path.relpath(path, ROOT)
 
 
-def roofline(prof, bytes_per_item, form):
+def roofline(prof, bytes_per_item, form, class_bytes=None):
     """Roofline entry of the longest kernel class of a run with a known
-    algorithmic byte count per item."""
-    dom = max((k for k in prof if k in bytes_per_item and prof[k]["items"] > 0),
+    algorithmic byte count: per item (bytes_per_item), or in total for the
+    run (class_bytes)."""
+    class_bytes = class_bytes or {}
+    known = set(bytes_per_item) | set(class_bytes)
+    dom = max((k for k in prof if k in known and prof[k]["items"] > 0),
               key=lambda k: prof[k]["ms"])
     p = prof[dom]
-    achieved = bytes_per_item[dom] * p["items"] / (p["ms"] * 1e-3) / 1e9
+    total = class_bytes[dom] if dom in class_bytes else bytes_per_item[dom] * p["items"]
+    achieved = total / (p["ms"] * 1e-3) / 1e9
     name = KERNEL_OF_CLASS[dom] + ("_corrector" if dom == "flux_corrector" else "")
     traffic, src = measured_traffic(name, form)
     launches = max(p["launches"], 1)
@@ -328,9 +349,9 @@ def roofline(prof, bytes_per_item, form):
                  "traffic_unit": "HBM bytes per launch", "traffic_source": src,
                  "kernel": name, "timing_class": dom,
                  "avg_launch_us": round(1e3 * p["ms"] / launches, 2),
-                 "bytes_per_item": bytes_per_item[dom], "items": p["items"],
+                 "bytes_per_item": round(total / max(p["items"], 1), 1), "items": p["items"],
                  "launches": p["launches"],
-                 "algorithmic_bytes_per_launch": int(bytes_per_item[dom] * p["items"] / launches)}
+                 "algorithmic_bytes_per_launch": int(total / launches)}
 
 
 def copy_bandwidth(torch, nbytes=1 << 30, reps=5):
@@ -419,11 +440,20 @@ FORMS = ("fp64", "fp32_flux", "fp32_learned", "time_order_2_fp64", "time_order_2
          "moving_mesh_fp64", "batched")
 
 
-def with_roofline(entry, run, bpi, form, copy_gbs):
+def with_roofline(entry, run, bpi, form, copy_gbs, f_loc=None):
     """Adds the roofline of the run's longest kernel (algorithmic bytes per
     launch over its average launch time, from HIP events on the library's
-    stream), its share of a plain copy's bandwidth and the kernel times."""
-    _, roof = roofline(run["prof"], bpi, form)
+    stream), its share of a plain copy's bandwidth and the kernel times.
+    f_loc: share of half-faces local to a chunk, for the fused launches."""
+    extra = {}
+    gf = run["prof"].get("grad_flux")
+    if gf and gf["items"] > 0 and f_loc is not None:
+        cell, wf, face = GRAD_FLUX_BYTES["fp32" if "fp32" in form else "fp64"]
+        local_faces = run["faces"] - run["prof"].get("flux", {}).get("items", 0)
+        extra["grad_flux"] = gf["items"] * (cell - wf * f_loc) + local_faces * face
+        entry["faces_computed_in_gradient_launches"] = round(local_faces / max(run["faces"], 1), 4)
+        entry["half_faces_local_to_a_chunk"] = round(f_loc, 4)
+    _, roof = roofline(run["prof"], bpi, form, extra)
     if copy_gbs:
         roof["copy_gbs_measured"] = round(copy_gbs, 1)
         roof["frac_of_copy"] = round(roof["achieved"] / copy_gbs, 4)
@@ -452,6 +482,9 @@ def main():
     ap.add_argument("--no-moving", action="store_true", help="skip the moving-mesh form")
     ap.add_argument("--only", choices=FORMS,
                     help="run this form alone (for profiling); prints its entry as the JSON line")
+    ap.add_argument("--fuse-faces", type=int, default=0, choices=(0, 1),
+                    help="1: whole-mesh gradient launches also compute the faces local to a "
+                         "256-cell chunk; 0: every face through the flux kernel")
     ap.add_argument("--cell-order", type=int, default=0,
                     help="internal cell order: 0 the mesh's own, 1 Morton order of the centroids")
     ap.add_argument("--batch-only", action="store_true",
@@ -467,8 +500,9 @@ def main():
     if args.copy_probe:
         copy_probe()
         return
-    global CELL_ORDER
+    global CELL_ORDER, FUSE_FACES
     CELL_ORDER = args.cell_order
+    FUSE_FACES = args.fuse_faces
 
     import torch
 
@@ -492,6 +526,7 @@ def main():
         f"{UNITS} units, steps {args.steps}, warmup {args.warmup}")
     bpi = BYTES_PER_ITEM_GATHER if args.scatter == 1 else BYTES_PER_ITEM
     copy_gbs = None if args.only else copy_bandwidth(torch)
+    f_loc = local_half_face_share(T, cfg)
     out = {}
     forms = {}
     r64 = None
@@ -499,7 +534,7 @@ def main():
         r64 = run_form(T, torch, cfg, T.FP64, args.steps, args.warmup, args.scatter)
         value = r64["updates"] / (r64["ms"] * 1e-3)
         log(f"fp64: {r64['ms']:.2f} ms for {args.steps} steps, {value / 1e9:.3f} G cell-updates/s")
-        head = with_roofline({}, r64, bpi["fp64"], "fp64", copy_gbs)
+        head = with_roofline({}, r64, bpi["fp64"], "fp64", copy_gbs, f_loc)
         roof = head["roofline"]
         log(f"dominant kernel {roof['kernel']} at {roof['achieved']:.0f} GB/s algorithmic "
             f"({roof['frac']:.3f} of 8 TB/s)" +
@@ -528,6 +563,8 @@ def main():
                        "levels_t0": r64["stats"]["cells_per_level"][:5]},
             "roofline": roof,
             "kernels_ms": head["kernels_ms"],
+            **{k: head[k] for k in ("faces_computed_in_gradient_launches",
+                                    "half_faces_local_to_a_chunk") if k in head},
             "profiled_pass_ms_per_step": round(r64["ms_prof"] / args.steps, 4),
         }
 
@@ -547,7 +584,7 @@ def main():
             e["speedup_vs_fp64"] = round(v32 / out["value"], 3)
             e["l1_reference"] = "FP64 GPU result of the same run (equal to the oracle within 1e-12)"
         l1_vs_fp64(e, r32)
-        forms["fp32_flux"] = with_roofline(e, r32, bpi["fp32"], "fp32", copy_gbs)
+        forms["fp32_flux"] = with_roofline(e, r32, bpi["fp32"], "fp32", copy_gbs, f_loc)
         log(f"fp32 flux: {v32 / 1e9:.3f} G/s, L1 rho {e.get('l1_rho', float('nan')):.2e}, "
             f"L1 E {e.get('l1_E', float('nan')):.2e}")
     g = None

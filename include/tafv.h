@@ -84,7 +84,8 @@ enum { TAFV_ORDER_CALLER = 0, TAFV_ORDER_MORTON = 1 };
  * newton_tol 1e-12, level_margin 1e-9, max_levels 5, order 2, precision
  * TAFV_FP64, guess TAFV_GUESS_TR, boundary TAFV_BC_WALL, newton_max_iter
  * 50, reclassify 1, scatter TAFV_SCATTER_GATHER, cell_order TAFV_ORDER_CALLER,
- * guess_stats 0, guess_gate 0, batch 0, guess_strength 0, time_order 1. */
+ * guess_stats 0, guess_gate 0, batch 0, guess_strength 0, time_order 1,
+ * fuse_faces 0. */
 typedef struct {
   double gamma;          /* ratio of specific heats, > 1                        */
   double cfl;            /* dt_i = cfl V_i / sum_f (|u_i . n_f| + a_i) |A_f|    */
@@ -145,6 +146,16 @@ typedef struct {
                             conservative; two face solves per face step.
                             Needs TAFV_SCATTER_GATHER and batch 0;
                             checkpoints are written at phase 0 only.      */
+  int32_t fuse_faces;    /* 1: at second order in gather mode with
+                            time_order 1 on a fixed mesh (no face statistics
+                            or logging), a gradient launch over the whole
+                            mesh also computes the fluxes of the faces with
+                            both cells in one block of 256 cells (and of the
+                            boundary faces) from face values held on chip;
+                            the face list keeps those faces apart and the
+                            flux kernel takes the others.  0 (default): one
+                            face list, every face through the flux kernel.
+                            Either way the results are the same bits.     */
 } tafv_params;
 
 /* Counters (int64) and schedule state.  Summed over meshes where a call

@@ -15,6 +15,10 @@ ARCH = os.environ.get("TAFV_OFFLOAD_ARCH", "gfx950")
 
 HIPCC_FLAGS = [
     "--offload-arch=" + ARCH, "-O3", "-std=c++17", "-fPIC", "-x", "hip",
+    # a * b + c is fused where one expression writes it, never across
+    # statements: an inlined device function then rounds the same way in
+    # every kernel that uses it
+    "-ffp-contract=on",
     # packed FP32 instructions stay off: scalar/float2 code only
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-I" + os.path.join(ROOT, "include"), "-I" + CSRC,

@@ -65,9 +65,11 @@ float* scratch_ptr(int device) {
 }
 
 // per-kernel timing classes; "flux_corrector" is the corrector pass of the
-// predictor/corrector form (it also reads the predictor flux)
-const char* kProfNames[] = {"classify", "grad",    "flux",          "update",
-                            "gather",   "predict", "flux_corrector"};
+// predictor/corrector form (it also reads the predictor flux), "grad_flux"
+// the gradient launches that also compute the faces local to a chunk (items:
+// cells)
+const char* kProfNames[] = {"classify", "grad",    "flux",           "update",
+                            "gather",   "predict", "flux_corrector", "grad_flux"};
 
 thread_local std::string g_create_err;
 
@@ -102,7 +104,8 @@ void free_mesh(tafv_ctx* c, DevMesh* m) {
                   m->pf.tot, m->pc.tot, m->Q, m->frec, m->fkey, m->ckey, m->fpack,
                   m->perm, m->xfer, m->chist, m->rb, m->dmin, m->Q0, m->D, m->Ut,
                   m->vol0, m->fnode, m->sF, m->Rv, m->sweepf, m->lkey, m->pg.list,
-                  m->pg.counts, m->pg.start, m->pg.offs, m->pg.tot};
+                  m->pg.counts, m->pg.start, m->pg.offs, m->pg.tot, m->flocal,
+                  m->lf_start, m->lf_face};
   for (void* p : ptrs) dev_free(c, p);
   delete m;
 }
@@ -175,11 +178,15 @@ int early_order(const tafv_ctx* c, const DevMesh& m) {
   return (m.scatter == TAFV_SCATTER_GATHER && c->prm.time_order == 1) ? c->prm.order : 0;
 }
 
+FluxFeatures flux_features(tafv_ctx* c, DevMesh& m);
+bool fusable(const tafv_ctx* c, const DevMesh& m, const FluxFeatures& ft);
+
 // Enqueues the classification at an iteration start (time steps, levels,
 // sweeps, keys, lists) and the copy of its results to the pinned host
 // buffer; c->rb_event marks the copy's end.
 tafv_status classify_enqueue(tafv_ctx* c, DevMesh& m) {
   StepArgs a = step_args(c, m);
+  m.split_local = fusable(c, m, flux_features(c, m));
   {
     ProfScope ps(c, P_CLASSIFY, m.nc);
     HIP_TRY(c, launch_dt(c->stream, m, a));
@@ -197,7 +204,7 @@ tafv_status classify_enqueue(tafv_ctx* c, DevMesh& m) {
 // the list starts and the level histogram.
 tafv_status classify_finish(tafv_ctx* c, DevMesh& m) {
   HIP_TRY(c, hipEventSynchronize(c->rb_event));
-  const int K = m.scatter == TAFV_SCATTER_COLOUR ? m.ncolours * kMaxLevels : kMaxLevels;
+  const int K = face_list_keys(m);
   const int32_t* h = c->hpin;
   unsigned long long bits[3];
   std::memcpy(bits, h, sizeof(bits));
@@ -215,11 +222,6 @@ tafv_status classify_finish(tafv_ctx* c, DevMesh& m) {
   m.theta = theta;
   m.classified = true;
   return TAFV_OK;
-}
-
-tafv_status classify(tafv_ctx* c, DevMesh& m) {
-  tafv_status st = classify_enqueue(c, m);
-  return st != TAFV_OK ? st : classify_finish(c, m);
 }
 
 // cells with an active face when levels <= g start a step (tau_g <= g):
@@ -251,6 +253,23 @@ int64_t cells_upto_tau(const DevMesh& m, int t) {
   return n;
 }
 
+// The active faces of levels <= t (gather mode): a prefix of the face list,
+// and, when the faces local to a chunk are listed after the others, the
+// prefix of those too.
+struct FaceRanges {
+  int first1 = 0, n1 = 0, first2 = 0, n2 = 0;
+  int count() const { return n1 + n2; }
+};
+FaceRanges faces_active(const DevMesh& m, int t, bool with_local = true) {
+  FaceRanges r;
+  r.n1 = m.hstart_f[t + 1];
+  if (m.split_local && with_local) {
+    r.first2 = m.hstart_f[kMaxLevels];
+    r.n2 = m.hstart_f[kMaxLevels + t + 1] - r.first2;
+  }
+  return r;
+}
+
 FluxFeatures flux_features(tafv_ctx* c, DevMesh& m) {
   FluxFeatures ft;
   bool mlp = c->prm.guess == TAFV_GUESS_MLP;
@@ -279,7 +298,8 @@ FluxFeatures flux_features(tafv_ctx* c, DevMesh& m) {
 tafv_status subiteration2(tafv_ctx* c, DevMesh& m, const StepArgs& a, int tau_s, int upd,
                           int64_t s, int64_t& faces) {
   const double dt_min = m.dt_min;
-  const int pcnt = m.hstart_f[tau_s + 1], ccnt = m.hstart_f[upd + 1];
+  const FaceRanges pr = faces_active(m, tau_s), cr = faces_active(m, upd);
+  const int pcnt = pr.count(), ccnt = cr.count();
   if (c->prm.order == 2) {
     const CellRange r = cells_active(m, tau_s);
     ProfScope ps(c, P_GRAD, r.count());
@@ -287,7 +307,8 @@ tafv_status subiteration2(tafv_ctx* c, DevMesh& m, const StepArgs& a, int tau_s,
   }
   {
     ProfScope ps(c, P_FLUX, pcnt);
-    HIP_TRY(c, launch_flux(c->stream, m, a, 0, pcnt, flux_features(c, m), m.Ut, m.Q0, 1));
+    HIP_TRY(c, launch_flux(c->stream, m, a, 0, pr.n1, flux_features(c, m), m.Ut, m.Q0, 1, nullptr,
+                           false, pr.first2, pr.n2));
   }
   {
     ProfScope ps(c, P_PREDICT, m.nc);
@@ -300,7 +321,8 @@ tafv_status subiteration2(tafv_ctx* c, DevMesh& m, const StepArgs& a, int tau_s,
   }
   {
     ProfScope ps(c, P_FLUX_CORR, ccnt);
-    HIP_TRY(c, launch_flux(c->stream, m, a, 0, ccnt, flux_features(c, m), m.Ut, m.Q, 2, m.Q0));
+    HIP_TRY(c, launch_flux(c->stream, m, a, 0, cr.n1, flux_features(c, m), m.Ut, m.Q, 2, m.Q0,
+                           false, cr.first2, cr.n2));
   }
   {
     const CellRange r = cells_active(m, upd);
@@ -325,6 +347,23 @@ void end_subiteration(DevMesh& m, tafv_stats* acc, int64_t s, int64_t ucnt, int6
   }
 }
 
+// Gather mode, second order, forward Euler level steps on a fixed mesh,
+// with no flux feature or the learned guess alone (gamma 1.4): a gradient
+// launch over the whole mesh can also compute the faces local to a chunk
+// (k_grad_flux).  Face statistics and logging keep the flux kernel.
+bool fusable(const tafv_ctx* c, const DevMesh& m, const FluxFeatures& ft) {
+  const bool feat_ok = ft.feat == 0 || (ft.feat == 2 && c->prm.gamma == 1.4);
+  return m.flocal && c->prm.fuse_faces && c->prm.order == 2 && c->prm.time_order == 1 &&
+         !m.moving && feat_ok;
+}
+
+// A whole-mesh gradient launch computes the chunk-local faces when the
+// face list of this iteration keeps them apart.
+bool fuse_local_faces(const tafv_ctx* c, const DevMesh& m, const FluxFeatures& ft,
+                      int64_t grad_cells) {
+  return m.split_local && fusable(c, m, ft) && grad_whole_mesh(m, grad_cells);
+}
+
 // Gather mode with one face pass per level step on a fixed mesh: the first
 // subiteration of an iteration runs at tau_s = theta, so every face and
 // every cell take part, and cells of level 0 end their step.  Its launches
@@ -339,16 +378,23 @@ bool first_subiteration_ahead(const tafv_ctx* c, const DevMesh& m) {
 tafv_status first_subiteration(tafv_ctx* c, DevMesh& m, tafv_stats* acc) {
   StepArgs a = step_args(c, m);
   const int all = kMaxLevels - 1;  // at least theta
+  const FluxFeatures ft = flux_features(c, m);
+  const bool fuse = fuse_local_faces(c, m, ft, m.nc);
   if (c->prm.order == 2) {
-    CellRange r;
-    r.n1 = m.nc;
-    ProfScope ps(c, P_GRAD, m.nc);
-    HIP_TRY(c, launch_grad(c->stream, m, a, r, all));
+    ProfScope ps(c, fuse ? P_GRAD_FLUX : P_GRAD, m.nc);
+    if (fuse) {
+      HIP_TRY(c, launch_grad_flux(c->stream, m, a, all, ft, true));
+    } else {
+      CellRange r;
+      r.n1 = m.nc;
+      HIP_TRY(c, launch_grad(c->stream, m, a, r, all));
+    }
   }
   {
-    ProfScope ps(c, P_FLUX, m.nf);
-    HIP_TRY(c, launch_flux(c->stream, m, a, 0, m.nf, flux_features(c, m), nullptr, nullptr, 0,
-                           nullptr, true));
+    // the faces between chunks come first in the face list
+    const int n = fuse ? m.nf - m.n_local : m.nf;
+    ProfScope ps(c, P_FLUX, n);
+    HIP_TRY(c, launch_flux(c->stream, m, a, 0, n, ft, nullptr, nullptr, 0, nullptr, true));
   }
   {
     ListRanges r;
@@ -372,10 +418,14 @@ tafv_status subiteration(tafv_ctx* c, DevMesh& m, tafv_stats* acc) {
   }
   StepArgs a = step_args(c, m);
   int tau_s = subiteration_level((int64_t)m.phase + 1, m.theta);
+  const FluxFeatures ft = flux_features(c, m);
+  bool fuse = false;
   if (c->prm.order == 2 && c->prm.time_order == 1) {
     const CellRange r = cells_active(m, tau_s);
-    ProfScope ps(c, P_GRAD, r.count());
-    HIP_TRY(c, launch_grad(c->stream, m, a, r, tau_s));
+    fuse = m.scatter == TAFV_SCATTER_GATHER && fuse_local_faces(c, m, ft, r.count());
+    ProfScope ps(c, fuse ? P_GRAD_FLUX : P_GRAD, r.count());
+    if (fuse) HIP_TRY(c, launch_grad_flux(c->stream, m, a, tau_s, ft, false));
+    else HIP_TRY(c, launch_grad(c->stream, m, a, r, tau_s));
   }
   int64_t s = (int64_t)m.phase + 1;
   // cells whose step ends after this subiteration: tau_i <= min(theta, ctz(s))
@@ -404,11 +454,14 @@ tafv_status subiteration(tafv_ctx* c, DevMesh& m, tafv_stats* acc) {
     ProfScope ps(c, P_UPDATE, r.count());
     HIP_TRY(c, launch_update(c->stream, m, r, upd));
   } else {
-    int cnt = m.hstart_f[tau_s + 1];
-    faces = cnt;
+    // with the faces local to a chunk computed by the gradient launch, the
+    // flux kernel takes the others
+    const FaceRanges fr = faces_active(m, tau_s, !fuse);
+    faces = faces_active(m, tau_s).count();
     {
-      ProfScope ps(c, P_FLUX, cnt);
-      HIP_TRY(c, launch_flux(c->stream, m, a, 0, cnt, flux_features(c, m)));
+      ProfScope ps(c, P_FLUX, fr.count());
+      HIP_TRY(c, launch_flux(c->stream, m, a, 0, fr.n1, ft, nullptr, nullptr, 0, nullptr, false,
+                             fr.first2, fr.n2));
     }
     const ListRanges r = cells_gather(m, tau_s, upd);
     ProfScope ps(c, P_GATHER, r.count());
@@ -607,6 +660,41 @@ tafv_status upload_host_mesh(tafv_ctx* c, const HostMesh& hm, DevMesh** out) {
   chk(up(m->fnode, hm.fnode));
   m->n_nodes = hm.n_nodes;
   chk(up(m->perm, hm.perm));
+  if (e == hipSuccess && m->scatter == TAFV_SCATTER_GATHER && c->prm.order == 2 &&
+      c->prm.time_order == 1 && c->prm.fuse_faces && !c->batch) {
+    // faces with both sides in one chunk of kFuseChunk cells, and boundary
+    // faces, grouped by chunk (their first cell's).  The face partition
+    // then keeps them apart from the faces between chunks (key tau_f + 8).
+    const int64_t chunks = (hm.nc + kFuseChunk - 1) / kFuseChunk;
+    std::vector<int32_t> start(chunks + 1, 0);
+    std::vector<int8_t> loc(nf, 0);
+    for (size_t f = 0; f < nf; ++f) {
+      const int32_t hl = hm.fhL[f], hr = hm.fhR[f];
+      const int32_t L = hl >> 2, Rc = hr >= 0 ? hr >> 2 : -1;
+      if (Rc < 0 || Rc / kFuseChunk == L / kFuseChunk) {
+        loc[f] = 1;
+        start[L / kFuseChunk + 1]++;
+      }
+    }
+    for (int64_t k = 0; k < chunks; ++k) start[k + 1] += start[k];
+    std::vector<int2> lf(start[chunks]);
+    std::vector<int32_t> fill(start.begin(), start.end() - 1);
+    for (size_t f = 0; f < nf; ++f) {
+      if (!loc[f]) continue;
+      const int32_t hl = hm.fhL[f], hr = hm.fhR[f];
+      const int32_t L = hl >> 2, Rc = hr >= 0 ? hr >> 2 : L;
+      const int32_t pos = (L % kFuseChunk) | ((hl & 3) << 8) | ((Rc % kFuseChunk) << 10) |
+                          ((hr >= 0 ? hr & 3 : 0) << 18) | ((hr < 0 ? 1 : 0) << 20);
+      lf[fill[L / kFuseChunk]++] = make_int2((int)f, pos);
+    }
+    m->n_local = start[chunks];
+    chk(dalloc(c, &m->flocal, nf));
+    chk(dalloc(c, &m->lf_start, chunks + 1));
+    chk(dalloc(c, &m->lf_face, std::max<size_t>(lf.size(), 1)));
+    chk(up(m->flocal, loc));
+    chk(up(m->lf_start, start));
+    if (!lf.empty()) chk(up(m->lf_face, lf));
+  }
   // the time-step minimum slots start at +inf (each classification sets
   // them back once it has read them)
   chk(launch_fill_u64(c->stream, m->dmin, 0x7ff0000000000000ull, kCounterWords));
@@ -642,6 +730,7 @@ tafv_status tafv_params_default(tafv_params* p) {
   p->batch = 0;
   p->guess_strength = 0.0;
   p->time_order = 1;
+  p->fuse_faces = 0;
   return TAFV_OK;
 }
 
@@ -668,6 +757,8 @@ tafv_status tafv_create(int device, const tafv_params* params, void* hip_stream,
     return fail(nullptr, TAFV_E_ARG, "the batched form needs gather scatter");
   if (p.time_order != 1 && p.time_order != 2)
     return fail(nullptr, TAFV_E_ARG, "time_order must be 1 or 2");
+  if (p.fuse_faces != 0 && p.fuse_faces != 1)
+    return fail(nullptr, TAFV_E_ARG, "fuse_faces must be 0 or 1");
   if (p.time_order == 2 && (p.batch || p.scatter != TAFV_SCATTER_GATHER))
     return fail(nullptr, TAFV_E_ARG,
                 "the predictor/corrector form needs gather scatter and no batch");
@@ -1132,8 +1223,9 @@ tafv_status tafv_checkpoint_write(tafv_ctx* c, int32_t mesh_id, const double* co
   unsigned long long dbits;
   std::memcpy(&dbits, &dt_min, sizeof(dbits));
   HIP_TRY(c, launch_fill_u64(c->stream, m->dscal, dbits, 1));
+  m->split_local = fusable(c, *m, flux_features(c, *m));
   HIP_TRY(c, launch_partitions(c->stream, *m, early_order(c, *m)));
-  int K = m->scatter == TAFV_SCATTER_COLOUR ? m->ncolours * kMaxLevels : kMaxLevels;
+  int K = face_list_keys(*m);
   HIP_TRY(c, hipMemcpyAsync(m->hstart_f, m->pf.start, (K + 1) * sizeof(int32_t),
                             hipMemcpyDeviceToHost, c->stream));
   HIP_TRY(c, hipMemcpyAsync(m->hstart_c, m->pc.start, (kMaxLevels + 1) * sizeof(int32_t),

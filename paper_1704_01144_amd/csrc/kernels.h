@@ -56,6 +56,25 @@ hipError_t launch_grad(hipStream_t s, DevMesh& m, const StepArgs& a, CellRange r
                        const double* U = nullptr);
 // optional flux features: feat bit 0 = gate statistics and face logging,
 // bit 1 = learned guess (gamma = 1.4, gather mode)
+// Faces whose fluxes the gradient launch computes (k_grad_flux): per chunk
+// of kFuseChunk consecutive cells of the mesh order, the faces with both
+// sides in the chunk and the chunk's boundary faces, as {face id, positions}
+// with bits 0-7 the lower cell's index in the chunk, 8-9 its local face slot,
+// 10-17 the higher cell's index, 18-19 its slot, bit 20 set for a boundary
+// face.  Built at upload (gather mode, second order).
+constexpr int kFuseChunk = 256;
+// keys of the face list: (colour, tau_f) in colour mode; tau_f + 8 flocal
+// while the chunk-local faces are kept apart (the faces between chunks
+// first); tau_f else
+inline int face_list_keys(const DevMesh& m) {
+  if (m.scatter == TAFV_SCATTER_COLOUR) return m.ncolours * kMaxLevels;
+  return m.split_local ? 2 * kMaxLevels : kMaxLevels;
+}
+struct LocalFaces {
+  const int* start;  // [chunks + 1]
+  const int2* face;  // [faces local to a chunk]
+};
+
 struct FluxFeatures {
   int feat = 0;
   const MlpDev* mlp = nullptr;
@@ -72,10 +91,21 @@ struct FluxFeatures {
 // passes of the predictor/corrector form (see FluxArgs)
 // dt_min_on_device: the kernels read dt_min from the device scalars (its
 // bits in m.dscal[0]) instead of the host's value
+// The faces are entries [first, first + count) and [first2, first2 + count2)
+// of the face list.
 hipError_t launch_flux(hipStream_t s, DevMesh& m, const StepArgs& a, int first, int count,
                        const FluxFeatures& ft, const double* U = nullptr, void* Q = nullptr,
                        int pass_mode = 0, const void* Qpred = nullptr,
-                       bool dt_min_on_device = false);
+                       bool dt_min_on_device = false, int first2 = 0, int count2 = 0);
+// Gradient over the whole mesh (cells of tau_g <= tau_s) with the fluxes of
+// the active faces local to a chunk (k_grad_flux); the other active faces are
+// left to launch_flux.  Features: none, or the learned guess alone
+// (ft.feat == 2, gamma 1.4); others give hipErrorInvalidValue.
+hipError_t launch_grad_flux(hipStream_t s, DevMesh& m, const StepArgs& a, int tau_s,
+                            const FluxFeatures& ft, bool dt_min_on_device);
+// whether a gradient launch over `count` cells of the tau_g list takes the
+// whole mesh in its own order (cells outside the key range skipped)
+bool grad_whole_mesh(const DevMesh& m, int64_t count);
 hipError_t launch_cell_gather(hipStream_t s, DevMesh& m, const ListRanges& r, int tau_s,
                               int tau_upd, double dt_min, int precision,
                               bool dt_min_on_device = false);

@@ -191,7 +191,8 @@ __device__ inline void block_count_keys(int* cnt, bool valid, int k_mine) {
 
 // Keys of one classification, one item per thread, with the partition
 // counts of each block of kPartChunk (= kBlock) items: blocks [0, nbf) take
-// the faces (tau_f, or (colour, tau_f)) into fcounts[key][block]; blocks
+// the faces (tau_f, (colour, tau_f), or tau_f + 8 flocal) into
+// fcounts[key][block]; blocks
 // [nbf, nbf + nbc) the cells: tau_g and the packed face word, the
 // (tau_g, tau) histogram, and, unless the gather's list is built too
 // (count_cells = 0; k_cell_list_keys then counts both cell keys), the tau_g
@@ -199,6 +200,7 @@ __device__ inline void block_count_keys(int* cnt, bool valid, int k_mine) {
 __global__ __launch_bounds__(kBlock) void k_keys(int nf, int nbf, const int* __restrict__ fhL,
                                                  const int* __restrict__ fhR,
                                                  const int8_t* __restrict__ fcol, int use_colour,
+                                                 const int8_t* __restrict__ flocal,
                                                  int Kf, int8_t* __restrict__ fkey,
                                                  int* __restrict__ fcounts, int nc, int nbc,
                                                  const int* __restrict__ nb,
@@ -217,6 +219,7 @@ __global__ __launch_bounds__(kBlock) void k_keys(int nf, int nbf, const int* __r
     int key = -1;
     if (valid) {
       key = face_key_item(f, fhL, fhR, fcol, lev, use_colour);
+      if (flocal) key += kMaxLevels * flocal[f];
       fkey[f] = (int8_t)key;
     }
     block_count_keys(cnt, valid, key);
@@ -334,9 +337,12 @@ __device__ inline void wave_scatter_keys(int* base, bool valid, int k_mine, int 
 }
 
 // One block per key row (blocks [0, Kf) the face partition's rows, the rest
-// the cell partition's): the exclusive scan of the row's counts, each thread
-// summing a run of consecutive blocks, and the row total.
+// the cell partition's): the exclusive scan of the row's counts and the row
+// total.  The row goes through LDS in tiles (coalesced loads and stores);
+// in a tile each thread sums a run of consecutive entries, the threads'
+// sums are scanned across the block, and the runs are rewritten in place.
 constexpr int kScanThreads = 1024;
+constexpr int kScanTile = 8192;
 __global__ __launch_bounds__(kScanThreads) void k_part_scan(int Kf, int nbf,
                                                             const int* __restrict__ fcounts,
                                                             int* __restrict__ foffs,
@@ -344,41 +350,55 @@ __global__ __launch_bounds__(kScanThreads) void k_part_scan(int Kf, int nbf,
                                                             const int* __restrict__ ccounts,
                                                             int* __restrict__ coffs,
                                                             int* __restrict__ ctot) {
+  __shared__ int tile[kScanTile];
   __shared__ int wsum[kScanThreads / 64];
+  __shared__ int tile_end;
   const bool face = (int)blockIdx.x < Kf;
   const int k = face ? blockIdx.x : blockIdx.x - Kf;
   const int nb = face ? nbf : nbc;
   const int* in = (face ? fcounts : ccounts) + (size_t)k * nb;
   int* out = (face ? foffs : coffs) + (size_t)k * nb;
   const int t = threadIdx.x, lane = t & 63, w = t >> 6;
-  const int per = (nb + kScanThreads - 1) / kScanThreads;
-  const int b0 = min(t * per, nb), b1 = min(b0 + per, nb);
-  int sum = 0;
-  for (int b = b0; b < b1; ++b) sum += in[b];
-  // exclusive scan of the thread sums: within the wave, then over the waves
-  int inc = sum;
-  for (int off = 1; off < 64; off <<= 1) {
-    int y = __shfl_up(inc, off, 64);
-    if (lane >= off) inc += y;
-  }
-  if (lane == 63) wsum[w] = inc;
-  __syncthreads();
-  if (w == 0) {
-    int x = lane < kScanThreads / 64 ? wsum[lane] : 0, xi = x;
+  int carry = 0;
+  for (int t0 = 0; t0 < nb; t0 += kScanTile) {
+    const int n = min(kScanTile, nb - t0);
+    for (int j = t; j < n; j += kScanThreads) tile[j] = in[t0 + j];
+    __syncthreads();
+    const int per = (n + kScanThreads - 1) / kScanThreads;
+    const int b0 = min(t * per, n), b1 = min(b0 + per, n);
+    int sum = 0;
+    for (int b = b0; b < b1; ++b) sum += tile[b];
+    // exclusive scan of the thread sums: within the wave, then over the waves
+    int inc = sum;
     for (int off = 1; off < 64; off <<= 1) {
-      int y = __shfl_up(xi, off, 64);
-      if (lane >= off) xi += y;
+      int y = __shfl_up(inc, off, 64);
+      if (lane >= off) inc += y;
     }
-    if (lane < kScanThreads / 64) wsum[lane] = xi - x;  // exclusive over the waves
-    if (lane == kScanThreads / 64 - 1) (face ? ftot : ctot)[k] = xi;
+    if (lane == 63) wsum[w] = inc;
+    __syncthreads();
+    if (w == 0) {
+      int x = lane < kScanThreads / 64 ? wsum[lane] : 0, xi = x;
+      for (int off = 1; off < 64; off <<= 1) {
+        int y = __shfl_up(xi, off, 64);
+        if (lane >= off) xi += y;
+      }
+      if (lane < kScanThreads / 64) wsum[lane] = xi - x;  // exclusive over the waves
+    }
+    __syncthreads();
+    int run = carry + wsum[w] + inc - sum;
+    for (int b = b0; b < b1; ++b) {
+      const int c = tile[b];
+      tile[b] = run;
+      run += c;
+    }
+    // the running total after this tile: the last thread's run end
+    if (t == kScanThreads - 1) tile_end = run;
+    __syncthreads();
+    for (int j = t; j < n; j += kScanThreads) out[t0 + j] = tile[j];
+    carry = tile_end;
+    __syncthreads();
   }
-  __syncthreads();
-  int run = wsum[w] + inc - sum;
-  for (int b = b0; b < b1; ++b) {
-    const int c = in[b];
-    out[b] = run;
-    run += c;
-  }
+  if (t == 0) (face ? ftot : ctot)[k] = carry;
 }
 
 // base[k] <- the first slot of key k: the row totals of the keys before it
@@ -459,6 +479,81 @@ __global__ __launch_bounds__(kBlock) void k_grad(GradArgs<T> a) {
   grad_compute<T>(a, ic, in, sStage[threadIdx.x >> 6], g);
 }
 
+// Gradient and the fluxes of the chunk's own faces in one launch (gather
+// mode, whole-mesh launches over the mesh order, forward Euler level steps).
+// Block b takes cells [256 b, 256 b + 256) (a chunk), stages their face
+// values in LDS as k_grad does, and stores to the face-value array only the
+// half-faces whose other cell lies outside the chunk; after a barrier it
+// computes the active faces with both sides in the chunk (and its boundary
+// faces) from the staged values and stores their fluxes.  Their face values
+// never leave the chip, and the flux kernel is left with the faces between
+// chunks.  FEAT = 2: the learned guess, the network evaluated once per wave
+// and pass over the chunk's faces as in k_flux_feat.  The face values,
+// fluxes and counters are those of k_grad followed by the flux kernel, bit
+// for bit.
+template <typename T, bool G14, int FEAT>
+__global__ __launch_bounds__(kBlock) void k_grad_flux(GradArgs<T> g, FluxArgs<T> f,
+                                                      LocalFaces lf,
+                                                      const uint32_t* __restrict__ fpack,
+                                                      int tau_s) {
+  __shared__ T sStage[kBlock / 64][kStageVals];
+  __shared__ __attribute__((aligned(16))) uint16_t sNet[FEAT ? (kBlock / 64) * kMlpFwdLds : 8];
+  const int chunk = xcd_block();
+  const int idx = chunk * kBlock + threadIdx.x;
+  // every wave reaches the barrier below: a lane past the end or outside the
+  // key range computes its copy of a cell and stores nothing
+  const int ic = idx < g.count ? idx : g.count - 1;
+  const GradIn<T> gi = grad_load<T>(g, ic);
+  const bool in = idx < g.count && g.key[idx] <= g.key_max;
+  unsigned outside = 0;  // slots whose neighbour lies in another chunk
+  for (int m = 0; m < 4; ++m)
+    outside |= (unsigned)(gi.nb[m] >= 0 && gi.nb[m] / kBlock != chunk) << m;
+  if (__ballot(in) != 0ull) grad_compute<T>(g, ic, in, sStage[threadIdx.x >> 6], gi, outside);
+  __syncthreads();
+  // an active face has both cells in range (tau_g <= tau_f <= tau_s), so
+  // both staged values are its face values
+  SolveInfo info{0, 0, 0, 0, 0, 0, 0, 0};
+  double i0 = 0, i1 = 0, i2 = 0;
+  const double dt_min = flux_dt_min(f);
+  const int q0 = lf.start[chunk], q1 = lf.start[chunk + 1];
+  // the block's passes over its faces: the same count for every wave (the
+  // network pass needs whole waves)
+  for (int base = q0; base < q1; base += kBlock) {
+    const int q = base + threadIdx.x;
+    bool valid = q < q1;
+    int2 e = make_int2(0, 0);
+    int tf = 0;
+    if (valid) {
+      e = lf.face[q];
+      // (the packed word of the face's first cell: its tau_f per face slot)
+      tf = (int)((fpack[chunk * kBlock + (e.y & 255)] >> (4 * ((e.y >> 8) & 3))) & 15u);
+      valid = tf <= tau_s;
+    }
+    if (FEAT == 0 && !valid) continue;
+    const int lL = e.y & 255, sL = (e.y >> 8) & 3, lR = (e.y >> 10) & 255, sR = (e.y >> 18) & 3;
+    const bool bnd = (e.y >> 20) & 1;
+    T wl[5] = {1, 0, 0, 0, 1}, wr[5] = {1, 0, 0, 0, 1};
+    if (valid) {
+      const T* pl = &sStage[lL >> 6][sL * 320 + 5 * (lL & 63)];
+      const T* pr = &sStage[lR >> 6][sR * 320 + 5 * (lR & 63)];
+      for (int k = 0; k < 5; ++k) wl[k] = pl[k];
+      for (int k = 0; k < 5; ++k) wr[k] = bnd ? wl[k] : pr[k];
+    }
+    const int4 r = make_int4(e.x, 0, bnd ? -1 : 0, tf);
+    if (FEAT == 0) {
+      T phi[5];
+      SolveInfo one{0, 0, 0, 0, 0, 0, 0, 0};
+      face_flux_w<T, G14>(f, e.x, !bnd, wl, wr, phi, one);
+      add_info(info, one);
+      store_face_flux(f, r, dt_min, phi, bnd && f.s.boundary == TAFV_BC_WALL, i0, i1, i2);
+    } else {
+      flux_feat_w<T, FEAT>(f, valid, r, wl, wr, dt_min, sNet + (threadIdx.x >> 6) * kMlpFwdLds,
+                           info, i0, i1, i2);
+    }
+  }
+  flush_counters(info, i0, i1, i2, f.dcount, f.dimpulse);
+}
+
 // ---------------------------------------------------------------------------
 // face flux
 
@@ -509,8 +604,8 @@ __global__ __launch_bounds__(kBlock) void k_flux_store(FluxArgs<T> a) {
   SolveInfo info{0, 0, 0, 0, 0, 0, 0, 0};
   double i0 = 0, i1 = 0, i2 = 0;
   if (idx < a.count)
-    flux_store_item<ORDER, T, G14, MOVE>(a, nt_rec(a.rec + idx), flux_dt_min(a), info, i0, i1,
-                                         i2);
+    flux_store_item<ORDER, T, G14, MOVE>(a, nt_rec(flux_rec(a, idx)), flux_dt_min(a), info, i0,
+                                         i1, i2);
   flush_counters(info, i0, i1, i2, a.dcount, a.dimpulse);
 }
 
@@ -524,7 +619,7 @@ void k_flux_feat(FluxArgs<T> a) {
   const bool valid = idx < a.count;
   SolveInfo info{0, 0, 0, 0, 0, 0, 0, 0};
   double i0 = 0, i1 = 0, i2 = 0;
-  int4 r = valid ? nt_rec(a.rec + idx) : make_int4(0, 0, -1, 0);
+  int4 r = valid ? nt_rec(flux_rec(a, idx)) : make_int4(0, 0, -1, 0);
   flux_feat_item<ORDER, T, FEAT>(a, valid, r, flux_dt_min(a), lds + (threadIdx.x >> 6) * kMlpFwdLds,
                                  info, i0, i1, i2);
   flush_counters(info, i0, i1, i2, a.dcount, a.dimpulse);
@@ -707,11 +802,12 @@ hipError_t launch_partitions(hipStream_t s, DevMesh& m, int early_order) {
   static_assert(kMaxLevels + kCellKeys <= kMaxKeys, "the two cell lists share one scan");
   static_assert(kPartChunk == kBlock, "the key kernels count one block of items each");
   const int use_colour = m.scatter == TAFV_SCATTER_COLOUR;
-  const int Kf = use_colour ? m.ncolours * kMaxLevels : kMaxLevels;
+  const int Kf = face_list_keys(m);
   const int Kc = early_order ? kMaxLevels + kCellKeys : kMaxLevels;
   const int nbf = partition_blocks(m.nf), nbc = partition_blocks(m.nc);
   hipLaunchKernelGGL(k_keys, dim3(nbf + nbc), dim3(kBlock), 0, s, m.nf, nbf, m.fhL, m.fhR,
-                     m.fcol, use_colour, Kf, m.fkey, m.pf.counts, m.nc, nbc, m.nb_, m.lev,
+                     m.fcol, use_colour, m.split_local ? m.flocal : nullptr, Kf, m.fkey,
+                     m.pf.counts, m.nc, nbc, m.nb_, m.lev,
                      m.ckey, m.fpack, m.chist, early_order ? 0 : 1, m.pc.counts);
   if (early_order)
     hipLaunchKernelGGL(k_cell_list_keys, dim3(nbc), dim3(kBlock), 0, s, m.nc, nbc, m.nb_, m.lev,
@@ -782,6 +878,7 @@ hipError_t launch_from_caller_i8(hipStream_t s, DevMesh& m, const int8_t* src, i
 // then close in time, and their states and shared face fluxes are still in
 // L2 when read again.
 static bool whole_mesh(int64_t count, int64_t nc) { return count * 100 >= kWholeMeshPct * nc; }
+bool grad_whole_mesh(const DevMesh& m, int64_t count) { return whole_mesh(count, m.nc); }
 
 hipError_t launch_grad(hipStream_t s, DevMesh& m, const StepArgs& a, CellRange r, int tau_g,
                        const double* U) {
@@ -803,6 +900,46 @@ hipError_t launch_grad(hipStream_t s, DevMesh& m, const StepArgs& a, CellRange r
                        (double*)m.Wf, a.gas.gm1, a.boundary, m.moving ? m.sF : nullptr,
                        r.n1, r.off2, m.ckey, tau_g};
     hipLaunchKernelGGL(k_grad<double>, dim3(blocks_for(count)), dim3(kBlock), 0, s, g);
+  }
+  return hipGetLastError();
+}
+
+template <typename T>
+static void grad_flux_launch(hipStream_t s, const DevMesh& m, const GradArgs<T>& g,
+                             const FluxArgs<T>& f, int feat, bool is14, int tau_s) {
+  const LocalFaces lf{m.lf_start, m.lf_face};
+  const dim3 grid(blocks_for(m.nc)), block(kBlock);
+  if (feat == 2)
+    hipLaunchKernelGGL((k_grad_flux<T, true, 2>), grid, block, 0, s, g, f, lf, m.fpack, tau_s);
+  else if (is14)
+    hipLaunchKernelGGL((k_grad_flux<T, true, 0>), grid, block, 0, s, g, f, lf, m.fpack, tau_s);
+  else
+    hipLaunchKernelGGL((k_grad_flux<T, false, 0>), grid, block, 0, s, g, f, lf, m.fpack, tau_s);
+}
+
+hipError_t launch_grad_flux(hipStream_t s, DevMesh& m, const StepArgs& a, int tau_s,
+                            const FluxFeatures& ft, bool dt_min_on_device) {
+  static_assert(kFuseChunk == kBlock, "a chunk is one block of cells");
+  if (m.nc <= 0) return hipSuccess;
+  // the learned guess alone (FEAT 2, gamma 1.4), or no features
+  if (ft.feat != 0 && (ft.feat != 2 || !a.gas.is14)) return hipErrorInvalidValue;
+  const unsigned long long* dtd = dt_min_on_device ? m.dscal : nullptr;
+  if (a.precision == TAFV_FP32_FLUX) {
+    GradArgs<float> g{nullptr, m.nc, m.nc, m.nf, m.U, m.nb_, m.grc32, m.fA, (float*)m.Wf,
+                      a.gas.gm1, a.boundary, nullptr, 0, 0, m.ckey, tau_s};
+    FluxArgs<float> f{m.frec, 0, m.nf, m.nc, m.fA32, m.U, (const float*)m.Wf, m.R, (float*)m.Q,
+                      m.dcount, m.dimpulse, a, ft.mlp, ft.log_rows, ft.log_count, ft.log_cap,
+                      ft.log_rate, ft.log_seed, ft.subit, ft.guess_gate, ft.guess_strength,
+                      0, nullptr, nullptr, dtd};
+    grad_flux_launch<float>(s, m, g, f, ft.feat, a.gas.is14, tau_s);
+  } else {
+    GradArgs<double> g{nullptr, m.nc, m.nc, m.nf, m.U, m.nb_, m.grc, m.fA, (double*)m.Wf,
+                       a.gas.gm1, a.boundary, nullptr, 0, 0, m.ckey, tau_s};
+    FluxArgs<double> f{m.frec, 0, m.nf, m.nc, m.fA, m.U, (const double*)m.Wf, m.R, (double*)m.Q,
+                       m.dcount, m.dimpulse, a, ft.mlp, ft.log_rows, ft.log_count, ft.log_cap,
+                       ft.log_rate, ft.log_seed, ft.subit, ft.guess_gate, ft.guess_strength,
+                       0, nullptr, nullptr, dtd};
+    grad_flux_launch<double>(s, m, g, f, ft.feat, a.gas.is14, tau_s);
   }
   return hipGetLastError();
 }
@@ -842,8 +979,15 @@ static void flux_feat_launch(hipStream_t s, int order, int feat, int count, cons
 
 hipError_t launch_flux(hipStream_t s, DevMesh& m, const StepArgs& a, int first, int count,
                        const FluxFeatures& ft, const double* U, void* Q, int pass_mode,
-                       const void* Qpred, bool dt_min_on_device) {
-  if (count <= 0) return hipSuccess;
+                       const void* Qpred, bool dt_min_on_device, int first2, int count2) {
+  if (count <= 0) {  // the second range alone
+    first = first2;
+    count = count2;
+    count2 = 0;
+  }
+  if (count + count2 <= 0) return hipSuccess;
+  const int n1 = count, off2 = first2 - first;
+  count += count2;
   const int4* rec = m.frec + first;
   if (!U) U = m.U;
   if (!Q) Q = m.Q;
@@ -852,7 +996,7 @@ hipError_t launch_flux(hipStream_t s, DevMesh& m, const StepArgs& a, int first, 
                       m.dimpulse, a, ft.mlp, ft.log_rows, ft.log_count, ft.log_cap,
                       ft.log_rate, ft.log_seed, ft.subit, ft.guess_gate, ft.guess_strength,
                       pass_mode, (const float*)Qpred, m.moving ? m.sF : nullptr,
-                      dt_min_on_device ? m.dscal : nullptr};
+                      dt_min_on_device ? m.dscal : nullptr, n1, off2};
     if (ft.feat && a.gas.is14 && m.scatter == TAFV_SCATTER_GATHER && !m.moving)
       flux_feat_launch<float>(s, a.order, ft.feat, count, f);
     else if (a.gas.is14) flux_launch<float, true>(s, a.order, m.scatter, count, f);
@@ -862,7 +1006,7 @@ hipError_t launch_flux(hipStream_t s, DevMesh& m, const StepArgs& a, int first, 
                        m.dcount, m.dimpulse, a, ft.mlp, ft.log_rows, ft.log_count, ft.log_cap,
                        ft.log_rate, ft.log_seed, ft.subit, ft.guess_gate, ft.guess_strength,
                        pass_mode, (const double*)Qpred, m.moving ? m.sF : nullptr,
-                       dt_min_on_device ? m.dscal : nullptr};
+                       dt_min_on_device ? m.dscal : nullptr, n1, off2};
     if (ft.feat && a.gas.is14 && m.scatter == TAFV_SCATTER_GATHER && !m.moving)
       flux_feat_launch<double>(s, a.order, ft.feat, count, f);
     else if (a.gas.is14) flux_launch<double, true>(s, a.order, m.scatter, count, f);

@@ -268,7 +268,9 @@ template <typename T>
 struct FaceValueWriter {
   T* st;  // this wave's staging area, [slot][lane][variable]
   int mine;
-  __device__ FaceValueWriter(T* stage, int i, bool valid) : st(stage), mine(valid ? i : -1) {}
+  unsigned slots;  // the slots of this lane's cell that are stored (bit m: slot m)
+  __device__ FaceValueWriter(T* stage, int i, bool valid, unsigned store_slots = 0xfu)
+      : st(stage), mine(valid ? i : -1), slots(store_slots) {}
   __device__ void put(int m, int k, T v) { st[m * 320 + 5 * (threadIdx.x & 63) + k] = v; }
   __device__ void flush(T* __restrict__ Wf, int nc) {
     const int lane = threadIdx.x & 63;
@@ -278,11 +280,13 @@ struct FaceValueWriter {
     for (int j = 0; j < 5; ++j) {
       const int d = 64 * j + lane, src = d / 5, kk = d - 5 * src;
       const int cell = __shfl(mine, src, 64);
+      const unsigned sl = (unsigned)__shfl((int)slots, src, 64);
       if (cell < 0) continue;
       // non-temporal: the face values are read once, by the next kernel;
       // kept out of the way of the neighbour states in L2
       for (int m = 0; m < 4; ++m)
-        __builtin_nontemporal_store(st[m * 320 + d], &Wf[((size_t)m * nc + cell) * 5 + kk]);
+        if ((sl >> m) & 1u)
+          __builtin_nontemporal_store(st[m * 320 + d], &Wf[((size_t)m * nc + cell) * 5 + kk]);
     }
   }
 };
@@ -341,11 +345,13 @@ __device__ inline GradIn<T> grad_load(const GradArgs<T>& a, int i) {
   return g;
 }
 
+// store_slots: the slots whose face values are stored (the others stay in
+// the stage only)
 template <typename T>
 __device__ inline void grad_compute(const GradArgs<T>& a, int i, bool valid, T* stage,
-                                    const GradIn<T>& g) {
+                                    const GradIn<T>& g, unsigned store_slots = 0xfu) {
   const int nc = a.nc;
-  FaceValueWriter<T> out(stage, i, valid);
+  FaceValueWriter<T> out(stage, i, valid, store_slots);
   const int* nb = g.nb;
   const double* ui = g.ui;
   double un[4][5];
@@ -440,7 +446,15 @@ struct FluxArgs {
   // when set, dt_min is read here on the device (its bit pattern) instead of
   // from s.dt_min: a launch enqueued before the host knows dt_min
   const unsigned long long* dtmin_dev = nullptr;
+  // the launch's items: rec[idx] for idx < n1, then rec[off2 + idx - n1]
+  // (two ranges of the face list)
+  int n1 = 0x7fffffff, off2 = 0;
 };
+
+template <typename T>
+__device__ inline const int4* flux_rec(const FluxArgs<T>& a, int idx) {
+  return a.rec + (idx < a.n1 ? idx : a.off2 + (idx - a.n1));
+}
 
 template <typename T>
 __device__ inline double flux_dt_min(const FluxArgs<T>& a) {
@@ -520,15 +534,14 @@ __device__ inline void add_info(SolveInfo& a, const SolveInfo& b) {
 // the flux through the moving face is |A| (F(W) . n - xi U(W)): the
 // convective terms take the relative normal velocity, the pressure work the
 // absolute one (+ |A| p xi in the energy flux).
-template <int ORDER, typename T, bool G14, bool MOVE = false>
-__device__ inline void face_flux(const FluxArgs<T>& a, int4 r, T* phi, SolveInfo& info) {
+// The flux of face f from its two reconstructed states (interior = false: a
+// boundary face, wr unused).
+template <typename T, bool G14, bool MOVE = false>
+__device__ inline void face_flux_w(const FluxArgs<T>& a, int f, bool interior, const T* wl,
+                                   const T* wr, T* phi, SolveInfo& info) {
   const Gas& G = a.s.gas;
-  const int f = r.x, hL = r.y, hR = r.z;
   T ax = nt_load(a.fA + f), ay = nt_load(a.fA + a.nf + f);
   T az = nt_load(a.fA + 2 * (size_t)a.nf + f);
-  T wl[5], wr[5];
-  load_side<ORDER, T>(a, hL, wl);
-  if (hR >= 0) load_side<ORDER, T>(a, hR, wr);
   T a2 = ax * ax + ay * ay + az * az;
   T ia = frsq(a2);
   T am = a2 * ia;
@@ -539,7 +552,7 @@ __device__ inline void face_flux(const FluxArgs<T>& a, int4 r, T* phi, SolveInfo
     xi = (T)a.sF[f] * ia;
     unl -= xi;
   }
-  if (hR < 0 && a.s.boundary != TAFV_BC_WALL) {  // transmissive: F(W_L)
+  if (!interior && a.s.boundary != TAFV_BC_WALL) {  // transmissive: F(W_L)
     T E = wl[4] * (T)(1.0 / G.gm1) + (T)0.5 * wl[0] * (wl[1] * wl[1] + wl[2] * wl[2] + wl[3] * wl[3]);
     phi[0] = am * wl[0] * unl;
     phi[1] = am * (wl[0] * unl * wl[1] + wl[4] * nx);
@@ -549,7 +562,7 @@ __device__ inline void face_flux(const FluxArgs<T>& a, int4 r, T* phi, SolveInfo
     if (MOVE) phi[4] += am * wl[4] * xi;
     return;
   }
-  const bool wall = hR < 0;
+  const bool wall = !interior;
   T unr = wall ? -unl : wr[1] * nx + wr[2] * ny + wr[3] * nz;
   if (MOVE && !wall) unr -= xi;
   const double rl = wl[0], pl = wl[4];
@@ -612,6 +625,16 @@ __device__ inline void face_flux(const FluxArgs<T>& a, int4 r, T* phi, SolveInfo
   phi[3] = am * (rs * us * vz + ps * nz);
   phi[4] = am * us * (E + ps);
   if (MOVE) phi[4] += am * ps * xi;
+}
+
+// |A| F(W(0)) . n for one face record (reconstructed states from the face
+// values, or the cells' states at first order)
+template <int ORDER, typename T, bool G14, bool MOVE = false>
+__device__ inline void face_flux(const FluxArgs<T>& a, int4 r, T* phi, SolveInfo& info) {
+  T wl[5], wr[5];
+  load_side<ORDER, T>(a, r.y, wl);
+  if (r.z >= 0) load_side<ORDER, T>(a, r.z, wr);
+  face_flux_w<T, G14, MOVE>(a, r.x, r.z >= 0, wl, wr, phi, info);
 }
 
 // Counters are spread over kCountSlots slots 128 bytes apart (slot = wave
@@ -721,15 +744,18 @@ __device__ inline bool strength_pregate(const Gas& G, const T* wl, const T* wr, 
   return du * du >= d * d * ((float)G.g * pm / rm);
 }
 
-template <int ORDER, typename T, int FEAT>
-__device__ inline void flux_feat_item(const FluxArgs<T>& a, bool valid, int4 r, double dt_min,
-                                      uint16_t* wave_lds, SolveInfo& acc, double& i0,
-                                      double& i1, double& i2) {
+// The gather-mode flux with the optional features, as described above, from
+// the face's two reconstructed states wl and wr (wr unused on a boundary
+// face, r.z < 0); r.x the face, r.w its tau_f.  All 64 lanes of a wave call
+// it together; invalid lanes pass any finite states.
+template <typename T, int FEAT>
+__device__ inline void flux_feat_w(const FluxArgs<T>& a, bool valid, int4 r, const T* wl,
+                                   const T* wr, double dt_min, uint16_t* wave_lds,
+                                   SolveInfo& acc, double& i0, double& i1, double& i2) {
   const Gas& G = a.s.gas;
   SolveInfo info{0, 0, 0, 0, 0, 0, 0, 0};
-  // 1. the face's states and normal and the strength pre-gate: all that is
-  // kept across the wave's network pass
-  T wl[5] = {1, 0, 0, 0, 1}, wr[5] = {1, 0, 0, 0, 1};
+  // 1. the face's normal and the strength pre-gate: with the states, all
+  // that is kept across the wave's network pass
   T am = 1, nx = 1, ny = 0, nz = 0, unl = 0, unr = 0;
   bool wall = false, transmit = false, net = false;
   float x[kMlpIn] = {0, 0, 0, 0, 0, 0};
@@ -737,10 +763,8 @@ __device__ inline void flux_feat_item(const FluxArgs<T>& a, bool valid, int4 r, 
     const int f = r.x;
     T ax = nt_load(a.fA + f), ay = nt_load(a.fA + a.nf + f);
     T az = nt_load(a.fA + 2 * (size_t)a.nf + f);
-    load_side<ORDER, T>(a, r.y, wl);
     wall = r.z < 0 && a.s.boundary == TAFV_BC_WALL;
     transmit = r.z < 0 && !wall;
-    if (r.z >= 0) load_side<ORDER, T>(a, r.z, wr);
     T a2 = ax * ax + ay * ay + az * az;
     T ia = frsq(a2);
     am = a2 * ia;
@@ -859,6 +883,20 @@ __device__ inline void flux_feat_item(const FluxArgs<T>& a, bool valid, int4 r, 
     store_face_flux(a, r, dt_min, phi, wall, i0, i1, i2);
   }
   add_info(acc, info);
+}
+
+// One face record: the two face values (or cell states at first order)
+// from memory, then flux_feat_w.
+template <int ORDER, typename T, int FEAT>
+__device__ inline void flux_feat_item(const FluxArgs<T>& a, bool valid, int4 r, double dt_min,
+                                      uint16_t* wave_lds, SolveInfo& acc, double& i0,
+                                      double& i1, double& i2) {
+  T wl[5] = {1, 0, 0, 0, 1}, wr[5] = {1, 0, 0, 0, 1};
+  if (valid) {
+    load_side<ORDER, T>(a, r.y, wl);
+    if (r.z >= 0) load_side<ORDER, T>(a, r.z, wr);
+  }
+  flux_feat_w<T, FEAT>(a, valid, r, wl, wr, dt_min, wave_lds, acc, i0, i1, i2);
 }
 
 // Adds s_m q_m to acc for the faces m of a cell whose bit is set in act

@@ -98,6 +98,17 @@ struct DevMesh {
   double* D = nullptr;     // [nc][5] predicted change of each cell's current step
   double* Ut = nullptr;    // [nc][5] cell states at the time the next face pass reads
   int4* frec = nullptr;    // [nf] face records {f, hL, hR, tau_f} in partition order
+  // gather mode, second order: faces whose fluxes the whole-mesh gradient
+  // launch computes (both sides, or the one side of a boundary face, in one
+  // chunk of kFuseChunk cells): flocal[f] = 1 for them, and per chunk their
+  // list (see LocalFaces).  While split_local is set (chosen at each
+  // classification: the fused launches can run), the face list is sorted by
+  // tau_f + 8 flocal, the faces between chunks first.
+  int8_t* flocal = nullptr;  // [nf]
+  int32_t* lf_start = nullptr;  // [chunks + 1]
+  int2* lf_face = nullptr;      // [n_local]
+  int32_t n_local = 0;
+  bool split_local = false;
   // schedule lists
   Partition pf, pc, pg;    // faces by (colour, tau_f); cells by tau_g; the gather's
                            // cell list (see cells_gather)
@@ -257,7 +268,7 @@ tafv_status read_slot_counters(tafv_ctx* c, DevMesh& m, tafv_stats* st);
 
 // per-kernel-class timing with HIP events on the context stream
 enum { P_CLASSIFY = 0, P_GRAD = 1, P_FLUX = 2, P_UPDATE = 3, P_GATHER = 4, P_PREDICT = 5,
-       P_FLUX_CORR = 6, P_N = 7 };
+       P_FLUX_CORR = 6, P_GRAD_FLUX = 7, P_N = 8 };
 struct ProfScope {
   tafv_ctx* c;
   int cls;

@@ -325,3 +325,72 @@ def test_full_scale_whole_run(T, full_oracle):
             e_E = l1_rel(cons[:, 4], full_oracle["cons"][:, 4], vol)
             say(f"full run FP32 form: L1 rho {e_rho:.2e}, L1 E {e_E:.2e}")
             assert e_rho <= 1e-5 and e_E <= 1e-5
+
+
+@pytest.mark.parametrize("precision,boundary,cell_order", [(0, 0, 0), (1, 0, 0), (0, 1, 1)],
+                         ids=["fp64-walls", "fp32-walls", "fp64-transmissive-morton"])
+def test_fused_local_faces_bit_identical(T, precision, boundary, cell_order):
+    """Second order in gather mode: whole-mesh gradient launches also compute
+    the faces local to a chunk of 256 cells (k_grad_flux) and leave the
+    others to the flux kernel.  Against fuse_faces = 0 (every face through
+    k_flux_store) and against face statistics on (every face through the
+    feature flux kernel), the runs give the same bits."""
+    nodes, tets = I.graded_box_mesh(17, 13, 11, 8.0)
+    prim = I.blast_state(nodes, tets, centre=I.blast_centre(6))
+    out = {}
+    for name, kw in (("fused", dict(fuse_faces=1)), ("unfused", dict(fuse_faces=0)),
+                     ("stats", dict(guess_stats=1))):
+        s = T.Solver(max_levels=5, order=2, precision=precision, boundary=boundary,
+                     cell_order=cell_order, **kw)
+        s.upload(nodes, tets)
+        s.init(prim)
+        for n in (1, 6, 9, 16):
+            s.advance(n)
+        out[name] = (s.checkpoint(), s.stats())
+        s.close()
+    a, sa = out["fused"]
+    for other in ("unfused", "stats"):
+        b, sb = out[other]
+        for key in ("levels", "cons", "accum"):
+            diff = a[key] != b[key]
+            ne = np.flatnonzero(diff.any(axis=1) if diff.ndim > 1 else diff)
+            say(f"fused vs {other}: {key} differs in {ne.size} of {len(a[key])} cells")
+            assert ne.size == 0, (other, key, ne[:8])
+        for key in ("cell_updates", "face_solves", "newton_updates", "newton_fallbacks"):
+            assert sa[key] == sb[key], (other, key)
+    say(f"fused, unfused and feature face passes: identical bits, "
+        f"{sa['face_solves']} face solves")
+
+
+@pytest.mark.parametrize("precision", [0, 1], ids=["fp64", "fp32"])
+def test_fused_local_faces_learned_guess(T, precision):
+    """The learned guess in the fused launches (the network evaluated per
+    wave and pass over a chunk's faces) against every face through the
+    feature flux kernel: the same bits and the same network counters.  A
+    random network with gate 0 starts Newton from its guess on every face
+    where the two-rarefaction value is inexact."""
+    nodes, tets = I.graded_box_mesh(17, 13, 11, 8.0)
+    prim = I.blast_state(nodes, tets, centre=I.blast_centre(6))
+    theta = np.random.default_rng(11).normal(0.0, 0.2, T.MLP_PARAMS).astype(np.float32)
+    out = {}
+    for fuse in (1, 0):
+        s = T.Solver(max_levels=5, order=2, precision=precision, guess=T.GUESS_MLP,
+                     guess_gate=0.0, fuse_faces=fuse)
+        s.upload(nodes, tets)
+        T.tafv_mlp_set(s.ctx, theta)
+        s.init(prim)
+        for n in (1, 6, 9, 16):
+            s.advance(n)
+        out[fuse] = (s.checkpoint(), s.stats())
+        s.close()
+    (a, sa), (b, sb) = out[1], out[0]
+    for key in ("levels", "cons", "accum"):
+        diff = a[key] != b[key]
+        ne = np.flatnonzero(diff.any(axis=1) if diff.ndim > 1 else diff)
+        say(f"learned guess, fused vs unfused: {key} differs in {ne.size} of {len(a[key])} cells")
+        assert ne.size == 0, (key, ne[:8])
+    for key in ("cell_updates", "face_solves", "newton_updates", "guess_evaluated",
+                "guess_used", "guess_rejected"):
+        assert sa[key] == sb[key], (key, sa[key], sb[key])
+    assert sa["guess_used"] > 0
+    say(f"learned guess fused: identical bits, network start on {sa['guess_used']} faces")
