@@ -102,7 +102,7 @@ void free_mesh(tafv_ctx* c, DevMesh* m) {
                   m->pf.list, m->pf.counts, m->pf.start, m->pc.list, m->pc.counts,
                   m->pc.start, m->dscal, m->dcount, m->dimpulse, m->pf.offs, m->pc.offs,
                   m->pf.tot, m->pc.tot, m->Q, m->frec, m->fkey, m->ckey, m->fpack,
-                  m->perm, m->xfer, m->chist, m->rb, m->dmin, m->Q0, m->D, m->Ut,
+                  m->perm, m->xfer, m->chist, m->rb, m->dmin, m->Q0, m->D, m->Ut, m->nkey,
                   m->vol0, m->fnode, m->sF, m->Rv, m->sweepf, m->lkey, m->pg.list,
                   m->pg.counts, m->pg.start, m->pg.offs, m->pg.tot, m->flocal,
                   m->lf_start, m->lf_face};
@@ -312,7 +312,7 @@ tafv_status subiteration2(tafv_ctx* c, DevMesh& m, const StepArgs& a, int tau_s,
   }
   {
     ProfScope ps(c, P_PREDICT, m.nc);
-    HIP_TRY(c, launch_predict(c->stream, m, tau_s, (int)s, dt_min, c->prm.precision));
+    HIP_TRY(c, launch_predict(c->stream, m, tau_s, (int)s, upd, dt_min, c->prm.precision));
   }
   if (c->prm.order == 2) {
     const CellRange r = cells_active(m, upd);
@@ -627,6 +627,7 @@ tafv_status upload_host_mesh(tafv_ctx* c, const HostMesh& hm, DevMesh** out) {
                               5 * std::max<size_t>(nf, 1)));
     chk(dalloc(c, &m->D, 5 * nc));
     chk(dalloc(c, &m->Ut, 5 * nc));
+    chk(dalloc(c, &m->nkey, nc));
   }
   chk(dalloc(c, &m->fkey, nf));
   chk(dalloc(c, &m->ckey, nc));

@@ -116,11 +116,12 @@ hipError_t launch_face_speed(hipStream_t s, DevMesh& m, const double* d_vel);
 hipError_t launch_vol_to_caller(hipStream_t s, DevMesh& m, const double* src, double* dst);
 // predictor/corrector form (gather mode): predictions D of the cells whose
 // step starts (tau <= tau_s) from the predictor fluxes Q0, and the states Ut
-// of every cell at the end of subiteration `sub`; then the corrector sums
+// at the end of subiteration `sub` of the cells that the passes over the
+// faces of tau_f <= upd read (nkey <= upd); then the corrector sums
 // of the first `count` listed cells for the faces whose step ends (tau_f <=
 // tau_upd, Q holding phi0 + phi1), ending cells applied to U and Ut
-hipError_t launch_predict(hipStream_t s, DevMesh& m, int tau_s, int sub, double dt_min,
-                          int precision);
+hipError_t launch_predict(hipStream_t s, DevMesh& m, int tau_s, int sub, int upd,
+                          double dt_min, int precision);
 hipError_t launch_cell_gather2(hipStream_t s, DevMesh& m, CellRange r, int tau_upd,
                                double dt_min, int precision);
 constexpr int kCellKeys = 2 * kMaxLevels;  // keys of the gather's cell list

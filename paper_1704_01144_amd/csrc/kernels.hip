@@ -678,7 +678,8 @@ __global__ void k_face_speed(int nf, const int* __restrict__ fnode, const double
 }
 
 // predictor/corrector form: predictions of the starting cells and the
-// states of every cell at the end of the subiteration
+// states at the end of the subiteration of the cells the next face passes
+// read (nkey <= upd)
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_predict(int nc, const uint32_t* __restrict__ fpack,
                                                     const int* __restrict__ c2f,
@@ -686,10 +687,26 @@ __global__ __launch_bounds__(kBlock) void k_predict(int nc, const uint32_t* __re
                                                     const double* __restrict__ vol,
                                                     const double* __restrict__ U,
                                                     double* __restrict__ D,
-                                                    double* __restrict__ Ut, int tau_s, int s) {
+                                                    double* __restrict__ Ut, int tau_s, int s,
+                                                    const int8_t* __restrict__ nkey, int upd) {
   int i = xcd_block() * kBlock + threadIdx.x;
   if (i >= nc) return;
-  predict_item<T>(i, nc, fpack, c2f, Q0, dt_min, vol, U, D, Ut, tau_s, s);
+  predict_item<T>(i, nc, fpack, c2f, Q0, dt_min, vol, U, D, Ut, tau_s, s, nkey, upd);
+}
+
+// predictor/corrector form: nkey = the smallest tau_g (ckey) over the cell
+// and its face neighbours
+__global__ __launch_bounds__(kBlock) void k_ring_keys(int nc, const int* __restrict__ nb,
+                                                      const int8_t* __restrict__ ckey,
+                                                      int8_t* __restrict__ nkey) {
+  const int i = xcd_block() * kBlock + threadIdx.x;
+  if (i >= nc) return;
+  int n[4];
+  for (int m = 0; m < 4; ++m) n[m] = nb[(size_t)m * nc + i];
+  int k = ckey[i];
+  for (int m = 0; m < 4; ++m)
+    if (n[m] >= 0) k = min(k, (int)ckey[n[m]]);
+  nkey[i] = (int8_t)k;
 }
 
 // predictor/corrector form: corrector sums of the listed cells
@@ -812,6 +829,9 @@ hipError_t launch_partitions(hipStream_t s, DevMesh& m, int early_order) {
   if (early_order)
     hipLaunchKernelGGL(k_cell_list_keys, dim3(nbc), dim3(kBlock), 0, s, m.nc, nbc, m.nb_, m.lev,
                        m.ckey, m.fpack, m.lkey, early_order, m.pc.counts);
+  if (m.nkey)
+    hipLaunchKernelGGL(k_ring_keys, dim3(blocks_for(m.nc)), dim3(kBlock), 0, s, m.nc, m.nb_,
+                       m.ckey, m.nkey);
   hipLaunchKernelGGL(k_part_scan, dim3(Kf + Kc), dim3(kScanThreads), 0, s, Kf, nbf, m.pf.counts,
                      m.pf.offs, m.pf.tot, nbc, m.pc.counts, m.pc.offs, m.pc.tot);
   const Readback none{nullptr, nullptr, 0, nullptr, nullptr, nullptr, nullptr};
@@ -1049,17 +1069,18 @@ hipError_t launch_cell_gather(hipStream_t s, DevMesh& m, const ListRanges& r, in
   return hipGetLastError();
 }
 
-hipError_t launch_predict(hipStream_t s, DevMesh& m, int tau_s, int sub, double dt_min,
-                          int precision) {
+hipError_t launch_predict(hipStream_t s, DevMesh& m, int tau_s, int sub, int upd,
+                          double dt_min, int precision) {
   if (m.nc <= 0) return hipSuccess;
+  if (!m.nkey) return hipErrorInvalidValue;
   if (precision == TAFV_FP32_FLUX)
     hipLaunchKernelGGL(k_predict<float>, dim3(blocks_for(m.nc)), dim3(kBlock), 0, s, m.nc,
                        m.fpack, m.c2f, (const float*)m.Q0, dt_min, m.vol, m.U, m.D, m.Ut,
-                       tau_s, sub);
+                       tau_s, sub, m.nkey, upd);
   else
     hipLaunchKernelGGL(k_predict<double>, dim3(blocks_for(m.nc)), dim3(kBlock), 0, s, m.nc,
                        m.fpack, m.c2f, (const double*)m.Q0, dt_min, m.vol, m.U, m.D, m.Ut,
-                       tau_s, sub);
+                       tau_s, sub, m.nkey, upd);
   return hipGetLastError();
 }
 

@@ -1037,9 +1037,17 @@ __device__ inline void predict_item(int i, int nc, const uint32_t* __restrict__ 
                                     const int* __restrict__ c2f, const T* __restrict__ Q0,
                                     double dt_min, const double* __restrict__ vol,
                                     const double* __restrict__ U, double* __restrict__ D,
-                                    double* __restrict__ Ut, int tau_s, int s) {
+                                    double* __restrict__ Ut, int tau_s, int s,
+                                    const int8_t* __restrict__ nkey, int upd) {
   const uint32_t pk = fpack[i];
   const int ti = (pk >> 20) & 15;
+  // the interpolated state at the subiteration's end is read by the
+  // corrector pass and the next predictor pass, both over the faces of
+  // tau_f <= upd: the cells with such a face and their neighbours (their
+  // gradient stencils), nkey <= upd.  A cell whose step does not start and
+  // that no such pass reads has nothing to write (it is written again
+  // before it is read).
+  if (ti > tau_s && nkey[i] > upd) return;
   double d[5];
   double* Di = D + 5 * (size_t)i;
   if (ti <= tau_s) {

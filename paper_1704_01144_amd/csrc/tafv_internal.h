@@ -114,6 +114,9 @@ struct DevMesh {
                            // cell list (see cells_gather)
   int8_t* fkey = nullptr;  // [nf] partition key of each face
   int8_t* ckey = nullptr;  // [nc] tau_g of each cell
+  // [nc] predictor/corrector form: the smallest tau_g over the cell and its
+  // face neighbours (which face passes read its interpolated state)
+  int8_t* nkey = nullptr;
   int8_t* lkey = nullptr;  // [nc] key of the gather's cell list (see list_cell)
   int* chist = nullptr;    // [kCounterSlots][64] cell count per (tau_g, tau), summed
                            // over the slots by the readback kernel
