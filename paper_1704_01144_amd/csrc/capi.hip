@@ -105,7 +105,7 @@ void free_mesh(tafv_ctx* c, DevMesh* m) {
                   m->perm, m->xfer, m->chist, m->rb, m->dmin, m->Q0, m->D, m->Ut, m->nkey,
                   m->vol0, m->fnode, m->sF, m->Rv, m->sweepf, m->lkey, m->pg.list,
                   m->pg.counts, m->pg.start, m->pg.offs, m->pg.tot, m->flocal,
-                  m->lf_start, m->lf_face};
+                  m->lf_start, m->lf_face, m->Wx, m->xb, m->fxL, m->fxR};
   for (void* p : ptrs) dev_free(c, p);
   delete m;
 }
@@ -391,10 +391,13 @@ tafv_status first_subiteration(tafv_ctx* c, DevMesh& m, tafv_stats* acc) {
     }
   }
   {
-    // the faces between chunks come first in the face list
-    const int n = fuse ? m.nf - m.n_local : m.nf;
-    ProfScope ps(c, P_FLUX, n);
-    HIP_TRY(c, launch_flux(c->stream, m, a, 0, n, ft, nullptr, nullptr, 0, nullptr, true));
+    // with the chunk-local faces kept apart, the faces between chunks come
+    // first in the face list (the first range); the others follow
+    const int n1 = m.split_local ? m.nf - m.n_local : m.nf;
+    const int n2 = (m.split_local && !fuse) ? m.n_local : 0;
+    ProfScope ps(c, P_FLUX, n1 + n2);
+    HIP_TRY(c, launch_flux(c->stream, m, a, 0, n1, ft, nullptr, nullptr, 0, nullptr, true, n1,
+                           n2));
   }
   {
     ListRanges r;
@@ -689,12 +692,49 @@ tafv_status upload_host_mesh(tafv_ctx* c, const HostMesh& hm, DevMesh** out) {
       lf[fill[L / kFuseChunk]++] = make_int2((int)f, pos);
     }
     m->n_local = start[chunks];
+    // compact positions of the half-faces whose neighbour lies in another
+    // chunk, in cell order and by slot within a cell
+    std::vector<int32_t> xb(hm.nc), fxL(nf), fxR(nf);
+    int64_t nx = 0;
+    for (int64_t i = 0; i < hm.nc; ++i) {
+      xb[i] = (int32_t)nx;
+      for (int s4 = 0; s4 < 4; ++s4) {
+        const int32_t n = hm.nb[(size_t)s4 * hm.nc + i];
+        nx += (n >= 0 && n / kFuseChunk != i / kFuseChunk) ? 1 : 0;
+      }
+    }
+    // position of half-face h (cell h >> 2, slot h & 3) in the compact array
+    auto xpos = [&](int32_t h) {
+      const int32_t i = h >> 2;
+      int32_t x = xb[i];
+      for (int s4 = 0; s4 < (h & 3); ++s4) {
+        const int32_t n = hm.nb[(size_t)s4 * hm.nc + i];
+        x += (n >= 0 && n / kFuseChunk != i / kFuseChunk) ? 1 : 0;
+      }
+      return x;
+    };
+    for (size_t f = 0; f < nf; ++f) {
+      fxL[f] = loc[f] ? hm.fhL[f] : xpos(hm.fhL[f]);
+      fxR[f] = loc[f] ? hm.fhR[f] : xpos(hm.fhR[f]);
+    }
+    m->nx = nx;
     chk(dalloc(c, &m->flocal, nf));
     chk(dalloc(c, &m->lf_start, chunks + 1));
     chk(dalloc(c, &m->lf_face, std::max<size_t>(lf.size(), 1)));
+    chk(dalloc(c, &m->xb, std::max<int64_t>(hm.nc, 1)));
+    chk(dalloc(c, &m->fxL, std::max<size_t>(nf, 1)));
+    chk(dalloc(c, &m->fxR, std::max<size_t>(nf, 1)));
+    chk(dev_malloc(c, &m->Wx, (c->prm.precision == TAFV_FP32_FLUX ? sizeof(float)
+                                                                    : sizeof(double)) *
+                                  5 * (size_t)std::max<int64_t>(nx, 1)));
     chk(up(m->flocal, loc));
     chk(up(m->lf_start, start));
     if (!lf.empty()) chk(up(m->lf_face, lf));
+    if (hm.nc > 0) chk(up(m->xb, xb));
+    if (nf > 0) {
+      chk(up(m->fxL, fxL));
+      chk(up(m->fxR, fxR));
+    }
   }
   // the time-step minimum slots start at +inf (each classification sets
   // them back once it has read them)

@@ -482,8 +482,8 @@ __global__ __launch_bounds__(kBlock) void k_grad(GradArgs<T> a) {
 // Gradient and the fluxes of the chunk's own faces in one launch (gather
 // mode, whole-mesh launches over the mesh order, forward Euler level steps).
 // Block b takes cells [256 b, 256 b + 256) (a chunk), stages their face
-// values in LDS as k_grad does, and stores to the face-value array only the
-// half-faces whose other cell lies outside the chunk; after a barrier it
+// values in LDS as k_grad does, and stores only the half-faces whose other
+// cell lies outside the chunk (to the compact array); after a barrier it
 // computes the active faces with both sides in the chunk (and its boundary
 // faces) from the staged values and stores their fluxes.  Their face values
 // never leave the chip, and the flux kernel is left with the faces between
@@ -505,10 +505,9 @@ __global__ __launch_bounds__(kBlock) void k_grad_flux(GradArgs<T> g, FluxArgs<T>
   const int ic = idx < g.count ? idx : g.count - 1;
   const GradIn<T> gi = grad_load<T>(g, ic);
   const bool in = idx < g.count && g.key[idx] <= g.key_max;
-  unsigned outside = 0;  // slots whose neighbour lies in another chunk
-  for (int m = 0; m < 4; ++m)
-    outside |= (unsigned)(gi.nb[m] >= 0 && gi.nb[m] / kBlock != chunk) << m;
-  if (__ballot(in) != 0ull) grad_compute<T>(g, ic, in, sStage[threadIdx.x >> 6], gi, outside);
+  // the face values of the slots across chunks go to the compact array, the
+  // others stay in LDS
+  if (__ballot(in) != 0ull) grad_compute<T>(g, ic, in, sStage[threadIdx.x >> 6], gi, 0u);
   __syncthreads();
   // an active face has both cells in range (tau_g <= tau_f <= tau_s), so
   // both staged values are its face values
@@ -605,7 +604,7 @@ __global__ __launch_bounds__(kBlock) void k_flux_store(FluxArgs<T> a) {
   double i0 = 0, i1 = 0, i2 = 0;
   if (idx < a.count)
     flux_store_item<ORDER, T, G14, MOVE>(a, nt_rec(flux_rec(a, idx)), flux_dt_min(a), info, i0,
-                                         i1, i2);
+                                         i1, i2, flux_compact(a, idx));
   flush_counters(info, i0, i1, i2, a.dcount, a.dimpulse);
 }
 
@@ -621,7 +620,7 @@ void k_flux_feat(FluxArgs<T> a) {
   double i0 = 0, i1 = 0, i2 = 0;
   int4 r = valid ? nt_rec(flux_rec(a, idx)) : make_int4(0, 0, -1, 0);
   flux_feat_item<ORDER, T, FEAT>(a, valid, r, flux_dt_min(a), lds + (threadIdx.x >> 6) * kMlpFwdLds,
-                                 info, i0, i1, i2);
+                                 info, i0, i1, i2, flux_compact(a, idx));
   flush_counters(info, i0, i1, i2, a.dcount, a.dimpulse);
 }
 
@@ -836,7 +835,7 @@ hipError_t launch_partitions(hipStream_t s, DevMesh& m, int early_order) {
                      m.pf.offs, m.pf.tot, nbc, m.pc.counts, m.pc.offs, m.pc.tot);
   const Readback none{nullptr, nullptr, 0, nullptr, nullptr, nullptr, nullptr};
   hipLaunchKernelGGL((k_part_scatter<ByteKey, FaceWriter, IndexWriter>), dim3(nbf), dim3(64), 0,
-                     s, m.nf, ByteKey{m.fkey}, Kf, FaceWriter{m.frec, m.fhL, m.fhR}, m.pf.start,
+                     s, m.nf, ByteKey{m.fkey}, Kf, FaceWriter{m.frec, m.split_local ? m.fxL : m.fhL, m.split_local ? m.fxR : m.fhR}, m.pf.start,
                      ByteKey{nullptr}, 0, IndexWriter{nullptr}, nullptr, nbf, m.pf.offs,
                      m.pf.tot, none);
   const Readback rb{m.dscal, m.pf.start, Kf, m.pc.start, early_order ? m.pg.start : nullptr,
@@ -910,15 +909,16 @@ hipError_t launch_grad(hipStream_t s, DevMesh& m, const StepArgs& a, CellRange r
     list = nullptr;
     count = m.nc;
   }
+  const int* xb = m.split_local ? m.xb : nullptr;
   if (a.precision == TAFV_FP32_FLUX) {
     GradArgs<float> g{list, count, m.nc, m.nf, U, m.nb_, m.grc32, m.fA,
                       (float*)m.Wf, a.gas.gm1, a.boundary, m.moving ? m.sF : nullptr,
-                      r.n1, r.off2, m.ckey, tau_g};
+                      r.n1, r.off2, m.ckey, tau_g, xb ? (float*)m.Wx : nullptr, xb};
     hipLaunchKernelGGL(k_grad<float>, dim3(blocks_for(count)), dim3(kBlock), 0, s, g);
   } else {
     GradArgs<double> g{list, count, m.nc, m.nf, U, m.nb_, m.grc, m.fA,
                        (double*)m.Wf, a.gas.gm1, a.boundary, m.moving ? m.sF : nullptr,
-                       r.n1, r.off2, m.ckey, tau_g};
+                       r.n1, r.off2, m.ckey, tau_g, xb ? (double*)m.Wx : nullptr, xb};
     hipLaunchKernelGGL(k_grad<double>, dim3(blocks_for(count)), dim3(kBlock), 0, s, g);
   }
   return hipGetLastError();
@@ -939,14 +939,15 @@ static void grad_flux_launch(hipStream_t s, const DevMesh& m, const GradArgs<T>&
 
 hipError_t launch_grad_flux(hipStream_t s, DevMesh& m, const StepArgs& a, int tau_s,
                             const FluxFeatures& ft, bool dt_min_on_device) {
-  static_assert(kFuseChunk == kBlock, "a chunk is one block of cells");
+  static_assert(kFuseChunk == kBlock && kChunkCells == kBlock, "a chunk is one block of cells");
   if (m.nc <= 0) return hipSuccess;
   // the learned guess alone (FEAT 2, gamma 1.4), or no features
   if (ft.feat != 0 && (ft.feat != 2 || !a.gas.is14)) return hipErrorInvalidValue;
+  if (!m.split_local) return hipErrorInvalidValue;
   const unsigned long long* dtd = dt_min_on_device ? m.dscal : nullptr;
   if (a.precision == TAFV_FP32_FLUX) {
     GradArgs<float> g{nullptr, m.nc, m.nc, m.nf, m.U, m.nb_, m.grc32, m.fA, (float*)m.Wf,
-                      a.gas.gm1, a.boundary, nullptr, 0, 0, m.ckey, tau_s};
+                      a.gas.gm1, a.boundary, nullptr, 0, 0, m.ckey, tau_s, (float*)m.Wx, m.xb};
     FluxArgs<float> f{m.frec, 0, m.nf, m.nc, m.fA32, m.U, (const float*)m.Wf, m.R, (float*)m.Q,
                       m.dcount, m.dimpulse, a, ft.mlp, ft.log_rows, ft.log_count, ft.log_cap,
                       ft.log_rate, ft.log_seed, ft.subit, ft.guess_gate, ft.guess_strength,
@@ -954,7 +955,8 @@ hipError_t launch_grad_flux(hipStream_t s, DevMesh& m, const StepArgs& a, int ta
     grad_flux_launch<float>(s, m, g, f, ft.feat, a.gas.is14, tau_s);
   } else {
     GradArgs<double> g{nullptr, m.nc, m.nc, m.nf, m.U, m.nb_, m.grc, m.fA, (double*)m.Wf,
-                       a.gas.gm1, a.boundary, nullptr, 0, 0, m.ckey, tau_s};
+                       a.gas.gm1, a.boundary, nullptr, 0, 0, m.ckey, tau_s, (double*)m.Wx,
+                       m.xb};
     FluxArgs<double> f{m.frec, 0, m.nf, m.nc, m.fA, m.U, (const double*)m.Wf, m.R, (double*)m.Q,
                        m.dcount, m.dimpulse, a, ft.mlp, ft.log_rows, ft.log_count, ft.log_cap,
                        ft.log_rate, ft.log_seed, ft.subit, ft.guess_gate, ft.guess_strength,
@@ -1000,6 +1002,9 @@ static void flux_feat_launch(hipStream_t s, int order, int feat, int count, cons
 hipError_t launch_flux(hipStream_t s, DevMesh& m, const StepArgs& a, int first, int count,
                        const FluxFeatures& ft, const double* U, void* Q, int pass_mode,
                        const void* Qpred, bool dt_min_on_device, int first2, int count2) {
+  // with the chunk-local faces kept apart, the first range holds faces
+  // between chunks, whose records point into the compact face values
+  const bool compact1 = m.split_local && count > 0;
   if (count <= 0) {  // the second range alone
     first = first2;
     count = count2;
@@ -1016,7 +1021,8 @@ hipError_t launch_flux(hipStream_t s, DevMesh& m, const StepArgs& a, int first, 
                       m.dimpulse, a, ft.mlp, ft.log_rows, ft.log_count, ft.log_cap,
                       ft.log_rate, ft.log_seed, ft.subit, ft.guess_gate, ft.guess_strength,
                       pass_mode, (const float*)Qpred, m.moving ? m.sF : nullptr,
-                      dt_min_on_device ? m.dscal : nullptr, n1, off2};
+                      dt_min_on_device ? m.dscal : nullptr, n1, off2,
+                      compact1 ? (const float*)m.Wx : nullptr};
     if (ft.feat && a.gas.is14 && m.scatter == TAFV_SCATTER_GATHER && !m.moving)
       flux_feat_launch<float>(s, a.order, ft.feat, count, f);
     else if (a.gas.is14) flux_launch<float, true>(s, a.order, m.scatter, count, f);
@@ -1026,7 +1032,8 @@ hipError_t launch_flux(hipStream_t s, DevMesh& m, const StepArgs& a, int first, 
                        m.dcount, m.dimpulse, a, ft.mlp, ft.log_rows, ft.log_count, ft.log_cap,
                        ft.log_rate, ft.log_seed, ft.subit, ft.guess_gate, ft.guess_strength,
                        pass_mode, (const double*)Qpred, m.moving ? m.sF : nullptr,
-                       dt_min_on_device ? m.dscal : nullptr, n1, off2};
+                       dt_min_on_device ? m.dscal : nullptr, n1, off2,
+                       compact1 ? (const double*)m.Wx : nullptr};
     if (ft.feat && a.gas.is14 && m.scatter == TAFV_SCATTER_GATHER && !m.moving)
       flux_feat_launch<double>(s, a.order, ft.feat, count, f);
     else if (a.gas.is14) flux_launch<double, true>(s, a.order, m.scatter, count, f);

@@ -252,7 +252,24 @@ struct GradArgs {
   // visited in mesh order
   const int8_t* key;
   int key_max;
+  // when set: the face values of the half-faces whose neighbour lies in
+  // another chunk of kChunkCells cells go to Wx[xb[cell] + rank of the slot
+  // among those of the cell] instead of Wf
+  T* Wx = nullptr;
+  const int* xb = nullptr;
 };
+
+// cells per chunk of the compact cross-chunk face values (a block's cells
+// in the fused gradient and local-face launch)
+constexpr int kChunkCells = 256;
+
+// slots of cell i whose neighbour lies in another chunk
+__device__ inline unsigned cross_slots(const int* nb, int i) {
+  unsigned x = 0;
+  for (int m = 0; m < 4; ++m)
+    x |= (unsigned)(nb[m] >= 0 && nb[m] / kChunkCells != i / kChunkCells) << m;
+  return x;
+}
 
 // Face values are stored per slot and cell with the 5 values of a half-face
 // contiguous: Wf[(slot * nc + cell) * 5 + variable], so that the flux kernel
@@ -329,6 +346,7 @@ struct GradIn {
   int nb[4];
   double ui[5];
   T cr[3][4];
+  int xb;  // the cell's first compact position (GradArgs::Wx set)
 };
 
 template <typename T>
@@ -342,16 +360,19 @@ __device__ inline GradIn<T> grad_load(const GradArgs<T>& a, int i) {
   for (int m = 0; m < 3; ++m)
     for (int j = 0; j < 4; ++j)
       g.cr[m][j] = __builtin_nontemporal_load(a.grc + (size_t)(4 * m + j) * nc + i);
+  g.xb = a.xb ? a.xb[i] : 0;
   return g;
 }
 
 // store_slots: the slots whose face values are stored (the others stay in
-// the stage only)
+// the stage only); with a.Wx, the slots across chunks go to the compact
+// array instead
 template <typename T>
 __device__ inline void grad_compute(const GradArgs<T>& a, int i, bool valid, T* stage,
                                     const GradIn<T>& g, unsigned store_slots = 0xfu) {
   const int nc = a.nc;
-  FaceValueWriter<T> out(stage, i, valid, store_slots);
+  const unsigned cross = a.Wx ? cross_slots(g.nb, i) : 0u;
+  FaceValueWriter<T> out(stage, i, valid, store_slots & ~cross);
   const int* nb = g.nb;
   const double* ui = g.ui;
   double un[4][5];
@@ -405,6 +426,15 @@ __device__ inline void grad_compute(const GradArgs<T>& a, int i, bool valid, T* 
     for (int m = 0; m < 4; ++m) out.put(m, k, wi[k] + psi * delta[m]);
   }
   out.flush(a.Wf, nc);
+  if (valid && cross) {  // this lane's own staged values
+    const T* st = stage + 5 * (threadIdx.x & 63);
+    T* x = a.Wx + 5 * (size_t)g.xb;
+    for (int m = 0; m < 4; ++m) {
+      if (!((cross >> m) & 1u)) continue;
+      for (int k = 0; k < 5; ++k) x[k] = st[m * 320 + k];
+      x += 5;
+    }
+  }
 }
 
 template <typename T>
@@ -449,7 +479,16 @@ struct FluxArgs {
   // the launch's items: rec[idx] for idx < n1, then rec[off2 + idx - n1]
   // (two ranges of the face list)
   int n1 = 0x7fffffff, off2 = 0;
+  // when set: the items of the first range are faces between chunks, their
+  // records hold positions in this compact array of face values
+  const T* Wx = nullptr;
 };
+
+// whether item idx reads its face values from the compact array
+template <typename T>
+__device__ inline bool flux_compact(const FluxArgs<T>& a, int idx) {
+  return a.Wx != nullptr && idx < a.n1;
+}
 
 template <typename T>
 __device__ inline const int4* flux_rec(const FluxArgs<T>& a, int idx) {
@@ -484,9 +523,9 @@ __device__ inline void store_face_flux(const FluxArgs<T>& a, int4 r, double dt_m
 }
 
 template <int ORDER, typename T>
-__device__ inline void load_side(const FluxArgs<T>& a, int h, T* w) {
-  if (ORDER == 2) {  // Wf[(slot * nc + cell) * 5 + variable]
-    const T* p = a.Wf + 5 * ((size_t)(h & 3) * a.nc + (h >> 2));
+__device__ inline void load_side(const FluxArgs<T>& a, int h, T* w, bool compact = false) {
+  if (ORDER == 2) {  // Wf[(slot * nc + cell) * 5 + variable], or Wx[h * 5 + variable]
+    const T* p = compact ? a.Wx + 5 * (size_t)h : a.Wf + 5 * ((size_t)(h & 3) * a.nc + (h >> 2));
     for (int k = 0; k < 5; ++k) w[k] = p[k];
   } else {
     double t[5];
@@ -630,10 +669,11 @@ __device__ inline void face_flux_w(const FluxArgs<T>& a, int f, bool interior, c
 // |A| F(W(0)) . n for one face record (reconstructed states from the face
 // values, or the cells' states at first order)
 template <int ORDER, typename T, bool G14, bool MOVE = false>
-__device__ inline void face_flux(const FluxArgs<T>& a, int4 r, T* phi, SolveInfo& info) {
+__device__ inline void face_flux(const FluxArgs<T>& a, int4 r, T* phi, SolveInfo& info,
+                                 bool compact = false) {
   T wl[5], wr[5];
-  load_side<ORDER, T>(a, r.y, wl);
-  if (r.z >= 0) load_side<ORDER, T>(a, r.z, wr);
+  load_side<ORDER, T>(a, r.y, wl, compact);
+  if (r.z >= 0) load_side<ORDER, T>(a, r.z, wr, compact);
   face_flux_w<T, G14, MOVE>(a, r.x, r.z >= 0, wl, wr, phi, info);
 }
 
@@ -669,10 +709,11 @@ __device__ inline void flush_counters(const SolveInfo& info, double i0, double i
 // colour scatter forms); the wall impulse q is added to (i0, i1, i2).
 template <int ORDER, typename T, bool G14, bool MOVE = false>
 __device__ inline void flux_store_item(const FluxArgs<T>& a, int4 r, double dt_min,
-                                       SolveInfo& acc, double& i0, double& i1, double& i2) {
+                                       SolveInfo& acc, double& i0, double& i1, double& i2,
+                                       bool compact = false) {
   SolveInfo info{0, 0, 0, 0, 0, 0, 0, 0};
   T phi[5];
-  face_flux<ORDER, T, G14, MOVE>(a, r, phi, info);
+  face_flux<ORDER, T, G14, MOVE>(a, r, phi, info, compact);
   add_info(acc, info);
   store_face_flux(a, r, dt_min, phi, r.z < 0 && a.s.boundary == TAFV_BC_WALL, i0, i1, i2);
 }
@@ -890,11 +931,11 @@ __device__ inline void flux_feat_w(const FluxArgs<T>& a, bool valid, int4 r, con
 template <int ORDER, typename T, int FEAT>
 __device__ inline void flux_feat_item(const FluxArgs<T>& a, bool valid, int4 r, double dt_min,
                                       uint16_t* wave_lds, SolveInfo& acc, double& i0,
-                                      double& i1, double& i2) {
+                                      double& i1, double& i2, bool compact = false) {
   T wl[5] = {1, 0, 0, 0, 1}, wr[5] = {1, 0, 0, 0, 1};
   if (valid) {
-    load_side<ORDER, T>(a, r.y, wl);
-    if (r.z >= 0) load_side<ORDER, T>(a, r.z, wr);
+    load_side<ORDER, T>(a, r.y, wl, compact);
+    if (r.z >= 0) load_side<ORDER, T>(a, r.z, wr, compact);
   }
   flux_feat_w<T, FEAT>(a, valid, r, wl, wr, dt_min, wave_lds, acc, i0, i1, i2);
 }

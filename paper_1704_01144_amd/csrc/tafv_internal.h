@@ -109,6 +109,16 @@ struct DevMesh {
   int2* lf_face = nullptr;      // [n_local]
   int32_t n_local = 0;
   bool split_local = false;
+  // While split_local is set, the face values of the half-faces whose
+  // neighbour lies in another chunk go to a compact array Wx [nx][5] in
+  // cell order (cell c's from xb[c], by slot), and the face records of the
+  // faces between chunks take their positions there (fxL, fxR; the other
+  // faces keep their half-face ids).
+  void* Wx = nullptr;
+  int32_t* xb = nullptr;   // [nc]
+  int32_t* fxL = nullptr;  // [nf]
+  int32_t* fxR = nullptr;  // [nf]
+  int64_t nx = 0;
   // schedule lists
   Partition pf, pc, pg;    // faces by (colour, tau_f); cells by tau_g; the gather's
                            // cell list (see cells_gather)
