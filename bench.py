@@ -95,7 +95,7 @@ FUSE_FACES = 0  # chunk-local faces computed by the gradient launches (set from 
 def run_form(T, torch, cfg, precision, steps, warmup, scatter, mlp=None, stats=0, time_order=1,
              motion=None):
     stream = torch.cuda.current_stream()
-    extra = {}
+    extra = dict(guess_stats=stats)
     if mlp is not None:
         extra = dict(guess=T.GUESS_MLP, guess_stats=stats, guess_gate=mlp["gate"],
                      guess_strength=mlp["strength"])
@@ -146,8 +146,9 @@ def run_form(T, torch, cfg, precision, steps, warmup, scatter, mlp=None, stats=0
     newton = st1["newton_updates"] - st0["newton_updates"]
     cons, lev = s.read()
     s.close()
+    hist = (np.array(st1["newton_hist"]) - np.array(st0["newton_hist"])).tolist()
     return dict(ms=ms, ms_prof=ms_prof, wall_s=wall, updates=updates, faces=faces, newton=newton,
-                prof=prof,
+                prof=prof, newton_hist=hist,
                 stats=st1, cons=cons, levels=lev,
                 gated=st1["guess_faces"] - st0["guess_faces"],
                 gated_newton=st1["guess_newton_updates"] - st0["guess_newton_updates"],
@@ -169,7 +170,7 @@ def train_guess(T, torch, I, n, train_seeds=(1, 2, 3, 4, 5), rows_per_seed=40000
     for seed in train_seeds:
         prim = I.blast_state(cfg["nodes"], cfg["tets"], centre=I.blast_centre(seed))
         s.init(prim)
-        T.tafv_facelog_config(s.ctx, rows_per_seed, 0.3, seed)
+        T.tafv_facelog_config(s.ctx, rows_per_seed, 0.75, seed)
         T.tafv_advance(s.ctx, UNITS)
         rows.append(T.tafv_facelog_read(s.ctx, rows_per_seed))
     rows = np.concatenate(rows)
@@ -597,6 +598,7 @@ def main():
         # the Newton counts on the faces where two-rarefaction is inexact
         # come from a run with statistics (they cost a little time)
         rs = run_form(T, torch, cfg, T.FP32_FLUX, 1, 0, args.scatter, mlp=g, stats=1)
+        rs_tr = run_form(T, torch, cfg, T.FP32_FLUX, 1, 0, args.scatter, stats=1)
         vl = rate(rl)
         e = {"value": round(vl, 1), "ms_per_step": round(rl["ms"] / args.steps, 4)}
         if r64 is not None:
@@ -612,7 +614,11 @@ def main():
             "eval_newton_per_inexact_face": round(rs["gated_newton"] / max(rs["gated"], 1), 4),
             "eval_faces_network_evaluated_per_step": rs["evaluated"],
             "eval_faces_started_by_network_per_step": rs["used"],
-            "newton_per_face_all": round(rs["newton"] / max(rs["faces"], 1), 4)})
+            "newton_per_face_all": round(rs["newton"] / max(rs["faces"], 1), 4),
+            # face solves of one step by category (rarefactions, one shock,
+            # two shocks) and Newton updates (1..7, 8 or more)
+            "newton_histogram_by_category": {"two_rarefaction_start": rs_tr["newton_hist"],
+                                             "learned_start": rs["newton_hist"]}})
         forms["fp32_learned"] = with_roofline(e, rl, BYTES_PER_ITEM_FORM["fp32_learned"],
                                               "fp32_learned", copy_gbs)
         log(f"fp32 + learned: {vl / 1e9:.3f} G/s, gate {g['gate']}, "

@@ -178,6 +178,16 @@ typedef struct {
   int64_t guess_rejected;  /* network guesses rejected (non-finite or <= 0)    */
   int64_t guess_used;      /* face solves started from the network's guess     */
   int64_t guess_evaluated; /* faces the network was evaluated for             */
+  int64_t newton_hist[3][8]; /* with guess_stats: Newton solves by category
+                              and updates.  Category: [0] p* <= min(p_L, p_R)
+                              (two rarefactions: the two-rarefaction value is
+                              exact), [1] p* between them (one shock), [2]
+                              p* above both (two shocks); a wall's mirror
+                              state has p_R = p_L.  [c][b]: solves with b + 1
+                              Newton updates (b < 7), [c][7]: 8 or more (the
+                              bisection fallback included).  Vacuum and
+                              transmissive faces are not counted.          */
+  int64_t newton_hist_long_updates[3]; /* Newton updates of the [c][7] solves */
 } tafv_stats;
 
 /* Fill *p with the defaults listed above. */

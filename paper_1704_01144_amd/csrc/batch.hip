@@ -784,6 +784,7 @@ tafv_status build_merged(tafv_ctx* c) {
   B_TRY(c, hipMemcpy(B.cc, cc.data(), sizeof(int32_t) * (M + 1), hipMemcpyHostToDevice));
   B_TRY(c, hipMemcpy(B.fc, fc.data(), sizeof(int32_t) * (M + 1), hipMemcpyHostToDevice));
   B_TRY(c, launch_fill_u64(c->stream, B.m->dcount, 0ull, kCounterWords));
+  B_TRY(c, launch_fill_u64(c->stream, B.m->dnewton, 0ull, kCounterSlots * kNewtonWords));
   B_TRY(c, launch_fill_f64(c->stream, B.m->dimpulse, 0.0, kCounterWords));
   B_TRY(c, launch_fill_u64(c->stream, B.m->dscal, 0ull, 4));
   B_TRY(c, launch_fill_f64(c->stream, B.m->U, 0.0, (int64_t)5 * merged.nc));
@@ -842,6 +843,7 @@ struct Ptrs {
   double* R;
   const int32_t* tp;  // work tile prefixes [3][M + 1]
   const BatchSched* S;
+  unsigned long long* dnewton;  // Newton-update histogram (null: not kept)
 };
 
 hipError_t run_reclass(tafv_ctx* c, hipStream_t s) {
@@ -983,11 +985,13 @@ hipError_t run_flux(tafv_ctx* c, hipStream_t s, const Ptrs& p) {
     FluxArgs<float> f{m.frec, 0, m.nf, m.nc, m.fA32, m.U, (const float*)m.Wf, m.R, (float*)m.Q,
                       p.dcount, p.dimpulse, a, ft.mlp, nullptr, nullptr, 0, 0.0, 0, 0,
                       ft.guess_gate, ft.guess_strength};
+    f.dnewton = (ft.feat & 1) ? p.dnewton : nullptr;
     flux_dispatch<float>(s, B, c->prm.order, ft.feat, a.gas.is14, grid, f);
   } else {
     FluxArgs<double> f{m.frec, 0, m.nf, m.nc, m.fA, m.U, (const double*)m.Wf, m.R, (double*)m.Q,
                        p.dcount, p.dimpulse, a, ft.mlp, nullptr, nullptr, 0, 0.0, 0, 0,
                        ft.guess_gate, ft.guess_strength};
+    f.dnewton = (ft.feat & 1) ? p.dnewton : nullptr;
     flux_dispatch<double>(s, B, c->prm.order, ft.feat, a.gas.is14, grid, f);
   }
   return hipGetLastError();
@@ -1032,7 +1036,7 @@ hipError_t run_gather(tafv_ctx* c, hipStream_t s, const LaunchSet& ls, const Ptr
 }
 
 Ptrs live_ptrs(Batch& B) {
-  return Ptrs{B.m->dcount, B.m->dimpulse, B.m->U, B.m->R, B.tp, B.dsched};
+  return Ptrs{B.m->dcount, B.m->dimpulse, B.m->U, B.m->R, B.tp, B.dsched, B.m->dnewton};
 }
 
 // one subiteration on stream s (profiling scopes only when s is the
@@ -1187,7 +1191,7 @@ tafv_status autotune(tafv_ctx* c) {
     if (e == hipSuccess)
       e = hipMemcpyAsync(tpt, htp.data(), sizeof(int32_t) * 3 * (M + 1), hipMemcpyHostToDevice, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);  // host buffers reused next level
-    Ptrs scratch{m.dcount, m.dimpulse, Us, Rs, tpt, St};
+    Ptrs scratch{m.dcount, m.dimpulse, Us, Rs, tpt, St, nullptr};
     for (int w = 0; w < 2 && e == hipSuccess; ++w) {
       if (w == 0 && c->prm.order != 2) continue;
       for (size_t k = 0; k < cand.size() && e == hipSuccess; ++k) {
@@ -1467,6 +1471,11 @@ tafv_status batch_advance(tafv_ctx* c, int64_t n, tafv_stats* out) {
     acc.guess_rejected = now.guess_rejected - B.last.guess_rejected;
     acc.guess_used = now.guess_used - B.last.guess_used;
     acc.guess_evaluated = now.guess_evaluated - B.last.guess_evaluated;
+    for (int k = 0; k < 24; ++k)
+      acc.newton_hist[k / 8][k % 8] = now.newton_hist[k / 8][k % 8] - B.last.newton_hist[k / 8][k % 8];
+    for (int k = 0; k < 3; ++k)
+      acc.newton_hist_long_updates[k] =
+          now.newton_hist_long_updates[k] - B.last.newton_hist_long_updates[k];
     for (int k = 0; k < 3; ++k) acc.wall_impulse[k] = now.wall_impulse[k] - B.last.wall_impulse[k];
     *out = acc;
   }

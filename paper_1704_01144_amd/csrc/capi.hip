@@ -105,7 +105,7 @@ void free_mesh(tafv_ctx* c, DevMesh* m) {
                   m->perm, m->xfer, m->chist, m->rb, m->dmin, m->Q0, m->D, m->Ut, m->nkey,
                   m->vol0, m->fnode, m->sF, m->Rv, m->sweepf, m->lkey, m->pg.list,
                   m->pg.counts, m->pg.start, m->pg.offs, m->pg.tot, m->flocal,
-                  m->lf_start, m->lf_face, m->Wx, m->xb, m->fxL, m->fxR};
+                  m->lf_start, m->lf_face, m->Wx, m->xb, m->fxL, m->fxR, m->dnewton};
   for (void* p : ptrs) dev_free(c, p);
   delete m;
 }
@@ -547,7 +547,17 @@ tafv_status read_slot_counters(tafv_ctx* c, DevMesh& m, tafv_stats* st) {
                             hipMemcpyDeviceToHost, c->stream));
   HIP_TRY(c, hipMemcpyAsync(imp.data(), m.dimpulse, kCounterWords * sizeof(double),
                             hipMemcpyDeviceToHost, c->stream));
+  std::vector<unsigned long long> nh(kCounterSlots * kNewtonWords);
+  HIP_TRY(c, hipMemcpyAsync(nh.data(), m.dnewton, nh.size() * sizeof(unsigned long long),
+                            hipMemcpyDeviceToHost, c->stream));
   HIP_TRY(c, hipStreamSynchronize(c->stream));
+  for (int k = 0; k < 24; ++k) st->newton_hist[k / 8][k % 8] = 0;
+  for (int k = 0; k < 3; ++k) st->newton_hist_long_updates[k] = 0;
+  for (int sl = 0; sl < kCounterSlots; ++sl) {
+    for (int k = 0; k < 24; ++k) st->newton_hist[k / 8][k % 8] += (int64_t)nh[sl * kNewtonWords + k];
+    for (int k = 0; k < 3; ++k)
+      st->newton_hist_long_updates[k] += (int64_t)nh[sl * kNewtonWords + 24 + k];
+  }
   unsigned long long tot[8] = {0, 0, 0, 0, 0, 0, 0, 0};
   double itot[3] = {0, 0, 0};
   for (int sl = 0; sl < kCounterSlots; ++sl) {
@@ -643,6 +653,7 @@ tafv_status upload_host_mesh(tafv_ctx* c, const HostMesh& hm, DevMesh** out) {
   chk(dalloc(c, &m->xfer, 5 * nc));
   chk(dalloc(c, &m->dscal, 4));
   chk(dalloc(c, &m->dcount, kCounterWords));
+  chk(dalloc(c, &m->dnewton, kCounterSlots * kNewtonWords));
   chk(dalloc(c, &m->dimpulse, kCounterWords));
   if (e != hipSuccess) {
     free_mesh(c, m);
@@ -976,6 +987,8 @@ tafv_status tafv_state_init(tafv_ctx* c, int32_t mesh_id, const double* prim) {
   if (e == hipSuccess) e = sync_time_states(c, *m);
   if (e == hipSuccess) e = reset_volumes(c, *m);
   if (e == hipSuccess) e = launch_fill_u64(c->stream, m->dcount, 0ull, kCounterWords);
+  if (e == hipSuccess)
+    e = launch_fill_u64(c->stream, m->dnewton, 0ull, kCounterSlots * kNewtonWords);
   if (e == hipSuccess) e = launch_fill_f64(c->stream, m->dimpulse, 0.0, kCounterWords);
   if (e == hipSuccess) e = launch_fill_u64(c->stream, m->dscal, 0ull, 4);
   if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
@@ -1121,6 +1134,8 @@ tafv_status tafv_advance_group(tafv_ctx* const* ctxs, int32_t n, int64_t n_dt_mi
     tot.guess_used += one.guess_used;
     tot.guess_evaluated += one.guess_evaluated;
     for (int k = 0; k < 3; ++k) tot.wall_impulse[k] += one.wall_impulse[k];
+    for (int k = 0; k < 24; ++k) tot.newton_hist[k / 8][k % 8] += one.newton_hist[k / 8][k % 8];
+    for (int k = 0; k < 3; ++k) tot.newton_hist_long_updates[k] += one.newton_hist_long_updates[k];
     for (int t = 0; t < kMaxLevels; ++t) tot.cells_per_level[t] += one.cells_per_level[t];
     tot.theta = std::max(tot.theta, one.theta);
     tot.phase = one.phase;
@@ -1159,6 +1174,9 @@ tafv_status call_stats(tafv_ctx* c, tafv_stats acc, tafv_stats* out) {
       acc.guess_used += m->st.guess_used;
       acc.guess_evaluated += m->st.guess_evaluated;
       for (int k = 0; k < 3; ++k) acc.wall_impulse[k] += m->st.wall_impulse[k];
+      for (int k = 0; k < 24; ++k) acc.newton_hist[k / 8][k % 8] += m->st.newton_hist[k / 8][k % 8];
+      for (int k = 0; k < 3; ++k)
+        acc.newton_hist_long_updates[k] += m->st.newton_hist_long_updates[k];
     }
     *out = acc;
   }

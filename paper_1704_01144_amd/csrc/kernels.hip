@@ -1022,7 +1022,8 @@ hipError_t launch_flux(hipStream_t s, DevMesh& m, const StepArgs& a, int first, 
                       ft.log_rate, ft.log_seed, ft.subit, ft.guess_gate, ft.guess_strength,
                       pass_mode, (const float*)Qpred, m.moving ? m.sF : nullptr,
                       dt_min_on_device ? m.dscal : nullptr, n1, off2,
-                      compact1 ? (const float*)m.Wx : nullptr};
+                      compact1 ? (const float*)m.Wx : nullptr,
+                      (ft.feat & 1) ? m.dnewton : nullptr};
     if (ft.feat && a.gas.is14 && m.scatter == TAFV_SCATTER_GATHER && !m.moving)
       flux_feat_launch<float>(s, a.order, ft.feat, count, f);
     else if (a.gas.is14) flux_launch<float, true>(s, a.order, m.scatter, count, f);
@@ -1033,7 +1034,8 @@ hipError_t launch_flux(hipStream_t s, DevMesh& m, const StepArgs& a, int first, 
                        ft.log_rate, ft.log_seed, ft.subit, ft.guess_gate, ft.guess_strength,
                        pass_mode, (const double*)Qpred, m.moving ? m.sF : nullptr,
                        dt_min_on_device ? m.dscal : nullptr, n1, off2,
-                       compact1 ? (const double*)m.Wx : nullptr};
+                       compact1 ? (const double*)m.Wx : nullptr,
+                       (ft.feat & 1) ? m.dnewton : nullptr};
     if (ft.feat && a.gas.is14 && m.scatter == TAFV_SCATTER_GATHER && !m.moving)
       flux_feat_launch<double>(s, a.order, ft.feat, count, f);
     else if (a.gas.is14) flux_launch<double, true>(s, a.order, m.scatter, count, f);

@@ -482,6 +482,9 @@ struct FluxArgs {
   // when set: the items of the first range are faces between chunks, their
   // records hold positions in this compact array of face values
   const T* Wx = nullptr;
+  // face statistics (FEAT & 1): Newton updates per face by category, in
+  // kCountSlots slots of kNewtonWords words (see newton_hist_add)
+  unsigned long long* dnewton = nullptr;
 };
 
 // whether item idx reads its face values from the compact array
@@ -785,6 +788,29 @@ __device__ inline bool strength_pregate(const Gas& G, const T* wl, const T* wr, 
   return du * du >= d * d * ((float)G.g * pm / rm);
 }
 
+// Newton updates per face solve by category, per counter slot: word
+// 8 c + b counts the solves of category c with b + 1 updates (b < 7) or
+// with 8 or more (b = 7), word 24 + c sums the updates of that last bin.
+// Category: 0 p* <= min(p_L, p_R) (two rarefactions, the two-rarefaction
+// value exact), 1 between them (one shock), 2 above both (two shocks); a
+// wall's mirror state has p_R = p_L.  Vacuum faces and transmissive faces
+// have no Newton solve and are not counted.  Called by all 64 lanes of a
+// wave; key < 0 for lanes without a solve.
+__device__ inline void newton_hist_add(unsigned long long* dn, int key, int iters) {
+  const int lane = threadIdx.x & 63;
+  unsigned long long* d =
+      dn + ((blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6)) % kCountSlots) * kNewtonWords;
+  unsigned long long pending = __ballot(key >= 0);
+  while (pending) {
+    const int leader = __ffsll((long long)pending) - 1;
+    const int k = __shfl(key, leader, 64);
+    const unsigned long long same = __ballot(key == k);
+    if (lane == leader) atomicAdd(&d[k], (unsigned long long)__popcll(same));
+    pending &= ~same;
+  }
+  if (key >= 0 && (key & 7) == 7) atomicAdd(&d[24 + (key >> 3)], (unsigned long long)iters);
+}
+
 // The gather-mode flux with the optional features, as described above, from
 // the face's two reconstructed states wl and wr (wr unused on a boundary
 // face, r.z < 0); r.x the face, r.w its tau_f.  All 64 lanes of a wave call
@@ -800,6 +826,7 @@ __device__ inline void flux_feat_w(const FluxArgs<T>& a, bool valid, int4 r, con
   T am = 1, nx = 1, ny = 0, nz = 0, unl = 0, unr = 0;
   bool wall = false, transmit = false, net = false;
   float x[kMlpIn] = {0, 0, 0, 0, 0, 0};
+  int hist_key = -1, hist_iters = 0;  // face statistics: category and bin
   if (valid) {
     const int f = r.x;
     T ax = nt_load(a.fA + f), ay = nt_load(a.fA + a.nf + f);
@@ -875,6 +902,11 @@ __device__ inline void flux_feat_w(const FluxArgs<T>& a, bool valid, int4 r, con
       info.iters = st.iters;
       info.fallback = st.fallback;
       info.vacuum = st.vacuum;
+      if ((FEAT & 1) && !st.vacuum) {
+        const int cat = (st.p > fmin(pl, pr) ? 1 : 0) + (st.p > fmax(pl, pr) ? 1 : 0);
+        hist_key = 8 * cat + min(max(st.iters, 1), 8) - 1;
+        hist_iters = st.iters;
+      }
       if (gate) {
         info.gated = 1;
         info.gated_iters = st.iters;
@@ -923,6 +955,7 @@ __device__ inline void flux_feat_w(const FluxArgs<T>& a, bool valid, int4 r, con
     }
     store_face_flux(a, r, dt_min, phi, wall, i0, i1, i2);
   }
+  if ((FEAT & 1) && a.dnewton) newton_hist_add(a.dnewton, hist_key, hist_iters);
   add_info(acc, info);
 }
 

@@ -18,6 +18,8 @@ constexpr int kMaxKeys = kMaxColours * kMaxLevels;
 constexpr int kCounterSlots = 64;
 constexpr int kCounterStride = 16;
 constexpr int kCounterWords = kCounterSlots * kCounterStride;
+// Newton-update histogram by category: kCounterSlots slots of kNewtonWords
+constexpr int kNewtonWords = 32;
 
 // Host-side mesh after preprocessing: faces in colour-major order.
 struct HostMesh {
@@ -127,6 +129,7 @@ struct DevMesh {
   // [nc] predictor/corrector form: the smallest tau_g over the cell and its
   // face neighbours (which face passes read its interpolated state)
   int8_t* nkey = nullptr;
+  unsigned long long* dnewton = nullptr;  // [kCounterSlots][kNewtonWords]
   int8_t* lkey = nullptr;  // [nc] key of the gather's cell list (see list_cell)
   int* chist = nullptr;    // [kCounterSlots][64] cell count per (tau_g, tau), summed
                            // over the slots by the readback kernel

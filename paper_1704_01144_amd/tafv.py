@@ -51,12 +51,16 @@ class tafv_stats(C.Structure):
                 ("dt_min", C.c_double), ("t_reached", C.c_double),
                 ("wall_impulse", C.c_double * 3), ("guess_faces", C.c_int64),
                 ("guess_newton_updates", C.c_int64), ("guess_rejected", C.c_int64),
-                ("guess_used", C.c_int64), ("guess_evaluated", C.c_int64)]
+                ("guess_used", C.c_int64), ("guess_evaluated", C.c_int64),
+                ("newton_hist", (C.c_int64 * 8) * 3),
+                ("newton_hist_long_updates", C.c_int64 * 3)]
 
     def as_dict(self):
         d = {k: getattr(self, k) for k, _ in self._fields_}
         d["cells_per_level"] = list(self.cells_per_level)
         d["wall_impulse"] = list(self.wall_impulse)
+        d["newton_hist"] = [list(row) for row in self.newton_hist]
+        d["newton_hist_long_updates"] = list(self.newton_hist_long_updates)
         return d
 
 

@@ -211,3 +211,58 @@ def test_nonfinite_network_parameter(T):
     T.tafv_mlp_set(s.ctx, good)
     s.advance(1)
     s.close()
+
+
+def _oracle_newton_hist(orc, nodes, tets, prim, max_iter=50):
+    """Category x update-count histogram of the oracle's Newton solves of
+    every face from the cell states (first order, walls), binned as the
+    library bins them."""
+    mesh = orc.Mesh(nodes, tets)
+    g = mesh.geometry()
+    w = orc.cons_to_prim(orc.prim_to_cons(prim))
+    hist = np.zeros((3, 8), np.int64)
+    long_updates = np.zeros(3, np.int64)
+    for f in range(mesh.n_faces):
+        L, R = int(g["face_L"][f]), int(g["face_R"][f])
+        wl = w[L]
+        wr = w[R] if R >= 0 else None
+        _, out = orc.face_flux(wl, wr, g["face_area"][f],
+                               orc.KIND_INTERIOR if R >= 0 else orc.KIND_WALL, max_iter=max_iter)
+        if out.vacuum:
+            continue
+        pl, pr = wl[4], (wr[4] if R >= 0 else wl[4])
+        cat = int(out.p_star > min(pl, pr)) + int(out.p_star > max(pl, pr))
+        b = min(max(out.newton_updates, 1), 8) - 1
+        hist[cat, b] += 1
+        if b == 7:
+            long_updates[cat] += out.newton_updates
+    return hist, long_updates
+
+
+@pytest.mark.parametrize("max_iter", [50, 2], ids=["newton", "bisection"])
+def test_newton_histogram_against_oracle(T, orc, max_iter):
+    """Face statistics by category and Newton update count: the first
+    subiteration at first order solves every face once from the cell
+    states; the library's histogram matches the oracle's solves of the same
+    faces, and it sums to the face solves and the Newton updates."""
+    nodes, tets = I.graded_box_mesh(10, 8, 6, 4.0)
+    prim = I.blast_state(nodes, tets, centre=I.blast_centre(3))
+    s = T.Solver(max_levels=4, order=1, guess_stats=1, newton_max_iter=max_iter)
+    s.upload(nodes, tets)
+    s.init(prim)
+    st = s.advance(1)
+    s.close()
+    h = np.array(st["newton_hist"], np.int64)
+    lu = np.array(st["newton_hist_long_updates"], np.int64)
+    ho, luo = _oracle_newton_hist(orc, nodes, tets, prim, max_iter)
+    say(f"GPU histogram (rows: rarefactions, one shock, two shocks; columns 1..7, 8+ "
+        f"updates):\n{h}\noracle:\n{ho}")
+    assert h.sum() == st["face_solves"] - st["vacuum_faces"]
+    upd = sum((b + 1) * h[:, b].sum() for b in range(7)) + lu.sum()
+    assert upd == st["newton_updates"]
+    assert h.sum() == ho.sum()
+    assert np.abs(h - ho).max() <= 1e-3 * ho.sum() + 5
+    assert abs(int(lu.sum()) - int(luo.sum())) <= 1e-3 * max(int(luo.sum()), 1) + 5 * max_iter
+    assert h[1:].sum() > 0  # the blast has shocks
+    if max_iter == 2:
+        assert h[:, 7].sum() == 0 and st["newton_fallbacks"] > 0
