@@ -243,7 +243,7 @@ struct GradArgs {
   const int* nb;
   const T* grc;  // [12][nc] a_mj = c_j . r_m at (4 m + j) nc + cell, m < 3
   const double* fA;
-  T* Wf;  // [4][5][nc]
+  T* Wf;  // [4][nc][5]: Wf[(slot * nc + cell) * 5 + variable]
   double gm1;
   int boundary;
   const double* sF;  // moving mesh: face volume rates (walls move with them)

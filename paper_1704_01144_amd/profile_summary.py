@@ -19,6 +19,13 @@ kept with the sources.
       per-wave means of SQ counters (each divided by SQ_WAVES of the same
       dispatches) for each kernel whose name contains a SUBSTR, from one
       or more --pmc runs that each also collected SQ_WAVES.
+
+  python -m paper_1704_01144_amd.profile_summary gaps DIR --command CMD
+      from DIR/*kernel_trace.csv: the dispatches split into bursts wherever
+      the GPU idles for more than --split-ms (host synchronisation between
+      the phases of a run); for the --top longest bursts, their span, the
+      time with no kernel running, and the idle gaps between kernels by
+      length.
 """
 import argparse
 import csv
@@ -145,6 +152,38 @@ def sq_text(a):
     return "\n".join(lines) + "\n"
 
 
+def gaps_text(d, command, split_ms=1.0, top=2):
+    rows = list(csv.DictReader(open(_one(os.path.join(d, "*kernel_trace.csv")))))
+    iv = sorted((int(r["Start_Timestamp"]), int(r["End_Timestamp"])) for r in rows)
+    bursts, cur, end = [], [], None
+    for a, b in iv:
+        if cur and a - end > split_ms * 1e6:
+            bursts.append(cur)
+            cur = []
+        cur.append((a, b))
+        end = b if end is None or not cur[:-1] else max(end, b)
+    if cur:
+        bursts.append(cur)
+    edges = [2e3, 5e3, 10e3, 50e3, split_ms * 1e6]
+    out = [f"command: {command}", f"bursts split at idle > {split_ms} ms: {len(bursts)}"]
+    for k, bu in enumerate(sorted(bursts, key=lambda x: -(x[-1][1] - x[0][0]))[:top]):
+        span = max(b for _, b in bu) - bu[0][0]
+        idle, last, counts = 0, bu[0][1], [0] * len(edges)
+        for a, b in bu[1:]:
+            g = a - last
+            if g > 0:
+                idle += g
+                counts[next(i for i, e in enumerate(edges) if g <= e)] += 1
+            last = max(last, b)
+        out.append(f"burst {k}: {len(bu)} dispatches, span {span / 1e6:.3f} ms, "
+                   f"no kernel running {idle / 1e6:.3f} ms ({100.0 * idle / span:.1f}%)")
+        lo = 0
+        for e, n in zip(edges, counts):
+            out.append(f"  idle gaps {lo / 1e3:g}-{e / 1e3:g} us: {n}")
+            lo = e
+    return "\n".join(out) + "\n"
+
+
 def read_record(path):
     """key: value lines of a counter record -> dict (repeated keys -> list)."""
     out = {}
@@ -177,6 +216,11 @@ def main(argv=None):
     c.add_argument("--copy-write", required=True)
     c.add_argument("--copy-bytes", type=int, required=True)
     c.add_argument("--command", action="append", required=True)
+    gp = sub.add_parser("gaps")
+    gp.add_argument("dir")
+    gp.add_argument("--command", required=True)
+    gp.add_argument("--split-ms", type=float, default=1.0)
+    gp.add_argument("--top", type=int, default=2)
     q = sub.add_parser("sq")
     q.add_argument("--kernel", action="append", required=True)
     q.add_argument("--dir", action="append", required=True)
@@ -186,6 +230,8 @@ def main(argv=None):
         sys.stdout.write(stats_text(a.dir, a.command, a.top))
     elif a.what == "sq":
         sys.stdout.write(sq_text(a))
+    elif a.what == "gaps":
+        sys.stdout.write(gaps_text(a.dir, a.command, a.split_ms, a.top))
     else:
         sys.stdout.write(counters_text(a))
 
