@@ -308,7 +308,7 @@ tafv_status subiteration2(tafv_ctx* c, DevMesh& m, const StepArgs& a, int tau_s,
   {
     ProfScope ps(c, P_FLUX, pcnt);
     HIP_TRY(c, launch_flux(c->stream, m, a, 0, pr.n1, flux_features(c, m), m.Ut, m.Q0, 1, nullptr,
-                           false, pr.first2, pr.n2));
+                           false, pr.first2, pr.n2, tau_s));
   }
   {
     ProfScope ps(c, P_PREDICT, m.nc);
@@ -322,7 +322,7 @@ tafv_status subiteration2(tafv_ctx* c, DevMesh& m, const StepArgs& a, int tau_s,
   {
     ProfScope ps(c, P_FLUX_CORR, ccnt);
     HIP_TRY(c, launch_flux(c->stream, m, a, 0, cr.n1, flux_features(c, m), m.Ut, m.Q, 2, m.Q0,
-                           false, cr.first2, cr.n2));
+                           false, cr.first2, cr.n2, upd));
   }
   {
     const CellRange r = cells_active(m, upd);
@@ -397,7 +397,7 @@ tafv_status first_subiteration(tafv_ctx* c, DevMesh& m, tafv_stats* acc) {
     const int n2 = (m.split_local && !fuse) ? m.n_local : 0;
     ProfScope ps(c, P_FLUX, n1 + n2);
     HIP_TRY(c, launch_flux(c->stream, m, a, 0, n1, ft, nullptr, nullptr, 0, nullptr, true, n1,
-                           n2));
+                           n2, all));
   }
   {
     ListRanges r;
@@ -464,7 +464,7 @@ tafv_status subiteration(tafv_ctx* c, DevMesh& m, tafv_stats* acc) {
     {
       ProfScope ps(c, P_FLUX, fr.count());
       HIP_TRY(c, launch_flux(c->stream, m, a, 0, fr.n1, ft, nullptr, nullptr, 0, nullptr, false,
-                             fr.first2, fr.n2));
+                             fr.first2, fr.n2, tau_s));
     }
     const ListRanges r = cells_gather(m, tau_s, upd);
     ProfScope ps(c, P_GATHER, r.count());

@@ -92,11 +92,14 @@ struct FluxFeatures {
 // dt_min_on_device: the kernels read dt_min from the device scalars (its
 // bits in m.dscal[0]) instead of the host's value
 // The faces are entries [first, first + count) and [first2, first2 + count2)
-// of the face list.
+// of the face list.  key_max >= 0: those are the faces of key <= key_max
+// (gather mode, one range from the list's start); when they are most of the
+// faces the launch walks all faces in face order and takes those.
 hipError_t launch_flux(hipStream_t s, DevMesh& m, const StepArgs& a, int first, int count,
                        const FluxFeatures& ft, const double* U = nullptr, void* Q = nullptr,
                        int pass_mode = 0, const void* Qpred = nullptr,
-                       bool dt_min_on_device = false, int first2 = 0, int count2 = 0);
+                       bool dt_min_on_device = false, int first2 = 0, int count2 = 0,
+                       int key_max = -1);
 // Gradient over the whole mesh (cells of tau_g <= tau_s) with the fluxes of
 // the active faces local to a chunk (k_grad_flux); the other active faces are
 // left to launch_flux.  Features: none, or the learned guess alone

@@ -485,7 +485,15 @@ struct FluxArgs {
   // face statistics (FEAT & 1): Newton updates per face by category, in
   // kCountSlots slots of kNewtonWords words (see newton_hist_add)
   unsigned long long* dnewton = nullptr;
+  // when set: the launch walks every face in face order (count = nf), and
+  // the faces of partition key <= key_max are its items, their records
+  // formed from fhL, fhR and the key (tau_f) instead of read from rec
+  const int8_t* fkey = nullptr;
+  int key_max = 0;
+  const int* fhL = nullptr;
+  const int* fhR = nullptr;
 };
+
 
 // whether item idx reads its face values from the compact array
 template <typename T>
@@ -549,6 +557,24 @@ typedef int tafv_i4v __attribute__((ext_vector_type(4)));
 __device__ inline int4 nt_rec(const int4* p) {
   const tafv_i4v v = __builtin_nontemporal_load(reinterpret_cast<const tafv_i4v*>(p));
   return make_int4(v.x, v.y, v.z, v.w);
+}
+
+// Item idx of a flux launch: its record and whether it is a face to compute.
+// A face-order launch requests the key and both half-face ids together.
+template <typename T>
+__device__ inline bool flux_item(const FluxArgs<T>& a, int idx, int4& r) {
+  if (a.fkey) {
+    const int f = idx < a.count ? idx : a.count - 1;
+    const int k = a.fkey[f], hl = a.fhL[f], hr = a.fhR[f];
+    r = make_int4(f, hl, hr, k);
+    return idx < a.count && k <= a.key_max;
+  }
+  if (idx >= a.count) {
+    r = make_int4(0, 0, -1, 0);
+    return false;
+  }
+  r = nt_rec(flux_rec(a, idx));
+  return true;
 }
 
 struct SolveInfo {
