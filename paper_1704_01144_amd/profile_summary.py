@@ -24,8 +24,8 @@ kept with the sources.
       from DIR/*kernel_trace.csv: the dispatches split into bursts wherever
       the GPU idles for more than --split-ms (host synchronisation between
       the phases of a run); for the --top longest bursts, their span, the
-      time with no kernel running, and the idle gaps between kernels by
-      length.
+      time with no kernel running, the idle gaps between kernels by length,
+      and with --kernels K their K longest kernels.
 """
 import argparse
 import csv
@@ -152,24 +152,25 @@ def sq_text(a):
     return "\n".join(lines) + "\n"
 
 
-def gaps_text(d, command, split_ms=1.0, top=2):
+def gaps_text(d, command, split_ms=1.0, top=2, kernels=0):
     rows = list(csv.DictReader(open(_one(os.path.join(d, "*kernel_trace.csv")))))
-    iv = sorted((int(r["Start_Timestamp"]), int(r["End_Timestamp"])) for r in rows)
+    iv = sorted((int(r["Start_Timestamp"]), int(r["End_Timestamp"]), r.get("Kernel_Name", ""))
+                for r in rows)
     bursts, cur, end = [], [], None
-    for a, b in iv:
+    for a, b, n in iv:
         if cur and a - end > split_ms * 1e6:
             bursts.append(cur)
             cur = []
-        cur.append((a, b))
+        cur.append((a, b, n))
         end = b if end is None or not cur[:-1] else max(end, b)
     if cur:
         bursts.append(cur)
     edges = [2e3, 5e3, 10e3, 50e3, split_ms * 1e6]
     out = [f"command: {command}", f"bursts split at idle > {split_ms} ms: {len(bursts)}"]
     for k, bu in enumerate(sorted(bursts, key=lambda x: -(x[-1][1] - x[0][0]))[:top]):
-        span = max(b for _, b in bu) - bu[0][0]
+        span = max(b for _, b, _ in bu) - bu[0][0]
         idle, last, counts = 0, bu[0][1], [0] * len(edges)
-        for a, b in bu[1:]:
+        for a, b, _ in bu[1:]:
             g = a - last
             if g > 0:
                 idle += g
@@ -181,6 +182,15 @@ def gaps_text(d, command, split_ms=1.0, top=2):
         for e, n in zip(edges, counts):
             out.append(f"  idle gaps {lo / 1e3:g}-{e / 1e3:g} us: {n}")
             lo = e
+        if kernels:
+            per = {}
+            for a, b, n in bu:
+                t = per.setdefault(n, [0, 0])
+                t[0] += 1
+                t[1] += b - a
+            out.append(f"  {'calls':>7} {'total ms':>10} {'avg us':>9}  kernel")
+            for n, (c, t) in sorted(per.items(), key=lambda x: -x[1][1])[:kernels]:
+                out.append(f"  {c:7d} {t / 1e6:10.3f} {t / c / 1e3:9.2f}  {_short(n, 80)}")
     return "\n".join(out) + "\n"
 
 
@@ -221,6 +231,8 @@ def main(argv=None):
     gp.add_argument("--command", required=True)
     gp.add_argument("--split-ms", type=float, default=1.0)
     gp.add_argument("--top", type=int, default=2)
+    gp.add_argument("--kernels", type=int, default=0,
+                    help="also list the longest kernels of each reported burst")
     q = sub.add_parser("sq")
     q.add_argument("--kernel", action="append", required=True)
     q.add_argument("--dir", action="append", required=True)
@@ -231,7 +243,7 @@ def main(argv=None):
     elif a.what == "sq":
         sys.stdout.write(sq_text(a))
     elif a.what == "gaps":
-        sys.stdout.write(gaps_text(a.dir, a.command, a.split_ms, a.top))
+        sys.stdout.write(gaps_text(a.dir, a.command, a.split_ms, a.top, a.kernels))
     else:
         sys.stdout.write(counters_text(a))
 
