@@ -90,6 +90,7 @@ def log(*a):
 
 CELL_ORDER = 0  # internal cell order of the single-mesh runs (set from --cell-order)
 FUSE_FACES = 0  # chunk-local faces computed by the gradient launches (set from --fuse-faces)
+PIPELINE_CHUNKS = 1  # pipelined whole-mesh subiterations (set from --pipeline-chunks)
 
 
 def run_form(T, torch, cfg, precision, steps, warmup, scatter, mlp=None, stats=0, time_order=1,
@@ -101,7 +102,7 @@ def run_form(T, torch, cfg, precision, steps, warmup, scatter, mlp=None, stats=0
                      guess_strength=mlp["strength"])
     s = T.Solver(device=0, hip_stream=stream.cuda_stream, max_levels=cfg["max_levels"],
                  order=cfg["order"], precision=precision, scatter=scatter, time_order=time_order,
-                 cell_order=CELL_ORDER, fuse_faces=FUSE_FACES,
+                 cell_order=CELL_ORDER, fuse_faces=FUSE_FACES, pipeline_chunks=PIPELINE_CHUNKS,
                  allocator=T.torch_allocator(0, stream), **extra)
     s.upload(cfg["nodes"], cfg["tets"])
     if mlp is not None:
@@ -486,6 +487,8 @@ def main():
     ap.add_argument("--fuse-faces", type=int, default=0, choices=(0, 1),
                     help="1: whole-mesh gradient launches also compute the faces local to a "
                          "256-cell chunk; 0: every face through the flux kernel")
+    ap.add_argument("--pipeline-chunks", type=int, default=1,
+                    help="K > 1: whole-mesh subiterations as a pipeline over K chunks")
     ap.add_argument("--cell-order", type=int, default=0,
                     help="internal cell order: 0 the mesh's own, 1 Morton order of the centroids")
     ap.add_argument("--batch-only", action="store_true",
@@ -501,9 +504,10 @@ def main():
     if args.copy_probe:
         copy_probe()
         return
-    global CELL_ORDER, FUSE_FACES
+    global CELL_ORDER, FUSE_FACES, PIPELINE_CHUNKS
     CELL_ORDER = args.cell_order
     FUSE_FACES = args.fuse_faces
+    PIPELINE_CHUNKS = args.pipeline_chunks
 
     import torch
 

@@ -85,7 +85,7 @@ enum { TAFV_ORDER_CALLER = 0, TAFV_ORDER_MORTON = 1 };
  * TAFV_FP64, guess TAFV_GUESS_TR, boundary TAFV_BC_WALL, newton_max_iter
  * 50, reclassify 1, scatter TAFV_SCATTER_GATHER, cell_order TAFV_ORDER_CALLER,
  * guess_stats 0, guess_gate 0, batch 0, guess_strength 0, time_order 1,
- * fuse_faces 0. */
+ * fuse_faces 0, pipeline_chunks 1. */
 typedef struct {
   double gamma;          /* ratio of specific heats, > 1                        */
   double cfl;            /* dt_i = cfl V_i / sum_f (|u_i . n_f| + a_i) |A_f|    */
@@ -156,6 +156,18 @@ typedef struct {
                             flux kernel takes the others.  0 (default): one
                             face list, every face through the flux kernel.
                             Either way the results are the same bits.     */
+  int32_t pipeline_chunks; /* K > 1: at second order in gather mode with
+                            time_order 1 on a fixed mesh, a subiteration
+                            whose gradient, flux and gather launches would
+                            each cover the whole mesh runs them as a
+                            pipeline over K chunks of consecutive cells
+                            (gradient of chunk k + 1, fluxes of the faces
+                            whose first cell lies in chunk k, gather of
+                            chunk k - 1), so that face values and fluxes
+                            are read back soon after they are written.
+                            Meshes whose faces span more than a chunk run
+                            unchunked.  0 or 1 (default): no pipeline.
+                            The results are the same bits either way.     */
 } tafv_params;
 
 /* Counters (int64) and schedule state.  Summed over meshes where a call

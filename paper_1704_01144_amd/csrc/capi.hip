@@ -364,6 +364,45 @@ bool fuse_local_faces(const tafv_ctx* c, const DevMesh& m, const FluxFeatures& f
   return m.split_local && fusable(c, m, ft) && grad_whole_mesh(m, grad_cells);
 }
 
+// Gather mode, second order, forward Euler level steps on a fixed mesh
+// whose faces fit its chunks: a subiteration whose gradient and flux
+// launches would both cover the whole mesh runs them, with the gather, as
+// a pipeline over the chunks.
+bool pipelined(const tafv_ctx* c, const DevMesh& m, int64_t grad_cells, int64_t faces) {
+  return m.pipe_k > 1 && !m.split_local && !m.moving && c->prm.order == 2 &&
+         c->prm.time_order == 1 && m.scatter == TAFV_SCATTER_GATHER &&
+         grad_whole_mesh(m, grad_cells) && faces_whole_mesh(m, faces);
+}
+
+// Step j of the pipeline: gradients of chunk j, fluxes of chunk j - 1's
+// faces (which need the gradients of chunks j - 1 and j), gather of chunk
+// j - 2 (whose faces are all computed by then; the gradients that read its
+// states are done).  The items of each class go with its first launch.
+tafv_status run_pipeline(tafv_ctx* c, DevMesh& m, const StepArgs& a, const FluxFeatures& ft,
+                         int tau_s, int upd, double dt_min, bool dt_min_on_device,
+                         int64_t grad_cells, int64_t faces, int64_t gather_cells) {
+  const int K = m.pipe_k;
+  for (int j = 0; j < K + 2; ++j) {
+    if (j < K) {
+      ProfScope ps(c, P_GRAD, j == 0 ? grad_cells : 0);
+      HIP_TRY(c, launch_grad_chunk(c->stream, m, a, tau_s, m.pipe_c[j], m.pipe_c[j + 1]));
+    }
+    const int k = j - 1;
+    if (k >= 0 && k < K) {
+      ProfScope ps(c, P_FLUX, k == 0 ? faces : 0);
+      HIP_TRY(c, launch_flux_chunk(c->stream, m, a, ft, tau_s, m.pipe_f[k], m.pipe_f[k + 1],
+                                   dt_min_on_device));
+    }
+    const int g = j - 2;
+    if (g >= 0 && g < K) {
+      ProfScope ps(c, P_GATHER, g == 0 ? gather_cells : 0);
+      HIP_TRY(c, launch_gather_chunk(c->stream, m, tau_s, upd, dt_min, c->prm.precision,
+                                     m.pipe_c[g], m.pipe_c[g + 1], dt_min_on_device));
+    }
+  }
+  return TAFV_OK;
+}
+
 // Gather mode with one face pass per level step on a fixed mesh: the first
 // subiteration of an iteration runs at tau_s = theta, so every face and
 // every cell take part, and cells of level 0 end their step.  Its launches
@@ -380,6 +419,14 @@ tafv_status first_subiteration(tafv_ctx* c, DevMesh& m, tafv_stats* acc) {
   const int all = kMaxLevels - 1;  // at least theta
   const FluxFeatures ft = flux_features(c, m);
   const bool fuse = fuse_local_faces(c, m, ft, m.nc);
+  if (pipelined(c, m, m.nc, m.nf)) {
+    tafv_status st = run_pipeline(c, m, a, ft, all, 0, 0.0, true, m.nc, m.nf, m.nc);
+    if (st != TAFV_OK) return st;
+    st = classify_finish(c, m);
+    if (st != TAFV_OK) return st;
+    end_subiteration(m, acc, 1, cells_upto_tau(m, 0), m.nf);
+    return TAFV_OK;
+  }
   if (c->prm.order == 2) {
     ProfScope ps(c, fuse ? P_GRAD_FLUX : P_GRAD, m.nc);
     if (fuse) {
@@ -422,14 +469,6 @@ tafv_status subiteration(tafv_ctx* c, DevMesh& m, tafv_stats* acc) {
   StepArgs a = step_args(c, m);
   int tau_s = subiteration_level((int64_t)m.phase + 1, m.theta);
   const FluxFeatures ft = flux_features(c, m);
-  bool fuse = false;
-  if (c->prm.order == 2 && c->prm.time_order == 1) {
-    const CellRange r = cells_active(m, tau_s);
-    fuse = m.scatter == TAFV_SCATTER_GATHER && fuse_local_faces(c, m, ft, r.count());
-    ProfScope ps(c, fuse ? P_GRAD_FLUX : P_GRAD, r.count());
-    if (fuse) HIP_TRY(c, launch_grad_flux(c->stream, m, a, tau_s, ft, false));
-    else HIP_TRY(c, launch_grad(c->stream, m, a, r, tau_s));
-  }
   int64_t s = (int64_t)m.phase + 1;
   // cells whose step ends after this subiteration: tau_i <= min(theta, ctz(s))
   int upd = 0;
@@ -439,6 +478,24 @@ tafv_status subiteration(tafv_ctx* c, DevMesh& m, tafv_stats* acc) {
       x >>= 1;
       ++upd;
     }
+  }
+  if (c->prm.time_order == 1 && m.scatter == TAFV_SCATTER_GATHER) {
+    const int64_t gc = cells_active(m, tau_s).count(), fc = faces_active(m, tau_s).count();
+    if (pipelined(c, m, gc, fc)) {
+      tafv_status st = run_pipeline(c, m, a, ft, tau_s, upd, m.dt_min, false, gc, fc,
+                                    cells_gather(m, tau_s, upd).count());
+      if (st != TAFV_OK) return st;
+      end_subiteration(m, acc, s, cells_upto_tau(m, upd), fc);
+      return TAFV_OK;
+    }
+  }
+  bool fuse = false;
+  if (c->prm.order == 2 && c->prm.time_order == 1) {
+    const CellRange r = cells_active(m, tau_s);
+    fuse = m.scatter == TAFV_SCATTER_GATHER && fuse_local_faces(c, m, ft, r.count());
+    ProfScope ps(c, fuse ? P_GRAD_FLUX : P_GRAD, r.count());
+    if (fuse) HIP_TRY(c, launch_grad_flux(c->stream, m, a, tau_s, ft, false));
+    else HIP_TRY(c, launch_grad(c->stream, m, a, r, tau_s));
   }
   int64_t ucnt = cells_upto_tau(m, upd);
   int64_t faces = 0;
@@ -747,6 +804,39 @@ tafv_status upload_host_mesh(tafv_ctx* c, const HostMesh& hm, DevMesh** out) {
       chk(up(m->fxR, fxR));
     }
   }
+  if (m->scatter == TAFV_SCATTER_GATHER && c->prm.order == 2 && c->prm.time_order == 1 &&
+      c->prm.pipeline_chunks > 1 && !c->batch && hm.nc > 0 && nf > 0) {
+    // chunks of consecutive cells (multiples of a block of kFuseChunk cells,
+    // one launch block); the faces are in
+    // the order of their lower cell, and no face may reach past the next
+    // chunk (a chunk's faces need the gradients of it and the next one)
+    const int K = c->prm.pipeline_chunks;
+    std::vector<int32_t> pc(K + 1), pf(K + 1);
+    for (int k = 0; k <= K; ++k)
+      pc[k] = (int32_t)std::min<int64_t>(
+          hm.nc, ((hm.nc * k / K + kFuseChunk - 1) / kFuseChunk) * kFuseChunk);
+    pc[K] = (int32_t)hm.nc;
+    bool ok = true;
+    int64_t span = 0;
+    for (size_t f = 0; f < nf && ok; ++f) {
+      const int32_t lo = hm.fhL[f] >> 2;
+      if (f > 0 && lo < (hm.fhL[f - 1] >> 2)) ok = false;
+      if (hm.fhR[f] >= 0) span = std::max<int64_t>(span, (hm.fhR[f] >> 2) - lo);
+    }
+    for (int k = 0; k < K && ok; ++k)
+      if (pc[k + 1] - pc[k] < span || pc[k + 1] <= pc[k]) ok = false;
+    if (ok) {
+      size_t f = 0;
+      for (int k = 0; k <= K; ++k) {
+        while (f < nf && (hm.fhL[f] >> 2) < pc[k]) ++f;
+        pf[k] = (int32_t)f;
+      }
+      pf[K] = (int32_t)nf;
+      m->pipe_k = K;
+      m->pipe_c = pc;
+      m->pipe_f = pf;
+    }
+  }
   // the time-step minimum slots start at +inf (each classification sets
   // them back once it has read them)
   chk(launch_fill_u64(c->stream, m->dmin, 0x7ff0000000000000ull, kCounterWords));
@@ -783,6 +873,7 @@ tafv_status tafv_params_default(tafv_params* p) {
   p->guess_strength = 0.0;
   p->time_order = 1;
   p->fuse_faces = 0;
+  p->pipeline_chunks = 1;
   return TAFV_OK;
 }
 
@@ -811,6 +902,8 @@ tafv_status tafv_create(int device, const tafv_params* params, void* hip_stream,
     return fail(nullptr, TAFV_E_ARG, "time_order must be 1 or 2");
   if (p.fuse_faces != 0 && p.fuse_faces != 1)
     return fail(nullptr, TAFV_E_ARG, "fuse_faces must be 0 or 1");
+  if (p.pipeline_chunks < 0 || p.pipeline_chunks > 64)
+    return fail(nullptr, TAFV_E_ARG, "pipeline_chunks must be in 0..64");
   if (p.time_order == 2 && (p.batch || p.scatter != TAFV_SCATTER_GATHER))
     return fail(nullptr, TAFV_E_ARG,
                 "the predictor/corrector form needs gather scatter and no batch");

@@ -109,10 +109,23 @@ hipError_t launch_grad_flux(hipStream_t s, DevMesh& m, const StepArgs& a, int ta
 // whether a gradient launch over `count` cells of the tau_g list takes the
 // whole mesh in its own order (cells outside the key range skipped)
 bool grad_whole_mesh(const DevMesh& m, int64_t count);
+// the same for a flux launch over `count` faces
+bool faces_whole_mesh(const DevMesh& m, int64_t count);
 hipError_t launch_cell_gather(hipStream_t s, DevMesh& m, const ListRanges& r, int tau_s,
                               int tau_upd, double dt_min, int precision,
                               bool dt_min_on_device = false);
 hipError_t launch_update(hipStream_t s, DevMesh& m, CellRange r, int tau_upd);
+// the stages of a pipelined whole-mesh subiteration (gather mode, time
+// order 1): gradients of the cells [c0, c1) of tau_g <= tau_s; fluxes of the
+// faces [f0, f1) of tau_f <= tau_s in face order; the gather of the cells
+// [c0, c1)
+hipError_t launch_grad_chunk(hipStream_t s, DevMesh& m, const StepArgs& a, int tau_s, int c0,
+                             int c1);
+hipError_t launch_flux_chunk(hipStream_t s, DevMesh& m, const StepArgs& a,
+                             const FluxFeatures& ft, int tau_s, int f0, int f1,
+                             bool dt_min_on_device);
+hipError_t launch_gather_chunk(hipStream_t s, DevMesh& m, int tau_s, int tau_upd, double dt_min,
+                               int precision, int c0, int c1, bool dt_min_on_device);
 // moving mesh: face volume rates sF from node velocities d_vel [n_nodes][3]
 hipError_t launch_face_speed(hipStream_t s, DevMesh& m, const double* d_vel);
 // one double per cell to the caller's order

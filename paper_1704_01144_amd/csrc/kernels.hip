@@ -458,7 +458,7 @@ __global__ __launch_bounds__(64) void k_part_scatter(int n, Key key1, int K1, W1
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_grad(GradArgs<T> a) {
   __shared__ T sStage[kBlock / 64][kStageVals];
-  const int b0 = xcd_block() * kBlock;
+  const int b0 = a.first + xcd_block() * kBlock;
   const int idx = b0 + threadIdx.x;
   const int w0 = b0 + (threadIdx.x & ~63);  // the wave's first item
   if (w0 >= a.count) return;                // the whole wave is past the end
@@ -635,8 +635,9 @@ __global__ __launch_bounds__(kBlock) void k_cell_gather(int count, const int* __
                                                         double* __restrict__ U,
                                                         double* __restrict__ R, int tau_s,
                                                         int tau_upd, unsigned long long* dscal,
-                                                        int dt_min_on_device) {
-  int idx = xcd_block() * kBlock + threadIdx.x;
+                                                        int dt_min_on_device, int first) {
+  // first: a whole-mesh launch over the cells [first, count)
+  int idx = first + xcd_block() * kBlock + threadIdx.x;
   if (idx >= count) return;
   // dt_min_on_device: a launch enqueued before the host read dt_min back
   if (dt_min_on_device) dt_min = __longlong_as_double((long long)dscal[0]);
@@ -899,6 +900,7 @@ hipError_t launch_from_caller_i8(hipStream_t s, DevMesh& m, const int8_t* src, i
 // L2 when read again.
 static bool whole_mesh(int64_t count, int64_t nc) { return count * 100 >= kWholeMeshPct * nc; }
 bool grad_whole_mesh(const DevMesh& m, int64_t count) { return whole_mesh(count, m.nc); }
+bool faces_whole_mesh(const DevMesh& m, int64_t count) { return whole_mesh(count, m.nf); }
 
 hipError_t launch_grad(hipStream_t s, DevMesh& m, const StepArgs& a, CellRange r, int tau_g,
                        const double* U) {
@@ -1008,10 +1010,8 @@ hipError_t launch_flux(hipStream_t s, DevMesh& m, const StepArgs& a, int first, 
   // between chunks, whose records point into the compact face values
   const bool compact1 = m.split_local && count > 0;
   // most faces active: walk all faces in face order instead of the list
-  // (FP64 flux: measured faster there, slower with FP32 flux)
   const bool face_order = key_max >= 0 && !m.split_local && first == 0 && count2 <= 0 &&
-                          m.scatter == TAFV_SCATTER_GATHER && a.precision == TAFV_FP64 &&
-                          whole_mesh(count, m.nf);
+                          m.scatter == TAFV_SCATTER_GATHER && whole_mesh(count, m.nf);
   if (count <= 0) {  // the second range alone
     first = first2;
     count = count2;
@@ -1091,11 +1091,87 @@ hipError_t launch_cell_gather(hipStream_t s, DevMesh& m, const ListRanges& r, in
   if (precision == TAFV_FP32_FLUX)
     hipLaunchKernelGGL(k_cell_gather<float>, dim3(blocks_for(count)), dim3(kBlock), 0, s, count,
                        list, r, m.nc, m.fpack, m.c2f, (const float*)m.Q, dt_min,
-                       m.vol, m.U, m.R, tau_s, tau_upd, m.dscal, dt_min_on_device ? 1 : 0);
+                       m.vol, m.U, m.R, tau_s, tau_upd, m.dscal, dt_min_on_device ? 1 : 0, 0);
   else
     hipLaunchKernelGGL(k_cell_gather<double>, dim3(blocks_for(count)), dim3(kBlock), 0, s, count,
                        list, r, m.nc, m.fpack, m.c2f, (const double*)m.Q, dt_min,
-                       m.vol, m.U, m.R, tau_s, tau_upd, m.dscal, dt_min_on_device ? 1 : 0);
+                       m.vol, m.U, m.R, tau_s, tau_upd, m.dscal, dt_min_on_device ? 1 : 0, 0);
+  return hipGetLastError();
+}
+
+// One stage of a pipelined whole-mesh subiteration: the gradients of the
+// cells [c0, c1) of tau_g <= tau_s, or the fluxes of the faces [f0, f1) of
+// tau_f <= tau_s in face order, or the gather of the cells [c0, c1).
+hipError_t launch_grad_chunk(hipStream_t s, DevMesh& m, const StepArgs& a, int tau_s, int c0,
+                             int c1) {
+  if (c1 <= c0) return hipSuccess;
+  const dim3 grid(blocks_for(c1 - c0)), block(kBlock);
+  if (a.precision == TAFV_FP32_FLUX) {
+    GradArgs<float> g{nullptr, c1, m.nc, m.nf, m.U, m.nb_, m.grc32, m.fA, (float*)m.Wf,
+                      a.gas.gm1, a.boundary, nullptr, 0, 0, m.ckey, tau_s};
+    g.first = c0;
+    hipLaunchKernelGGL(k_grad<float>, grid, block, 0, s, g);
+  } else {
+    GradArgs<double> g{nullptr, c1, m.nc, m.nf, m.U, m.nb_, m.grc, m.fA, (double*)m.Wf,
+                       a.gas.gm1, a.boundary, nullptr, 0, 0, m.ckey, tau_s};
+    g.first = c0;
+    hipLaunchKernelGGL(k_grad<double>, grid, block, 0, s, g);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_flux_chunk(hipStream_t s, DevMesh& m, const StepArgs& a,
+                             const FluxFeatures& ft, int tau_s, int f0, int f1,
+                             bool dt_min_on_device) {
+  if (f1 <= f0) return hipSuccess;
+  const int n = f1 - f0;
+  const unsigned long long* dtd = dt_min_on_device ? m.dscal : nullptr;
+  if (a.precision == TAFV_FP32_FLUX) {
+    FluxArgs<float> f{m.frec, f1, m.nf, m.nc, m.fA32, m.U, (const float*)m.Wf, m.R, (float*)m.Q,
+                      m.dcount, m.dimpulse, a, ft.mlp, ft.log_rows, ft.log_count, ft.log_cap,
+                      ft.log_rate, ft.log_seed, ft.subit, ft.guess_gate, ft.guess_strength,
+                      0, nullptr, nullptr, dtd};
+    f.dnewton = (ft.feat & 1) ? m.dnewton : nullptr;
+    f.fkey = m.fkey;
+    f.key_max = tau_s;
+    f.fhL = m.fhL;
+    f.fhR = m.fhR;
+    f.ffirst = f0;
+    if (ft.feat && a.gas.is14) flux_feat_launch<float>(s, a.order, ft.feat, n, f);
+    else if (a.gas.is14) flux_launch<float, true>(s, a.order, m.scatter, n, f);
+    else flux_launch<float, false>(s, a.order, m.scatter, n, f);
+  } else {
+    FluxArgs<double> f{m.frec, f1, m.nf, m.nc, m.fA, m.U, (const double*)m.Wf, m.R, (double*)m.Q,
+                       m.dcount, m.dimpulse, a, ft.mlp, ft.log_rows, ft.log_count, ft.log_cap,
+                       ft.log_rate, ft.log_seed, ft.subit, ft.guess_gate, ft.guess_strength,
+                       0, nullptr, nullptr, dtd};
+    f.dnewton = (ft.feat & 1) ? m.dnewton : nullptr;
+    f.fkey = m.fkey;
+    f.key_max = tau_s;
+    f.fhL = m.fhL;
+    f.fhR = m.fhR;
+    f.ffirst = f0;
+    if (ft.feat && a.gas.is14) flux_feat_launch<double>(s, a.order, ft.feat, n, f);
+    else if (a.gas.is14) flux_launch<double, true>(s, a.order, m.scatter, n, f);
+    else flux_launch<double, false>(s, a.order, m.scatter, n, f);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_gather_chunk(hipStream_t s, DevMesh& m, int tau_s, int tau_upd, double dt_min,
+                               int precision, int c0, int c1, bool dt_min_on_device) {
+  if (c1 <= c0) return hipSuccess;
+  const ListRanges none{};
+  const dim3 grid(blocks_for(c1 - c0)), block(kBlock);
+  if (precision == TAFV_FP32_FLUX)
+    hipLaunchKernelGGL(k_cell_gather<float>, grid, block, 0, s, c1, (const int*)nullptr, none, m.nc,
+                       m.fpack,
+                       m.c2f, (const float*)m.Q, dt_min, m.vol, m.U, m.R, tau_s, tau_upd,
+                       m.dscal, dt_min_on_device ? 1 : 0, c0);
+  else
+    hipLaunchKernelGGL(k_cell_gather<double>, grid, block, 0, s, c1, (const int*)nullptr, none,
+                       m.nc, m.fpack, m.c2f, (const double*)m.Q, dt_min, m.vol, m.U, m.R, tau_s,
+                       tau_upd, m.dscal, dt_min_on_device ? 1 : 0, c0);
   return hipGetLastError();
 }
 

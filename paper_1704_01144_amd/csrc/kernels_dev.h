@@ -257,6 +257,8 @@ struct GradArgs {
   // among those of the cell] instead of Wf
   T* Wx = nullptr;
   const int* xb = nullptr;
+  // whole-mesh launches: the items are the cells first + idx < count
+  int first = 0;
 };
 
 // cells per chunk of the compact cross-chunk face values (a block's cells
@@ -492,6 +494,7 @@ struct FluxArgs {
   int key_max = 0;
   const int* fhL = nullptr;
   const int* fhR = nullptr;
+  int ffirst = 0;  // face-order launches: the faces ffirst + idx < count
 };
 
 
@@ -564,10 +567,11 @@ __device__ inline int4 nt_rec(const int4* p) {
 template <typename T>
 __device__ inline bool flux_item(const FluxArgs<T>& a, int idx, int4& r) {
   if (a.fkey) {
-    const int f = idx < a.count ? idx : a.count - 1;
+    const int fi = a.ffirst + idx;
+    const int f = fi < a.count ? fi : a.count - 1;
     const int k = a.fkey[f], hl = a.fhL[f], hr = a.fhR[f];
     r = make_int4(f, hl, hr, k);
-    return idx < a.count && k <= a.key_max;
+    return fi < a.count && k <= a.key_max;
   }
   if (idx >= a.count) {
     r = make_int4(0, 0, -1, 0);

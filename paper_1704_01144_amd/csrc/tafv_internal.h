@@ -106,6 +106,11 @@ struct DevMesh {
   // list (see LocalFaces).  While split_local is set (chosen at each
   // classification: the fused launches can run), the face list is sorted by
   // tau_f + 8 flocal, the faces between chunks first.
+  // pipelined whole-mesh subiterations: chunk k holds cells
+  // [pipe_c[k], pipe_c[k + 1]) and the faces [pipe_f[k], pipe_f[k + 1])
+  // whose first (lower) cell lies in it; pipe_k = 1: no pipeline
+  int pipe_k = 1;
+  std::vector<int32_t> pipe_c, pipe_f;
   int8_t* flocal = nullptr;  // [nf]
   int32_t* lf_start = nullptr;  // [chunks + 1]
   int2* lf_face = nullptr;      // [n_local]

@@ -40,7 +40,8 @@ class tafv_params(C.Structure):
                 ("scatter", C.c_int32), ("cell_order", C.c_int32),
                 ("guess_stats", C.c_int32), ("guess_gate", C.c_double),
                 ("batch", C.c_int32), ("guess_strength", C.c_double),
-                ("time_order", C.c_int32), ("fuse_faces", C.c_int32)]
+                ("time_order", C.c_int32), ("fuse_faces", C.c_int32),
+                ("pipeline_chunks", C.c_int32)]
 
 
 class tafv_stats(C.Structure):

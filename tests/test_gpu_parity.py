@@ -394,3 +394,43 @@ def test_fused_local_faces_learned_guess(T, precision):
         assert sa[key] == sb[key], (key, sa[key], sb[key])
     assert sa["guess_used"] > 0
     say(f"learned guess fused: identical bits, network start on {sa['guess_used']} faces")
+
+
+@pytest.mark.parametrize("precision,guess,stats", [(0, 0, 0), (1, 0, 0), (1, 1, 0), (0, 0, 1)],
+                         ids=["fp64", "fp32", "fp32-learned", "fp64-stats"])
+def test_pipelined_subiterations_bit_identical(T, precision, guess, stats):
+    """Whole-mesh subiterations as a pipeline over chunks of consecutive
+    cells (gradient of chunk k + 1, fluxes of chunk k's faces, gather of
+    chunk k - 1) against the unpipelined launches: the same bits and
+    counters; with chunks smaller than the faces' reach the mesh runs
+    unpipelined."""
+    nodes, tets = I.graded_box_mesh(17, 13, 11, 8.0)
+    prim = I.blast_state(nodes, tets, centre=I.blast_centre(6))
+    theta = np.random.default_rng(11).normal(0.0, 0.2, T.MLP_PARAMS).astype(np.float32)
+    out = {}
+    for k in (1, 4, 7, 16):
+        kw = dict(guess=T.GUESS_MLP, guess_gate=0.0) if guess else {}
+        s = T.Solver(max_levels=5, order=2, precision=precision, guess_stats=stats,
+                     pipeline_chunks=k, **kw)
+        s.upload(nodes, tets)
+        if guess:
+            T.tafv_mlp_set(s.ctx, theta)
+        s.init(prim)
+        for n in (1, 6, 9, 16):
+            s.advance(n)
+        out[k] = (s.checkpoint(), s.stats())
+        s.close()
+    a, sa = out[1]
+    for k in (4, 7, 16):
+        b, sb = out[k]
+        for key in ("levels", "cons", "accum"):
+            diff = a[key] != b[key]
+            ne = np.flatnonzero(diff.any(axis=1) if diff.ndim > 1 else diff)
+            assert ne.size == 0, (k, key, ne[:8])
+        for key in ("cell_updates", "face_solves", "newton_updates", "guess_evaluated",
+                    "guess_used", "guess_faces"):
+            assert sa[key] == sb[key], (k, key, sa[key], sb[key])
+        if stats:
+            assert sa["newton_hist"] == sb["newton_hist"], k
+    say(f"pipelined subiterations: identical bits for 4, 7 and 16 chunks "
+        f"({sa['face_solves']} face solves)")
