@@ -190,33 +190,48 @@ __global__ __launch_bounds__(256) void k_b_reduce(const int32_t* __restrict__ rp
   }
 }
 
+// levels from each mesh's dt ratio together with the first lowering sweep
+// (a neighbour's level is classified from its own time step)
 __global__ __launch_bounds__(kBlock) void k_b_classify(const int32_t* __restrict__ rp,
-                                                       const BatchSched* S, int M,
+                                                       const BatchSched* S, int M, int NC,
                                                        const double* __restrict__ dt,
-                                                       double margin, int8_t* __restrict__ lev) {
+                                                       double margin,
+                                                       const int* __restrict__ nb,
+                                                       int8_t* __restrict__ lev) {
   STAGE_PREFIX(rp);
   const int total = s_pre[M];
   TILE_LOOP(total, 1) {
     int m = find_mesh(s_pre, M, t);
     int i = S[m].c0 + (t - s_pre[m]) * kBlock + threadIdx.x;
-    if (i < S[m].c0 + S[m].nc)
-      lev[i] = classify_item(dt[i], __longlong_as_double((long long)S[m].dtbits), margin, S[m].L);
+    if (i < S[m].c0 + S[m].nc) {
+      const double dtmin = __longlong_as_double((long long)S[m].dtbits);
+      const int L = S[m].L;
+      int n[4];
+      double dn[4];
+      for (int q = 0; q < 4; ++q) n[q] = nb[(size_t)q * NC + i];
+      for (int q = 0; q < 4; ++q) dn[q] = dt[n[q] >= 0 ? n[q] : i];
+      int tl = classify_item(dt[i], dtmin, margin, L);
+      for (int q = 0; q < 4; ++q)
+        if (n[q] >= 0) tl = min(tl, classify_item(dn[q], dtmin, margin, L) + 1);
+      lev[i] = (int8_t)tl;
+    }
   }
 }
 
-// sweep k of the even count S: meshes whose own L - 1 sweeps are done copy
-// their levels across instead (further sweeps would change nothing)
+// lowering sweep k >= 1 in place for the meshes with k < L - 1 (a neighbour
+// read while it is lowered gives its old or new level, both at or above the
+// final one, so L - 1 sweeps reach the same levels as L - 1 Jacobi sweeps)
 __global__ __launch_bounds__(kBlock) void k_b_sweep(const int32_t* __restrict__ rp,
                                                     const BatchSched* S, int M, int NC, int k,
                                                     const int* __restrict__ nb,
-                                                    const int8_t* __restrict__ src,
-                                                    int8_t* __restrict__ dst) {
+                                                    int8_t* lev) {
   STAGE_PREFIX(rp);
   const int total = s_pre[M];
   TILE_LOOP(total, 1) {
     int m = find_mesh(s_pre, M, t);
+    if (k >= S[m].L - 1) continue;
     int i = S[m].c0 + (t - s_pre[m]) * kBlock + threadIdx.x;
-    if (i < S[m].c0 + S[m].nc) dst[i] = k < S[m].L - 1 ? sweep_item(i, NC, nb, src) : src[i];
+    if (i < S[m].c0 + S[m].nc) lev[i] = sweep_item(i, NC, nb, lev);
   }
 }
 
@@ -860,17 +875,12 @@ hipError_t run_reclass(tafv_ctx* c, hipStream_t s) {
                      m.vol, m.c2f, m.fA, c->prm.gamma, c->prm.cfl, m.dt, B.tmin, flag);
   hipLaunchKernelGGL(k_b_reduce, dim3(M), dim3(256), 0, s, rc, B.dsched, M, B.tmin,
                      (const int*)nullptr);
-  hipLaunchKernelGGL(k_b_classify, dim3(G), dim3(kBlock), lds, s, rc, B.dsched, M, m.dt,
-                     c->prm.level_margin, m.lev);
-  // lowering sweeps: an even count >= lmax - 1 leaves the result in lev
-  int sweeps = B.lmax - 1;
-  sweeps += sweeps & 1;
-  for (int k = 0; k < sweeps; ++k) {
-    const int8_t* src = (k & 1) ? m.lev2 : m.lev;
-    int8_t* dst = (k & 1) ? m.lev : m.lev2;
+  hipLaunchKernelGGL(k_b_classify, dim3(G), dim3(kBlock), lds, s, rc, B.dsched, M, m.nc, m.dt,
+                     c->prm.level_margin, m.nb_, m.lev);
+  // the classification took the first of the L - 1 lowering sweeps
+  for (int k = 1; k < B.lmax - 1; ++k)
     hipLaunchKernelGGL(k_b_sweep, dim3(G), dim3(kBlock), lds, s, rc, B.dsched, M, m.nc, k,
-                       m.nb_, src, dst);
-  }
+                       m.nb_, m.lev);
   hipLaunchKernelGGL(k_b_cell_keys, dim3(G), dim3(kBlock), lds, s, rc, B.dsched, M, m.nc, m.nb_,
                      m.lev, m.ckey, m.fpack, B.thist);
   hipLaunchKernelGGL(k_b_cell_early, dim3(G), dim3(kBlock), lds, s, rc, B.dsched, M, m.nc, m.nb_,
