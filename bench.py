@@ -41,14 +41,17 @@ BYTES_PER_ITEM = {
     "fp64": {"flux": 278, "grad": 316, "update": 172},
     "fp32": {"flux": 226, "grad": 188, "update": 172},
 }
-# gather mode: the flux kernel reads a 16-byte face record, the area vector,
-# two reconstructed states and writes one flux (5 values in the flux
-# precision); the cell kernel reads its index, its packed level word, 4 face
-# ids, the active faces' fluxes (about 2 per cell), reads+writes the FP64
-# accumulator, and for ending steps the volume and state.
+# gather mode: the flux kernel reads the face's key and half-face ids (9
+# bytes; launches over most of the faces walk them in face order, which
+# carry most face solves; a launch over the level-sorted list reads a
+# 16-byte record instead), the area vector, two reconstructed states and
+# writes one flux (5 values in the flux precision); the cell kernel reads
+# its index, its packed level word, 4 face ids, the active faces' fluxes
+# (about 2 per cell), reads+writes the FP64 accumulator, and for ending steps
+# the volume and state.
 BYTES_PER_ITEM_GATHER = {
-    "fp64": {"flux": 160, "grad": 316, "gather": 270},
-    "fp32": {"flux": 88, "grad": 188, "gather": 230},
+    "fp64": {"flux": 153, "grad": 316, "gather": 270},
+    "fp32": {"flux": 81, "grad": 188, "gather": 230},
 }
 # the other forms (gather mode): the predictor/corrector form's corrector
 # pass also reads the predictor flux (5 values in the flux precision) and its
@@ -60,9 +63,9 @@ BYTES_PER_ITEM_FORM = {
     "fp64": BYTES_PER_ITEM_GATHER["fp64"],
     "fp32": BYTES_PER_ITEM_GATHER["fp32"],
     "fp32_learned": BYTES_PER_ITEM_GATHER["fp32"],
-    "time2_fp64": {"flux": 160, "flux_corrector": 200, "grad": 316, "gather": 310},
-    "time2_fp32": {"flux": 88, "flux_corrector": 108, "grad": 188, "gather": 270},
-    "moving_fp64": {"flux": 168, "grad": 316, "gather": 302},
+    "time2_fp64": {"flux": 153, "flux_corrector": 193, "grad": 316, "gather": 310},
+    "time2_fp32": {"flux": 81, "flux_corrector": 101, "grad": 188, "gather": 270},
+    "moving_fp64": {"flux": 161, "grad": 316, "gather": 302},
 }
 # kernel of each timing class, by form (names of the counter records)
 KERNEL_OF_CLASS = {"flux": "k_flux", "flux_corrector": "k_flux", "grad": "k_grad",
