@@ -804,18 +804,19 @@ __device__ inline void face_features(const Gas& G, const T* wl, const T* wr, T u
 }
 
 // The strength pre-gate |u_R - u_L| / a_m + |p_L - p_R| / p_m >= s of an
-// interior face, in FP32 and without a square root: with
-// d = s - |p_L - p_R| / p_m, it holds where d <= 0 or
-// (u_R - u_L)^2 >= d^2 a_m^2, a_m^2 = g p_m / rho_m.
+// interior face, in FP32 and without a square root or a division: with
+// D = s p_m - |p_L - p_R| (p_m times the pressure term's shortfall), it
+// holds where D <= 0 or (u_R - u_L)^2 p_m rho_m >= D^2 g
+// (a_m^2 = g p_m / rho_m; p_m, rho_m > 0).
 template <typename T>
 __device__ inline bool strength_pregate(const Gas& G, const T* wl, const T* wr, T unl, T unr,
                                         float s) {
   const float rm = 0.5f * ((float)wl[0] + (float)wr[0]);
   const float pm = 0.5f * ((float)wl[4] + (float)wr[4]);
-  const float d = s - fabsf((float)wl[4] - (float)wr[4]) / pm;
-  if (d <= 0.f) return true;
+  const float D = s * pm - fabsf((float)wl[4] - (float)wr[4]);
+  if (D <= 0.f) return true;
   const float du = (float)unr - (float)unl;
-  return du * du >= d * d * ((float)G.g * pm / rm);
+  return du * du * pm * rm >= D * D * (float)G.g;
 }
 
 // Newton updates per face solve by category, per counter slot: word
