@@ -161,32 +161,48 @@ __global__ __launch_bounds__(kBlock) void k_b_dt(const int32_t* __restrict__ rp,
 // given) or the (tau_g, tau) histogram from its tiles' histograms (thist
 // given), in place of per-tile atomics on the mesh's entry (which
 // serialised on large meshes).
-__global__ __launch_bounds__(256) void k_b_reduce(const int32_t* __restrict__ rp, BatchSched* S,
-                                                  int M, const double* __restrict__ tmin,
-                                                  const int* __restrict__ thist) {
-  __shared__ double sm[256];
-  __shared__ int sh[4][kMaxKeys];
+constexpr int kReduceThreads = 1024;
+__global__ __launch_bounds__(kReduceThreads) void k_b_reduce(const int32_t* __restrict__ rp,
+                                                             BatchSched* S, int M,
+                                                             const double* __restrict__ tmin,
+                                                             const int* __restrict__ thist) {
+  constexpr int G = kReduceThreads / 64;  // groups of 64 bins
+  __shared__ double sm[kReduceThreads];
+  __shared__ int sh[G][kMaxKeys];
   const int m = blockIdx.x;
   if (m >= M || !S[m].reclass) return;
   const int t0 = rp[m], t1 = rp[m + 1], tid = threadIdx.x;
   if (tmin) {
     double v = INFINITY;
-    for (int t = t0 + tid; t < t1; t += 256) v = fmin(v, tmin[t]);
+    for (int t = t0 + tid; t < t1; t += kReduceThreads) v = fmin(v, tmin[t]);
     sm[tid] = v;
     __syncthreads();
-    for (int off = 128; off > 0; off >>= 1) {
+    for (int off = kReduceThreads / 2; off > 0; off >>= 1) {
       if (tid < off) sm[tid] = fmin(sm[tid], sm[tid + off]);
       __syncthreads();
     }
     if (tid == 0) S[m].dtbits = (unsigned long long)__double_as_longlong(sm[0]);
   }
   if (thist) {
-    const int g = tid >> 6, k = tid & 63;  // 4 groups of 64 bins
-    int acc = 0;
-    for (int t = t0 + g; t < t1; t += 4) acc += thist[(size_t)t * kMaxKeys + k];
-    sh[g][k] = acc;
+    // group g sums tiles t0 + g, t0 + g + G, ...; four loads in flight per
+    // thread
+    const int g = tid >> 6, k = tid & 63;
+    int a0 = 0, a1 = 0, a2 = 0, a3 = 0;
+    int t = t0 + g;
+    for (; t + 3 * G < t1; t += 4 * G) {
+      a0 += thist[(size_t)t * kMaxKeys + k];
+      a1 += thist[(size_t)(t + G) * kMaxKeys + k];
+      a2 += thist[(size_t)(t + 2 * G) * kMaxKeys + k];
+      a3 += thist[(size_t)(t + 3 * G) * kMaxKeys + k];
+    }
+    for (; t < t1; t += G) a0 += thist[(size_t)t * kMaxKeys + k];
+    sh[g][k] = (a0 + a1) + (a2 + a3);
     __syncthreads();
-    if (tid < kMaxKeys) S[m].hist[tid] = sh[0][tid] + sh[1][tid] + sh[2][tid] + sh[3][tid];
+    if (tid < kMaxKeys) {
+      int sum = 0;
+      for (int q = 0; q < G; ++q) sum += sh[q][tid];
+      S[m].hist[tid] = sum;
+    }
   }
 }
 
@@ -873,7 +889,7 @@ hipError_t run_reclass(tafv_ctx* c, hipStream_t s) {
                      B.ft, B.cc, B.fc, B.rp);
   hipLaunchKernelGGL(k_b_dt, dim3(G), dim3(kBlock), lds, s, rc, B.dsched, M, m.nc, m.nf, m.U,
                      m.vol, m.c2f, m.fA, c->prm.gamma, c->prm.cfl, m.dt, B.tmin, flag);
-  hipLaunchKernelGGL(k_b_reduce, dim3(M), dim3(256), 0, s, rc, B.dsched, M, B.tmin,
+  hipLaunchKernelGGL(k_b_reduce, dim3(M), dim3(kReduceThreads), 0, s, rc, B.dsched, M, B.tmin,
                      (const int*)nullptr);
   hipLaunchKernelGGL(k_b_classify, dim3(G), dim3(kBlock), lds, s, rc, B.dsched, M, m.nc, m.dt,
                      c->prm.level_margin, m.nb_, m.lev);
@@ -885,7 +901,8 @@ hipError_t run_reclass(tafv_ctx* c, hipStream_t s) {
                      m.lev, m.ckey, m.fpack, B.thist);
   hipLaunchKernelGGL(k_b_cell_early, dim3(G), dim3(kBlock), lds, s, rc, B.dsched, M, m.nc, m.nb_,
                      m.lev, m.ckey, m.fpack, c->prm.order);
-  hipLaunchKernelGGL(k_b_reduce, dim3(M), dim3(256), 0, s, rc, B.dsched, M, nullptr, B.thist);
+  hipLaunchKernelGGL(k_b_reduce, dim3(M), dim3(kReduceThreads), 0, s, rc, B.dsched, M, nullptr,
+                     B.thist);
   hipLaunchKernelGGL(k_b_face_keys, dim3(G), dim3(kBlock), lds, s, rf, B.dsched, M, m.fhL, m.fhR,
                      m.lev, m.fkey);
   const int PG = 4 * G;  // 64-thread blocks
