@@ -67,10 +67,26 @@ __device__ inline int mesh_after(const int32_t* __restrict__ tp, int m0, int u) 
   return m;
 }
 
-// Tiles of a launch: block b (XCD-remapped rank r) takes tiles
-// [(k G + r) grab, (k G + r + 1) grab) for k = 0, 1, ...  Block-uniform.
-#define TILE_LOOP(total, grab)                                                       \
-  for (int base_ = xcd_block() * (grab); base_ < (total); base_ += gridDim.x * (grab)) \
+// The grids here are sized before the work is known (persistent grids, or
+// the static count of a work class), so often only part of a grid has work.
+// The hardware hands blocks out in index order, round-robin over the 8 XCDs:
+// the first n blocks are the ones that work, spread over all XCDs, each
+// taking its XCD-remapped rank among those n (with ranks over the whole
+// grid, the working ranks would sit on the first XCDs only).
+// Number of blocks that take part in a loop over `count` items:
+__device__ inline int loop_blocks(int count) { return min((int)gridDim.x, count); }
+// This block's rank among them, or `count` for a block that does not:
+__device__ inline int loop_rank(int count) {
+  const int n = loop_blocks(count);
+  return (int)blockIdx.x < n ? xcd_rank((int)blockIdx.x, n) : count;
+}
+
+// Tiles of a launch: with n blocks taking part, block rank r takes tiles
+// [(k n + r) grab, (k n + r + 1) grab) for k = 0, 1, ...  Block-uniform.
+#define TILE_LOOP(total, grab)                                                      \
+  for (int n_ = loop_blocks(((total) + (grab) - 1) / (grab)),                        \
+           base_ = loop_rank(((total) + (grab) - 1) / (grab)) * (grab);             \
+       base_ < (total); base_ += n_ * (grab))                                        \
     for (int t = base_, tend_ = min(base_ + (grab), (total)); t < tend_; ++t)
 
 // The prefix array of a launch (M + 1 ints) is staged in LDS, where the
@@ -327,7 +343,7 @@ __global__ __launch_bounds__(64) void k_b_part_count(const int32_t* __restrict__
   __shared__ int cnt[kMaxLevels];
   const int lane = threadIdx.x;
   const int total = s_pre[M];
-  for (int t = xcd_block(); t < total; t += gridDim.x) {
+  for (int t = loop_rank(total), n_ = loop_blocks(total); t < total; t += n_) {
     int m = find_mesh(s_pre, M, t);
     int j = t - s_pre[m], nch = cp[m + 1] - cp[m];
     int b0 = faces ? S[m].f0 : S[m].c0;
@@ -401,7 +417,7 @@ __global__ __launch_bounds__(64) void k_b_part_scatter(const int32_t* __restrict
   const int lane = threadIdx.x;
   const unsigned long long lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
   const int total = s_pre[M];
-  for (int t = xcd_block(); t < total; t += gridDim.x) {
+  for (int t = loop_rank(total), n_ = loop_blocks(total); t < total; t += n_) {
     int m = find_mesh(s_pre, M, t);
     int j = t - s_pre[m], nch = cp[m + 1] - cp[m];
     int b0 = faces ? S[m].f0 : S[m].c0;
@@ -538,8 +554,8 @@ __global__ __launch_bounds__(BS) void k_b_grad(const int32_t* __restrict__ tp,
       }
     }
   } else {
-    const int u0 = xcd_block() * Q, u = u0 + wv;
-    if (u >= tp[M]) return;  // no barrier follows
+    const int total = tp[M], u0 = loop_rank((total + Q - 1) / Q) * Q, u = u0 + wv;
+    if (u >= total) return;  // no barrier follows
     int m = mesh_after(tp, find_mesh(tp, M, u0), u);
     int j0 = (u - tp[m]) * kUnit, j = j0 + lane;
     bool valid = j < S[m].n_grad;
@@ -556,7 +572,7 @@ __global__ __launch_bounds__(kBlock) void k_b_flux(const int32_t* __restrict__ t
                                                    const BatchSched* S, int M, FluxArgs<T> a) {
   constexpr int Q = kBlock / kUnit;
   const int total = tp[M];
-  const int u0 = xcd_block() * Q;
+  const int u0 = loop_rank((total + Q - 1) / Q) * Q;
   if (u0 >= total) return;  // the whole block
   const int u = u0 + (int)(threadIdx.x / kUnit);
   SolveInfo info{0, 0, 0, 0, 0, 0, 0, 0};
@@ -577,7 +593,7 @@ void k_b_flux_feat(const int32_t* __restrict__ tp, const BatchSched* S, int M, F
   __shared__ __attribute__((aligned(16))) uint16_t lds[(FEAT & 2) ? (kBlock / 64) * kMlpFwdLds : 8];
   constexpr int Q = kBlock / kUnit;
   const int total = tp[M];
-  const int u0 = xcd_block() * Q;
+  const int u0 = loop_rank((total + Q - 1) / Q) * Q;
   if (u0 >= total) return;  // the whole block
   const int u = u0 + (int)(threadIdx.x / kUnit);
   SolveInfo info{0, 0, 0, 0, 0, 0, 0, 0};
@@ -621,8 +637,8 @@ __global__ __launch_bounds__(BS) void k_b_gather(const int32_t* __restrict__ tp,
       }
     }
   } else {
-    const int u0 = xcd_block() * QU, u = u0 + wv;
-    if (u >= tp[M]) return;  // no barrier follows
+    const int total = tp[M], u0 = loop_rank((total + QU - 1) / QU) * QU, u = u0 + wv;
+    if (u >= total) return;  // no barrier follows
     int m = mesh_after(tp, find_mesh(tp, M, u0), u);
     int j = (u - tp[m]) * kUnit + lane;
     if (j < S[m].n_gather)
