@@ -71,8 +71,9 @@ __device__ inline int mesh_after(const int32_t* __restrict__ tp, int m0, int u) 
 // the static count of a work class), so often only part of a grid has work.
 // The hardware hands blocks out in index order, round-robin over the 8 XCDs:
 // the first n blocks are the ones that work, spread over all XCDs, each
-// taking its XCD-remapped rank among those n (with ranks over the whole
-// grid, the working ranks would sit on the first XCDs only).
+// taking its XCD-remapped rank among those n (ranks over the whole grid
+// would leave the working ranks unevenly spread over the XCDs, and the
+// persistent loops' strides would not match the working blocks).
 // Number of blocks that take part in a loop over `count` items:
 __device__ inline int loop_blocks(int count) { return min((int)gridDim.x, count); }
 // This block's rank among them, or `count` for a block that does not:

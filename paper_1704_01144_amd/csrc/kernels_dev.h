@@ -17,12 +17,20 @@ constexpr int kCountSlots = kCounterSlots;
 constexpr int kSlotStride = kCounterStride;  // 128 bytes between slots
 
 // Blocks are dispatched round-robin over the 8 XCDs (block b -> XCD b % 8).
-// Remap so that each XCD works on one contiguous range of the list: its
-// neighbour gathers then hit the L2 of that XCD.
+// Remap so that each XCD works on runs of kXcdRun consecutive ranks (4096
+// items of 256-thread blocks), the runs dealt round-robin to the XCDs: the
+// neighbour gathers of a run mostly hit the L2 of its XCD, and work that
+// clusters in space (the active cells and faces of a subiteration, the
+// faces that need more Newton updates) still spreads over all XCDs.  Runs
+// of 1/8 of the launch each (one contiguous range per XCD) left the XCDs
+// unevenly loaded; one block per run loses the L2 locality.  Ranks past the
+// last whole round of runs keep their index.
+constexpr int kXcdRun = 16;
 __device__ inline int xcd_rank(int b, int n) {
-  int q = n >> 3;
-  if (b < (q << 3)) return (b & 7) * q + (b >> 3);
-  return b;
+  const int full = (n / (8 * kXcdRun)) * (8 * kXcdRun);
+  if (b >= full) return b;
+  const int x = b & 7, i = b >> 3;  // the block's XCD and its index there
+  return ((i / kXcdRun) * 8 + x) * kXcdRun + i % kXcdRun;
 }
 __device__ inline int xcd_block() { return xcd_rank(blockIdx.x, gridDim.x); }
 
