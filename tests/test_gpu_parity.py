@@ -237,16 +237,18 @@ def test_error_codes(T):
     assert e.value.code == T.E_ARG
 
 
-@SCATTERS
-def test_full_scale_one_subiteration(T, orc, scatter):
-    """The 64^3 graded mesh (1,572,864 cells) in the benchmark's launch
-    configuration: levels at t = 0 equal the oracle's classification, and
-    one full subiteration and one level-0 subiteration, started from the
-    device checkpoint, match the oracle cell by cell."""
+@pytest.mark.parametrize("scatter,cell_order", [(0, 0), (1, 0), (1, 1)],
+                         ids=["colour", "gather", "gather-morton"])
+def test_full_scale_one_subiteration(T, orc, scatter, cell_order):
+    """The 64^3 graded mesh (1,572,864 cells), also in the benchmark's launch
+    configuration (gather, cells in Morton order inside the library):
+    levels at t = 0 equal the oracle's classification, and one full
+    subiteration and one level-0 subiteration, started from the device
+    checkpoint, match the oracle cell by cell."""
     cfg = I.config_scale(64, 0)
     nodes, tets, prim = cfg["nodes"], cfg["tets"], cfg["prim"]
-    say(f"full scale: upload, scatter {scatter}")
-    s = T.Solver(max_levels=5, order=2, scatter=scatter)
+    say(f"full scale: upload, scatter {scatter}, cell order {cell_order}")
+    s = T.Solver(max_levels=5, order=2, scatter=scatter, cell_order=cell_order)
     s.upload(nodes, tets)
     s.init(prim)
     m = orc.Mesh(nodes, tets)
@@ -297,13 +299,15 @@ def full_oracle(orc):
 
 def test_full_scale_whole_run(T, full_oracle):
     """The benchmark step itself (32 units from the initial state, the
-    benchmark's launch configuration) against the oracle, every cell:
+    benchmark's launch configuration, cells in Morton order inside the
+    library, and in the mesh's own order) against the oracle, every cell:
     FP64 to 1e-12 normwise with identical levels and counters; the FP32
     form within the L1 bound."""
     cfg = full_oracle["cfg"]
     vol = None
-    for prec in (T.FP64, T.FP32_FLUX):
-        s = T.Solver(max_levels=5, order=2, precision=prec)
+    for prec, cell_order in ((T.FP64, 1), (T.FP32_FLUX, 1), (T.FP64, 0), (T.FP32_FLUX, 0)):
+        say(f"full run: precision {prec}, cell order {cell_order}")
+        s = T.Solver(max_levels=5, order=2, precision=prec, cell_order=cell_order)
         s.upload(cfg["nodes"], cfg["tets"])
         s.init(cfg["prim"])
         st = s.advance(32)

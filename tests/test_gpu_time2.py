@@ -235,18 +235,21 @@ def full_oracle2(orc):
     return dict(cfg=cfg, cons=u_o, levels=lev_o, stats=o.stats())
 
 
-def test_full_scale_whole_run(T, full_oracle2):
-    """The benchmark step in the predictor/corrector form, every cell."""
+@pytest.mark.parametrize("cell_order", [1, 0], ids=["morton", "mesh-order"])
+def test_full_scale_whole_run(T, full_oracle2, cell_order):
+    """The benchmark step in the predictor/corrector form, every cell, with
+    the cells in Morton order inside the library (the benchmark's
+    configuration) and in the mesh's own order."""
     cfg = full_oracle2["cfg"]
-    s = T.Solver(max_levels=5, order=2, time_order=2)
+    s = T.Solver(max_levels=5, order=2, time_order=2, cell_order=cell_order)
     s.upload(cfg["nodes"], cfg["tets"])
     s.init(cfg["prim"])
     st = s.advance(32)
     cons, lev = s.read()
     s.close()
     err = normwise(cons, full_oracle2["cons"])
-    say(f"full run, time order 2: err {err:.2e}, updates {st['cell_updates']}, "
-        f"face solves {st['face_solves']}")
+    say(f"full run, time order 2, cell order {cell_order}: err {err:.2e}, updates "
+        f"{st['cell_updates']}, face solves {st['face_solves']}")
     assert err <= TOL
     assert (lev == full_oracle2["levels"]).all()
     assert st["cell_updates"] == full_oracle2["stats"]["cell_updates"]
