@@ -74,13 +74,25 @@ __device__ inline int mesh_after(const int32_t* __restrict__ tp, int m0, int u) 
 // taking its XCD-remapped rank among those n (ranks over the whole grid
 // would leave the working ranks unevenly spread over the XCDs, and the
 // persistent loops' strides would not match the working blocks).
-// Number of blocks that take part in a loop over `count` items:
-__device__ inline int loop_blocks(int count) { return min((int)gridDim.x, count); }
-// This block's rank among them, or `count` for a block that does not:
-__device__ inline int loop_rank(int count) {
-  const int n = loop_blocks(count);
-  return (int)blockIdx.x < n ? xcd_rank((int)blockIdx.x, n) : count;
+// Number of blocks that take part in a loop over `count` items run by nb
+// blocks (the grid, or one of its two halves, see split_half):
+__device__ inline int loop_blocks(int count, int nb) { return min(nb, count); }
+__device__ inline int loop_blocks(int count) { return loop_blocks(count, (int)gridDim.x); }
+// The rank among them of block b of those nb, or `count` for a block that
+// does not take part:
+__device__ inline int loop_rank(int count, int b, int nb) {
+  const int n = loop_blocks(count, nb);
+  return b < n ? xcd_rank(b, n) : count;
 }
+__device__ inline int loop_rank(int count) {
+  return loop_rank(count, (int)blockIdx.x, (int)gridDim.x);
+}
+
+// Two independent loops in one launch (the face and the cell classes of a
+// reclassification step): blocks [0, h) run the first, [h, gridDim.x) the
+// second, h a multiple of 8 so that a block's XCD is its index within its
+// half modulo 8.
+__device__ inline int split_half() { return (int)(gridDim.x >> 4) << 3; }
 
 // Tiles of a launch: with n blocks taking part, block rank r takes tiles
 // [(k n + r) grab, (k n + r + 1) grab) for k = 0, 1, ...  Block-uniform.
@@ -272,27 +284,43 @@ __global__ __launch_bounds__(kBlock) void k_b_sweep(const int32_t* __restrict__ 
   }
 }
 
-__global__ __launch_bounds__(kBlock) void k_b_cell_keys(const int32_t* __restrict__ rp,
-                                                        BatchSched* S, int M, int NC,
-                                                        const int* __restrict__ nb,
-                                                        const int8_t* __restrict__ lev,
-                                                        int8_t* __restrict__ ckey,
-                                                        uint32_t* __restrict__ fpack,
-                                                        int* __restrict__ thist) {
-  STAGE_PREFIX(rp);
-  __shared__ int h[kMaxKeys];
+// Keys of the marked meshes after the sweeps, cells and faces in one
+// launch (split_half): per cell tau_g, the packed face word and its tile's
+// (tau_g, tau) histogram; per face tau_f.
+__global__ __launch_bounds__(kBlock) void k_b_keys(const int32_t* __restrict__ rc,
+                                                   const int32_t* __restrict__ rf,
+                                                   BatchSched* S, int M, int NC,
+                                                   const int* __restrict__ nb,
+                                                   const int8_t* __restrict__ lev,
+                                                   int8_t* __restrict__ ckey,
+                                                   uint32_t* __restrict__ fpack,
+                                                   int* __restrict__ thist,
+                                                   const int* __restrict__ fhL,
+                                                   const int* __restrict__ fhR,
+                                                   int8_t* __restrict__ fkey) {
+  const int h = split_half();
+  const bool faces = (int)blockIdx.x >= h;  // block-uniform
+  const int b = faces ? (int)blockIdx.x - h : (int)blockIdx.x;
+  const int nbk = faces ? (int)gridDim.x - h : h;
+  STAGE_PREFIX(faces ? rf : rc);
+  __shared__ int hs[kMaxKeys];
   const int total = s_pre[M];
-  TILE_LOOP(total, 1) {
+  for (int t = loop_rank(total, b, nbk), n_ = loop_blocks(total, nbk); t < total; t += n_) {
     int m = find_mesh(s_pre, M, t);
+    if (faces) {
+      int f = S[m].f0 + (t - s_pre[m]) * kBlock + threadIdx.x;
+      if (f < S[m].f0 + S[m].nf) fkey[f] = face_key_item(f, fhL, fhR, nullptr, lev, 0);
+      continue;
+    }
     __syncthreads();
-    for (int k = threadIdx.x; k < kMaxKeys; k += blockDim.x) h[k] = 0;
+    for (int k = threadIdx.x; k < kMaxKeys; k += blockDim.x) hs[k] = 0;
     __syncthreads();
     int i = S[m].c0 + (t - s_pre[m]) * kBlock + threadIdx.x;
     const bool in = i < S[m].c0 + S[m].nc;
     int bin = in ? cell_key_item(i, NC, nb, lev, ckey, fpack) : 0;
-    wave_hist_add(h, in, bin);
+    wave_hist_add(hs, in, bin);
     __syncthreads();
-    for (int k = threadIdx.x; k < kMaxKeys; k += blockDim.x) thist[(size_t)t * kMaxKeys + k] = h[k];
+    for (int k = threadIdx.x; k < kMaxKeys; k += blockDim.x) thist[(size_t)t * kMaxKeys + k] = hs[k];
   }
 }
 
@@ -312,21 +340,6 @@ __global__ __launch_bounds__(kBlock) void k_b_cell_early(const int32_t* __restri
   }
 }
 
-__global__ __launch_bounds__(kBlock) void k_b_face_keys(const int32_t* __restrict__ rp,
-                                                        const BatchSched* S, int M,
-                                                        const int* __restrict__ fhL,
-                                                        const int* __restrict__ fhR,
-                                                        const int8_t* __restrict__ lev,
-                                                        int8_t* __restrict__ fkey) {
-  STAGE_PREFIX(rp);
-  const int total = s_pre[M];
-  TILE_LOOP(total, 1) {
-    int m = find_mesh(s_pre, M, t);
-    int f = S[m].f0 + (t - s_pre[m]) * kBlock + threadIdx.x;
-    if (f < S[m].f0 + S[m].nf) fkey[f] = face_key_item(f, fhL, fhR, nullptr, lev, 0);
-  }
-}
-
 // ---- per-mesh stable partitions by level ----------------------------------
 // Chunk j of mesh m covers segment items [j kChunk, (j + 1) kChunk); the
 // count of key k in that chunk sits at 8 cp[m] + k nch + j (cp: the static
@@ -335,18 +348,18 @@ __global__ __launch_bounds__(kBlock) void k_b_face_keys(const int32_t* __restric
 // first slot in the merged list.  rp: the chunk prefix over the meshes that
 // reclassify.
 
+// Per chunk of the marked meshes' items, the counts of each key, faces and
+// cells in one launch (split_half: faces in the first half).  pre is the
+// staged chunk prefix of the block's class.
 template <typename Key>
-__global__ __launch_bounds__(64) void k_b_part_count(const int32_t* __restrict__ rp,
-                                                     const int32_t* __restrict__ cp,
-                                                     const BatchSched* S, int M, int faces,
-                                                     Key key, int32_t* __restrict__ counts) {
-  STAGE_PREFIX(rp);
-  __shared__ int cnt[kMaxLevels];
+__device__ inline void count_chunks(const int32_t* pre, const int32_t* __restrict__ cp,
+                                    const BatchSched* S, int M, int faces, Key key,
+                                    int32_t* __restrict__ counts, int* cnt, int b, int nbk) {
   const int lane = threadIdx.x;
-  const int total = s_pre[M];
-  for (int t = loop_rank(total), n_ = loop_blocks(total); t < total; t += n_) {
-    int m = find_mesh(s_pre, M, t);
-    int j = t - s_pre[m], nch = cp[m + 1] - cp[m];
+  const int total = pre[M];
+  for (int t = loop_rank(total, b, nbk), n_ = loop_blocks(total, nbk); t < total; t += n_) {
+    int m = find_mesh(pre, M, t);
+    int j = t - pre[m], nch = cp[m + 1] - cp[m];
     int b0 = faces ? S[m].f0 : S[m].c0;
     int end = b0 + (faces ? S[m].nf : S[m].nc);
     __syncthreads();
@@ -371,14 +384,39 @@ __global__ __launch_bounds__(64) void k_b_part_count(const int32_t* __restrict__
   }
 }
 
-// one block per mesh: exclusive scan of its counts in place, plus the
-// list starts per level
-__global__ __launch_bounds__(256) void k_b_part_scan(const int32_t* __restrict__ cp,
-                                                     BatchSched* S, int M, int faces,
-                                                     int32_t* __restrict__ counts) {
+template <typename Key>
+__global__ __launch_bounds__(64) void k_b_part_count(const int32_t* __restrict__ rpf,
+                                                     const int32_t* __restrict__ rpc,
+                                                     const int32_t* __restrict__ fcp,
+                                                     const int32_t* __restrict__ ccp,
+                                                     const BatchSched* S, int M, Key fkey,
+                                                     Key ckey, int32_t* __restrict__ fcounts,
+                                                     int32_t* __restrict__ ccounts) {
+  const int h = split_half();
+  const bool cells = (int)blockIdx.x >= h;  // block-uniform
+  STAGE_PREFIX(cells ? rpc : rpf);
+  __shared__ int cnt[kMaxLevels];
+  if (cells)
+    count_chunks(s_pre, ccp, S, M, 0, ckey, ccounts, cnt, (int)blockIdx.x - h,
+                 (int)gridDim.x - h);
+  else
+    count_chunks(s_pre, fcp, S, M, 1, fkey, fcounts, cnt, (int)blockIdx.x, h);
+}
+
+// one block per mesh and class (blocks [0, M) the faces, [M, 2M) the
+// cells): exclusive scan of its counts in place, plus the list starts per
+// level
+__global__ __launch_bounds__(256) void k_b_part_scan(const int32_t* __restrict__ fcp,
+                                                     const int32_t* __restrict__ ccp,
+                                                     BatchSched* S, int M,
+                                                     int32_t* __restrict__ fcounts,
+                                                     int32_t* __restrict__ ccounts) {
   __shared__ int sh[256];
-  const int m = blockIdx.x;
+  const int faces = (int)blockIdx.x < M;
+  const int m = faces ? (int)blockIdx.x : (int)blockIdx.x - M;
   if (m >= M || !S[m].reclass) return;
+  const int32_t* cp = faces ? fcp : ccp;
+  int32_t* counts = faces ? fcounts : ccounts;
   const int tid = threadIdx.x;
   const int nch = cp[m + 1] - cp[m];
   const int n = kMaxLevels * nch;
@@ -406,21 +444,20 @@ __global__ __launch_bounds__(256) void k_b_part_scan(const int32_t* __restrict__
   if (tid == 0) start[kMaxLevels] = b0 + cnt_all;
 }
 
+// The stable scatter of the marked meshes' items into their level-sorted
+// lists, faces and cells in one launch (split_half: faces in the first
+// half).  pre is the staged chunk prefix of the block's class.
 template <typename Key, typename Writer>
-__global__ __launch_bounds__(64) void k_b_part_scatter(const int32_t* __restrict__ rp,
-                                                       const int32_t* __restrict__ cp,
-                                                       const BatchSched* S, int M, int faces,
-                                                       Key key,
-                                                       const int32_t* __restrict__ offs,
-                                                       Writer out) {
-  STAGE_PREFIX(rp);
-  __shared__ int base[kMaxLevels];
+__device__ inline void scatter_chunks(const int32_t* pre, const int32_t* __restrict__ cp,
+                                      const BatchSched* S, int M, int faces, Key key,
+                                      const int32_t* __restrict__ offs, Writer out, int* base,
+                                      int b, int nbk) {
   const int lane = threadIdx.x;
   const unsigned long long lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-  const int total = s_pre[M];
-  for (int t = loop_rank(total), n_ = loop_blocks(total); t < total; t += n_) {
-    int m = find_mesh(s_pre, M, t);
-    int j = t - s_pre[m], nch = cp[m + 1] - cp[m];
+  const int total = pre[M];
+  for (int t = loop_rank(total, b, nbk), n_ = loop_blocks(total, nbk); t < total; t += n_) {
+    int m = find_mesh(pre, M, t);
+    int j = t - pre[m], nch = cp[m + 1] - cp[m];
     int b0 = faces ? S[m].f0 : S[m].c0;
     int end = b0 + (faces ? S[m].nf : S[m].nc);
     __syncthreads();
@@ -445,6 +482,27 @@ __global__ __launch_bounds__(64) void k_b_part_scatter(const int32_t* __restrict
       }
     }
   }
+}
+
+template <typename Key, typename FWriter, typename CWriter>
+__global__ __launch_bounds__(64) void k_b_part_scatter(const int32_t* __restrict__ rpf,
+                                                       const int32_t* __restrict__ rpc,
+                                                       const int32_t* __restrict__ fcp,
+                                                       const int32_t* __restrict__ ccp,
+                                                       const BatchSched* S, int M, Key fkey,
+                                                       Key ckey,
+                                                       const int32_t* __restrict__ foffs,
+                                                       const int32_t* __restrict__ coffs,
+                                                       FWriter fout, CWriter cout) {
+  const int h = split_half();
+  const bool cells = (int)blockIdx.x >= h;  // block-uniform
+  STAGE_PREFIX(cells ? rpc : rpf);
+  __shared__ int base[kMaxLevels];
+  if (cells)
+    scatter_chunks(s_pre, ccp, S, M, 0, ckey, coffs, cout, base, (int)blockIdx.x - h,
+                   (int)gridDim.x - h);
+  else
+    scatter_chunks(s_pre, fcp, S, M, 1, fkey, foffs, fout, base, (int)blockIdx.x, h);
 }
 
 // ---- per-subiteration schedule ------------------------------------------
@@ -918,26 +976,23 @@ hipError_t run_reclass(tafv_ctx* c, hipStream_t s) {
   for (int k = 1; k < B.lmax - 1; ++k)
     hipLaunchKernelGGL(k_b_sweep, dim3(G), dim3(kBlock), lds, s, rc, B.dsched, M, m.nc, k,
                        m.nb_, m.lev);
-  hipLaunchKernelGGL(k_b_cell_keys, dim3(G), dim3(kBlock), lds, s, rc, B.dsched, M, m.nc, m.nb_,
-                     m.lev, m.ckey, m.fpack, B.thist);
+  // the cell and the face classes of the next steps share a launch, each
+  // in one half of a grid twice the size (split_half)
+  hipLaunchKernelGGL(k_b_keys, dim3(2 * G), dim3(kBlock), lds, s, rc, rf, B.dsched, M, m.nc,
+                     m.nb_, m.lev, m.ckey, m.fpack, B.thist, m.fhL, m.fhR, m.fkey);
   hipLaunchKernelGGL(k_b_cell_early, dim3(G), dim3(kBlock), lds, s, rc, B.dsched, M, m.nc, m.nb_,
                      m.lev, m.ckey, m.fpack, c->prm.order);
   hipLaunchKernelGGL(k_b_reduce, dim3(M), dim3(kReduceThreads), 0, s, rc, B.dsched, M, nullptr,
                      B.thist);
-  hipLaunchKernelGGL(k_b_face_keys, dim3(G), dim3(kBlock), lds, s, rf, B.dsched, M, m.fhL, m.fhR,
-                     m.lev, m.fkey);
   const int PG = 4 * G;  // 64-thread blocks
-  hipLaunchKernelGGL(k_b_part_count<ByteKey>, dim3(PG), dim3(64), lds, s, rfc, B.fc, B.dsched, M,
-                     1, ByteKey{m.fkey}, B.cnt_f);
-  hipLaunchKernelGGL(k_b_part_count<ByteKey>, dim3(PG), dim3(64), lds, s, rcc, B.cc, B.dsched, M,
-                     0, ByteKey{m.ckey}, B.cnt_c);
-  hipLaunchKernelGGL(k_b_part_scan, dim3(M), dim3(256), 0, s, B.fc, B.dsched, M, 1, B.cnt_f);
-  hipLaunchKernelGGL(k_b_part_scan, dim3(M), dim3(256), 0, s, B.cc, B.dsched, M, 0, B.cnt_c);
-  hipLaunchKernelGGL((k_b_part_scatter<ByteKey, FaceWriter>), dim3(PG), dim3(64), lds, s, rfc,
-                     B.fc, B.dsched, M, 1, ByteKey{m.fkey}, B.cnt_f,
-                     FaceWriter{m.frec, m.fhL, m.fhR});
-  hipLaunchKernelGGL((k_b_part_scatter<ByteKey, IndexWriter>), dim3(PG), dim3(64), lds, s, rcc,
-                     B.cc, B.dsched, M, 0, ByteKey{m.ckey}, B.cnt_c, IndexWriter{m.pc.list});
+  hipLaunchKernelGGL(k_b_part_count<ByteKey>, dim3(2 * PG), dim3(64), lds, s, rfc, rcc, B.fc,
+                     B.cc, B.dsched, M, ByteKey{m.fkey}, ByteKey{m.ckey}, B.cnt_f, B.cnt_c);
+  hipLaunchKernelGGL(k_b_part_scan, dim3(2 * M), dim3(256), 0, s, B.fc, B.cc, B.dsched, M,
+                     B.cnt_f, B.cnt_c);
+  hipLaunchKernelGGL((k_b_part_scatter<ByteKey, FaceWriter, IndexWriter>), dim3(2 * PG), dim3(64),
+                     lds, s, rfc, rcc, B.fc, B.cc, B.dsched, M, ByteKey{m.fkey}, ByteKey{m.ckey},
+                     B.cnt_f, B.cnt_c, FaceWriter{m.frec, m.fhL, m.fhR},
+                     IndexWriter{m.pc.list});
   hipLaunchKernelGGL(k_b_sched, dim3(1), dim3(1024), 0, s, B.dsched, M, c->prm.order, flag, B.tp);
   return hipGetLastError();
 }
